@@ -1,0 +1,76 @@
+"""Model update: deform the model, register it point-to-pixel and fuse the new depth (Sec. II-G).
+
+Follows Alg. 2 steps 1-3 with Alg. 1 as the registration test and
+Eqs.(12), (14), (15) as the update.  Readings where the paper is silent or
+inconsistent:
+  * Reg map (Alg. 2 step 2): each pixel keeps the projecting point nearest to
+    the camera; equal depths go to the lower point index.
+  * Alg. 1 gate: depth present, |z~ - D(p)| < tau and the angle between the
+    warped normal and the depth normal below delta, i.e. n~ . N > cos(delta);
+    tau = 10 mm, delta = 10 degrees (Sec. III-B).  Eq.(11)'s weight is read as
+    this 0/1 gate (its stated growth with distance contradicts the text).
+  * Eq.(12) averages depth along the ray; the fused point is taken as the
+    weighted mean of positions, p <- (w p~ + Gamma_w(p)) / (w + 1) in world
+    coordinates, whose camera-z component is Eq.(12) when p~ lies on the ray.
+    Eq.(14) likewise for the normal, renormalised; Eq.(15) w <- min(w + 1, w_max)
+    with w_max = 20 (Sec. III-B; the 10 in Sec. II-G conflicts).
+  * Registered points are stamped with the frame index.  Every point moves to
+    its warped position; every node moves by its own translation, g_j + t_j.
+Test infrastructure only (see the package header).
+"""
+import numpy as np
+
+from .assoc import project
+from .depthmap import vertex_map
+from .warp import ed_warp, split, warp_normals
+
+
+def zbuffer(vc, inside, ui, vi, W, H):
+    """Winner point index per pixel (-1 = none): smallest camera z, then lowest index."""
+    win = np.full(W * H, -1, dtype=np.int64)
+    pts = np.nonzero(inside)[0]
+    if len(pts) == 0:
+        return win
+    pix = vi[pts] * W + ui[pts]
+    order = np.lexsort((pts, vc[pts, 2], pix))     # by pixel, then z, then index
+    pix_s = pix[order]
+    first = np.ones(len(order), dtype=bool)
+    first[1:] = pix_s[1:] != pix_s[:-1]
+    win[pix_s[first]] = pts[order[first]]
+    return win
+
+
+def fuse(points, normals, weight, stamp, nodes, params, idx, w, depth, camera, R, T, Nmap, Nvalid,
+         frame, tau=10.0, cos_delta=float(np.cos(np.deg2rad(10.0))), w_max=20.0):
+    """Returns dict(points, normals, weight, stamp, nodes, registered (N,) bool, reg (H*W,) winners)."""
+    W, H = camera[0], camera[1]
+    Rm = np.asarray(R, dtype=np.float64)
+    Tv = np.asarray(T, dtype=np.float64)
+    vw = ed_warp(points, nodes, params, idx, w)             # world
+    nw = warp_normals(normals, params, idx, w)
+    vc = vw @ Rm.T + Tv
+    nc = nw @ Rm.T
+    ui, vi, _, _, inside = project(vc, camera)
+    win = zbuffer(vc, inside, ui, vi, W, H)
+    n = vw.shape[0]
+    is_winner = np.zeros(n, dtype=bool)
+    ids = win[win >= 0]
+    is_winner[ids] = True
+    D = np.asarray(depth, dtype=np.float64)
+    d = D[vi, ui]
+    Np = np.asarray(Nmap, dtype=np.float64)[vi, ui]
+    ndot = (nc[:, 0] * Np[:, 0] + nc[:, 1] * Np[:, 1]) + nc[:, 2] * Np[:, 2]
+    reg = is_winner & (d > 0) & Nvalid[vi, ui] & (np.abs(vc[:, 2] - d) < tau) & (ndot > cos_delta)
+    Vm = vertex_map(D, camera)[vi, ui]
+    gam_w = (Vm - Tv) @ Rm                                   # R^T (V - T)
+    nobs_w = Np @ Rm                                         # R^T N
+    om = np.asarray(weight, dtype=np.float64)
+    p_new = np.where(reg[:, None], (om[:, None] * vw + gam_w) / (om[:, None] + 1.0), vw)
+    nn = np.where(reg[:, None], (om[:, None] * nw + nobs_w) / (om[:, None] + 1.0), nw)
+    nn = nn / np.linalg.norm(nn, axis=1, keepdims=True)
+    om_new = np.where(reg, np.minimum(om + 1.0, w_max), om)
+    st_new = np.where(reg, frame, np.asarray(stamp))
+    _, t = split(params)
+    g_new = np.asarray(nodes, dtype=np.float64) + t
+    return {"points": p_new, "normals": nn, "weight": om_new, "stamp": st_new, "nodes": g_new,
+            "registered": reg, "reg": win}
