@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Throughput of MIS-SLAM's per-frame deformable registration on one MI355X.
+
+One step = one frame of the hot path on the 640x480 / 250,000-point /
+1,600-node synthetic tissue problem: depth normal map, graph setup (kNN,
+skinning weights, node graph, lists), 10 Gauss-Newton iterations of 10 PCG
+iterations each.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  value = Gauss-Newton iterations per second over whole
+frames; ms_per_step = ms per frame.  A second, profiled region (HIP events
+around each phase, on the library's stream) gives the per-phase breakdown and
+the roofline of the dominant kernel.  The CPU baseline is the float64 oracle
+on a bounded sample of the same frame.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP32_VALU_PEAK = 157.3       # TFLOP/s vendor figure
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(phase, n, m, nnzb, k, width, height, pcg_iters, n_valid):
+    """Bytes one launch of a phase must move at minimum (float32 / int32 streams)."""
+    if phase == "point_pass":
+        # read v, n (24 B), k idx + k w (8k B), the matched pixel (16 B, valid points);
+        # write r, n', corr (20 B); node table reads are cache-resident
+        return n * (24 + 8 * k + 20) + n_valid * 16
+    if phase == "assemble":
+        # per point: k idx + k w, v, n', r, corr; per list entry 4 B; out: blocks, g
+        return n * (8 * k + 12 + 12 + 4 + 4) + k * n * 4 + nnzb * 576 + m * 48 + m * 48
+    if phase == "pcg":
+        # per iteration: the whole BSR once (576 B/block) + ~8 vector passes of 12 m floats + M (576 B/node)
+        return pcg_iters * (nnzb * 576 + m * 576 + 8 * 12 * m * 4) + m * 576
+    if phase == "bjacobi":
+        return m * 576 * 2
+    if phase == "normal_map":
+        return width * height * (4 + 16)
+    return 0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              f"(the per-frame registration does not shard across GPUs).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import gen
+    from paper_1803_02009_amd import _lib
+    from paper_1803_02009_amd import misslam as M
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    lib = _lib.load()
+    sc = gen.make_scene(args.config)
+    dev = "cuda"
+    pts = torch.tensor(np.concatenate([sc["points"].T, sc["normals"].T]), device=dev).contiguous()
+    nodes = torch.tensor(np.ascontiguousarray(sc["nodes"].T), device=dev).contiguous()
+    depth = torch.tensor(sc["depth"], device=dev).contiguous()
+    cam = M.camera(*sc["camera"])
+    pose = M.pose(sc["R"], sc["T"])
+    params = M.Params(sigma=sc["sigma"], gn_iters=sc["gn_iters"], pcg_iters=sc["pcg_iters"])
+    ws = M.Workspace()
+    n, m = pts.shape[1], nodes.shape[1]
+    G = params.gn_iters
+    x = M.identity_params(m)
+    x0 = x.clone()
+    state = {}
+
+    def frame():
+        g = M.build_graph(pts, nodes, params, ws)
+        x.copy_(x0)
+        rep, _ = M.gn_register(pts, nodes, x, g, depth, cam, pose, params, ws)
+        state["graph"], state["rep"] = g, rep
+
+    for _ in range(max(1, args.warmup)):
+        frame()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        frame()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_frame = 1000.0 * elapsed / args.steps
+    gn_per_s = G * args.steps / elapsed
+
+    # profiled region: per-phase HIP events on the library's stream
+    lib.misslam_profile_reset()
+    lib.misslam_profile_enable(1)
+    for _ in range(args.steps):
+        frame()
+    torch.cuda.synchronize()
+    lib.misslam_profile_enable(0)
+    import ctypes
+    phases = {}
+    for ph in ["normal_map", "build_graph", "point_pass", "assemble", "energy", "bjacobi", "pcg"]:
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _lib.check("misslam_profile_get", lib.misslam_profile_get(ph.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+        phases[ph] = {"total_ms": ms.value, "launches": cnt.value,
+                      "avg_us": 1000.0 * ms.value / cnt.value if cnt.value else 0.0}
+    rep = M.read_report(state["rep"])
+    info = state["graph"].info.cpu().numpy()
+    nnzb = int(info[0])
+    n_valid = int(np.mean([r["n_valid"] for r in rep[:G]]))
+    per_iter = ["point_pass", "assemble", "energy", "bjacobi", "pcg"]
+    gn_iter_ms = sum(phases[p]["total_ms"] for p in per_iter) / (args.steps * G)
+    dominant = max(["point_pass", "assemble", "pcg"], key=lambda p: phases[p]["avg_us"])
+    abytes = algorithmic_bytes(dominant, n, m, nnzb, params.k, cam.width, cam.height, params.pcg_iters, n_valid)
+    achieved = abytes / (phases[dominant]["avg_us"] * 1e-6) / 1e9
+    roofline = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": int(abytes), "avg_launch_us": round(phases[dominant]["avg_us"], 2)}
+
+    # accuracy against the stored float64 oracle result of the same frame
+    xg = x.cpu().numpy().astype(np.float64)
+    acc = {}
+    gold = os.path.join(ROOT, "tests", "golden", f"{args.config}_oracle.npz")
+    if os.path.exists(gold):
+        z = np.load(gold)
+        xo = z["x"]
+        xi = np.zeros_like(xo)
+        xi[:, [0, 4, 8]] = 1.0
+        acc["rel_err_params"] = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+        acc["rel_err_params_delta"] = float(np.linalg.norm((xg - xi) - (xo - xi)) / np.linalg.norm(xo - xi))
+        acc["rel_err_e_data_final"] = float(abs(rep[-1]["e_data"] - z["e_data_final"]) / z["e_data_final"])
+
+    out = {
+        "metric": "GN iters/s + ms/frame at 640x480, 1600 ED nodes, rel err vs FP64 oracle",
+        "value": round(gn_per_s, 2),
+        "unit": "GN iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_frame, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {cam.width}x{cam.height} depth, {n} points, {m} nodes, k={params.k}, "
+                               f"{G} GN x {params.pcg_iters} PCG per frame; step = graph setup + registration",
+                   "nnzb": nnzb, "n_valid_mean": n_valid},
+        "ms_per_frame": round(ms_frame, 4),
+        "gn_iter_ms_profiled": round(gn_iter_ms, 4),
+        "phases": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"]} for k, v in phases.items()},
+        "accuracy": acc,
+        "report_final": {"e_data": float(rep[-1]["e_data"]), "e_rot": float(rep[-1]["e_rot"]),
+                         "e_reg": float(rep[-1]["e_reg"]), "n_valid": int(rep[-1]["n_valid"]),
+                         "flags": int(rep[-1]["flags"])},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, params)
+    print(json.dumps(out))
+
+
+def cpu_baseline(sc, params):
+    """Float64 oracle on the same frame, single-threaded: graph setup and one GN iteration."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    import oracle
+    from oracle.gn import linearize
+    from oracle.pcg import block_jacobi, pcg
+
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        pb = oracle.Problem.from_scene(sc, gn_iters=1)
+        t0 = time.perf_counter()
+        graph = oracle.build_graph(pb.points, pb.nodes, pb.k, pb.weight_kind, pb.sigma)
+        t1 = time.perf_counter()
+        Nmap, Nvalid = oracle.normal_map(pb.depth, pb.camera)
+        x = oracle.identity_params(len(pb.nodes))
+        _, _, _, blocks, g, _ = linearize(pb, graph, x, Nmap, Nvalid)
+        Minv, _ = block_jacobi(graph["row_ptr"], graph["col_idx"], blocks, pb.lam)
+        pcg(graph["row_ptr"], graph["col_idx"], blocks, g, pb.lam, params.pcg_iters, Minv)
+        t2 = time.perf_counter()
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    gn_s = t2 - t1
+    return {"value": round(1.0 / gn_s, 4), "unit": "GN iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"one GN iteration ({params.pcg_iters} PCG) of the same frame after the oracle's graph setup; "
+                      f"graph setup {t1 - t0:.1f} s, GN iteration {gn_s:.1f} s, float64 numpy, 1 thread",
+            "graph_setup_s": round(t1 - t0, 2), "gn_iter_s": round(gn_s, 2)}
+
+
+if __name__ == "__main__":
+    main()

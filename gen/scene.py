@@ -39,7 +39,7 @@ class SceneSpec:
     bumps: tuple            # (min, max) number of Gaussian bumps on the surface
     rot_max_deg: float      # rigid pose bound
     trans_max: float        # rigid pose bound, mm
-    noise_sigma: float      # depth noise, mm
+    noise_sigma: float      # depth noise, mm; stereo depth error scales as z^2 / (f b), so 1/fx here
     gn_iters: int
     pcg_iters: int
     seed: int
@@ -51,10 +51,10 @@ SPECS = {
                     (65, 49), 0.1, (8, 6), 6.0, "smooth", (0, 0), 5.0, 8.0, 0.2, 5, 20, 1),
     # 320x240, 60k points, 400 nodes at 5 mm, bumps + breathing.
     "c2": SceneSpec("c2", 320, 240, 128.0, 128.0, 160.0, 120.0, (-62.5, 62.5, -40.0, 40.0),
-                    (300, 200), 0.05, (25, 16), 5.0, "breathing", (2, 4), 5.0, 8.0, 0.2, 10, 10, 2),
+                    (300, 200), 0.05, (25, 16), 5.0, "breathing", (2, 4), 5.0, 8.0, 0.2 * 60 / 128, 10, 10, 2),
     # 640x480, 250k points at 0.2 mm, 1600 nodes at 2.5 mm, bumps + breathing.
     "c3": SceneSpec("c3", 640, 480, 256.0, 256.0, 320.0, 240.0, (-62.5, 62.5, -40.0, 40.0),
-                    (625, 400), 0.02, (50, 32), 2.5, "breathing", (2, 4), 5.0, 8.0, 0.2, 10, 10, 3),
+                    (625, 400), 0.02, (50, 32), 2.5, "breathing", (2, 4), 5.0, 8.0, 0.2 * 60 / 256, 10, 10, 3),
 }
 
 

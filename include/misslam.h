@@ -1,0 +1,256 @@
+/*
+ * misslam.h - C ABI of a gfx950 (MI355X) library for the per-frame dense
+ * deformable registration of MIS-SLAM (Song et al., arXiv:1803.02009):
+ * Gauss-Newton registration of an embedded-deformation (ED) graph to a depth
+ * map, and the fusion of the depth into the deformed point model.
+ *
+ * Conventions
+ *  - Every array pointer is a DEVICE pointer owned by the caller unless marked
+ *    (host).  Structs themselves are host structs passed by pointer.
+ *  - Units are millimetres.  Model points, normals and nodes are SoA planes of
+ *    float32.  Node parameters are m x 12 float32 rows x_j = (c1, c2, c3, t_j):
+ *    A_j = [c1 c2 c3] column by column (the columns of the rotation term,
+ *    Eq.(5)), x[3c + a] = A_j[a][c], x[9 + a] = t_j[a].
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream); outputs are valid once the stream is synchronised.  Argument
+ *    checks happen on the host before anything is enqueued: a negative status
+ *    means nothing was launched.  Numeric failures found on the device are not
+ *    return codes; they set bits in misslam_report.flags.
+ *  - Hot calls allocate no device memory: scratch comes from the caller's
+ *    workspace `ws` of `ws_bytes` (query misslam_workspace_bytes).  Calls that
+ *    share a workspace must not overlap in time.
+ *  - Decision arithmetic (nearest nodes, pixel rounding, gates) is float64 with
+ *    a fixed operation order and no contraction, so integer results are
+ *    reproducible bit for bit by a float64 reference given the same inputs.
+ *  - No floating-point atomics are used: results are bitwise deterministic.
+ */
+#ifndef MISSLAM_H
+#define MISSLAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MISSLAM_OK = 0,
+    MISSLAM_EINVAL = -1,       /* null pointer or out-of-range scalar */
+    MISSLAM_ESHAPE = -2,       /* sizes inconsistent with each other */
+    MISSLAM_EWORKSPACE = -3,   /* workspace too small */
+    MISSLAM_EHIP = -4,         /* a HIP runtime call failed (see misslam_last_hip_error) */
+    MISSLAM_ECAPACITY = -5,    /* a caller-provided capacity is too small */
+    MISSLAM_EUNSUPPORTED = -6  /* valid request this build does not implement */
+} misslam_status;
+
+/* device-side failure bits in misslam_report.flags */
+#define MISSLAM_FLAG_NONSPD_BLOCK   0x1   /* a damped diagonal block was not SPD; its preconditioner is I */
+#define MISSLAM_FLAG_PCG_BREAKDOWN  0x2   /* p^T A p <= 0 in PCG; the solve stopped early */
+#define MISSLAM_FLAG_NONFINITE      0x4   /* NaN/Inf met in an energy or the update; x left unchanged */
+#define MISSLAM_FLAG_FRAME_REJECT   0x8   /* mean |r| above params.reject_threshold */
+#define MISSLAM_FLAG_GRAPH_OVERFLOW 0x10  /* a per-frame graph capacity was exceeded */
+
+#define MISSLAM_WEIGHT_GAUSS  0   /* w_j ~ exp(-|v-g_j|^2 / (2 sigma^2)), normalised over k */
+#define MISSLAM_WEIGHT_LINEAR 1   /* Eq.(2): w_j ~ max(0, 1 - |v-g_j| / d_(k+1)), normalised */
+
+#define MISSLAM_PREC_FP32 0       /* plain float32 normal equations */
+#define MISSLAM_PREC_BF16 1       /* data-term products in bfloat16 on the matrix cores, float32 accumulation */
+#define MISSLAM_PREC_FP16 2       /* same with float16 inputs */
+
+#define MISSLAM_MAX_K    8
+#define MISSLAM_MAX_PCG  64
+#define MISSLAM_MAX_ROW  32       /* max blocks per row of the normal matrix (node degree + 1) */
+#define MISSLAM_MAX_LIST 2048     /* max points influenced by one node */
+
+/* (host) pinhole camera of the depth map: pixel (u, v) = (fx x/z + cx, fy y/z + cy) */
+typedef struct { int32_t width, height; float fx, fy, cx, cy; } misslam_camera;
+
+/* (host) rigid scope pose of the frame, camera = R * world + T, R row-major (Eq.(1)'s R, T) */
+typedef struct { float R[9]; float T[3]; } misslam_pose;
+
+/* model point cloud (Sec. II-A): coordinate, normal, fusion weight, time stamp */
+typedef struct {
+    int64_t n, capacity;
+    float *px, *py, *pz;      /* canonical coordinates, n (<= capacity) each */
+    float *nx, *ny, *nz;      /* unit normals */
+    float *w;                 /* fusion weight (Eq.(15)); may be NULL outside misslam_fuse */
+    int32_t *stamp;           /* last registered frame; may be NULL outside misslam_fuse */
+} misslam_points;
+
+/* ED nodes (Sec. II-D): positions g_j and parameters x_j */
+typedef struct {
+    int32_t m, capacity;
+    float *gx, *gy, *gz;      /* m each */
+    float *params;            /* m x 12 */
+} misslam_nodes;
+
+/*
+ * Per-frame graph derived from the canonical points and nodes by
+ * misslam_build_graph; read by every other call of the frame.
+ *   knn_idx  k x n int32, slot-major (knn_idx[s*n + i]): the k nearest nodes of
+ *            point i by (squared distance, node index)
+ *   knn_w    k x n float32 normalised skinning weights (Eq.(2) / Gaussian)
+ *   row_ptr  m+1, col_idx bsr_cap: block pattern of the normal matrix, row j =
+ *            {j} U N(j) ascending, N(j) = nodes sharing a point with j (Eq.(6))
+ *   list_ptr m+1, list_pts k*n: the points each node influences, ordered by
+ *            (sorted k-node set, point index)
+ *   list_key 2*k*n int32: per list entry of node j, the positions in row j of
+ *            the entry's k nodes sorted by node index, 8 bits each (0xFF = cut
+ *            from an overflowed row), nodes 0-3 in word 0, 4-7 in word 1
+ *   info     8 int32 written by the device: [0] nnzb, [1] largest row,
+ *            [2] largest list, [3] overflow flag (MISSLAM_FLAG_GRAPH_OVERFLOW)
+ */
+typedef struct {
+    int32_t k, bsr_cap;
+    int32_t *knn_idx;
+    float *knn_w;
+    int32_t *row_ptr, *col_idx;
+    int32_t *list_ptr, *list_pts;
+    int32_t *list_key;
+    int32_t *info;
+} misslam_graph;
+
+/* (host) solver settings; defaults from the paper (Sec. III-B) via misslam_default_params */
+typedef struct {
+    int32_t k;                 /* nodes per point, 1..MISSLAM_MAX_K */
+    int32_t weight_kind;       /* MISSLAM_WEIGHT_* */
+    float sigma;               /* Gaussian width, mm */
+    float w_rot, w_reg, w_data;/* 1000, 10000, 1 */
+    double eps_d;              /* distance gate, Eq.(7): 15 mm */
+    double cos_eps_n;          /* normal gate, Eq.(7): cos(10 deg) */
+    float lambda;              /* damping added to the diagonal of H and of M */
+    int32_t gn_iters;          /* Gauss-Newton iterations per frame */
+    int32_t pcg_iters;         /* PCG iterations per Gauss-Newton step, <= MISSLAM_MAX_PCG */
+    int32_t precision;         /* MISSLAM_PREC_* */
+    int32_t refine_steps;      /* iterative-refinement steps for BF16/FP16 */
+    float reject_threshold;    /* mean |r| above which FRAME_REJECT is set; <= 0 disables */
+} misslam_params;
+
+/* one entry per Gauss-Newton iteration, plus a final entry at the returned parameters (device) */
+typedef struct {
+    double e_data, e_rot, e_reg;             /* unweighted sums of squares at the linearisation point */
+    double pcg_resid[MISSLAM_MAX_PCG + 1];   /* |r_i| of the PCG residual, i = 0..pcg_iters_done */
+    int32_t n_valid;                         /* points that passed the Eq.(7) gates */
+    int32_t flags;                           /* MISSLAM_FLAG_* */
+    int32_t pcg_iters_done;
+    int32_t reserved;
+} misslam_report;
+
+/* (host) fusion settings (Alg. 1-2, Eqs.(12)-(15), Sec. III-B) */
+typedef struct {
+    double tau;                /* |z~ - D| gate of Alg. 1: 10 mm */
+    double cos_delta;          /* normal angle gate of Alg. 1: cos(10 deg) */
+    float w_max;               /* weight cap of Eq.(15): 20 */
+    int32_t frame;             /* stamp written to registered points */
+} misslam_fuse_params;
+
+/* ------------------------------------------------------------------ utilities */
+
+/* Fills *p with the paper's settings (Sec. III-B) and k = 4 Gaussian weights, sigma = 1. (host) */
+void misslam_default_params(misslam_params *p);
+
+/* Static description of a status code. */
+const char *misslam_status_string(int32_t status);
+
+/* The last hipError_t seen by a failing call on this thread (0 if none). */
+int32_t misslam_last_hip_error(void);
+
+/* Bytes of workspace needed by every call below for n points, m nodes and a
+ * width x height depth map, or 0 if the sizes are invalid. */
+size_t misslam_workspace_bytes(int64_t n, int32_t m, int32_t width, int32_t height,
+                               const misslam_params *params);
+
+/* ------------------------------------------------------------------ per-frame setup */
+
+/*
+ * Depth preprocessing for the data term (Eq.(8)).  out (height x width x 4
+ * float32, pixel-major) receives (Nx, Ny, Nz, D) per pixel: the unit normal
+ * N = normalize(b x a), a = V(u+1,v) - V(u-1,v), b = V(u,v+1) - V(u,v-1),
+ * V(u,v) = D (u-cx)/fx, (v-cy)/fy, 1), computed in float64 and rounded; N = 0
+ * on the border, next to an empty pixel or where b x a = 0.
+ */
+misslam_status misslam_normal_map(const float *depth, const misslam_camera *camera, float *out,
+                                  void *stream);
+
+/*
+ * kNN sets, skinning weights (Eq.(2)), node graph N(j) (Eq.(6)), block pattern
+ * and node -> point lists from the canonical points and nodes.  Capacities:
+ * bsr_cap blocks; rows longer than MISSLAM_MAX_ROW or lists longer than
+ * MISSLAM_MAX_LIST set graph->info[3] (the caller checks it after a sync).
+ */
+misslam_status misslam_build_graph(const misslam_points *points, const misslam_nodes *nodes,
+                                   const misslam_params *params, misslam_graph *graph, void *ws,
+                                   size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ hot path */
+
+/*
+ * ED warp, Eq.(1): out_pos = R sum_j w_j [A_j (v - g_j) + g_j + t_j] + T and
+ * out_nrm = normalize(R sum_j w_j A_j^-T n), both 3 x n float32 planes.
+ * pose may be NULL (world coordinates).  out_nrm may be NULL.
+ */
+misslam_status misslam_warp(const misslam_points *points, const misslam_nodes *nodes,
+                            const misslam_graph *graph, const misslam_pose *pose, float *out_pos,
+                            float *out_nrm, void *stream);
+
+/*
+ * Linearisation of Eq.(3) (data, rotation and regularisation terms) at the
+ * current node parameters: warp, projective association with the Eq.(7)
+ * gates, point-to-plane residuals (Eq.(8)), and the normal equations
+ * H = sum w J^T J (BSR, graph pattern, nnzb x 12 x 12 float32 row-major, both
+ * triangles stored) and g = sum w J^T r (m x 12).  corr (n int32) receives
+ * the matched pixel v*width+u or -1; it may be NULL.  rep (device, 1 entry)
+ * receives the energies and n_valid.  nmap is the output of misslam_normal_map
+ * for this depth map.
+ */
+misslam_status misslam_build_normal_eq(const misslam_points *points, const misslam_nodes *nodes,
+                                       const misslam_graph *graph, const float *nmap,
+                                       const misslam_camera *camera, const misslam_pose *pose,
+                                       const misslam_params *params, float *blocks, float *g,
+                                       int32_t *corr, misslam_report *rep, void *ws, size_t ws_bytes,
+                                       void *stream);
+
+/*
+ * Block-Jacobi PCG for (H + lambda I) delta = -g on the graph pattern:
+ * params->pcg_iters iterations from delta = 0, float32 products and float64
+ * reductions.  delta: m x 12.  rep (device, 1 entry) receives the residual
+ * norms, iterations done and flags.
+ */
+misslam_status misslam_pcg_solve(const misslam_graph *graph, int32_t m, const float *blocks,
+                                 const float *g, const misslam_params *params, float *delta,
+                                 misslam_report *rep, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * One frame of registration (Sec. II-E, II-F): params->gn_iters damped
+ * Gauss-Newton steps on the node parameters (nodes->params in/out; the caller
+ * initialises them, normally to A = I, t = 0), pose fixed.  rep (device)
+ * holds gn_iters + 1 entries: one per step at its linearisation point and a
+ * final one at the returned parameters.  corr_hist, if not NULL, receives
+ * the gn_iters x n correspondence arrays.  depth is height x width float32.
+ */
+misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *nodes,
+                                   const misslam_graph *graph, const float *depth,
+                                   const misslam_camera *camera, const misslam_pose *pose,
+                                   const misslam_params *params, misslam_report *rep,
+                                   int32_t *corr_hist, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ profiling */
+
+/*
+ * Phase timers for measurement.  While enabled, each call brackets the
+ * launches of every phase it runs with HIP events on its own stream (not
+ * allowed during stream capture).  Phases: "normal_map", "build_graph",
+ * "point_pass", "assemble", "energy", "bjacobi", "pcg" (the whole PCG solve,
+ * including the parameter update).  misslam_profile_get synchronises the
+ * recorded events and returns the accumulated milliseconds and number of
+ * bracketed launches since the last reset.  Returns the previous state.
+ */
+int32_t misslam_profile_enable(int32_t on);
+misslam_status misslam_profile_get(const char *phase, double *total_ms, int64_t *launches);
+void misslam_profile_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MISSLAM_H */

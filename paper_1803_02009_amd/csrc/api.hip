@@ -1,0 +1,428 @@
+// Host side of libmisslam: argument validation, workspace carving and the
+// extern "C" entry points declared in include/misslam.h.  Nothing here
+// computes; every step of the method runs in the gfx950 kernels.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "frame.h"
+
+namespace {
+
+// ---------------------------------------------------------------- phase timers (profiling only)
+
+enum Phase { PH_NORMAL_MAP, PH_GRAPH, PH_POINT_PASS, PH_ASSEMBLE, PH_ENERGY, PH_BJACOBI, PH_PCG, PH_COUNT };
+const char *const kPhaseNames[PH_COUNT] = {"normal_map", "build_graph", "point_pass", "assemble",
+                                           "energy",     "bjacobi",     "pcg"};
+
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    struct Rec {
+        hipEvent_t a, b;
+        int phase;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double total_ms[PH_COUNT] = {};
+    int64_t launches[PH_COUNT] = {};
+
+    hipEvent_t get_event() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void collect() {
+        for (auto &r : pending) {
+            float ms = 0.f;
+            if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                total_ms[r.phase] += ms;
+                launches[r.phase] += 1;
+            }
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+};
+
+Profiler &prof() {
+    static Profiler p;
+    return p;
+}
+
+// Brackets the launches of one phase with events on its stream when profiling is on.
+struct Timed {
+    hipStream_t st;
+    int phase;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(int ph, hipStream_t s) : st(s), phase(ph) {
+        Profiler &p = prof();
+        std::lock_guard<std::mutex> lk(p.mu);
+        if (!p.on) return;
+        a = p.get_event();
+        b = p.get_event();
+        if (a && b) hipEventRecord(a, st);
+    }
+    ~Timed() {
+        if (!a || !b) return;
+        Profiler &p = prof();
+        std::lock_guard<std::mutex> lk(p.mu);
+        hipEventRecord(b, st);
+        p.pending.push_back({a, b, phase});
+    }
+};
+
+thread_local int32_t g_last_hip = 0;
+
+misslam_status hip_fail(hipError_t e) {
+    g_last_hip = (int32_t)e;
+    return MISSLAM_EHIP;
+}
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Bump allocator over the caller's workspace; with base == nullptr it only measures.
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t count) {
+        off = align_up(off);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct Layout {
+    msl::StepScratch step;
+    msl::PcgScratch pcg;
+    msl::GraphScratch graph;
+    float4 *nmap;
+    float *blocks;
+    float *gvec;
+    float *delta;
+    size_t bytes;
+};
+
+Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters) {
+    Carver c{static_cast<char *>(ws)};
+    Layout L{};
+    const int64_t npb = (n + 255) / 256 + 1;
+    const int nblk = msl::pcg_blocks(m > 0 ? m : 1);
+    L.nmap = c.take<float4>((size_t)W * H);
+    L.step.nr = c.take<float4>((size_t)n);
+    L.step.corr = c.take<int32_t>((size_t)n);
+    L.step.pt_part = c.take<double>((size_t)3 * npb);
+    L.step.node_part = c.take<double>((size_t)2 * m);
+    L.step.minv = c.take<float>((size_t)144 * m);
+    L.step.flags = c.take<int32_t>(4);
+    L.blocks = c.take<float>((size_t)m * MISSLAM_MAX_ROW * 144);
+    L.gvec = c.take<float>((size_t)12 * m);
+    L.delta = c.take<float>((size_t)12 * m);
+    L.pcg.r = c.take<float>((size_t)12 * m);
+    L.pcg.z = c.take<float>((size_t)12 * m);
+    L.pcg.p = c.take<float>((size_t)12 * m);
+    L.pcg.q = c.take<float>((size_t)12 * m);
+    L.pcg.part = c.take<double>((size_t)(pcg_iters + 2) * 4 * nblk);
+    L.pcg.status = c.take<int32_t>((size_t)2 * (pcg_iters + 2));
+    L.pcg.nblk = nblk;
+    L.graph.tmp = c.take<int32_t>((size_t)m * MISSLAM_MAX_ROW);
+    L.graph.cnt = c.take<int32_t>((size_t)2 * m + 8);
+    L.bytes = align_up(c.off);
+    return L;
+}
+
+bool valid_params(const misslam_params *p) {
+    return p && p->k >= 1 && p->k <= MISSLAM_MAX_K &&
+           (p->weight_kind == MISSLAM_WEIGHT_GAUSS || p->weight_kind == MISSLAM_WEIGHT_LINEAR) &&
+           (p->weight_kind != MISSLAM_WEIGHT_GAUSS || p->sigma > 0.f) && p->gn_iters >= 0 && p->pcg_iters >= 0 &&
+           p->pcg_iters <= MISSLAM_MAX_PCG && std::isfinite(p->lambda) && p->lambda >= 0.f &&
+           std::isfinite(p->w_rot) && std::isfinite(p->w_reg) && std::isfinite(p->w_data) &&
+           p->precision >= MISSLAM_PREC_FP32 && p->precision <= MISSLAM_PREC_FP16 && p->refine_steps >= 0;
+}
+
+bool valid_points(const misslam_points *p) {
+    return p && p->n >= 0 && p->n <= p->capacity && p->n < (int64_t)1 << 31 &&
+           (p->n == 0 || (p->px && p->py && p->pz && p->nx && p->ny && p->nz));
+}
+
+bool valid_nodes(const misslam_nodes *nd) {
+    return nd && nd->m >= 1 && nd->m <= nd->capacity && nd->m < 65535 && nd->gx && nd->gy && nd->gz && nd->params;
+}
+
+bool valid_graph(const misslam_graph *g, int64_t n) {
+    return g && g->k >= 1 && g->k <= MISSLAM_MAX_K && g->bsr_cap >= 1 && g->row_ptr && g->col_idx && g->info &&
+           g->list_ptr && (n == 0 || (g->knn_idx && g->knn_w && g->list_pts && g->list_key));
+}
+
+bool valid_camera(const misslam_camera *c) {
+    return c && c->width >= 1 && c->height >= 1 && std::isfinite(c->fx) && std::isfinite(c->fy) && c->fx != 0.f &&
+           c->fy != 0.f && std::isfinite(c->cx) && std::isfinite(c->cy);
+}
+
+msl::PointsView view(const misslam_points *p) {
+    return msl::PointsView{p->px, p->py, p->pz, p->nx, p->ny, p->nz, p->n};
+}
+msl::NodesView view(const misslam_nodes *nd) { return msl::NodesView{nd->gx, nd->gy, nd->gz, nd->params, nd->m}; }
+msl::GraphView view(const misslam_graph *g) {
+    return msl::GraphView{g->k,        g->bsr_cap,  g->knn_idx,  g->knn_w, g->row_ptr,
+                          g->col_idx,  g->list_ptr, g->list_pts, reinterpret_cast<uint32_t *>(g->list_key), g->info};
+}
+msl::Cam view(const misslam_camera *c) { return msl::Cam{c->width, c->height, c->fx, c->fy, c->cx, c->cy}; }
+msl::Pose view(const misslam_pose *p) {
+    msl::Pose P;
+    std::memcpy(P.R, p->R, sizeof(P.R));
+    std::memcpy(P.T, p->T, sizeof(P.T));
+    return P;
+}
+
+hipStream_t stream_of(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+void misslam_default_params(misslam_params *p) {
+    if (!p) return;
+    p->k = 4;
+    p->weight_kind = MISSLAM_WEIGHT_GAUSS;
+    p->sigma = 1.0f;
+    p->w_rot = 1000.0f;
+    p->w_reg = 10000.0f;
+    p->w_data = 1.0f;
+    p->eps_d = 15.0;
+    p->cos_eps_n = std::cos(10.0 * 3.14159265358979323846 / 180.0);
+    p->lambda = 1e-3f;
+    p->gn_iters = 10;
+    p->pcg_iters = 10;
+    p->precision = MISSLAM_PREC_FP32;
+    p->refine_steps = 0;
+    p->reject_threshold = 0.0f;
+}
+
+const char *misslam_status_string(int32_t s) {
+    switch (s) {
+        case MISSLAM_OK: return "ok";
+        case MISSLAM_EINVAL: return "invalid argument";
+        case MISSLAM_ESHAPE: return "inconsistent sizes";
+        case MISSLAM_EWORKSPACE: return "workspace too small";
+        case MISSLAM_EHIP: return "HIP runtime error";
+        case MISSLAM_ECAPACITY: return "capacity too small";
+        case MISSLAM_EUNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+int32_t misslam_last_hip_error(void) { return g_last_hip; }
+
+size_t misslam_workspace_bytes(int64_t n, int32_t m, int32_t width, int32_t height, const misslam_params *params) {
+    if (n < 0 || m < 1 || width < 1 || height < 1 || !valid_params(params)) return 0;
+    return carve(nullptr, n, m, width, height, params->pcg_iters).bytes;
+}
+
+misslam_status misslam_normal_map(const float *depth, const misslam_camera *camera, float *out, void *stream) {
+    if (!depth || !out || !valid_camera(camera)) return MISSLAM_EINVAL;
+    Timed t(PH_NORMAL_MAP, stream_of(stream));
+    const hipError_t e = msl::launch_normal_map(depth, view(camera), reinterpret_cast<float4 *>(out), stream_of(stream));
+    return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
+}
+
+misslam_status misslam_build_graph(const misslam_points *points, const misslam_nodes *nodes,
+                                   const misslam_params *params, misslam_graph *graph, void *ws, size_t ws_bytes,
+                                   void *stream) {
+    if (!valid_points(points) || !valid_nodes(nodes) || !valid_params(params) || !valid_graph(graph, points->n) || !ws)
+        return MISSLAM_EINVAL;
+    if (graph->k != params->k || nodes->m < params->k) return MISSLAM_ESHAPE;
+    const Layout L = carve(ws, points->n, nodes->m, 1, 1, params->pcg_iters);
+    if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
+    Timed t(PH_GRAPH, stream_of(stream));
+    const hipError_t e = msl::launch_build_graph(view(points), view(nodes), params->k, params->weight_kind,
+                                                 params->sigma, view(graph), L.graph, stream_of(stream));
+    return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
+}
+
+misslam_status misslam_warp(const misslam_points *points, const misslam_nodes *nodes, const misslam_graph *graph,
+                            const misslam_pose *pose, float *out_pos, float *out_nrm, void *stream) {
+    if (!valid_points(points) || !valid_nodes(nodes) || !valid_graph(graph, points->n) || !out_pos)
+        return MISSLAM_EINVAL;
+    msl::Pose P{};
+    if (pose) P = view(pose);
+    const hipError_t e = msl::launch_warp(view(points), view(nodes), view(graph), pose ? &P : nullptr, out_pos,
+                                          out_nrm, stream_of(stream));
+    return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
+}
+
+static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, int64_t n, int m,
+                            misslam_report *rep, float reject, hipStream_t st) {
+    hipError_t e;
+    {
+        Timed t(PH_POINT_PASS, st);
+        e = msl::launch_point_pass(a, s, st);
+    }
+    if (e == hipSuccess) {
+        Timed t(PH_ASSEMBLE, st);
+        e = msl::launch_assemble(a, s, st);
+    }
+    if (e == hipSuccess) {
+        Timed t(PH_ENERGY, st);
+        e = msl::launch_energy_report(s, n, m, rep, reject, st);
+    }
+    return e;
+}
+
+static hipError_t solve(const msl::GraphView &g, int m, const float *blocks, const float *gvec, float *minv,
+                        float lambda, int iters, float *delta, const msl::PcgScratch &s, misslam_report *rep,
+                        float *params, hipStream_t st) {
+    hipError_t e;
+    {
+        Timed t(PH_BJACOBI, st);
+        e = msl::launch_bjacobi(g, m, blocks, lambda, minv, &rep->flags, st);
+    }
+    if (e == hipSuccess) {
+        Timed t(PH_PCG, st);
+        e = msl::launch_pcg_update(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st);
+    }
+    return e;
+}
+
+static msl::StepArgs step_args(const misslam_points *points, const misslam_nodes *nodes, const misslam_graph *graph,
+                               const float4 *nmap, const misslam_camera *camera, const misslam_pose *pose,
+                               const misslam_params *params, float *blocks, float *g, int32_t *corr) {
+    msl::StepArgs a;
+    a.pts = view(points);
+    a.nd = view(nodes);
+    a.g = view(graph);
+    a.nmap = nmap;
+    a.cam = view(camera);
+    a.pose = view(pose);
+    a.eps_d = params->eps_d;
+    a.cos_eps_n = params->cos_eps_n;
+    a.w_rot = params->w_rot;
+    a.w_reg = params->w_reg;
+    a.w_data = params->w_data;
+    a.lambda = params->lambda;
+    a.blocks = blocks;
+    a.gvec = g;
+    a.corr_out = corr;
+    a.minv = nullptr;
+    a.flags = nullptr;
+    return a;
+}
+
+misslam_status misslam_build_normal_eq(const misslam_points *points, const misslam_nodes *nodes,
+                                       const misslam_graph *graph, const float *nmap, const misslam_camera *camera,
+                                       const misslam_pose *pose, const misslam_params *params, float *blocks, float *g,
+                                       int32_t *corr, misslam_report *rep, void *ws, size_t ws_bytes, void *stream) {
+    if (!valid_points(points) || !valid_nodes(nodes) || !valid_graph(graph, points->n) || !nmap ||
+        !valid_camera(camera) || !pose || !valid_params(params) || !blocks || !g || !rep || !ws)
+        return MISSLAM_EINVAL;
+    if (graph->k != params->k) return MISSLAM_ESHAPE;
+    if (params->precision != MISSLAM_PREC_FP32) return MISSLAM_EUNSUPPORTED;
+    const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, params->pcg_iters);
+    if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
+    const hipStream_t st = stream_of(stream);
+    const msl::StepArgs a = step_args(points, nodes, graph, reinterpret_cast<const float4 *>(nmap), camera, pose,
+                                      params, blocks, g, corr);
+    hipError_t e = msl::launch_report_init(rep, 1, st);
+    if (e == hipSuccess) e = linearize(a, L.step, points->n, nodes->m, rep, params->reject_threshold, st);
+    return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
+}
+
+misslam_status misslam_pcg_solve(const misslam_graph *graph, int32_t m, const float *blocks, const float *g,
+                                 const misslam_params *params, float *delta, misslam_report *rep, void *ws,
+                                 size_t ws_bytes, void *stream) {
+    if (!graph || !graph->row_ptr || !graph->col_idx || m < 1 || m >= 65535 || !blocks || !g ||
+        !valid_params(params) || !delta || !rep || !ws)
+        return MISSLAM_EINVAL;
+    const Layout L = carve(ws, 0, m, 1, 1, params->pcg_iters);
+    if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
+    const hipStream_t st = stream_of(stream);
+    const msl::GraphView gv = view(graph);
+    hipError_t e = msl::launch_report_init(rep, 1, st);
+    if (e == hipSuccess)
+        e = solve(gv, m, blocks, g, L.step.minv, params->lambda, params->pcg_iters, delta, L.pcg, rep, nullptr, st);
+    return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
+}
+
+misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
+                                   const float *depth, const misslam_camera *camera, const misslam_pose *pose,
+                                   const misslam_params *params, misslam_report *rep, int32_t *corr_hist, void *ws,
+                                   size_t ws_bytes, void *stream) {
+    if (!valid_points(points) || !valid_nodes(nodes) || !valid_graph(graph, points->n) || !depth ||
+        !valid_camera(camera) || !pose || !valid_params(params) || !rep || !ws)
+        return MISSLAM_EINVAL;
+    if (graph->k != params->k) return MISSLAM_ESHAPE;
+    if (params->precision != MISSLAM_PREC_FP32) return MISSLAM_EUNSUPPORTED;
+    const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, params->pcg_iters);
+    if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
+    if ((int64_t)graph->bsr_cap > (int64_t)nodes->m * MISSLAM_MAX_ROW) return MISSLAM_ECAPACITY;
+    const hipStream_t st = stream_of(stream);
+    const int G = params->gn_iters;
+    const int64_t n = points->n;
+    const int m = nodes->m;
+    hipError_t e = msl::launch_report_init(rep, G + 1, st);
+    if (e == hipSuccess) {
+        Timed t(PH_NORMAL_MAP, st);
+        e = msl::launch_normal_map(depth, view(camera), L.nmap, st);
+    }
+    for (int it = 0; it <= G && e == hipSuccess; ++it) {
+        int32_t *corr = (corr_hist && it < G) ? corr_hist + (size_t)it * n : nullptr;
+        msl::StepArgs a = step_args(points, nodes, graph, L.nmap, camera, pose, params, L.blocks, L.gvec, corr);
+        if (it < G) {
+            a.minv = L.step.minv;     // block-Jacobi inverses come out of the assembly
+            a.flags = &rep[it].flags;
+        }
+        e = linearize(a, L.step, n, m, rep + it, params->reject_threshold, st);
+        if (it == G) break;
+        if (e == hipSuccess) {
+            Timed t(PH_PCG, st);
+            e = msl::launch_pcg_update(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda,
+                                       params->pcg_iters, L.delta, L.pcg, rep + it, nodes->params, st);
+        }
+    }
+    return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
+}
+
+int32_t misslam_profile_enable(int32_t on) {
+    Profiler &p = prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    const int32_t was = p.on;
+    p.on = on != 0;
+    return was;
+}
+
+misslam_status misslam_profile_get(const char *phase, double *total_ms, int64_t *launches) {
+    if (!phase || !total_ms || !launches) return MISSLAM_EINVAL;
+    Profiler &p = prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    for (int i = 0; i < PH_COUNT; ++i)
+        if (std::strcmp(phase, kPhaseNames[i]) == 0) {
+            p.collect();
+            *total_ms = p.total_ms[i];
+            *launches = p.launches[i];
+            return MISSLAM_OK;
+        }
+    return MISSLAM_EINVAL;
+}
+
+void misslam_profile_reset(void) {
+    Profiler &p = prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    p.collect();
+    for (int i = 0; i < PH_COUNT; ++i) {
+        p.total_ms[i] = 0.0;
+        p.launches[i] = 0;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,237 @@
+// Internal device helpers shared by the gfx950 kernels of libmisslam.
+//
+// Built with -ffp-contract=off: every float64 decision below (projection,
+// rounding, gates, nearest-node ordering) keeps the written operation order,
+// and float32 arithmetic that should fuse says so with fmaf().
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "misslam.h"
+
+namespace msl {
+
+constexpr int kWave = 64;
+
+struct Cam {
+    int W, H;
+    float fx, fy, cx, cy;
+};
+
+struct Pose {
+    float R[9];
+    float T[3];
+};
+
+struct PointsView {
+    const float *px, *py, *pz, *nx, *ny, *nz;
+    int64_t n;
+};
+
+struct NodesView {
+    const float *gx, *gy, *gz, *x;   // x: m x 12
+    int m;
+};
+
+// ---------------------------------------------------------------- Eq.(1): ED warp of one point
+
+// Blends the k node transforms of a point in kNN order (float32):
+//   y = sum_s w_s [A_s (v - g_s) + g_s + t_s]
+template <int K>
+__device__ __forceinline__ void ed_blend(float vx, float vy, float vz, const int32_t *idx, const float *w,
+                                         int64_t n, int64_t i, const NodesView &nd, float &ox, float &oy,
+                                         float &oz) {
+    ox = 0.f;
+    oy = 0.f;
+    oz = 0.f;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const int j = idx[(int64_t)s * n + i];
+        const float ws = w[(int64_t)s * n + i];
+        const float gx = nd.gx[j], gy = nd.gy[j], gz = nd.gz[j];
+        const float *x = nd.x + (size_t)j * 12;
+        const float dx = vx - gx, dy = vy - gy, dz = vz - gz;
+        // A d with A[:, c] = x[3c .. 3c+2]
+        float ax = fmaf(x[6], dz, fmaf(x[3], dy, x[0] * dx));
+        float ay = fmaf(x[7], dz, fmaf(x[4], dy, x[1] * dx));
+        float az = fmaf(x[8], dz, fmaf(x[5], dy, x[2] * dx));
+        ax = ax + gx + x[9];
+        ay = ay + gy + x[10];
+        az = az + gz + x[11];
+        ox = fmaf(ws, ax, ox);
+        oy = fmaf(ws, ay, oy);
+        oz = fmaf(ws, az, oz);
+    }
+}
+
+// Warped normal direction (unnormalised): sum_s w_s A_s^{-T} n, A^{-T} = cof(A) / det(A).
+template <int K>
+__device__ __forceinline__ void ed_blend_normal(float nx, float ny, float nz, const int32_t *idx, const float *w,
+                                                int64_t n, int64_t i, const NodesView &nd, float &ox, float &oy,
+                                                float &oz) {
+    ox = 0.f;
+    oy = 0.f;
+    oz = 0.f;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        const int j = idx[(int64_t)s * n + i];
+        const float ws = w[(int64_t)s * n + i];
+        const float *x = nd.x + (size_t)j * 12;
+        // A[a][c] = x[3c + a]
+        const float a00 = x[0], a10 = x[1], a20 = x[2];
+        const float a01 = x[3], a11 = x[4], a21 = x[5];
+        const float a02 = x[6], a12 = x[7], a22 = x[8];
+        // cofactor matrix C[a][c]; A^{-T} = C / det
+        const float c00 = a11 * a22 - a12 * a21, c01 = a12 * a20 - a10 * a22, c02 = a10 * a21 - a11 * a20;
+        const float c10 = a02 * a21 - a01 * a22, c11 = a00 * a22 - a02 * a20, c12 = a01 * a20 - a00 * a21;
+        const float c20 = a01 * a12 - a02 * a11, c21 = a02 * a10 - a00 * a12, c22 = a00 * a11 - a01 * a10;
+        const float det = a00 * c00 + a01 * c01 + a02 * c02;
+        const float sc = ws / det;
+        ox = fmaf(sc, c00 * nx + c01 * ny + c02 * nz, ox);
+        oy = fmaf(sc, c10 * nx + c11 * ny + c12 * nz, oy);
+        oz = fmaf(sc, c20 * nx + c21 * ny + c22 * nz, oz);
+    }
+}
+
+__device__ __forceinline__ void apply_pose(const Pose &P, float &x, float &y, float &z) {
+    const float X = x, Y = y, Z = z;
+    x = fmaf(P.R[2], Z, fmaf(P.R[1], Y, P.R[0] * X)) + P.T[0];
+    y = fmaf(P.R[5], Z, fmaf(P.R[4], Y, P.R[3] * X)) + P.T[1];
+    z = fmaf(P.R[8], Z, fmaf(P.R[7], Y, P.R[6] * X)) + P.T[2];
+}
+
+__device__ __forceinline__ void rotate(const Pose &P, float &x, float &y, float &z) {
+    const float X = x, Y = y, Z = z;
+    x = fmaf(P.R[2], Z, fmaf(P.R[1], Y, P.R[0] * X));
+    y = fmaf(P.R[5], Z, fmaf(P.R[4], Y, P.R[3] * X));
+    z = fmaf(P.R[8], Z, fmaf(P.R[7], Y, P.R[6] * X));
+}
+
+__device__ __forceinline__ void normalize3(float &x, float &y, float &z) {
+    const float s = sqrtf(x * x + y * y + z * z);
+    const float inv = s > 0.f ? 1.0f / s : 0.f;
+    x *= inv;
+    y *= inv;
+    z *= inv;
+}
+
+// ---------------------------------------------------------------- Eqs.(7)-(8): association
+
+struct Match {
+    int pix;        // v*W + u, or -1
+    float r;        // point-to-plane residual N . (v~ - V)
+    float Nx, Ny, Nz;
+};
+
+// Projects a warped camera-frame point to its nearest pixel and applies the
+// visibility gates; every decision is float64 in a fixed order.
+//   u_f = (x / z) fx + cx, u = floor(u_f + 0.5); likewise v
+//   valid: z > 0, pixel inside, D > 0, normal present,
+//          |v~ - V| < eps_d and n~ . N > cos_eps_n (both strict)
+// nmap holds (Nx, Ny, Nz, D) per pixel.
+__device__ __forceinline__ Match associate(float vx, float vy, float vz, float nx, float ny, float nz,
+                                           const float4 *__restrict__ nmap, const Cam &cam, double eps_d,
+                                           double cos_eps_n) {
+    Match out{-1, 0.f, 0.f, 0.f, 0.f};
+    const double x = vx, y = vy, z = vz;
+    if (!(z > 0.0)) return out;
+    const double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy;
+    const double uf = (x / z) * fx + cx;
+    const double vf = (y / z) * fy + cy;
+    const double uu = floor(uf + 0.5);
+    const double vv = floor(vf + 0.5);
+    if (!(uu >= 0.0 && uu < (double)cam.W && vv >= 0.0 && vv < (double)cam.H)) return out;
+    const int u = (int)uu, v = (int)vv;
+    const float4 q = nmap[(size_t)v * cam.W + u];
+    const double d = q.w;
+    if (!(d > 0.0)) return out;
+    if (q.x == 0.f && q.y == 0.f && q.z == 0.f) return out;
+    const double Vx = d * (((double)u - cx) / fx);
+    const double Vy = d * (((double)v - cy) / fy);
+    const double Vz = d;
+    const double dx = x - Vx, dy = y - Vy, dz = z - Vz;
+    const double dist = sqrt((dx * dx + dy * dy) + dz * dz);
+    const double Nx = q.x, Ny = q.y, Nz = q.z;
+    const double nd = ((double)nx * Nx + (double)ny * Ny) + (double)nz * Nz;
+    if (!(dist < eps_d && nd > cos_eps_n)) return out;
+    out.pix = v * cam.W + u;
+    out.r = (float)((Nx * dx + Ny * dy) + Nz * dz);
+    out.Nx = q.x;
+    out.Ny = q.y;
+    out.Nz = q.z;
+    return out;
+}
+
+// ---------------------------------------------------------------- deterministic block reductions
+
+// Sum of one double per thread over a block of BS threads, fixed tree order.
+// Every thread returns the total.  lds must hold BS doubles.
+template <int BS>
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+    lds[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = BS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double t = lds[0];
+    __syncthreads();
+    return t;
+}
+
+// ---------------------------------------------------------------- damped block inverse (block-Jacobi)
+
+// Orders the LDS traffic of one wave (its lanes' writes before other lanes'
+// reads); LDS operations of a wave complete in issue order.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// M = A^-1 for one SPD 12x12 block held in LDS as float64, by one wave (all
+// 64 lanes call it).  A is overwritten by its Cholesky factor L (lower
+// triangle); M = L^-T L^-1 goes to out (row-major 144 float32).  Returns false
+// on every lane when a pivot is not positive, and M is then I.
+__device__ __forceinline__ bool chol_inverse_wave(double (*A)[12], double (*Li)[12], float *out) {
+    const int lane = threadIdx.x % 64;
+    bool bad = false;
+    for (int k = 0; k < 12; ++k) {
+        const double d = A[k][k];
+        bad = bad || !(d > 0.0);
+        const double lkk = d > 0.0 ? sqrt(d) : 1.0;
+        wave_sync();
+        if (lane == 0) A[k][k] = lkk;
+        if (lane > k && lane < 12) A[lane][k] = A[lane][k] / lkk;
+        wave_sync();
+        for (int t = lane; t < 144; t += 64) {
+            const int i = t / 12, c = t % 12;
+            if (c > k && c <= i) A[i][c] = A[i][c] - A[i][k] * A[c][k];
+        }
+        wave_sync();
+    }
+    if (lane < 12) {
+        const int c = lane;
+        for (int i = 0; i < 12; ++i) {
+            if (i < c) {
+                Li[i][c] = 0.0;
+                continue;
+            }
+            double s = i == c ? 1.0 : 0.0;
+            for (int t = c; t < i; ++t) s -= A[i][t] * Li[t][c];
+            Li[i][c] = s / A[i][i];
+        }
+    }
+    wave_sync();
+    for (int t = lane; t < 144; t += 64) {
+        const int i = t / 12, k = t % 12;
+        double s = 0.0;
+        for (int q = i > k ? i : k; q < 12; ++q) s += Li[q][i] * Li[q][k];
+        out[t] = bad ? (i == k ? 1.f : 0.f) : (float)s;
+    }
+    return !bad;
+}
+
+}  // namespace msl

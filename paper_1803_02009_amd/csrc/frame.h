@@ -1,0 +1,75 @@
+// Internal declarations shared by the host layer and the kernel files of libmisslam.
+#pragma once
+
+#include "common.h"
+
+namespace msl {
+
+struct GraphView {
+    int k, bsr_cap;
+    int32_t *knn_idx;
+    float *knn_w;
+    int32_t *row_ptr, *col_idx, *list_ptr, *list_pts;
+    uint32_t *list_key;   // 2 words per list entry
+    int32_t *info;
+};
+
+struct GraphScratch {
+    int32_t *tmp;     // m x MISSLAM_MAX_ROW row columns
+    int32_t *cnt;     // 2m + 8
+};
+
+// Per-iteration scratch of the registration step.
+struct StepScratch {
+    float4 *nr;           // n: (R^T N of the matched pixel, point-to-plane residual); 0 when unmatched
+    int32_t *corr;        // n
+    double *pt_part;      // 3 per point block: sum r^2, count, sum |r|
+    double *node_part;    // 2 per node: rot and reg energy of the node's terms
+    float *minv;          // m x 144 block-Jacobi inverses
+    int32_t *flags;       // 4 ints of device flags
+};
+
+struct PcgScratch {
+    float *r, *z, *p, *q;  // 12m each
+    double *part;          // (pcg_iters + 1) x 4 x nblk partial sums
+    int32_t *status;       // 2 x (pcg_iters + 2): stop status, then per-iteration "updated" flags
+    int nblk;
+};
+
+hipError_t launch_normal_map(const float *depth, const Cam &cam, float4 *out, hipStream_t st);
+hipError_t launch_build_graph(const PointsView &pts, const NodesView &nd, int k, int wkind, float sigma,
+                              const GraphView &g, const GraphScratch &s, hipStream_t st);
+hipError_t launch_warp(const PointsView &pts, const NodesView &nd, const GraphView &g, const Pose *pose,
+                       float *out_pos, float *out_nrm, hipStream_t st);
+
+struct StepArgs {
+    PointsView pts;
+    NodesView nd;
+    GraphView g;
+    const float4 *nmap;
+    Cam cam;
+    Pose pose;
+    double eps_d, cos_eps_n;
+    float w_rot, w_reg, w_data, lambda;
+    float *blocks;     // nnzb x 144
+    float *gvec;       // 12 m
+    int32_t *corr_out; // optional copy of correspondences
+    float *minv;       // optional m x 144 block-Jacobi inverses computed with the assembly
+    int32_t *flags;    // report flags (NONSPD_BLOCK) when minv is set
+};
+
+hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_t st);
+hipError_t launch_assemble(const StepArgs &a, const StepScratch &s, hipStream_t st);
+hipError_t launch_energy_report(const StepScratch &s, int64_t n, int m, misslam_report *rep, float reject_thr,
+                                hipStream_t st);
+hipError_t launch_bjacobi(const GraphView &g, int m, const float *blocks, float lambda, float *minv,
+                          int32_t *flags, hipStream_t st);
+// PCG solve into delta; when params != nullptr also applies params += delta (the GN update).
+hipError_t launch_pcg_update(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
+                             float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
+                             float *params, hipStream_t st);
+hipError_t launch_report_init(misslam_report *rep, int count, hipStream_t st);
+int pcg_blocks(int m);
+hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t st);
+
+}  // namespace msl

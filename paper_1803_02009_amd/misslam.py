@@ -1,0 +1,215 @@
+"""Tensor-level Python binding of libmisslam: same names as the C entry points.
+
+PyTorch provides device memory and the current HIP stream; every step of the
+method runs in the library's gfx950 kernels.  Layouts:
+  points  (6, N) float32 cuda: rows px, py, pz, nx, ny, nz (canonical frame)
+  nodes   (3, m) float32 cuda: rows gx, gy, gz
+  x       (m, 12) float32 cuda: node parameters (c1, c2, c3, t)
+  depth   (H, W) float32 cuda
+"""
+import ctypes
+import dataclasses
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, load
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, name):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+
+
+@dataclasses.dataclass
+class Params:
+    """Solver settings (paper defaults, Sec. III-B)."""
+    k: int = 4
+    weight_kind: int = _lib.WEIGHT_GAUSS
+    sigma: float = 1.0
+    w_rot: float = 1000.0
+    w_reg: float = 10000.0
+    w_data: float = 1.0
+    eps_d: float = 15.0
+    cos_eps_n: float = math.cos(math.radians(10.0))
+    lam: float = 1e-3
+    gn_iters: int = 10
+    pcg_iters: int = 10
+    precision: int = _lib.PREC_FP32
+    refine_steps: int = 0
+    reject_threshold: float = 0.0
+
+    def c(self):
+        return _lib.Params(self.k, self.weight_kind, self.sigma, self.w_rot, self.w_reg, self.w_data, self.eps_d,
+                           self.cos_eps_n, self.lam, self.gn_iters, self.pcg_iters, self.precision,
+                           self.refine_steps, self.reject_threshold)
+
+
+def camera(width, height, fx, fy, cx, cy):
+    return _lib.Camera(int(width), int(height), float(fx), float(fy), float(cx), float(cy))
+
+
+def pose(R, T):
+    R = np.asarray(R, dtype=np.float32).reshape(9)
+    T = np.asarray(T, dtype=np.float32).reshape(3)
+    return _lib.Pose((ctypes.c_float * 9)(*R.tolist()), (ctypes.c_float * 3)(*T.tolist()))
+
+
+def points_struct(points, w=None, stamp=None, capacity=None):
+    _need(points, torch.float32, "points")
+    n = points.shape[1]
+    base = points.data_ptr()
+    cap = n if capacity is None else capacity
+    row = points.stride(0) * 4
+    return _lib.Points(n, cap, base, base + row, base + 2 * row, base + 3 * row, base + 4 * row, base + 5 * row,
+                       w.data_ptr() if w is not None else 0, stamp.data_ptr() if stamp is not None else 0)
+
+
+def nodes_struct(nodes, x):
+    _need(nodes, torch.float32, "nodes")
+    _need(x, torch.float32, "x")
+    m = nodes.shape[1]
+    base = nodes.data_ptr()
+    row = nodes.stride(0) * 4
+    return _lib.Nodes(m, m, base, base + row, base + 2 * row, x.data_ptr())
+
+
+def identity_params(m, device="cuda"):
+    x = torch.zeros((m, 12), dtype=torch.float32, device=device)
+    x[:, 0] = 1.0
+    x[:, 4] = 1.0
+    x[:, 8] = 1.0
+    return x
+
+
+class Workspace:
+    """Caller-owned scratch for the library (grown on demand, never shrunk)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes):
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        return self.buf
+
+
+def workspace_bytes(n, m, width, height, params):
+    return int(load().misslam_workspace_bytes(n, m, width, height, ctypes.byref(params.c())))
+
+
+class Graph:
+    """Per-frame graph tensors (see misslam_graph in include/misslam.h)."""
+
+    def __init__(self, k, n, m, bsr_cap=None, device="cuda"):
+        self.k, self.n, self.m = k, n, m
+        self.bsr_cap = int(bsr_cap if bsr_cap is not None else m * _lib.MAX_ROW)
+        i32 = dict(dtype=torch.int32, device=device)
+        self.knn_idx = torch.empty((k, max(n, 1)), **i32)
+        self.knn_w = torch.empty((k, max(n, 1)), dtype=torch.float32, device=device)
+        self.row_ptr = torch.empty(m + 1, **i32)
+        self.col_idx = torch.empty(self.bsr_cap, **i32)
+        self.list_ptr = torch.empty(m + 1, **i32)
+        self.list_pts = torch.empty(max(k * n, 1), **i32)
+        self.list_key = torch.empty(max(2 * k * n, 2), **i32)
+        self.info = torch.zeros(8, **i32)
+
+    def c(self):
+        return _lib.Graph(self.k, self.bsr_cap, self.knn_idx.data_ptr(), self.knn_w.data_ptr(),
+                          self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.list_ptr.data_ptr(),
+                          self.list_pts.data_ptr(), self.list_key.data_ptr(), self.info.data_ptr())
+
+
+REPORT_DTYPE = np.dtype([("e_data", "<f8"), ("e_rot", "<f8"), ("e_reg", "<f8"),
+                         ("pcg_resid", "<f8", (_lib.MAX_PCG + 1,)), ("n_valid", "<i4"), ("flags", "<i4"),
+                         ("pcg_iters_done", "<i4"), ("reserved", "<i4")])
+assert REPORT_DTYPE.itemsize == ctypes.sizeof(_lib.Report)
+
+
+def new_report(count):
+    return torch.zeros(count * REPORT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+
+
+def read_report(rep):
+    """Device report buffer -> numpy structured array (synchronises)."""
+    return np.frombuffer(rep.cpu().numpy().tobytes(), dtype=REPORT_DTYPE)
+
+
+# ------------------------------------------------------------------------------ entry points
+
+def normal_map(depth, cam):
+    _need(depth, torch.float32, "depth")
+    out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device=depth.device)
+    check("misslam_normal_map", load().misslam_normal_map(_ptr(depth), ctypes.byref(cam), _ptr(out), _stream()))
+    return out
+
+
+def build_graph(points, nodes, params, ws, bsr_cap=None):
+    n, m = points.shape[1], nodes.shape[1]
+    g = Graph(params.k, n, m, bsr_cap)
+    x = identity_params(m)
+    pc = params.c()
+    nb = workspace_bytes(n, m, 1, 1, params)
+    buf = ws.get(nb)
+    check("misslam_build_graph", load().misslam_build_graph(
+        ctypes.byref(points_struct(points)), ctypes.byref(nodes_struct(nodes, x)), ctypes.byref(pc),
+        ctypes.byref(g.c()), _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
+    return g
+
+
+def warp(points, nodes, x, graph, pose_=None, normals=True):
+    n = points.shape[1]
+    pos = torch.empty((3, n), dtype=torch.float32, device=points.device)
+    nrm = torch.empty((3, n), dtype=torch.float32, device=points.device) if normals else None
+    pz = ctypes.byref(pose_) if pose_ is not None else None
+    check("misslam_warp", load().misslam_warp(
+        ctypes.byref(points_struct(points)), ctypes.byref(nodes_struct(nodes, x)), ctypes.byref(graph.c()), pz,
+        _ptr(pos), _ptr(nrm), _stream()))
+    return pos, nrm
+
+
+def build_normal_eq(points, nodes, x, graph, nmap, cam, pose_, params, ws):
+    n, m = points.shape[1], nodes.shape[1]
+    blocks = torch.zeros((graph.bsr_cap, 12, 12), dtype=torch.float32, device=points.device)
+    g = torch.empty((m, 12), dtype=torch.float32, device=points.device)
+    corr = torch.empty(max(n, 1), dtype=torch.int32, device=points.device)
+    rep = new_report(1)
+    buf = ws.get(workspace_bytes(n, m, cam.width, cam.height, params))
+    check("misslam_build_normal_eq", load().misslam_build_normal_eq(
+        ctypes.byref(points_struct(points)), ctypes.byref(nodes_struct(nodes, x)), ctypes.byref(graph.c()),
+        _ptr(nmap), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(params.c()), _ptr(blocks), _ptr(g),
+        _ptr(corr), _ptr(rep), _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
+    return blocks, g, corr[:n], rep
+
+
+def pcg_solve(graph, m, blocks, g, params, ws):
+    delta = torch.empty((m, 12), dtype=torch.float32, device=blocks.device)
+    rep = new_report(1)
+    buf = ws.get(workspace_bytes(0, m, 1, 1, params))
+    check("misslam_pcg_solve", load().misslam_pcg_solve(
+        ctypes.byref(graph.c()), m, _ptr(blocks), _ptr(g), ctypes.byref(params.c()), _ptr(delta), _ptr(rep),
+        _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
+    return delta, rep
+
+
+def gn_register(points, nodes, x, graph, depth, cam, pose_, params, ws, corr_hist=False):
+    """Runs params.gn_iters Gauss-Newton steps, updating x in place; returns (report, corr_hist or None)."""
+    n, m = points.shape[1], nodes.shape[1]
+    rep = new_report(params.gn_iters + 1)
+    ch = torch.empty((params.gn_iters, n), dtype=torch.int32, device=points.device) if corr_hist else None
+    buf = ws.get(workspace_bytes(n, m, cam.width, cam.height, params))
+    check("misslam_gn_register", load().misslam_gn_register(
+        ctypes.byref(points_struct(points)), ctypes.byref(nodes_struct(nodes, x)), ctypes.byref(graph.c()),
+        _ptr(depth), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(params.c()), _ptr(rep), _ptr(ch),
+        _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
+    return rep, ch
