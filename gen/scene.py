@@ -55,6 +55,9 @@ SPECS = {
     # 640x480, 250k points at 0.2 mm, 1600 nodes at 2.5 mm, bumps + breathing.
     "c3": SceneSpec("c3", 640, 480, 256.0, 256.0, 320.0, 240.0, (-62.5, 62.5, -40.0, 40.0),
                     (625, 400), 0.02, (50, 32), 2.5, "breathing", (2, 4), 5.0, 8.0, 0.2 * 60 / 256, 10, 10, 3),
+    # ragged sizes for edge-case tests: point and node counts that fill no tile evenly
+    "ragged": SceneSpec("ragged", 64, 48, 60.0, 60.0, 32.0, 24.0, (-21.0, 21.0, -15.0, 15.0),
+                        (37, 29), 0.1, (7, 5), 6.0, "smooth", (1, 2), 3.0, 3.0, 0.2, 4, 15, 7),
 }
 
 

@@ -235,6 +235,26 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
                                    const misslam_params *params, misslam_report *rep,
                                    int32_t *corr_hist, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Model update after registration (Sec. II-G, Alg. 1-2, Eqs.(12), (14), (15)).
+ * Deforms every point and normal with the frame's final node parameters
+ * (world frame, Eq.(1) without the pose), projects them with the pose and
+ * keeps per pixel the nearest point (float32 depth, ties to the lower index:
+ * the registration map of Alg. 2 step 2).  A winner is registered when the
+ * pixel has depth and a normal, |z~ - D| < tau and n~ . N > cos_delta
+ * (float64, Alg. 1); it is fused: p <- (w p~ + R^T(V - T)) / (w + 1),
+ * n <- normalize((w n~ + R^T N) / (w + 1)), w <- min(w + 1, w_max),
+ * stamp <- frame.  All other points take their deformed position and normal.
+ * points (in/out) must carry w and stamp.  nodes (in/out): g_j <- g_j + t_j,
+ * params reset to A = I, t = 0.  nmap is misslam_normal_map of this depth.
+ * reg_map (height x width int32, winner point or -1) and registered (n int32,
+ * 1/0) are optional outputs.
+ */
+misslam_status misslam_fuse(misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
+                            const float *nmap, const misslam_camera *camera, const misslam_pose *pose,
+                            const misslam_fuse_params *fp, int32_t *reg_map, int32_t *registered, void *ws,
+                            size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------ profiling */
 
 /*
@@ -242,7 +262,7 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
  * launches of every phase it runs with HIP events on its own stream (not
  * allowed during stream capture).  Phases: "normal_map", "build_graph",
  * "point_pass", "assemble", "energy", "bjacobi", "pcg" (the whole PCG solve,
- * including the parameter update).  misslam_profile_get synchronises the
+ * including the parameter update), "fuse".  misslam_profile_get synchronises the
  * recorded events and returns the accumulated milliseconds and number of
  * bracketed launches since the last reset.  Returns the previous state.
  */

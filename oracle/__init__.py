@@ -28,5 +28,5 @@ from .system import (data_jacobian_rows, rot_jacobian, reg_jacobian, dense_syste
 from .pcg import block_jacobi, pcg, cholesky_solve  # noqa: F401
 from .gn import gn_register, Problem  # noqa: F401
 from .grad import energy_grad_params, energy_grad_points, total_energy_fixed  # noqa: F401
-from .fuse import fuse  # noqa: F401
+from .fuse import fuse, fuse_warped, zbuffer  # noqa: F401
 from .mixed import round_bf16, round_fp16  # noqa: F401

@@ -26,13 +26,18 @@ from .warp import ed_warp, split, warp_normals
 
 
 def zbuffer(vc, inside, ui, vi, W, H):
-    """Winner point index per pixel (-1 = none): smallest camera z, then lowest index."""
+    """Winner point index per pixel (-1 = none): smallest camera z, then lowest index.
+
+    Reading: depths are compared at float32 resolution (the precision the
+    model is stored in); equal float32 depths go to the lower point index.
+    """
     win = np.full(W * H, -1, dtype=np.int64)
     pts = np.nonzero(inside)[0]
     if len(pts) == 0:
         return win
     pix = vi[pts] * W + ui[pts]
-    order = np.lexsort((pts, vc[pts, 2], pix))     # by pixel, then z, then index
+    z32 = np.asarray(vc[pts, 2], dtype=np.float32)
+    order = np.lexsort((pts, z32, pix))            # by pixel, then z, then index
     pix_s = pix[order]
     first = np.ones(len(order), dtype=bool)
     first[1:] = pix_s[1:] != pix_s[:-1]
@@ -40,22 +45,26 @@ def zbuffer(vc, inside, ui, vi, W, H):
     return win
 
 
-def fuse(points, normals, weight, stamp, nodes, params, idx, w, depth, camera, R, T, Nmap, Nvalid,
-         frame, tau=10.0, cos_delta=float(np.cos(np.deg2rad(10.0))), w_max=20.0):
-    """Returns dict(points, normals, weight, stamp, nodes, registered (N,) bool, reg (H*W,) winners)."""
+def fuse_warped(vw, nw, vc, nc, weight, stamp, depth, camera, R, T, Nmap, Nvalid, frame,
+                tau=10.0, cos_delta=float(np.cos(np.deg2rad(10.0))), w_max=20.0):
+    """Alg. 1-2 steps 2-3 and Eqs.(12), (14), (15) for an already warped model.
+
+    vw, nw: warped points and unit normals in world coordinates; vc, nc: the same
+    in the camera frame.  Returns dict(points, normals, weight, stamp,
+    registered (N,) bool, reg (H*W,) winner per pixel).
+    """
     W, H = camera[0], camera[1]
     Rm = np.asarray(R, dtype=np.float64)
     Tv = np.asarray(T, dtype=np.float64)
-    vw = ed_warp(points, nodes, params, idx, w)             # world
-    nw = warp_normals(normals, params, idx, w)
-    vc = vw @ Rm.T + Tv
-    nc = nw @ Rm.T
+    vw = np.asarray(vw, dtype=np.float64)
+    nw = np.asarray(nw, dtype=np.float64)
+    vc = np.asarray(vc, dtype=np.float64)
+    nc = np.asarray(nc, dtype=np.float64)
     ui, vi, _, _, inside = project(vc, camera)
     win = zbuffer(vc, inside, ui, vi, W, H)
     n = vw.shape[0]
     is_winner = np.zeros(n, dtype=bool)
-    ids = win[win >= 0]
-    is_winner[ids] = True
+    is_winner[win[win >= 0]] = True
     D = np.asarray(depth, dtype=np.float64)
     d = D[vi, ui]
     Np = np.asarray(Nmap, dtype=np.float64)[vi, ui]
@@ -70,7 +79,21 @@ def fuse(points, normals, weight, stamp, nodes, params, idx, w, depth, camera, R
     nn = nn / np.linalg.norm(nn, axis=1, keepdims=True)
     om_new = np.where(reg, np.minimum(om + 1.0, w_max), om)
     st_new = np.where(reg, frame, np.asarray(stamp))
+    return {"points": p_new, "normals": nn, "weight": om_new, "stamp": st_new, "registered": reg, "reg": win}
+
+
+def fuse(points, normals, weight, stamp, nodes, params, idx, w, depth, camera, R, T, Nmap, Nvalid,
+         frame, tau=10.0, cos_delta=float(np.cos(np.deg2rad(10.0))), w_max=20.0):
+    """Deform the model with the frame's final parameters, then fuse (see fuse_warped).
+
+    Also returns the moved nodes g_j + t_j.
+    """
+    Rm = np.asarray(R, dtype=np.float64)
+    Tv = np.asarray(T, dtype=np.float64)
+    vw = ed_warp(points, nodes, params, idx, w)             # world
+    nw = warp_normals(normals, params, idx, w)
+    out = fuse_warped(vw, nw, vw @ Rm.T + Tv, nw @ Rm.T, weight, stamp, depth, camera, R, T, Nmap, Nvalid, frame,
+                      tau, cos_delta, w_max)
     _, t = split(params)
-    g_new = np.asarray(nodes, dtype=np.float64) + t
-    return {"points": p_new, "normals": nn, "weight": om_new, "stamp": st_new, "nodes": g_new,
-            "registered": reg, "reg": win}
+    out["nodes"] = np.asarray(nodes, dtype=np.float64) + t
+    return out

@@ -86,6 +86,8 @@ SIGNATURES = {
     "misslam_pcg_solve": (st, [P(Graph), ctypes.c_int32, vp, vp, P(Params), vp, vp, vp, ctypes.c_size_t, vp]),
     "misslam_gn_register": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params), vp, vp, vp,
                                  ctypes.c_size_t, vp]),
+    "misslam_fuse": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(FuseParams), vp, vp, vp,
+                          ctypes.c_size_t, vp]),
     "misslam_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "misslam_profile_get": (st, [ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int64)]),
     "misslam_profile_reset": (None, []),

@@ -12,9 +12,9 @@ namespace {
 
 // ---------------------------------------------------------------- phase timers (profiling only)
 
-enum Phase { PH_NORMAL_MAP, PH_GRAPH, PH_POINT_PASS, PH_ASSEMBLE, PH_ENERGY, PH_BJACOBI, PH_PCG, PH_COUNT };
+enum Phase { PH_NORMAL_MAP, PH_GRAPH, PH_POINT_PASS, PH_ASSEMBLE, PH_ENERGY, PH_BJACOBI, PH_PCG, PH_FUSE, PH_COUNT };
 const char *const kPhaseNames[PH_COUNT] = {"normal_map", "build_graph", "point_pass", "assemble",
-                                           "energy",     "bjacobi",     "pcg"};
+                                           "energy",     "bjacobi",     "pcg",        "fuse"};
 
 struct Profiler {
     std::mutex mu;
@@ -108,6 +108,9 @@ struct Layout {
     msl::PcgScratch pcg;
     msl::GraphScratch graph;
     float4 *nmap;
+    float *fuse_tmp;
+    int32_t *fuse_pix;
+    unsigned long long *zbuf;
     float *blocks;
     float *gvec;
     float *delta;
@@ -119,6 +122,7 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
     Layout L{};
     const int64_t npb = (n + 255) / 256 + 1;
     const int nblk = msl::pcg_blocks(m > 0 ? m : 1);
+    const int nblk_max = nblk > 4096 ? nblk : 4096;
     L.nmap = c.take<float4>((size_t)W * H);
     L.step.nr = c.take<float4>((size_t)n);
     L.step.corr = c.take<int32_t>((size_t)n);
@@ -133,10 +137,14 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
     L.pcg.z = c.take<float>((size_t)12 * m);
     L.pcg.p = c.take<float>((size_t)12 * m);
     L.pcg.q = c.take<float>((size_t)12 * m);
-    L.pcg.part = c.take<double>((size_t)(pcg_iters + 2) * 4 * nblk);
+    L.pcg.part = c.take<double>((size_t)(pcg_iters + 2) * 4 * nblk_max);
     L.pcg.status = c.take<int32_t>((size_t)2 * (pcg_iters + 2));
     L.pcg.nblk = nblk;
+    L.pcg.nblk_max = nblk_max;
     L.graph.tmp = c.take<int32_t>((size_t)m * MISSLAM_MAX_ROW);
+    L.fuse_tmp = c.take<float>((size_t)6 * n);
+    L.fuse_pix = c.take<int32_t>((size_t)n);
+    L.zbuf = c.take<unsigned long long>((size_t)W * H);
     L.graph.cnt = c.take<int32_t>((size_t)2 * m + 8);
     L.bytes = align_up(c.off);
     return L;
@@ -386,10 +394,59 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
         if (it == G) break;
         if (e == hipSuccess) {
             Timed t(PH_PCG, st);
-            e = msl::launch_pcg_update(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda,
-                                       params->pcg_iters, L.delta, L.pcg, rep + it, nodes->params, st);
+            bool used = false;
+            e = msl::launch_pcg_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda,
+                                           params->pcg_iters, L.delta, L.pcg, rep + it, nodes->params, st, &used);
+            if (e == hipSuccess && !used)
+                e = msl::launch_pcg_update(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda,
+                                           params->pcg_iters, L.delta, L.pcg, rep + it, nodes->params, st);
         }
     }
+    return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
+}
+
+misslam_status misslam_fuse(misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
+                            const float *nmap, const misslam_camera *camera, const misslam_pose *pose,
+                            const misslam_fuse_params *fp, int32_t *reg_map, int32_t *registered, void *ws,
+                            size_t ws_bytes, void *stream) {
+    if (!valid_points(points) || !valid_nodes(nodes) || !valid_graph(graph, points->n) || !nmap ||
+        !valid_camera(camera) || !pose || !fp || !ws || (points->n > 0 && (!points->w || !points->stamp)) ||
+        !std::isfinite(fp->tau) || !std::isfinite(fp->cos_delta) || !(fp->w_max > 0.f))
+        return MISSLAM_EINVAL;
+    misslam_params dp;
+    misslam_default_params(&dp);
+    const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, dp.pcg_iters);
+    if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
+    msl::FuseArgs f;
+    f.pts = view(points);
+    f.nd = view(nodes);
+    f.g = view(graph);
+    f.nmap = reinterpret_cast<const float4 *>(nmap);
+    f.cam = view(camera);
+    f.pose = view(pose);
+    for (int t = 0; t < 9; ++t) f.Rd[t] = pose->R[t];
+    for (int t = 0; t < 3; ++t) f.Td[t] = pose->T[t];
+    f.tau = fp->tau;
+    f.cos_delta = fp->cos_delta;
+    f.w_max = fp->w_max;
+    f.frame = fp->frame;
+    f.w_in = points->w;
+    f.stamp_in = points->stamp;
+    f.out_px = points->px;
+    f.out_py = points->py;
+    f.out_pz = points->pz;
+    f.out_nx = points->nx;
+    f.out_ny = points->ny;
+    f.out_nz = points->nz;
+    f.out_w = points->w;
+    f.out_stamp = points->stamp;
+    f.registered = registered;
+    f.tmp = L.fuse_tmp;
+    f.pix = L.fuse_pix;
+    f.zbuf = L.zbuf;
+    Timed t(PH_FUSE, stream_of(stream));
+    const hipError_t e = msl::launch_fuse(f, nodes->gx, nodes->gy, nodes->gz, nodes->params, nodes->m, reg_map,
+                                          stream_of(stream));
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
 }
 

@@ -33,7 +33,8 @@ struct PcgScratch {
     float *r, *z, *p, *q;  // 12m each
     double *part;          // (pcg_iters + 1) x 4 x nblk partial sums
     int32_t *status;       // 2 x (pcg_iters + 2): stop status, then per-iteration "updated" flags
-    int nblk;
+    int nblk;              // workgroups of the multi-kernel path
+    int nblk_max;          // partial slots per reduction (>= every path's workgroup count)
 };
 
 hipError_t launch_normal_map(const float *depth, const Cam &cam, float4 *out, hipStream_t st);
@@ -58,6 +59,30 @@ struct StepArgs {
     int32_t *flags;    // report flags (NONSPD_BLOCK) when minv is set
 };
 
+struct FuseArgs {
+    PointsView pts;
+    NodesView nd;
+    GraphView g;
+    const float4 *nmap;
+    Cam cam;
+    Pose pose;
+    double Rd[9], Td[3];
+    double tau, cos_delta;
+    float w_max;
+    int frame;
+    const float *w_in;
+    const int32_t *stamp_in;
+    float *out_px, *out_py, *out_pz, *out_nx, *out_ny, *out_nz, *out_w;
+    int32_t *out_stamp;
+    int32_t *registered;           // optional, n
+    float *tmp;                    // 6 x n: world warp and unnormalised warped normal
+    int32_t *pix;                  // n
+    unsigned long long *zbuf;      // H x W
+};
+
+hipError_t launch_fuse(const FuseArgs &f, float *gx, float *gy, float *gz, float *params, int m, int32_t *reg_map,
+                       hipStream_t st);
+
 hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_t st);
 hipError_t launch_assemble(const StepArgs &a, const StepScratch &s, hipStream_t st);
 hipError_t launch_energy_report(const StepScratch &s, int64_t n, int m, misslam_report *rep, float reject_thr,
@@ -69,6 +94,11 @@ hipError_t launch_pcg_update(const GraphView &g, int m, const float *blocks, con
                              float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
                              float *params, hipStream_t st);
 hipError_t launch_report_init(misslam_report *rep, int count, hipStream_t st);
+// Same solve as launch_pcg_update in one cooperative launch; *used = false when
+// the device cannot co-schedule it (nothing launched, caller falls back).
+hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
+                                 float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
+                                 float *params, hipStream_t st, bool *used);
 int pcg_blocks(int m);
 hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t st);
 

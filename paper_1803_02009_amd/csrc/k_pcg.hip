@@ -8,6 +8,8 @@
 // reproducible.  The recurrence is the textbook PCG with the direction
 // product folded as q = A z + beta q (A p with p = z + beta p, unchanged in
 // exact arithmetic), which needs one workgroup-wide sync less per iteration.
+#include <hip/hip_cooperative_groups.h>
+
 #include "frame.h"
 
 namespace msl {
@@ -281,5 +283,209 @@ hipError_t launch_report_init(misslam_report *rep, int count, hipStream_t st) {
 }
 
 int pcg_blocks(int m) { return (m + kRowsPerBlk - 1) / kRowsPerBlk; }
+
+// ---------------------------------------------------------------- persistent PCG (one cooperative launch)
+
+constexpr int kPersistLdsBytes = 64 * 1024;
+
+// The same recurrence in one launch: each workgroup owns a contiguous range of
+// rows, keeps their blocks (as many as fit) and their preconditioner blocks in
+// LDS and its slice of x, r, p, q in LDS; only z travels through global memory.
+// Two grid-wide barriers per iteration; every reduction is re-added by every
+// workgroup in the same order, so all take identical decisions.
+__global__ void __launch_bounds__(kPcgThreads) pcg_persistent_kernel(PcgArgs A, int rows_per_wg, int cache_blocks,
+                                                                    misslam_report *rep, float *__restrict__ params) {
+    namespace cg = cooperative_groups;
+    cg::grid_group grid = cg::this_grid();
+    extern __shared__ float dyn[];
+    __shared__ double red[kPcgThreads];
+    __shared__ float vx[kRowsPerBlk * 12], vr[kRowsPerBlk * 12], vp[kRowsPerBlk * 12], vq[kRowsPerBlk * 12];
+    const int G = gridDim.x;
+    const int r0 = min(A.m, (int)blockIdx.x * rows_per_wg);
+    const int r1 = min(A.m, r0 + rows_per_wg);
+    const int b0 = min(A.row_ptr[r0], A.cap), b1 = min(A.row_ptr[r1], A.cap);
+    const int cached = min(b1 - b0, cache_blocks);
+    float *hc = dyn;                                   // cached blocks
+    float *mc = dyn + (size_t)cache_blocks * 144;      // preconditioner blocks of the rows
+    for (int t = threadIdx.x; t < cached * 144; t += kPcgThreads) hc[t] = A.blocks[(size_t)b0 * 144 + t];
+    for (int t = threadIdx.x; t < (r1 - r0) * 144; t += kPcgThreads) mc[t] = A.minv[(size_t)r0 * 144 + t];
+    // thread -> (row, component); rows_per_wg <= kRowsPerBlk
+    const int lr = threadIdx.x / 12, a = threadIdx.x % 12;
+    const int j = r0 + lr;
+    const bool act = lr < kRowsPerBlk && j < r1;
+    const int li = lr * 12 + a;
+    __syncthreads();
+
+    // init: r = -g, z = M r, x = 0
+    float r = 0.f, z = 0.f;
+    if (act) {
+        r = -A.g[(size_t)j * 12 + a];
+        vr[li] = r;
+        vx[li] = 0.f;
+    }
+    __syncthreads();
+    if (act) {
+        const float *M = mc + (size_t)lr * 144 + a * 12;
+        float s = 0.f;
+#pragma unroll
+        for (int b = 0; b < 12; ++b) s = fmaf(M[b], vr[lr * 12 + b], s);
+        z = s;
+        A.z[(size_t)j * 12 + a] = z;
+    }
+    {
+        const double rz0 = block_sum<kPcgThreads>((double)r * (double)z, red);
+        const double rr0 = block_sum<kPcgThreads>((double)r * (double)r, red);
+        if (threadIdx.x == 0) {
+            A.part[(size_t)(0 * 4 + 0) * G + blockIdx.x] = rz0;
+            A.part[(size_t)(0 * 4 + 1) * G + blockIdx.x] = rr0;
+        }
+    }
+    grid.sync();
+    bool stopped = false;
+    int done = 0;
+    double rz_prev = 1.0;
+    for (int it = 0; it < A.iters; ++it) {
+        const double rz = gather_sum(A.part + (size_t)(it * 4 + 0) * G, G, red);
+        const bool skip = stopped || rz == 0.0;
+        // ---- direction and product: p = z + beta p, q = (H + lambda I) z + beta q
+        double pq = 0.0;
+        if (act && !skip) {
+            const float beta = it > 0 ? (float)(rz / rz_prev) : 0.f;
+            float az = 0.f;
+            const int p0 = A.row_ptr[j], p1 = min(A.row_ptr[j + 1], A.cap);
+            for (int pb = p0; pb < p1; ++pb) {
+                const int l = A.col_idx[pb];
+                const float *B = (pb - b0 < cached) ? hc + (size_t)(pb - b0) * 144 + a * 12
+                                                    : A.blocks + (size_t)pb * 144 + a * 12;
+                const float *zl = A.z + (size_t)l * 12;
+#pragma unroll
+                for (int b = 0; b < 12; ++b) az = fmaf(B[b], zl[b], az);
+            }
+            az = fmaf(A.lambda, z, az);
+            const float pv = it > 0 ? fmaf(beta, vp[li], z) : z;
+            const float qv = it > 0 ? fmaf(beta, vq[li], az) : az;
+            vp[li] = pv;
+            vq[li] = qv;
+            pq = (double)pv * (double)qv;
+        }
+        {
+            const double t = block_sum<kPcgThreads>(pq, red);
+            if (threadIdx.x == 0) A.part[(size_t)(it * 4 + 2) * G + blockIdx.x] = t;
+        }
+        grid.sync();
+        // ---- step: alpha = r.z / p.q, x += alpha p, r -= alpha q, z = M r
+        const double pqs = gather_sum(A.part + (size_t)(it * 4 + 2) * G, G, red);
+        const bool brk = !skip && !(pqs > 0.0);
+        const bool upd = !skip && !brk;
+        double bad = 0.0;
+        if (act && upd) {
+            const float alpha = (float)(rz / pqs);
+            vx[li] = fmaf(alpha, vp[li], vx[li]);
+            r = fmaf(-alpha, vq[li], r);
+            vr[li] = r;
+        }
+        if (act) bad = isfinite(vx[li]) ? 0.0 : 1.0;
+        __syncthreads();
+        if (act && upd) {
+            const float *M = mc + (size_t)lr * 144 + a * 12;
+            float s = 0.f;
+#pragma unroll
+            for (int b = 0; b < 12; ++b) s = fmaf(M[b], vr[lr * 12 + b], s);
+            z = s;
+            A.z[(size_t)j * 12 + a] = z;
+        }
+        {
+            const double rzn = block_sum<kPcgThreads>((double)r * (double)z, red);
+            const double rrn = block_sum<kPcgThreads>((double)r * (double)r, red);
+            const double nb = block_sum<kPcgThreads>(bad, red);
+            if (threadIdx.x == 0) {
+                A.part[(size_t)((it + 1) * 4 + 0) * G + blockIdx.x] = rzn;
+                A.part[(size_t)((it + 1) * 4 + 1) * G + blockIdx.x] = rrn;
+                A.part[(size_t)((it + 1) * 4 + 3) * G + blockIdx.x] = nb;
+            }
+        }
+        if (upd) ++done;
+        if (brk) stopped = true;
+        if (!skip) rz_prev = rz;
+        grid.sync();
+    }
+    // ---- finish: report (block 0), x out, params += x unless non-finite
+    const double nbad = A.iters > 0 ? gather_sum(A.part + (size_t)(A.iters * 4 + 3) * G, G, red) : 0.0;
+    if (act) {
+        A.x[(size_t)j * 12 + a] = vx[li];
+        if (params && nbad == 0.0) params[(size_t)j * 12 + a] += vx[li];
+    }
+    if (blockIdx.x == 0) {
+        for (int q = 0; q <= done; ++q) {
+            const double rr = gather_sum(A.part + (size_t)(q * 4 + 1) * G, G, red);
+            if (threadIdx.x == 0 && q <= MISSLAM_MAX_PCG) rep->pcg_resid[q] = sqrt(rr);
+        }
+        if (threadIdx.x == 0) {
+            rep->pcg_iters_done = done;
+            int f = rep->flags;
+            if (stopped) f |= MISSLAM_FLAG_PCG_BREAKDOWN;
+            if (nbad != 0.0) f |= MISSLAM_FLAG_NONFINITE;
+            rep->flags = f;
+        }
+    }
+}
+
+// Grid shape of the persistent solve for m rows on this device, or 0 when a
+// cooperative launch cannot hold it (the multi-kernel path is used then).
+static int persistent_grid(int m, int &rows_per_wg) {
+    static int max_blocks = -1;
+    if (max_blocks < 0) {
+        int dev = 0, cus = 0, per_cu = 0, coop = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pcg_persistent_kernel, kPcgThreads,
+                                                         kPersistLdsBytes) != hipSuccess ||
+            !coop)
+            max_blocks = 0;
+        else
+            max_blocks = cus * (per_cu < 1 ? per_cu : 1);   // one workgroup per CU keeps the barriers small
+    }
+    if (max_blocks <= 0) return 0;
+    rows_per_wg = (m + max_blocks - 1) / max_blocks;
+    if (rows_per_wg > kRowsPerBlk) return 0;
+    return (m + rows_per_wg - 1) / rows_per_wg;
+}
+
+hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
+                                 float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
+                                 float *params, hipStream_t st, bool *used) {
+    *used = false;
+    int rows = 0;
+    const int G = persistent_grid(m, rows);
+    if (G <= 0 || G > s.nblk_max) return hipSuccess;
+    PcgArgs A;
+    A.row_ptr = g.row_ptr;
+    A.col_idx = g.col_idx;
+    A.blocks = blocks;
+    A.minv = minv;
+    A.g = gvec;
+    A.lambda = lambda;
+    A.m = m;
+    A.nblk = G;
+    A.iters = iters;
+    A.cap = g.bsr_cap;
+    A.x = delta;
+    A.r = s.r;
+    A.z = s.z;
+    A.p = s.p;
+    A.q = s.q;
+    A.part = s.part;
+    A.status = s.status;
+    A.done = s.status + (iters + 2);
+    const int mc_floats = rows * 144;
+    const int cache_blocks = (kPersistLdsBytes / 4 - mc_floats) / 144;
+    void *args[] = {&A, (void *)&rows, (void *)&cache_blocks, &rep, &params};
+    const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(pcg_persistent_kernel), dim3(G),
+                                                    dim3(kPcgThreads), args, kPersistLdsBytes, st);
+    if (e == hipSuccess) *used = true;
+    return e;
+}
+
 
 }  // namespace msl

@@ -213,3 +213,26 @@ def gn_register(points, nodes, x, graph, depth, cam, pose_, params, ws, corr_his
         _ptr(depth), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(params.c()), _ptr(rep), _ptr(ch),
         _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
     return rep, ch
+
+
+def fuse_params(frame, tau=10.0, cos_delta=math.cos(math.radians(10.0)), w_max=20.0):
+    """Alg. 1 thresholds and the Eq.(15) cap (Sec. III-B: 10 mm, 10 degrees, 20)."""
+    return _lib.FuseParams(float(tau), float(cos_delta), float(w_max), int(frame))
+
+
+def fuse(points, w, stamp, nodes, x, graph, nmap, cam, pose_, fp, ws, outputs=False):
+    """Deforms and fuses in place: points (6, N), w (N), stamp (N int32), nodes (3, m) and x (reset to identity).
+
+    Returns (reg_map (H, W) int32, registered (N,) int32) when outputs=True.
+    """
+    n, m = points.shape[1], nodes.shape[1]
+    _need(w, torch.float32, "w")
+    _need(stamp, torch.int32, "stamp")
+    reg = torch.empty((cam.height, cam.width), dtype=torch.int32, device=points.device) if outputs else None
+    regd = torch.empty(max(n, 1), dtype=torch.int32, device=points.device) if outputs else None
+    buf = ws.get(workspace_bytes(n, m, cam.width, cam.height, Params()))
+    check("misslam_fuse", load().misslam_fuse(
+        ctypes.byref(points_struct(points, w, stamp)), ctypes.byref(nodes_struct(nodes, x)), ctypes.byref(graph.c()),
+        _ptr(nmap), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(fp), _ptr(reg), _ptr(regd), _ptr(buf),
+        ctypes.c_size_t(buf.numel()), _stream()))
+    return (reg, regd[:n]) if outputs else None

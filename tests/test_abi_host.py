@@ -1,0 +1,152 @@
+"""Host-side checks of the C ABI: exported symbols, struct layout, argument validation.
+
+These run without a GPU: every call below returns on the host before any
+HIP call (argument checks precede all launches).
+"""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_1803_02009_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "misslam.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(misslam_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_struct_layout_matches_header():
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "misslam.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(misslam_camera), sizeof(misslam_pose),
+         sizeof(misslam_points), sizeof(misslam_nodes), sizeof(misslam_graph), sizeof(misslam_params),
+         sizeof(misslam_report), sizeof(misslam_fuse_params));
+  printf("%zu %zu %zu %zu\n", offsetof(misslam_params, eps_d), offsetof(misslam_params, lambda),
+         offsetof(misslam_report, n_valid), offsetof(misslam_graph, info));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.check_output([exe]).decode().split("\n")
+    sizes = [int(v) for v in out[0].split()]
+    want = [ctypes.sizeof(t) for t in (_lib.Camera, _lib.Pose, _lib.Points, _lib.Nodes, _lib.Graph, _lib.Params,
+                                       _lib.Report, _lib.FuseParams)]
+    assert sizes == want
+    offs = [int(v) for v in out[1].split()]
+    assert offs == [_lib.Params.eps_d.offset, _lib.Params.lambda_.offset, _lib.Report.n_valid.offset,
+                    _lib.Graph.info.offset]
+
+
+def test_default_params_are_the_papers(lib):
+    p = _lib.Params()
+    lib.misslam_default_params(ctypes.byref(p))
+    assert (p.k, p.w_rot, p.w_reg, p.w_data, p.eps_d) == (4, 1000.0, 10000.0, 1.0, 15.0)
+    assert abs(p.cos_eps_n - 0.984807753012208) < 1e-15
+    assert (p.gn_iters, p.pcg_iters, p.precision) == (10, 10, _lib.PREC_FP32)
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.misslam_status_string(code)
+    assert lib.misslam_status_string(-99) == b"unknown status"
+
+
+def test_workspace_query(lib):
+    p = _lib.Params()
+    lib.misslam_default_params(ctypes.byref(p))
+    small = lib.misslam_workspace_bytes(1000, 10, 64, 48, ctypes.byref(p))
+    big = lib.misslam_workspace_bytes(250000, 1600, 640, 480, ctypes.byref(p))
+    assert 0 < small < big
+    assert lib.misslam_workspace_bytes(-1, 10, 64, 48, ctypes.byref(p)) == 0
+    assert lib.misslam_workspace_bytes(10, 0, 64, 48, ctypes.byref(p)) == 0
+    bad = _lib.Params()
+    lib.misslam_default_params(ctypes.byref(bad))
+    bad.k = 9
+    assert lib.misslam_workspace_bytes(10, 10, 64, 48, ctypes.byref(bad)) == 0
+    bad.k = 4
+    bad.pcg_iters = _lib.MAX_PCG + 1
+    assert lib.misslam_workspace_bytes(10, 10, 64, 48, ctypes.byref(bad)) == 0
+
+
+FAKE = 0x1000   # never dereferenced: every call below fails validation first
+
+
+def _structs(n=100, m=10, k=4):
+    pts = _lib.Points(n, n, *([FAKE] * 6), 0, 0)
+    nds = _lib.Nodes(m, m, FAKE, FAKE, FAKE, FAKE)
+    gr = _lib.Graph(k, m * _lib.MAX_ROW, *([FAKE] * 8))
+    p = _lib.Params()
+    _lib.load().misslam_default_params(ctypes.byref(p))
+    cam = _lib.Camera(64, 48, 60.0, 60.0, 32.0, 24.0)
+    pose = _lib.Pose()
+    return pts, nds, gr, p, cam, pose
+
+
+def test_validation_errors(lib):
+    pts, nds, gr, p, cam, pose = _structs()
+    B = ctypes.byref
+    # null pointers
+    assert lib.misslam_build_graph(None, B(nds), B(p), B(gr), FAKE, 1 << 30, None) == _lib.EINVAL
+    assert lib.misslam_warp(B(pts), B(nds), B(gr), None, None, None, None) == _lib.EINVAL
+    assert lib.misslam_normal_map(None, B(cam), FAKE, None) == _lib.EINVAL
+    # k mismatch between graph and params
+    gr5 = _lib.Graph(5, gr.bsr_cap, *([FAKE] * 8))
+    assert lib.misslam_build_graph(B(pts), B(nds), B(p), B(gr5), FAKE, 1 << 30, None) == _lib.ESHAPE
+    # fewer nodes than k
+    nds3 = _lib.Nodes(3, 3, FAKE, FAKE, FAKE, FAKE)
+    assert lib.misslam_build_graph(B(pts), B(nds3), B(p), B(gr), FAKE, 1 << 30, None) == _lib.ESHAPE
+    # workspace too small
+    assert lib.misslam_build_graph(B(pts), B(nds), B(p), B(gr), FAKE, 16, None) == _lib.EWORKSPACE
+    assert lib.misslam_gn_register(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(p), FAKE, None, FAKE, 16,
+                                   None) == _lib.EWORKSPACE
+    # n above capacity, bad camera, bad k
+    over = _lib.Points(200, 100, *([FAKE] * 6), 0, 0)
+    assert lib.misslam_warp(B(over), B(nds), B(gr), None, FAKE, None, None) == _lib.EINVAL
+    badcam = _lib.Camera(0, 48, 60.0, 60.0, 32.0, 24.0)
+    assert lib.misslam_normal_map(FAKE, B(badcam), FAKE, None) == _lib.EINVAL
+    p2 = _lib.Params()
+    lib.misslam_default_params(ctypes.byref(p2))
+    p2.k = 0
+    assert lib.misslam_build_graph(B(pts), B(nds), B(p2), B(gr), FAKE, 1 << 30, None) == _lib.EINVAL
+    p2.k = 4
+    p2.lambda_ = -1.0
+    assert lib.misslam_pcg_solve(B(gr), 10, FAKE, FAKE, B(p2), FAKE, FAKE, FAKE, 1 << 30, None) == _lib.EINVAL
+
+
+def test_profiler_api_on_host(lib):
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    assert lib.misslam_profile_get(b"nope", ctypes.byref(ms), ctypes.byref(cnt)) == _lib.EINVAL
+    lib.misslam_profile_reset()
+    assert lib.misslam_profile_get(b"assemble", ctypes.byref(ms), ctypes.byref(cnt)) == _lib.OK
+    assert cnt.value == 0 and ms.value == 0.0
+    prev = lib.misslam_profile_enable(1)
+    assert lib.misslam_profile_enable(prev) == 1

@@ -1,0 +1,132 @@
+"""Full-size parity at the benchmark's configuration (640x480, 250,000 points, 1,600 nodes).
+
+The oracle cannot redo the whole frame in seconds, so it checks sampled
+outputs it can compute one at a time (kNN of sampled points, pattern rows and
+normal-equation rows of sampled nodes), whole-image products it computes
+quickly (normal map, correspondences on shared inputs, the PCG solve), and the
+end-to-end parameters against the stored float64 oracle run of this frame
+(tests/golden/make_oracle_golden.py).
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import Scene, rel_err
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def c3(lib):
+    return Scene("c3")
+
+
+def _local_knn(s, j, radius):
+    """Oracle kNN of every point within `radius` of node j; returns (point ids, idx rows)."""
+    P = s.sc["points"].astype(np.float64)
+    gj = s.sc["nodes"][j].astype(np.float64)
+    cand = np.nonzero(np.sum((P - gj) ** 2, axis=1) < radius * radius)[0]
+    idx, _ = oracle.knn(P[cand], s.sc["nodes"], 4)
+    return cand, idx[:, :4]
+
+
+def test_c3_normal_map_and_knn_samples(c3):
+    s = c3
+    got = s.M.normal_map(s.depth, s.cam).cpu().numpy()
+    N, ok = oracle.normal_map(s.sc["depth"], s.sc["camera"])
+    assert np.array_equal(got[..., :3].view(np.uint32), N.astype(np.float32).view(np.uint32))
+    rng = np.random.default_rng(0)
+    sel = np.sort(rng.choice(s.n, 4000, replace=False))
+    idx, d2 = oracle.knn(s.sc["points"][sel], s.sc["nodes"], 4)
+    assert np.array_equal(s.graph.knn_idx.cpu().numpy()[:, sel].T, idx[:, :4])
+    w = oracle.skin_weights(d2, 4, "gauss", s.sc["sigma"])
+    assert np.abs(s.graph.knn_w.cpu().numpy()[:, sel].T - w).max() <= 2e-7
+
+
+def test_c3_pattern_and_rows_sampled(c3):
+    s = c3
+    g = s.graph
+    info = g.info.cpu().numpy()
+    assert info[3] == 0
+    rp = g.row_ptr.cpu().numpy()
+    ci = g.col_idx.cpu().numpy()
+    lp = g.list_ptr.cpu().numpy()
+    lst = g.list_pts.cpu().numpy()
+    from gpu_util import random_params
+    xg = random_params(s.m, 31, 0.003, 0.2)
+    x = torch.tensor(xg, device="cuda")
+    nmap = s.M.normal_map(s.depth, s.cam)
+    blocks, gv, corr, _ = s.M.build_normal_eq(s.pts, s.nodes, x, g, nmap, s.cam, s.pose, s.params, s.ws)
+    pos, nrm = s.M.warp(s.pts, s.nodes, x, g, s.pose)
+    torch.cuda.synchronize()
+    Nm, ok = oracle.normal_map(s.sc["depth"], s.sc["camera"])
+    Nm32 = Nm.astype(np.float32)
+    a = oracle.associate(pos.cpu().numpy().T, nrm.cpu().numpy().T, s.sc["depth"], s.sc["camera"], Nm32, ok,
+                         s.params.eps_d, s.params.cos_eps_n)
+    cg = corr.cpu().numpy()
+    assert np.array_equal(cg, a["corr"])                       # decisions bit-exact on shared inputs
+    rng = np.random.default_rng(1)
+    rows = np.sort(rng.choice(s.m, 24, replace=False))
+    radius = 3.0 * s.sc["node_spacing"]
+    pts_all = []
+    for j in rows:
+        cand, idx = _local_knn(s, j, radius)
+        mine = cand[np.any(idx == j, axis=1)]
+        # list of node j: exactly these points, ordered by (sorted set, index)
+        assert sorted(lst[lp[j]:lp[j + 1]]) == sorted(mine.tolist())
+        nb = sorted(set(idx[np.any(idx == j, axis=1)].ravel().tolist()))
+        assert list(ci[rp[j]:rp[j + 1]]) == nb                 # row j = {j} U N(j)
+        pts_all.append(mine)
+    sub = np.unique(np.concatenate(pts_all))
+    # normal-equation rows from exactly those points (rows of the sampled nodes are then complete)
+    og = s.oracle_graph_from_gpu()
+    sub_idx = og["idx"][sub]
+    sub_w = og["w"][sub]
+    from oracle.gn import _adopt
+    vc = oracle.ed_warp(s.sc["points"][sub], s.sc["nodes"], xg.astype(np.float64), sub_idx, sub_w,
+                        s.sc["R"], s.sc["T"])
+    pb = s.problem()
+    asc = _adopt({}, cg[sub], vc, pb, Nm32)
+    hb, hg = oracle.block_system(s.sc["points"][sub], s.sc["nodes"], xg.astype(np.float64), sub_idx, sub_w,
+                                 s.sc["R"], asc, og["nbrs"], og["row_ptr"], og["col_idx"],
+                                 (pb.w_rot, pb.w_reg, pb.w_data))
+    gb = blocks.cpu().numpy()
+    for j in rows:
+        sl = slice(rp[j], rp[j + 1])
+        assert rel_err(gb[sl], hb[sl]) < 1e-5, j
+        assert rel_err(gv.cpu().numpy()[j], hg[j]) < 1e-5, j
+
+
+def test_c3_pcg_full(c3):
+    s = c3
+    from gpu_util import random_params
+    xg = random_params(s.m, 32, 0.003, 0.2)
+    x = torch.tensor(xg, device="cuda")
+    nmap = s.M.normal_map(s.depth, s.cam)
+    blocks, gv, _, _ = s.M.build_normal_eq(s.pts, s.nodes, x, s.graph, nmap, s.cam, s.pose, s.params, s.ws)
+    delta, rep = s.M.pcg_solve(s.graph, s.m, blocks, gv, s.params, s.ws)
+    og = s.oracle_graph_from_gpu()
+    nnzb = len(og["col_idx"])
+    dx, info = oracle.pcg(og["row_ptr"], og["col_idx"], blocks.cpu().numpy()[:nnzb].astype(np.float64),
+                          gv.cpu().numpy().astype(np.float64), float(np.float32(s.params.lam)), s.params.pcg_iters)
+    assert rel_err(delta.cpu().numpy().reshape(-1), dx) < 1e-4
+    assert s.M.read_report(rep)[0]["pcg_iters_done"] == info["iters"]
+
+
+def test_c3_end_to_end_against_stored_oracle(c3):
+    s = c3
+    gold = np.load(os.path.join(HERE, "golden", "c3_oracle.npz"))
+    x = s.M.identity_params(s.m)
+    rep, _ = s.M.gn_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, s.params, s.ws)
+    r = s.M.read_report(rep)
+    xg = x.cpu().numpy().astype(np.float64)
+    xo = gold["x"]
+    xi = oracle.identity_params(s.m)
+    assert rel_err(xg, xo) < 1e-5
+    assert rel_err(xg - xi, xo - xi) < 1e-4
+    assert r[-1]["e_data"] == pytest.approx(float(gold["e_data_final"]), rel=1e-4)
+    assert np.all((r["flags"] & ~8) == 0)
