@@ -224,7 +224,13 @@ misslam_status misslam_pcg_solve(const misslam_graph *graph, int32_t m, const fl
 /*
  * One frame of registration (Sec. II-E, II-F): params->gn_iters damped
  * Gauss-Newton steps on the node parameters (nodes->params in/out; the caller
- * initialises them, normally to A = I, t = 0), pose fixed.  rep (device)
+ * initialises them, normally to A = I, t = 0), pose fixed.
+ * With params->precision BF16 or FP16 (k <= 4) the data term of each step's
+ * normal matrix is formed on the matrix cores from Jacobian rows rounded to
+ * that type (float32 accumulation; regularisers, gradient and PCG as in the
+ * float32 form), and params->refine_steps iterative-refinement steps win the
+ * accuracy back: rho = -g - H32 dx with H32 dx evaluated matrix-free in
+ * float32 from the points, then dx += (H_lo + lambda I)^-1 rho.  rep (device)
  * holds gn_iters + 1 entries: one per step at its linearisation point and a
  * final one at the returned parameters.  corr_hist, if not NULL, receives
  * the gn_iters x n correspondence arrays.  depth is height x width float32.
@@ -255,6 +261,27 @@ misslam_status misslam_fuse(misslam_points *points, misslam_nodes *nodes, const 
                             const misslam_fuse_params *fp, int32_t *reg_map, int32_t *registered, void *ws,
                             size_t ws_bytes, void *stream);
 
+/*
+ * Energy of Eq.(3) (data, rotation and regularisation terms) and its adjoint.
+ * With corr_in == NULL the correspondences are found as in
+ * misslam_build_normal_eq (Eq.(7) gates) and written to corr_out (optional);
+ * with corr_in given they are held fixed (no gates; the Gauss-Newton
+ * linearisation point).  Outputs (each optional, device):
+ *   energy      1 double: w_data E_data + w_rot E_rot + w_reg E_reg
+ *   grad_params m x 12: dE/dx = 2 sum w J^T r (twice the g of the normal equations)
+ *   grad_points 3 x n: dE/dv with kNN sets fixed and the normalised Gaussian
+ *               weights moving with the point (MISSLAM_WEIGHT_GAUSS only)
+ *   rep         1 report entry (energies, n_valid)
+ * Gradients are scaled by *grad_e (device float; NULL means 1).  The paper
+ * has no gradient; this is the adjoint of its energy for learning-based or
+ * differentiable uses of the registration.
+ */
+misslam_status misslam_energy_vjp(const misslam_points *points, const misslam_nodes *nodes,
+                                  const misslam_graph *graph, const float *nmap, const misslam_camera *camera,
+                                  const misslam_pose *pose, const misslam_params *params, const int32_t *corr_in,
+                                  int32_t *corr_out, const float *grad_e, float *grad_params, float *grad_points,
+                                  double *energy, misslam_report *rep, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------ profiling */
 
 /*
@@ -262,7 +289,8 @@ misslam_status misslam_fuse(misslam_points *points, misslam_nodes *nodes, const 
  * launches of every phase it runs with HIP events on its own stream (not
  * allowed during stream capture).  Phases: "normal_map", "build_graph",
  * "point_pass", "assemble", "energy", "bjacobi", "pcg" (the whole PCG solve,
- * including the parameter update), "fuse".  misslam_profile_get synchronises the
+ * including the parameter update), "fuse", "refine" (the float32 matrix-free
+ * residual of a low-precision step).  misslam_profile_get synchronises the
  * recorded events and returns the accumulated milliseconds and number of
  * bracketed launches since the last reset.  Returns the previous state.
  */

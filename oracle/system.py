@@ -112,11 +112,14 @@ def dense_system(points, nodes, params, idx, w, R, assoc, nbrs, weights):
     return J, wd, r, H, g
 
 
-def block_system(points, nodes, params, idx, w, R, assoc, nbrs, row_ptr, col_idx, weights):
+def block_system(points, nodes, params, idx, w, R, assoc, nbrs, row_ptr, col_idx, weights, jac_round=None):
     """The same normal equations accumulated block by block into the BSR pattern.
 
     Every term's contribution J_a^T J_b is added to block (a, b); the sums use
     np.bincount over block ids, one entry of the 12x12 block at a time.
+    jac_round, if given, maps the data-term Jacobian rows before they enter
+    the blocks (not the gradient): the rounding a low-precision matrix-core
+    product applies to its inputs.
     Returns (blocks (nnzb, 12, 12), g (m, 12)).
     """
     w_rot, w_reg, w_data = weights
@@ -152,7 +155,8 @@ def block_system(points, nodes, params, idx, w, R, assoc, nbrs, row_ptr, col_idx
             for b in range(k):
                 jb = idx[sel, b]
                 bid = key[ja, jb]
-                outer = Jd[:, a, :, None] * Jd[:, b, None, :]
+                Jl = Jd if jac_round is None else jac_round(Jd)
+                outer = Jl[:, a, :, None] * Jl[:, b, None, :]
                 for e in range(12):
                     for f in range(12):
                         blocks[:, e, f] += w_data * np.bincount(bid, weights=outer[:, e, f], minlength=nnzb)

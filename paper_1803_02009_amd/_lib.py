@@ -88,6 +88,8 @@ SIGNATURES = {
                                  ctypes.c_size_t, vp]),
     "misslam_fuse": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(FuseParams), vp, vp, vp,
                           ctypes.c_size_t, vp]),
+    "misslam_energy_vjp": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params), vp, vp, vp, vp,
+                                vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "misslam_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "misslam_profile_get": (st, [ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int64)]),
     "misslam_profile_reset": (None, []),

@@ -12,9 +12,11 @@ namespace {
 
 // ---------------------------------------------------------------- phase timers (profiling only)
 
-enum Phase { PH_NORMAL_MAP, PH_GRAPH, PH_POINT_PASS, PH_ASSEMBLE, PH_ENERGY, PH_BJACOBI, PH_PCG, PH_FUSE, PH_COUNT };
-const char *const kPhaseNames[PH_COUNT] = {"normal_map", "build_graph", "point_pass", "assemble",
-                                           "energy",     "bjacobi",     "pcg",        "fuse"};
+enum Phase {
+    PH_NORMAL_MAP, PH_GRAPH, PH_POINT_PASS, PH_ASSEMBLE, PH_ENERGY, PH_BJACOBI, PH_PCG, PH_FUSE, PH_REFINE, PH_COUNT
+};
+const char *const kPhaseNames[PH_COUNT] = {"normal_map", "build_graph", "point_pass", "assemble", "energy",
+                                           "bjacobi",    "pcg",         "fuse",       "refine"};
 
 struct Profiler {
     std::mutex mu;
@@ -111,6 +113,11 @@ struct Layout {
     float *fuse_tmp;
     int32_t *fuse_pix;
     unsigned long long *zbuf;
+    misslam_report *rep;
+    float *rr;          // regulariser + rotation blocks (low-precision refinement)
+    float *jv;          // n: J dx of the matrix-free product
+    float *rhs;         // 12m
+    float *delta2;      // 12m
     float *blocks;
     float *gvec;
     float *delta;
@@ -145,6 +152,12 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
     L.fuse_tmp = c.take<float>((size_t)6 * n);
     L.fuse_pix = c.take<int32_t>((size_t)n);
     L.zbuf = c.take<unsigned long long>((size_t)W * H);
+    L.rep = c.take<misslam_report>(1);
+    const bool lp = pcg_iters >= 0;   // sized for every precision
+    L.rr = lp ? c.take<float>((size_t)m * MISSLAM_MAX_ROW * 144) : nullptr;
+    L.jv = c.take<float>((size_t)n);
+    L.rhs = c.take<float>((size_t)12 * m);
+    L.delta2 = c.take<float>((size_t)12 * m);
     L.graph.cnt = c.take<int32_t>((size_t)2 * m + 8);
     L.bytes = align_up(c.off);
     return L;
@@ -303,6 +316,16 @@ static hipError_t solve(const msl::GraphView &g, int m, const float *blocks, con
     return e;
 }
 
+static hipError_t solve_persistent(const msl::GraphView &g, int m, const float *blocks, const float *gvec,
+                                   const float *minv, float lambda, int iters, float *delta, const msl::PcgScratch &s,
+                                   misslam_report *rep, float *params, hipStream_t st) {
+    bool used = false;
+    hipError_t e = msl::launch_pcg_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st, &used);
+    if (e == hipSuccess && !used)
+        e = msl::launch_pcg_update(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st);
+    return e;
+}
+
 static msl::StepArgs step_args(const misslam_points *points, const misslam_nodes *nodes, const misslam_graph *graph,
                                const float4 *nmap, const misslam_camera *camera, const misslam_pose *pose,
                                const misslam_params *params, float *blocks, float *g, int32_t *corr) {
@@ -322,6 +345,7 @@ static msl::StepArgs step_args(const misslam_points *points, const misslam_nodes
     a.blocks = blocks;
     a.gvec = g;
     a.corr_out = corr;
+    a.corr_in = nullptr;
     a.minv = nullptr;
     a.flags = nullptr;
     return a;
@@ -335,13 +359,19 @@ misslam_status misslam_build_normal_eq(const misslam_points *points, const missl
         !valid_camera(camera) || !pose || !valid_params(params) || !blocks || !g || !rep || !ws)
         return MISSLAM_EINVAL;
     if (graph->k != params->k) return MISSLAM_ESHAPE;
-    if (params->precision != MISSLAM_PREC_FP32) return MISSLAM_EUNSUPPORTED;
+    if (params->precision != MISSLAM_PREC_FP32 && params->k > 4) return MISSLAM_EUNSUPPORTED;
     const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, params->pcg_iters);
     if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
     const hipStream_t st = stream_of(stream);
     const msl::StepArgs a = step_args(points, nodes, graph, reinterpret_cast<const float4 *>(nmap), camera, pose,
                                       params, blocks, g, corr);
     hipError_t e = msl::launch_report_init(rep, 1, st);
+    if (e == hipSuccess && params->precision != MISSLAM_PREC_FP32) {
+        e = msl::launch_point_pass(a, L.step, st);
+        if (e == hipSuccess) e = msl::launch_assemble_lp(a, L.step, params->precision, nullptr, st);
+        if (e == hipSuccess) e = msl::launch_energy_report(L.step, points->n, nodes->m, rep, params->reject_threshold, st);
+        return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
+    }
     if (e == hipSuccess) e = linearize(a, L.step, points->n, nodes->m, rep, params->reject_threshold, st);
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
 }
@@ -370,15 +400,17 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
         !valid_camera(camera) || !pose || !valid_params(params) || !rep || !ws)
         return MISSLAM_EINVAL;
     if (graph->k != params->k) return MISSLAM_ESHAPE;
-    if (params->precision != MISSLAM_PREC_FP32) return MISSLAM_EUNSUPPORTED;
+    if (params->precision != MISSLAM_PREC_FP32 && params->k > 4) return MISSLAM_EUNSUPPORTED;
     const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, params->pcg_iters);
     if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
     if ((int64_t)graph->bsr_cap > (int64_t)nodes->m * MISSLAM_MAX_ROW) return MISSLAM_ECAPACITY;
+    const bool lowp = params->precision != MISSLAM_PREC_FP32;
     const hipStream_t st = stream_of(stream);
     const int G = params->gn_iters;
     const int64_t n = points->n;
     const int m = nodes->m;
     hipError_t e = msl::launch_report_init(rep, G + 1, st);
+    if (e == hipSuccess && lowp) e = msl::launch_report_init(L.rep, 1, st);
     if (e == hipSuccess) {
         Timed t(PH_NORMAL_MAP, st);
         e = msl::launch_normal_map(depth, view(camera), L.nmap, st);
@@ -390,17 +422,52 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
             a.minv = L.step.minv;     // block-Jacobi inverses come out of the assembly
             a.flags = &rep[it].flags;
         }
-        e = linearize(a, L.step, n, m, rep + it, params->reject_threshold, st);
-        if (it == G) break;
+        if (it == G) {   // final entry: energies at the returned parameters, no system needed
+            {
+                Timed t(PH_POINT_PASS, st);
+                e = msl::launch_point_pass(a, L.step, st);
+            }
+            if (e == hipSuccess) e = msl::launch_node_energy(a, L.step, st);
+            if (e == hipSuccess) e = msl::launch_energy_report(L.step, n, m, rep + it, params->reject_threshold, st);
+            break;
+        }
+        if (!lowp) {
+            e = linearize(a, L.step, n, m, rep + it, params->reject_threshold, st);
+            if (e == hipSuccess) {
+                Timed t(PH_PCG, st);
+                e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
+                                     L.delta, L.pcg, rep + it, nodes->params, st);
+            }
+            continue;
+        }
+        // low precision: H_lo from the matrix cores, then float32 refinement of the step
+        {
+            Timed t(PH_POINT_PASS, st);
+            e = msl::launch_point_pass(a, L.step, st);
+        }
+        if (e == hipSuccess) {
+            Timed t(PH_ASSEMBLE, st);
+            e = msl::launch_assemble_lp(a, L.step, params->precision, L.rr, st);
+        }
+        if (e == hipSuccess) e = msl::launch_energy_report(L.step, n, m, rep + it, params->reject_threshold, st);
         if (e == hipSuccess) {
             Timed t(PH_PCG, st);
-            bool used = false;
-            e = msl::launch_pcg_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda,
-                                           params->pcg_iters, L.delta, L.pcg, rep + it, nodes->params, st, &used);
-            if (e == hipSuccess && !used)
-                e = msl::launch_pcg_update(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda,
-                                           params->pcg_iters, L.delta, L.pcg, rep + it, nodes->params, st);
+            e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
+                                 L.delta, L.pcg, rep + it, nullptr, st);
         }
+        for (int r = 0; r < params->refine_steps && e == hipSuccess; ++r) {
+            {
+                Timed t(PH_REFINE, st);
+                e = msl::launch_refine_rhs(a, L.step, L.delta, L.rr, L.gvec, L.jv, L.rhs, st);
+            }
+            if (e == hipSuccess) {
+                Timed t(PH_PCG, st);
+                e = solve_persistent(view(graph), m, L.blocks, L.rhs, L.step.minv, params->lambda, params->pcg_iters,
+                                     L.delta2, L.pcg, L.rep, nullptr, st);
+            }
+            if (e == hipSuccess) e = msl::launch_axpy(L.delta, L.delta2, 12 * m, st);
+        }
+        if (e == hipSuccess) e = msl::launch_axpy(nodes->params, L.delta, 12 * m, st);
     }
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
 }
@@ -447,6 +514,35 @@ misslam_status misslam_fuse(misslam_points *points, misslam_nodes *nodes, const 
     Timed t(PH_FUSE, stream_of(stream));
     const hipError_t e = msl::launch_fuse(f, nodes->gx, nodes->gy, nodes->gz, nodes->params, nodes->m, reg_map,
                                           stream_of(stream));
+    return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
+}
+
+misslam_status misslam_energy_vjp(const misslam_points *points, const misslam_nodes *nodes,
+                                  const misslam_graph *graph, const float *nmap, const misslam_camera *camera,
+                                  const misslam_pose *pose, const misslam_params *params, const int32_t *corr_in,
+                                  int32_t *corr_out, const float *grad_e, float *grad_params, float *grad_points,
+                                  double *energy, misslam_report *rep, void *ws, size_t ws_bytes, void *stream) {
+    if (!valid_points(points) || !valid_nodes(nodes) || !valid_graph(graph, points->n) || !nmap ||
+        !valid_camera(camera) || !pose || !valid_params(params) || !ws)
+        return MISSLAM_EINVAL;
+    if (graph->k != params->k) return MISSLAM_ESHAPE;
+    if (grad_points && params->weight_kind != MISSLAM_WEIGHT_GAUSS) return MISSLAM_EUNSUPPORTED;
+    const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, params->pcg_iters);
+    if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
+    if ((int64_t)graph->bsr_cap > (int64_t)nodes->m * MISSLAM_MAX_ROW) return MISSLAM_ECAPACITY;
+    const hipStream_t st = stream_of(stream);
+    misslam_report *r = rep ? rep : L.rep;
+    msl::StepArgs a = step_args(points, nodes, graph, reinterpret_cast<const float4 *>(nmap), camera, pose, params,
+                                L.blocks, L.gvec, corr_out);
+    a.corr_in = corr_in;
+    hipError_t e = msl::launch_report_init(r, 1, st);
+    if (e == hipSuccess) e = msl::launch_point_pass(a, L.step, st);
+    if (e == hipSuccess) e = grad_params ? msl::launch_assemble(a, L.step, st) : msl::launch_node_energy(a, L.step, st);
+    if (e == hipSuccess) e = msl::launch_energy_report(L.step, points->n, nodes->m, r, params->reject_threshold, st);
+    if (e == hipSuccess && energy)
+        e = msl::launch_energy_total(r, params->w_data, params->w_rot, params->w_reg, energy, st);
+    if (e == hipSuccess && grad_params) e = msl::launch_grad_params(L.gvec, nodes->m, grad_e, grad_params, st);
+    if (e == hipSuccess && grad_points) e = msl::launch_vjp_points(a, L.step, params->sigma, grad_e, grad_points, st);
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
 }
 

@@ -163,6 +163,26 @@ __device__ __forceinline__ Match associate(float vx, float vy, float vz, float n
     return out;
 }
 
+// Residual against a given pixel (frozen correspondence): no gates are applied.
+__device__ __forceinline__ Match match_fixed(float vx, float vy, float vz, int pix, const float4 *__restrict__ nmap,
+                                             const Cam &cam) {
+    Match out{-1, 0.f, 0.f, 0.f, 0.f};
+    if (pix < 0 || pix >= cam.W * cam.H) return out;
+    const float4 q = nmap[pix];
+    const double d = q.w;
+    if (!(d > 0.0) || (q.x == 0.f && q.y == 0.f && q.z == 0.f)) return out;
+    const int u = pix % cam.W, v = pix / cam.W;
+    const double Vx = d * (((double)u - (double)cam.cx) / (double)cam.fx);
+    const double Vy = d * (((double)v - (double)cam.cy) / (double)cam.fy);
+    const double dx = (double)vx - Vx, dy = (double)vy - Vy, dz = (double)vz - d;
+    out.pix = pix;
+    out.r = (float)(((double)q.x * dx + (double)q.y * dy) + (double)q.z * dz);
+    out.Nx = q.x;
+    out.Ny = q.y;
+    out.Nz = q.z;
+    return out;
+}
+
 // ---------------------------------------------------------------- deterministic block reductions
 
 // Sum of one double per thread over a block of BS threads, fixed tree order.

@@ -55,6 +55,7 @@ struct StepArgs {
     float *blocks;     // nnzb x 144
     float *gvec;       // 12 m
     int32_t *corr_out; // optional copy of correspondences
+    const int32_t *corr_in;  // optional frozen correspondences (no association, no gates)
     float *minv;       // optional m x 144 block-Jacobi inverses computed with the assembly
     int32_t *flags;    // report flags (NONSPD_BLOCK) when minv is set
 };
@@ -85,6 +86,17 @@ hipError_t launch_fuse(const FuseArgs &f, float *gx, float *gy, float *gz, float
 
 hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_t st);
 hipError_t launch_assemble(const StepArgs &a, const StepScratch &s, hipStream_t st);
+hipError_t launch_assemble_lp(const StepArgs &a, const StepScratch &s, int precision, float *rr_out,
+                              hipStream_t st);
+hipError_t launch_refine_rhs(const StepArgs &a, const StepScratch &s, const float *dx, const float *rr, const float *g,
+                             float *jv, float *rhs, hipStream_t st);
+hipError_t launch_axpy(float *y, const float *x, int count, hipStream_t st);
+hipError_t launch_node_energy(const StepArgs &a, const StepScratch &s, hipStream_t st);
+hipError_t launch_vjp_points(const StepArgs &a, const StepScratch &s, float sigma, const float *grad_e, float *out,
+                             hipStream_t st);
+hipError_t launch_grad_params(const float *g, int m, const float *grad_e, float *out, hipStream_t st);
+hipError_t launch_energy_total(const misslam_report *rep, float w_data, float w_rot, float w_reg, double *out,
+                               hipStream_t st);
 hipError_t launch_energy_report(const StepScratch &s, int64_t n, int m, misslam_report *rep, float reject_thr,
                                 hipStream_t st);
 hipError_t launch_bjacobi(const GraphView &g, int m, const float *blocks, float lambda, float *minv,

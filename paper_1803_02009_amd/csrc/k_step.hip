@@ -74,7 +74,8 @@ __global__ void __launch_bounds__(kPtBlock) point_pass_kernel(StepArgs a, StepSc
         ed_blend_normal<K>(a.pts.nx[i], a.pts.ny[i], a.pts.nz[i], a.g.knn_idx, a.g.knn_w, n, i, a.nd, nx, ny, nz);
         rotate(a.pose, nx, ny, nz);
         normalize3(nx, ny, nz);
-        const Match mt = associate(x, y, z, nx, ny, nz, a.nmap, a.cam, a.eps_d, a.cos_eps_n);
+        const Match mt = a.corr_in ? match_fixed(x, y, z, a.corr_in[i], a.nmap, a.cam)
+                                   : associate(x, y, z, nx, ny, nz, a.nmap, a.cam, a.eps_d, a.cos_eps_n);
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, rr = 0.f;
         if (mt.pix >= 0) {
             const float *R = a.pose.R;
@@ -129,6 +130,22 @@ constexpr int kAsmThreads = 256;
 constexpr int kAsmWaves = kAsmThreads / kWave;
 constexpr int kBatch = 64;
 
+// LDS of the node-level part of a row: columns, regulariser residuals,
+// rotation Jacobian, the damped diagonal block and its Cholesky scratch.
+template <int NT>
+struct RowNode {
+    int cols[MISSLAM_MAX_ROW];
+    float rg[MISSLAM_MAX_ROW][9];    // per neighbour slot: e = g_l - g_j, r_jl, r_lj
+    float EE[10];                    // sum over neighbours of e^_c e^_c', e^ = (e, 1)
+    float Jr[6][9];                  // rotation-term Jacobian of node j
+    float rr[6];
+    float xj[12];
+    float gd[12];                    // data-term gradient of the row (unweighted)
+    double Hd[12][12];               // damped diagonal block for the preconditioner
+    double Li[12][12];
+    double red[NT];
+};
+
 template <int K>
 struct AsmShared {
     float accS[kAsmWaves][MISSLAM_MAX_ROW][64];
@@ -137,16 +154,146 @@ struct AsmShared {
     float4 W[kAsmWaves][kBatch][(K + 3) / 4];
     uint32_t key[kAsmWaves][kBatch][2];
     float gw[kAsmWaves][12];
-    int cols[MISSLAM_MAX_ROW];
-    float rg[MISSLAM_MAX_ROW][9];    // per neighbour slot: e = g_l - g_j, r_jl, r_lj
-    float EE[10];                    // sum over neighbours of e^_c e^_c', e^ = (e, 1)
-    float Jr[6][9];                  // rotation-term Jacobian of node j
-    float rr[6];
-    float xj[12];
-    double Hd[12][12];               // damped diagonal block for the preconditioner
-    double Li[12][12];
-    double red[kAsmThreads];
+    RowNode<kAsmThreads> rn;
 };
+
+// Node-level terms and output of one row, shared by the float32 and the
+// low-precision assembly: Eq.(6) regulariser blocks for both edge directions,
+// the Eq.(5) rotation block, the gradient, the row's blocks (data term given
+// by data(slot, R, C), already weighted by the point weights) and, when
+// requested, the block-Jacobi inverse of the damped diagonal block.  rr_out,
+// if set, receives the regulariser + rotation part of each block alone.
+template <int NT, class DataFn>
+__device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratch &s, RowNode<NT> &rn, int j, int rb,
+                                             int nslots, float gjx, float gjy, float gjz, DataFn data,
+                                             float *rr_out) {
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave, lane = tid % kWave;
+    double e_reg = 0.0;
+    if (tid < nslots) {
+        const int l = rn.cols[tid];
+        float ex = 0.f, ey = 0.f, ez = 0.f, r0 = 0.f, r1 = 0.f, r2 = 0.f, q0 = 0.f, q1 = 0.f, q2 = 0.f;
+        if (l != j) {
+            const float glx = a.nd.gx[l], gly = a.nd.gy[l], glz = a.nd.gz[l];
+            const float *xl = a.nd.x + (size_t)l * 12;
+            const float *xj = rn.xj;
+            ex = glx - gjx;
+            ey = gly - gjy;
+            ez = glz - gjz;
+            // r_jl = A_j e + g_j + t_j - g_l - t_l   (edge j -> l)
+            r0 = fmaf(xj[6], ez, fmaf(xj[3], ey, xj[0] * ex)) + gjx + xj[9] - glx - xl[9];
+            r1 = fmaf(xj[7], ez, fmaf(xj[4], ey, xj[1] * ex)) + gjy + xj[10] - gly - xl[10];
+            r2 = fmaf(xj[8], ez, fmaf(xj[5], ey, xj[2] * ex)) + gjz + xj[11] - glz - xl[11];
+            // r_lj = A_l (-e) + g_l + t_l - g_j - t_j   (edge l -> j)
+            q0 = -fmaf(xl[6], ez, fmaf(xl[3], ey, xl[0] * ex)) + glx + xl[9] - gjx - xj[9];
+            q1 = -fmaf(xl[7], ez, fmaf(xl[4], ey, xl[1] * ex)) + gly + xl[10] - gjy - xj[10];
+            q2 = -fmaf(xl[8], ez, fmaf(xl[5], ey, xl[2] * ex)) + glz + xl[11] - gjz - xj[11];
+            e_reg = ((double)r0 * r0 + (double)r1 * r1) + (double)r2 * r2;
+        }
+        float *rg = rn.rg[tid];
+        rg[0] = ex; rg[1] = ey; rg[2] = ez;
+        rg[3] = r0; rg[4] = r1; rg[5] = r2;
+        rg[6] = q0; rg[7] = q1; rg[8] = q2;
+    }
+    if (tid == 0) {
+        const float *x = rn.xj;
+        const float *c[3] = {x, x + 3, x + 6};
+        auto dot = [](const float *u, const float *v) { return fmaf(u[2], v[2], fmaf(u[1], v[1], u[0] * v[0])); };
+        rn.rr[0] = dot(c[0], c[1]);
+        rn.rr[1] = dot(c[0], c[2]);
+        rn.rr[2] = dot(c[1], c[2]);
+        rn.rr[3] = dot(c[0], c[0]) - 1.f;
+        rn.rr[4] = dot(c[1], c[1]) - 1.f;
+        rn.rr[5] = dot(c[2], c[2]) - 1.f;
+        for (int q = 0; q < 6; ++q)
+            for (int t = 0; t < 9; ++t) rn.Jr[q][t] = 0.f;
+        const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+        for (int q = 0; q < 3; ++q) {
+            for (int t = 0; t < 3; ++t) {
+                rn.Jr[q][3 * pa[q] + t] = c[pb[q]][t];
+                rn.Jr[q][3 * pb[q] + t] = c[pa[q]][t];
+            }
+        }
+        for (int q = 0; q < 3; ++q)
+            for (int t = 0; t < 3; ++t) rn.Jr[3 + q][3 * q + t] = 2.f * c[q][t];
+    }
+    const double ereg_tot = block_sum<NT>(e_reg, rn.red);   // also a barrier
+    if (tid < 10) {
+        float sacc = 0.f;
+        for (int t = 0; t < nslots; ++t) {
+            if (rn.cols[t] == j) continue;
+            const float eh[4] = {rn.rg[t][0], rn.rg[t][1], rn.rg[t][2], 1.f};
+            sacc = fmaf(eh[kPairC0[tid]], eh[kPairC1[tid]], sacc);
+        }
+        rn.EE[tid] = sacc;
+    }
+    if (tid < 144) rn.Hd[tid / 12][tid % 12] = tid / 12 == tid % 12 ? (double)a.lambda : 0.0;
+    __syncthreads();
+    if (tid == 0) {
+        double erot = 0.0;
+        for (int q = 0; q < 6; ++q) erot += (double)rn.rr[q] * rn.rr[q];
+        s.node_part[2 * j + 0] = erot;
+        s.node_part[2 * j + 1] = ereg_tot;
+    }
+    int deg = 0;
+    for (int q = 0; q < nslots; ++q) deg += rn.cols[q] != j;
+    const float wd = a.w_data, wreg = a.w_reg, wrot = a.w_rot;
+    float *outb = a.blocks + (size_t)rb * 144;
+    for (int t = tid; t < nslots * 144; t += NT) {
+        const int sl = t / 144, en = t % 144;
+        const int R = en / 12, C = en % 12;
+        const int c = R / 3, aa = R % 3, c2 = C / 3, a2 = C % 3;
+        const int l = rn.cols[sl];
+        const float hd = data(sl, R, C);
+        float reg = 0.f, rot = 0.f;
+        if (l != j) {
+            if (aa == a2) {
+                const float eh_c = c < 3 ? rn.rg[sl][c] : 1.f;
+                const float fh_c2 = c2 < 3 ? -rn.rg[sl][c2] : 1.f;
+                if (c2 == 3) reg -= eh_c;      // edge j -> l
+                if (c == 3) reg -= fh_c2;      // edge l -> j
+            }
+        } else {
+            if (aa == a2) {
+                reg = rn.EE[pc_index(c, c2)];
+                if (c == 3 && c2 == 3) reg += (float)deg;
+            }
+            if (c < 3 && c2 < 3) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) rot = fmaf(rn.Jr[q][R], rn.Jr[q][C], rot);
+            }
+        }
+        const float rr = fmaf(wrot, rot, wreg * reg);
+        const float h = l != j ? fmaf(wreg, reg, wd * hd) : fmaf(wrot, rot, fmaf(wreg, reg, wd * hd));
+        if (l == j) rn.Hd[R][C] = (double)h + (R == C ? (double)a.lambda : 0.0);
+        outb[(size_t)sl * 144 + en] = h;
+        if (rr_out) rr_out[(size_t)(rb + sl) * 144 + en] = rr;
+    }
+    if (tid < 12) {
+        const int c = tid / 3, aa = tid % 3;
+        float reg = 0.f;
+        for (int t = 0; t < nslots; ++t) {
+            if (rn.cols[t] == j) continue;
+            const float eh_c = c < 3 ? rn.rg[t][c] : 1.f;
+            reg = fmaf(eh_c, rn.rg[t][3 + aa], reg);
+            if (c == 3) reg -= rn.rg[t][6 + aa];
+        }
+        float rot = 0.f;
+        if (c < 3) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) rot = fmaf(rn.Jr[q][tid], rn.rr[q], rot);
+        }
+        a.gvec[(size_t)j * 12 + tid] = fmaf(wrot, rot, fmaf(wreg, reg, wd * rn.gd[tid]));
+    }
+    // block-Jacobi preconditioner of this row: (H_jj + lambda I)^-1 in float64, by wave 0
+    if (a.minv) {
+        __syncthreads();
+        if (wave == 0) {
+            const bool ok = chol_inverse_wave(rn.Hd, rn.Li, a.minv + (size_t)j * 144);
+            if (!ok && lane == 0) atomicOr(a.flags, MISSLAM_FLAG_NONSPD_BLOCK);
+        }
+    }
+}
 
 // Registers of one list entry between its global loads and its LDS staging.
 template <int K>
@@ -200,7 +347,7 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_rows_kernel(StepArgs a, 
     const int nslots = min(re - rb, MISSLAM_MAX_ROW);
     for (int t = tid; t < (re - rb - nslots) * 144; t += kAsmThreads)
         a.blocks[(size_t)(rb + nslots) * 144 + t] = 0.f;   // blocks of a row longer than MISSLAM_MAX_ROW
-    for (int t = tid; t < nslots; t += kAsmThreads) sh.cols[t] = a.g.col_idx[rb + t];
+    for (int t = tid; t < nslots; t += kAsmThreads) sh.rn.cols[t] = a.g.col_idx[rb + t];
     for (int t = lane; t < MISSLAM_MAX_ROW * 64; t += kWave) (&sh.accS[wave][0][0])[t] = 0.f;
 
     const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
@@ -344,8 +491,7 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_rows_kernel(StepArgs a, 
 #pragma unroll
         for (int q = 0; q < 12; ++q) sh.gw[wave][q] = gacc[q];
     }
-    // ---- node-level terms: parameters, regulariser residuals, rotation Jacobian
-    if (tid < 12) sh.xj[tid] = a.nd.x[(size_t)j * 12 + tid];
+    if (tid < 12) sh.rn.xj[tid] = a.nd.x[(size_t)j * 12 + tid];
     __syncthreads();
     for (int t = tid; t < nslots * 64; t += kAsmThreads) {
         const int sl = t / 64, en = t % 64;
@@ -354,140 +500,499 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_rows_kernel(StepArgs a, 
             sh.accS[0][sl][en] = v;
         }
     }
-    double e_reg = 0.0;
-    if (tid < nslots) {
-        const int l = sh.cols[tid];
-        float ex = 0.f, ey = 0.f, ez = 0.f, r0 = 0.f, r1 = 0.f, r2 = 0.f, q0 = 0.f, q1 = 0.f, q2 = 0.f;
-        if (l != j) {
-            const float glx = a.nd.gx[l], gly = a.nd.gy[l], glz = a.nd.gz[l];
-            const float *xl = a.nd.x + (size_t)l * 12;
-            const float *xj = sh.xj;
-            ex = glx - gjx;
-            ey = gly - gjy;
-            ez = glz - gjz;
-            // r_jl = A_j e + g_j + t_j - g_l - t_l   (edge j -> l)
-            r0 = fmaf(xj[6], ez, fmaf(xj[3], ey, xj[0] * ex)) + gjx + xj[9] - glx - xl[9];
-            r1 = fmaf(xj[7], ez, fmaf(xj[4], ey, xj[1] * ex)) + gjy + xj[10] - gly - xl[10];
-            r2 = fmaf(xj[8], ez, fmaf(xj[5], ey, xj[2] * ex)) + gjz + xj[11] - glz - xl[11];
-            // r_lj = A_l (-e) + g_l + t_l - g_j - t_j   (edge l -> j)
-            q0 = -fmaf(xl[6], ez, fmaf(xl[3], ey, xl[0] * ex)) + glx + xl[9] - gjx - xj[9];
-            q1 = -fmaf(xl[7], ez, fmaf(xl[4], ey, xl[1] * ex)) + gly + xl[10] - gjy - xj[10];
-            q2 = -fmaf(xl[8], ez, fmaf(xl[5], ey, xl[2] * ex)) + glz + xl[11] - gjz - xj[11];
-            e_reg = ((double)r0 * r0 + (double)r1 * r1) + (double)r2 * r2;
-        }
-        float *rg = sh.rg[tid];
-        rg[0] = ex; rg[1] = ey; rg[2] = ez;
-        rg[3] = r0; rg[4] = r1; rg[5] = r2;
-        rg[6] = q0; rg[7] = q1; rg[8] = q2;
-    }
-    if (tid == 0) {
-        const float *x = sh.xj;
-        const float *c[3] = {x, x + 3, x + 6};
-        auto dot = [](const float *u, const float *v) { return fmaf(u[2], v[2], fmaf(u[1], v[1], u[0] * v[0])); };
-        sh.rr[0] = dot(c[0], c[1]);
-        sh.rr[1] = dot(c[0], c[2]);
-        sh.rr[2] = dot(c[1], c[2]);
-        sh.rr[3] = dot(c[0], c[0]) - 1.f;
-        sh.rr[4] = dot(c[1], c[1]) - 1.f;
-        sh.rr[5] = dot(c[2], c[2]) - 1.f;
-        for (int q = 0; q < 6; ++q)
-            for (int t = 0; t < 9; ++t) sh.Jr[q][t] = 0.f;
-        const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
-        for (int q = 0; q < 3; ++q) {
-            for (int t = 0; t < 3; ++t) {
-                sh.Jr[q][3 * pa[q] + t] = c[pb[q]][t];
-                sh.Jr[q][3 * pb[q] + t] = c[pa[q]][t];
-            }
-        }
-        for (int q = 0; q < 3; ++q)
-            for (int t = 0; t < 3; ++t) sh.Jr[3 + q][3 * q + t] = 2.f * c[q][t];
-    }
-    const double ereg_tot = block_sum<kAsmThreads>(e_reg, sh.red);   // also a barrier
-    if (tid < 10) {
-        float sacc = 0.f;
-        for (int t = 0; t < nslots; ++t) {
-            if (sh.cols[t] == j) continue;
-            const float eh[4] = {sh.rg[t][0], sh.rg[t][1], sh.rg[t][2], 1.f};
-            sacc = fmaf(eh[kPairC0[tid]], eh[kPairC1[tid]], sacc);
-        }
-        sh.EE[tid] = sacc;
-    }
+    if (tid < 12) sh.rn.gd[tid] = sh.gw[0][tid] + sh.gw[1][tid] + sh.gw[2][tid] + sh.gw[3][tid];
     __syncthreads();
-    if (tid == 0) {
-        double erot = 0.0;
-        for (int q = 0; q < 6; ++q) erot += (double)sh.rr[q] * sh.rr[q];
-        s.node_part[2 * j + 0] = erot;
-        s.node_part[2 * j + 1] = ereg_tot;
-    }
-    int deg = 0;
-    for (int q = 0; q < nslots; ++q) deg += sh.cols[q] != j;
-    if (tid < 144) sh.Hd[tid / 12][tid % 12] = tid / 12 == tid % 12 ? (double)a.lambda : 0.0;
-    __syncthreads();
-    const float wd = a.w_data, wreg = a.w_reg, wrot = a.w_rot;
-    // ---- expand statistics into 12x12 blocks and add the regularisers
-    float *outb = a.blocks + (size_t)rb * 144;
-    const int nent = nslots * 144;
-    for (int t = tid; t < nent; t += kAsmThreads) {
-        const int sl = t / 144, en = t % 144;
-        const int R = en / 12, C = en % 12;
+    // data-term block from the statistic: H[(c,a),(c',a')] = S[c,c',a,a'] + delta_c' S[c,3,a,a']
+    auto data = [&](int sl, int R, int C) {
         const int c = R / 3, aa = R % 3, c2 = C / 3, a2 = C % 3;
-        const int l = sh.cols[sl];
         const float *S = sh.accS[0][sl];
         const int ni = na_index(aa, a2);
         float h = S[pc_index(c, c2) * 6 + ni];
-        float reg = 0.f;
-        if (l != j) {
-            // delta = g_j - g_l = -e
-            const float dl = c2 < 3 ? -sh.rg[sl][c2] : 0.f;
-            h = fmaf(dl, S[pc_index(c, 3) * 6 + ni], h);
-            if (aa == a2) {
-                const float eh_c = c < 3 ? sh.rg[sl][c] : 1.f;
-                const float fh_c2 = c2 < 3 ? -sh.rg[sl][c2] : 1.f;
-                if (c2 == 3) reg -= eh_c;      // edge j -> l
-                if (c == 3) reg -= fh_c2;      // edge l -> j
-            }
-            h = fmaf(wreg, reg, wd * h);
-        } else {
-            h = wd * h;
-            if (aa == a2) {
-                reg = sh.EE[pc_index(c, c2)];
-                if (c == 3 && c2 == 3) reg += (float)deg;
-            }
-            float rot = 0.f;
-            if (c < 3 && c2 < 3) {
+        if (sh.rn.cols[sl] != j && c2 < 3) h = fmaf(-sh.rn.rg[sl][c2], S[pc_index(c, 3) * 6 + ni], h);   // delta = -e
+        return h;
+    };
+    row_finalize<kAsmThreads>(a, s, sh.rn, j, rb, nslots, gjx, gjy, gjz, data, nullptr);
+}
+
+
+// ---------------------------------------------------------------- low-precision assembly on the matrix cores
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaOp;
+template <>
+struct MfmaOp<__bf16> {
+    typedef bf16x8_t vec;
+    static __device__ __forceinline__ f32x4_t run(vec a, vec b, f32x4_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct MfmaOp<_Float16> {
+    typedef f16x8_t vec;
+    static __device__ __forceinline__ f32x4_t run(vec a, vec b, f32x4_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+constexpr int kLpThreads = 128;
+constexpr int kLpWaves = kLpThreads / kWave;
+
+template <int K, typename T>
+struct LpShared {
+    float acc[kLpWaves][MISSLAM_MAX_ROW * 144];
+    T Jt[kLpWaves][12 * (K + 1)][kBatch];   // per entry: J of node j (rows 0-11), then of its k set nodes
+    uint32_t key[kLpWaves][kBatch][2];
+    float gw[kLpWaves][12];
+    RowNode<kLpThreads> rn;
+};
+
+// Same rows as assemble_rows_kernel, but the data term is formed from the
+// per-point Jacobian rows J_pj = w_pj kron((v_p - g_j, 1), n'_p) rounded to T
+// (bfloat16 or float16) and contracted on the matrix cores with float32
+// accumulation: for each run of equal kNN sets, chunks of 32 list entries
+// give J_j^T J_{set} (16x32 by 32x16 tiles, 12 useful rows).  The
+// gradient g and every regulariser block stay float32.  rr_out receives the
+// regulariser + rotation blocks alone for the float32 refinement.
+template <int K, typename T>
+__global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, StepScratch s, float *rr_out) {
+    __shared__ LpShared<K, T> sh;
+    constexpr int NT = (12 * K + 15) / 16;           // column tiles of the set nodes' parameters
+    const int m = a.nd.m;
+    const int per = (int)((m + 7) / 8);
+    const int j = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (j >= m) return;
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave, lane = tid % kWave;
+    const int64_t n = a.pts.n;
+
+    const int rb = min(a.g.row_ptr[j], a.g.bsr_cap);
+    const int re = min(a.g.row_ptr[j + 1], a.g.bsr_cap);
+    const int nslots = min(re - rb, MISSLAM_MAX_ROW);
+    for (int t = tid; t < (re - rb - nslots) * 144; t += kLpThreads) a.blocks[(size_t)(rb + nslots) * 144 + t] = 0.f;
+    for (int t = tid; t < nslots; t += kLpThreads) sh.rn.cols[t] = a.g.col_idx[rb + t];
+    for (int t = lane; t < MISSLAM_MAX_ROW * 144; t += kWave) sh.acc[wave][t] = 0.f;
+
+    const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
+    const int lb = a.g.list_ptr[j];
+    const int cnt = min(a.g.list_ptr[j + 1] - lb, MISSLAM_MAX_LIST);
+    const int quota = (cnt + kLpWaves - 1) / kLpWaves;
+    const int my0 = min(cnt, wave * quota), my1 = min(cnt, my0 + quota);
+    const int nbatch = (my1 - my0 + kBatch - 1) / kBatch;
+    const int r16 = lane % 16, kb = 8 * (lane / 16);
+
+    f32x4_t D[NT];
 #pragma unroll
-                for (int q = 0; q < 6; ++q) rot = fmaf(sh.Jr[q][R], sh.Jr[q][C], rot);
+    for (int q = 0; q < NT; ++q) D[q] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    uint32_t cur0 = 0xFFFFFFFFu, cur1 = 0xFFFFFFFFu;
+    float gacc[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) gacc[q] = 0.f;
+    __syncthreads();   // cols visible to every wave
+
+    auto flush = [&]() {
+        if (cur0 == 0xFFFFFFFFu) return;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            const int col = 16 * q + r16;
+            const int sidx = col / 12;
+            if (sidx < K) {
+                const uint32_t slot = sidx < 4 ? (cur0 >> (8 * sidx)) & 0xFF : (cur1 >> (8 * (sidx - 4))) & 0xFF;
+                if (slot < (uint32_t)nslots) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = 4 * (lane / 16) + i;
+                        if (row < 12) sh.acc[wave][slot * 144 + row * 12 + col % 12] += D[q][i];
+                    }
+                }
             }
-            h = fmaf(wrot, rot, fmaf(wreg, reg, h));
-            sh.Hd[R][C] = (double)h + (R == C ? (double)a.lambda : 0.0);
+            D[q] = f32x4_t{0.f, 0.f, 0.f, 0.f};
         }
-        outb[(size_t)sl * 144 + en] = h;
+    };
+
+    EntryRegs<K> nxt;
+    if (nbatch > 0 && lane < min(kBatch, my1 - my0)) entry_load<K>(a, s, n, lb + my0 + lane, nxt);
+    for (int bt = 0; bt < nbatch; ++bt) {
+        const int e0 = my0 + bt * kBatch;
+        const int nb = min(kBatch, my1 - e0);
+        EntryRegs<K> cu = nxt;
+        if (bt + 1 < nbatch && lane < min(kBatch, my1 - e0 - kBatch))
+            entry_load<K>(a, s, n, lb + e0 + kBatch + lane, nxt);
+        // ---- phase 1: lane = list entry; Jacobian rows in T, gradient in float32
+        if (lane < nb) {
+            float wj = 0.f;
+#pragma unroll
+            for (int t = 0; t < K; ++t)
+                if (cu.q[t] == j) wj = cu.wq[t];
+#pragma unroll
+            for (int u = 1; u < K; ++u)
+#pragma unroll
+                for (int v = u; v > 0; --v)
+                    if (cu.q[v] < cu.q[v - 1]) {
+                        const int ti = cu.q[v];
+                        cu.q[v] = cu.q[v - 1];
+                        cu.q[v - 1] = ti;
+                        const float tw = cu.wq[v];
+                        cu.wq[v] = cu.wq[v - 1];
+                        cu.wq[v - 1] = tw;
+                    }
+            const float nn[3] = {cu.nr.x, cu.nr.y, cu.nr.z};
+            const float uj[4] = {cu.vx - gjx, cu.vy - gjy, cu.vz - gjz, 1.f};
+#pragma unroll
+            for (int p = 0; p < 12; ++p) sh.Jt[wave][p][lane] = (T)(wj * uj[p / 3] * nn[p % 3]);
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+                const int l = cu.q[t];
+                const float ul[4] = {cu.vx - a.nd.gx[l], cu.vy - a.nd.gy[l], cu.vz - a.nd.gz[l], 1.f};
+#pragma unroll
+                for (int p = 0; p < 12; ++p) sh.Jt[wave][12 + 12 * t + p][lane] = (T)(cu.wq[t] * ul[p / 3] * nn[p % 3]);
+            }
+            sh.key[wave][lane][0] = cu.k0;
+            sh.key[wave][lane][1] = cu.k1;
+            const float wr = wj * cu.nr.w;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float f = wr * uj[c];
+#pragma unroll
+                for (int aa = 0; aa < 3; ++aa) gacc[3 * c + aa] = fmaf(f, nn[aa], gacc[3 * c + aa]);
+            }
+        }
+        bool start;
+        {
+            const uint32_t p0 = __shfl_up(cu.k0, 1, 64), p1 = __shfl_up(cu.k1, 1, 64);
+            const uint32_t q0 = lane == 0 ? cur0 : p0, q1 = lane == 0 ? cur1 : p1;
+            start = lane < nb && (cu.k0 != q0 || cu.k1 != q1);
+        }
+        const uint64_t starts = __ballot(start);
+        wave_sync();
+        // ---- phase 2: per run of equal sets, 32-entry chunks on the matrix cores
+        int t = 0;
+        while (t < nb) {
+            if (starts & (1ull << t)) {
+                flush();
+                cur0 = sh.key[wave][t][0];
+                cur1 = sh.key[wave][t][1];
+            }
+            const uint64_t later = t + 1 < 64 ? (starts >> (t + 1)) : 0ull;
+            const int t1 = later ? min(nb, t + 1 + __builtin_ctzll(later)) : nb;
+            for (int c0 = t; c0 < t1; c0 += 32) {
+                typename MfmaOp<T>::vec av;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int e = c0 + kb + i;
+                    av[i] = (e < t1 && r16 < 12) ? sh.Jt[wave][r16][e] : (T)0.f;
+                }
+#pragma unroll
+                for (int q = 0; q < NT; ++q) {
+                    const int col = 16 * q + r16;
+                    typename MfmaOp<T>::vec bv;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int e = c0 + kb + i;
+                        bv[i] = (e < t1 && col < 12 * K) ? sh.Jt[wave][12 + col][e] : (T)0.f;
+                    }
+                    D[q] = MfmaOp<T>::run(av, bv, D[q]);
+                }
+            }
+            t = t1;
+        }
+        wave_sync();
+    }
+    flush();
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        float v = gacc[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        gacc[q] = v;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 12; ++q) sh.gw[wave][q] = gacc[q];
+    }
+    if (tid < 12) sh.rn.xj[tid] = a.nd.x[(size_t)j * 12 + tid];
+    __syncthreads();
+    for (int t = tid; t < nslots * 144; t += kLpThreads) {
+        float v = sh.acc[0][t];
+#pragma unroll
+        for (int w = 1; w < kLpWaves; ++w) v += sh.acc[w][t];
+        sh.acc[0][t] = v;
     }
     if (tid < 12) {
-        const int c = tid / 3, aa = tid % 3;
-        const float gd = sh.gw[0][tid] + sh.gw[1][tid] + sh.gw[2][tid] + sh.gw[3][tid];
-        float reg = 0.f;
-        for (int t = 0; t < nslots; ++t) {
-            if (sh.cols[t] == j) continue;
-            const float eh_c = c < 3 ? sh.rg[t][c] : 1.f;
-            reg = fmaf(eh_c, sh.rg[t][3 + aa], reg);
-            if (c == 3) reg -= sh.rg[t][6 + aa];
-        }
-        float rot = 0.f;
-        if (c < 3) {
+        float v = sh.gw[0][tid];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) rot = fmaf(sh.Jr[q][tid], sh.rr[q], rot);
-        }
-        a.gvec[(size_t)j * 12 + tid] = fmaf(wrot, rot, fmaf(wreg, reg, wd * gd));
+        for (int w = 1; w < kLpWaves; ++w) v += sh.gw[w][tid];
+        sh.rn.gd[tid] = v;
     }
-    // ---- block-Jacobi preconditioner of this row: (H_jj + lambda I)^-1 in float64, by wave 0
-    if (a.minv) {
-        __syncthreads();
-        if (wave == 0) {
-            const bool ok = chol_inverse_wave(sh.Hd, sh.Li, a.minv + (size_t)j * 144);
-            if (!ok && lane == 0) atomicOr(a.flags, MISSLAM_FLAG_NONSPD_BLOCK);
+    __syncthreads();
+    auto data = [&](int sl, int R, int C) { return sh.acc[0][sl * 144 + R * 12 + C]; };
+    row_finalize<kLpThreads>(a, s, sh.rn, j, rb, nslots, gjx, gjy, gjz, data, rr_out);
+}
+
+hipError_t launch_assemble_lp(const StepArgs &a, const StepScratch &s, int precision, float *rr_out,
+                              hipStream_t st) {
+    const unsigned rows = 8 * (unsigned)((a.nd.m + 7) / 8);
+    const bool bf = precision == MISSLAM_PREC_BF16;
+    switch (a.g.k) {
+#define MSL_LP_CASE(KK)                                                                                         \
+    case KK:                                                                                                    \
+        if (bf)                                                                                                 \
+            hipLaunchKernelGGL((assemble_lp_kernel<KK, __bf16>), dim3(rows), dim3(kLpThreads), 0, st, a, s, rr_out); \
+        else                                                                                                    \
+            hipLaunchKernelGGL((assemble_lp_kernel<KK, _Float16>), dim3(rows), dim3(kLpThreads), 0, st, a, s, rr_out); \
+        break;
+        MSL_LP_CASE(1) MSL_LP_CASE(2) MSL_LP_CASE(3) MSL_LP_CASE(4)
+#undef MSL_LP_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- float32 matrix-free data term (refinement)
+
+// (J dx)_p = n'_p . sum_s w_ps (dA_s (v_p - g_s) + dt_s): the linearised data
+// residual change of each point for a parameter step dx.
+template <int K>
+__global__ void __launch_bounds__(256) jv_kernel(StepArgs a, StepScratch s, const float *__restrict__ dx,
+                                                 float *__restrict__ out) {
+    const int64_t n = a.pts.n;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float4 nr = s.nr[i];
+    const float vx = a.pts.px[i], vy = a.pts.py[i], vz = a.pts.pz[i];
+    float ux = 0.f, uy = 0.f, uz = 0.f;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const int j = a.g.knn_idx[(int64_t)t * n + i];
+        const float w = a.g.knn_w[(int64_t)t * n + i];
+        const float *d = dx + (size_t)j * 12;
+        const float ex = vx - a.nd.gx[j], ey = vy - a.nd.gy[j], ez = vz - a.nd.gz[j];
+        ux = fmaf(w, fmaf(d[6], ez, fmaf(d[3], ey, fmaf(d[0], ex, d[9]))), ux);
+        uy = fmaf(w, fmaf(d[7], ez, fmaf(d[4], ey, fmaf(d[1], ex, d[10]))), uy);
+        uz = fmaf(w, fmaf(d[8], ez, fmaf(d[5], ey, fmaf(d[2], ex, d[11]))), uz);
+    }
+    out[i] = fmaf(nr.z, uz, fmaf(nr.y, uy, nr.x * ux));
+}
+
+// One wave per row j: y_j = w_data sum_{p in list(j)} w_pj (J dx)_p kron((v_p - g_j, 1), n'_p)
+//                            + (H_rr dx)_j + lambda dx_j;  rhs_j = g_j + y_j.
+// (The next solve of (H_lo + lambda I) d = -rhs gives d = (H_lo + lambda I)^-1 (-g - y).)
+template <int K>
+__global__ void __launch_bounds__(64) jtv_row_kernel(StepArgs a, StepScratch s, const float *__restrict__ jv,
+                                                     const float *__restrict__ rr, const float *__restrict__ dx,
+                                                     const float *__restrict__ g, float *__restrict__ rhs) {
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t n = a.pts.n;
+    const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
+    const int lb = a.g.list_ptr[j];
+    const int cnt = min(a.g.list_ptr[j + 1] - lb, MISSLAM_MAX_LIST);
+    float acc[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[q] = 0.f;
+    for (int t = lane; t < cnt; t += 64) {
+        const int p = a.g.list_pts[lb + t];
+        float wj = 0.f;
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+            if (a.g.knn_idx[(int64_t)u * n + p] == j) wj = a.g.knn_w[(int64_t)u * n + p];
+        const float4 nr = s.nr[p];
+        const float f = wj * jv[p];
+        const float uu[4] = {a.pts.px[p] - gjx, a.pts.py[p] - gjy, a.pts.pz[p] - gjz, 1.f};
+        const float nn[3] = {nr.x, nr.y, nr.z};
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int aa = 0; aa < 3; ++aa) acc[3 * c + aa] = fmaf(f * uu[c], nn[aa], acc[3 * c + aa]);
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        float v = acc[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        acc[q] = v;
+    }
+    if (lane < 12) {
+        float y = 0.f;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) y = q == lane ? acc[q] : y;
+        y = a.w_data * y;
+        const int rb = min(a.g.row_ptr[j], a.g.bsr_cap), re = min(a.g.row_ptr[j + 1], a.g.bsr_cap);
+        for (int pb = rb; pb < re; ++pb) {
+            const int l = a.g.col_idx[pb];
+            const float *B = rr + (size_t)pb * 144 + lane * 12;
+            const float *xl = dx + (size_t)l * 12;
+#pragma unroll
+            for (int b = 0; b < 12; ++b) y = fmaf(B[b], xl[b], y);
+        }
+        y = fmaf(a.lambda, dx[(size_t)j * 12 + lane], y);
+        rhs[(size_t)j * 12 + lane] = g[(size_t)j * 12 + lane] + y;
+    }
+}
+
+__global__ void axpy_kernel(float *__restrict__ y, const float *__restrict__ x, int count) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < count) y[t] += x[t];
+}
+
+hipError_t launch_refine_rhs(const StepArgs &a, const StepScratch &s, const float *dx, const float *rr, const float *g,
+                             float *jv, float *rhs, hipStream_t st) {
+    const int64_t n = a.pts.n;
+    if (n > 0) {
+        switch (a.g.k) {
+#define MSL_JV_CASE(KK) \
+    case KK: hipLaunchKernelGGL((jv_kernel<KK>), dim3(nblk(n, 256)), dim3(256), 0, st, a, s, dx, jv); break;
+            MSL_JV_CASE(1) MSL_JV_CASE(2) MSL_JV_CASE(3) MSL_JV_CASE(4)
+            MSL_JV_CASE(5) MSL_JV_CASE(6) MSL_JV_CASE(7) MSL_JV_CASE(8)
+#undef MSL_JV_CASE
+            default: return hipErrorInvalidValue;
         }
     }
+    switch (a.g.k) {
+#define MSL_JT_CASE(KK) \
+    case KK: hipLaunchKernelGGL((jtv_row_kernel<KK>), dim3(a.nd.m), dim3(64), 0, st, a, s, jv, rr, dx, g, rhs); break;
+        MSL_JT_CASE(1) MSL_JT_CASE(2) MSL_JT_CASE(3) MSL_JT_CASE(4)
+        MSL_JT_CASE(5) MSL_JT_CASE(6) MSL_JT_CASE(7) MSL_JT_CASE(8)
+#undef MSL_JT_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(float *y, const float *x, int count, hipStream_t st) {
+    hipLaunchKernelGGL(axpy_kernel, dim3(nblk(count, 256)), dim3(256), 0, st, y, x, count);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- node energies without assembly
+
+// E_rot of node j (Eq.(5)) and E_reg over its outgoing edges (Eq.(6)), float64
+// sums of float32 residuals in the assembly's order; one thread per node.
+__global__ void __launch_bounds__(256) node_energy_kernel(StepArgs a, StepScratch s) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= a.nd.m) return;
+    const float *xj = a.nd.x + (size_t)j * 12;
+    auto dot = [](const float *u, const float *v) { return fmaf(u[2], v[2], fmaf(u[1], v[1], u[0] * v[0])); };
+    const float rr[6] = {dot(xj, xj + 3), dot(xj, xj + 6), dot(xj + 3, xj + 6),
+                         dot(xj, xj) - 1.f, dot(xj + 3, xj + 3) - 1.f, dot(xj + 6, xj + 6) - 1.f};
+    double erot = 0.0;
+    for (int q = 0; q < 6; ++q) erot += (double)rr[q] * rr[q];
+    const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
+    const int rb = min(a.g.row_ptr[j], a.g.bsr_cap), re = min(a.g.row_ptr[j + 1], a.g.bsr_cap);
+    double ereg = 0.0;
+    for (int p = rb; p < re && p - rb < MISSLAM_MAX_ROW; ++p) {
+        const int l = a.g.col_idx[p];
+        if (l == j) continue;
+        const float glx = a.nd.gx[l], gly = a.nd.gy[l], glz = a.nd.gz[l];
+        const float *xl = a.nd.x + (size_t)l * 12;
+        const float ex = glx - gjx, ey = gly - gjy, ez = glz - gjz;
+        const float r0 = fmaf(xj[6], ez, fmaf(xj[3], ey, xj[0] * ex)) + gjx + xj[9] - glx - xl[9];
+        const float r1 = fmaf(xj[7], ez, fmaf(xj[4], ey, xj[1] * ex)) + gjy + xj[10] - gly - xl[10];
+        const float r2 = fmaf(xj[8], ez, fmaf(xj[5], ey, xj[2] * ex)) + gjz + xj[11] - glz - xl[11];
+        ereg += ((double)r0 * r0 + (double)r1 * r1) + (double)r2 * r2;
+    }
+    s.node_part[2 * j + 0] = erot;
+    s.node_part[2 * j + 1] = ereg;
+}
+
+hipError_t launch_node_energy(const StepArgs &a, const StepScratch &s, hipStream_t st) {
+    hipLaunchKernelGGL(node_energy_kernel, dim3(nblk(a.nd.m, 256)), dim3(256), 0, st, a, s);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- adjoint of the energy
+
+// dE/dv_i for frozen correspondences and kNN sets, normalised Gaussian weights:
+//   2 w_data r_i n'^T sum_j [w_j A_j + y_j (grad w_j)^T],  y_j = A_j (v - g_j) + g_j + t_j,
+//   grad w_j = w_j (-(v - g_j) + sum_l w_l (v - g_l)) / sigma^2
+// scaled by the upstream gradient.  One thread per point.
+template <int K>
+__global__ void __launch_bounds__(256) vjp_points_kernel(StepArgs a, StepScratch s, float sigma,
+                                                         const float *__restrict__ grad_e, float *__restrict__ out) {
+    const int64_t n = a.pts.n;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float4 nr = s.nr[i];
+    const float ge = grad_e ? grad_e[0] : 1.f;
+    const float vx = a.pts.px[i], vy = a.pts.py[i], vz = a.pts.pz[i];
+    float d[K][3], wv[K];
+    float md[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const int j = a.g.knn_idx[(int64_t)t * n + i];
+        wv[t] = a.g.knn_w[(int64_t)t * n + i];     // the normalised Gaussian weights of this point
+        d[t][0] = vx - a.nd.gx[j];
+        d[t][1] = vy - a.nd.gy[j];
+        d[t][2] = vz - a.nd.gz[j];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) md[c] = fmaf(wv[t], d[t][c], md[c]);
+    }
+    const float is2 = 1.f / (sigma * sigma);
+    // row = n'^T M, M = sum_j [w_j A_j + y_j grad_w_j^T]
+    float row[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        const int j = a.g.knn_idx[(int64_t)t * n + i];
+        const float *x = a.nd.x + (size_t)j * 12;
+        // n'^T A_j: component c = sum_a n'_a A[a][c] = n' . column c
+        const float nA[3] = {fmaf(nr.z, x[2], fmaf(nr.y, x[1], nr.x * x[0])),
+                             fmaf(nr.z, x[5], fmaf(nr.y, x[4], nr.x * x[3])),
+                             fmaf(nr.z, x[8], fmaf(nr.y, x[7], nr.x * x[6]))};
+        const float y0 = fmaf(x[6], d[t][2], fmaf(x[3], d[t][1], x[0] * d[t][0])) + a.nd.gx[j] + x[9];
+        const float y1 = fmaf(x[7], d[t][2], fmaf(x[4], d[t][1], x[1] * d[t][0])) + a.nd.gy[j] + x[10];
+        const float y2 = fmaf(x[8], d[t][2], fmaf(x[5], d[t][1], x[2] * d[t][0])) + a.nd.gz[j] + x[11];
+        const float ny = fmaf(nr.z, y2, fmaf(nr.y, y1, nr.x * y0));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float gw = wv[t] * (md[c] - d[t][c]) * is2;
+            row[c] = fmaf(wv[t], nA[c], fmaf(ny, gw, row[c]));
+        }
+    }
+    const float sc = 2.f * a.w_data * nr.w * ge;
+    out[i] = sc * row[0];
+    out[n + i] = sc * row[1];
+    out[2 * n + i] = sc * row[2];
+}
+
+hipError_t launch_vjp_points(const StepArgs &a, const StepScratch &s, float sigma, const float *grad_e, float *out,
+                             hipStream_t st) {
+    if (a.pts.n == 0) return hipSuccess;
+    const dim3 grid(nblk(a.pts.n, 256)), blk(256);
+    switch (a.g.k) {
+#define MSL_VJ_CASE(KK) \
+    case KK: hipLaunchKernelGGL((vjp_points_kernel<KK>), grid, blk, 0, st, a, s, sigma, grad_e, out); break;
+        MSL_VJ_CASE(1) MSL_VJ_CASE(2) MSL_VJ_CASE(3) MSL_VJ_CASE(4)
+        MSL_VJ_CASE(5) MSL_VJ_CASE(6) MSL_VJ_CASE(7) MSL_VJ_CASE(8)
+#undef MSL_VJ_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// dE/dx = 2 g (g = sum w J^T r of the normal equations), scaled by the upstream gradient.
+__global__ void scale_grad_kernel(const float *__restrict__ g, int count, const float *__restrict__ grad_e,
+                                  float *__restrict__ out) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < count) out[t] = 2.f * (grad_e ? grad_e[0] : 1.f) * g[t];
+}
+
+// E = w_data E_data + w_rot E_rot + w_reg E_reg (Eq.(3) restricted to the hot-path terms).
+__global__ void energy_total_kernel(const misslam_report *rep, double w_data, double w_rot, double w_reg,
+                                    double *out) {
+    if (threadIdx.x == 0) out[0] = (w_data * rep->e_data + w_rot * rep->e_rot) + w_reg * rep->e_reg;
+}
+
+hipError_t launch_grad_params(const float *g, int m, const float *grad_e, float *out, hipStream_t st) {
+    hipLaunchKernelGGL(scale_grad_kernel, dim3(nblk(12 * (int64_t)m, 256)), dim3(256), 0, st, g, 12 * m, grad_e, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_total(const misslam_report *rep, float w_data, float w_rot, float w_reg, double *out,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(energy_total_kernel, dim3(1), dim3(64), 0, st, rep, (double)w_data, (double)w_rot,
+                       (double)w_reg, out);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- energy report

@@ -236,3 +236,57 @@ def fuse(points, w, stamp, nodes, x, graph, nmap, cam, pose_, fp, ws, outputs=Fa
         _ptr(nmap), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(fp), _ptr(reg), _ptr(regd), _ptr(buf),
         ctypes.c_size_t(buf.numel()), _stream()))
     return (reg, regd[:n]) if outputs else None
+
+
+def energy_vjp(points, nodes, x, graph, nmap, cam, pose_, params, ws, corr=None, grad_e=None, want_params=True,
+               want_points=True):
+    """Energy (and gradients) at x.  corr=None: associate now; else hold the given correspondences.
+
+    Returns (energy (1,) float64, grad_params (m, 12) or None, grad_points (3, N) or None, corr, report).
+    """
+    n, m = points.shape[1], nodes.shape[1]
+    dev = points.device
+    e = torch.empty(1, dtype=torch.float64, device=dev)
+    gp = torch.empty((m, 12), dtype=torch.float32, device=dev) if want_params else None
+    gv = torch.empty((3, n), dtype=torch.float32, device=dev) if want_points else None
+    co = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if corr is None else None
+    rep = new_report(1)
+    buf = ws.get(workspace_bytes(n, m, cam.width, cam.height, params))
+    check("misslam_energy_vjp", load().misslam_energy_vjp(
+        ctypes.byref(points_struct(points)), ctypes.byref(nodes_struct(nodes, x)), ctypes.byref(graph.c()),
+        _ptr(nmap), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(params.c()), _ptr(corr), _ptr(co),
+        _ptr(grad_e), _ptr(gp), _ptr(gv), _ptr(e), _ptr(rep), _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
+    return e, gp, gv, (corr if corr is not None else co[:n]), rep
+
+
+class WarpEnergy(torch.autograd.Function):
+    """E(x, v) of Eq.(3) (data + rotation + regularisation) as a differentiable function.
+
+    Forward finds the correspondences; backward holds them (and the kNN sets)
+    fixed and runs the library's adjoint kernels for dE/dx and dE/dv.
+    Usage: WarpEnergy.apply(x, positions, context) with context = dict(points,
+    nodes, graph, nmap, cam, pose, params, ws); positions (3, N) are the
+    canonical coordinates (rows 0-2 of points).
+    """
+
+    @staticmethod
+    def forward(ctx, x, positions, context):
+        pts = context["points"]
+        if positions.data_ptr() != pts.data_ptr():
+            pts = torch.cat([positions.detach(), pts[3:]], 0).contiguous()
+        e, _, _, corr, _ = energy_vjp(pts, context["nodes"], x.detach().contiguous(), context["graph"],
+                                      context["nmap"], context["cam"], context["pose"], context["params"],
+                                      context["ws"], want_params=False, want_points=False)
+        ctx.context = context
+        ctx.save_for_backward(x.detach().contiguous(), pts, corr)
+        return e[0]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        x, pts, corr = ctx.saved_tensors
+        c = ctx.context
+        ge = grad_out.detach().reshape(1).to(torch.float32).contiguous()
+        _, gp, gv, _, _ = energy_vjp(pts, c["nodes"], x, c["graph"], c["nmap"], c["cam"], c["pose"], c["params"],
+                                     c["ws"], corr=corr, grad_e=ge, want_params=ctx.needs_input_grad[0],
+                                     want_points=ctx.needs_input_grad[1])
+        return gp, gv, None
