@@ -17,7 +17,7 @@ from .assoc import associate
 from .depthmap import normal_map
 from .energy import energies
 from .graph import build_graph
-from .pcg import block_jacobi, pcg
+from .pcg import block_jacobi, bsr_matvec, pcg
 from .system import block_system
 from .warp import ed_warp, identity_params, warp_normals
 
@@ -62,11 +62,11 @@ def evaluate(pb, graph, x, Nmap, Nvalid, corr_override=None):
     return vc, nc, asc, energies(x, pb.nodes, graph["nbrs"], asc["r"])
 
 
-def linearize(pb, graph, x, Nmap, Nvalid, corr_override=None):
+def linearize(pb, graph, x, Nmap, Nvalid, corr_override=None, jac_round=None):
     """Warp, associate and assemble at parameters x; returns everything the step needs."""
     vc, nc, asc, e = evaluate(pb, graph, x, Nmap, Nvalid, corr_override)
     blocks, g = block_system(pb.points, pb.nodes, x, graph["idx"], graph["w"], pb.R, asc, graph["nbrs"],
-                             graph["row_ptr"], graph["col_idx"], (pb.w_rot, pb.w_reg, pb.w_data))
+                             graph["row_ptr"], graph["col_idx"], (pb.w_rot, pb.w_reg, pb.w_data), jac_round)
     return vc, nc, asc, blocks, g, e
 
 
@@ -93,7 +93,7 @@ def _adopt(asc, corr, vc, pb, Nmap):
     return out
 
 
-def gn_register(pb, graph=None, x0=None, corr_sequence=None, record=False):
+def gn_register(pb, graph=None, x0=None, corr_sequence=None, record=False, jac_round=None, refine_steps=0):
     """Run pb.gn_iters Gauss-Newton steps.  Returns (x, report).
 
     report["iters"][it] holds energies at the linearisation point of step it
@@ -101,6 +101,11 @@ def gn_register(pb, graph=None, x0=None, corr_sequence=None, record=False):
     the PCG residual norms; report["final"] the energies at the returned x.
     corr_sequence, if given, supplies the correspondence set of each step
     (decision-sync mode).
+
+    jac_round / refine_steps emulate the low-precision form: the step is solved
+    on H_lo (data-term Jacobian rows passed through jac_round before J^T J),
+    then refined refine_steps times: rho = -g - (H + lambda I) dx with the
+    unrounded H, dx += P iterations of PCG on H_lo for rho.
     """
     if graph is None:
         graph = build_graph(pb.points, pb.nodes, pb.k, pb.weight_kind, pb.sigma)
@@ -110,9 +115,16 @@ def gn_register(pb, graph=None, x0=None, corr_sequence=None, record=False):
     rep = {"iters": [], "graph": graph}
     for it in range(pb.gn_iters):
         co = None if corr_sequence is None else corr_sequence[it]
-        vc, nc, asc, blocks, g, e = linearize(pb, graph, x, Nmap, Nvalid, co)
+        vc, nc, asc, blocks, g, e = linearize(pb, graph, x, Nmap, Nvalid, co, jac_round)
         Minv, spd = block_jacobi(graph["row_ptr"], graph["col_idx"], blocks, pb.lam)
         dx, info = pcg(graph["row_ptr"], graph["col_idx"], blocks, g, pb.lam, pb.pcg_iters, Minv)
+        if jac_round is not None and refine_steps > 0:
+            h32, _ = block_system(pb.points, pb.nodes, x, graph["idx"], graph["w"], pb.R, asc, graph["nbrs"],
+                                  graph["row_ptr"], graph["col_idx"], (pb.w_rot, pb.w_reg, pb.w_data))
+            for _ in range(refine_steps):
+                rho = -np.asarray(g).reshape(-1) - bsr_matvec(graph["row_ptr"], graph["col_idx"], h32, dx, pb.lam)
+                d2, _ = pcg(graph["row_ptr"], graph["col_idx"], blocks, -rho, pb.lam, pb.pcg_iters, Minv)
+                dx = dx + d2
         entry = {"e_data": e[0], "e_rot": e[1], "e_reg": e[2], "n_valid": int(asc["valid"].sum()),
                  "resid": info["resid"], "breakdown": info["breakdown"], "nonspd": int((~spd).sum())}
         if record:

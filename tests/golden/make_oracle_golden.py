@@ -1,10 +1,13 @@
 """Writes the float64 oracle's registration result for a generated frame.
 
 Calls only the scene generator and oracle/: nothing here comes from the GPU
-path.  Usage: python tests/golden/make_oracle_golden.py c3
-Output: tests/golden/<config>_oracle.npz with x (m, 12) after the frame's
-Gauss-Newton iterations (independent decisions), the final data energy and the
-per-iteration energies.
+path.  Usage: python tests/golden/make_oracle_golden.py c3 [c3:bf16:2 ...]
+A plain name runs the float64 oracle; name:prec:R runs its emulation of the
+low-precision form (data-term Jacobian rows rounded to bf16 / fp16 before
+J^T J, R refinement passes of each step against the unrounded system).
+Output: tests/golden/<name>[_<prec>_r<R>]_oracle.npz with x (m, 12) after the
+frame's Gauss-Newton iterations (independent decisions), the final energies
+and the per-iteration data energies.
 """
 import os
 import sys
@@ -17,19 +20,30 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import gen  # noqa: E402
 import oracle  # noqa: E402
 
+ROUND = {"bf16": oracle.round_bf16, "fp16": oracle.round_fp16}
 
-def main(name):
+
+def main(spec):
+    parts = spec.split(":")
+    name = parts[0]
     sc = gen.make_scene(name)
     pb = oracle.Problem.from_scene(sc)
-    x, rep = oracle.gn_register(pb)
+    if len(parts) == 1:
+        x, rep = oracle.gn_register(pb)
+        out = f"{name}_oracle.npz"
+    else:
+        prec, steps = parts[1], int(parts[2])
+        rnd = ROUND[prec]
+        x, rep = oracle.gn_register(pb, jac_round=lambda J: rnd(J.astype(np.float32)), refine_steps=steps)
+        out = f"{name}_{prec}_r{steps}_oracle.npz"
     it = rep["iters"]
-    np.savez_compressed(os.path.join(HERE, f"{name}_oracle.npz"), x=x, e_data_final=rep["final"]["e_data"],
+    np.savez_compressed(os.path.join(HERE, out), x=x, e_data_final=rep["final"]["e_data"],
                         e_rot_final=rep["final"]["e_rot"], e_reg_final=rep["final"]["e_reg"],
                         n_valid_final=rep["final"]["n_valid"],
                         e_data=np.array([e["e_data"] for e in it]), n_valid=np.array([e["n_valid"] for e in it]))
-    print(name, "final e_data", rep["final"]["e_data"], "n_valid", rep["final"]["n_valid"])
+    print(out, "final e_data", rep["final"]["e_data"], "n_valid", rep["final"]["n_valid"])
 
 
 if __name__ == "__main__":
-    for nm in sys.argv[1:] or ["c3"]:
-        main(nm)
+    for sp in sys.argv[1:] or ["c3"]:
+        main(sp)
