@@ -2,15 +2,21 @@
 """Throughput of MIS-SLAM's per-frame deformable registration on one MI355X.
 
 One step = one frame of the hot path on the 640x480 / 250,000-point /
-1,600-node synthetic tissue problem: depth normal map, graph setup (kNN,
-skinning weights, node graph, lists), 10 Gauss-Newton iterations of 10 PCG
-iterations each.  Inputs are resident in HBM before timing starts.
+1,600-node synthetic tissue problem: graph setup (kNN, skinning weights, node
+graph, lists), depth normal map, 10 Gauss-Newton iterations of 10 PCG
+iterations each, and the fusion of the frame into the deformed model.  Inputs
+are resident in HBM before timing starts; each step first restores the model
+(points, normals, weights, stamps, node positions: about 9 MB of device
+copies) because fusion updates it in place.
 
 Prints one JSON line.  value = Gauss-Newton iterations per second over whole
 frames; ms_per_step = ms per frame.  A second, profiled region (HIP events
 around each phase, on the library's stream) gives the per-phase breakdown and
-the roofline of the dominant kernel.  The CPU baseline is the float64 oracle
-on a bounded sample of the same frame.
+the roofline of the dominant kernel.  The low-precision form (bf16 data-term
+normal matrix on the matrix cores, two float32 refinement passes) is timed on
+the same frame and reported beside it with its error against the oracle's
+emulation of that form.  The CPU baseline is the float64 oracle on a bounded
+sample of the same frame.
 """
 import argparse
 import json
@@ -85,20 +91,35 @@ def main():
     x0 = x.clone()
     state = {}
 
-    def frame():
-        g = M.build_graph(pts, nodes, params, ws)
+    pts0, nodes0 = pts.clone(), nodes.clone()
+    w = torch.zeros(n, dtype=torch.float32, device=dev)
+    stamp = torch.zeros(n, dtype=torch.int32, device=dev)
+    w0, stamp0 = w.clone(), stamp.clone()
+    fp = M.fuse_params(frame=1)
+
+    def frame(p=params):
+        pts.copy_(pts0)
+        nodes.copy_(nodes0)
+        w.copy_(w0)
+        stamp.copy_(stamp0)
         x.copy_(x0)
-        rep, _ = M.gn_register(pts, nodes, x, g, depth, cam, pose, params, ws)
-        state["graph"], state["rep"] = g, rep
+        g = M.build_graph(pts, nodes, p, ws)
+        rep, _ = M.gn_register(pts, nodes, x, g, depth, cam, pose, p, ws)
+        state["graph"], state["rep"], state["x"] = g, rep, x.clone()
+        nmap = M.normal_map(depth, cam)
+        M.fuse(pts, w, stamp, nodes, x, g, nmap, cam, pose, fp, ws)
+
+    def timed(p, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            frame(p)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
 
     for _ in range(max(1, args.warmup)):
         frame()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        frame()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed = timed(params, args.steps)
     ms_frame = 1000.0 * elapsed / args.steps
     gn_per_s = G * args.steps / elapsed
 
@@ -111,7 +132,7 @@ def main():
     lib.misslam_profile_enable(0)
     import ctypes
     phases = {}
-    for ph in ["normal_map", "build_graph", "point_pass", "assemble", "energy", "bjacobi", "pcg"]:
+    for ph in ["normal_map", "build_graph", "point_pass", "assemble", "energy", "bjacobi", "pcg", "fuse", "refine"]:
         ms = ctypes.c_double()
         cnt = ctypes.c_int64()
         _lib.check("misslam_profile_get", lib.misslam_profile_get(ph.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
@@ -131,17 +152,28 @@ def main():
                 "algorithmic_bytes_per_launch": int(abytes), "avg_launch_us": round(phases[dominant]["avg_us"], 2)}
 
     # accuracy against the stored float64 oracle result of the same frame
-    xg = x.cpu().numpy().astype(np.float64)
-    acc = {}
-    gold = os.path.join(ROOT, "tests", "golden", f"{args.config}_oracle.npz")
-    if os.path.exists(gold):
-        z = np.load(gold)
-        xo = z["x"]
-        xi = np.zeros_like(xo)
-        xi[:, [0, 4, 8]] = 1.0
-        acc["rel_err_params"] = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
-        acc["rel_err_params_delta"] = float(np.linalg.norm((xg - xi) - (xo - xi)) / np.linalg.norm(xo - xi))
-        acc["rel_err_e_data_final"] = float(abs(rep[-1]["e_data"] - z["e_data_final"]) / z["e_data_final"])
+    acc = accuracy(state, rep, os.path.join(ROOT, "tests", "golden", f"{args.config}_oracle.npz"))
+
+    # the low-precision form on the same frame: without refinement (the float64
+    # oracle's algorithm on a rounded data term) and with two refinement passes
+    lowp = {"form": "bf16 data-term J^T J on the matrix cores (fp32 accumulation); refine_steps fp32 "
+                    "matrix-free refinement passes per GN step"}
+    plain = os.path.join(ROOT, "tests", "golden", f"{args.config}_oracle.npz")
+    for steps in (0, 2):
+        lp = M.Params(sigma=sc["sigma"], gn_iters=sc["gn_iters"], pcg_iters=sc["pcg_iters"],
+                      precision=_lib.PREC_BF16, refine_steps=steps)
+        for _ in range(max(1, args.warmup)):
+            frame(lp)
+        lp_elapsed = timed(lp, args.steps)
+        lp_rep = M.read_report(state["rep"])
+        entry = {"refine_steps": steps, "ms_per_frame": round(1000.0 * lp_elapsed / args.steps, 4),
+                 "gn_iters_per_s": round(G * args.steps / lp_elapsed, 2),
+                 "accuracy_vs_fp64_oracle": accuracy(state, lp_rep, plain),
+                 "e_data_final": float(lp_rep[-1]["e_data"])}
+        emu = os.path.join(ROOT, "tests", "golden", f"{args.config}_bf16_r{steps}_oracle.npz")
+        if steps > 0:
+            entry["accuracy_vs_same_form_oracle"] = accuracy(state, lp_rep, emu)
+        lowp[f"bf16_r{steps}"] = entry
 
     out = {
         "metric": "GN iters/s + ms/frame at 640x480, 1600 ED nodes, rel err vs FP64 oracle",
@@ -157,7 +189,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {cam.width}x{cam.height} depth, {n} points, {m} nodes, k={params.k}, "
-                               f"{G} GN x {params.pcg_iters} PCG per frame; step = graph setup + registration",
+                               f"{G} GN x {params.pcg_iters} PCG per frame; step = graph setup + registration + fusion",
                    "nnzb": nnzb, "n_valid_mean": n_valid},
         "ms_per_frame": round(ms_frame, 4),
         "gn_iter_ms_profiled": round(gn_iter_ms, 4),
@@ -167,10 +199,25 @@ def main():
                          "e_reg": float(rep[-1]["e_reg"]), "n_valid": int(rep[-1]["n_valid"]),
                          "flags": int(rep[-1]["flags"])},
         "roofline": roofline,
+        "low_precision": lowp,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, params)
     print(json.dumps(out))
+
+
+def accuracy(state, rep, gold):
+    """Relative errors of the frame's parameters and final data energy against a stored oracle run."""
+    if not os.path.exists(gold):
+        return {}
+    xg = state["x"].cpu().numpy().astype(np.float64)
+    z = np.load(gold)
+    xo = z["x"]
+    xi = np.zeros_like(xo)
+    xi[:, [0, 4, 8]] = 1.0
+    return {"rel_err_params": float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)),
+            "rel_err_params_delta": float(np.linalg.norm((xg - xi) - (xo - xi)) / np.linalg.norm(xo - xi)),
+            "rel_err_e_data_final": float(abs(rep[-1]["e_data"] - z["e_data_final"]) / z["e_data_final"])}
 
 
 def cpu_baseline(sc, params):

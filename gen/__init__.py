@@ -2,4 +2,4 @@
 
 Only input manufacture lives here; see ``gen.scene``.
 """
-from .scene import SPECS, SceneSpec, make_scene, plane_scene  # noqa: F401
+from .scene import SPECS, SceneSpec, batch_spec, make_scene, plane_scene  # noqa: F401

@@ -248,6 +248,27 @@ def render_depth(spec, surface, field, R, T, rng, noise_sigma):
 # scene assembly
 
 
+def batch_spec(b, base_seed=500):
+    """Spec of problem b of the uneven batch: frame width from {320, ..., 640} (4:3,
+    fx = 0.4 W, so every problem sees the same 150 x 112.5 mm field at 60 mm), a
+    log-uniform point count in [20k, 300k] over the 125 x 80 mm patch and a
+    log-uniform node count in [100, 2000] on a grid of the patch's aspect; the
+    320x240 family otherwise (bumps, breathing, 10 x 10 iterations)."""
+    rng = np.random.Generator(np.random.PCG64(base_seed + b))
+    W = int(rng.choice([320, 384, 448, 512, 576, 640]))
+    H = 3 * W // 4
+    fx = 0.4 * W
+    n_pts = math.exp(rng.uniform(math.log(20000.0), math.log(300000.0)))
+    pitch = math.sqrt(10000.0 / n_pts)
+    pnx, pny = max(2, int(round(125.0 / pitch))), max(2, int(round(80.0 / pitch)))
+    m_nodes = math.exp(rng.uniform(math.log(100.0), math.log(2000.0)))
+    s = math.sqrt(10000.0 / m_nodes)
+    mx, my = max(2, int(round(125.0 / s))), max(2, int(round(80.0 / s)))
+    return SceneSpec(f"batch{b}", W, H, fx, fx, W / 2.0, H / 2.0, (-62.5, 62.5, -40.0, 40.0), (pnx, pny),
+                     min(0.05, 0.25 * pitch), (mx, my), s, "breathing", (2, 4), 5.0, 8.0, 0.2 * 60 / fx, 10, 10,
+                     base_seed + b)
+
+
 def make_scene(name, seed=None, noise_sigma=None, with_depth=True, deformation=None):
     """Build one synthetic registration problem.
 
@@ -261,7 +282,8 @@ def make_scene(name, seed=None, noise_sigma=None, with_depth=True, deformation=N
       gt_node_A, gt_node_t: the deformation's first-order expansion at each node
       sigma    Gaussian skinning width (= node spacing), gn_iters, pcg_iters
     """
-    spec = SPECS[name]
+    spec = name if isinstance(name, SceneSpec) else SPECS[name]
+    name = spec.name
     seed = spec.seed if seed is None else seed
     rng = np.random.Generator(np.random.PCG64(seed))
     bmin, bmax = spec.bumps

@@ -50,6 +50,7 @@ typedef enum {
 #define MISSLAM_FLAG_NONFINITE      0x4   /* NaN/Inf met in an energy or the update; x left unchanged */
 #define MISSLAM_FLAG_FRAME_REJECT   0x8   /* mean |r| above params.reject_threshold */
 #define MISSLAM_FLAG_GRAPH_OVERFLOW 0x10  /* a per-frame graph capacity was exceeded */
+#define MISSLAM_FLAG_SYNC_TIMEOUT   0x20  /* the persistent solve gave up waiting at a grid barrier; discard the step */
 
 #define MISSLAM_WEIGHT_GAUSS  0   /* w_j ~ exp(-|v-g_j|^2 / (2 sigma^2)), normalised over k */
 #define MISSLAM_WEIGHT_LINEAR 1   /* Eq.(2): w_j ~ max(0, 1 - |v-g_j| / d_(k+1)), normalised */
@@ -281,6 +282,60 @@ misslam_status misslam_energy_vjp(const misslam_points *points, const misslam_no
                                   const misslam_pose *pose, const misslam_params *params, const int32_t *corr_in,
                                   int32_t *corr_out, const float *grad_e, float *grad_params, float *grad_points,
                                   double *energy, misslam_report *rep, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ uneven batches */
+
+/*
+ * Many independent registration problems of different sizes (each its own
+ * frame, camera, pose, points, nodes and graph) registered together: every
+ * phase of the per-frame loop of misslam_gn_register (normal map, then per
+ * Gauss-Newton step the point pass, the row assembly, the energy report and
+ * the persistent PCG solve with its update) runs as ONE launch over all
+ * problems, and the whole frame is captured once into a hipGraph and
+ * replayed by every later call.  Each problem's arithmetic, partition and
+ * reduction order are those of misslam_gn_register with the same workgroup
+ * tile, so with rows_per_wg = 21 every result is bitwise that of calling
+ * misslam_gn_register once per problem; another tile changes only the
+ * rounding order of the PCG reductions.
+ *
+ * misslam_problem: host structs holding device pointers, copied at
+ *   creation; the pointed-to buffers (points, nodes and their params, graph,
+ *   depth) may change contents between calls but not address.  report: device,
+ *   params.gn_iters + 1 entries, filled as by misslam_gn_register.
+ * misslam_batch_create: count in [1, 1024]; every problem valid for
+ *   misslam_gn_register with params (float32 form, graph->k == params->k).
+ *   rows_per_wg: the node rows each solve workgroup owns, 1..21, or 0 to let
+ *   the first misslam_batch_register time the candidate tiles on the batch
+ *   itself and keep the fastest (the tuning runs restore every problem's
+ *   params, so results are as if only the final run happened).  Allocates
+ *   host and device bookkeeping (released by misslam_batch_destroy).
+ * misslam_batch_workspace_bytes: the caller-owned device workspace one call needs.
+ * misslam_batch_register: runs the frame of every problem on stream; the
+ *   first call (and a call with another workspace or stream) uploads the
+ *   descriptors, tunes if asked and captures the graph, synchronising the
+ *   stream; later calls only launch the graph and allocate nothing.  Errors
+ *   as misslam_gn_register; MISSLAM_EUNSUPPORTED if the solves of the batch
+ *   cannot all be resident at once with any tile.
+ * misslam_batch_tile: the rows per workgroup in use (0 before the first call).
+ */
+typedef struct {
+    misslam_points points;
+    misslam_nodes nodes;
+    misslam_graph graph;
+    const float *depth;
+    misslam_camera camera;
+    misslam_pose pose;
+    misslam_report *report;
+} misslam_problem;
+
+typedef struct misslam_batch misslam_batch;
+
+misslam_status misslam_batch_create(const misslam_problem *problems, int32_t count, const misslam_params *params,
+                                    int32_t rows_per_wg, misslam_batch **out);
+size_t misslam_batch_workspace_bytes(const misslam_batch *batch);
+misslam_status misslam_batch_register(misslam_batch *batch, void *ws, size_t ws_bytes, void *stream);
+int32_t misslam_batch_tile(const misslam_batch *batch);
+void misslam_batch_destroy(misslam_batch *batch);
 
 /* ------------------------------------------------------------------ profiling */
 

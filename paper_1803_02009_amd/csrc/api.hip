@@ -70,13 +70,13 @@ struct Timed {
         if (!p.on) return;
         a = p.get_event();
         b = p.get_event();
-        if (a && b) hipEventRecord(a, st);
+        if (a && b) (void)hipEventRecord(a, st);
     }
     ~Timed() {
         if (!a || !b) return;
         Profiler &p = prof();
         std::lock_guard<std::mutex> lk(p.mu);
-        hipEventRecord(b, st);
+        (void)hipEventRecord(b, st);
         p.pending.push_back({a, b, phase});
     }
 };
@@ -146,6 +146,7 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
     L.pcg.q = c.take<float>((size_t)12 * m);
     L.pcg.part = c.take<double>((size_t)(pcg_iters + 2) * 4 * nblk_max);
     L.pcg.status = c.take<int32_t>((size_t)2 * (pcg_iters + 2));
+    L.pcg.bar = c.take<unsigned>(64);
     L.pcg.nblk = nblk;
     L.pcg.nblk_max = nblk_max;
     L.graph.tmp = c.take<int32_t>((size_t)m * MISSLAM_MAX_ROW);
@@ -159,6 +160,11 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
     L.rhs = c.take<float>((size_t)12 * m);
     L.delta2 = c.take<float>((size_t)12 * m);
     L.graph.cnt = c.take<int32_t>((size_t)2 * m + 8);
+    L.graph.grid.hdr = c.take<double>(4);
+    L.graph.grid.dims = c.take<int32_t>(4);
+    L.graph.grid.start = c.take<int32_t>((size_t)msl::MSL_GRID_CELLS + 1);
+    L.graph.grid.cursor = c.take<int32_t>((size_t)msl::MSL_GRID_CELLS);
+    L.graph.grid.nodes = c.take<float4>((size_t)m);
     L.bytes = align_up(c.off);
     return L;
 }
@@ -284,7 +290,7 @@ misslam_status misslam_warp(const misslam_points *points, const misslam_nodes *n
 }
 
 static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, int64_t n, int m,
-                            misslam_report *rep, float reject, hipStream_t st) {
+                            misslam_report *rep, float reject, hipStream_t st, unsigned *zero_words = nullptr) {
     hipError_t e;
     {
         Timed t(PH_POINT_PASS, st);
@@ -296,8 +302,22 @@ static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, i
     }
     if (e == hipSuccess) {
         Timed t(PH_ENERGY, st);
-        e = msl::launch_energy_report(s, n, m, rep, reject, st);
+        e = msl::launch_energy_report(s, n, m, rep, reject, st, zero_words);
     }
+    return e;
+}
+
+// The one-launch persistent solve where the device holds its grid, else the
+// multi-kernel recurrence: the same arithmetic, with reductions added in a
+// different (but in each path fixed) order, so the two agree to rounding.
+static hipError_t solve_persistent(const msl::GraphView &g, int m, const float *blocks, const float *gvec,
+                                   const float *minv, float lambda, int iters, float *delta, const msl::PcgScratch &s,
+                                   misslam_report *rep, float *params, hipStream_t st, bool bar_zeroed = false) {
+    bool used = false;
+    hipError_t e =
+        msl::launch_pcg_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st, &used, bar_zeroed);
+    if (e == hipSuccess && !used)
+        e = msl::launch_pcg_update(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st);
     return e;
 }
 
@@ -311,20 +331,11 @@ static hipError_t solve(const msl::GraphView &g, int m, const float *blocks, con
     }
     if (e == hipSuccess) {
         Timed t(PH_PCG, st);
-        e = msl::launch_pcg_update(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st);
+        e = solve_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st);
     }
     return e;
 }
 
-static hipError_t solve_persistent(const msl::GraphView &g, int m, const float *blocks, const float *gvec,
-                                   const float *minv, float lambda, int iters, float *delta, const msl::PcgScratch &s,
-                                   misslam_report *rep, float *params, hipStream_t st) {
-    bool used = false;
-    hipError_t e = msl::launch_pcg_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st, &used);
-    if (e == hipSuccess && !used)
-        e = msl::launch_pcg_update(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st);
-    return e;
-}
 
 static msl::StepArgs step_args(const misslam_points *points, const misslam_nodes *nodes, const misslam_graph *graph,
                                const float4 *nmap, const misslam_camera *camera, const misslam_pose *pose,
@@ -432,11 +443,11 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
             break;
         }
         if (!lowp) {
-            e = linearize(a, L.step, n, m, rep + it, params->reject_threshold, st);
+            e = linearize(a, L.step, n, m, rep + it, params->reject_threshold, st, L.pcg.bar);
             if (e == hipSuccess) {
                 Timed t(PH_PCG, st);
                 e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
-                                     L.delta, L.pcg, rep + it, nodes->params, st);
+                                     L.delta, L.pcg, rep + it, nodes->params, st, true);
             }
             continue;
         }
@@ -576,6 +587,283 @@ void misslam_profile_reset(void) {
         p.total_ms[i] = 0.0;
         p.launches[i] = 0;
     }
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ uneven batches
+
+struct misslam_batch {
+    std::vector<misslam_problem> probs;
+    misslam_params params;
+    int count = 0;
+    int req_rows = 0;          // 0: tune on the first call
+    int rows = 0;              // tile in use
+    msl::BatchItem *d_items = nullptr;
+    float *d_backup = nullptr; // params of every problem (tuning restores them)
+    std::vector<size_t> param_off;
+    std::vector<msl::BatchItem> items;
+    void *items_ws = nullptr;  // workspace the items were carved from
+    int items_rows = 0;
+    int64_t total_pp = 0;
+    int total_nm = 0, total_rows = 0, total_ne = 0, total_wgs = 0;
+    unsigned *bar = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *exec_ws = nullptr;
+    hipStream_t exec_stream = nullptr;
+    int exec_rows = 0;
+};
+
+namespace {
+
+size_t batch_bytes(const misslam_batch *b) {
+    size_t off = align_up(64 * sizeof(unsigned));
+    for (const auto &p : b->probs)
+        off += align_up(carve(nullptr, p.points.n, p.nodes.m, p.camera.width, p.camera.height, b->params.pcg_iters).bytes);
+    return off;
+}
+
+// Host descriptors of every problem for workspace ws and tile rows.
+void batch_items(misslam_batch *b, void *ws, int rows) {
+    char *base = static_cast<char *>(ws);
+    b->bar = reinterpret_cast<unsigned *>(base);
+    size_t off = align_up(64 * sizeof(unsigned));
+    b->items.assign(b->count, msl::BatchItem{});
+    int64_t pp = 0;
+    int nm = 0, row = 0, ne = 0, wg = 0;
+    const int G = b->params.gn_iters;
+    for (int i = 0; i < b->count; ++i) {
+        const misslam_problem &p = b->probs[i];
+        const Layout L = carve(base + off, p.points.n, p.nodes.m, p.camera.width, p.camera.height,
+                               b->params.pcg_iters);
+        off += align_up(L.bytes);
+        msl::BatchItem &it = b->items[i];
+        it.a = step_args(&p.points, &p.nodes, &p.graph, L.nmap, &p.camera, &p.pose, &b->params, L.blocks, L.gvec,
+                         nullptr);
+        it.a.minv = L.step.minv;
+        it.s = L.step;
+        const int m = p.nodes.m;
+        const int wgs = (m + rows - 1) / rows;
+        msl::PcgArgs &A = it.p;
+        A.row_ptr = p.graph.row_ptr;
+        A.col_idx = p.graph.col_idx;
+        A.blocks = L.blocks;
+        A.minv = L.step.minv;
+        A.g = L.gvec;
+        A.lambda = b->params.lambda;
+        A.m = m;
+        A.nblk = wgs;
+        A.iters = b->params.pcg_iters;
+        A.cap = p.graph.bsr_cap;
+        A.x = L.delta;
+        A.r = L.pcg.r;
+        A.z = L.pcg.z;
+        A.p = L.pcg.p;
+        A.q = L.pcg.q;
+        A.part = L.pcg.part;
+        A.status = L.pcg.status;
+        A.done = L.pcg.status + (b->params.pcg_iters + 2);
+        it.rep = p.report;
+        it.params = p.nodes.params;
+        it.depth = p.depth;
+        it.reject = b->params.reject_threshold;
+        const int64_t n = p.points.n;
+        it.npb = (int)((n > 0 ? n + 255 : 256) / 256);
+        it.pp0 = pp;
+        pp += (n + 255) / 256;
+        it.nm0 = nm;
+        nm += (int)(((int64_t)p.camera.width * p.camera.height + 255) / 256);
+        it.row0 = row;
+        row += m;
+        it.ne0 = ne;
+        ne += (m + 255) / 256;
+        it.wg0 = wg;
+        it.wgs = wgs;
+        wg += wgs;
+        (void)G;
+    }
+    b->total_pp = pp;
+    b->total_nm = nm;
+    b->total_rows = row;
+    b->total_ne = ne;
+    b->total_wgs = wg;
+}
+
+// The frame of every problem, enqueued on st (eagerly or under capture).
+hipError_t batch_enqueue(misslam_batch *b, hipStream_t st, bool cooperative) {
+    const int G = b->params.gn_iters;
+    const int count = b->count, k = b->params.k;
+    const msl::BatchItem *d = b->d_items;
+    hipError_t e = msl::launch_report_init_batched(d, count, G + 1, st);
+    if (e == hipSuccess) e = msl::launch_normal_map_batched(d, count, b->total_nm, st);
+    for (int it = 0; it < G && e == hipSuccess; ++it) {
+        e = msl::launch_point_pass_batched(d, count, k, b->total_pp, it, st);
+        if (e == hipSuccess) e = msl::launch_assemble_batched(d, count, k, b->total_rows, it, st);
+        if (e == hipSuccess) e = msl::launch_energy_report_batched(d, count, it, b->bar, st);
+        bool used = false;
+        if (e == hipSuccess)
+            e = msl::launch_pcg_batched(d, count, b->rows, b->total_wgs, it, b->bar, cooperative, st, &used);
+        if (e == hipSuccess && !used) return hipErrorInvalidConfiguration;
+    }
+    if (e == hipSuccess) e = msl::launch_point_pass_batched(d, count, k, b->total_pp, G, st);
+    if (e == hipSuccess) e = msl::launch_node_energy_batched(d, count, b->total_ne, st);
+    if (e == hipSuccess) e = msl::launch_energy_report_batched(d, count, G, nullptr, st);
+    return e;
+}
+
+hipError_t batch_upload(misslam_batch *b, void *ws, int rows) {
+    batch_items(b, ws, rows);
+    b->items_ws = ws;
+    b->items_rows = rows;
+    return hipMemcpy(b->d_items, b->items.data(), sizeof(msl::BatchItem) * b->count, hipMemcpyHostToDevice);
+}
+
+hipError_t batch_save_params(misslam_batch *b, hipStream_t st, bool restore) {
+    for (int i = 0; i < b->count; ++i) {
+        const misslam_problem &p = b->probs[i];
+        const size_t bytes = sizeof(float) * 12 * (size_t)p.nodes.m;
+        float *dev = b->d_backup + b->param_off[i];
+        const hipError_t e = restore ? hipMemcpyAsync(p.nodes.params, dev, bytes, hipMemcpyDeviceToDevice, st)
+                                     : hipMemcpyAsync(dev, p.nodes.params, bytes, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Times one eager frame with tile rows (params restored afterwards); < 0 if the tile does not fit.
+float batch_try(misslam_batch *b, void *ws, int rows, hipStream_t st) {
+    int wgs = 0;
+    for (const auto &p : b->probs) wgs += (p.nodes.m + rows - 1) / rows;
+    if (!msl::pcg_batched_fits(wgs)) return -1.f;
+    if (batch_upload(b, ws, rows) != hipSuccess) return -1.f;
+    b->rows = rows;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float ms = -1.f;
+    if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+        bool ok = batch_enqueue(b, st, true) == hipSuccess;   // warm
+        ok = ok && batch_save_params(b, st, true) == hipSuccess;
+        ok = ok && hipEventRecord(e0, st) == hipSuccess;
+        ok = ok && batch_enqueue(b, st, true) == hipSuccess;
+        ok = ok && hipEventRecord(e1, st) == hipSuccess;
+        ok = ok && batch_save_params(b, st, true) == hipSuccess;
+        ok = ok && hipStreamSynchronize(st) == hipSuccess;
+        if (ok && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = -1.f;
+        if (!ok) ms = -1.f;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+misslam_status misslam_batch_create(const misslam_problem *problems, int32_t count, const misslam_params *params,
+                                    int32_t rows_per_wg, misslam_batch **out) {
+    if (!problems || count < 1 || count > 1024 || !valid_params(params) || !out || rows_per_wg < 0 ||
+        rows_per_wg > 21)
+        return MISSLAM_EINVAL;
+    if (params->precision != MISSLAM_PREC_FP32) return MISSLAM_EUNSUPPORTED;
+    for (int i = 0; i < count; ++i) {
+        const misslam_problem &p = problems[i];
+        if (!valid_points(&p.points) || !valid_nodes(&p.nodes) || !valid_graph(&p.graph, p.points.n) || !p.depth ||
+            !valid_camera(&p.camera) || !p.report)
+            return MISSLAM_EINVAL;
+        if (p.graph.k != params->k) return MISSLAM_ESHAPE;
+        if ((int64_t)p.graph.bsr_cap > (int64_t)p.nodes.m * MISSLAM_MAX_ROW) return MISSLAM_ECAPACITY;
+    }
+    misslam_batch *b = new misslam_batch();
+    b->probs.assign(problems, problems + count);
+    b->params = *params;
+    b->count = count;
+    b->req_rows = rows_per_wg;
+    size_t poff = 0;
+    for (int i = 0; i < count; ++i) {
+        b->param_off.push_back(poff);
+        poff += 12 * (size_t)problems[i].nodes.m;
+    }
+    hipError_t e = hipMalloc(&b->d_items, sizeof(msl::BatchItem) * count);
+    if (e == hipSuccess) e = hipMalloc(&b->d_backup, sizeof(float) * (poff > 0 ? poff : 1));
+    if (e != hipSuccess) {
+        misslam_batch_destroy(b);
+        return hip_fail(e);
+    }
+    *out = b;
+    return MISSLAM_OK;
+}
+
+size_t misslam_batch_workspace_bytes(const misslam_batch *batch) { return batch ? batch_bytes(batch) : 0; }
+
+int32_t misslam_batch_tile(const misslam_batch *batch) { return batch ? batch->rows : 0; }
+
+misslam_status misslam_batch_register(misslam_batch *b, void *ws, size_t ws_bytes, void *stream) {
+    if (!b || !ws) return MISSLAM_EINVAL;
+    if (ws_bytes < batch_bytes(b)) return MISSLAM_EWORKSPACE;
+    const hipStream_t st = stream_of(stream);
+    hipError_t e = hipSuccess;
+    if (b->rows == 0) {
+        if (b->req_rows > 0) {
+            int wgs = 0;
+            for (const auto &p : b->probs) wgs += (p.nodes.m + b->req_rows - 1) / b->req_rows;
+            if (!msl::pcg_batched_fits(wgs)) return MISSLAM_EUNSUPPORTED;
+            b->rows = b->req_rows;
+        } else {
+            // the tile: rows per solve workgroup, timed on this batch
+            e = batch_save_params(b, st, false);
+            float best = -1.f;
+            int best_rows = 0;
+            const int cand[4] = {21, 14, 10, 7};
+            for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+                const float ms = batch_try(b, ws, cand[c], st);
+                if (ms > 0.f && (best < 0.f || ms < best)) {
+                    best = ms;
+                    best_rows = cand[c];
+                }
+            }
+            if (e != hipSuccess) return hip_fail(e);
+            if (best_rows == 0) return MISSLAM_EUNSUPPORTED;
+            b->rows = best_rows;
+        }
+    }
+    if (b->items_ws != ws || b->items_rows != b->rows) {
+        e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = batch_upload(b, ws, b->rows);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    if (!b->exec || b->exec_ws != ws || b->exec_stream != st || b->exec_rows != b->rows) {
+        if (b->exec) {
+            (void)hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        hipError_t ee = hipSuccess;
+        if (e == hipSuccess) {
+            ee = batch_enqueue(b, st, false);
+            e = hipStreamEndCapture(st, &g);
+        }
+        if (ee != hipSuccess) e = ee;
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            b->exec = nullptr;
+            return e == hipErrorInvalidConfiguration ? MISSLAM_EUNSUPPORTED : hip_fail(e);
+        }
+        b->exec_ws = ws;
+        b->exec_stream = st;
+        b->exec_rows = b->rows;
+    }
+    e = hipGraphLaunch(b->exec, st);
+    return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
+}
+
+void misslam_batch_destroy(misslam_batch *b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_backup) (void)hipFree(b->d_backup);
+    delete b;
 }
 
 }  // extern "C"

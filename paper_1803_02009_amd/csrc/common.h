@@ -94,6 +94,28 @@ __device__ __forceinline__ void ed_blend_normal(float nx, float ny, float nz, co
     }
 }
 
+// c . c - 1 for column a of A (c = (x[3a], x[3a+1], x[3a+2]), diagonal entry
+// c[a]) without the cancellation of forming c . c near 1: (c[a] - 1) is exact
+// for c[a] in [0.5, 2] and (c[a] - 1)(c[a] + 1) + the other squares keeps the
+// residual's own relative precision (Eq.(5), its norm terms).
+__device__ __forceinline__ float unit_residual(const float *c, int a) {
+    const float d = c[a] - 1.f;
+    const float o1 = c[(a + 1) % 3], o2 = c[(a + 2) % 3];
+    return fmaf(d, c[a] + 1.f, fmaf(o2, o2, o1 * o1));
+}
+
+// Eq.(6) residual of the edge j -> l, A_j (g_l - g_j) + g_j + t_j - (g_l + t_l),
+// evaluated as (A_j - I) e + (t_j - t_l) with e = g_l - g_j: the node
+// positions cancel exactly instead of in float32 sums of millimetre-scale
+// coordinates, so the residual keeps its own relative precision.
+__device__ __forceinline__ void reg_residual(const float *xj, const float *xl, float ex, float ey, float ez, float &r0,
+                                             float &r1, float &r2) {
+    const float d0 = xj[0] - 1.f, d4 = xj[4] - 1.f, d8 = xj[8] - 1.f;   // diagonal of A_j - I, exact
+    r0 = fmaf(xj[6], ez, fmaf(xj[3], ey, d0 * ex)) + (xj[9] - xl[9]);
+    r1 = fmaf(xj[7], ez, fmaf(d4, ey, xj[1] * ex)) + (xj[10] - xl[10]);
+    r2 = fmaf(d8, ez, fmaf(xj[5], ey, xj[2] * ex)) + (xj[11] - xl[11]);
+}
+
 __device__ __forceinline__ void apply_pose(const Pose &P, float &x, float &y, float &z) {
     const float X = x, Y = y, Z = z;
     x = fmaf(P.R[2], Z, fmaf(P.R[1], Y, P.R[0] * X)) + P.T[0];
@@ -251,6 +273,52 @@ __device__ __forceinline__ bool chol_inverse_wave(double (*A)[12], double (*Li)[
         for (int q = i > k ? i : k; q < 12; ++q) s += Li[q][i] * Li[q][k];
         out[t] = bad ? (i == k ? 1.f : 0.f) : (float)s;
     }
+    return !bad;
+}
+
+// out = A^-1 (float32) for one SPD 12x12 block held in LDS as float64, by a
+// whole workgroup of NT threads: Gauss-Jordan elimination on the diagonal
+// pivots, each step reading row k and column k, then every thread rewriting
+// its own entries.  Without pivoting the k-th pivot is the Schur complement
+// d_k = det(A_1..k) / det(A_1..k-1), positive for every k exactly when A is
+// SPD; a non-positive pivot marks the block non-SPD and the identity is
+// written instead.  A is overwritten.  Every thread must call this.
+template <int NT>
+__device__ __forceinline__ bool gj_inverse_block(double (*A)[12], float *out) {
+    constexpr int E = (144 + NT - 1) / NT;   // entries per thread
+    const int tid = threadIdx.x;
+    bool bad = false;
+    for (int k = 0; k < 12; ++k) {
+        const double p = A[k][k];
+        double ark[E], akc[E], own[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int t = tid + e * NT;
+            if (t < 144) {
+                ark[e] = A[t / 12][k];
+                akc[e] = A[k][t % 12];
+                own[e] = A[t / 12][t % 12];
+            }
+        }
+        __syncthreads();
+        bad = bad || !(p > 0.0);
+        const double ip = p > 0.0 ? 1.0 / p : 1.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int t = tid + e * NT;
+            if (t < 144) {
+                const int R = t / 12, C = t % 12;
+                double v;
+                if (R == k && C == k) v = ip;
+                else if (R == k) v = akc[e] * ip;
+                else if (C == k) v = -ark[e] * ip;
+                else v = own[e] - ark[e] * (akc[e] * ip);
+                A[R][C] = v;
+            }
+        }
+        __syncthreads();
+    }
+    for (int t = tid; t < 144; t += NT) out[t] = bad ? (t / 12 == t % 12 ? 1.f : 0.f) : (float)A[t / 12][t % 12];
     return !bad;
 }
 

@@ -14,9 +14,20 @@ struct GraphView {
     int32_t *info;
 };
 
+// Uniform grid of the nodes for the kNN search.
+constexpr int MSL_GRID_CELLS = 1 << 18;
+struct GridView {
+    double *hdr;      // origin x, y, z, cell width
+    int32_t *dims;    // cells per axis (0: no nodes)
+    int32_t *start;   // MSL_GRID_CELLS + 1 cell offsets into nodes
+    int32_t *cursor;  // MSL_GRID_CELLS fill cursors
+    float4 *nodes;    // m: x, y, z, index bits, in cell order
+};
+
 struct GraphScratch {
     int32_t *tmp;     // m x MISSLAM_MAX_ROW row columns
     int32_t *cnt;     // 2m + 8
+    GridView grid;
 };
 
 // Per-iteration scratch of the registration step.
@@ -35,6 +46,7 @@ struct PcgScratch {
     int32_t *status;       // 2 x (pcg_iters + 2): stop status, then per-iteration "updated" flags
     int nblk;              // workgroups of the multi-kernel path
     int nblk_max;          // partial slots per reduction (>= every path's workgroup count)
+    unsigned *bar;         // 64 words: grid barrier of the persistent solve
 };
 
 hipError_t launch_normal_map(const float *depth, const Cam &cam, float4 *out, hipStream_t st);
@@ -58,6 +70,36 @@ struct StepArgs {
     const int32_t *corr_in;  // optional frozen correspondences (no association, no gates)
     float *minv;       // optional m x 144 block-Jacobi inverses computed with the assembly
     int32_t *flags;    // report flags (NONSPD_BLOCK) when minv is set
+};
+
+struct PcgArgs {
+    const int32_t *row_ptr, *col_idx;
+    const float *blocks, *minv, *g;
+    float lambda;
+    int m, nblk, iters, cap;
+    float *x, *r, *z, *p, *q;
+    double *part;     // [(it * 4 + kind) * nblk + block], kind 0 = r.z, 1 = r.r, 2 = p.q, 3 = #non-finite x
+    int32_t *status;  // [it]: 0 running, 2 stopped by breakdown (propagates)
+    int32_t *done;    // [it]: 1 if iteration it updated x
+};
+
+// One registration problem of a batch solved side by side: its step and
+// solve arguments (carved from its own slice of the batch workspace) and
+// where its blocks start in each batched launch.
+struct BatchItem {
+    StepArgs a;          // minv set; flags come from rep[it]
+    StepScratch s;
+    PcgArgs p;
+    misslam_report *rep; // gn_iters + 1 entries
+    float *params;       // m x 12, updated in place
+    const float *depth;
+    float reject;
+    int64_t pp0;         // first point-pass block
+    int npb;             // point-pass blocks
+    int nm0;             // first normal-map block
+    int row0;            // first assembly workgroup
+    int ne0;             // first node-energy block
+    int wg0, wgs;        // persistent-solve workgroups
 };
 
 struct FuseArgs {
@@ -97,8 +139,9 @@ hipError_t launch_vjp_points(const StepArgs &a, const StepScratch &s, float sigm
 hipError_t launch_grad_params(const float *g, int m, const float *grad_e, float *out, hipStream_t st);
 hipError_t launch_energy_total(const misslam_report *rep, float w_data, float w_rot, float w_reg, double *out,
                                hipStream_t st);
+// zero_words (optional): 64 words cleared on the way (the persistent solve's barrier)
 hipError_t launch_energy_report(const StepScratch &s, int64_t n, int m, misslam_report *rep, float reject_thr,
-                                hipStream_t st);
+                                hipStream_t st, unsigned *zero_words = nullptr);
 hipError_t launch_bjacobi(const GraphView &g, int m, const float *blocks, float lambda, float *minv,
                           int32_t *flags, hipStream_t st);
 // PCG solve into delta; when params != nullptr also applies params += delta (the GN update).
@@ -110,8 +153,25 @@ hipError_t launch_report_init(misslam_report *rep, int count, hipStream_t st);
 // the device cannot co-schedule it (nothing launched, caller falls back).
 hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                                  float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
-                                 float *params, hipStream_t st, bool *used);
+                                 float *params, hipStream_t st, bool *used,
+                                 bool bar_zeroed = false);
 int pcg_blocks(int m);
+// Batched launches: one grid covers every problem of items[0..count).
+hipError_t launch_normal_map_batched(const BatchItem *items, int count, int total_blocks, hipStream_t st);
+hipError_t launch_point_pass_batched(const BatchItem *items, int count, int k, int64_t total_blocks, int it,
+                                     hipStream_t st);
+hipError_t launch_assemble_batched(const BatchItem *items, int count, int k, int total_rows, int it, hipStream_t st);
+hipError_t launch_energy_report_batched(const BatchItem *items, int count, int it, unsigned *zero_words,
+                                        hipStream_t st);
+hipError_t launch_node_energy_batched(const BatchItem *items, int count, int total_blocks, hipStream_t st);
+hipError_t launch_report_init_batched(const BatchItem *items, int count, int per_problem, hipStream_t st);
+// Side-by-side persistent solves: cooperative (co-residency checked by the
+// runtime) unless capture is set, where the grid is checked against the
+// occupancy instead.  *used = false: the shape does not fit; nothing launched.
+hipError_t launch_pcg_batched(const BatchItem *items, int count, int rows_per_wg, int total_wgs, int it,
+                              unsigned *bar, bool cooperative, hipStream_t st, bool *used);
+int pcg_batched_fits(int total_wgs);
+
 hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t st);
 
 }  // namespace msl

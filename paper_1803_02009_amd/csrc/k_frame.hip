@@ -12,9 +12,9 @@ namespace msl {
 
 // One thread per pixel.  V(u,v) = D ((u-cx)/fx, (v-cy)/fy, 1); N = normalize(b x a)
 // with a = V(u+1,v) - V(u-1,v), b = V(u,v+1) - V(u,v-1); float64, rounded at the end.
-__global__ void __launch_bounds__(256) normal_map_kernel(const float *__restrict__ depth, Cam cam,
-                                                         float4 *__restrict__ out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void normal_map_body(const float *__restrict__ depth, const Cam &cam,
+                                                float4 *__restrict__ out, int64_t blk) {
+    const int64_t t = blk * 256 + threadIdx.x;
     const int64_t npx = (int64_t)cam.W * cam.H;
     if (t >= npx) return;
     const int u = (int)(t % cam.W), v = (int)(t / cam.W);
@@ -50,22 +50,173 @@ __global__ void __launch_bounds__(256) normal_map_kernel(const float *__restrict
     out[t] = res;
 }
 
+__global__ void __launch_bounds__(256) normal_map_kernel(const float *__restrict__ depth, Cam cam,
+                                                         float4 *__restrict__ out) {
+    normal_map_body(depth, cam, out, blockIdx.x);
+}
+
+// The normal maps of a batch of problems in one grid.
+__global__ void __launch_bounds__(256) normal_map_batched_kernel(const BatchItem *__restrict__ items, int count) {
+    int b = count - 1;
+    while (b > 0 && items[b].nm0 > (int)blockIdx.x) --b;
+    const BatchItem &it = items[b];
+    normal_map_body(it.depth, it.a.cam, const_cast<float4 *>(it.a.nmap), (int64_t)blockIdx.x - it.nm0);
+}
+
 // ---------------------------------------------------------------- kNN + skinning weights (Eq.(2))
 
 constexpr int kKnnBlock = 256;
-constexpr int kNodeTile = 2048;
+constexpr int kGridThreads = 1024;
 
-// One thread per point; node coordinates staged through LDS in tiles.  Keeps
-// the k+1 smallest (d^2, index) pairs, d^2 = ((dx dx + dy dy) + dz dz) in float64.
+// Uniform grid over the node bounding box: header, cell offsets (counting
+// sort) and the nodes in cell order as (x, y, z, index bits).  Cell width
+// h = 2 sqrt(A / m), A the product of the two largest box extents (about
+// twice the node spacing of a surface-sampled graph), widened until the
+// cell count fits MSL_GRID_CELLS.  The width only affects speed: the search
+// below is exact for any h.  One workgroup.
+__global__ void __launch_bounds__(kGridThreads) node_grid_kernel(NodesView nd, GridView gv) {
+    __shared__ float red[6][kGridThreads];
+    __shared__ int part[kGridThreads];
+    const int m = nd.m, tid = threadIdx.x;
+    float lo[3] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf()};
+    float hi[3] = {-__builtin_huge_valf(), -__builtin_huge_valf(), -__builtin_huge_valf()};
+    for (int t = tid; t < m; t += kGridThreads) {
+        const float c[3] = {nd.gx[t], nd.gy[t], nd.gz[t]};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], c[a]);
+            hi[a] = fmaxf(hi[a], c[a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        red[a][tid] = lo[a];
+        red[3 + a][tid] = hi[a];
+    }
+    __syncthreads();
+    for (int off = kGridThreads / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                red[a][tid] = fminf(red[a][tid], red[a][tid + off]);
+                red[3 + a][tid] = fmaxf(red[3 + a][tid], red[3 + a][tid + off]);
+            }
+        }
+        __syncthreads();
+    }
+    // header (identical in every thread)
+    double org[3], ext[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        org[a] = m > 0 ? (double)red[a][0] : 0.0;
+        ext[a] = m > 0 ? (double)red[3 + a][0] - org[a] : 0.0;
+        if (!(ext[a] >= 0.0) || !isfinite(ext[a])) ext[a] = 0.0;   // non-finite nodes: one cell on that axis
+    }
+    double e0 = fmax(ext[0], fmax(ext[1], ext[2]));
+    double e2 = fmin(ext[0], fmin(ext[1], ext[2]));
+    double e1 = ext[0] + ext[1] + ext[2] - e0 - e2;
+    double h = 2.0 * sqrt(fmax(e0 * e1, 1e-12) / (double)(m > 0 ? m : 1));
+    if (!(h > 0.0) || !isfinite(h)) h = 1.0;
+    int dim[3];
+    for (int guard = 0; guard < 200; ++guard) {
+        int64_t tot = 1;
+        for (int a = 0; a < 3; ++a) {
+            const double q = floor(ext[a] / h) + 1.0;
+            dim[a] = q < 1e6 ? (int)q : 1000000;
+            tot *= dim[a];
+        }
+        if (tot <= MSL_GRID_CELLS) break;
+        h *= 1.25;
+    }
+    const int ncell = m > 0 ? dim[0] * dim[1] * dim[2] : 0;
+    if (tid == 0) {
+        gv.hdr[0] = org[0];
+        gv.hdr[1] = org[1];
+        gv.hdr[2] = org[2];
+        gv.hdr[3] = h;
+        gv.dims[0] = m > 0 ? dim[0] : 0;
+        gv.dims[1] = m > 0 ? dim[1] : 0;
+        gv.dims[2] = m > 0 ? dim[2] : 0;
+    }
+    // counting sort of the nodes by cell
+    for (int c = tid; c <= ncell; c += kGridThreads) gv.start[c] = 0;
+    __syncthreads();
+    const double ih = 1.0 / h;
+    auto cell_of = [&](int t) {
+        const double c[3] = {(double)nd.gx[t], (double)nd.gy[t], (double)nd.gz[t]};
+        int q[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double f = floor((c[a] - org[a]) * ih);
+            q[a] = f >= 0.0 ? (f < (double)(dim[a] - 1) ? (int)f : dim[a] - 1) : 0;   // NaN -> 0
+        }
+        return (q[2] * dim[1] + q[1]) * dim[0] + q[0];
+    };
+    for (int t = tid; t < m; t += kGridThreads) atomicAdd(&gv.start[cell_of(t)], 1);
+    __syncthreads();
+    // exclusive scan of ncell counts: each thread a contiguous chunk
+    const int chunk = (ncell + kGridThreads - 1) / kGridThreads;
+    const int c0 = min(ncell, tid * chunk), c1 = min(ncell, c0 + chunk);
+    int sum = 0;
+    // counts were formed by atomics in the L2: read them from there
+    for (int c = c0; c < c1; ++c) sum += __hip_atomic_load(&gv.start[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < kGridThreads; off <<= 1) {
+        const int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = tid == 0 ? 0 : part[tid - 1];
+    for (int c = c0; c < c1; ++c) {
+        const int v = __hip_atomic_load(&gv.start[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        gv.start[c] = run;
+        gv.cursor[c] = run;
+        run += v;
+    }
+    if (tid == 0) gv.start[ncell] = m;
+    __syncthreads();
+    for (int t = tid; t < m; t += kGridThreads) {
+        const int pos = atomicAdd(&gv.cursor[cell_of(t)], 1);
+        gv.nodes[pos] = make_float4(nd.gx[t], nd.gy[t], nd.gz[t], __int_as_float(t));
+    }
+}
+
+// Keeps the KK smallest (d^2, index) pairs in lexicographic order (equal
+// distances: lower index first), so the result does not depend on the order
+// in which candidates arrive.
+template <int KK>
+__device__ __forceinline__ void knn_insert(double (&bd)[KK], int (&bi)[KK], double d2, int idx) {
+    if (!(d2 < bd[KK - 1] || (d2 == bd[KK - 1] && (unsigned)idx < (unsigned)bi[KK - 1]))) return;
+    double cd = d2;
+    int ci = idx;
+#pragma unroll
+    for (int s = 0; s < KK; ++s) {
+        if (cd < bd[s] || (cd == bd[s] && (unsigned)ci < (unsigned)bi[s])) {
+            const double td = bd[s];
+            const int ti = bi[s];
+            bd[s] = cd;
+            bi[s] = ci;
+            cd = td;
+            ci = ti;
+        }
+    }
+}
+
+// One thread per point.  d^2 = ((dx dx + dy dy) + dz dz) in float64 against
+// the nodes of the point's grid cell, then of the shells of cells at
+// Chebyshev cell distance r = 1, 2, ...  Every node outside the cells seen
+// lies farther than r h from the point, so the search stops once the
+// (k+1)-th best d^2 is below (r h)^2 (with a margin for the rounding of the
+// cell index) or the cube covers the grid: the result equals the exhaustive
+// search.  The weights of Eq.(2) follow in float64.
 template <int K>
-__global__ void __launch_bounds__(kKnnBlock) knn_kernel(PointsView pts, NodesView nd, int wkind, float sigma,
+__global__ void __launch_bounds__(kKnnBlock) knn_kernel(PointsView pts, GridView gv, int wkind, float sigma,
                                                         int32_t *__restrict__ idx_out, float *__restrict__ w_out) {
-    __shared__ float sx[kNodeTile], sy[kNodeTile], sz[kNodeTile];
     const int64_t i = (int64_t)blockIdx.x * kKnnBlock + threadIdx.x;
-    const bool live = i < pts.n;
-    const double px = live ? (double)pts.px[i] : 0.0;
-    const double py = live ? (double)pts.py[i] : 0.0;
-    const double pz = live ? (double)pts.pz[i] : 0.0;
+    if (i >= pts.n) return;
+    const double px = (double)pts.px[i], py = (double)pts.py[i], pz = (double)pts.pz[i];
     constexpr int KK = K + 1;
     double bd[KK];
     int bi[KK];
@@ -74,40 +225,45 @@ __global__ void __launch_bounds__(kKnnBlock) knn_kernel(PointsView pts, NodesVie
         bd[s] = __builtin_huge_val();
         bi[s] = -1;
     }
-    for (int base = 0; base < nd.m; base += kNodeTile) {
-        const int cnt = min(kNodeTile, nd.m - base);
-        __syncthreads();
-        for (int t = threadIdx.x; t < cnt; t += kKnnBlock) {
-            sx[t] = nd.gx[base + t];
-            sy[t] = nd.gy[base + t];
-            sz[t] = nd.gz[base + t];
-        }
-        __syncthreads();
-        if (!live) continue;
-        for (int t = 0; t < cnt; ++t) {
-            const double dx = px - (double)sx[t];
-            const double dy = py - (double)sy[t];
-            const double dz = pz - (double)sz[t];
-            const double d2 = (dx * dx + dy * dy) + dz * dz;
-            if (d2 < bd[KK - 1]) {
-                // insert after every entry with distance <= d2 (equal distances keep the lower index first)
-                double cd = d2;
-                int ci = base + t;
+    const int dx = gv.dims[0], dy = gv.dims[1], dz = gv.dims[2];
+    if (dx > 0) {
+        const double h = gv.hdr[3], ih = 1.0 / h;
+        const double p[3] = {px, py, pz};
+        const int dim[3] = {dx, dy, dz};
+        int q[3];
 #pragma unroll
-                for (int s = 0; s < KK; ++s) {
-                    if (cd < bd[s]) {
-                        const double td = bd[s];
-                        const int ti = bi[s];
-                        bd[s] = cd;
-                        bi[s] = ci;
-                        cd = td;
-                        ci = ti;
+        for (int a = 0; a < 3; ++a) {
+            const double f = floor((p[a] - gv.hdr[a]) * ih);
+            q[a] = f >= 0.0 ? (f < (double)(dim[a] - 1) ? (int)f : dim[a] - 1) : 0;
+        }
+        const int rmax = max(max(max(q[0], dx - 1 - q[0]), max(q[1], dy - 1 - q[1])), max(q[2], dz - 1 - q[2]));
+        for (int r = 0; r <= rmax; ++r) {
+            const int z0 = max(0, q[2] - r), z1 = min(dz - 1, q[2] + r);
+            const int y0 = max(0, q[1] - r), y1 = min(dy - 1, q[1] + r);
+            const int x0 = max(0, q[0] - r), x1 = min(dx - 1, q[0] + r);
+            for (int cz = z0; cz <= z1; ++cz) {
+                for (int cy = y0; cy <= y1; ++cy) {
+                    const bool face = abs(cz - q[2]) == r || abs(cy - q[1]) == r;
+                    // on a face row every x; otherwise only the two x ends of the shell
+                    const int step = face ? 1 : 2 * r;
+                    for (int cx = face ? x0 : q[0] - r; cx <= (face ? x1 : q[0] + r); cx += step > 0 ? step : 1) {
+                        if (cx < 0 || cx >= dx) continue;
+                        const int c = (cz * dy + cy) * dx + cx;
+                        const int n0 = gv.start[c], n1 = gv.start[c + 1];
+                        for (int t = n0; t < n1; ++t) {
+                            const float4 g = gv.nodes[t];
+                            const double ex = px - (double)g.x;
+                            const double ey = py - (double)g.y;
+                            const double ez = pz - (double)g.z;
+                            knn_insert<KK>(bd, bi, (ex * ex + ey * ey) + ez * ez, __float_as_int(g.w));
+                        }
                     }
                 }
             }
+            const double b = ((double)r - 1e-6) * h;
+            if (b > 0.0 && bd[KK - 1] < b * b) break;
         }
     }
-    if (!live) return;
     double wv[K];
     double sum = 0.0;
     if (wkind == MISSLAM_WEIGHT_GAUSS) {
@@ -468,6 +624,12 @@ hipError_t launch_normal_map(const float *depth, const Cam &cam, float4 *out, hi
     return hipGetLastError();
 }
 
+hipError_t launch_normal_map_batched(const BatchItem *items, int count, int total_blocks, hipStream_t st) {
+    if (total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(normal_map_batched_kernel, dim3(total_blocks), dim3(256), 0, st, items, count);
+    return hipGetLastError();
+}
+
 template <int K>
 static hipError_t graph_k(const PointsView &pts, const NodesView &nd, int wkind, float sigma, const GraphView &g,
                           const GraphScratch &s, hipStream_t st) {
@@ -478,8 +640,9 @@ static hipError_t graph_k(const PointsView &pts, const NodesView &nd, int wkind,
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, (uint32_t *)g.info, (size_t)8, 0u);
     int32_t *lcnt = s.cnt + m;
     if (n > 0) {
-        hipLaunchKernelGGL((knn_kernel<K>), dim3(nblk(n, kKnnBlock)), dim3(kKnnBlock), 0, st, pts, nd, wkind, sigma,
-                           g.knn_idx, g.knn_w);
+        hipLaunchKernelGGL(node_grid_kernel, dim3(1), dim3(kGridThreads), 0, st, nd, s.grid);
+        hipLaunchKernelGGL((knn_kernel<K>), dim3(nblk(n, kKnnBlock)), dim3(kKnnBlock), 0, st, pts, s.grid, wkind,
+                           sigma, g.knn_idx, g.knn_w);
         hipLaunchKernelGGL((list_count_kernel<K>), dim3(nblk(n, 256)), dim3(256), 0, st, g.knn_idx, n, lcnt);
     }
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, lcnt, m, g.list_ptr, g.info, -1, 2,

@@ -53,16 +53,11 @@ hipError_t launch_bjacobi(const GraphView &g, int m, const float *blocks, float 
 
 // ---------------------------------------------------------------- PCG
 
-struct PcgArgs {
-    const int32_t *row_ptr, *col_idx;
-    const float *blocks, *minv, *g;
-    float lambda;
-    int m, nblk, iters, cap;
-    float *x, *r, *z, *p, *q;
-    double *part;     // [(it * 4 + kind) * nblk + block], kind 0 = r.z, 1 = r.r, 2 = p.q, 3 = #non-finite x
-    int32_t *status;  // [it]: 0 running, 2 stopped by breakdown (propagates)
-    int32_t *done;    // [it]: 1 if iteration it updated x
-};
+__global__ void fill_u32_kernel_pcg(unsigned *p, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0u;
+}
+
 
 __device__ __forceinline__ double gather_sum(const double *part, int nblk, double *lds) {
     double s = 0.0;
@@ -123,25 +118,27 @@ __global__ void __launch_bounds__(kPcgThreads) pcg_dir_kernel(PcgArgs A, int it)
     double pq = 0.0;
     if (act) {
         const float beta = it > 0 ? (float)(rz / rz_prev) : 0.f;
-        float az = 0.f;
+        // float32 products summed exactly in float64: the regulariser blocks
+        // cancel each other to a small product, which float32 sums would blur
+        double az = 0.0;
         const int p0 = A.row_ptr[j], p1 = min(A.row_ptr[j + 1], A.cap);
         for (int pb = p0; pb < p1; ++pb) {
             const int l = A.col_idx[pb];
             const float *B = A.blocks + (size_t)pb * 144 + a * 12;
             const float *zl = A.z + (size_t)l * 12;
 #pragma unroll
-            for (int b = 0; b < 12; ++b) az = fmaf(B[b], zl[b], az);
+            for (int b = 0; b < 12; ++b) az = fma((double)B[b], (double)zl[b], az);
         }
         const size_t o = (size_t)j * 12 + a;
         const float zj = A.z[o];
-        az = fmaf(A.lambda, zj, az);
+        az = fma((double)A.lambda, (double)zj, az);
         float p, q;
         if (it > 0) {
             p = fmaf(beta, A.p[o], zj);
-            q = fmaf(beta, A.q[o], az);
+            q = (float)fma((double)beta, (double)A.q[o], az);
         } else {
             p = zj;
-            q = az;
+            q = (float)az;
         }
         A.p[o] = p;
         A.q[o] = q;
@@ -262,6 +259,26 @@ hipError_t launch_pcg_update(const GraphView &g, int m, const float *blocks, con
     return hipGetLastError();
 }
 
+__global__ void report_init_batched_kernel(const BatchItem *__restrict__ items, int per_problem) {
+    misslam_report *rep = items[blockIdx.x].rep;
+    for (int t = threadIdx.x; t < per_problem; t += blockDim.x) {
+        rep[t].e_data = 0.0;
+        rep[t].e_rot = 0.0;
+        rep[t].e_reg = 0.0;
+        for (int q = 0; q <= MISSLAM_MAX_PCG; ++q) rep[t].pcg_resid[q] = 0.0;
+        rep[t].n_valid = 0;
+        rep[t].flags = 0;
+        rep[t].pcg_iters_done = 0;
+        rep[t].reserved = 0;
+    }
+}
+
+hipError_t launch_report_init_batched(const BatchItem *items, int count, int per_problem, hipStream_t st) {
+    if (count <= 0 || per_problem <= 0) return hipSuccess;
+    hipLaunchKernelGGL(report_init_batched_kernel, dim3(count), dim3(64), 0, st, items, per_problem);
+    return hipGetLastError();
+}
+
 __global__ void report_init_kernel(misslam_report *rep, int count) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < count) {
@@ -286,34 +303,122 @@ int pcg_blocks(int m) { return (m + kRowsPerBlk - 1) / kRowsPerBlk; }
 
 // ---------------------------------------------------------------- persistent PCG (one cooperative launch)
 
-constexpr int kPersistLdsBytes = 64 * 1024;
-
-// The same recurrence in one launch: each workgroup owns a contiguous range of
-// rows, keeps their blocks (as many as fit) and their preconditioner blocks in
-// LDS and its slice of x, r, p, q in LDS; only z travels through global memory.
-// Two grid-wide barriers per iteration; every reduction is re-added by every
+// The same recurrence in one launch.  Each workgroup owns a contiguous range
+// of up to kRowsPerBlk rows and keeps their H blocks (as many as fit), their
+// preconditioner blocks and its slice of x, r, p, q in LDS.  Between
+// workgroups only z and the reduction partials travel, through device-scope
+// loads and stores (coherent across the XCDs' separate L2 caches without
+// cache maintenance), and a counter barrier on device-scope atomics orders
+// them: two barriers per iteration.  Every reduction is re-added by every
 // workgroup in the same order, so all take identical decisions.
-__global__ void __launch_bounds__(kPcgThreads) pcg_persistent_kernel(PcgArgs A, int rows_per_wg, int cache_blocks,
-                                                                    misslam_report *rep, float *__restrict__ params) {
-    namespace cg = cooperative_groups;
-    cg::grid_group grid = cg::this_grid();
+constexpr int kPersistMaxLds = 160 * 1024;   // LDS of one CU (gfx950)
+
+__device__ __forceinline__ void st_dev(float *p, float v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float ld_dev(const float *p) {
+    return __hip_atomic_load(const_cast<float *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double *p) {
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier: bar[0] counts arrivals, bar[32] is the generation.  Each
+// wave first waits until its own device-scope stores are acknowledged, so
+// they are visible once the arrival is.  The wait is bounded: a workgroup
+// that gives up (which a cooperative launch, where every workgroup is
+// resident, never causes) stops waiting at later barriers and reports it.
+constexpr unsigned kSpinLimit = 1u << 18;
+
+__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nblocks, bool &broken) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    __shared__ int give_up;
+    if (threadIdx.x == 0) {
+        give_up = broken ? 1 : 0;
+        const unsigned g0 = __hip_atomic_load(&bar[32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned a = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == nblocks - 1) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);
+            __hip_atomic_fetch_add(&bar[32], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (!broken) {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&bar[32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+                if (++spins > kSpinLimit) {
+                    give_up = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __syncthreads();
+    broken = give_up != 0;
+}
+
+// Sum of up to three doubles over the workgroup: wave butterflies, then the
+// waves in order (fixed order: bitwise reproducible).
+template <int NV>
+__device__ __forceinline__ void wg_sum(double (&v)[NV], double (*lds)[kPcgThreads / kWave]) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double t = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (lane == 0) lds[q][wave] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double t = lds[q][0];
+#pragma unroll
+        for (int w = 1; w < kPcgThreads / kWave; ++w) t += lds[q][w];
+        v[q] = t;
+    }
+    __syncthreads();
+}
+
+// Fixed-order sum of the G partials of one reduction (device-scope loads).
+__device__ __forceinline__ double gather_dev(const double *part, int G, double (*lds)[kPcgThreads / kWave]) {
+    double v[1] = {0.0};
+    for (int t = threadIdx.x; t < G; t += kPcgThreads) v[0] += ld_dev(part + t);
+    wg_sum<1>(v, lds);
+    return v[0];
+}
+
+// One workgroup's share of the solve: workgroup wg of the G that own this
+// system's rows; the barrier counts nbar workgroups (G, or every workgroup of
+// a batch of systems solved side by side).
+__device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_per_wg, int cache_blocks, unsigned *bar,
+                                                    unsigned nbar, int wg, int G, misslam_report *rep,
+                                                    float *params) {
     extern __shared__ float dyn[];
-    __shared__ double red[kPcgThreads];
+    __shared__ double red[3][kPcgThreads / kWave];
     __shared__ float vx[kRowsPerBlk * 12], vr[kRowsPerBlk * 12], vp[kRowsPerBlk * 12], vq[kRowsPerBlk * 12];
-    const int G = gridDim.x;
-    const int r0 = min(A.m, (int)blockIdx.x * rows_per_wg);
+    const int r0 = min(A.m, wg * rows_per_wg);
     const int r1 = min(A.m, r0 + rows_per_wg);
     const int b0 = min(A.row_ptr[r0], A.cap), b1 = min(A.row_ptr[r1], A.cap);
-    const int cached = min(b1 - b0, cache_blocks);
+    const int nb = b1 - b0;                            // blocks of this workgroup's rows
+    const int cached = min(nb, cache_blocks);
     float *hc = dyn;                                   // cached blocks
-    float *mc = dyn + (size_t)cache_blocks * 144;      // preconditioner blocks of the rows
+    float *mc = hc + (size_t)cache_blocks * 144;       // preconditioner blocks of the rows
+    float *zc = mc + (size_t)kRowsPerBlk * 144;        // z of every block's column, per iteration
+    int *cc = reinterpret_cast<int *>(zc + (size_t)cache_blocks * 12);   // column of every cached-z block
     for (int t = threadIdx.x; t < cached * 144; t += kPcgThreads) hc[t] = A.blocks[(size_t)b0 * 144 + t];
     for (int t = threadIdx.x; t < (r1 - r0) * 144; t += kPcgThreads) mc[t] = A.minv[(size_t)r0 * 144 + t];
-    // thread -> (row, component); rows_per_wg <= kRowsPerBlk
+    for (int t = threadIdx.x; t < cached; t += kPcgThreads) cc[t] = A.col_idx[b0 + t];
     const int lr = threadIdx.x / 12, a = threadIdx.x % 12;
     const int j = r0 + lr;
     const bool act = lr < kRowsPerBlk && j < r1;
     const int li = lr * 12 + a;
+    bool broken = false;
     __syncthreads();
 
     // init: r = -g, z = M r, x = 0
@@ -330,61 +435,73 @@ __global__ void __launch_bounds__(kPcgThreads) pcg_persistent_kernel(PcgArgs A, 
 #pragma unroll
         for (int b = 0; b < 12; ++b) s = fmaf(M[b], vr[lr * 12 + b], s);
         z = s;
-        A.z[(size_t)j * 12 + a] = z;
+        st_dev(A.z + (size_t)j * 12 + a, z);
     }
     {
-        const double rz0 = block_sum<kPcgThreads>((double)r * (double)z, red);
-        const double rr0 = block_sum<kPcgThreads>((double)r * (double)r, red);
+        double v[2] = {(double)r * (double)z, (double)r * (double)r};
+        wg_sum<2>(v, red);
         if (threadIdx.x == 0) {
-            A.part[(size_t)(0 * 4 + 0) * G + blockIdx.x] = rz0;
-            A.part[(size_t)(0 * 4 + 1) * G + blockIdx.x] = rr0;
+            st_dev(A.part + (size_t)(0 * 4 + 0) * G + wg, v[0]);
+            st_dev(A.part + (size_t)(0 * 4 + 1) * G + wg, v[1]);
         }
     }
-    grid.sync();
+    grid_barrier(bar, nbar, broken);
     bool stopped = false;
     int done = 0;
     double rz_prev = 1.0;
+    double rz = gather_dev(A.part + (size_t)(0 * 4 + 0) * G, G, red);
     for (int it = 0; it < A.iters; ++it) {
-        const double rz = gather_sum(A.part + (size_t)(it * 4 + 0) * G, G, red);
         const bool skip = stopped || rz == 0.0;
+        // ---- z of the blocks' columns into LDS
+        if (!skip) {
+            for (int t = threadIdx.x; t < cached * 12; t += kPcgThreads)
+                zc[t] = ld_dev(A.z + (size_t)cc[t / 12] * 12 + t % 12);
+            __syncthreads();
+        }
         // ---- direction and product: p = z + beta p, q = (H + lambda I) z + beta q
         double pq = 0.0;
         if (act && !skip) {
             const float beta = it > 0 ? (float)(rz / rz_prev) : 0.f;
-            float az = 0.f;
+            double az = 0.0;                           // exact float64 sum of float32 products
             const int p0 = A.row_ptr[j], p1 = min(A.row_ptr[j + 1], A.cap);
             for (int pb = p0; pb < p1; ++pb) {
-                const int l = A.col_idx[pb];
-                const float *B = (pb - b0 < cached) ? hc + (size_t)(pb - b0) * 144 + a * 12
-                                                    : A.blocks + (size_t)pb * 144 + a * 12;
-                const float *zl = A.z + (size_t)l * 12;
+                const int q = pb - b0;
+                if (q < cached) {
+                    const float *B = hc + (size_t)q * 144 + a * 12;
+                    const float *zl = zc + (size_t)q * 12;
 #pragma unroll
-                for (int b = 0; b < 12; ++b) az = fmaf(B[b], zl[b], az);
+                    for (int b = 0; b < 12; ++b) az = fma((double)B[b], (double)zl[b], az);
+                } else {
+                    const float *B = A.blocks + (size_t)pb * 144 + a * 12;
+                    const float *zl = A.z + (size_t)A.col_idx[pb] * 12;
+#pragma unroll
+                    for (int b = 0; b < 12; ++b) az = fma((double)B[b], (double)ld_dev(zl + b), az);
+                }
             }
-            az = fmaf(A.lambda, z, az);
+            az = fma((double)A.lambda, (double)z, az);
             const float pv = it > 0 ? fmaf(beta, vp[li], z) : z;
-            const float qv = it > 0 ? fmaf(beta, vq[li], az) : az;
+            const float qv = it > 0 ? (float)fma((double)beta, (double)vq[li], az) : (float)az;
             vp[li] = pv;
             vq[li] = qv;
             pq = (double)pv * (double)qv;
         }
         {
-            const double t = block_sum<kPcgThreads>(pq, red);
-            if (threadIdx.x == 0) A.part[(size_t)(it * 4 + 2) * G + blockIdx.x] = t;
+            double v[1] = {pq};
+            wg_sum<1>(v, red);
+            if (threadIdx.x == 0) st_dev(A.part + (size_t)(it * 4 + 2) * G + wg, v[0]);
         }
-        grid.sync();
+        grid_barrier(bar, nbar, broken);
         // ---- step: alpha = r.z / p.q, x += alpha p, r -= alpha q, z = M r
-        const double pqs = gather_sum(A.part + (size_t)(it * 4 + 2) * G, G, red);
+        const double pqs = gather_dev(A.part + (size_t)(it * 4 + 2) * G, G, red);
         const bool brk = !skip && !(pqs > 0.0);
         const bool upd = !skip && !brk;
-        double bad = 0.0;
         if (act && upd) {
             const float alpha = (float)(rz / pqs);
             vx[li] = fmaf(alpha, vp[li], vx[li]);
             r = fmaf(-alpha, vq[li], r);
             vr[li] = r;
         }
-        if (act) bad = isfinite(vx[li]) ? 0.0 : 1.0;
+        const double bad = act ? (isfinite(vx[li]) ? 0.0 : 1.0) : 0.0;
         __syncthreads();
         if (act && upd) {
             const float *M = mc + (size_t)lr * 144 + a * 12;
@@ -392,32 +509,32 @@ __global__ void __launch_bounds__(kPcgThreads) pcg_persistent_kernel(PcgArgs A, 
 #pragma unroll
             for (int b = 0; b < 12; ++b) s = fmaf(M[b], vr[lr * 12 + b], s);
             z = s;
-            A.z[(size_t)j * 12 + a] = z;
+            st_dev(A.z + (size_t)j * 12 + a, z);
         }
         {
-            const double rzn = block_sum<kPcgThreads>((double)r * (double)z, red);
-            const double rrn = block_sum<kPcgThreads>((double)r * (double)r, red);
-            const double nb = block_sum<kPcgThreads>(bad, red);
+            double v[3] = {(double)r * (double)z, (double)r * (double)r, bad};
+            wg_sum<3>(v, red);
             if (threadIdx.x == 0) {
-                A.part[(size_t)((it + 1) * 4 + 0) * G + blockIdx.x] = rzn;
-                A.part[(size_t)((it + 1) * 4 + 1) * G + blockIdx.x] = rrn;
-                A.part[(size_t)((it + 1) * 4 + 3) * G + blockIdx.x] = nb;
+                st_dev(A.part + (size_t)((it + 1) * 4 + 0) * G + wg, v[0]);
+                st_dev(A.part + (size_t)((it + 1) * 4 + 1) * G + wg, v[1]);
+                st_dev(A.part + (size_t)((it + 1) * 4 + 3) * G + wg, v[2]);
             }
         }
         if (upd) ++done;
         if (brk) stopped = true;
         if (!skip) rz_prev = rz;
-        grid.sync();
+        grid_barrier(bar, nbar, broken);
+        rz = gather_dev(A.part + (size_t)((it + 1) * 4 + 0) * G, G, red);
     }
     // ---- finish: report (block 0), x out, params += x unless non-finite
-    const double nbad = A.iters > 0 ? gather_sum(A.part + (size_t)(A.iters * 4 + 3) * G, G, red) : 0.0;
+    const double nbad = A.iters > 0 ? gather_dev(A.part + (size_t)(A.iters * 4 + 3) * G, G, red) : 0.0;
     if (act) {
         A.x[(size_t)j * 12 + a] = vx[li];
-        if (params && nbad == 0.0) params[(size_t)j * 12 + a] += vx[li];
+        if (params && nbad == 0.0 && !broken) params[(size_t)j * 12 + a] += vx[li];
     }
-    if (blockIdx.x == 0) {
+    if (wg == 0) {
         for (int q = 0; q <= done; ++q) {
-            const double rr = gather_sum(A.part + (size_t)(q * 4 + 1) * G, G, red);
+            const double rr = gather_dev(A.part + (size_t)(q * 4 + 1) * G, G, red);
             if (threadIdx.x == 0 && q <= MISSLAM_MAX_PCG) rep->pcg_resid[q] = sqrt(rr);
         }
         if (threadIdx.x == 0) {
@@ -428,36 +545,58 @@ __global__ void __launch_bounds__(kPcgThreads) pcg_persistent_kernel(PcgArgs A, 
             rep->flags = f;
         }
     }
+    if (broken && threadIdx.x == 0) atomicOr(&rep->flags, MISSLAM_FLAG_SYNC_TIMEOUT);
+}
+
+__global__ void __launch_bounds__(kPcgThreads) pcg_persistent_kernel(PcgArgs A, int rows_per_wg, int cache_blocks,
+                                                                    unsigned *bar, misslam_report *rep,
+                                                                    float *params) {
+    pcg_persistent_body(A, rows_per_wg, cache_blocks, bar, gridDim.x, blockIdx.x, gridDim.x, rep, params);
 }
 
 // Grid shape of the persistent solve for m rows on this device, or 0 when a
 // cooperative launch cannot hold it (the multi-kernel path is used then).
-static int persistent_grid(int m, int &rows_per_wg) {
-    static int max_blocks = -1;
+// Rows are packed kRowsPerBlk to a workgroup: fewer workgroups make the
+// barriers cheaper, and one workgroup per CU must hold them all.
+static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes) {
+    static int max_blocks = -1, max_lds = 0;
     if (max_blocks < 0) {
-        int dev = 0, cus = 0, per_cu = 0, coop = 0;
+        int dev = 0, cus = 0, coop = 0, shmem = 0;
+        hipFuncAttributes fa{};
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pcg_persistent_kernel, kPcgThreads,
-                                                         kPersistLdsBytes) != hipSuccess ||
-            !coop)
+            hipDeviceGetAttribute(&shmem, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+            hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(pcg_persistent_kernel)) != hipSuccess || !coop) {
             max_blocks = 0;
-        else
-            max_blocks = cus * (per_cu < 1 ? per_cu : 1);   // one workgroup per CU keeps the barriers small
+        } else {
+            max_lds = (shmem < kPersistMaxLds ? shmem : kPersistMaxLds) - (int)fa.sharedSizeBytes - 1024;
+            int per_cu = 0;
+            if (max_lds <= 0 ||
+                hipFuncSetAttribute(reinterpret_cast<const void *>(pcg_persistent_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pcg_persistent_kernel, kPcgThreads,
+                                                             max_lds) != hipSuccess ||
+                per_cu < 1)
+                max_blocks = 0;
+            else
+                max_blocks = cus;
+        }
     }
-    if (max_blocks <= 0) return 0;
-    rows_per_wg = (m + max_blocks - 1) / max_blocks;
-    if (rows_per_wg > kRowsPerBlk) return 0;
-    return (m + rows_per_wg - 1) / rows_per_wg;
+    if (max_blocks <= 0 || m <= 0) return 0;
+    rows_per_wg = kRowsPerBlk;
+    const int G = (m + rows_per_wg - 1) / rows_per_wg;
+    if (G > max_blocks) return 0;
+    lds_bytes = max_lds;
+    return G;
 }
 
 hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                                  float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
-                                 float *params, hipStream_t st, bool *used) {
+                                 float *params, hipStream_t st, bool *used, bool bar_zeroed) {
     *used = false;
-    int rows = 0;
-    const int G = persistent_grid(m, rows);
+    int rows = 0, lds = 0;
+    const int G = persistent_grid(m, rows, lds);
     if (G <= 0 || G > s.nblk_max) return hipSuccess;
     PcgArgs A;
     A.row_ptr = g.row_ptr;
@@ -478,14 +617,94 @@ hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks,
     A.part = s.part;
     A.status = s.status;
     A.done = s.status + (iters + 2);
-    const int mc_floats = rows * 144;
-    const int cache_blocks = (kPersistLdsBytes / 4 - mc_floats) / 144;
-    void *args[] = {&A, (void *)&rows, (void *)&cache_blocks, &rep, &params};
+    // LDS: cached blocks (144 floats), their z (12 floats) and column (1 int); the rows' preconditioner
+    const int cache_blocks = (lds / 4 - kRowsPerBlk * 144) / (144 + 12 + 1);
+    if (cache_blocks < 1) return hipSuccess;
+    unsigned *bar = s.bar;
+    if (!bar_zeroed) hipLaunchKernelGGL(fill_u32_kernel_pcg, dim3(1), dim3(64), 0, st, bar, 64);
+    void *args[] = {&A, (void *)&rows, (void *)&cache_blocks, &bar, &rep, &params};
     const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(pcg_persistent_kernel), dim3(G),
-                                                    dim3(kPcgThreads), args, kPersistLdsBytes, st);
+                                                    dim3(kPcgThreads), args, (unsigned)lds, st);
     if (e == hipSuccess) *used = true;
     return e;
 }
 
+
+}  // namespace msl
+
+namespace msl {
+
+// ---------------------------------------------------------------- side-by-side persistent solves
+
+// Every problem of a batch runs the same recurrence on its own rows: workgroup
+// w belongs to the problem whose range holds it, keeps that problem's
+// partials, and joins one barrier with every workgroup of the launch.
+__global__ void __launch_bounds__(kPcgThreads) pcg_batched_kernel(const BatchItem *__restrict__ items, int count,
+                                                                 int rows_per_wg, int cache_blocks, unsigned *bar,
+                                                                 int gi) {
+    int b = count - 1;
+    while (b > 0 && items[b].wg0 > (int)blockIdx.x) --b;
+    const BatchItem &it = items[b];
+    pcg_persistent_body(it.p, rows_per_wg, cache_blocks, bar, gridDim.x, (int)blockIdx.x - it.wg0, it.wgs,
+                        it.rep + gi, it.params);
+}
+
+static int batched_static_lds() {
+    static int v = -1;
+    if (v < 0) {
+        hipFuncAttributes fa{};
+        v = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(pcg_batched_kernel)) == hipSuccess
+                ? (int)fa.sharedSizeBytes
+                : 1 << 30;
+    }
+    return v;
+}
+
+// Dynamic LDS per workgroup for total_wgs co-resident workgroups, or 0 if they cannot all be resident.
+static int batched_lds(int total_wgs) {
+    int dev = 0, cus = 0, shmem = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&shmem, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || cus <= 0)
+        return 0;
+    const int per_cu = (total_wgs + cus - 1) / cus;
+    if (per_cu > 4) return 0;
+    const int cu_lds = kPersistMaxLds;
+    int lds = cu_lds / per_cu - batched_static_lds() - 1024;
+    if (lds > shmem - batched_static_lds() - 1024) lds = shmem - batched_static_lds() - 1024;
+    const int min_lds = (kRowsPerBlk * 144 + 157) * 4;   // the rows' preconditioner and one cached block
+    if (lds < min_lds) return 0;
+    int occ = 0;
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(pcg_batched_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pcg_batched_kernel, kPcgThreads, lds) != hipSuccess ||
+        occ * cus < total_wgs)
+        return 0;
+    return lds;
+}
+
+int pcg_batched_fits(int total_wgs) { return total_wgs > 0 && batched_lds(total_wgs) > 0 ? 1 : 0; }
+
+hipError_t launch_pcg_batched(const BatchItem *items, int count, int rows_per_wg, int total_wgs, int it,
+                              unsigned *bar, bool cooperative, hipStream_t st, bool *used) {
+    *used = false;
+    const int lds = batched_lds(total_wgs);
+    if (lds <= 0 || rows_per_wg < 1 || rows_per_wg > kRowsPerBlk) return hipSuccess;
+    const int cache_blocks = (lds / 4 - kRowsPerBlk * 144) / (144 + 12 + 1);
+    if (cache_blocks < 1) return hipSuccess;
+    hipError_t e;
+    if (cooperative) {
+        void *args[] = {(void *)&items, (void *)&count, (void *)&rows_per_wg, (void *)&cache_blocks, (void *)&bar,
+                        (void *)&it};
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(pcg_batched_kernel), dim3(total_wgs),
+                                       dim3(kPcgThreads), args, (unsigned)lds, st);
+    } else {
+        hipLaunchKernelGGL(pcg_batched_kernel, dim3(total_wgs), dim3(kPcgThreads), (unsigned)lds, st, items, count,
+                           rows_per_wg, cache_blocks, bar, it);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) *used = true;
+    return e;
+}
 
 }  // namespace msl

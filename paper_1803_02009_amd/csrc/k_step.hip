@@ -62,10 +62,10 @@ constexpr int kPtBlock = 256;
 // the matched pixel, stores (n', r) with n' = R^T N for the assembly, and leaves
 // per-block float64 sums (r^2, count, |r|) for the energy report.
 template <int K>
-__global__ void __launch_bounds__(kPtBlock) point_pass_kernel(StepArgs a, StepScratch s) {
+__device__ __forceinline__ void point_pass_body(const StepArgs &a, const StepScratch &s, int64_t blk) {
     __shared__ double red[kPtBlock];
     const int64_t n = a.pts.n;
-    const int64_t i = (int64_t)blockIdx.x * kPtBlock + threadIdx.x;
+    const int64_t i = blk * kPtBlock + threadIdx.x;
     double r2 = 0.0, cnt = 0.0, ra = 0.0;
     if (i < n) {
         float x, y, z, nx, ny, nz;
@@ -96,10 +96,15 @@ __global__ void __launch_bounds__(kPtBlock) point_pass_kernel(StepArgs a, StepSc
     const double t1 = block_sum<kPtBlock>(cnt, red);
     const double t2 = block_sum<kPtBlock>(ra, red);
     if (threadIdx.x == 0) {
-        s.pt_part[3 * blockIdx.x + 0] = t0;
-        s.pt_part[3 * blockIdx.x + 1] = t1;
-        s.pt_part[3 * blockIdx.x + 2] = t2;
+        s.pt_part[3 * blk + 0] = t0;
+        s.pt_part[3 * blk + 1] = t1;
+        s.pt_part[3 * blk + 2] = t2;
     }
+}
+
+template <int K>
+__global__ void __launch_bounds__(kPtBlock) point_pass_kernel(StepArgs a, StepScratch s) {
+    point_pass_body<K>(a, s, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- row assembly
@@ -140,9 +145,8 @@ struct RowNode {
     float Jr[6][9];                  // rotation-term Jacobian of node j
     float rr[6];
     float xj[12];
-    float gd[12];                    // data-term gradient of the row (unweighted)
+    double gd[12];                   // data-term gradient of the row (unweighted)
     double Hd[12][12];               // damped diagonal block for the preconditioner
-    double Li[12][12];
     double red[NT];
 };
 
@@ -153,41 +157,33 @@ struct AsmShared {
     float Na[kAsmWaves][kBatch][6];
     float4 W[kAsmWaves][kBatch][(K + 3) / 4];
     uint32_t key[kAsmWaves][kBatch][2];
-    float gw[kAsmWaves][12];
+    double gw[kAsmWaves][12];
     RowNode<kAsmThreads> rn;
 };
 
-// Node-level terms and output of one row, shared by the float32 and the
-// low-precision assembly: Eq.(6) regulariser blocks for both edge directions,
-// the Eq.(5) rotation block, the gradient, the row's blocks (data term given
-// by data(slot, R, C), already weighted by the point weights) and, when
-// requested, the block-Jacobi inverse of the damped diagonal block.  rr_out,
-// if set, receives the regulariser + rotation part of each block alone.
-template <int NT, class DataFn>
-__device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratch &s, RowNode<NT> &rn, int j, int rb,
-                                             int nslots, float gjx, float gjy, float gjz, DataFn data,
-                                             float *rr_out) {
+// Node-level residuals of row j, computed before the data phase so that their
+// loads overlap it: for each neighbour slot (thread tid < nslots) the edge
+// vector and both Eq.(6) residuals, and (thread 0) the Eq.(5) residuals and
+// Jacobian of node j; threads < 12 stage x_j.  Returns this thread's share of
+// E_reg (summed in row_finalize).  The columns must already be in rn.cols.
+template <int NT>
+__device__ __forceinline__ double row_prepare(const StepArgs &a, RowNode<NT> &rn, int j, int nslots, float gjx,
+                                              float gjy, float gjz) {
     const int tid = threadIdx.x;
-    const int wave = tid / kWave, lane = tid % kWave;
+    const float *xj = a.nd.x + (size_t)j * 12;
+    if (tid < 12) rn.xj[tid] = xj[tid];
     double e_reg = 0.0;
     if (tid < nslots) {
-        const int l = rn.cols[tid];
+        const int l = a.g.col_idx[min(a.g.row_ptr[j], a.g.bsr_cap) + tid];
         float ex = 0.f, ey = 0.f, ez = 0.f, r0 = 0.f, r1 = 0.f, r2 = 0.f, q0 = 0.f, q1 = 0.f, q2 = 0.f;
         if (l != j) {
             const float glx = a.nd.gx[l], gly = a.nd.gy[l], glz = a.nd.gz[l];
             const float *xl = a.nd.x + (size_t)l * 12;
-            const float *xj = rn.xj;
             ex = glx - gjx;
             ey = gly - gjy;
             ez = glz - gjz;
-            // r_jl = A_j e + g_j + t_j - g_l - t_l   (edge j -> l)
-            r0 = fmaf(xj[6], ez, fmaf(xj[3], ey, xj[0] * ex)) + gjx + xj[9] - glx - xl[9];
-            r1 = fmaf(xj[7], ez, fmaf(xj[4], ey, xj[1] * ex)) + gjy + xj[10] - gly - xl[10];
-            r2 = fmaf(xj[8], ez, fmaf(xj[5], ey, xj[2] * ex)) + gjz + xj[11] - glz - xl[11];
-            // r_lj = A_l (-e) + g_l + t_l - g_j - t_j   (edge l -> j)
-            q0 = -fmaf(xl[6], ez, fmaf(xl[3], ey, xl[0] * ex)) + glx + xl[9] - gjx - xj[9];
-            q1 = -fmaf(xl[7], ez, fmaf(xl[4], ey, xl[1] * ex)) + gly + xl[10] - gjy - xj[10];
-            q2 = -fmaf(xl[8], ez, fmaf(xl[5], ey, xl[2] * ex)) + glz + xl[11] - gjz - xj[11];
+            reg_residual(xj, xl, ex, ey, ez, r0, r1, r2);      // edge j -> l
+            reg_residual(xl, xj, -ex, -ey, -ez, q0, q1, q2);   // edge l -> j
             e_reg = ((double)r0 * r0 + (double)r1 * r1) + (double)r2 * r2;
         }
         float *rg = rn.rg[tid];
@@ -196,15 +192,17 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
         rg[6] = q0; rg[7] = q1; rg[8] = q2;
     }
     if (tid == 0) {
-        const float *x = rn.xj;
+        float x[12];
+#pragma unroll
+        for (int t = 0; t < 12; ++t) x[t] = xj[t];
         const float *c[3] = {x, x + 3, x + 6};
         auto dot = [](const float *u, const float *v) { return fmaf(u[2], v[2], fmaf(u[1], v[1], u[0] * v[0])); };
         rn.rr[0] = dot(c[0], c[1]);
         rn.rr[1] = dot(c[0], c[2]);
         rn.rr[2] = dot(c[1], c[2]);
-        rn.rr[3] = dot(c[0], c[0]) - 1.f;
-        rn.rr[4] = dot(c[1], c[1]) - 1.f;
-        rn.rr[5] = dot(c[2], c[2]) - 1.f;
+        rn.rr[3] = unit_residual(c[0], 0);
+        rn.rr[4] = unit_residual(c[1], 1);
+        rn.rr[5] = unit_residual(c[2], 2);
         for (int q = 0; q < 6; ++q)
             for (int t = 0; t < 9; ++t) rn.Jr[q][t] = 0.f;
         const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
@@ -217,6 +215,20 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
         for (int q = 0; q < 3; ++q)
             for (int t = 0; t < 3; ++t) rn.Jr[3 + q][3 * q + t] = 2.f * c[q][t];
     }
+    return e_reg;
+}
+
+// Output of one row, shared by the float32 and the low-precision assembly:
+// Eq.(6) regulariser blocks for both edge directions, the Eq.(5) rotation
+// block, the gradient, the row's blocks (data term given by data(slot, R, C),
+// already weighted by the point weights) and, when requested, the
+// block-Jacobi inverse of the damped diagonal block.  rr_out, if set,
+// receives the regulariser + rotation part of each block alone.  The
+// node-level residuals come from row_prepare (e_reg: this thread's share).
+template <int NT, class DataFn>
+__device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratch &s, RowNode<NT> &rn, int j, int rb,
+                                             int nslots, double e_reg, DataFn data, float *rr_out) {
+    const int tid = threadIdx.x;
     const double ereg_tot = block_sum<NT>(e_reg, rn.red);   // also a barrier
     if (tid < 10) {
         float sacc = 0.f;
@@ -227,7 +239,7 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
         }
         rn.EE[tid] = sacc;
     }
-    if (tid < 144) rn.Hd[tid / 12][tid % 12] = tid / 12 == tid % 12 ? (double)a.lambda : 0.0;
+    for (int t = tid; t < 144; t += NT) rn.Hd[t / 12][t % 12] = t / 12 == t % 12 ? (double)a.lambda : 0.0;
     __syncthreads();
     if (tid == 0) {
         double erot = 0.0;
@@ -271,27 +283,26 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
     }
     if (tid < 12) {
         const int c = tid / 3, aa = tid % 3;
-        float reg = 0.f;
+        double reg = 0.0;
         for (int t = 0; t < nslots; ++t) {
             if (rn.cols[t] == j) continue;
             const float eh_c = c < 3 ? rn.rg[t][c] : 1.f;
-            reg = fmaf(eh_c, rn.rg[t][3 + aa], reg);
+            reg = fma((double)eh_c, (double)rn.rg[t][3 + aa], reg);
             if (c == 3) reg -= rn.rg[t][6 + aa];
         }
-        float rot = 0.f;
+        double rot = 0.0;
         if (c < 3) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) rot = fmaf(rn.Jr[q][tid], rn.rr[q], rot);
+            for (int q = 0; q < 6; ++q) rot = fma((double)rn.Jr[q][tid], (double)rn.rr[q], rot);
         }
-        a.gvec[(size_t)j * 12 + tid] = fmaf(wrot, rot, fmaf(wreg, reg, wd * rn.gd[tid]));
+        // the three terms balance near convergence: combined in float64, rounded once
+        a.gvec[(size_t)j * 12 + tid] = (float)fma((double)wrot, rot, fma((double)wreg, reg, (double)wd * rn.gd[tid]));
     }
-    // block-Jacobi preconditioner of this row: (H_jj + lambda I)^-1 in float64, by wave 0
+    // block-Jacobi preconditioner of this row: (H_jj + lambda I)^-1 in float64, whole workgroup
     if (a.minv) {
         __syncthreads();
-        if (wave == 0) {
-            const bool ok = chol_inverse_wave(rn.Hd, rn.Li, a.minv + (size_t)j * 144);
-            if (!ok && lane == 0) atomicOr(a.flags, MISSLAM_FLAG_NONSPD_BLOCK);
-        }
+        const bool ok = gj_inverse_block<NT>(rn.Hd, a.minv + (size_t)j * 144);
+        if (!ok && tid == 0) atomicOr(a.flags, MISSLAM_FLAG_NONSPD_BLOCK);
     }
 }
 
@@ -331,12 +342,8 @@ __device__ __forceinline__ void entry_load(const StepArgs &a, const StepScratch 
 // written, and the damped diagonal block is inverted for the block-Jacobi
 // preconditioner.  Fixed summation order throughout: bitwise reproducible.
 template <int K>
-__global__ void __launch_bounds__(kAsmThreads) assemble_rows_kernel(StepArgs a, StepScratch s) {
+__device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const StepScratch &s, int j) {
     __shared__ AsmShared<K> sh;
-    const int m = a.nd.m;
-    const int per = (int)((m + 7) / 8);
-    const int j = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (j >= m) return;
     const int tid = threadIdx.x;
     const int wave = tid / kWave, lane = tid % kWave;
     const int64_t n = a.pts.n;
@@ -351,6 +358,7 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_rows_kernel(StepArgs a, 
     for (int t = lane; t < MISSLAM_MAX_ROW * 64; t += kWave) (&sh.accS[wave][0][0])[t] = 0.f;
 
     const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
+    const double e_reg = row_prepare<kAsmThreads>(a, sh.rn, j, nslots, gjx, gjy, gjz);
     const int lb = a.g.list_ptr[j];
     const int cnt = min(a.g.list_ptr[j + 1] - lb, MISSLAM_MAX_LIST);
     const int quota = (cnt + kAsmWaves - 1) / kAsmWaves;
@@ -363,9 +371,9 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_rows_kernel(StepArgs a, 
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] = 0.f;
     uint32_t cur0 = 0xFFFFFFFFu, cur1 = 0xFFFFFFFFu;
-    float gacc[12];
+    double gacc[12];                 // data gradient: float64, it cancels near convergence
 #pragma unroll
-    for (int q = 0; q < 12; ++q) gacc[q] = 0.f;
+    for (int q = 0; q < 12; ++q) gacc[q] = 0.0;
 
     EntryRegs<K> nxt;
     if (nbatch > 0 && lane < min(kBatch, my1 - my0)) entry_load<K>(a, s, n, lb + my0 + lane, nxt);
@@ -415,7 +423,7 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_rows_kernel(StepArgs a, 
             for (int c = 0; c < 4; ++c) {
                 const float f = wr * uu[c];
 #pragma unroll
-                for (int aa = 0; aa < 3; ++aa) gacc[3 * c + aa] = fmaf(f, nn[aa], gacc[3 * c + aa]);
+                for (int aa = 0; aa < 3; ++aa) gacc[3 * c + aa] = fma((double)f, (double)nn[aa], gacc[3 * c + aa]);
             }
         }
         // run starts: an entry whose kNN set differs from the previous entry's
@@ -483,7 +491,7 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_rows_kernel(StepArgs a, 
     // wave reduction of the data gradient (fixed butterfly order)
 #pragma unroll
     for (int q = 0; q < 12; ++q) {
-        float v = gacc[q];
+        double v = gacc[q];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         gacc[q] = v;
     }
@@ -491,7 +499,6 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_rows_kernel(StepArgs a, 
 #pragma unroll
         for (int q = 0; q < 12; ++q) sh.gw[wave][q] = gacc[q];
     }
-    if (tid < 12) sh.rn.xj[tid] = a.nd.x[(size_t)j * 12 + tid];
     __syncthreads();
     for (int t = tid; t < nslots * 64; t += kAsmThreads) {
         const int sl = t / 64, en = t % 64;
@@ -511,7 +518,16 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_rows_kernel(StepArgs a, 
         if (sh.rn.cols[sl] != j && c2 < 3) h = fmaf(-sh.rn.rg[sl][c2], S[pc_index(c, 3) * 6 + ni], h);   // delta = -e
         return h;
     };
-    row_finalize<kAsmThreads>(a, s, sh.rn, j, rb, nslots, gjx, gjy, gjz, data, nullptr);
+    row_finalize<kAsmThreads>(a, s, sh.rn, j, rb, nslots, e_reg, data, nullptr);
+}
+
+template <int K>
+__global__ void __launch_bounds__(kAsmThreads) assemble_rows_kernel(StepArgs a, StepScratch s) {
+    const int m = a.nd.m;
+    const int per = (int)((m + 7) / 8);
+    const int j = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (j >= m) return;
+    assemble_rows_body<K>(a, s, j);
 }
 
 
@@ -546,7 +562,7 @@ struct LpShared {
     float acc[kLpWaves][MISSLAM_MAX_ROW * 144];
     T Jt[kLpWaves][12 * (K + 1)][kBatch];   // per entry: J of node j (rows 0-11), then of its k set nodes
     uint32_t key[kLpWaves][kBatch][2];
-    float gw[kLpWaves][12];
+    double gw[kLpWaves][12];
     RowNode<kLpThreads> rn;
 };
 
@@ -577,6 +593,7 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
     for (int t = lane; t < MISSLAM_MAX_ROW * 144; t += kWave) sh.acc[wave][t] = 0.f;
 
     const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
+    const double e_reg = row_prepare<kLpThreads>(a, sh.rn, j, nslots, gjx, gjy, gjz);
     const int lb = a.g.list_ptr[j];
     const int cnt = min(a.g.list_ptr[j + 1] - lb, MISSLAM_MAX_LIST);
     const int quota = (cnt + kLpWaves - 1) / kLpWaves;
@@ -588,9 +605,9 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
 #pragma unroll
     for (int q = 0; q < NT; ++q) D[q] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     uint32_t cur0 = 0xFFFFFFFFu, cur1 = 0xFFFFFFFFu;
-    float gacc[12];
+    double gacc[12];                 // data gradient: float64, it cancels near convergence
 #pragma unroll
-    for (int q = 0; q < 12; ++q) gacc[q] = 0.f;
+    for (int q = 0; q < 12; ++q) gacc[q] = 0.0;
     __syncthreads();   // cols visible to every wave
 
     auto flush = [&]() {
@@ -657,7 +674,7 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
             for (int c = 0; c < 4; ++c) {
                 const float f = wr * uj[c];
 #pragma unroll
-                for (int aa = 0; aa < 3; ++aa) gacc[3 * c + aa] = fmaf(f, nn[aa], gacc[3 * c + aa]);
+                for (int aa = 0; aa < 3; ++aa) gacc[3 * c + aa] = fma((double)f, (double)nn[aa], gacc[3 * c + aa]);
             }
         }
         bool start;
@@ -704,7 +721,7 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
     flush();
 #pragma unroll
     for (int q = 0; q < 12; ++q) {
-        float v = gacc[q];
+        double v = gacc[q];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         gacc[q] = v;
     }
@@ -712,7 +729,6 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
 #pragma unroll
         for (int q = 0; q < 12; ++q) sh.gw[wave][q] = gacc[q];
     }
-    if (tid < 12) sh.rn.xj[tid] = a.nd.x[(size_t)j * 12 + tid];
     __syncthreads();
     for (int t = tid; t < nslots * 144; t += kLpThreads) {
         float v = sh.acc[0][t];
@@ -721,14 +737,14 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
         sh.acc[0][t] = v;
     }
     if (tid < 12) {
-        float v = sh.gw[0][tid];
+        double v = sh.gw[0][tid];
 #pragma unroll
         for (int w = 1; w < kLpWaves; ++w) v += sh.gw[w][tid];
         sh.rn.gd[tid] = v;
     }
     __syncthreads();
     auto data = [&](int sl, int R, int C) { return sh.acc[0][sl * 144 + R * 12 + C]; };
-    row_finalize<kLpThreads>(a, s, sh.rn, j, rb, nslots, gjx, gjy, gjz, data, rr_out);
+    row_finalize<kLpThreads>(a, s, sh.rn, j, rb, nslots, e_reg, data, rr_out);
 }
 
 hipError_t launch_assemble_lp(const StepArgs &a, const StepScratch &s, int precision, float *rr_out,
@@ -869,13 +885,13 @@ hipError_t launch_axpy(float *y, const float *x, int count, hipStream_t st) {
 
 // E_rot of node j (Eq.(5)) and E_reg over its outgoing edges (Eq.(6)), float64
 // sums of float32 residuals in the assembly's order; one thread per node.
-__global__ void __launch_bounds__(256) node_energy_kernel(StepArgs a, StepScratch s) {
-    const int j = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void node_energy_body(const StepArgs &a, const StepScratch &s, int blk) {
+    const int j = blk * 256 + threadIdx.x;
     if (j >= a.nd.m) return;
     const float *xj = a.nd.x + (size_t)j * 12;
     auto dot = [](const float *u, const float *v) { return fmaf(u[2], v[2], fmaf(u[1], v[1], u[0] * v[0])); };
     const float rr[6] = {dot(xj, xj + 3), dot(xj, xj + 6), dot(xj + 3, xj + 6),
-                         dot(xj, xj) - 1.f, dot(xj + 3, xj + 3) - 1.f, dot(xj + 6, xj + 6) - 1.f};
+                         unit_residual(xj, 0), unit_residual(xj + 3, 1), unit_residual(xj + 6, 2)};
     double erot = 0.0;
     for (int q = 0; q < 6; ++q) erot += (double)rr[q] * rr[q];
     const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
@@ -887,13 +903,16 @@ __global__ void __launch_bounds__(256) node_energy_kernel(StepArgs a, StepScratc
         const float glx = a.nd.gx[l], gly = a.nd.gy[l], glz = a.nd.gz[l];
         const float *xl = a.nd.x + (size_t)l * 12;
         const float ex = glx - gjx, ey = gly - gjy, ez = glz - gjz;
-        const float r0 = fmaf(xj[6], ez, fmaf(xj[3], ey, xj[0] * ex)) + gjx + xj[9] - glx - xl[9];
-        const float r1 = fmaf(xj[7], ez, fmaf(xj[4], ey, xj[1] * ex)) + gjy + xj[10] - gly - xl[10];
-        const float r2 = fmaf(xj[8], ez, fmaf(xj[5], ey, xj[2] * ex)) + gjz + xj[11] - glz - xl[11];
+        float r0, r1, r2;
+        reg_residual(xj, xl, ex, ey, ez, r0, r1, r2);
         ereg += ((double)r0 * r0 + (double)r1 * r1) + (double)r2 * r2;
     }
     s.node_part[2 * j + 0] = erot;
     s.node_part[2 * j + 1] = ereg;
+}
+
+__global__ void __launch_bounds__(256) node_energy_kernel(StepArgs a, StepScratch s) {
+    node_energy_body(a, s, blockIdx.x);
 }
 
 hipError_t launch_node_energy(const StepArgs &a, const StepScratch &s, hipStream_t st) {
@@ -997,26 +1016,35 @@ hipError_t launch_energy_total(const misslam_report *rep, float w_data, float w_
 
 // ---------------------------------------------------------------- energy report
 
-__global__ void __launch_bounds__(256) energy_report_kernel(const double *__restrict__ pt_part, int npb,
-                                                            const double *__restrict__ node_part, int m,
-                                                            misslam_report *rep, float reject_thr) {
-    __shared__ double red[256];
-    double a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0;
+__device__ __forceinline__ void energy_report_body(const double *__restrict__ pt_part, int npb,
+                                                   const double *__restrict__ node_part, int m, misslam_report *rep,
+                                                   float reject_thr, unsigned *__restrict__ zero_words) {
+    __shared__ double red[5][256 / kWave];
+    if (zero_words && threadIdx.x < 64) zero_words[threadIdx.x] = 0u;   // the next solve's grid barrier
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int t = threadIdx.x; t < npb; t += 256) {
-        a0 += pt_part[3 * t];
-        a1 += pt_part[3 * t + 1];
-        a2 += pt_part[3 * t + 2];
+        v[0] += pt_part[3 * t];
+        v[1] += pt_part[3 * t + 1];
+        v[2] += pt_part[3 * t + 2];
     }
     for (int t = threadIdx.x; t < m; t += 256) {
-        b0 += node_part[2 * t];
-        b1 += node_part[2 * t + 1];
+        v[3] += node_part[2 * t];
+        v[4] += node_part[2 * t + 1];
     }
-    const double ed = block_sum<256>(a0, red);
-    const double nv = block_sum<256>(a1, red);
-    const double sa = block_sum<256>(a2, red);
-    const double er = block_sum<256>(b0, red);
-    const double eg = block_sum<256>(b1, red);
+    // wave butterflies, then the four waves in order: a fixed summation order
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        double t = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (lane == 0) red[q][wave] = t;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        double tot[5];
+        for (int q = 0; q < 5; ++q) tot[q] = ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
+        const double ed = tot[0], nv = tot[1], sa = tot[2], er = tot[3], eg = tot[4];
         rep->e_data = ed;
         rep->e_rot = er;
         rep->e_reg = eg;
@@ -1026,6 +1054,13 @@ __global__ void __launch_bounds__(256) energy_report_kernel(const double *__rest
         if (reject_thr > 0.f && nv > 0 && sa / nv > (double)reject_thr) flags |= MISSLAM_FLAG_FRAME_REJECT;
         rep->flags |= flags;
     }
+}
+
+__global__ void __launch_bounds__(256) energy_report_kernel(const double *__restrict__ pt_part, int npb,
+                                                            const double *__restrict__ node_part, int m,
+                                                            misslam_report *rep, float reject_thr,
+                                                            unsigned *__restrict__ zero_words) {
+    energy_report_body(pt_part, npb, node_part, m, rep, reject_thr, zero_words);
 }
 
 hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_t st) {
@@ -1057,16 +1092,103 @@ hipError_t launch_assemble(const StepArgs &a, const StepScratch &s, hipStream_t 
 }
 
 hipError_t launch_energy_report(const StepScratch &s, int64_t n, int m, misslam_report *rep, float reject_thr,
-                                hipStream_t st) {
+                                hipStream_t st, unsigned *zero_words) {
     const int npb = (int)nblk(n > 0 ? n : 1, kPtBlock);
     hipLaunchKernelGGL(energy_report_kernel, dim3(1), dim3(256), 0, st, s.pt_part, npb, s.node_part, m, rep,
-                       reject_thr);
+                       reject_thr, zero_words);
     return hipGetLastError();
 }
 
 __global__ void copy_i32_kernel(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------- batched launches
+
+__device__ __forceinline__ int batch_of(const BatchItem *items, int count, int64_t blk, int which) {
+    int b = count - 1;
+    while (b > 0) {
+        const int64_t start = which == 0 ? items[b].pp0 : which == 1 ? items[b].row0 : items[b].ne0;
+        if (start <= blk) break;
+        --b;
+    }
+    return b;
+}
+
+template <int K>
+__global__ void __launch_bounds__(kPtBlock) point_pass_batched_kernel(const BatchItem *__restrict__ items, int count) {
+    const BatchItem &it = items[batch_of(items, count, blockIdx.x, 0)];
+    point_pass_body<K>(it.a, it.s, (int64_t)blockIdx.x - it.pp0);
+}
+
+template <int K>
+__global__ void __launch_bounds__(kAsmThreads) assemble_batched_kernel(const BatchItem *__restrict__ items, int count,
+                                                                       int gi) {
+    const BatchItem &it = items[batch_of(items, count, blockIdx.x, 1)];
+    StepArgs a = it.a;
+    a.flags = &it.rep[gi].flags;
+    assemble_rows_body<K>(a, it.s, (int)blockIdx.x - it.row0);
+}
+
+__global__ void __launch_bounds__(256) node_energy_batched_kernel(const BatchItem *__restrict__ items, int count) {
+    const BatchItem &it = items[batch_of(items, count, blockIdx.x, 2)];
+    node_energy_body(it.a, it.s, (int)blockIdx.x - it.ne0);
+}
+
+// One workgroup per problem.
+__global__ void __launch_bounds__(256) energy_report_batched_kernel(const BatchItem *__restrict__ items, int gi,
+                                                                    unsigned *__restrict__ zero_words) {
+    const BatchItem &it = items[blockIdx.x];
+    energy_report_body(it.s.pt_part, it.npb, it.s.node_part, it.a.nd.m, it.rep + gi, it.reject,
+                       blockIdx.x == 0 ? zero_words : nullptr);
+}
+
+hipError_t launch_point_pass_batched(const BatchItem *items, int count, int k, int64_t total_blocks, int it,
+                                     hipStream_t st) {
+    (void)it;
+    if (total_blocks <= 0) return hipSuccess;
+    switch (k) {
+#define MSL_PB_CASE(KK)                                                                                          \
+    case KK:                                                                                                     \
+        hipLaunchKernelGGL((point_pass_batched_kernel<KK>), dim3((unsigned)total_blocks), dim3(kPtBlock), 0, st, \
+                           items, count);                                                                        \
+        break;
+        MSL_PB_CASE(1) MSL_PB_CASE(2) MSL_PB_CASE(3) MSL_PB_CASE(4)
+        MSL_PB_CASE(5) MSL_PB_CASE(6) MSL_PB_CASE(7) MSL_PB_CASE(8)
+#undef MSL_PB_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_batched(const BatchItem *items, int count, int k, int total_rows, int it, hipStream_t st) {
+    if (total_rows <= 0) return hipSuccess;
+    switch (k) {
+#define MSL_AB_CASE(KK)                                                                                        \
+    case KK:                                                                                                   \
+        hipLaunchKernelGGL((assemble_batched_kernel<KK>), dim3(total_rows), dim3(kAsmThreads), 0, st, items, \
+                           count, it);                                                                         \
+        break;
+        MSL_AB_CASE(1) MSL_AB_CASE(2) MSL_AB_CASE(3) MSL_AB_CASE(4)
+        MSL_AB_CASE(5) MSL_AB_CASE(6) MSL_AB_CASE(7) MSL_AB_CASE(8)
+#undef MSL_AB_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_report_batched(const BatchItem *items, int count, int it, unsigned *zero_words,
+                                        hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(energy_report_batched_kernel, dim3(count), dim3(256), 0, st, items, it, zero_words);
+    return hipGetLastError();
+}
+
+hipError_t launch_node_energy_batched(const BatchItem *items, int count, int total_blocks, hipStream_t st) {
+    if (total_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(node_energy_batched_kernel, dim3(total_blocks), dim3(256), 0, st, items, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t st) {

@@ -36,6 +36,8 @@ def test_empty_depth_regularisers_only(lib):
     r = s.M.read_report(rep)
     assert np.all(r["n_valid"] == 0) and np.all(r["e_data"] == 0)
     xo, orep = oracle.gn_register(s.problem(), graph=s.oracle_graph_from_gpu(), x0=x0.astype(np.float64))
+    print("delta rel", rel_err(x.cpu().numpy() - x0, xo - x0), "e_rot", r[-1]["e_rot"], orep["final"]["e_rot"],
+          "e_reg", r[-1]["e_reg"], orep["final"]["e_reg"])
     assert rel_err(x.cpu().numpy() - x0, xo - x0) < 1e-4
     assert r[-1]["e_reg"] == pytest.approx(orep["final"]["e_reg"], rel=1e-4, abs=1e-8)
     assert r[-1]["e_rot"] == pytest.approx(orep["final"]["e_rot"], rel=1e-4, abs=1e-8)
@@ -49,8 +51,10 @@ def test_ragged_sizes_end_to_end(lib):
     nnzb = int(s.graph.info.cpu().numpy()[0])
     assert np.array_equal(s.graph.col_idx.cpu().numpy()[:nnzb], ref["col_idx"])
     x = s.M.identity_params(s.m)
+    xi = oracle.identity_params(s.m)
     rep, ch = s.M.gn_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, s.params, s.ws, corr_hist=True)
     xo, orep = oracle.gn_register(s.problem(), graph=s.oracle_graph_from_gpu(), corr_sequence=list(ch.cpu().numpy()))
+    print("x rel", rel_err(x.cpu().numpy(), xo), "delta rel", rel_err(x.cpu().numpy() - xi, xo - xi))
     assert rel_err(x.cpu().numpy(), xo) < 1e-5
     r = s.M.read_report(rep)
     assert r[-1]["e_data"] == pytest.approx(orep["final"]["e_data"], rel=1e-4)

@@ -171,8 +171,9 @@ def test_gn_register_c1(lib, c1):
     assert np.array_equal(cs[0], rep_indep["iters"][0]["corr"])
     xo, orep = oracle.gn_register(pb, graph=og, corr_sequence=cs)
     xg = x.cpu().numpy().astype(np.float64)
-    assert rel_err(xg, xo) < 1e-4
     x0 = oracle.identity_params(s.m)
+    print("c1 x rel", rel_err(xg, xo), "delta rel", rel_err(xg - x0, xo - x0))
+    assert rel_err(xg, xo) < 1e-4
     assert rel_err(xg - x0, xo - x0) < 1e-3
     for it in range(pb.gn_iters):
         assert r[it]["e_data"] == pytest.approx(orep["iters"][it]["e_data"], rel=1e-4)
