@@ -63,6 +63,7 @@ typedef enum {
 #define MISSLAM_MAX_PCG  64
 #define MISSLAM_MAX_ROW  32       /* max blocks per row of the normal matrix (node degree + 1) */
 #define MISSLAM_MAX_LIST 2048     /* max points influenced by one node */
+#define MISSLAM_SOLVE_ROWS 16     /* node rows per workgroup of the one-launch PCG of a single problem */
 
 /* (host) pinhole camera of the depth map: pixel (u, v) = (fx x/z + cx, fy y/z + cy) */
 typedef struct { int32_t width, height; float fx, fy, cx, cy; } misslam_camera;
@@ -294,9 +295,9 @@ misslam_status misslam_energy_vjp(const misslam_points *points, const misslam_no
  * problems, and the whole frame is captured once into a hipGraph and
  * replayed by every later call.  Each problem's arithmetic, partition and
  * reduction order are those of misslam_gn_register with the same workgroup
- * tile, so with rows_per_wg = 21 every result is bitwise that of calling
- * misslam_gn_register once per problem; another tile changes only the
- * rounding order of the PCG reductions.
+ * tile, so with rows_per_wg = MISSLAM_SOLVE_ROWS every result is bitwise that
+ * of calling misslam_gn_register once per problem; another tile changes only
+ * the rounding order of the PCG reductions.
  *
  * misslam_problem: host structs holding device pointers, copied at
  *   creation; the pointed-to buffers (points, nodes and their params, graph,

@@ -10,9 +10,10 @@ LIB_PATH = os.path.join(HERE, "libmisslam.so")
 
 OK, EINVAL, ESHAPE, EWORKSPACE, EHIP, ECAPACITY, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FLAG_NONSPD_BLOCK, FLAG_PCG_BREAKDOWN, FLAG_NONFINITE, FLAG_FRAME_REJECT, FLAG_GRAPH_OVERFLOW = 1, 2, 4, 8, 16
+FLAG_SYNC_TIMEOUT = 32
 WEIGHT_GAUSS, WEIGHT_LINEAR = 0, 1
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
-MAX_K, MAX_PCG, MAX_ROW, MAX_LIST = 8, 64, 32, 2048
+MAX_K, MAX_PCG, MAX_ROW, MAX_LIST, SOLVE_ROWS = 8, 64, 32, 2048, 16
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
 c_int32_p = ctypes.POINTER(ctypes.c_int32)
@@ -67,6 +68,11 @@ class FuseParams(ctypes.Structure):
                 ("frame", ctypes.c_int32)]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("points", Points), ("nodes", Nodes), ("graph", Graph), ("depth", ctypes.c_void_p),
+                ("camera", Camera), ("pose", Pose), ("report", ctypes.c_void_p)]
+
+
 P = ctypes.POINTER
 vp = ctypes.c_void_p
 st = ctypes.c_int32
@@ -90,6 +96,11 @@ SIGNATURES = {
                           ctypes.c_size_t, vp]),
     "misslam_energy_vjp": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params), vp, vp, vp, vp,
                                 vp, vp, vp, vp, ctypes.c_size_t, vp]),
+    "misslam_batch_create": (st, [P(Problem), ctypes.c_int32, P(Params), ctypes.c_int32, P(vp)]),
+    "misslam_batch_workspace_bytes": (ctypes.c_size_t, [vp]),
+    "misslam_batch_register": (st, [vp, vp, ctypes.c_size_t, vp]),
+    "misslam_batch_tile": (ctypes.c_int32, [vp]),
+    "misslam_batch_destroy": (None, [vp]),
     "misslam_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "misslam_profile_get": (st, [ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int64)]),
     "misslam_profile_reset": (None, []),

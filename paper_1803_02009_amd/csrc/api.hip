@@ -146,7 +146,7 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
     L.pcg.q = c.take<float>((size_t)12 * m);
     L.pcg.part = c.take<double>((size_t)(pcg_iters + 2) * 4 * nblk_max);
     L.pcg.status = c.take<int32_t>((size_t)2 * (pcg_iters + 2));
-    L.pcg.bar = c.take<unsigned>(64);
+    L.pcg.bar = c.take<unsigned>(msl::MSL_BAR_WORDS);
     L.pcg.nblk = nblk;
     L.pcg.nblk_max = nblk_max;
     L.graph.tmp = c.take<int32_t>((size_t)m * MISSLAM_MAX_ROW);
@@ -608,16 +608,16 @@ struct misslam_batch {
     int64_t total_pp = 0;
     int total_nm = 0, total_rows = 0, total_ne = 0, total_wgs = 0;
     unsigned *bar = nullptr;
+    hipStream_t cap = nullptr;  // capture stream (the caller's may be the null stream, which cannot capture)
     hipGraphExec_t exec = nullptr;
     void *exec_ws = nullptr;
-    hipStream_t exec_stream = nullptr;
     int exec_rows = 0;
 };
 
 namespace {
 
 size_t batch_bytes(const misslam_batch *b) {
-    size_t off = align_up(64 * sizeof(unsigned));
+    size_t off = align_up(msl::MSL_BAR_WORDS * sizeof(unsigned));
     for (const auto &p : b->probs)
         off += align_up(carve(nullptr, p.points.n, p.nodes.m, p.camera.width, p.camera.height, b->params.pcg_iters).bytes);
     return off;
@@ -627,7 +627,7 @@ size_t batch_bytes(const misslam_batch *b) {
 void batch_items(misslam_batch *b, void *ws, int rows) {
     char *base = static_cast<char *>(ws);
     b->bar = reinterpret_cast<unsigned *>(base);
-    size_t off = align_up(64 * sizeof(unsigned));
+    size_t off = align_up(msl::MSL_BAR_WORDS * sizeof(unsigned));
     b->items.assign(b->count, msl::BatchItem{});
     int64_t pp = 0;
     int nm = 0, row = 0, ne = 0, wg = 0;
@@ -668,9 +668,9 @@ void batch_items(misslam_batch *b, void *ws, int rows) {
         it.depth = p.depth;
         it.reject = b->params.reject_threshold;
         const int64_t n = p.points.n;
-        it.npb = (int)((n > 0 ? n + 255 : 256) / 256);
+        it.npb = (int)((n > 0 ? n + 255 : 256) / 256);   // as the single call: one block even for no points
         it.pp0 = pp;
-        pp += (n + 255) / 256;
+        pp += it.npb;
         it.nm0 = nm;
         nm += (int)(((int64_t)p.camera.width * p.camera.height + 255) / 256);
         it.row0 = row;
@@ -785,6 +785,7 @@ misslam_status misslam_batch_create(const misslam_problem *problems, int32_t cou
     }
     hipError_t e = hipMalloc(&b->d_items, sizeof(msl::BatchItem) * count);
     if (e == hipSuccess) e = hipMalloc(&b->d_backup, sizeof(float) * (poff > 0 ? poff : 1));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         misslam_batch_destroy(b);
         return hip_fail(e);
@@ -813,7 +814,7 @@ misslam_status misslam_batch_register(misslam_batch *b, void *ws, size_t ws_byte
             e = batch_save_params(b, st, false);
             float best = -1.f;
             int best_rows = 0;
-            const int cand[4] = {21, 14, 10, 7};
+            const int cand[4] = {21, 16, 12, 8};
             for (int c = 0; c < 4 && e == hipSuccess; ++c) {
                 const float ms = batch_try(b, ws, cand[c], st);
                 if (ms > 0.f && (best < 0.f || ms < best)) {
@@ -831,19 +832,19 @@ misslam_status misslam_batch_register(misslam_batch *b, void *ws, size_t ws_byte
         if (e == hipSuccess) e = batch_upload(b, ws, b->rows);
         if (e != hipSuccess) return hip_fail(e);
     }
-    if (!b->exec || b->exec_ws != ws || b->exec_stream != st || b->exec_rows != b->rows) {
+    if (!b->exec || b->exec_ws != ws || b->exec_rows != b->rows) {
         if (b->exec) {
             (void)hipGraphExecDestroy(b->exec);
             b->exec = nullptr;
         }
+        e = hipStreamSynchronize(st);
         hipGraph_t g = nullptr;
-        e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-        hipError_t ee = hipSuccess;
+        if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            ee = batch_enqueue(b, st, false);
-            e = hipStreamEndCapture(st, &g);
+            const hipError_t ee = batch_enqueue(b, b->cap, true);
+            e = hipStreamEndCapture(b->cap, &g);
+            if (ee != hipSuccess) e = ee;
         }
-        if (ee != hipSuccess) e = ee;
         if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
         if (g) (void)hipGraphDestroy(g);
         if (e != hipSuccess) {
@@ -851,7 +852,6 @@ misslam_status misslam_batch_register(misslam_batch *b, void *ws, size_t ws_byte
             return e == hipErrorInvalidConfiguration ? MISSLAM_EUNSUPPORTED : hip_fail(e);
         }
         b->exec_ws = ws;
-        b->exec_stream = st;
         b->exec_rows = b->rows;
     }
     e = hipGraphLaunch(b->exec, st);
@@ -861,6 +861,7 @@ misslam_status misslam_batch_register(misslam_batch *b, void *ws, size_t ws_byte
 void misslam_batch_destroy(misslam_batch *b) {
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->d_items) (void)hipFree(b->d_items);
     if (b->d_backup) (void)hipFree(b->d_backup);
     delete b;

@@ -14,6 +14,9 @@ struct GraphView {
     int32_t *info;
 };
 
+// Words of a persistent solve's grid barrier (group counters, top counter, generation).
+constexpr int MSL_BAR_WORDS = 512;
+
 // Uniform grid of the nodes for the kNN search.
 constexpr int MSL_GRID_CELLS = 1 << 18;
 struct GridView {
@@ -46,7 +49,7 @@ struct PcgScratch {
     int32_t *status;       // 2 x (pcg_iters + 2): stop status, then per-iteration "updated" flags
     int nblk;              // workgroups of the multi-kernel path
     int nblk_max;          // partial slots per reduction (>= every path's workgroup count)
-    unsigned *bar;         // 64 words: grid barrier of the persistent solve
+    unsigned *bar;         // MSL_BAR_WORDS words: grid barrier of the persistent solve
 };
 
 hipError_t launch_normal_map(const float *depth, const Cam &cam, float4 *out, hipStream_t st);
@@ -139,7 +142,7 @@ hipError_t launch_vjp_points(const StepArgs &a, const StepScratch &s, float sigm
 hipError_t launch_grad_params(const float *g, int m, const float *grad_e, float *out, hipStream_t st);
 hipError_t launch_energy_total(const misslam_report *rep, float w_data, float w_rot, float w_reg, double *out,
                                hipStream_t st);
-// zero_words (optional): 64 words cleared on the way (the persistent solve's barrier)
+// zero_words (optional): MSL_BAR_WORDS words cleared on the way (the persistent solve's barrier)
 hipError_t launch_energy_report(const StepScratch &s, int64_t n, int m, misslam_report *rep, float reject_thr,
                                 hipStream_t st, unsigned *zero_words = nullptr);
 hipError_t launch_bjacobi(const GraphView &g, int m, const float *blocks, float lambda, float *minv,

@@ -326,29 +326,46 @@ __device__ __forceinline__ double ld_dev(const double *p) {
     return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier: bar[0] counts arrivals, bar[32] is the generation.  Each
-// wave first waits until its own device-scope stores are acknowledged, so
-// they are visible once the arrival is.  The wait is bounded: a workgroup
-// that gives up (which a cooperative launch, where every workgroup is
-// resident, never causes) stops waiting at later barriers and reports it.
+// Grid barrier over nblocks workgroups (participant id in [0, nblocks)).
+// Arrivals are counted in 8 group counters (id % 8, one 128-byte line each,
+// so they do not serialise on one address); the last arrival of a group
+// counts its group in a top counter, whose last arrival bumps the
+// generation that the others poll.  Layout in words: group g at 32 g, top at
+// 256, generation at 288.  Each wave first waits until its own device-scope
+// stores are acknowledged, so they are visible once the arrival is.  The
+// wait is bounded: a workgroup that gives up (which a launch whose
+// workgroups are all resident never causes) stops waiting at later barriers
+// and the solve reports it.
 constexpr unsigned kSpinLimit = 1u << 18;
 
-__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nblocks, bool &broken) {
+__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nblocks, unsigned id, bool &broken) {
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     __shared__ int give_up;
     if (threadIdx.x == 0) {
         give_up = broken ? 1 : 0;
-        const unsigned g0 = __hip_atomic_load(&bar[32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned a = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (a == nblocks - 1) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned *top = bar + 256, *gen = bar + 288;
+        const unsigned g = id % 8u;
+        const unsigned ngroups = nblocks < 8u ? nblocks : 8u;
+        const unsigned gsize = (nblocks - g + 7u) / 8u;
+        const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bool released = false;
+        const unsigned a = __hip_atomic_fetch_add(bar + 32 * g, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == gsize - 1) {
+            __hip_atomic_store(bar + 32 * g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_s_waitcnt(0);
-            __hip_atomic_fetch_add(&bar[32], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else if (!broken) {
+            const unsigned t = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == ngroups - 1) {
+                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_s_waitcnt(0);
+                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                released = true;
+            }
+        }
+        if (!released && !broken) {
             unsigned spins = 0;
-            while (__hip_atomic_load(&bar[32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
                 if (++spins > kSpinLimit) {
                     give_up = 1;
                     break;
@@ -393,33 +410,130 @@ __device__ __forceinline__ double gather_dev(const double *part, int G, double (
     return v[0];
 }
 
+constexpr int kMaxBlocksWg = kRowsPerBlk * MISSLAM_MAX_ROW;   // blocks of one workgroup's rows
+constexpr int kMaxUnique = 256;                                // distinct columns staged per iteration
+constexpr int kZPer = (kMaxUnique * 6 + kPcgThreads - 1) / kPcgThreads;
+
+__device__ __forceinline__ unsigned long long ld_dev64(const float *p) {
+    return __hip_atomic_load(reinterpret_cast<unsigned long long *>(const_cast<float *>(p)), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // One workgroup's share of the solve: workgroup wg of the G that own this
 // system's rows; the barrier counts nbar workgroups (G, or every workgroup of
-// a batch of systems solved side by side).
+// a batch of systems solved side by side) and this one is participant bar_id.
+// The columns of the workgroup's blocks are reduced to their distinct nodes
+// once; each iteration stages z of those nodes in LDS (8-byte device-scope
+// loads, issued together with the loads of the next reduction's partials).
 __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_per_wg, int cache_blocks, unsigned *bar,
-                                                    unsigned nbar, int wg, int G, misslam_report *rep,
-                                                    float *params) {
+                                                    unsigned nbar, unsigned bar_id, int wg, int G,
+                                                    misslam_report *rep, float *params) {
     extern __shared__ float dyn[];
     __shared__ double red[3][kPcgThreads / kWave];
     __shared__ float vx[kRowsPerBlk * 12], vr[kRowsPerBlk * 12], vp[kRowsPerBlk * 12], vq[kRowsPerBlk * 12];
+    __shared__ int bmap[kMaxBlocksWg];                 // block -> distinct-column slot (-1: beyond the cap)
+    __shared__ int colL[kMaxBlocksWg];
+    __shared__ int scan_w[kPcgThreads / kWave];
+    __shared__ int ucol[kMaxUnique];
+    __shared__ float zc[kMaxUnique * 12];
+    __shared__ int cnt_u;
     const int r0 = min(A.m, wg * rows_per_wg);
     const int r1 = min(A.m, r0 + rows_per_wg);
     const int b0 = min(A.row_ptr[r0], A.cap), b1 = min(A.row_ptr[r1], A.cap);
-    const int nb = b1 - b0;                            // blocks of this workgroup's rows
+    const int nb = min(b1 - b0, kMaxBlocksWg);         // blocks of this workgroup's rows
     const int cached = min(nb, cache_blocks);
     float *hc = dyn;                                   // cached blocks
     float *mc = hc + (size_t)cache_blocks * 144;       // preconditioner blocks of the rows
-    float *zc = mc + (size_t)kRowsPerBlk * 144;        // z of every block's column, per iteration
-    int *cc = reinterpret_cast<int *>(zc + (size_t)cache_blocks * 12);   // column of every cached-z block
     for (int t = threadIdx.x; t < cached * 144; t += kPcgThreads) hc[t] = A.blocks[(size_t)b0 * 144 + t];
     for (int t = threadIdx.x; t < (r1 - r0) * 144; t += kPcgThreads) mc[t] = A.minv[(size_t)r0 * 144 + t];
-    for (int t = threadIdx.x; t < cached; t += kPcgThreads) cc[t] = A.col_idx[b0 + t];
+    // distinct columns: a block whose column appears at no earlier block of the workgroup gets the next
+    // slot (in block order, by a workgroup scan); later blocks of that column share it
+    for (int t = threadIdx.x; t < nb; t += kPcgThreads) colL[t] = A.col_idx[b0 + t];
+    __syncthreads();
+    constexpr int kPerT = (kMaxBlocksWg + kPcgThreads - 1) / kPcgThreads;   // entries per thread in the scan
+    int firstpos[kPerT];
+    int nfirst = 0;
+#pragma unroll
+    for (int e = 0; e < kPerT; ++e) {
+        const int t = threadIdx.x * kPerT + e;
+        firstpos[e] = -1;
+        if (t < nb) {
+            const int c = colL[t];
+            int f = t;
+            for (int u = 0; u < t; ++u)
+                if (colL[u] == c) {
+                    f = u;
+                    break;
+                }
+            firstpos[e] = f;
+            nfirst += f == t;
+        }
+    }
+    // exclusive scan of nfirst over the workgroup: wave scans, then the waves in order
+    {
+        const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+        int incl = nfirst;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int v = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += v;
+        }
+        if (lane == kWave - 1) scan_w[wave] = incl;
+        __syncthreads();
+        int base = 0;
+        for (int w = 0; w < wave; ++w) base += scan_w[w];
+        int slot = base + incl - nfirst;
+#pragma unroll
+        for (int e = 0; e < kPerT; ++e) {
+            const int t = threadIdx.x * kPerT + e;
+            if (t < nb && firstpos[e] == t) {
+                const int sl = slot < kMaxUnique ? slot : -1;
+                if (sl >= 0) ucol[sl] = colL[t];
+                bmap[t] = sl;
+                ++slot;
+            }
+        }
+        if (threadIdx.x == kPcgThreads - 1) {
+            int tot = 0;
+            for (int w = 0; w < kPcgThreads / kWave; ++w) tot += scan_w[w];
+            cnt_u = tot < kMaxUnique ? tot : kMaxUnique;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kPerT; ++e) {
+        const int t = threadIdx.x * kPerT + e;
+        if (t < nb && firstpos[e] != t) bmap[t] = bmap[firstpos[e]];   // a first occurrence: already set
+    }
+    __syncthreads();
+    const int U = cnt_u;
     const int lr = threadIdx.x / 12, a = threadIdx.x % 12;
     const int j = r0 + lr;
     const bool act = lr < kRowsPerBlk && j < r1;
     const int li = lr * 12 + a;
     bool broken = false;
-    __syncthreads();
+
+    // stage z of the distinct columns and read one reduction's partials, all loads in flight together
+    auto stage = [&](const double *part) {
+        unsigned long long zv[kZPer];
+#pragma unroll
+        for (int e = 0; e < kZPer; ++e) {
+            const int t = threadIdx.x + e * kPcgThreads;
+            if (t < U * 6) zv[e] = ld_dev64(A.z + (size_t)ucol[t / 6] * 12 + 2 * (t % 6));
+        }
+        double v[1] = {0.0};
+        for (int t = threadIdx.x; t < G; t += kPcgThreads) v[0] += ld_dev(part + t);
+#pragma unroll
+        for (int e = 0; e < kZPer; ++e) {
+            const int t = threadIdx.x + e * kPcgThreads;
+            if (t < U * 6) {
+                zc[(t / 6) * 12 + 2 * (t % 6)] = __uint_as_float((unsigned)(zv[e] & 0xFFFFFFFFull));
+                zc[(t / 6) * 12 + 2 * (t % 6) + 1] = __uint_as_float((unsigned)(zv[e] >> 32));
+            }
+        }
+        wg_sum<1>(v, red);                             // also orders the zc writes before their reads
+        return v[0];
+    };
 
     // init: r = -g, z = M r, x = 0
     float r = 0.f, z = 0.f;
@@ -445,19 +559,13 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
             st_dev(A.part + (size_t)(0 * 4 + 1) * G + wg, v[1]);
         }
     }
-    grid_barrier(bar, nbar, broken);
+    grid_barrier(bar, nbar, bar_id, broken);
     bool stopped = false;
     int done = 0;
     double rz_prev = 1.0;
-    double rz = gather_dev(A.part + (size_t)(0 * 4 + 0) * G, G, red);
+    double rz = stage(A.part + (size_t)(0 * 4 + 0) * G);
     for (int it = 0; it < A.iters; ++it) {
         const bool skip = stopped || rz == 0.0;
-        // ---- z of the blocks' columns into LDS
-        if (!skip) {
-            for (int t = threadIdx.x; t < cached * 12; t += kPcgThreads)
-                zc[t] = ld_dev(A.z + (size_t)cc[t / 12] * 12 + t % 12);
-            __syncthreads();
-        }
         // ---- direction and product: p = z + beta p, q = (H + lambda I) z + beta q
         double pq = 0.0;
         if (act && !skip) {
@@ -466,13 +574,13 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
             const int p0 = A.row_ptr[j], p1 = min(A.row_ptr[j + 1], A.cap);
             for (int pb = p0; pb < p1; ++pb) {
                 const int q = pb - b0;
-                if (q < cached) {
-                    const float *B = hc + (size_t)q * 144 + a * 12;
-                    const float *zl = zc + (size_t)q * 12;
+                const int slot = q < nb ? bmap[q] : -1;
+                const float *B = q < cached ? hc + (size_t)q * 144 + a * 12 : A.blocks + (size_t)pb * 144 + a * 12;
+                if (slot >= 0) {
+                    const float *zl = zc + slot * 12;
 #pragma unroll
                     for (int b = 0; b < 12; ++b) az = fma((double)B[b], (double)zl[b], az);
                 } else {
-                    const float *B = A.blocks + (size_t)pb * 144 + a * 12;
                     const float *zl = A.z + (size_t)A.col_idx[pb] * 12;
 #pragma unroll
                     for (int b = 0; b < 12; ++b) az = fma((double)B[b], (double)ld_dev(zl + b), az);
@@ -490,7 +598,7 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
             wg_sum<1>(v, red);
             if (threadIdx.x == 0) st_dev(A.part + (size_t)(it * 4 + 2) * G + wg, v[0]);
         }
-        grid_barrier(bar, nbar, broken);
+        grid_barrier(bar, nbar, bar_id, broken);
         // ---- step: alpha = r.z / p.q, x += alpha p, r -= alpha q, z = M r
         const double pqs = gather_dev(A.part + (size_t)(it * 4 + 2) * G, G, red);
         const bool brk = !skip && !(pqs > 0.0);
@@ -523,10 +631,10 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
         if (upd) ++done;
         if (brk) stopped = true;
         if (!skip) rz_prev = rz;
-        grid_barrier(bar, nbar, broken);
-        rz = gather_dev(A.part + (size_t)((it + 1) * 4 + 0) * G, G, red);
+        grid_barrier(bar, nbar, bar_id, broken);
+        rz = stage(A.part + (size_t)((it + 1) * 4 + 0) * G);
     }
-    // ---- finish: report (block 0), x out, params += x unless non-finite
+    // ---- finish: report (first workgroup), x out, params += x unless non-finite
     const double nbad = A.iters > 0 ? gather_dev(A.part + (size_t)(A.iters * 4 + 3) * G, G, red) : 0.0;
     if (act) {
         A.x[(size_t)j * 12 + a] = vx[li];
@@ -551,13 +659,15 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
 __global__ void __launch_bounds__(kPcgThreads) pcg_persistent_kernel(PcgArgs A, int rows_per_wg, int cache_blocks,
                                                                     unsigned *bar, misslam_report *rep,
                                                                     float *params) {
-    pcg_persistent_body(A, rows_per_wg, cache_blocks, bar, gridDim.x, blockIdx.x, gridDim.x, rep, params);
+    pcg_persistent_body(A, rows_per_wg, cache_blocks, bar, gridDim.x, blockIdx.x, blockIdx.x, gridDim.x, rep, params);
 }
 
 // Grid shape of the persistent solve for m rows on this device, or 0 when a
 // cooperative launch cannot hold it (the multi-kernel path is used then).
-// Rows are packed kRowsPerBlk to a workgroup: fewer workgroups make the
-// barriers cheaper, and one workgroup per CU must hold them all.
+// Rows are packed MISSLAM_SOLVE_ROWS to a workgroup: fewer workgroups make
+// the barriers cheaper, while the blocks of that many rows (about 13 per row
+// on a surface graph) still fit the LDS left beside the static arrays, and
+// one workgroup per CU must hold them all.
 static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes) {
     static int max_blocks = -1, max_lds = 0;
     if (max_blocks < 0) {
@@ -584,7 +694,7 @@ static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes) {
         }
     }
     if (max_blocks <= 0 || m <= 0) return 0;
-    rows_per_wg = kRowsPerBlk;
+    rows_per_wg = MISSLAM_SOLVE_ROWS;
     const int G = (m + rows_per_wg - 1) / rows_per_wg;
     if (G > max_blocks) return 0;
     lds_bytes = max_lds;
@@ -617,11 +727,12 @@ hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks,
     A.part = s.part;
     A.status = s.status;
     A.done = s.status + (iters + 2);
-    // LDS: cached blocks (144 floats), their z (12 floats) and column (1 int); the rows' preconditioner
-    const int cache_blocks = (lds / 4 - kRowsPerBlk * 144) / (144 + 12 + 1);
+    // dynamic LDS: cached blocks (144 floats each) and the rows' preconditioner
+    const int cache_blocks = (lds / 4 - kRowsPerBlk * 144) / 144;
     if (cache_blocks < 1) return hipSuccess;
     unsigned *bar = s.bar;
-    if (!bar_zeroed) hipLaunchKernelGGL(fill_u32_kernel_pcg, dim3(1), dim3(64), 0, st, bar, 64);
+    if (!bar_zeroed)
+        hipLaunchKernelGGL(fill_u32_kernel_pcg, dim3((MSL_BAR_WORDS + 255) / 256), dim3(256), 0, st, bar, MSL_BAR_WORDS);
     void *args[] = {&A, (void *)&rows, (void *)&cache_blocks, &bar, &rep, &params};
     const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(pcg_persistent_kernel), dim3(G),
                                                     dim3(kPcgThreads), args, (unsigned)lds, st);
@@ -645,8 +756,8 @@ __global__ void __launch_bounds__(kPcgThreads) pcg_batched_kernel(const BatchIte
     int b = count - 1;
     while (b > 0 && items[b].wg0 > (int)blockIdx.x) --b;
     const BatchItem &it = items[b];
-    pcg_persistent_body(it.p, rows_per_wg, cache_blocks, bar, gridDim.x, (int)blockIdx.x - it.wg0, it.wgs,
-                        it.rep + gi, it.params);
+    pcg_persistent_body(it.p, rows_per_wg, cache_blocks, bar, gridDim.x, blockIdx.x, (int)blockIdx.x - it.wg0,
+                        it.wgs, it.rep + gi, it.params);
 }
 
 static int batched_static_lds() {
@@ -672,7 +783,7 @@ static int batched_lds(int total_wgs) {
     const int cu_lds = kPersistMaxLds;
     int lds = cu_lds / per_cu - batched_static_lds() - 1024;
     if (lds > shmem - batched_static_lds() - 1024) lds = shmem - batched_static_lds() - 1024;
-    const int min_lds = (kRowsPerBlk * 144 + 157) * 4;   // the rows' preconditioner and one cached block
+    const int min_lds = (kRowsPerBlk * 144 + 144) * 4;   // the rows' preconditioner and one cached block
     if (lds < min_lds) return 0;
     int occ = 0;
     if (hipFuncSetAttribute(reinterpret_cast<const void *>(pcg_batched_kernel),
@@ -690,7 +801,7 @@ hipError_t launch_pcg_batched(const BatchItem *items, int count, int rows_per_wg
     *used = false;
     const int lds = batched_lds(total_wgs);
     if (lds <= 0 || rows_per_wg < 1 || rows_per_wg > kRowsPerBlk) return hipSuccess;
-    const int cache_blocks = (lds / 4 - kRowsPerBlk * 144) / (144 + 12 + 1);
+    const int cache_blocks = (lds / 4 - kRowsPerBlk * 144) / 144;
     if (cache_blocks < 1) return hipSuccess;
     hipError_t e;
     if (cooperative) {

@@ -1020,7 +1020,8 @@ __device__ __forceinline__ void energy_report_body(const double *__restrict__ pt
                                                    const double *__restrict__ node_part, int m, misslam_report *rep,
                                                    float reject_thr, unsigned *__restrict__ zero_words) {
     __shared__ double red[5][256 / kWave];
-    if (zero_words && threadIdx.x < 64) zero_words[threadIdx.x] = 0u;   // the next solve's grid barrier
+    if (zero_words)   // the next solve's grid barrier
+        for (int t = threadIdx.x; t < MSL_BAR_WORDS; t += 256) zero_words[t] = 0u;
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int t = threadIdx.x; t < npb; t += 256) {
         v[0] += pt_part[3 * t];

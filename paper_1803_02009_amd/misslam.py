@@ -290,3 +290,54 @@ class WarpEnergy(torch.autograd.Function):
                                      c["ws"], corr=corr, grad_e=ge, want_params=ctx.needs_input_grad[0],
                                      want_points=ctx.needs_input_grad[1])
         return gp, gv, None
+
+
+class Batch:
+    """Uneven problems registered together (misslam_batch_*): one launch per
+    phase over every problem, the frame captured once into a hipGraph.
+
+    problems: list of dicts with keys points (6, N), nodes (3, m), x (m, 12),
+    graph (Graph), depth (H, W), cam, pose.  Tensors must stay alive and keep
+    their addresses while the batch is used.  rows_per_wg: solve tile (1..21)
+    or 0 to time the candidates on the first call.
+    """
+
+    def __init__(self, problems, params, rows_per_wg=0):
+        self.params = params
+        self.keep = []
+        self.reports = []
+        arr = (_lib.Problem * len(problems))()
+        for i, pr in enumerate(problems):
+            rep = new_report(params.gn_iters + 1)
+            self.reports.append(rep)
+            _need(pr["depth"], torch.float32, "depth")
+            self.keep.append((pr, rep))
+            arr[i] = _lib.Problem(points_struct(pr["points"]), nodes_struct(pr["nodes"], pr["x"]), pr["graph"].c(),
+                                  pr["depth"].data_ptr(), pr["cam"], pr["pose"], rep.data_ptr())
+        self._arr = arr
+        h = ctypes.c_void_p()
+        check("misslam_batch_create", load().misslam_batch_create(arr, len(problems), ctypes.byref(params.c()),
+                                                                  int(rows_per_wg), ctypes.byref(h)))
+        self.h = h
+        nb = load().misslam_batch_workspace_bytes(h)
+        self.ws = torch.empty(max(int(nb), 1), dtype=torch.uint8, device="cuda")
+
+    def register(self):
+        check("misslam_batch_register", load().misslam_batch_register(self.h, _ptr(self.ws),
+                                                                      ctypes.c_size_t(self.ws.numel()), _stream()))
+        return self.reports
+
+    @property
+    def tile(self):
+        return int(load().misslam_batch_tile(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().misslam_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # pragma: no cover - interpreter shutdown
+            pass

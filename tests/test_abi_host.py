@@ -42,9 +42,9 @@ def test_struct_layout_matches_header():
 #include <stddef.h>
 #include "misslam.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(misslam_camera), sizeof(misslam_pose),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(misslam_camera), sizeof(misslam_pose),
          sizeof(misslam_points), sizeof(misslam_nodes), sizeof(misslam_graph), sizeof(misslam_params),
-         sizeof(misslam_report), sizeof(misslam_fuse_params));
+         sizeof(misslam_report), sizeof(misslam_fuse_params), sizeof(misslam_problem));
   printf("%zu %zu %zu %zu\n", offsetof(misslam_params, eps_d), offsetof(misslam_params, lambda),
          offsetof(misslam_report, n_valid), offsetof(misslam_graph, info));
   return 0;
@@ -58,7 +58,7 @@ int main(void) {
         out = subprocess.check_output([exe]).decode().split("\n")
     sizes = [int(v) for v in out[0].split()]
     want = [ctypes.sizeof(t) for t in (_lib.Camera, _lib.Pose, _lib.Points, _lib.Nodes, _lib.Graph, _lib.Params,
-                                       _lib.Report, _lib.FuseParams)]
+                                       _lib.Report, _lib.FuseParams, _lib.Problem)]
     assert sizes == want
     offs = [int(v) for v in out[1].split()]
     assert offs == [_lib.Params.eps_d.offset, _lib.Params.lambda_.offset, _lib.Report.n_valid.offset,

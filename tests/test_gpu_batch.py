@@ -1,0 +1,86 @@
+"""Uneven batches: every phase as one launch over all problems, the frame replayed from a hipGraph.
+
+Six problems of the 16-problem uneven batch (different frame sizes, 21k to
+202k points, 104 to 1134 nodes).  With the single-call tile (16 rows per
+solve workgroup) each problem's arithmetic and reduction order are those of
+misslam_gn_register, so parameters and reports must be bitwise equal to six
+single calls (which the parity tests hold against the float64 oracle); with
+the autotuned tile only the PCG reductions' order may differ.
+"""
+import numpy as np
+import pytest
+import torch
+
+import gen
+from gpu_util import Scene, rel_err
+
+pytestmark = pytest.mark.gpu
+IDS = [0, 1, 2, 3, 4, 5]
+SOLVE_ROWS = 16   # MISSLAM_SOLVE_ROWS: the single call's tile
+
+
+@pytest.fixture(scope="module")
+def problems(lib):
+    out = []
+    for b in IDS:
+        s = Scene(gen.make_scene(gen.batch_spec(b)))
+        _ = s.graph
+        out.append(s)
+    torch.cuda.synchronize()
+    return out
+
+
+def _single(problems):
+    xs, reps = [], []
+    for s in problems:
+        x = s.M.identity_params(s.m)
+        rep, _ = s.M.gn_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, s.params, s.ws)
+        xs.append(x)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in xs], [s.M.read_report(r) for s, r in zip(problems, reps)]
+
+
+def _batch(problems, rows, calls=1):
+    M = problems[0].M
+    items = []
+    for s in problems:
+        items.append(dict(points=s.pts, nodes=s.nodes, x=s.M.identity_params(s.m), graph=s.graph, depth=s.depth,
+                          cam=s.cam, pose=s.pose))
+    params = problems[0].params
+    bt = M.Batch(items, params, rows_per_wg=rows)
+    outs = []
+    for _ in range(calls):
+        for it in items:
+            it["x"].copy_(M.identity_params(it["x"].shape[0]))
+        reps = bt.register()
+        torch.cuda.synchronize()
+        outs.append(([it["x"].cpu().numpy() for it in items], [M.read_report(r) for r in reps]))
+    tile = bt.tile
+    bt.close()
+    return outs, tile
+
+
+def test_batch_equals_single_calls_bitwise(problems):
+    xs, reps = _single(problems)
+    outs, tile = _batch(problems, SOLVE_ROWS, calls=2)
+    assert tile == SOLVE_ROWS
+    for call, (xb, rb) in enumerate(outs):
+        for i in range(len(problems)):
+            assert np.array_equal(xb[i].view(np.uint32), xs[i].view(np.uint32)), (call, i)
+            assert rb[i].tobytes() == reps[i].tobytes(), (call, i)
+    for r in reps:
+        assert np.all(r["flags"] == 0)
+
+
+def test_batch_autotuned_tile(problems):
+    xs, reps = _single(problems)
+    outs, tile = _batch(problems, 0, calls=2)
+    print("autotuned rows per workgroup", tile)
+    assert tile in (21, 16, 12, 8)
+    (x1, r1), (x2, r2) = outs
+    for i in range(len(problems)):
+        assert np.array_equal(x1[i].view(np.uint32), x2[i].view(np.uint32))   # graph replays are identical
+        assert rel_err(x1[i], xs[i]) < 1e-5
+        assert r1[i][-1]["e_data"] == pytest.approx(reps[i][-1]["e_data"], rel=1e-4)
+        assert np.array_equal(r1[i]["n_valid"][:1], reps[i]["n_valid"][:1])
