@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     return ap.parse_args()
 
 
@@ -201,9 +202,65 @@ def main():
         "roofline": roofline,
         "low_precision": lowp,
     }
+    if not args.no_batch:
+        out["batch"] = batch_bench(M, _lib, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, params)
     print(json.dumps(out))
+
+
+def batch_bench(M, _lib, args, count=16):
+    """16 uneven problems (frames 320x240 to 640x480, 21k-264k points, 104-1716 nodes):
+    16 single registration calls against one batched call replayed from its hipGraph."""
+    import torch
+
+    import gen
+    probs = []
+    for b in range(count):
+        sc = gen.make_scene(gen.batch_spec(b))
+        pts = torch.tensor(np.concatenate([sc["points"].T, sc["normals"].T]), device="cuda").contiguous()
+        nodes = torch.tensor(np.ascontiguousarray(sc["nodes"].T), device="cuda").contiguous()
+        depth = torch.tensor(sc["depth"], device="cuda").contiguous()
+        params = M.Params(sigma=sc["sigma"], gn_iters=sc["gn_iters"], pcg_iters=sc["pcg_iters"])
+        ws = M.Workspace()
+        g = M.build_graph(pts, nodes, params, ws)
+        probs.append(dict(points=pts, nodes=nodes, x=M.identity_params(nodes.shape[1]), graph=g, depth=depth,
+                          cam=M.camera(*sc["camera"]), pose=M.pose(sc["R"], sc["T"]), params=params, ws=ws))
+    torch.cuda.synchronize()
+    n_tot = sum(p["points"].shape[1] for p in probs)
+    m_tot = sum(p["nodes"].shape[1] for p in probs)
+    G = probs[0]["params"].gn_iters
+
+    def singles():
+        for p in probs:
+            p["x"].copy_(M.identity_params(p["x"].shape[0]))
+            M.gn_register(p["points"], p["nodes"], p["x"], p["graph"], p["depth"], p["cam"], p["pose"], p["params"],
+                          p["ws"])
+
+    bt = M.Batch(probs, probs[0]["params"], rows_per_wg=0)
+
+    def batched():
+        for p in probs:
+            p["x"].copy_(M.identity_params(p["x"].shape[0]))
+        bt.register()
+
+    res = {}
+    for name, fn in (("single_calls", singles), ("batched_graph", batched)):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        res[name] = {"ms_per_batch_frame": round(1000 * dt, 4), "gn_iters_per_s": round(count * G / dt, 1)}
+    out = {"workload": f"{count} uneven problems, {n_tot} points and {m_tot} nodes in all, {G} GN x "
+                       f"{probs[0]['params'].pcg_iters} PCG each; a step registers every problem once",
+           "solve_tile_rows": bt.tile, **res,
+           "speedup": round(res["single_calls"]["ms_per_batch_frame"] / res["batched_graph"]["ms_per_batch_frame"], 3)}
+    bt.close()
+    return out
 
 
 def accuracy(state, rep, gold):

@@ -428,28 +428,56 @@ __device__ __forceinline__ unsigned long long ld_dev64(const float *p) {
 __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_per_wg, int cache_blocks, unsigned *bar,
                                                     unsigned nbar, unsigned bar_id, int wg, int G,
                                                     misslam_report *rep, float *params) {
-    extern __shared__ float dyn[];
+    extern __shared__ float4 dyn4[];
     __shared__ double red[3][kPcgThreads / kWave];
     __shared__ float vx[kRowsPerBlk * 12], vr[kRowsPerBlk * 12], vp[kRowsPerBlk * 12], vq[kRowsPerBlk * 12];
     __shared__ int bmap[kMaxBlocksWg];                 // block -> distinct-column slot (-1: beyond the cap)
     __shared__ int colL[kMaxBlocksWg];
     __shared__ int scan_w[kPcgThreads / kWave];
     __shared__ int ucol[kMaxUnique];
-    __shared__ float zc[kMaxUnique * 12];
-    __shared__ int cnt_u;
+    __shared__ float4 zc4[kMaxUnique * 3];             // z of the distinct columns (setup: first-block map)
+    __shared__ int cnt_u, cmin_s, cmax_s;
+    float *zc = reinterpret_cast<float *>(zc4);
     const int r0 = min(A.m, wg * rows_per_wg);
     const int r1 = min(A.m, r0 + rows_per_wg);
     const int b0 = min(A.row_ptr[r0], A.cap), b1 = min(A.row_ptr[r1], A.cap);
     const int nb = min(b1 - b0, kMaxBlocksWg);         // blocks of this workgroup's rows
     const int cached = min(nb, cache_blocks);
-    float *hc = dyn;                                   // cached blocks
+    float *hc = reinterpret_cast<float *>(dyn4);       // cached blocks
     float *mc = hc + (size_t)cache_blocks * 144;       // preconditioner blocks of the rows
-    for (int t = threadIdx.x; t < cached * 144; t += kPcgThreads) hc[t] = A.blocks[(size_t)b0 * 144 + t];
-    for (int t = threadIdx.x; t < (r1 - r0) * 144; t += kPcgThreads) mc[t] = A.minv[(size_t)r0 * 144 + t];
+    {   // 16-byte copies, several in flight per thread
+        const float4 *src = reinterpret_cast<const float4 *>(A.blocks + (size_t)b0 * 144);
+        const int n4 = cached * 36;
+#pragma unroll 4
+        for (int t = threadIdx.x; t < n4; t += kPcgThreads) dyn4[t] = src[t];
+        const float4 *srcm = reinterpret_cast<const float4 *>(A.minv + (size_t)r0 * 144);
+        float4 *dstm = reinterpret_cast<float4 *>(mc);
+        for (int t = threadIdx.x; t < (r1 - r0) * 36; t += kPcgThreads) dstm[t] = srcm[t];
+    }
     // distinct columns: a block whose column appears at no earlier block of the workgroup gets the next
     // slot (in block order, by a workgroup scan); later blocks of that column share it
-    for (int t = threadIdx.x; t < nb; t += kPcgThreads) colL[t] = A.col_idx[b0 + t];
+    if (threadIdx.x == 0) {
+        cmin_s = 0x7FFFFFFF;
+        cmax_s = -1;
+    }
     __syncthreads();
+    for (int t = threadIdx.x; t < nb; t += kPcgThreads) {
+        const int c = A.col_idx[b0 + t];
+        colL[t] = c;
+        atomicMin(&cmin_s, c);
+        atomicMax(&cmax_s, c);
+    }
+    __syncthreads();
+    const int cmin = cmin_s, crange = cmax_s - cmin_s + 1;
+    constexpr int kMapRange = kMaxUnique * 12;         // ints of the first-block map (in zc's space)
+    int *firstmap = reinterpret_cast<int *>(zc4);
+    const bool mapped = nb > 0 && crange <= kMapRange;
+    if (mapped) {
+        for (int t = threadIdx.x; t < crange; t += kPcgThreads) firstmap[t] = 0x7FFFFFFF;
+        __syncthreads();
+        for (int t = threadIdx.x; t < nb; t += kPcgThreads) atomicMin(&firstmap[colL[t] - cmin], t);
+        __syncthreads();
+    }
     constexpr int kPerT = (kMaxBlocksWg + kPcgThreads - 1) / kPcgThreads;   // entries per thread in the scan
     int firstpos[kPerT];
     int nfirst = 0;
@@ -460,15 +488,20 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
         if (t < nb) {
             const int c = colL[t];
             int f = t;
-            for (int u = 0; u < t; ++u)
-                if (colL[u] == c) {
-                    f = u;
-                    break;
-                }
+            if (mapped) {
+                f = firstmap[c - cmin];
+            } else {
+                for (int u = 0; u < t; ++u)
+                    if (colL[u] == c) {
+                        f = u;
+                        break;
+                    }
+            }
             firstpos[e] = f;
             nfirst += f == t;
         }
     }
+    __syncthreads();   // the map's space becomes zc again
     // exclusive scan of nfirst over the workgroup: wave scans, then the waves in order
     {
         const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -576,7 +609,18 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
                 const int q = pb - b0;
                 const int slot = q < nb ? bmap[q] : -1;
                 const float *B = q < cached ? hc + (size_t)q * 144 + a * 12 : A.blocks + (size_t)pb * 144 + a * 12;
-                if (slot >= 0) {
+                if (slot >= 0 && q < cached) {
+                    const float4 *B4 = reinterpret_cast<const float4 *>(B);
+                    const float4 *z4 = zc4 + slot * 3;
+#pragma unroll
+                    for (int h = 0; h < 3; ++h) {
+                        const float4 bv = B4[h], zv = z4[h];
+                        az = fma((double)bv.x, (double)zv.x, az);
+                        az = fma((double)bv.y, (double)zv.y, az);
+                        az = fma((double)bv.z, (double)zv.z, az);
+                        az = fma((double)bv.w, (double)zv.w, az);
+                    }
+                } else if (slot >= 0) {
                     const float *zl = zc + slot * 12;
 #pragma unroll
                     for (int b = 0; b < 12; ++b) az = fma((double)B[b], (double)zl[b], az);
