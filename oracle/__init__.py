@@ -11,6 +11,7 @@ section and equation number as numbered in the LaTeX source order:
   Eq.(6) regularisation term          Eq.(7) visibility gates
   Eq.(8) point-to-plane data term     Sec. II-F optimisation (LM; here damped GN + PCG)
   Alg. 1/2 registration and fusion    Eqs.(12)-(15) fusion update (Sec. II-G)
+  Alg. 2 steps 3-5, Alg. 3            growth, removal, down-sampling, node regeneration
 Where the paper is silent or garbled the reading taken is stated in the
 function's docstring.  Everything is float64 numpy; inputs arrive as float32
 values promoted exactly.
@@ -30,3 +31,4 @@ from .gn import gn_register, Problem  # noqa: F401
 from .grad import energy_grad_params, energy_grad_points, total_energy_fixed  # noqa: F401
 from .fuse import fuse, fuse_warped, zbuffer  # noqa: F401
 from .mixed import round_bf16, round_fp16  # noqa: F401
+from .grow import grow, voxel_keys  # noqa: F401
