@@ -284,6 +284,48 @@ misslam_status misslam_energy_vjp(const misslam_points *points, const misslam_no
                                   int32_t *corr_out, const float *grad_e, float *grad_params, float *grad_points,
                                   double *energy, misslam_report *rep, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------ growth and maintenance */
+
+/* (host) settings of the model's growth and maintenance (Alg. 2 steps 3-5, Alg. 3, Sec. III-B) */
+typedef struct {
+    float voxel;               /* down-sampling box edge: 0.22 mm */
+    float node_spacing;        /* node regeneration voxel edge and minimum distance to a node, mm */
+    float tau_weight;          /* removal weight bound (the paper gives none): 2 */
+    int32_t tau_time;          /* removal age, frames: 10 */
+    int32_t frame;             /* the frame's index: the stamp of registered and lifted points */
+} misslam_grow_params;
+
+/*
+ * Growth and maintenance of the model after misslam_fuse for the same frame
+ * (Alg. 2 steps 3-5, Alg. 3).  In order:
+ *   1. removal: a point with frame - stamp > tau_time and w < tau_weight is dropped;
+ *   2. Group 2: every pixel with depth and a depth normal (nmap, as from
+ *      misslam_normal_map) whose reg_map winner is absent or was not
+ *      registered (both outputs of misslam_fuse) becomes a point
+ *      p = R^T (V - T), n = R^T N, w = 1, stamp = frame, appended in pixel order;
+ *   3. down-sampling: voxels of edge voxel (origin 0); in every voxel that
+ *      holds a point stamped with this frame and two or more points, the
+ *      points merge into the lowest-index one: mean position, renormalised
+ *      mean normal (float64, ascending index), largest w and stamp;
+ *   4. node regeneration: for each voxel of edge node_spacing holding points,
+ *      a node (identity parameters) is appended at their centroid when no
+ *      node lies within node_spacing of it; new nodes in ascending
+ *      (kz, ky, kx) voxel order.
+ * The model is rewritten in place up to points->capacity / nodes->capacity
+ * (positions and normals world-frame, as left by misslam_fuse); points->n and
+ * nodes->m are the counts before the call and are NOT updated: the device
+ * writes counts_out (7 int64): new n, new m, lifted, removed, merged away,
+ * new nodes, overflow (1 if a capacity cut the model or the node list).
+ * Read them after synchronising the stream and rebuild the graph
+ * (misslam_build_graph) before the next registration.  points->w and
+ * points->stamp are required.
+ */
+size_t misslam_grow_workspace_bytes(int64_t n, int32_t width, int32_t height);
+misslam_status misslam_grow(misslam_points *points, misslam_nodes *nodes, const int32_t *reg_map,
+                            const int32_t *registered, const float *nmap, const misslam_camera *camera,
+                            const misslam_pose *pose, const misslam_grow_params *gp, int64_t *counts_out, void *ws,
+                            size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------ uneven batches */
 
 /*

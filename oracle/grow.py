@@ -76,8 +76,12 @@ def grow(points, normals, weight, stamp, registered, reg, depth, camera, R, T, N
     lift = (D > 0) & np.asarray(Nvalid, dtype=bool).reshape(-1) & ~reg_pix
     V = _vertex(depth, camera).reshape(-1, 3)[lift]
     Nm = np.asarray(Nmap, dtype=np.float64).reshape(-1, 3)[lift]
-    lp = ((V - Tv) @ Rm).astype(np.float32)                  # R^T (V - T)
-    ln = (Nm @ Rm).astype(np.float32)                        # R^T N
+    dv = V - Tv
+    # R^T (V - T) and R^T N, each component summed as ((r0 x0 + r1 x1) + r2 x2)
+    lp = np.stack([(Rm[0, a] * dv[:, 0] + Rm[1, a] * dv[:, 1]) + Rm[2, a] * dv[:, 2] for a in range(3)],
+                  axis=1).astype(np.float32)
+    ln = np.stack([(Rm[0, a] * Nm[:, 0] + Rm[1, a] * Nm[:, 1]) + Rm[2, a] * Nm[:, 2] for a in range(3)],
+                  axis=1).astype(np.float32)
 
     pts = np.concatenate([P[keep].astype(np.float32), lp])
     nrm = np.concatenate([Nn[keep].astype(np.float32), ln])

@@ -68,6 +68,11 @@ class FuseParams(ctypes.Structure):
                 ("frame", ctypes.c_int32)]
 
 
+class GrowParams(ctypes.Structure):
+    _fields_ = [("voxel", ctypes.c_float), ("node_spacing", ctypes.c_float), ("tau_weight", ctypes.c_float),
+                ("tau_time", ctypes.c_int32), ("frame", ctypes.c_int32)]
+
+
 class Problem(ctypes.Structure):
     _fields_ = [("points", Points), ("nodes", Nodes), ("graph", Graph), ("depth", ctypes.c_void_p),
                 ("camera", Camera), ("pose", Pose), ("report", ctypes.c_void_p)]
@@ -96,6 +101,9 @@ SIGNATURES = {
                           ctypes.c_size_t, vp]),
     "misslam_energy_vjp": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params), vp, vp, vp, vp,
                                 vp, vp, vp, vp, ctypes.c_size_t, vp]),
+    "misslam_grow_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
+    "misslam_grow": (st, [P(Points), P(Nodes), vp, vp, vp, P(Camera), P(Pose), P(GrowParams), vp, vp,
+                          ctypes.c_size_t, vp]),
     "misslam_batch_create": (st, [P(Problem), ctypes.c_int32, P(Params), ctypes.c_int32, P(vp)]),
     "misslam_batch_workspace_bytes": (ctypes.c_size_t, [vp]),
     "misslam_batch_register": (st, [vp, vp, ctypes.c_size_t, vp]),

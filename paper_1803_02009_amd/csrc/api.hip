@@ -13,10 +13,11 @@ namespace {
 // ---------------------------------------------------------------- phase timers (profiling only)
 
 enum Phase {
-    PH_NORMAL_MAP, PH_GRAPH, PH_POINT_PASS, PH_ASSEMBLE, PH_ENERGY, PH_BJACOBI, PH_PCG, PH_FUSE, PH_REFINE, PH_COUNT
+    PH_NORMAL_MAP, PH_GRAPH, PH_POINT_PASS, PH_ASSEMBLE, PH_ENERGY, PH_BJACOBI, PH_PCG, PH_FUSE, PH_REFINE, PH_GROW,
+    PH_COUNT
 };
 const char *const kPhaseNames[PH_COUNT] = {"normal_map", "build_graph", "point_pass", "assemble", "energy",
-                                           "bjacobi",    "pcg",         "fuse",       "refine"};
+                                           "bjacobi",    "pcg",         "fuse",       "refine",   "grow"};
 
 struct Profiler {
     std::mutex mu;
@@ -587,6 +588,107 @@ void misslam_profile_reset(void) {
         p.total_ms[i] = 0.0;
         p.launches[i] = 0;
     }
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ growth and maintenance
+
+namespace {
+
+struct GrowLayout {
+    msl::GrowScratch s;
+    float *stage;
+    int32_t *stage_stamp;
+    size_t bytes;
+};
+
+GrowLayout carve_grow(void *ws, int64_t n, int32_t W, int32_t H) {
+    Carver c{static_cast<char *>(ws)};
+    GrowLayout L{};
+    const int64_t C = n + (int64_t)W * H;
+    const int64_t Cb = C > 0 ? C : 1;
+    const int64_t nb = (Cb + 255) / 256;
+    L.stage = c.take<float>((size_t)7 * Cb);
+    L.stage_stamp = c.take<int32_t>((size_t)Cb);
+    L.s.flags = c.take<int32_t>((size_t)Cb);
+    L.s.alive = c.take<int32_t>((size_t)Cb);
+    L.s.bcount = c.take<int32_t>((size_t)nb);
+    L.s.boffs = c.take<int32_t>((size_t)nb);
+    L.s.bcount2 = c.take<int32_t>((size_t)nb);
+    L.s.boffs2 = c.take<int32_t>((size_t)nb);
+    L.s.count = c.take<int32_t>(8);
+    L.s.hist = c.take<int32_t>((size_t)msl::grow_hist_entries(Cb));
+    L.s.hoffs = c.take<int32_t>((size_t)msl::grow_hist_entries(Cb));
+    L.s.k0 = c.take<unsigned long long>((size_t)Cb);
+    L.s.k1 = c.take<unsigned long long>((size_t)Cb);
+    L.s.v0 = c.take<uint32_t>((size_t)Cb);
+    L.s.v1 = c.take<uint32_t>((size_t)Cb);
+    L.s.cent = c.take<float>((size_t)3 * Cb);
+    L.bytes = align_up(c.off);
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t misslam_grow_workspace_bytes(int64_t n, int32_t width, int32_t height) {
+    if (n < 0 || width < 1 || height < 1) return 0;
+    return carve_grow(nullptr, n, width, height).bytes;
+}
+
+misslam_status misslam_grow(misslam_points *points, misslam_nodes *nodes, const int32_t *reg_map,
+                            const int32_t *registered, const float *nmap, const misslam_camera *camera,
+                            const misslam_pose *pose, const misslam_grow_params *gp, int64_t *counts_out, void *ws,
+                            size_t ws_bytes, void *stream) {
+    if (!points || points->n < 0 || points->n > points->capacity || !points->px || !points->py || !points->pz ||
+        !points->nx || !points->ny || !points->nz || !points->w || !points->stamp || !nodes || nodes->m < 0 ||
+        nodes->m > nodes->capacity || !nodes->gx || !nodes->gy || !nodes->gz || !nodes->params || !reg_map ||
+        (points->n > 0 && !registered) || !nmap || !valid_camera(camera) || !pose || !gp || !counts_out || !ws)
+        return MISSLAM_EINVAL;
+    if (!(gp->voxel > 0.f) || !(gp->node_spacing > 0.f) || !std::isfinite(gp->tau_weight) || gp->tau_time < 0)
+        return MISSLAM_EINVAL;
+    const int64_t C = points->n + (int64_t)camera->width * camera->height;
+    if (C >= (int64_t)1 << 31 || points->capacity >= (int64_t)1 << 31) return MISSLAM_ESHAPE;
+    const GrowLayout L = carve_grow(ws, points->n, camera->width, camera->height);
+    if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
+    msl::GrowArgs g;
+    g.px = points->px;
+    g.py = points->py;
+    g.pz = points->pz;
+    g.nx = points->nx;
+    g.ny = points->ny;
+    g.nz = points->nz;
+    g.w = points->w;
+    g.stamp = points->stamp;
+    g.n = points->n;
+    g.capacity = points->capacity;
+    g.gx = nodes->gx;
+    g.gy = nodes->gy;
+    g.gz = nodes->gz;
+    g.params = nodes->params;
+    g.m = nodes->m;
+    g.node_capacity = nodes->capacity;
+    g.reg_map = reg_map;
+    g.registered = registered;
+    g.nmap = reinterpret_cast<const float4 *>(nmap);
+    g.cam = view(camera);
+    for (int t = 0; t < 9; ++t) g.Rd[t] = pose->R[t];
+    for (int t = 0; t < 3; ++t) g.Td[t] = pose->T[t];
+    g.voxel = gp->voxel;
+    g.node_spacing = gp->node_spacing;
+    g.tau_weight = gp->tau_weight;
+    g.tau_time = gp->tau_time;
+    g.frame = gp->frame;
+    g.stage = L.stage;
+    g.stage_stamp = L.stage_stamp;
+    g.stage_cap = C;
+    g.count = L.s.count;
+    const hipStream_t st = stream_of(stream);
+    Timed t(PH_GROW, st);
+    const hipError_t e = msl::launch_grow(g, L.s, counts_out, st);
+    return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
 }
 
 }  // extern "C"

@@ -105,6 +105,34 @@ struct BatchItem {
     int wg0, wgs;        // persistent-solve workgroups
 };
 
+// Growth and maintenance after fusion: the model (in/out, up to its
+// capacity), the fusion's registration outputs, the frame and the settings;
+// stage* are the workspace copies of [survivors | lifted pixels].
+struct GrowArgs {
+    float *px, *py, *pz, *nx, *ny, *nz, *w;
+    int32_t *stamp;
+    int64_t n, capacity;
+    float *gx, *gy, *gz, *params;
+    int m, node_capacity;
+    const int32_t *reg_map, *registered;
+    const float4 *nmap;
+    Cam cam;
+    double Rd[9], Td[3];
+    float voxel, node_spacing, tau_weight;
+    int tau_time, frame;
+    float *stage;             // 7 planes of stage_cap floats: p, n, w
+    int32_t *stage_stamp;
+    int64_t stage_cap;        // n + W H
+    const int32_t *count;     // device: [0] staged points, [1] kept, [2] final, [3] new nodes
+};
+
+struct GrowScratch {
+    int32_t *flags, *alive, *bcount, *boffs, *bcount2, *boffs2, *count, *hist, *hoffs;
+    unsigned long long *k0, *k1;
+    uint32_t *v0, *v1;
+    float *cent;
+};
+
 struct FuseArgs {
     PointsView pts;
     NodesView nd;
@@ -174,6 +202,9 @@ hipError_t launch_report_init_batched(const BatchItem *items, int count, int per
 hipError_t launch_pcg_batched(const BatchItem *items, int count, int rows_per_wg, int total_wgs, int it,
                               unsigned *bar, bool cooperative, hipStream_t st, bool *used);
 int pcg_batched_fits(int total_wgs);
+
+hipError_t launch_grow(GrowArgs g, const GrowScratch &s, int64_t *counts_out, hipStream_t st);
+int64_t grow_hist_entries(int64_t cap);
 
 hipError_t launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t st);
 

@@ -238,6 +238,32 @@ def fuse(points, w, stamp, nodes, x, graph, nmap, cam, pose_, fp, ws, outputs=Fa
     return (reg, regd[:n]) if outputs else None
 
 
+def grow_params(frame, node_spacing, voxel=0.22, tau_weight=2.0, tau_time=10):
+    """Alg. 2 steps 3-5 / Alg. 3 settings (Sec. III-B: 0.22 mm box, 10 frames; the weight bound is a reading)."""
+    return _lib.GrowParams(float(voxel), float(node_spacing), float(tau_weight), int(tau_time), int(frame))
+
+
+def grow(points, w, stamp, n, nodes, x, m, reg_map, registered, nmap, cam, pose_, gp, ws):
+    """Growth and maintenance after fuse (misslam_grow).
+
+    points (6, capacity), w, stamp (capacity), nodes (3, node_capacity), x (node_capacity, 12): the model with
+    n points and m nodes in use; rewritten in place.  Returns the device counts tensor (7,) int64:
+    new n, new m, lifted, removed, merged away, new nodes, overflow.
+    """
+    counts = torch.zeros(7, dtype=torch.int64, device=points.device)
+    cap = points.shape[1]
+    pstruct = points_struct(points, w, stamp, capacity=cap)
+    pstruct.n = int(n)
+    nstruct = nodes_struct(nodes, x)
+    nstruct.m = int(m)
+    nstruct.capacity = nodes.shape[1]
+    buf = ws.get(load().misslam_grow_workspace_bytes(int(n), cam.width, cam.height))
+    check("misslam_grow", load().misslam_grow(
+        ctypes.byref(pstruct), ctypes.byref(nstruct), _ptr(reg_map), _ptr(registered), _ptr(nmap), ctypes.byref(cam),
+        ctypes.byref(pose_), ctypes.byref(gp), _ptr(counts), _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
+    return counts
+
+
 def energy_vjp(points, nodes, x, graph, nmap, cam, pose_, params, ws, corr=None, grad_e=None, want_params=True,
                want_points=True):
     """Energy (and gradients) at x.  corr=None: associate now; else hold the given correspondences.

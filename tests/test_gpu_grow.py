@@ -1,0 +1,109 @@
+"""Parity of model growth and maintenance (Alg. 2 steps 3-5, Alg. 3) with the oracle.
+
+The 320x240 frame is registered and fused on the GPU; the fused model, the
+Reg map, the registration flags and the depth normal map (bit-exact with the
+oracle's) then feed both misslam_grow and the oracle, so every decision
+(removal, lifting, voxel groups, node creation) is compared bit for bit and
+every value to float32 rounding of the same float64 arithmetic.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import Scene
+
+pytestmark = pytest.mark.gpu
+
+
+def _fused(lib, frame, stamp0=0, w0=0.0):
+    s = Scene("c2")
+    x = s.M.identity_params(s.m)
+    s.M.gn_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, s.params, s.ws)
+    nmap = s.M.normal_map(s.depth, s.cam)
+    w = torch.full((s.n,), w0, device="cuda")
+    st = torch.full((s.n,), stamp0, dtype=torch.int32, device="cuda")
+    pts = s.pts.clone()
+    nodes = s.nodes.clone()
+    reg, regd = s.M.fuse(pts, w, st, nodes, x, s.graph, nmap, s.cam, s.pose, s.M.fuse_params(frame), s.ws,
+                         outputs=True)
+    torch.cuda.synchronize()
+    return s, pts, w, st, nodes, x, reg, regd, nmap
+
+
+def _grow_both(s, pts, w, st, nodes, x, reg, regd, nmap, frame, cap_pts=None, cap_nodes=None, spacing=5.0):
+    n, m = pts.shape[1], nodes.shape[1]
+    npx = s.cam.width * s.cam.height
+    C = cap_pts if cap_pts is not None else n + npx
+    Cm = cap_nodes if cap_nodes is not None else m + 4000
+    P = torch.zeros((6, C), device="cuda")
+    P[:, :n] = pts
+    W = torch.zeros(C, device="cuda")
+    W[:n] = w
+    S = torch.zeros(C, dtype=torch.int32, device="cuda")
+    S[:n] = st
+    G = torch.zeros((3, Cm), device="cuda")
+    G[:, :m] = nodes
+    X = torch.zeros((Cm, 12), device="cuda")
+    X[:m] = x
+    # the oracle's inputs: the same float32 model and registration outputs
+    fused = (pts.cpu().numpy(), w.cpu().numpy(), st.cpu().numpy(), reg.cpu().numpy(), regd.cpu().numpy(),
+             nmap.cpu().numpy(), nodes.cpu().numpy())
+    gp = s.M.grow_params(frame, spacing)
+    counts = s.M.grow(P, W, S, n, G, X, m, reg, regd, nmap, s.cam, s.pose, gp, s.ws)
+    torch.cuda.synchronize()
+    pf, wf, sf, rg, rd, nm, nd = fused
+    ok = ~np.all(nm[..., :3] == 0, axis=-1)
+    ref = oracle.grow(pf[:3].T, pf[3:].T, wf, sf, rd.astype(bool), rg.reshape(-1), s.sc["depth"], s.sc["camera"],
+                      s.sc["R"], s.sc["T"], nm[..., :3], ok, frame, nd.T, spacing, voxel=0.22)
+    return counts.cpu().numpy(), P.cpu().numpy(), W.cpu().numpy(), S.cpu().numpy(), G.cpu().numpy(), \
+        X.cpu().numpy(), ref
+
+
+@pytest.mark.parametrize("frame,stamp0", [(5, 0), (12, 0)])
+def test_grow_matches_oracle(lib, frame, stamp0):
+    s, pts, w, st, nodes, x, reg, regd, nmap = _fused(lib, frame, stamp0)
+    counts, P, W, S, G, X, ref = _grow_both(s, pts, w, st, nodes, x, reg, regd, nmap, frame)
+    n_out, m_out = int(counts[0]), int(counts[1])
+    print("frame", frame, "counts", counts.tolist(), "oracle lifted", ref["lifted"], "culled", ref["culled"],
+          "merged", ref["merged"], "new nodes", ref["new_nodes"])
+    assert counts[2] == ref["lifted"] and counts[3] == ref["culled"] and counts[4] == ref["merged"]
+    assert counts[5] == ref["new_nodes"] and counts[6] == 0
+    assert n_out == len(ref["points"]) and m_out == len(ref["nodes"])
+    assert ref["lifted"] > 1000 and ref["merged"] > 0
+    if frame > 10:
+        assert ref["culled"] > 0
+    np.testing.assert_array_equal(S[:n_out], ref["stamp"])
+    np.testing.assert_array_equal(W[:n_out], ref["weight"])
+    dp = np.abs(P[:3, :n_out].T - ref["points"]).max()
+    dn = np.abs(P[3:, :n_out].T - ref["normals"]).max()
+    print("max |dp|", dp, "max |dn|", dn)
+    assert dp <= 1e-5 and dn <= 1e-6
+    np.testing.assert_allclose(G[:, :m_out].T, ref["nodes"], rtol=0, atol=1e-5)
+    ident = np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], np.float32)
+    assert np.all(X[nodes.shape[1]:m_out] == ident)                 # new nodes start at identity
+
+
+def test_grow_empty_model_lifts_the_frame(lib):
+    s = Scene("c2")
+    nmap = s.M.normal_map(s.depth, s.cam)
+    npx = s.cam.width * s.cam.height
+    reg = torch.full((s.cam.height, s.cam.width), -1, dtype=torch.int32, device="cuda")
+    regd = torch.zeros(1, dtype=torch.int32, device="cuda")
+    empty = torch.zeros((6, 0), device="cuda")
+    counts, P, W, S, G, X, ref = _grow_both(s, empty, torch.zeros(0, device="cuda"),
+                                            torch.zeros(0, dtype=torch.int32, device="cuda"),
+                                            torch.zeros((3, 0), device="cuda"), torch.zeros((0, 12), device="cuda"),
+                                            reg, regd, nmap, 1, cap_pts=npx, cap_nodes=2000)
+    n_out = int(counts[0])
+    assert counts[2] == ref["lifted"] and n_out == len(ref["points"]) and counts[5] == ref["new_nodes"] > 0
+    assert np.abs(P[:3, :n_out].T - ref["points"]).max() <= 1e-5
+
+
+def test_grow_capacity_overflow_is_reported(lib):
+    s, pts, w, st, nodes, x, reg, regd, nmap = _fused(lib, 5)
+    n = pts.shape[1]
+    counts, P, W, S, G, X, ref = _grow_both(s, pts, w, st, nodes, x, reg, regd, nmap, 5, cap_pts=n + 100)
+    assert counts[6] == 1 and counts[0] == n + 100
+    # what fits is the oracle's model cut at the capacity
+    np.testing.assert_array_equal(S[:n + 100], ref["stamp"][:n + 100])
