@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--config", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--seq-frames", type=int, default=8, help="frames of the sweeping sequence (0: skip)")
+    ap.add_argument("--no-lowp", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -70,6 +74,15 @@ def main():
               f"(the per-frame registration does not shard across GPUs).", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if args.copy_mib > 0:   # a plain copy of known size, to scale the HBM byte counters
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch": src.numel() * 4}))
+        return
 
     import gen
     from paper_1803_02009_amd import _lib
@@ -145,36 +158,26 @@ def main():
     n_valid = int(np.mean([r["n_valid"] for r in rep[:G]]))
     per_iter = ["point_pass", "assemble", "energy", "bjacobi", "pcg"]
     gn_iter_ms = sum(phases[p]["total_ms"] for p in per_iter) / (args.steps * G)
-    dominant = max(["point_pass", "assemble", "pcg"], key=lambda p: phases[p]["avg_us"])
-    abytes = algorithmic_bytes(dominant, n, m, nnzb, params.k, cam.width, cam.height, params.pcg_iters, n_valid)
-    achieved = abytes / (phases[dominant]["avg_us"] * 1e-6) / 1e9
-    roofline = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "algorithmic_bytes_per_launch": int(abytes), "avg_launch_us": round(phases[dominant]["avg_us"], 2)}
+    # roofline of each per-iteration kernel; the dominant one (most time per frame) is `roofline`
+    lines = {}
+    for ph in ["point_pass", "assemble", "pcg"]:
+        if not phases[ph]["launches"]:
+            continue
+        abytes = algorithmic_bytes(ph, n, m, nnzb, params.k, cam.width, cam.height, params.pcg_iters, n_valid)
+        achieved = abytes / (phases[ph]["avg_us"] * 1e-6) / 1e9
+        lines[ph] = {"kernel": ph, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": int(abytes), "avg_launch_us": round(phases[ph]["avg_us"], 2),
+                     "ms_per_frame": round(phases[ph]["total_ms"] / args.steps, 4)}
+    dominant = max(lines, key=lambda p: lines[p]["ms_per_frame"])
+    roofline = lines[dominant]
 
     # accuracy against the stored float64 oracle result of the same frame
     acc = accuracy(state, rep, os.path.join(ROOT, "tests", "golden", f"{args.config}_oracle.npz"))
 
     # the low-precision form on the same frame: without refinement (the float64
     # oracle's algorithm on a rounded data term) and with two refinement passes
-    lowp = {"form": "bf16 data-term J^T J on the matrix cores (fp32 accumulation); refine_steps fp32 "
-                    "matrix-free refinement passes per GN step"}
-    plain = os.path.join(ROOT, "tests", "golden", f"{args.config}_oracle.npz")
-    for steps in (0, 2):
-        lp = M.Params(sigma=sc["sigma"], gn_iters=sc["gn_iters"], pcg_iters=sc["pcg_iters"],
-                      precision=_lib.PREC_BF16, refine_steps=steps)
-        for _ in range(max(1, args.warmup)):
-            frame(lp)
-        lp_elapsed = timed(lp, args.steps)
-        lp_rep = M.read_report(state["rep"])
-        entry = {"refine_steps": steps, "ms_per_frame": round(1000.0 * lp_elapsed / args.steps, 4),
-                 "gn_iters_per_s": round(G * args.steps / lp_elapsed, 2),
-                 "accuracy_vs_fp64_oracle": accuracy(state, lp_rep, plain),
-                 "e_data_final": float(lp_rep[-1]["e_data"])}
-        emu = os.path.join(ROOT, "tests", "golden", f"{args.config}_bf16_r{steps}_oracle.npz")
-        if steps > 0:
-            entry["accuracy_vs_same_form_oracle"] = accuracy(state, lp_rep, emu)
-        lowp[f"bf16_r{steps}"] = entry
+    lowp = None if args.no_lowp else lowp_bench(M, _lib, sc, frame, timed, state, G, args)
 
     out = {
         "metric": "GN iters/s + ms/frame at 640x480, 1600 ED nodes, rel err vs FP64 oracle",
@@ -200,10 +203,14 @@ def main():
                          "e_reg": float(rep[-1]["e_reg"]), "n_valid": int(rep[-1]["n_valid"]),
                          "flags": int(rep[-1]["flags"])},
         "roofline": roofline,
-        "low_precision": lowp,
+        "roofline_other": [v for k, v in lines.items() if k != dominant],
     }
+    if lowp is not None:
+        out["low_precision"] = lowp
     if not args.no_batch:
         out["batch"] = batch_bench(M, _lib, args)
+    if args.seq_frames > 0:
+        out["sequence"] = sequence_bench(M, args.seq_frames)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, params)
     print(json.dumps(out))
@@ -261,6 +268,83 @@ def batch_bench(M, _lib, args, count=16):
            "speedup": round(res["single_calls"]["ms_per_batch_frame"] / res["batched_graph"]["ms_per_batch_frame"], 3)}
     bt.close()
     return out
+
+
+def lowp_bench(M, _lib, sc, frame, timed, state, G, args):
+    """The low-precision form on the same frame: without refinement (the float64 oracle's algorithm on a
+    rounded data term) and with two refinement passes."""
+    lowp = {"form": "bf16 data-term J^T J on the matrix cores (fp32 accumulation); refine_steps fp32 "
+                    "matrix-free refinement passes per GN step"}
+    plain = os.path.join(ROOT, "tests", "golden", f"{args.config}_oracle.npz")
+    for steps in (0, 2):
+        lp = M.Params(sigma=sc["sigma"], gn_iters=sc["gn_iters"], pcg_iters=sc["pcg_iters"],
+                      precision=_lib.PREC_BF16, refine_steps=steps)
+        for _ in range(max(1, args.warmup)):
+            frame(lp)
+        lp_elapsed = timed(lp, args.steps)
+        lp_rep = M.read_report(state["rep"])
+        entry = {"refine_steps": steps, "ms_per_frame": round(1000.0 * lp_elapsed / args.steps, 4),
+                 "gn_iters_per_s": round(G * args.steps / lp_elapsed, 2),
+                 "accuracy_vs_fp64_oracle": accuracy(state, lp_rep, plain),
+                 "e_data_final": float(lp_rep[-1]["e_data"])}
+        emu = os.path.join(ROOT, "tests", "golden", f"{args.config}_bf16_r{steps}_oracle.npz")
+        if steps > 0:
+            entry["accuracy_vs_same_form_oracle"] = accuracy(state, lp_rep, emu)
+        lowp[f"bf16_r{steps}"] = entry
+    return lowp
+
+
+def sequence_bench(M, frames):
+    """The sweeping, breathing 250 x 200 mm sheet at 640x480: frame 0 lifts the first model and its nodes;
+    every later frame runs graph setup, registration (10 x 10), fusion and growth/maintenance.  Frames are
+    generated on the host before timing; only the GPU frame loop is timed (a host read of the new model
+    size closes every frame, as a caller sizing the next frame's buffers must)."""
+    import torch
+
+    from gen.sequence import Sequence
+    seq = Sequence()
+    data = [seq.frame(f) for f in range(frames + 1)]
+    cap_n, cap_m = 1_500_000, 10_000
+    P = torch.zeros((6, cap_n), device="cuda")
+    W = torch.zeros(cap_n, device="cuda")
+    S = torch.zeros(cap_n, dtype=torch.int32, device="cuda")
+    G = torch.zeros((3, cap_m), device="cuda")
+    X = torch.zeros((cap_m, 12), device="cuda")
+    params = M.Params(sigma=2.5, gn_iters=10, pcg_iters=10)
+    ws, ws_g = M.Workspace(), M.Workspace()
+    frames_in = []
+    for d in data:
+        frames_in.append(dict(depth=torch.tensor(d["depth"], device="cuda"), cam=M.camera(*d["camera"]),
+                              pose=M.pose(d["R"], d["T"])))
+    torch.cuda.synchronize()
+    # frame 0: the first model is the lifted frame
+    f0 = frames_in[0]
+    nmap = M.normal_map(f0["depth"], f0["cam"])
+    none = torch.full((f0["cam"].height, f0["cam"].width), -1, dtype=torch.int32, device="cuda")
+    c = M.grow(P, W, S, 0, G, X, 0, none, torch.zeros(1, dtype=torch.int32, device="cuda"), nmap, f0["cam"],
+               f0["pose"], M.grow_params(0, 2.5), ws_g).cpu().numpy()
+    n, m = int(c[0]), int(c[1])
+    sizes = [(n, m)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flags = 0
+    for f in range(1, frames + 1):
+        fi = frames_in[f]
+        g = M.build_graph(P[:, :n], G[:, :m], params, ws)
+        rep, _ = M.gn_register(P[:, :n], G[:, :m], X[:m], g, fi["depth"], fi["cam"], fi["pose"], params, ws)
+        nmap = M.normal_map(fi["depth"], fi["cam"])
+        reg, regd = M.fuse(P[:, :n], W[:n], S[:n], G[:, :m], X[:m], g, nmap, fi["cam"], fi["pose"],
+                           M.fuse_params(f), ws, outputs=True)
+        c = M.grow(P, W, S, n, G, X, m, reg, regd, nmap, fi["cam"], fi["pose"], M.grow_params(f, 2.5),
+                   ws_g).cpu().numpy()
+        flags |= int(M.read_report(rep)["flags"].max())
+        n, m = int(c[0]), int(c[1])
+        sizes.append((n, m))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / frames
+    return {"workload": f"sweep over a breathing 250x200 mm sheet, 640x480, frames 1..{frames} after the lifted "
+                        f"frame 0; graph + 10x10 registration + fusion + growth per frame",
+            "ms_per_frame": round(1000 * dt, 3), "points_nodes_per_frame": sizes, "report_flags": flags}
 
 
 def accuracy(state, rep, gold):

@@ -65,8 +65,14 @@ def pose(R, T):
     return _lib.Pose((ctypes.c_float * 9)(*R.tolist()), (ctypes.c_float * 3)(*T.tolist()))
 
 
+def _need_rows(t, dtype, name):
+    """A (rows, cols) tensor whose rows are contiguous planes (a column slice of a larger buffer is fine)."""
+    if not (t.is_cuda and t.dtype == dtype and t.dim() == 2 and (t.shape[1] <= 1 or t.stride(1) == 1)):
+        raise ValueError(f"{name} must be a (rows, n) {dtype} CUDA tensor with contiguous rows")
+
+
 def points_struct(points, w=None, stamp=None, capacity=None):
-    _need(points, torch.float32, "points")
+    _need_rows(points, torch.float32, "points")
     n = points.shape[1]
     base = points.data_ptr()
     cap = n if capacity is None else capacity
@@ -76,7 +82,7 @@ def points_struct(points, w=None, stamp=None, capacity=None):
 
 
 def nodes_struct(nodes, x):
-    _need(nodes, torch.float32, "nodes")
+    _need_rows(nodes, torch.float32, "nodes")
     _need(x, torch.float32, "x")
     m = nodes.shape[1]
     base = nodes.data_ptr()

@@ -107,3 +107,44 @@ def test_grow_capacity_overflow_is_reported(lib):
     assert counts[6] == 1 and counts[0] == n + 100
     # what fits is the oracle's model cut at the capacity
     np.testing.assert_array_equal(S[:n + 100], ref["stamp"][:n + 100])
+
+
+def test_sequence_two_frames(lib):
+    """Frame 0 of the sweep lifts the first model and its nodes; frame 1 registers it, fuses and grows it."""
+    from gen.sequence import Sequence
+    from paper_1803_02009_amd import misslam as M
+    seq = Sequence()
+    d0, d1 = seq.frame(0), seq.frame(1)
+    cap_n, cap_m = 700_000, 6000
+    P = torch.zeros((6, cap_n), device="cuda")
+    W = torch.zeros(cap_n, device="cuda")
+    S = torch.zeros(cap_n, dtype=torch.int32, device="cuda")
+    G = torch.zeros((3, cap_m), device="cuda")
+    X = torch.zeros((cap_m, 12), device="cuda")
+    ws, wsg = M.Workspace(), M.Workspace()
+    cam = M.camera(*d0["camera"])
+    dep0 = torch.tensor(d0["depth"], device="cuda")
+    nm0 = M.normal_map(dep0, cam)
+    none = torch.full((cam.height, cam.width), -1, dtype=torch.int32, device="cuda")
+    c = M.grow(P, W, S, 0, G, X, 0, none, torch.zeros(1, dtype=torch.int32, device="cuda"), nm0, cam,
+               M.pose(d0["R"], d0["T"]), M.grow_params(0, 2.5), wsg).cpu().numpy()
+    n, m = int(c[0]), int(c[1])
+    assert c[2] > 0.9 * cam.width * cam.height and m > 100 and c[6] == 0
+    params = M.Params(sigma=2.5, gn_iters=10, pcg_iters=10)
+    g = M.build_graph(P[:, :n], G[:, :m], params, ws)
+    dep1 = torch.tensor(d1["depth"], device="cuda")
+    pose1 = M.pose(d1["R"], d1["T"])
+    rep, _ = M.gn_register(P[:, :n], G[:, :m], X[:m], g, dep1, cam, pose1, params, ws)
+    r = M.read_report(rep)
+    print("sequence frame 1: n", n, "m", m, "n_valid", r["n_valid"][[0, -1]].tolist(), "e_data",
+          r["e_data"][[0, -1]].tolist())
+    assert np.all(r["flags"] == 0) and g.info.cpu().numpy()[3] == 0
+    # lifted points carry the noisy depth normals of frame 0, frame 1's are noisy too: the 10 degree gate keeps
+    # about a third of them at 0.23 mm pixels; the registration must still lower the data energy
+    assert r[-1]["n_valid"] > 0.25 * n and r[-1]["e_data"] < r[0]["e_data"]
+    nm1 = M.normal_map(dep1, cam)
+    reg, regd = M.fuse(P[:, :n], W[:n], S[:n], G[:, :m], X[:m], g, nm1, cam, pose1, M.fuse_params(1), ws,
+                       outputs=True)
+    c1 = M.grow(P, W, S, n, G, X, m, reg, regd, nm1, cam, pose1, M.grow_params(1, 2.5), wsg).cpu().numpy()
+    print("frame 1 growth counts", c1.tolist())
+    assert c1[6] == 0 and c1[0] > 0.9 * n and c1[1] >= m
