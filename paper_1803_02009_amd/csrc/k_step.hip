@@ -358,12 +358,15 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
     for (int t = lane; t < MISSLAM_MAX_ROW * 64; t += kWave) (&sh.accS[wave][0][0])[t] = 0.f;
 
     const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
-    const double e_reg = row_prepare<kAsmThreads>(a, sh.rn, j, nslots, gjx, gjy, gjz);
     const int lb = a.g.list_ptr[j];
     const int cnt = min(a.g.list_ptr[j + 1] - lb, MISSLAM_MAX_LIST);
     const int quota = (cnt + kAsmWaves - 1) / kAsmWaves;
     const int my0 = min(cnt, wave * quota), my1 = min(cnt, my0 + quota);
     const int nbatch = (my1 - my0 + kBatch - 1) / kBatch;
+    // the first batch's entries are fetched before the node-level loads are waited for
+    EntryRegs<K> nxt;
+    if (nbatch > 0 && lane < min(kBatch, my1 - my0)) entry_load<K>(a, s, n, lb + my0 + lane, nxt);
+    const double e_reg = row_prepare<kAsmThreads>(a, sh.rn, j, nslots, gjx, gjy, gjz);
 
     const int e = lane;                      // statistic entry owned in phase 2 (e < 60)
     const int pci = e < 60 ? e / 6 : 0, nai = e < 60 ? e % 6 : 0;
@@ -375,8 +378,6 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
 #pragma unroll
     for (int q = 0; q < 12; ++q) gacc[q] = 0.0;
 
-    EntryRegs<K> nxt;
-    if (nbatch > 0 && lane < min(kBatch, my1 - my0)) entry_load<K>(a, s, n, lb + my0 + lane, nxt);
     for (int bt = 0; bt < nbatch; ++bt) {
         const int e0 = my0 + bt * kBatch;
         const int nb = min(kBatch, my1 - e0);
@@ -454,6 +455,29 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
             const uint64_t later = t + 1 < 64 ? (starts >> (t + 1)) : 0ull;
             const int t1 = later ? min(nb, t + 1 + __builtin_ctzll(later)) : nb;
             int u = t;
+            for (; u + 3 < t1; u += 4) {   // four entries' LDS reads in flight, accumulated in entry order
+                float mv[4];
+#pragma unroll
+                for (int h = 0; h < 4; ++h) mv[h] = sh.Pc[wave][u + h][pci] * sh.Na[wave][u + h][nai];
+#pragma unroll
+                for (int g4 = 0; g4 < (K + 3) / 4; ++g4) {
+                    float4 wl[4];
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) wl[h] = sh.W[wave][u + h][g4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (4 * g4 + q < K) {
+                            float v = acc[4 * g4 + q];
+#pragma unroll
+                            for (int h = 0; h < 4; ++h) {
+                                const float wq = q == 0 ? wl[h].x : q == 1 ? wl[h].y : q == 2 ? wl[h].z : wl[h].w;
+                                v = fmaf(wq, mv[h], v);
+                            }
+                            acc[4 * g4 + q] = v;
+                        }
+                    }
+                }
+            }
             for (; u + 1 < t1; u += 2) {
                 const float m0 = sh.Pc[wave][u][pci] * sh.Na[wave][u][nai];
                 const float m1 = sh.Pc[wave][u + 1][pci] * sh.Na[wave][u + 1][nai];
@@ -503,11 +527,18 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
     for (int t = tid; t < nslots * 64; t += kAsmThreads) {
         const int sl = t / 64, en = t % 64;
         if (en < 60) {
-            const float v = sh.accS[0][sl][en] + sh.accS[1][sl][en] + sh.accS[2][sl][en] + sh.accS[3][sl][en];
+            float v = sh.accS[0][sl][en];
+#pragma unroll
+            for (int w = 1; w < kAsmWaves; ++w) v += sh.accS[w][sl][en];   // waves in order
             sh.accS[0][sl][en] = v;
         }
     }
-    if (tid < 12) sh.rn.gd[tid] = sh.gw[0][tid] + sh.gw[1][tid] + sh.gw[2][tid] + sh.gw[3][tid];
+    if (tid < 12) {
+        double v = sh.gw[0][tid];
+#pragma unroll
+        for (int w = 1; w < kAsmWaves; ++w) v += sh.gw[w][tid];
+        sh.rn.gd[tid] = v;
+    }
     __syncthreads();
     // data-term block from the statistic: H[(c,a),(c',a')] = S[c,c',a,a'] + delta_c' S[c,3,a,a']
     auto data = [&](int sl, int R, int C) {
