@@ -50,7 +50,7 @@ typedef enum {
 #define MISSLAM_FLAG_NONFINITE      0x4   /* NaN/Inf met in an energy or the update; x left unchanged */
 #define MISSLAM_FLAG_FRAME_REJECT   0x8   /* mean |r| above params.reject_threshold */
 #define MISSLAM_FLAG_GRAPH_OVERFLOW 0x10  /* a per-frame graph capacity was exceeded */
-#define MISSLAM_FLAG_SYNC_TIMEOUT   0x20  /* the persistent solve gave up waiting at a grid barrier; discard the step */
+#define MISSLAM_FLAG_SYNC_TIMEOUT   0x20  /* the persistent solve gave up waiting for another workgroup; discard the step */
 
 #define MISSLAM_WEIGHT_GAUSS  0   /* w_j ~ exp(-|v-g_j|^2 / (2 sigma^2)), normalised over k */
 #define MISSLAM_WEIGHT_LINEAR 1   /* Eq.(2): w_j ~ max(0, 1 - |v-g_j| / d_(k+1)), normalised */

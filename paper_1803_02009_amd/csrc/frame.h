@@ -14,8 +14,12 @@ struct GraphView {
     int32_t *info;
 };
 
-// Words of a persistent solve's grid barrier (group counters, top counter, generation).
-constexpr int MSL_BAR_WORDS = 512;
+// Sync area of a persistent solve: MSL_TAG_WORD0 words kept free, then 8 words
+// (4 tagged 8-byte words) for each of at most MSL_TAG_WGS workgroups of one
+// launch.  It must be zero when a solve starts.
+constexpr int MSL_TAG_WORD0 = 512;
+constexpr int MSL_TAG_WGS = 1024;
+constexpr int MSL_BAR_WORDS = MSL_TAG_WORD0 + 8 * MSL_TAG_WGS;
 
 // Uniform grid of the nodes for the kNN search.
 constexpr int MSL_GRID_CELLS = 1 << 18;
@@ -49,7 +53,7 @@ struct PcgScratch {
     int32_t *status;       // 2 x (pcg_iters + 2): stop status, then per-iteration "updated" flags
     int nblk;              // workgroups of the multi-kernel path
     int nblk_max;          // partial slots per reduction (>= every path's workgroup count)
-    unsigned *bar;         // MSL_BAR_WORDS words: grid barrier of the persistent solve
+    unsigned *bar;         // MSL_BAR_WORDS words: sync area of the persistent solve
 };
 
 hipError_t launch_normal_map(const float *depth, const Cam &cam, float4 *out, hipStream_t st);
@@ -170,7 +174,7 @@ hipError_t launch_vjp_points(const StepArgs &a, const StepScratch &s, float sigm
 hipError_t launch_grad_params(const float *g, int m, const float *grad_e, float *out, hipStream_t st);
 hipError_t launch_energy_total(const misslam_report *rep, float w_data, float w_rot, float w_reg, double *out,
                                hipStream_t st);
-// zero_words (optional): MSL_BAR_WORDS words cleared on the way (the persistent solve's barrier)
+// zero_words (optional): MSL_BAR_WORDS words cleared on the way (the persistent solve's sync area)
 hipError_t launch_energy_report(const StepScratch &s, int64_t n, int m, misslam_report *rep, float reject_thr,
                                 hipStream_t st, unsigned *zero_words = nullptr);
 hipError_t launch_bjacobi(const GraphView &g, int m, const float *blocks, float lambda, float *minv,

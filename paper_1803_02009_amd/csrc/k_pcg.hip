@@ -308,9 +308,12 @@ int pcg_blocks(int m) { return (m + kRowsPerBlk - 1) / kRowsPerBlk; }
 // preconditioner blocks and its slice of x, r, p, q in LDS.  Between
 // workgroups only z and the reduction partials travel, through device-scope
 // loads and stores (coherent across the XCDs' separate L2 caches without
-// cache maintenance), and a counter barrier on device-scope atomics orders
-// them: two barriers per iteration.  Every reduction is re-added by every
-// workgroup in the same order, so all take identical decisions.
+// cache maintenance).  There is no grid barrier: the two reductions of an
+// iteration (p.q, then r.z) are exchanged as tagged words, and a workgroup
+// publishes its r.z partial only after its z stores are acknowledged, so the
+// wait for the r.z partials is also the wait for the z that the next product
+// reads.  Every reduction is re-added by every workgroup in the same order,
+// so all take identical decisions.
 constexpr int kPersistMaxLds = 160 * 1024;   // LDS of one CU (gfx950)
 
 __device__ __forceinline__ void st_dev(float *p, float v) {
@@ -326,58 +329,10 @@ __device__ __forceinline__ double ld_dev(const double *p) {
     return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier over nblocks workgroups (participant id in [0, nblocks)).
-// Arrivals are counted in 8 group counters (id % 8, one 128-byte line each,
-// so they do not serialise on one address); the last arrival of a group
-// counts its group in a top counter, whose last arrival bumps the
-// generation that the others poll.  Layout in words: group g at 32 g, top at
-// 256, generation at 288.  Each wave first waits until its own device-scope
-// stores are acknowledged, so they are visible once the arrival is.  The
-// wait is bounded: a workgroup that gives up (which a launch whose
-// workgroups are all resident never causes) stops waiting at later barriers
+// Bound on the polls of one wait.  A workgroup that gives up (which a launch
+// whose workgroups are all resident never causes) stops waiting from then on
 // and the solve reports it.
 constexpr unsigned kSpinLimit = 1u << 18;
-
-__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nblocks, unsigned id, bool &broken) {
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __syncthreads();
-    __shared__ int give_up;
-    if (threadIdx.x == 0) {
-        give_up = broken ? 1 : 0;
-        unsigned *top = bar + 256, *gen = bar + 288;
-        const unsigned g = id % 8u;
-        const unsigned ngroups = nblocks < 8u ? nblocks : 8u;
-        const unsigned gsize = (nblocks - g + 7u) / 8u;
-        const unsigned g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        bool released = false;
-        const unsigned a = __hip_atomic_fetch_add(bar + 32 * g, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (a == gsize - 1) {
-            __hip_atomic_store(bar + 32 * g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_s_waitcnt(0);
-            const unsigned t = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (t == ngroups - 1) {
-                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __builtin_amdgcn_s_waitcnt(0);
-                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                released = true;
-            }
-        }
-        if (!released && !broken) {
-            unsigned spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
-                if (++spins > kSpinLimit) {
-                    give_up = 1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    __syncthreads();
-    broken = give_up != 0;
-}
 
 // Sum of up to three doubles over the workgroup: wave butterflies, then the
 // waves in order (fixed order: bitwise reproducible).
@@ -410,6 +365,53 @@ __device__ __forceinline__ double gather_dev(const double *part, int G, double (
     return v[0];
 }
 
+// Tagged exchange of one double per workgroup, the synchronisation of the
+// solve: workgroup g of the launch owns 4 eight-byte words of the sync area,
+// (high half | tag, low half | tag) for the direction product and the same for
+// r.z.  Each 8-byte word is stored and loaded whole (device scope), so a
+// reader that finds the expected tag in both words holds both halves of the
+// value published with it.  A slot is rewritten two exchanges later, which no
+// workgroup reaches before every workgroup has read it.  The words must be
+// zero at launch (tags start at 1).
+__device__ __forceinline__ unsigned long long *tag_slots(unsigned *bar) {
+    return reinterpret_cast<unsigned long long *>(bar + MSL_TAG_WORD0);
+}
+
+__device__ __forceinline__ void tag_publish(unsigned *bar, int gid, int which, unsigned tag, double v) {
+    unsigned long long *w = tag_slots(bar) + 4 * gid + 2 * which;
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    __hip_atomic_store(w, (bits & 0xFFFFFFFF00000000ull) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(w + 1, (bits << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Fixed-order sum of the values that workgroups g0 .. g0+G-1 published with
+// `tag`, waiting for each (bounded: a timeout marks the workgroup broken).
+__device__ __forceinline__ double tag_sum(unsigned *bar, int g0, int G, int which, unsigned tag, bool &broken,
+                                          double (*lds)[kPcgThreads / kWave]) {
+    const unsigned long long *base = tag_slots(bar) + 2 * which;
+    double v[1] = {0.0};
+    bool ok = true;
+    for (int t = threadIdx.x; t < G; t += kPcgThreads) {
+        unsigned long long *w = const_cast<unsigned long long *>(base) + 4 * (g0 + t);
+        unsigned long long hi = 0, lo = 0;
+        unsigned spins = 0;
+        for (;;) {
+            hi = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            lo = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((unsigned)hi == tag && (unsigned)lo == tag) break;
+            if (broken || ++spins > kSpinLimit) {
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (ok) v[0] += __longlong_as_double((long long)((hi & 0xFFFFFFFF00000000ull) | (lo >> 32)));
+    }
+    broken = __syncthreads_or(broken || !ok) != 0;
+    wg_sum<1>(v, lds);
+    return v[0];
+}
+
 constexpr int kMaxBlocksWg = kRowsPerBlk * MISSLAM_MAX_ROW;   // blocks of one workgroup's rows
 constexpr int kMaxUnique = 256;                                // distinct columns staged per iteration
 constexpr int kZPer = (kMaxUnique * 6 + kPcgThreads - 1) / kPcgThreads;
@@ -420,14 +422,13 @@ __device__ __forceinline__ unsigned long long ld_dev64(const float *p) {
 }
 
 // One workgroup's share of the solve: workgroup wg of the G that own this
-// system's rows; the barrier counts nbar workgroups (G, or every workgroup of
-// a batch of systems solved side by side) and this one is participant bar_id.
-// The columns of the workgroup's blocks are reduced to their distinct nodes
-// once; each iteration stages z of those nodes in LDS (8-byte device-scope
-// loads, issued together with the loads of the next reduction's partials).
+// system's rows, which are workgroups gid0 .. gid0+G-1 of the launch (a batch
+// solves several systems side by side, each over its own sync slots).  The
+// columns of the workgroup's blocks are reduced to their distinct nodes once;
+// each iteration stages z of those nodes in LDS (8-byte device-scope loads,
+// all in flight together).
 __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_per_wg, int cache_blocks, unsigned *bar,
-                                                    unsigned nbar, unsigned bar_id, int wg, int G,
-                                                    misslam_report *rep, float *params) {
+                                                    int gid0, int wg, int G, misslam_report *rep, float *params) {
     extern __shared__ float4 dyn4[];
     __shared__ double red[3][kPcgThreads / kWave];
     __shared__ float vx[kRowsPerBlk * 12], vr[kRowsPerBlk * 12], vp[kRowsPerBlk * 12], vq[kRowsPerBlk * 12];
@@ -546,16 +547,14 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
     const int li = lr * 12 + a;
     bool broken = false;
 
-    // stage z of the distinct columns and read one reduction's partials, all loads in flight together
-    auto stage = [&](const double *part) {
+    // stage z of the distinct columns, all loads in flight together
+    auto stage = [&]() {
         unsigned long long zv[kZPer];
 #pragma unroll
         for (int e = 0; e < kZPer; ++e) {
             const int t = threadIdx.x + e * kPcgThreads;
             if (t < U * 6) zv[e] = ld_dev64(A.z + (size_t)ucol[t / 6] * 12 + 2 * (t % 6));
         }
-        double v[1] = {0.0};
-        for (int t = threadIdx.x; t < G; t += kPcgThreads) v[0] += ld_dev(part + t);
 #pragma unroll
         for (int e = 0; e < kZPer; ++e) {
             const int t = threadIdx.x + e * kPcgThreads;
@@ -564,8 +563,13 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
                 zc[(t / 6) * 12 + 2 * (t % 6) + 1] = __uint_as_float((unsigned)(zv[e] >> 32));
             }
         }
-        wg_sum<1>(v, red);                             // also orders the zc writes before their reads
-        return v[0];
+        __syncthreads();
+    };
+    // publish this workgroup's value once every wave's device-scope stores are acknowledged
+    auto publish = [&](int which, unsigned tag, double v) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) tag_publish(bar, gid0 + wg, which, tag, v);
     };
 
     // init: r = -g, z = M r, x = 0
@@ -584,19 +588,18 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
         z = s;
         st_dev(A.z + (size_t)j * 12 + a, z);
     }
+    double rz;
     {
         double v[2] = {(double)r * (double)z, (double)r * (double)r};
         wg_sum<2>(v, red);
-        if (threadIdx.x == 0) {
-            st_dev(A.part + (size_t)(0 * 4 + 0) * G + wg, v[0]);
-            st_dev(A.part + (size_t)(0 * 4 + 1) * G + wg, v[1]);
-        }
+        if (threadIdx.x == 0) st_dev(A.part + (size_t)(0 * 4 + 1) * G + wg, v[1]);
+        publish(1, 1u, v[0]);
+        rz = tag_sum(bar, gid0, G, 1, 1u, broken, red);
+        stage();
     }
-    grid_barrier(bar, nbar, bar_id, broken);
     bool stopped = false;
     int done = 0;
     double rz_prev = 1.0;
-    double rz = stage(A.part + (size_t)(0 * 4 + 0) * G);
     for (int it = 0; it < A.iters; ++it) {
         const bool skip = stopped || rz == 0.0;
         // ---- direction and product: p = z + beta p, q = (H + lambda I) z + beta q
@@ -637,14 +640,14 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
             vq[li] = qv;
             pq = (double)pv * (double)qv;
         }
+        double pqs;
         {
             double v[1] = {pq};
             wg_sum<1>(v, red);
-            if (threadIdx.x == 0) st_dev(A.part + (size_t)(it * 4 + 2) * G + wg, v[0]);
+            publish(0, (unsigned)(it + 1), v[0]);
+            pqs = tag_sum(bar, gid0, G, 0, (unsigned)(it + 1), broken, red);
         }
-        grid_barrier(bar, nbar, bar_id, broken);
         // ---- step: alpha = r.z / p.q, x += alpha p, r -= alpha q, z = M r
-        const double pqs = gather_dev(A.part + (size_t)(it * 4 + 2) * G, G, red);
         const bool brk = !skip && !(pqs > 0.0);
         const bool upd = !skip && !brk;
         if (act && upd) {
@@ -663,20 +666,20 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
             z = s;
             st_dev(A.z + (size_t)j * 12 + a, z);
         }
+        if (upd) ++done;
+        if (brk) stopped = true;
+        if (!skip) rz_prev = rz;
         {
             double v[3] = {(double)r * (double)z, (double)r * (double)r, bad};
             wg_sum<3>(v, red);
             if (threadIdx.x == 0) {
-                st_dev(A.part + (size_t)((it + 1) * 4 + 0) * G + wg, v[0]);
                 st_dev(A.part + (size_t)((it + 1) * 4 + 1) * G + wg, v[1]);
                 st_dev(A.part + (size_t)((it + 1) * 4 + 3) * G + wg, v[2]);
             }
+            publish(1, (unsigned)(it + 2), v[0]);
+            rz = tag_sum(bar, gid0, G, 1, (unsigned)(it + 2), broken, red);
         }
-        if (upd) ++done;
-        if (brk) stopped = true;
-        if (!skip) rz_prev = rz;
-        grid_barrier(bar, nbar, bar_id, broken);
-        rz = stage(A.part + (size_t)((it + 1) * 4 + 0) * G);
+        stage();
     }
     // ---- finish: report (first workgroup), x out, params += x unless non-finite
     const double nbad = A.iters > 0 ? gather_dev(A.part + (size_t)(A.iters * 4 + 3) * G, G, red) : 0.0;
@@ -703,7 +706,7 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
 __global__ void __launch_bounds__(kPcgThreads) pcg_persistent_kernel(PcgArgs A, int rows_per_wg, int cache_blocks,
                                                                     unsigned *bar, misslam_report *rep,
                                                                     float *params) {
-    pcg_persistent_body(A, rows_per_wg, cache_blocks, bar, gridDim.x, blockIdx.x, blockIdx.x, gridDim.x, rep, params);
+    pcg_persistent_body(A, rows_per_wg, cache_blocks, bar, 0, blockIdx.x, gridDim.x, rep, params);
 }
 
 // Grid shape of the persistent solve for m rows on this device, or 0 when a
@@ -740,7 +743,7 @@ static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes) {
     if (max_blocks <= 0 || m <= 0) return 0;
     rows_per_wg = MISSLAM_SOLVE_ROWS;
     const int G = (m + rows_per_wg - 1) / rows_per_wg;
-    if (G > max_blocks) return 0;
+    if (G > max_blocks || G > MSL_TAG_WGS) return 0;
     lds_bytes = max_lds;
     return G;
 }
@@ -800,8 +803,8 @@ __global__ void __launch_bounds__(kPcgThreads) pcg_batched_kernel(const BatchIte
     int b = count - 1;
     while (b > 0 && items[b].wg0 > (int)blockIdx.x) --b;
     const BatchItem &it = items[b];
-    pcg_persistent_body(it.p, rows_per_wg, cache_blocks, bar, gridDim.x, blockIdx.x, (int)blockIdx.x - it.wg0,
-                        it.wgs, it.rep + gi, it.params);
+    pcg_persistent_body(it.p, rows_per_wg, cache_blocks, bar, it.wg0, (int)blockIdx.x - it.wg0, it.wgs, it.rep + gi,
+                        it.params);
 }
 
 static int batched_static_lds() {
@@ -823,7 +826,7 @@ static int batched_lds(int total_wgs) {
         hipDeviceGetAttribute(&shmem, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || cus <= 0)
         return 0;
     const int per_cu = (total_wgs + cus - 1) / cus;
-    if (per_cu > 4) return 0;
+    if (per_cu > 4 || total_wgs > MSL_TAG_WGS) return 0;
     const int cu_lds = kPersistMaxLds;
     int lds = cu_lds / per_cu - batched_static_lds() - 1024;
     if (lds > shmem - batched_static_lds() - 1024) lds = shmem - batched_static_lds() - 1024;

@@ -131,7 +131,7 @@ __device__ __forceinline__ int na_index(int a, int b) {  // a, b in 0..2
     return start[lo] + (hi - lo);
 }
 
-constexpr int kAsmThreads = 256;
+constexpr int kAsmThreads = 64;
 constexpr int kAsmWaves = kAsmThreads / kWave;
 constexpr int kBatch = 64;
 
@@ -1051,7 +1051,7 @@ __device__ __forceinline__ void energy_report_body(const double *__restrict__ pt
                                                    const double *__restrict__ node_part, int m, misslam_report *rep,
                                                    float reject_thr, unsigned *__restrict__ zero_words) {
     __shared__ double red[5][256 / kWave];
-    if (zero_words)   // the next solve's grid barrier
+    if (zero_words)   // the next solve's sync area
         for (int t = threadIdx.x; t < MSL_BAR_WORDS; t += 256) zero_words[t] = 0u;
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int t = threadIdx.x; t < npb; t += 256) {
