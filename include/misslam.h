@@ -63,7 +63,8 @@ typedef enum {
 #define MISSLAM_MAX_PCG  64
 #define MISSLAM_MAX_ROW  32       /* max blocks per row of the normal matrix (node degree + 1) */
 #define MISSLAM_MAX_LIST 2048     /* max points influenced by one node */
-#define MISSLAM_SOLVE_ROWS 16     /* node rows per workgroup of the one-launch PCG of a single problem */
+#define MISSLAM_SOLVE_ROWS 16     /* node rows per workgroup of the one-launch PCG of a single problem
+                                     with at most 16 rows per CU (larger ones pack up to 21) */
 
 /* (host) pinhole camera of the depth map: pixel (u, v) = (fx x/z + cx, fy y/z + cy) */
 typedef struct { int32_t width, height; float fx, fy, cx, cy; } misslam_camera;

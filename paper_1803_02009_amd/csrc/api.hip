@@ -291,7 +291,8 @@ misslam_status misslam_warp(const misslam_points *points, const misslam_nodes *n
 }
 
 static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, int64_t n, int m,
-                            misslam_report *rep, float reject, hipStream_t st, unsigned *zero_words = nullptr) {
+                            misslam_report *rep, float reject, hipStream_t st, unsigned *zero_words = nullptr,
+                            int zero_count = 0) {
     hipError_t e;
     {
         Timed t(PH_POINT_PASS, st);
@@ -303,7 +304,7 @@ static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, i
     }
     if (e == hipSuccess) {
         Timed t(PH_ENERGY, st);
-        e = msl::launch_energy_report(s, n, m, rep, reject, st, zero_words);
+        e = msl::launch_energy_report(s, n, m, rep, reject, st, zero_words, zero_count);
     }
     return e;
 }
@@ -313,10 +314,10 @@ static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, i
 // different (but in each path fixed) order, so the two agree to rounding.
 static hipError_t solve_persistent(const msl::GraphView &g, int m, const float *blocks, const float *gvec,
                                    const float *minv, float lambda, int iters, float *delta, const msl::PcgScratch &s,
-                                   misslam_report *rep, float *params, hipStream_t st, bool bar_zeroed = false) {
+                                   misslam_report *rep, float *params, hipStream_t st, int zeroed_words = 0) {
     bool used = false;
-    hipError_t e =
-        msl::launch_pcg_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st, &used, bar_zeroed);
+    hipError_t e = msl::launch_pcg_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st,
+                                              &used, zeroed_words);
     if (e == hipSuccess && !used)
         e = msl::launch_pcg_update(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st);
     return e;
@@ -444,11 +445,11 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
             break;
         }
         if (!lowp) {
-            e = linearize(a, L.step, n, m, rep + it, params->reject_threshold, st, L.pcg.bar);
+            e = linearize(a, L.step, n, m, rep + it, params->reject_threshold, st, L.pcg.bar, msl::msl_sync_words(m));
             if (e == hipSuccess) {
                 Timed t(PH_PCG, st);
                 e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
-                                     L.delta, L.pcg, rep + it, nodes->params, st, true);
+                                     L.delta, L.pcg, rep + it, nodes->params, st, msl::msl_sync_words(m));
             }
             continue;
         }
@@ -801,7 +802,8 @@ hipError_t batch_enqueue(misslam_batch *b, hipStream_t st, bool cooperative) {
     for (int it = 0; it < G && e == hipSuccess; ++it) {
         e = msl::launch_point_pass_batched(d, count, k, b->total_pp, it, st);
         if (e == hipSuccess) e = msl::launch_assemble_batched(d, count, k, b->total_rows, it, st);
-        if (e == hipSuccess) e = msl::launch_energy_report_batched(d, count, it, b->bar, st);
+        if (e == hipSuccess) e = msl::launch_energy_report_batched(d, count, it, b->bar,
+                                                                   std::min(8 * b->total_wgs, msl::MSL_BAR_WORDS), st);
         bool used = false;
         if (e == hipSuccess)
             e = msl::launch_pcg_batched(d, count, b->rows, b->total_wgs, it, b->bar, cooperative, st, &used);
@@ -809,7 +811,7 @@ hipError_t batch_enqueue(misslam_batch *b, hipStream_t st, bool cooperative) {
     }
     if (e == hipSuccess) e = msl::launch_point_pass_batched(d, count, k, b->total_pp, G, st);
     if (e == hipSuccess) e = msl::launch_node_energy_batched(d, count, b->total_ne, st);
-    if (e == hipSuccess) e = msl::launch_energy_report_batched(d, count, G, nullptr, st);
+    if (e == hipSuccess) e = msl::launch_energy_report_batched(d, count, G, nullptr, 0, st);
     return e;
 }
 

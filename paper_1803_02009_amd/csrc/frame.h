@@ -14,12 +14,16 @@ struct GraphView {
     int32_t *info;
 };
 
-// Sync area of a persistent solve: MSL_TAG_WORD0 words kept free, then 8 words
-// (4 tagged 8-byte words) for each of at most MSL_TAG_WGS workgroups of one
-// launch.  It must be zero when a solve starts.
-constexpr int MSL_TAG_WORD0 = 512;
+// Sync area of a persistent solve: 8 words (4 tagged 8-byte words) for each
+// of at most MSL_TAG_WGS workgroups of one launch.  The words of the
+// launch's workgroups must be zero when a solve starts.
 constexpr int MSL_TAG_WGS = 1024;
-constexpr int MSL_BAR_WORDS = MSL_TAG_WORD0 + 8 * MSL_TAG_WGS;
+constexpr int MSL_BAR_WORDS = 8 * MSL_TAG_WGS;
+// Sync words a persistent solve of m rows uses.
+inline int msl_sync_words(int m) {
+    const int g = (m + MISSLAM_SOLVE_ROWS - 1) / MISSLAM_SOLVE_ROWS;
+    return g < 1 ? 8 : (g > MSL_TAG_WGS ? MSL_BAR_WORDS : 8 * g);
+}
 
 // Uniform grid of the nodes for the kNN search.
 constexpr int MSL_GRID_CELLS = 1 << 18;
@@ -174,9 +178,10 @@ hipError_t launch_vjp_points(const StepArgs &a, const StepScratch &s, float sigm
 hipError_t launch_grad_params(const float *g, int m, const float *grad_e, float *out, hipStream_t st);
 hipError_t launch_energy_total(const misslam_report *rep, float w_data, float w_rot, float w_reg, double *out,
                                hipStream_t st);
-// zero_words (optional): MSL_BAR_WORDS words cleared on the way (the persistent solve's sync area)
+// zero_words (optional): zero_count words (a multiple of 4, 16-byte aligned) cleared on the way
+// (the next persistent solve's sync area)
 hipError_t launch_energy_report(const StepScratch &s, int64_t n, int m, misslam_report *rep, float reject_thr,
-                                hipStream_t st, unsigned *zero_words = nullptr);
+                                hipStream_t st, unsigned *zero_words = nullptr, int zero_count = 0);
 hipError_t launch_bjacobi(const GraphView &g, int m, const float *blocks, float lambda, float *minv,
                           int32_t *flags, hipStream_t st);
 // PCG solve into delta; when params != nullptr also applies params += delta (the GN update).
@@ -189,7 +194,7 @@ hipError_t launch_report_init(misslam_report *rep, int count, hipStream_t st);
 hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                                  float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
                                  float *params, hipStream_t st, bool *used,
-                                 bool bar_zeroed = false);
+                                 int zeroed_words = 0);
 int pcg_blocks(int m);
 // Batched launches: one grid covers every problem of items[0..count).
 hipError_t launch_normal_map_batched(const BatchItem *items, int count, int total_blocks, hipStream_t st);
@@ -197,7 +202,7 @@ hipError_t launch_point_pass_batched(const BatchItem *items, int count, int k, i
                                      hipStream_t st);
 hipError_t launch_assemble_batched(const BatchItem *items, int count, int k, int total_rows, int it, hipStream_t st);
 hipError_t launch_energy_report_batched(const BatchItem *items, int count, int it, unsigned *zero_words,
-                                        hipStream_t st);
+                                        int zero_count, hipStream_t st);
 hipError_t launch_node_energy_batched(const BatchItem *items, int count, int total_blocks, hipStream_t st);
 hipError_t launch_report_init_batched(const BatchItem *items, int count, int per_problem, hipStream_t st);
 // Side-by-side persistent solves: cooperative (co-residency checked by the

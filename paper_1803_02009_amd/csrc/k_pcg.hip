@@ -374,7 +374,7 @@ __device__ __forceinline__ double gather_dev(const double *part, int G, double (
 // workgroup reaches before every workgroup has read it.  The words must be
 // zero at launch (tags start at 1).
 __device__ __forceinline__ unsigned long long *tag_slots(unsigned *bar) {
-    return reinterpret_cast<unsigned long long *>(bar + MSL_TAG_WORD0);
+    return reinterpret_cast<unsigned long long *>(bar);
 }
 
 __device__ __forceinline__ void tag_publish(unsigned *bar, int gid, int which, unsigned tag, double v) {
@@ -712,9 +712,10 @@ __global__ void __launch_bounds__(kPcgThreads) pcg_persistent_kernel(PcgArgs A, 
 // Grid shape of the persistent solve for m rows on this device, or 0 when a
 // cooperative launch cannot hold it (the multi-kernel path is used then).
 // Rows are packed MISSLAM_SOLVE_ROWS to a workgroup: fewer workgroups make
-// the barriers cheaper, while the blocks of that many rows (about 13 per row
-// on a surface graph) still fit the LDS left beside the static arrays, and
-// one workgroup per CU must hold them all.
+// the exchanges cheaper, while the blocks of that many rows (about 13 per row
+// on a surface graph) still fit the LDS left beside the static arrays.  One
+// workgroup per CU must hold them all, so a larger system packs up to
+// kRowsPerBlk rows (blocks beyond the LDS cache are read from global memory).
 static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes) {
     static int max_blocks = -1, max_lds = 0;
     if (max_blocks < 0) {
@@ -741,7 +742,10 @@ static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes) {
         }
     }
     if (max_blocks <= 0 || m <= 0) return 0;
+    // more rows per workgroup once one workgroup per CU no longer holds the system
     rows_per_wg = MISSLAM_SOLVE_ROWS;
+    if (m > rows_per_wg * max_blocks) rows_per_wg = (m + max_blocks - 1) / max_blocks;
+    if (rows_per_wg > kRowsPerBlk) return 0;
     const int G = (m + rows_per_wg - 1) / rows_per_wg;
     if (G > max_blocks || G > MSL_TAG_WGS) return 0;
     lds_bytes = max_lds;
@@ -750,7 +754,7 @@ static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes) {
 
 hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                                  float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
-                                 float *params, hipStream_t st, bool *used, bool bar_zeroed) {
+                                 float *params, hipStream_t st, bool *used, int zeroed_words) {
     *used = false;
     int rows = 0, lds = 0;
     const int G = persistent_grid(m, rows, lds);
@@ -778,8 +782,7 @@ hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks,
     const int cache_blocks = (lds / 4 - kRowsPerBlk * 144) / 144;
     if (cache_blocks < 1) return hipSuccess;
     unsigned *bar = s.bar;
-    if (!bar_zeroed)
-        hipLaunchKernelGGL(fill_u32_kernel_pcg, dim3((MSL_BAR_WORDS + 255) / 256), dim3(256), 0, st, bar, MSL_BAR_WORDS);
+    if (zeroed_words < 8 * G) hipLaunchKernelGGL(fill_u32_kernel_pcg, dim3((8 * G + 255) / 256), dim3(256), 0, st, bar, 8 * G);
     void *args[] = {&A, (void *)&rows, (void *)&cache_blocks, &bar, &rep, &params};
     const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(pcg_persistent_kernel), dim3(G),
                                                     dim3(kPcgThreads), args, (unsigned)lds, st);

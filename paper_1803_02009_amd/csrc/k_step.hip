@@ -1049,10 +1049,12 @@ hipError_t launch_energy_total(const misslam_report *rep, float w_data, float w_
 
 __device__ __forceinline__ void energy_report_body(const double *__restrict__ pt_part, int npb,
                                                    const double *__restrict__ node_part, int m, misslam_report *rep,
-                                                   float reject_thr, unsigned *__restrict__ zero_words) {
+                                                   float reject_thr, unsigned *__restrict__ zero_words,
+                                                   int zero_count) {
     __shared__ double red[5][256 / kWave];
     if (zero_words)   // the next solve's sync area
-        for (int t = threadIdx.x; t < MSL_BAR_WORDS; t += 256) zero_words[t] = 0u;
+        for (int t = threadIdx.x; t < zero_count / 4; t += 256)
+            reinterpret_cast<uint4 *>(zero_words)[t] = make_uint4(0u, 0u, 0u, 0u);
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int t = threadIdx.x; t < npb; t += 256) {
         v[0] += pt_part[3 * t];
@@ -1091,8 +1093,8 @@ __device__ __forceinline__ void energy_report_body(const double *__restrict__ pt
 __global__ void __launch_bounds__(256) energy_report_kernel(const double *__restrict__ pt_part, int npb,
                                                             const double *__restrict__ node_part, int m,
                                                             misslam_report *rep, float reject_thr,
-                                                            unsigned *__restrict__ zero_words) {
-    energy_report_body(pt_part, npb, node_part, m, rep, reject_thr, zero_words);
+                                                            unsigned *__restrict__ zero_words, int zero_count) {
+    energy_report_body(pt_part, npb, node_part, m, rep, reject_thr, zero_words, zero_count);
 }
 
 hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_t st) {
@@ -1124,10 +1126,11 @@ hipError_t launch_assemble(const StepArgs &a, const StepScratch &s, hipStream_t 
 }
 
 hipError_t launch_energy_report(const StepScratch &s, int64_t n, int m, misslam_report *rep, float reject_thr,
-                                hipStream_t st, unsigned *zero_words) {
+                                hipStream_t st, unsigned *zero_words, int zero_count) {
     const int npb = (int)nblk(n > 0 ? n : 1, kPtBlock);
+    if (zero_count < 0 || zero_count > MSL_BAR_WORDS || zero_count % 4) return hipErrorInvalidValue;
     hipLaunchKernelGGL(energy_report_kernel, dim3(1), dim3(256), 0, st, s.pt_part, npb, s.node_part, m, rep,
-                       reject_thr, zero_words);
+                       reject_thr, zero_words, zero_count);
     return hipGetLastError();
 }
 
@@ -1170,10 +1173,11 @@ __global__ void __launch_bounds__(256) node_energy_batched_kernel(const BatchIte
 
 // One workgroup per problem.
 __global__ void __launch_bounds__(256) energy_report_batched_kernel(const BatchItem *__restrict__ items, int gi,
-                                                                    unsigned *__restrict__ zero_words) {
+                                                                    unsigned *__restrict__ zero_words,
+                                                                    int zero_count) {
     const BatchItem &it = items[blockIdx.x];
     energy_report_body(it.s.pt_part, it.npb, it.s.node_part, it.a.nd.m, it.rep + gi, it.reject,
-                       blockIdx.x == 0 ? zero_words : nullptr);
+                       blockIdx.x == 0 ? zero_words : nullptr, zero_count);
 }
 
 hipError_t launch_point_pass_batched(const BatchItem *items, int count, int k, int64_t total_blocks, int it,
@@ -1211,9 +1215,11 @@ hipError_t launch_assemble_batched(const BatchItem *items, int count, int k, int
 }
 
 hipError_t launch_energy_report_batched(const BatchItem *items, int count, int it, unsigned *zero_words,
-                                        hipStream_t st) {
+                                        int zero_count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(energy_report_batched_kernel, dim3(count), dim3(256), 0, st, items, it, zero_words);
+    if (zero_count < 0 || zero_count > MSL_BAR_WORDS || zero_count % 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(energy_report_batched_kernel, dim3(count), dim3(256), 0, st, items, it, zero_words,
+                       zero_count);
     return hipGetLastError();
 }
 
