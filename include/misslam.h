@@ -55,6 +55,14 @@ typedef enum {
 #define MISSLAM_WEIGHT_GAUSS  0   /* w_j ~ exp(-|v-g_j|^2 / (2 sigma^2)), normalised over k */
 #define MISSLAM_WEIGHT_LINEAR 1   /* Eq.(2): w_j ~ max(0, 1 - |v-g_j| / d_(k+1)), normalised */
 
+/* The one-launch PCG needs all of its workgroups (at most one per CU) resident
+ * at once, since they wait for each other's partials. */
+#define MISSLAM_LAUNCH_PLAIN 0       /* an ordinary launch: all are resident when no other work holds the CUs
+                                        (the usual case on the library's stream); a workgroup that waits too
+                                        long sets MISSLAM_FLAG_SYNC_TIMEOUT */
+#define MISSLAM_LAUNCH_COOPERATIVE 1 /* a cooperative launch: residency guaranteed by the runtime, at about
+                                        15 us more per solve */
+
 #define MISSLAM_PREC_FP32 0       /* plain float32 normal equations */
 #define MISSLAM_PREC_BF16 1       /* data-term products in bfloat16 on the matrix cores, float32 accumulation */
 #define MISSLAM_PREC_FP16 2       /* same with float16 inputs */
@@ -128,6 +136,7 @@ typedef struct {
     int32_t precision;         /* MISSLAM_PREC_* */
     int32_t refine_steps;      /* iterative-refinement steps for BF16/FP16 */
     float reject_threshold;    /* mean |r| above which FRAME_REJECT is set; <= 0 disables */
+    int32_t solve_launch;      /* MISSLAM_LAUNCH_*: how the one-launch PCG is started */
 } misslam_params;
 
 /* one entry per Gauss-Newton iteration, plus a final entry at the returned parameters (device) */

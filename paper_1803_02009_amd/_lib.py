@@ -13,6 +13,7 @@ FLAG_NONSPD_BLOCK, FLAG_PCG_BREAKDOWN, FLAG_NONFINITE, FLAG_FRAME_REJECT, FLAG_G
 FLAG_SYNC_TIMEOUT = 32
 WEIGHT_GAUSS, WEIGHT_LINEAR = 0, 1
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
+LAUNCH_PLAIN, LAUNCH_COOPERATIVE = 0, 1
 MAX_K, MAX_PCG, MAX_ROW, MAX_LIST, SOLVE_ROWS = 8, 64, 32, 2048, 16
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
@@ -54,7 +55,8 @@ class Params(ctypes.Structure):
                 ("w_rot", ctypes.c_float), ("w_reg", ctypes.c_float), ("w_data", ctypes.c_float),
                 ("eps_d", ctypes.c_double), ("cos_eps_n", ctypes.c_double), ("lambda_", ctypes.c_float),
                 ("gn_iters", ctypes.c_int32), ("pcg_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("refine_steps", ctypes.c_int32), ("reject_threshold", ctypes.c_float)]
+                ("refine_steps", ctypes.c_int32), ("reject_threshold", ctypes.c_float),
+                ("solve_launch", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):

@@ -176,7 +176,8 @@ bool valid_params(const misslam_params *p) {
            (p->weight_kind != MISSLAM_WEIGHT_GAUSS || p->sigma > 0.f) && p->gn_iters >= 0 && p->pcg_iters >= 0 &&
            p->pcg_iters <= MISSLAM_MAX_PCG && std::isfinite(p->lambda) && p->lambda >= 0.f &&
            std::isfinite(p->w_rot) && std::isfinite(p->w_reg) && std::isfinite(p->w_data) &&
-           p->precision >= MISSLAM_PREC_FP32 && p->precision <= MISSLAM_PREC_FP16 && p->refine_steps >= 0;
+           p->precision >= MISSLAM_PREC_FP32 && p->precision <= MISSLAM_PREC_FP16 && p->refine_steps >= 0 &&
+           (p->solve_launch == MISSLAM_LAUNCH_PLAIN || p->solve_launch == MISSLAM_LAUNCH_COOPERATIVE);
 }
 
 bool valid_points(const misslam_points *p) {
@@ -236,6 +237,7 @@ void misslam_default_params(misslam_params *p) {
     p->precision = MISSLAM_PREC_FP32;
     p->refine_steps = 0;
     p->reject_threshold = 0.0f;
+    p->solve_launch = MISSLAM_LAUNCH_PLAIN;
 }
 
 const char *misslam_status_string(int32_t s) {
@@ -314,10 +316,11 @@ static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, i
 // different (but in each path fixed) order, so the two agree to rounding.
 static hipError_t solve_persistent(const msl::GraphView &g, int m, const float *blocks, const float *gvec,
                                    const float *minv, float lambda, int iters, float *delta, const msl::PcgScratch &s,
-                                   misslam_report *rep, float *params, hipStream_t st, int zeroed_words = 0) {
+                                   misslam_report *rep, float *params, hipStream_t st, bool coop,
+                                   int zeroed_words = 0) {
     bool used = false;
     hipError_t e = msl::launch_pcg_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st,
-                                              &used, zeroed_words);
+                                              &used, coop, zeroed_words);
     if (e == hipSuccess && !used)
         e = msl::launch_pcg_update(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st);
     return e;
@@ -325,7 +328,7 @@ static hipError_t solve_persistent(const msl::GraphView &g, int m, const float *
 
 static hipError_t solve(const msl::GraphView &g, int m, const float *blocks, const float *gvec, float *minv,
                         float lambda, int iters, float *delta, const msl::PcgScratch &s, misslam_report *rep,
-                        float *params, hipStream_t st) {
+                        float *params, hipStream_t st, bool coop) {
     hipError_t e;
     {
         Timed t(PH_BJACOBI, st);
@@ -333,7 +336,7 @@ static hipError_t solve(const msl::GraphView &g, int m, const float *blocks, con
     }
     if (e == hipSuccess) {
         Timed t(PH_PCG, st);
-        e = solve_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st);
+        e = solve_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st, coop);
     }
     return e;
 }
@@ -401,7 +404,8 @@ misslam_status misslam_pcg_solve(const misslam_graph *graph, int32_t m, const fl
     const msl::GraphView gv = view(graph);
     hipError_t e = msl::launch_report_init(rep, 1, st);
     if (e == hipSuccess)
-        e = solve(gv, m, blocks, g, L.step.minv, params->lambda, params->pcg_iters, delta, L.pcg, rep, nullptr, st);
+        e = solve(gv, m, blocks, g, L.step.minv, params->lambda, params->pcg_iters, delta, L.pcg, rep, nullptr, st,
+                  params->solve_launch == MISSLAM_LAUNCH_COOPERATIVE);
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
 }
 
@@ -418,6 +422,7 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
     if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
     if ((int64_t)graph->bsr_cap > (int64_t)nodes->m * MISSLAM_MAX_ROW) return MISSLAM_ECAPACITY;
     const bool lowp = params->precision != MISSLAM_PREC_FP32;
+    const bool coop = params->solve_launch == MISSLAM_LAUNCH_COOPERATIVE;
     const hipStream_t st = stream_of(stream);
     const int G = params->gn_iters;
     const int64_t n = points->n;
@@ -449,7 +454,7 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
             if (e == hipSuccess) {
                 Timed t(PH_PCG, st);
                 e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
-                                     L.delta, L.pcg, rep + it, nodes->params, st, msl::msl_sync_words(m));
+                                     L.delta, L.pcg, rep + it, nodes->params, st, coop, msl::msl_sync_words(m));
             }
             continue;
         }
@@ -466,7 +471,7 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
         if (e == hipSuccess) {
             Timed t(PH_PCG, st);
             e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
-                                 L.delta, L.pcg, rep + it, nullptr, st);
+                                 L.delta, L.pcg, rep + it, nullptr, st, coop);
         }
         for (int r = 0; r < params->refine_steps && e == hipSuccess; ++r) {
             {
@@ -476,7 +481,7 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
             if (e == hipSuccess) {
                 Timed t(PH_PCG, st);
                 e = solve_persistent(view(graph), m, L.blocks, L.rhs, L.step.minv, params->lambda, params->pcg_iters,
-                                     L.delta2, L.pcg, L.rep, nullptr, st);
+                                     L.delta2, L.pcg, L.rep, nullptr, st, coop);
             }
             if (e == hipSuccess) e = msl::launch_axpy(L.delta, L.delta2, 12 * m, st);
         }
@@ -806,7 +811,8 @@ hipError_t batch_enqueue(misslam_batch *b, hipStream_t st, bool cooperative) {
                                                                    std::min(8 * b->total_wgs, msl::MSL_BAR_WORDS), st);
         bool used = false;
         if (e == hipSuccess)
-            e = msl::launch_pcg_batched(d, count, b->rows, b->total_wgs, it, b->bar, cooperative, st, &used);
+            e = msl::launch_pcg_batched(d, count, b->rows, b->total_wgs, it, b->bar,
+                                        cooperative && b->params.solve_launch == MISSLAM_LAUNCH_COOPERATIVE, st, &used);
         if (e == hipSuccess && !used) return hipErrorInvalidConfiguration;
     }
     if (e == hipSuccess) e = msl::launch_point_pass_batched(d, count, k, b->total_pp, G, st);

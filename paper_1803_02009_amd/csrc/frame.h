@@ -189,11 +189,13 @@ hipError_t launch_pcg_update(const GraphView &g, int m, const float *blocks, con
                              float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
                              float *params, hipStream_t st);
 hipError_t launch_report_init(misslam_report *rep, int count, hipStream_t st);
-// Same solve as launch_pcg_update in one cooperative launch; *used = false when
-// the device cannot co-schedule it (nothing launched, caller falls back).
+// Same solve as launch_pcg_update in one launch whose workgroups must all be
+// resident (cooperative: guaranteed by the runtime; plain: no other work may
+// hold the CUs); *used = false when the device cannot hold the grid at once
+// (nothing launched, caller falls back).
 hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                                  float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
-                                 float *params, hipStream_t st, bool *used,
+                                 float *params, hipStream_t st, bool *used, bool cooperative,
                                  int zeroed_words = 0);
 int pcg_blocks(int m);
 // Batched launches: one grid covers every problem of items[0..count).

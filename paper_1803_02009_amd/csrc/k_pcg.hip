@@ -754,7 +754,7 @@ static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes) {
 
 hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                                  float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
-                                 float *params, hipStream_t st, bool *used, int zeroed_words) {
+                                 float *params, hipStream_t st, bool *used, bool cooperative, int zeroed_words) {
     *used = false;
     int rows = 0, lds = 0;
     const int G = persistent_grid(m, rows, lds);
@@ -783,9 +783,16 @@ hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks,
     if (cache_blocks < 1) return hipSuccess;
     unsigned *bar = s.bar;
     if (zeroed_words < 8 * G) hipLaunchKernelGGL(fill_u32_kernel_pcg, dim3((8 * G + 255) / 256), dim3(256), 0, st, bar, 8 * G);
-    void *args[] = {&A, (void *)&rows, (void *)&cache_blocks, &bar, &rep, &params};
-    const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(pcg_persistent_kernel), dim3(G),
-                                                    dim3(kPcgThreads), args, (unsigned)lds, st);
+    hipError_t e;
+    if (cooperative) {
+        void *args[] = {&A, (void *)&rows, (void *)&cache_blocks, &bar, &rep, &params};
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(pcg_persistent_kernel), dim3(G),
+                                       dim3(kPcgThreads), args, (unsigned)lds, st);
+    } else {
+        hipLaunchKernelGGL(pcg_persistent_kernel, dim3(G), dim3(kPcgThreads), (unsigned)lds, st, A, rows,
+                           cache_blocks, bar, rep, params);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) *used = true;
     return e;
 }

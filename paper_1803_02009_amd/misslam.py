@@ -48,11 +48,12 @@ class Params:
     precision: int = _lib.PREC_FP32
     refine_steps: int = 0
     reject_threshold: float = 0.0
+    solve_launch: int = _lib.LAUNCH_PLAIN
 
     def c(self):
         return _lib.Params(self.k, self.weight_kind, self.sigma, self.w_rot, self.w_reg, self.w_data, self.eps_d,
                            self.cos_eps_n, self.lam, self.gn_iters, self.pcg_iters, self.precision,
-                           self.refine_steps, self.reject_threshold)
+                           self.refine_steps, self.reject_threshold, self.solve_launch)
 
 
 def camera(width, height, fx, fy, cx, cy):

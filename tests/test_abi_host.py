@@ -45,8 +45,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(misslam_camera), sizeof(misslam_pose),
          sizeof(misslam_points), sizeof(misslam_nodes), sizeof(misslam_graph), sizeof(misslam_params),
          sizeof(misslam_report), sizeof(misslam_fuse_params), sizeof(misslam_problem));
-  printf("%zu %zu %zu %zu\n", offsetof(misslam_params, eps_d), offsetof(misslam_params, lambda),
-         offsetof(misslam_report, n_valid), offsetof(misslam_graph, info));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(misslam_params, eps_d), offsetof(misslam_params, lambda),
+         offsetof(misslam_report, n_valid), offsetof(misslam_graph, info), offsetof(misslam_params, solve_launch));
   return 0;
 }
 """
@@ -62,7 +62,18 @@ int main(void) {
     assert sizes == want
     offs = [int(v) for v in out[1].split()]
     assert offs == [_lib.Params.eps_d.offset, _lib.Params.lambda_.offset, _lib.Report.n_valid.offset,
-                    _lib.Graph.info.offset]
+                    _lib.Graph.info.offset, _lib.Params.solve_launch.offset]
+
+
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+    defs = {k: int(v, 0) for k, v in re.findall(r"#define\s+MISSLAM_([A-Z_0-9]+)\s+(-?(?:0x[0-9a-fA-F]+|\d+))", text)}
+    want = {"FLAG_SYNC_TIMEOUT": _lib.FLAG_SYNC_TIMEOUT, "PREC_FP32": _lib.PREC_FP32, "PREC_BF16": _lib.PREC_BF16,
+            "PREC_FP16": _lib.PREC_FP16, "LAUNCH_PLAIN": _lib.LAUNCH_PLAIN,
+            "LAUNCH_COOPERATIVE": _lib.LAUNCH_COOPERATIVE, "MAX_K": _lib.MAX_K, "MAX_PCG": _lib.MAX_PCG,
+            "MAX_ROW": _lib.MAX_ROW, "MAX_LIST": _lib.MAX_LIST, "SOLVE_ROWS": _lib.SOLVE_ROWS}
+    for k, v in want.items():
+        assert defs[k] == v, k
 
 
 def test_default_params_are_the_papers(lib):
@@ -71,6 +82,7 @@ def test_default_params_are_the_papers(lib):
     assert (p.k, p.w_rot, p.w_reg, p.w_data, p.eps_d) == (4, 1000.0, 10000.0, 1.0, 15.0)
     assert abs(p.cos_eps_n - 0.984807753012208) < 1e-15
     assert (p.gn_iters, p.pcg_iters, p.precision) == (10, 10, _lib.PREC_FP32)
+    assert p.solve_launch == _lib.LAUNCH_PLAIN
 
 
 def test_status_strings(lib):
@@ -93,6 +105,9 @@ def test_workspace_query(lib):
     assert lib.misslam_workspace_bytes(10, 10, 64, 48, ctypes.byref(bad)) == 0
     bad.k = 4
     bad.pcg_iters = _lib.MAX_PCG + 1
+    assert lib.misslam_workspace_bytes(10, 10, 64, 48, ctypes.byref(bad)) == 0
+    bad.pcg_iters = 10
+    bad.solve_launch = 2
     assert lib.misslam_workspace_bytes(10, 10, 64, 48, ctypes.byref(bad)) == 0
 
 

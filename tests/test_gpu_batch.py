@@ -41,13 +41,13 @@ def _single(problems):
     return [x.cpu().numpy() for x in xs], [s.M.read_report(r) for s, r in zip(problems, reps)]
 
 
-def _batch(problems, rows, calls=1):
+def _batch(problems, rows, calls=1, params=None):
     M = problems[0].M
     items = []
     for s in problems:
         items.append(dict(points=s.pts, nodes=s.nodes, x=s.M.identity_params(s.m), graph=s.graph, depth=s.depth,
                           cam=s.cam, pose=s.pose))
-    params = problems[0].params
+    params = params or problems[0].params
     bt = M.Batch(items, params, rows_per_wg=rows)
     outs = []
     for _ in range(calls):
@@ -71,6 +71,18 @@ def test_batch_equals_single_calls_bitwise(problems):
             assert rb[i].tobytes() == reps[i].tobytes(), (call, i)
     for r in reps:
         assert np.all(r["flags"] == 0)
+
+
+def test_batch_cooperative_launch_equals_single_calls_bitwise(problems):
+    import dataclasses
+    from paper_1803_02009_amd import _lib
+    xs, reps = _single(problems)
+    p = dataclasses.replace(problems[0].params, solve_launch=_lib.LAUNCH_COOPERATIVE)
+    outs, tile = _batch(problems, SOLVE_ROWS, calls=1, params=p)
+    xb, rb = outs[0]
+    for i in range(len(problems)):
+        assert np.array_equal(xb[i].view(np.uint32), xs[i].view(np.uint32)), i
+        assert rb[i].tobytes() == reps[i].tobytes(), i
 
 
 def test_batch_autotuned_tile(problems):
