@@ -32,6 +32,41 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP32_VALU_PEAK = 157.3       # TFLOP/s vendor figure
 
+# source files each timed kernel is compiled from (its counter figures are void once any of them changes)
+KERNEL_SOURCES = {
+    "point_pass": ["k_step.hip"],
+    "assemble": ["k_step.hip"],
+    "pcg": ["k_pcg.hip"],
+}
+COUNTERS_MD = os.path.join(ROOT, "profiles", "c3_hbm_counters.md")
+
+
+def kernel_source_hash(phase):
+    """Short sha256 of the sources a phase's kernel is built from (its own file and the shared headers)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1803_02009_amd", "csrc")
+    for f in KERNEL_SOURCES[phase] + ["common.h", "frame.h"]:
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "misslam.h"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(phase):
+    """HBM bytes per launch of a phase's kernel from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, each scaled by its reading for a plain copy of known size), or None when the summary
+    has no row for it or was taken on other sources."""
+    if not os.path.exists(COUNTERS_MD):
+        return None
+    for line in open(COUNTERS_MD):
+        cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+        if len(cells) == 7 and cells[0] == phase:
+            try:
+                return int(cells[5]) if cells[6] == kernel_source_hash(phase) else None
+            except ValueError:
+                return None
+    return None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -70,7 +105,7 @@ def algorithmic_bytes(phase, n, m, nnzb, k, width, height, pcg_iters, n_valid):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the per-frame registration does not shard across GPUs).", file=sys.stderr)
         sys.exit(2)
     import torch
@@ -166,7 +201,7 @@ def main():
         abytes = algorithmic_bytes(ph, n, m, nnzb, params.k, cam.width, cam.height, params.pcg_iters, n_valid)
         achieved = abytes / (phases[ph]["avg_us"] * 1e-6) / 1e9
         lines[ph] = {"kernel": ph, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(ph),
                      "algorithmic_bytes_per_launch": int(abytes), "avg_launch_us": round(phases[ph]["avg_us"], 2),
                      "ms_per_frame": round(phases[ph]["total_ms"] / args.steps, 4)}
     dominant = max(lines, key=lambda p: lines[p]["ms_per_frame"])
