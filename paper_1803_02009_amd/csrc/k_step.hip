@@ -114,21 +114,24 @@ __global__ void __launch_bounds__(kPtBlock) point_pass_kernel(StepArgs a, StepSc
 // symmetric in (c, c') and in (a, a'): 10 x 6 = 60 values.  The 12x12 block is
 //   H_jl[(c,a),(c',a')] = S[c,c',a,a'] + delta_c' S[c,3,a,a'],  delta = (g_j - g_l, 0)
 // because the second factor of the data Jacobian is (v_p - g_l, 1) = u + delta.
-__constant__ int kPairC0[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
-__constant__ int kPairC1[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
-__constant__ int kPairA0[6] = {0, 0, 0, 1, 1, 2};
-__constant__ int kPairA1[6] = {0, 1, 2, 1, 2, 2};
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
+// pairs c <= c' of 0..3 (t = 0..9) and a <= a' of 0..2 (t = 0..5), as arithmetic so that unrolled
+// loops fold them to constants
+__device__ __forceinline__ constexpr int pair_c0(int t) { return t < 4 ? 0 : t < 7 ? 1 : t < 9 ? 2 : 3; }
+__device__ __forceinline__ constexpr int pair_c1(int t) { return t < 4 ? t : t < 7 ? t - 3 : t < 9 ? t - 5 : 3; }
+__device__ __forceinline__ constexpr int pair_a0(int t) { return t < 3 ? 0 : t < 5 ? 1 : 2; }
+__device__ __forceinline__ constexpr int pair_a1(int t) { return t < 3 ? t : t < 5 ? t - 2 : 2; }
+
+// (arithmetic, not a table: a table index becomes a memory load)
 __device__ __forceinline__ int pc_index(int c, int d) {  // c, d in 0..3
     const int lo = c < d ? c : d, hi = c < d ? d : c;
     // rows of the upper triangle: lo=0 -> 0..3, lo=1 -> 4..6, lo=2 -> 7..8, lo=3 -> 9
-    const int start[4] = {0, 4, 7, 9};
-    return start[lo] + (hi - lo);
+    return 4 * lo - (lo * (lo - 1)) / 2 + (hi - lo);
 }
 __device__ __forceinline__ int na_index(int a, int b) {  // a, b in 0..2
     const int lo = a < b ? a : b, hi = a < b ? b : a;
-    const int start[3] = {0, 3, 5};
-    return start[lo] + (hi - lo);
+    return 3 * lo - (lo * (lo - 1)) / 2 + (hi - lo);
 }
 
 constexpr int kAsmThreads = 64;
@@ -153,9 +156,10 @@ struct RowNode {
 template <int K>
 struct AsmShared {
     float accS[kAsmWaves][MISSLAM_MAX_ROW][64];
-    float Pc[kAsmWaves][kBatch][10];
-    float Na[kAsmWaves][kBatch][6];
-    float4 W[kAsmWaves][kBatch][(K + 3) / 4];
+    // kBatch + 9 per row: conflict-free by entry and by statistic entry, and room for the read-ahead
+    float Pc[kAsmWaves][10][kBatch + 9];
+    float Na[kAsmWaves][6][kBatch + 9];
+    float4 W[kAsmWaves][kBatch + 8][(K + 3) / 4];
     uint32_t key[kAsmWaves][kBatch][2];
     double gw[kAsmWaves][12];
     RowNode<kAsmThreads> rn;
@@ -235,7 +239,7 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
         for (int t = 0; t < nslots; ++t) {
             if (rn.cols[t] == j) continue;
             const float eh[4] = {rn.rg[t][0], rn.rg[t][1], rn.rg[t][2], 1.f};
-            sacc = fmaf(eh[kPairC0[tid]], eh[kPairC1[tid]], sacc);
+            sacc = fmaf(eh[pair_c0(tid)], eh[pair_c1(tid)], sacc);
         }
         rn.EE[tid] = sacc;
     }
@@ -247,26 +251,40 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
         s.node_part[2 * j + 0] = erot;
         s.node_part[2 * j + 1] = ereg_tot;
     }
-    int deg = 0;
-    for (int q = 0; q < nslots; ++q) deg += rn.cols[q] != j;
+    int deg = 0, dsl = -1;
+    for (int q = 0; q < nslots; ++q) {
+        deg += rn.cols[q] != j;
+        if (rn.cols[q] == j) dsl = q;
+    }
+    deg = __builtin_amdgcn_readfirstlane(deg);
+    dsl = __builtin_amdgcn_readfirstlane(dsl);
     const float wd = a.w_data, wreg = a.w_reg, wrot = a.w_rot;
     float *outb = a.blocks + (size_t)rb * 144;
-    for (int t = tid; t < nslots * 144; t += NT) {
-        const int sl = t / 144, en = t % 144;
+    // each thread owns entries en of every block of the row; the slots' loads are independent
+    for (int en = tid; en < 144; en += NT) {
         const int R = en / 12, C = en % 12;
         const int c = R / 3, aa = R % 3, c2 = C / 3, a2 = C % 3;
-        const int l = rn.cols[sl];
-        const float hd = data(sl, R, C);
-        float reg = 0.f, rot = 0.f;
-        if (l != j) {
-            if (aa == a2) {
-                const float eh_c = c < 3 ? rn.rg[sl][c] : 1.f;
-                const float fh_c2 = c2 < 3 ? -rn.rg[sl][c2] : 1.f;
-                if (c2 == 3) reg -= eh_c;      // edge j -> l
-                if (c == 3) reg -= fh_c2;      // edge l -> j
-            }
-        } else {
-            if (aa == a2) {
+        const bool same_a = aa == a2;
+        // straight-line body (selects, no branches) so that the slots' loads overlap; the diagonal slot
+        // gets this value too and is overwritten below (same thread, same address: in order)
+#pragma unroll 4
+        for (int sl = 0; sl < nslots; ++sl) {   // edges j -> l
+            const float hd = data(sl, R, C, true);
+            const float rgc = rn.rg[sl][c < 3 ? c : 0], rgc2 = rn.rg[sl][c2 < 3 ? c2 : 0];
+            const float eh_c = c < 3 ? rgc : 1.f;
+            const float fh_c2 = c2 < 3 ? -rgc2 : 1.f;
+            const float r1 = c2 == 3 ? 0.f - eh_c : 0.f;   // edge j -> l
+            const float r2 = c == 3 ? r1 - fh_c2 : r1;     // edge l -> j
+            const float reg = same_a ? r2 : 0.f;
+            const float rr = fmaf(wrot, 0.f, wreg * reg);
+            const float h = fmaf(wreg, reg, wd * hd);
+            outb[(size_t)sl * 144 + en] = h;
+            if (rr_out) rr_out[(size_t)(rb + sl) * 144 + en] = rr;
+        }
+        if (dsl >= 0) {   // the diagonal block: regulariser and rotation terms of node j
+            const float hd = data(dsl, R, C, false);
+            float reg = 0.f, rot = 0.f;
+            if (same_a) {
                 reg = rn.EE[pc_index(c, c2)];
                 if (c == 3 && c2 == 3) reg += (float)deg;
             }
@@ -274,12 +292,12 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
 #pragma unroll
                 for (int q = 0; q < 6; ++q) rot = fmaf(rn.Jr[q][R], rn.Jr[q][C], rot);
             }
+            const float rr = fmaf(wrot, rot, wreg * reg);
+            const float h = fmaf(wrot, rot, fmaf(wreg, reg, wd * hd));
+            rn.Hd[R][C] = (double)h + (R == C ? (double)a.lambda : 0.0);
+            outb[(size_t)dsl * 144 + en] = h;
+            if (rr_out) rr_out[(size_t)(rb + dsl) * 144 + en] = rr;
         }
-        const float rr = fmaf(wrot, rot, wreg * reg);
-        const float h = l != j ? fmaf(wreg, reg, wd * hd) : fmaf(wrot, rot, fmaf(wreg, reg, wd * hd));
-        if (l == j) rn.Hd[R][C] = (double)h + (R == C ? (double)a.lambda : 0.0);
-        outb[(size_t)sl * 144 + en] = h;
-        if (rr_out) rr_out[(size_t)(rb + sl) * 144 + en] = rr;
     }
     if (tid < 12) {
         const int c = tid / 3, aa = tid % 3;
@@ -316,6 +334,23 @@ struct EntryRegs {
     uint32_t k0, k1;
 };
 
+// The data of list entry le whose point p is already known.
+template <int K>
+__device__ __forceinline__ void entry_data(const StepArgs &a, const StepScratch &s, int64_t n, int le, int p,
+                                           EntryRegs<K> &r) {
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        r.q[t] = a.g.knn_idx[(int64_t)t * n + p];
+        r.wq[t] = a.g.knn_w[(int64_t)t * n + p];
+    }
+    r.nr = s.nr[p];
+    r.vx = a.pts.px[p];
+    r.vy = a.pts.py[p];
+    r.vz = a.pts.pz[p];
+    r.k0 = a.g.list_key[2 * (size_t)le];
+    r.k1 = a.g.list_key[2 * (size_t)le + 1];
+}
+
 template <int K>
 __device__ __forceinline__ void entry_load(const StepArgs &a, const StepScratch &s, int64_t n, int le,
                                            EntryRegs<K> &r) {
@@ -345,7 +380,7 @@ template <int K>
 __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const StepScratch &s, int j) {
     __shared__ AsmShared<K> sh;
     const int tid = threadIdx.x;
-    const int wave = tid / kWave, lane = tid % kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
     const int64_t n = a.pts.n;
 
     // an overflowed pattern (flagged by the graph build) is clamped to the capacity
@@ -363,9 +398,13 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
     const int quota = (cnt + kAsmWaves - 1) / kAsmWaves;
     const int my0 = min(cnt, wave * quota), my1 = min(cnt, my0 + quota);
     const int nbatch = (my1 - my0 + kBatch - 1) / kBatch;
-    // the first batch's entries are fetched before the node-level loads are waited for
+    // Entries are fetched in two stages: the point index two batches ahead (coalesced), the point's data one
+    // batch ahead (gathers whose addresses are known by then), so no wait in the loop is a chain of two
+    // dependent loads.  The first batch's entries are fetched before the node-level loads are waited for.
     EntryRegs<K> nxt;
+    int pnext = 0;   // point of this lane's entry in the next batch
     if (nbatch > 0 && lane < min(kBatch, my1 - my0)) entry_load<K>(a, s, n, lb + my0 + lane, nxt);
+    if (nbatch > 1 && lane < min(kBatch, my1 - my0 - kBatch)) pnext = a.g.list_pts[lb + my0 + kBatch + lane];
     const double e_reg = row_prepare<kAsmThreads>(a, sh.rn, j, nslots, gjx, gjy, gjz);
 
     const int e = lane;                      // statistic entry owned in phase 2 (e < 60)
@@ -373,7 +412,25 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
     float acc[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] = 0.f;
+    f32x4_t acc4 = {0.f, 0.f, 0.f, 0.f};   // K <= 4: the run's sums on the matrix cores (lane e, register q)
     uint32_t cur0 = 0xFFFFFFFFu, cur1 = 0xFFFFFFFFu;
+    // a finished run's sums into the slots of its kNN set's nodes (distinct slots: reads, then writes)
+    auto flush = [&](uint32_t k0, uint32_t k1, float(&ac)[K]) {
+        if (k0 != 0xFFFFFFFFu && e < 60) {
+            uint32_t slot[K];
+            float old[K];
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                slot[q] = q < 4 ? (k0 >> (8 * q)) & 0xFF : (k1 >> (8 * (q - 4))) & 0xFF;
+                old[q] = slot[q] < (uint32_t)nslots ? sh.accS[wave][slot[q]][e] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < K; ++q)
+                if (slot[q] < (uint32_t)nslots) sh.accS[wave][slot[q]][e] = old[q] + ac[q];
+        }
+#pragma unroll
+        for (int q = 0; q < K; ++q) ac[q] = 0.f;
+    };
     double gacc[12];                 // data gradient: float64, it cancels near convergence
 #pragma unroll
     for (int q = 0; q < 12; ++q) gacc[q] = 0.0;
@@ -382,12 +439,20 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
         const int e0 = my0 + bt * kBatch;
         const int nb = min(kBatch, my1 - e0);
         EntryRegs<K> cu = nxt;
-        // prefetch the next batch while this one is staged and accumulated
+        // prefetch: the next batch's data, then the point indices of the batch after next (issued last, so
+        // that waiting for this batch's data never waits for them)
         if (bt + 1 < nbatch && lane < min(kBatch, my1 - e0 - kBatch))
-            entry_load<K>(a, s, n, lb + e0 + kBatch + lane, nxt);
-        // ---- phase 1: lane = list entry
-        bool start = false;
-        if (lane < nb) {
+            entry_data<K>(a, s, n, lb + e0 + kBatch + lane, pnext, nxt);
+        if (bt + 2 < nbatch && lane < min(kBatch, my1 - e0 - 2 * kBatch))
+            pnext = a.g.list_pts[lb + e0 + 2 * kBatch + lane];
+        // ---- phase 1: lane = list entry.  An entry whose point has no correspondence (n' = 0 from the point
+        // pass) adds nothing, so the valid entries are packed in order (position pv) for phase 2.
+        const bool valid = lane < nb && (cu.nr.x != 0.f || cu.nr.y != 0.f || cu.nr.z != 0.f);
+        const uint64_t vmask = __ballot(valid);
+        const int pv = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(vmask >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)vmask, 0u));
+        const int np = __builtin_amdgcn_readfirstlane(__popcll(vmask));
+        if (valid) {
             float wj = 0.f;
 #pragma unroll
             for (int t = 0; t < K; ++t)
@@ -408,17 +473,17 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
             const float uu[4] = {cu.vx - gjx, cu.vy - gjy, cu.vz - gjz, 1.f};
             const float nn[3] = {cu.nr.x, cu.nr.y, cu.nr.z};
 #pragma unroll
-            for (int t = 0; t < 10; ++t) sh.Pc[wave][lane][t] = uu[kPairC0[t]] * uu[kPairC1[t]];
+            for (int t = 0; t < 10; ++t) sh.Pc[wave][t][pv] = uu[pair_c0(t)] * uu[pair_c1(t)];
 #pragma unroll
-            for (int t = 0; t < 6; ++t) sh.Na[wave][lane][t] = nn[kPairA0[t]] * nn[kPairA1[t]];
+            for (int t = 0; t < 6; ++t) sh.Na[wave][t][pv] = nn[pair_a0(t)] * nn[pair_a1(t)];
             float wv[4 * ((K + 3) / 4)];
 #pragma unroll
             for (int t = 0; t < 4 * ((K + 3) / 4); ++t) wv[t] = t < K ? wj * cu.wq[t] : 0.f;
 #pragma unroll
             for (int t = 0; t < (K + 3) / 4; ++t)
-                sh.W[wave][lane][t] = make_float4(wv[4 * t], wv[4 * t + 1], wv[4 * t + 2], wv[4 * t + 3]);
-            sh.key[wave][lane][0] = cu.k0;
-            sh.key[wave][lane][1] = cu.k1;
+                sh.W[wave][pv][t] = make_float4(wv[4 * t], wv[4 * t + 1], wv[4 * t + 2], wv[4 * t + 3]);
+            sh.key[wave][pv][0] = cu.k0;
+            sh.key[wave][pv][1] = cu.k1;
             const float wr = wj * cu.nr.w;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -427,91 +492,114 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
                 for (int aa = 0; aa < 3; ++aa) gacc[3 * c + aa] = fma((double)f, (double)nn[aa], gacc[3 * c + aa]);
             }
         }
-        // run starts: an entry whose kNN set differs from the previous entry's
+        wave_sync();
+        // run starts among the packed entries: an entry whose kNN set differs from the previous one's (the
+        // list is ordered by set, so equal sets stay contiguous after packing)
+        bool start = false;
+        if (lane < np) {
+            const uint32_t q0 = lane == 0 ? cur0 : sh.key[wave][lane - 1][0];
+            const uint32_t q1 = lane == 0 ? cur1 : sh.key[wave][lane - 1][1];
+            start = sh.key[wave][lane][0] != q0 || sh.key[wave][lane][1] != q1;
+        }
+        const uint64_t starts = __ballot(start);
+        // ---- phase 2: lane = statistic entry, the entries in order; a run of equal kNN sets ends by adding
+        // its sums into the slots of its nodes.  The products of the next four entries are read from LDS
+        // while the current four are accumulated.
+        if constexpr (K <= 4) {
+            // v_mfma_f32_4x4x1 (16 blocks): lane e = 4 b + c gives A = W[u][e % 4] and B = the product of entry u
+            // for statistic entry e, so register q of lane e accumulates W[u][q] * product (one fused
+            // multiply-add per entry, the same arithmetic as the vector path)
+            const float *Wf = reinterpret_cast<const float *>(&sh.W[wave][0][0]);
+            float cA[4], nA[4], wA[4], cB[4], nB[4], wB[4];
+            auto fetch = [&](int u0, float(&cv)[4], float(&nv)[4], float(&wv)[4]) {
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    cv[h] = sh.Pc[wave][pci][u0 + h];
+                    nv[h] = sh.Na[wave][nai][u0 + h];
+                    wv[h] = Wf[(u0 + h) * 4 + (lane & 3)];
+                }
+            };
+            auto consume = [&](int u0, const float(&cv)[4], const float(&nv)[4], const float(&wv)[4]) {
+                const uint32_t sbits = (uint32_t)(starts >> u0) & 0xFu;
+                if (sbits == 0 && u0 + 4 <= np) {   // inside one run: four products, no checks
+#pragma unroll
+                    for (int h = 0; h < 4; ++h)
+                        acc4 = __builtin_amdgcn_mfma_f32_4x4x1f32(wv[h], cv[h] * nv[h], acc4, 0, 0, 0);
+                    return;
+                }
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const int u = u0 + h;
+                    if (u >= np) break;
+                    if ((sbits >> h) & 1u) {   // a run starts at entry u
+#pragma unroll
+                        for (int q = 0; q < K; ++q) acc[q] = acc4[q];
+                        flush(cur0, cur1, acc);
+                        acc4 = f32x4_t{0.f, 0.f, 0.f, 0.f};
+                        cur0 = __builtin_amdgcn_readfirstlane(sh.key[wave][u][0]);
+                        cur1 = __builtin_amdgcn_readfirstlane(sh.key[wave][u][1]);
+                    }
+                    acc4 = __builtin_amdgcn_mfma_f32_4x4x1f32(wv[h], cv[h] * nv[h], acc4, 0, 0, 0);
+                }
+            };
+            fetch(0, cA, nA, wA);
+            for (int g = 0; g < np; g += 8) {
+                fetch(g + 4, cB, nB, wB);
+                consume(g, cA, nA, wA);
+                fetch(g + 8, cA, nA, wA);
+                consume(g + 4, cB, nB, wB);
+            }
+        } else
         {
-            const uint32_t p0 = __shfl_up(cu.k0, 1, 64), p1 = __shfl_up(cu.k1, 1, 64);
-            const uint32_t q0 = lane == 0 ? cur0 : p0, q1 = lane == 0 ? cur1 : p1;
-            start = lane < nb && (cu.k0 != q0 || cu.k1 != q1);
-        }
-        uint64_t starts = __ballot(start);
-        wave_sync();
-        // ---- phase 2: lane = statistic entry, one run of equal sets at a time
-        int t = 0;
-        while (t < nb) {
-            if (starts & (1ull << t)) {
-                if (cur0 != 0xFFFFFFFFu && e < 60) {
+            constexpr int KW = (K + 3) / 4;
+            float cA[4], nA[4], cB[4], nB[4];
+            float4 wA[4][KW], wB[4][KW];
+            auto fetch = [&](int u0, float(&cv)[4], float(&nv)[4], float4(&wv)[4][KW]) {
 #pragma unroll
-                    for (int q = 0; q < K; ++q) {
-                        const uint32_t slot = q < 4 ? (cur0 >> (8 * q)) & 0xFF : (cur1 >> (8 * (q - 4))) & 0xFF;
-                        if (slot < (uint32_t)nslots) sh.accS[wave][slot][e] += acc[q];
+                for (int h = 0; h < 4; ++h) {
+                    cv[h] = sh.Pc[wave][pci][u0 + h];
+                    nv[h] = sh.Na[wave][nai][u0 + h];
+#pragma unroll
+                    for (int g4 = 0; g4 < KW; ++g4) wv[h][g4] = sh.W[wave][u0 + h][g4];
+                }
+            };
+            auto consume = [&](int u0, const float(&cv)[4], const float(&nv)[4], const float4(&wv)[4][KW]) {
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    const int u = u0 + h;
+                    if (u >= np) break;
+                    if ((starts >> u) & 1ull) {   // a run starts at entry u
+                        flush(cur0, cur1, acc);
+                        cur0 = __builtin_amdgcn_readfirstlane(sh.key[wave][u][0]);
+                        cur1 = __builtin_amdgcn_readfirstlane(sh.key[wave][u][1]);
+                    }
+                    const float mv = cv[h] * nv[h];
+#pragma unroll
+                    for (int g4 = 0; g4 < KW; ++g4) {
+                        const float wq4[4] = {wv[h][g4].x, wv[h][g4].y, wv[h][g4].z, wv[h][g4].w};
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (4 * g4 + q < K) acc[4 * g4 + q] = fmaf(wq4[q], mv, acc[4 * g4 + q]);
                     }
                 }
-#pragma unroll
-                for (int q = 0; q < K; ++q) acc[q] = 0.f;
-                cur0 = sh.key[wave][t][0];
-                cur1 = sh.key[wave][t][1];
+            };
+            // entries beyond np (up to kBatch + 8, inside the arrays) are read and left unused, so that the
+            // reads are unconditional and stay in flight across the accumulation
+            fetch(0, cA, nA, wA);
+            for (int g = 0; g < np; g += 8) {
+                fetch(g + 4, cB, nB, wB);
+                consume(g, cA, nA, wA);
+                fetch(g + 8, cA, nA, wA);
+                consume(g + 4, cB, nB, wB);
             }
-            // end of this run: next start after t, or the batch end
-            const uint64_t later = t + 1 < 64 ? (starts >> (t + 1)) : 0ull;
-            const int t1 = later ? min(nb, t + 1 + __builtin_ctzll(later)) : nb;
-            int u = t;
-            for (; u + 3 < t1; u += 4) {   // four entries' LDS reads in flight, accumulated in entry order
-                float mv[4];
-#pragma unroll
-                for (int h = 0; h < 4; ++h) mv[h] = sh.Pc[wave][u + h][pci] * sh.Na[wave][u + h][nai];
-#pragma unroll
-                for (int g4 = 0; g4 < (K + 3) / 4; ++g4) {
-                    float4 wl[4];
-#pragma unroll
-                    for (int h = 0; h < 4; ++h) wl[h] = sh.W[wave][u + h][g4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        if (4 * g4 + q < K) {
-                            float v = acc[4 * g4 + q];
-#pragma unroll
-                            for (int h = 0; h < 4; ++h) {
-                                const float wq = q == 0 ? wl[h].x : q == 1 ? wl[h].y : q == 2 ? wl[h].z : wl[h].w;
-                                v = fmaf(wq, mv[h], v);
-                            }
-                            acc[4 * g4 + q] = v;
-                        }
-                    }
-                }
-            }
-            for (; u + 1 < t1; u += 2) {
-                const float m0 = sh.Pc[wave][u][pci] * sh.Na[wave][u][nai];
-                const float m1 = sh.Pc[wave][u + 1][pci] * sh.Na[wave][u + 1][nai];
-#pragma unroll
-                for (int g4 = 0; g4 < (K + 3) / 4; ++g4) {
-                    const float4 w0 = sh.W[wave][u][g4], w1 = sh.W[wave][u + 1][g4];
-                    const float w0v[4] = {w0.x, w0.y, w0.z, w0.w}, w1v[4] = {w1.x, w1.y, w1.z, w1.w};
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (4 * g4 + q < K) acc[4 * g4 + q] = fmaf(w1v[q], m1, fmaf(w0v[q], m0, acc[4 * g4 + q]));
-                }
-            }
-            if (u < t1) {
-                const float m0 = sh.Pc[wave][u][pci] * sh.Na[wave][u][nai];
-#pragma unroll
-                for (int g4 = 0; g4 < (K + 3) / 4; ++g4) {
-                    const float4 w0 = sh.W[wave][u][g4];
-                    const float w0v[4] = {w0.x, w0.y, w0.z, w0.w};
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (4 * g4 + q < K) acc[4 * g4 + q] = fmaf(w0v[q], m0, acc[4 * g4 + q]);
-                }
-            }
-            t = t1;
         }
         wave_sync();
     }
-    if (cur0 != 0xFFFFFFFFu && e < 60) {
+    if constexpr (K <= 4) {
 #pragma unroll
-        for (int q = 0; q < K; ++q) {
-            const uint32_t slot = q < 4 ? (cur0 >> (8 * q)) & 0xFF : (cur1 >> (8 * (q - 4))) & 0xFF;
-            if (slot < (uint32_t)nslots) sh.accS[wave][slot][e] += acc[q];
-        }
+        for (int q = 0; q < K; ++q) acc[q] = acc4[q];
     }
+    flush(cur0, cur1, acc);
     // wave reduction of the data gradient (fixed butterfly order)
 #pragma unroll
     for (int q = 0; q < 12; ++q) {
@@ -541,13 +629,14 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
     }
     __syncthreads();
     // data-term block from the statistic: H[(c,a),(c',a')] = S[c,c',a,a'] + delta_c' S[c,3,a,a']
-    auto data = [&](int sl, int R, int C) {
+    // off: slot sl is not the diagonal; every operand is read whether used or not (independent loads)
+    auto data = [&](int sl, int R, int C, bool off) {
         const int c = R / 3, aa = R % 3, c2 = C / 3, a2 = C % 3;
         const float *S = sh.accS[0][sl];
         const int ni = na_index(aa, a2);
-        float h = S[pc_index(c, c2) * 6 + ni];
-        if (sh.rn.cols[sl] != j && c2 < 3) h = fmaf(-sh.rn.rg[sl][c2], S[pc_index(c, 3) * 6 + ni], h);   // delta = -e
-        return h;
+        const float s1 = S[pc_index(c, c2) * 6 + ni], s3 = S[pc_index(c, 3) * 6 + ni];
+        const float e = sh.rn.rg[sl][c2 < 3 ? c2 : 0];
+        return off && c2 < 3 ? fmaf(-e, s3, s1) : s1;   // delta = -e
     };
     row_finalize<kAsmThreads>(a, s, sh.rn, j, rb, nslots, e_reg, data, nullptr);
 }
@@ -566,7 +655,6 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_rows_kernel(StepArgs a, 
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 template <typename T>
 struct MfmaOp;
@@ -774,7 +862,7 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
         sh.rn.gd[tid] = v;
     }
     __syncthreads();
-    auto data = [&](int sl, int R, int C) { return sh.acc[0][sl * 144 + R * 12 + C]; };
+    auto data = [&](int sl, int R, int C, bool) { return sh.acc[0][sl * 144 + R * 12 + C]; };
     row_finalize<kLpThreads>(a, s, sh.rn, j, rb, nslots, e_reg, data, rr_out);
 }
 
