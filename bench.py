@@ -181,7 +181,8 @@ def main():
     lib.misslam_profile_enable(0)
     import ctypes
     phases = {}
-    for ph in ["normal_map", "build_graph", "point_pass", "assemble", "energy", "bjacobi", "pcg", "fuse", "refine"]:
+    for ph in ["normal_map", "build_graph", "list_pack", "point_pass", "assemble", "energy", "bjacobi", "pcg", "fuse",
+               "refine"]:
         ms = ctypes.c_double()
         cnt = ctypes.c_int64()
         _lib.check("misslam_profile_get", lib.misslam_profile_get(ph.encode(), ctypes.byref(ms), ctypes.byref(cnt)))

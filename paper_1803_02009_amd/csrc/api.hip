@@ -14,10 +14,10 @@ namespace {
 
 enum Phase {
     PH_NORMAL_MAP, PH_GRAPH, PH_POINT_PASS, PH_ASSEMBLE, PH_ENERGY, PH_BJACOBI, PH_PCG, PH_FUSE, PH_REFINE, PH_GROW,
-    PH_COUNT
+    PH_LIST_PACK, PH_COUNT
 };
-const char *const kPhaseNames[PH_COUNT] = {"normal_map", "build_graph", "point_pass", "assemble", "energy",
-                                           "bjacobi",    "pcg",         "fuse",       "refine",   "grow"};
+const char *const kPhaseNames[PH_COUNT] = {"normal_map", "build_graph", "point_pass", "assemble", "energy",   "bjacobi",
+                                           "pcg",        "fuse",        "refine",     "grow",     "list_pack"};
 
 struct Profiler {
     std::mutex mu;
@@ -125,7 +125,7 @@ struct Layout {
     size_t bytes;
 };
 
-Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters) {
+Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters, int k) {
     Carver c{static_cast<char *>(ws)};
     Layout L{};
     const int64_t npb = (n + 255) / 256 + 1;
@@ -166,6 +166,9 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
     L.graph.grid.start = c.take<int32_t>((size_t)msl::MSL_GRID_CELLS + 1);
     L.graph.grid.cursor = c.take<int32_t>((size_t)msl::MSL_GRID_CELLS);
     L.graph.grid.nodes = c.take<float4>((size_t)m);
+    // last, so that every buffer above keeps its place whatever k is
+    L.step.lpa = c.take<float4>((size_t)k * n);
+    L.step.lpw = c.take<float4>((size_t)k * n * ((k + 3) / 4));
     L.bytes = align_up(c.off);
     return L;
 }
@@ -257,7 +260,7 @@ int32_t misslam_last_hip_error(void) { return g_last_hip; }
 
 size_t misslam_workspace_bytes(int64_t n, int32_t m, int32_t width, int32_t height, const misslam_params *params) {
     if (n < 0 || m < 1 || width < 1 || height < 1 || !valid_params(params)) return 0;
-    return carve(nullptr, n, m, width, height, params->pcg_iters).bytes;
+    return carve(nullptr, n, m, width, height, params->pcg_iters, params->k).bytes;
 }
 
 misslam_status misslam_normal_map(const float *depth, const misslam_camera *camera, float *out, void *stream) {
@@ -273,7 +276,7 @@ misslam_status misslam_build_graph(const misslam_points *points, const misslam_n
     if (!valid_points(points) || !valid_nodes(nodes) || !valid_params(params) || !valid_graph(graph, points->n) || !ws)
         return MISSLAM_EINVAL;
     if (graph->k != params->k || nodes->m < params->k) return MISSLAM_ESHAPE;
-    const Layout L = carve(ws, points->n, nodes->m, 1, 1, params->pcg_iters);
+    const Layout L = carve(ws, points->n, nodes->m, 1, 1, params->pcg_iters, params->k);
     if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
     Timed t(PH_GRAPH, stream_of(stream));
     const hipError_t e = msl::launch_build_graph(view(points), view(nodes), params->k, params->weight_kind,
@@ -376,7 +379,7 @@ misslam_status misslam_build_normal_eq(const misslam_points *points, const missl
         return MISSLAM_EINVAL;
     if (graph->k != params->k) return MISSLAM_ESHAPE;
     if (params->precision != MISSLAM_PREC_FP32 && params->k > 4) return MISSLAM_EUNSUPPORTED;
-    const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, params->pcg_iters);
+    const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, params->pcg_iters, params->k);
     if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
     const hipStream_t st = stream_of(stream);
     const msl::StepArgs a = step_args(points, nodes, graph, reinterpret_cast<const float4 *>(nmap), camera, pose,
@@ -388,6 +391,7 @@ misslam_status misslam_build_normal_eq(const misslam_points *points, const missl
         if (e == hipSuccess) e = msl::launch_energy_report(L.step, points->n, nodes->m, rep, params->reject_threshold, st);
         return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
     }
+    if (e == hipSuccess) e = msl::launch_list_pack(a, L.step, st);
     if (e == hipSuccess) e = linearize(a, L.step, points->n, nodes->m, rep, params->reject_threshold, st);
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
 }
@@ -398,7 +402,7 @@ misslam_status misslam_pcg_solve(const misslam_graph *graph, int32_t m, const fl
     if (!graph || !graph->row_ptr || !graph->col_idx || m < 1 || m >= 65535 || !blocks || !g ||
         !valid_params(params) || !delta || !rep || !ws)
         return MISSLAM_EINVAL;
-    const Layout L = carve(ws, 0, m, 1, 1, params->pcg_iters);
+    const Layout L = carve(ws, 0, m, 1, 1, params->pcg_iters, params->k);
     if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
     const hipStream_t st = stream_of(stream);
     const msl::GraphView gv = view(graph);
@@ -418,7 +422,7 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
         return MISSLAM_EINVAL;
     if (graph->k != params->k) return MISSLAM_ESHAPE;
     if (params->precision != MISSLAM_PREC_FP32 && params->k > 4) return MISSLAM_EUNSUPPORTED;
-    const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, params->pcg_iters);
+    const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, params->pcg_iters, params->k);
     if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
     if ((int64_t)graph->bsr_cap > (int64_t)nodes->m * MISSLAM_MAX_ROW) return MISSLAM_ECAPACITY;
     const bool lowp = params->precision != MISSLAM_PREC_FP32;
@@ -432,6 +436,12 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
     if (e == hipSuccess) {
         Timed t(PH_NORMAL_MAP, st);
         e = msl::launch_normal_map(depth, view(camera), L.nmap, st);
+    }
+    if (e == hipSuccess && !lowp && G > 0) {
+        Timed t(PH_LIST_PACK, st);
+        e = msl::launch_list_pack(step_args(points, nodes, graph, L.nmap, camera, pose, params, L.blocks, L.gvec,
+                                            nullptr),
+                                  L.step, st);
     }
     for (int it = 0; it <= G && e == hipSuccess; ++it) {
         int32_t *corr = (corr_hist && it < G) ? corr_hist + (size_t)it * n : nullptr;
@@ -500,7 +510,7 @@ misslam_status misslam_fuse(misslam_points *points, misslam_nodes *nodes, const 
         return MISSLAM_EINVAL;
     misslam_params dp;
     misslam_default_params(&dp);
-    const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, dp.pcg_iters);
+    const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, dp.pcg_iters, graph->k);
     if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
     msl::FuseArgs f;
     f.pts = view(points);
@@ -545,7 +555,7 @@ misslam_status misslam_energy_vjp(const misslam_points *points, const misslam_no
         return MISSLAM_EINVAL;
     if (graph->k != params->k) return MISSLAM_ESHAPE;
     if (grad_points && params->weight_kind != MISSLAM_WEIGHT_GAUSS) return MISSLAM_EUNSUPPORTED;
-    const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, params->pcg_iters);
+    const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, params->pcg_iters, params->k);
     if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
     if ((int64_t)graph->bsr_cap > (int64_t)nodes->m * MISSLAM_MAX_ROW) return MISSLAM_ECAPACITY;
     const hipStream_t st = stream_of(stream);
@@ -555,6 +565,7 @@ misslam_status misslam_energy_vjp(const misslam_points *points, const misslam_no
     a.corr_in = corr_in;
     hipError_t e = msl::launch_report_init(r, 1, st);
     if (e == hipSuccess) e = msl::launch_point_pass(a, L.step, st);
+    if (e == hipSuccess && grad_params) e = msl::launch_list_pack(a, L.step, st);
     if (e == hipSuccess) e = grad_params ? msl::launch_assemble(a, L.step, st) : msl::launch_node_energy(a, L.step, st);
     if (e == hipSuccess) e = msl::launch_energy_report(L.step, points->n, nodes->m, r, params->reject_threshold, st);
     if (e == hipSuccess && energy)
@@ -727,7 +738,8 @@ namespace {
 size_t batch_bytes(const misslam_batch *b) {
     size_t off = align_up(msl::MSL_BAR_WORDS * sizeof(unsigned));
     for (const auto &p : b->probs)
-        off += align_up(carve(nullptr, p.points.n, p.nodes.m, p.camera.width, p.camera.height, b->params.pcg_iters).bytes);
+        off += align_up(carve(nullptr, p.points.n, p.nodes.m, p.camera.width, p.camera.height, b->params.pcg_iters,
+                              b->params.k).bytes);
     return off;
 }
 
@@ -743,7 +755,7 @@ void batch_items(misslam_batch *b, void *ws, int rows) {
     for (int i = 0; i < b->count; ++i) {
         const misslam_problem &p = b->probs[i];
         const Layout L = carve(base + off, p.points.n, p.nodes.m, p.camera.width, p.camera.height,
-                               b->params.pcg_iters);
+                               b->params.pcg_iters, b->params.k);
         off += align_up(L.bytes);
         msl::BatchItem &it = b->items[i];
         it.a = step_args(&p.points, &p.nodes, &p.graph, L.nmap, &p.camera, &p.pose, &b->params, L.blocks, L.gvec,
@@ -804,6 +816,7 @@ hipError_t batch_enqueue(misslam_batch *b, hipStream_t st, bool cooperative) {
     const msl::BatchItem *d = b->d_items;
     hipError_t e = msl::launch_report_init_batched(d, count, G + 1, st);
     if (e == hipSuccess) e = msl::launch_normal_map_batched(d, count, b->total_nm, st);
+    if (e == hipSuccess && G > 0) e = msl::launch_list_pack_batched(d, count, k, b->total_rows, st);
     for (int it = 0; it < G && e == hipSuccess; ++it) {
         e = msl::launch_point_pass_batched(d, count, k, b->total_pp, it, st);
         if (e == hipSuccess) e = msl::launch_assemble_batched(d, count, k, b->total_rows, it, st);

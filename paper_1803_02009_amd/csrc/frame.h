@@ -49,6 +49,9 @@ struct StepScratch {
     double *node_part;    // 2 per node: rot and reg energy of the node's terms
     float *minv;          // m x 144 block-Jacobi inverses
     int32_t *flags;       // 4 ints of device flags
+    // per list entry of node j (point p), packed once per registration for the assembly:
+    float4 *lpa;          // k n: (v_p - g_j, w_pj)
+    float4 *lpw;          // k n x ceil(k/4): w_pj w_pq over the entry's nodes q in index order, zero-padded
 };
 
 struct PcgScratch {
@@ -166,6 +169,9 @@ hipError_t launch_fuse(const FuseArgs &f, float *gx, float *gy, float *gz, float
                        hipStream_t st);
 
 hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_t st);
+// The list-entry packing the assembly reads; run once per registration (the graph, canonical points and node
+// positions are fixed across its Gauss-Newton steps) before the first launch_assemble.
+hipError_t launch_list_pack(const StepArgs &a, const StepScratch &s, hipStream_t st);
 hipError_t launch_assemble(const StepArgs &a, const StepScratch &s, hipStream_t st);
 hipError_t launch_assemble_lp(const StepArgs &a, const StepScratch &s, int precision, float *rr_out,
                               hipStream_t st);
@@ -202,6 +208,7 @@ int pcg_blocks(int m);
 hipError_t launch_normal_map_batched(const BatchItem *items, int count, int total_blocks, hipStream_t st);
 hipError_t launch_point_pass_batched(const BatchItem *items, int count, int k, int64_t total_blocks, int it,
                                      hipStream_t st);
+hipError_t launch_list_pack_batched(const BatchItem *items, int count, int k, int total_rows, hipStream_t st);
 hipError_t launch_assemble_batched(const BatchItem *items, int count, int k, int total_rows, int it, hipStream_t st);
 hipError_t launch_energy_report_batched(const BatchItem *items, int count, int it, unsigned *zero_words,
                                         int zero_count, hipStream_t st);

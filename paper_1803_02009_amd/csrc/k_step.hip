@@ -334,21 +334,77 @@ struct EntryRegs {
     uint32_t k0, k1;
 };
 
+// Registers of one packed list entry: read in list order, except the point's (n', r) (a gather).
+template <int K>
+struct EntryPack {
+    float4 uw;                  // (v_p - g_j, w_pj)
+    float4 w[(K + 3) / 4];      // w_pj w_pq, nodes in index order
+    float4 nr;
+    uint32_t k0, k1;
+};
+
 // The data of list entry le whose point p is already known.
 template <int K>
-__device__ __forceinline__ void entry_data(const StepArgs &a, const StepScratch &s, int64_t n, int le, int p,
-                                           EntryRegs<K> &r) {
+__device__ __forceinline__ void entry_pack(const StepArgs &a, const StepScratch &s, int le, int p,
+                                           EntryPack<K> &r) {
+    constexpr int KW = (K + 3) / 4;
+    r.uw = s.lpa[le];
 #pragma unroll
-    for (int t = 0; t < K; ++t) {
-        r.q[t] = a.g.knn_idx[(int64_t)t * n + p];
-        r.wq[t] = a.g.knn_w[(int64_t)t * n + p];
-    }
+    for (int g4 = 0; g4 < KW; ++g4) r.w[g4] = s.lpw[(size_t)le * KW + g4];
     r.nr = s.nr[p];
-    r.vx = a.pts.px[p];
-    r.vy = a.pts.py[p];
-    r.vz = a.pts.pz[p];
     r.k0 = a.g.list_key[2 * (size_t)le];
     r.k1 = a.g.list_key[2 * (size_t)le + 1];
+}
+
+// Packs the list entries of node j, one per thread: (v_p - g_j, w_pj) and the weight products in the
+// order of the entry's row positions (the nodes of its kNN set sorted by index).
+template <int K>
+__device__ __forceinline__ void list_pack_body(const StepArgs &a, const StepScratch &s, int j) {
+    constexpr int KW = (K + 3) / 4;
+    if (j >= a.nd.m) return;
+    const int64_t n = a.pts.n;
+    const int lb = a.g.list_ptr[j];
+    const int cnt = min(a.g.list_ptr[j + 1] - lb, MISSLAM_MAX_LIST);
+    const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
+    for (int t = threadIdx.x; t < cnt; t += 256) {
+        const int le = lb + t;
+        const int p = a.g.list_pts[le];
+        int q[K];
+        float wq[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            q[u] = a.g.knn_idx[(int64_t)u * n + p];
+            wq[u] = a.g.knn_w[(int64_t)u * n + p];
+        }
+        float wj = 0.f;
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+            if (q[u] == j) wj = wq[u];
+#pragma unroll
+        for (int u = 1; u < K; ++u)
+#pragma unroll
+            for (int v = u; v > 0; --v)
+                if (q[v] < q[v - 1]) {
+                    const int ti = q[v];
+                    q[v] = q[v - 1];
+                    q[v - 1] = ti;
+                    const float tw = wq[v];
+                    wq[v] = wq[v - 1];
+                    wq[v - 1] = tw;
+                }
+        s.lpa[le] = make_float4(a.pts.px[p] - gjx, a.pts.py[p] - gjy, a.pts.pz[p] - gjz, wj);
+        float wv[4 * KW];
+#pragma unroll
+        for (int u = 0; u < 4 * KW; ++u) wv[u] = u < K ? wj * wq[u] : 0.f;
+#pragma unroll
+        for (int g4 = 0; g4 < KW; ++g4)
+            s.lpw[(size_t)le * KW + g4] = make_float4(wv[4 * g4], wv[4 * g4 + 1], wv[4 * g4 + 2], wv[4 * g4 + 3]);
+    }
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) list_pack_kernel(StepArgs a, StepScratch s) {
+    list_pack_body<K>(a, s, blockIdx.x);
 }
 
 template <int K>
@@ -401,9 +457,10 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
     // Entries are fetched in two stages: the point index two batches ahead (coalesced), the point's data one
     // batch ahead (gathers whose addresses are known by then), so no wait in the loop is a chain of two
     // dependent loads.  The first batch's entries are fetched before the node-level loads are waited for.
-    EntryRegs<K> nxt;
+    EntryPack<K> nxt;
     int pnext = 0;   // point of this lane's entry in the next batch
-    if (nbatch > 0 && lane < min(kBatch, my1 - my0)) entry_load<K>(a, s, n, lb + my0 + lane, nxt);
+    if (nbatch > 0 && lane < min(kBatch, my1 - my0))
+        entry_pack<K>(a, s, lb + my0 + lane, a.g.list_pts[lb + my0 + lane], nxt);
     if (nbatch > 1 && lane < min(kBatch, my1 - my0 - kBatch)) pnext = a.g.list_pts[lb + my0 + kBatch + lane];
     const double e_reg = row_prepare<kAsmThreads>(a, sh.rn, j, nslots, gjx, gjy, gjz);
 
@@ -438,11 +495,11 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
     for (int bt = 0; bt < nbatch; ++bt) {
         const int e0 = my0 + bt * kBatch;
         const int nb = min(kBatch, my1 - e0);
-        EntryRegs<K> cu = nxt;
+        EntryPack<K> cu = nxt;
         // prefetch: the next batch's data, then the point indices of the batch after next (issued last, so
         // that waiting for this batch's data never waits for them)
         if (bt + 1 < nbatch && lane < min(kBatch, my1 - e0 - kBatch))
-            entry_data<K>(a, s, n, lb + e0 + kBatch + lane, pnext, nxt);
+            entry_pack<K>(a, s, lb + e0 + kBatch + lane, pnext, nxt);
         if (bt + 2 < nbatch && lane < min(kBatch, my1 - e0 - 2 * kBatch))
             pnext = a.g.list_pts[lb + e0 + 2 * kBatch + lane];
         // ---- phase 1: lane = list entry.  An entry whose point has no correspondence (n' = 0 from the point
@@ -453,35 +510,15 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)vmask, 0u));
         const int np = __builtin_amdgcn_readfirstlane(__popcll(vmask));
         if (valid) {
-            float wj = 0.f;
-#pragma unroll
-            for (int t = 0; t < K; ++t)
-                if (cu.q[t] == j) wj = cu.wq[t];
-            // weights in node-index order, matching the entry's row positions
-#pragma unroll
-            for (int u = 1; u < K; ++u)
-#pragma unroll
-                for (int v = u; v > 0; --v)
-                    if (cu.q[v] < cu.q[v - 1]) {
-                        const int ti = cu.q[v];
-                        cu.q[v] = cu.q[v - 1];
-                        cu.q[v - 1] = ti;
-                        const float tw = cu.wq[v];
-                        cu.wq[v] = cu.wq[v - 1];
-                        cu.wq[v - 1] = tw;
-                    }
-            const float uu[4] = {cu.vx - gjx, cu.vy - gjy, cu.vz - gjz, 1.f};
+            const float wj = cu.uw.w;
+            const float uu[4] = {cu.uw.x, cu.uw.y, cu.uw.z, 1.f};
             const float nn[3] = {cu.nr.x, cu.nr.y, cu.nr.z};
 #pragma unroll
             for (int t = 0; t < 10; ++t) sh.Pc[wave][t][pv] = uu[pair_c0(t)] * uu[pair_c1(t)];
 #pragma unroll
             for (int t = 0; t < 6; ++t) sh.Na[wave][t][pv] = nn[pair_a0(t)] * nn[pair_a1(t)];
-            float wv[4 * ((K + 3) / 4)];
 #pragma unroll
-            for (int t = 0; t < 4 * ((K + 3) / 4); ++t) wv[t] = t < K ? wj * cu.wq[t] : 0.f;
-#pragma unroll
-            for (int t = 0; t < (K + 3) / 4; ++t)
-                sh.W[wave][pv][t] = make_float4(wv[4 * t], wv[4 * t + 1], wv[4 * t + 2], wv[4 * t + 3]);
+            for (int t = 0; t < (K + 3) / 4; ++t) sh.W[wave][pv][t] = cu.w[t];
             sh.key[wave][pv][0] = cu.k0;
             sh.key[wave][pv][1] = cu.k1;
             const float wr = wj * cu.nr.w;
@@ -1199,6 +1236,20 @@ hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_
     return hipGetLastError();
 }
 
+hipError_t launch_list_pack(const StepArgs &a, const StepScratch &s, hipStream_t st) {
+    const int m = a.nd.m;
+    if (m <= 0) return hipSuccess;
+    switch (a.g.k) {
+#define MSL_LK_CASE(KK) \
+    case KK: hipLaunchKernelGGL((list_pack_kernel<KK>), dim3(m), dim3(256), 0, st, a, s); break;
+        MSL_LK_CASE(1) MSL_LK_CASE(2) MSL_LK_CASE(3) MSL_LK_CASE(4)
+        MSL_LK_CASE(5) MSL_LK_CASE(6) MSL_LK_CASE(7) MSL_LK_CASE(8)
+#undef MSL_LK_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_assemble(const StepArgs &a, const StepScratch &s, hipStream_t st) {
     const int m = a.nd.m;
     const unsigned rows = 8 * (unsigned)((m + 7) / 8);
@@ -1246,6 +1297,12 @@ __global__ void __launch_bounds__(kPtBlock) point_pass_batched_kernel(const Batc
 }
 
 template <int K>
+__global__ void __launch_bounds__(256) list_pack_batched_kernel(const BatchItem *__restrict__ items, int count) {
+    const BatchItem &it = items[batch_of(items, count, blockIdx.x, 1)];
+    list_pack_body<K>(it.a, it.s, (int)blockIdx.x - it.row0);
+}
+
+template <int K>
 __global__ void __launch_bounds__(kAsmThreads) assemble_batched_kernel(const BatchItem *__restrict__ items, int count,
                                                                        int gi) {
     const BatchItem &it = items[batch_of(items, count, blockIdx.x, 1)];
@@ -1281,6 +1338,21 @@ hipError_t launch_point_pass_batched(const BatchItem *items, int count, int k, i
         MSL_PB_CASE(1) MSL_PB_CASE(2) MSL_PB_CASE(3) MSL_PB_CASE(4)
         MSL_PB_CASE(5) MSL_PB_CASE(6) MSL_PB_CASE(7) MSL_PB_CASE(8)
 #undef MSL_PB_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_list_pack_batched(const BatchItem *items, int count, int k, int total_rows, hipStream_t st) {
+    if (total_rows <= 0) return hipSuccess;
+    switch (k) {
+#define MSL_LB_CASE(KK)                                                                                          \
+    case KK:                                                                                                     \
+        hipLaunchKernelGGL((list_pack_batched_kernel<KK>), dim3(total_rows), dim3(256), 0, st, items, count); \
+        break;
+        MSL_LB_CASE(1) MSL_LB_CASE(2) MSL_LB_CASE(3) MSL_LB_CASE(4)
+        MSL_LB_CASE(5) MSL_LB_CASE(6) MSL_LB_CASE(7) MSL_LB_CASE(8)
+#undef MSL_LB_CASE
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
