@@ -413,7 +413,7 @@ __device__ __forceinline__ double tag_sum(unsigned *bar, int g0, int G, int whic
 }
 
 constexpr int kMaxBlocksWg = kRowsPerBlk * MISSLAM_MAX_ROW;   // blocks of one workgroup's rows
-constexpr int kMaxUnique = 256;                                // distinct columns staged per iteration
+constexpr int kMaxUnique = 192;                                // distinct columns staged per iteration
 constexpr int kZPer = (kMaxUnique * 6 + kPcgThreads - 1) / kPcgThreads;
 
 __device__ __forceinline__ unsigned long long ld_dev64(const float *p) {
@@ -546,6 +546,11 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
     const bool act = lr < kRowsPerBlk && j < r1;
     const int li = lr * 12 + a;
     bool broken = false;
+    // this thread's row: its blocks q in [rq0, rq1) of the workgroup; fast = all cached with a staged column
+    const int rq0 = act ? min(A.row_ptr[j], A.cap) - b0 : 0;
+    const int rq1 = act ? min(A.row_ptr[j + 1], A.cap) - b0 : 0;
+    bool fast = rq1 <= cached;
+    for (int q = rq0; q < rq1 && fast; ++q) fast = bmap[q] >= 0;
 
     // stage z of the distinct columns, all loads in flight together
     auto stage = [&]() {
@@ -606,8 +611,49 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
         double pq = 0.0;
         if (act && !skip) {
             const float beta = it > 0 ? (float)(rz / rz_prev) : 0.f;
-            double az = 0.0;                           // exact float64 sum of float32 products
+            double az = 0.0;                           // exact float64 sums of float32 products
             const int p0 = A.row_ptr[j], p1 = min(A.row_ptr[j + 1], A.cap);
+            if (fast) {   // even and odd blocks in two chains, both blocks' operands read before the products
+                double az1 = 0.0;
+                int q = rq0;
+                for (; q + 1 < rq1; q += 2) {
+                    const float4 *Ba = reinterpret_cast<const float4 *>(hc + (size_t)q * 144 + a * 12);
+                    const float4 *Bb = reinterpret_cast<const float4 *>(hc + (size_t)(q + 1) * 144 + a * 12);
+                    const float4 *za = zc4 + bmap[q] * 3, *zb = zc4 + bmap[q + 1] * 3;
+                    float4 ba[3], bb[3], zav[3], zbv[3];
+#pragma unroll
+                    for (int h = 0; h < 3; ++h) {
+                        ba[h] = Ba[h];
+                        bb[h] = Bb[h];
+                        zav[h] = za[h];
+                        zbv[h] = zb[h];
+                    }
+#pragma unroll
+                    for (int h = 0; h < 3; ++h) {
+                        az = fma((double)ba[h].x, (double)zav[h].x, az);
+                        az1 = fma((double)bb[h].x, (double)zbv[h].x, az1);
+                        az = fma((double)ba[h].y, (double)zav[h].y, az);
+                        az1 = fma((double)bb[h].y, (double)zbv[h].y, az1);
+                        az = fma((double)ba[h].z, (double)zav[h].z, az);
+                        az1 = fma((double)bb[h].z, (double)zbv[h].z, az1);
+                        az = fma((double)ba[h].w, (double)zav[h].w, az);
+                        az1 = fma((double)bb[h].w, (double)zbv[h].w, az1);
+                    }
+                }
+                if (q < rq1) {
+                    const float4 *Ba = reinterpret_cast<const float4 *>(hc + (size_t)q * 144 + a * 12);
+                    const float4 *za = zc4 + bmap[q] * 3;
+#pragma unroll
+                    for (int h = 0; h < 3; ++h) {
+                        const float4 bv = Ba[h], zv = za[h];
+                        az = fma((double)bv.x, (double)zv.x, az);
+                        az = fma((double)bv.y, (double)zv.y, az);
+                        az = fma((double)bv.z, (double)zv.z, az);
+                        az = fma((double)bv.w, (double)zv.w, az);
+                    }
+                }
+                az += az1;
+            } else
             for (int pb = p0; pb < p1; ++pb) {
                 const int q = pb - b0;
                 const int slot = q < nb ? bmap[q] : -1;
@@ -779,7 +825,7 @@ hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks,
     A.status = s.status;
     A.done = s.status + (iters + 2);
     // dynamic LDS: cached blocks (144 floats each) and the rows' preconditioner
-    const int cache_blocks = (lds / 4 - kRowsPerBlk * 144) / 144;
+    const int cache_blocks = (lds / 4 - rows * 144) / 144;
     if (cache_blocks < 1) return hipSuccess;
     unsigned *bar = s.bar;
     if (zeroed_words < 8 * G) hipLaunchKernelGGL(fill_u32_kernel_pcg, dim3((8 * G + 255) / 256), dim3(256), 0, st, bar, 8 * G);
@@ -858,7 +904,7 @@ hipError_t launch_pcg_batched(const BatchItem *items, int count, int rows_per_wg
     *used = false;
     const int lds = batched_lds(total_wgs);
     if (lds <= 0 || rows_per_wg < 1 || rows_per_wg > kRowsPerBlk) return hipSuccess;
-    const int cache_blocks = (lds / 4 - kRowsPerBlk * 144) / 144;
+    const int cache_blocks = (lds / 4 - rows_per_wg * 144) / 144;
     if (cache_blocks < 1) return hipSuccess;
     hipError_t e;
     if (cooperative) {
