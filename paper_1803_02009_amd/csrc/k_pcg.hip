@@ -438,6 +438,7 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
     __shared__ int ucol[kMaxUnique];
     __shared__ float4 zc4[kMaxUnique * 3];             // z of the distinct columns (setup: first-block map)
     __shared__ int cnt_u, cmin_s, cmax_s;
+    __shared__ int lslot[kRowsPerBlk];                 // staged slot of each of this workgroup's own columns
     float *zc = reinterpret_cast<float *>(zc4);
     const int r0 = min(A.m, wg * rows_per_wg);
     const int r1 = min(A.m, r0 + rows_per_wg);
@@ -461,6 +462,7 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
         cmin_s = 0x7FFFFFFF;
         cmax_s = -1;
     }
+    if (threadIdx.x < kRowsPerBlk) lslot[threadIdx.x] = -1;
     __syncthreads();
     for (int t = threadIdx.x; t < nb; t += kPcgThreads) {
         const int c = A.col_idx[b0 + t];
@@ -523,6 +525,7 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
             if (t < nb && firstpos[e] == t) {
                 const int sl = slot < kMaxUnique ? slot : -1;
                 if (sl >= 0) ucol[sl] = colL[t];
+                if (sl >= 0 && colL[t] >= r0 && colL[t] < r1) lslot[colL[t] - r0] = sl;
                 bmap[t] = sl;
                 ++slot;
             }
@@ -551,19 +554,53 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
     const int rq1 = act ? min(A.row_ptr[j + 1], A.cap) - b0 : 0;
     bool fast = rq1 <= cached;
     for (int q = rq0; q < rq1 && fast; ++q) fast = bmap[q] >= 0;
+    // Blocks whose column is one of this workgroup's own rows (bit i: block rq0 + i, fast rows only): their
+    // z is produced here and written straight into its staged slot, so their part of the next product is
+    // formed while the r.z exchange is in flight; the other blocks wait for the exchange.
+    uint32_t lmask = 0, rmask = 0;
+    if (act && fast)
+        for (int q = rq0; q < rq1; ++q) {
+            if (colL[q] >= r0 && colL[q] < r1)
+                lmask |= 1u << (q - rq0);
+            else
+                rmask |= 1u << (q - rq0);
+        }
+    const int zslot = act ? lslot[lr] : -1;   // staged slot of this row's own column (-1: none)
+    // product of one block (workgroup block q, staged column slot sl) and z, into chain t
+    auto block_dot = [&](int q, double t) {
+        const float4 *Bq = reinterpret_cast<const float4 *>(hc + (size_t)q * 144 + a * 12);
+        const float4 *zq = zc4 + bmap[q] * 3;
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+            const float4 b4 = Bq[h], z4 = zq[h];
+            t = fma((double)b4.x, (double)z4.x, t);
+            t = fma((double)b4.y, (double)z4.y, t);
+            t = fma((double)b4.z, (double)z4.z, t);
+            t = fma((double)b4.w, (double)z4.w, t);
+        }
+        return t;
+    };
+    // the local part of the product (own columns, in block order)
+    auto local_part = [&]() {
+        double t = 0.0;
+        for (uint32_t mk = lmask; mk; mk &= mk - 1) t = block_dot(rq0 + __builtin_ctz(mk), t);
+        return t;
+    };
 
-    // stage z of the distinct columns, all loads in flight together
+    // stage z of the distinct columns owned by other workgroups, all loads in flight together (the own
+    // columns' slots are written by their rows' threads)
     auto stage = [&]() {
         unsigned long long zv[kZPer];
 #pragma unroll
         for (int e = 0; e < kZPer; ++e) {
             const int t = threadIdx.x + e * kPcgThreads;
-            if (t < U * 6) zv[e] = ld_dev64(A.z + (size_t)ucol[t / 6] * 12 + 2 * (t % 6));
+            if (t < U * 6 && (ucol[t / 6] < r0 || ucol[t / 6] >= r1))
+                zv[e] = ld_dev64(A.z + (size_t)ucol[t / 6] * 12 + 2 * (t % 6));
         }
 #pragma unroll
         for (int e = 0; e < kZPer; ++e) {
             const int t = threadIdx.x + e * kPcgThreads;
-            if (t < U * 6) {
+            if (t < U * 6 && (ucol[t / 6] < r0 || ucol[t / 6] >= r1)) {
                 zc[(t / 6) * 12 + 2 * (t % 6)] = __uint_as_float((unsigned)(zv[e] & 0xFFFFFFFFull));
                 zc[(t / 6) * 12 + 2 * (t % 6) + 1] = __uint_as_float((unsigned)(zv[e] >> 32));
             }
@@ -592,13 +629,15 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
         for (int b = 0; b < 12; ++b) s = fmaf(M[b], vr[lr * 12 + b], s);
         z = s;
         st_dev(A.z + (size_t)j * 12 + a, z);
+        if (zslot >= 0) zc[zslot * 12 + a] = z;
     }
-    double rz;
+    double rz, azl;
     {
         double v[2] = {(double)r * (double)z, (double)r * (double)r};
         wg_sum<2>(v, red);
         if (threadIdx.x == 0) st_dev(A.part + (size_t)(0 * 4 + 1) * G + wg, v[1]);
         publish(1, 1u, v[0]);
+        azl = local_part();
         rz = tag_sum(bar, gid0, G, 1, 1u, broken, red);
         stage();
     }
@@ -613,43 +652,40 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
             const float beta = it > 0 ? (float)(rz / rz_prev) : 0.f;
             double az = 0.0;                           // exact float64 sums of float32 products
             const int p0 = A.row_ptr[j], p1 = min(A.row_ptr[j + 1], A.cap);
-            if (fast) {   // even and odd blocks in two chains, both blocks' operands read before the products
+            if (fast) {   // the local part, then the other blocks in two chains (pairs read together)
                 double az1 = 0.0;
-                int q = rq0;
-                for (; q + 1 < rq1; q += 2) {
-                    const float4 *Ba = reinterpret_cast<const float4 *>(hc + (size_t)q * 144 + a * 12);
-                    const float4 *Bb = reinterpret_cast<const float4 *>(hc + (size_t)(q + 1) * 144 + a * 12);
-                    const float4 *za = zc4 + bmap[q] * 3, *zb = zc4 + bmap[q + 1] * 3;
-                    float4 ba[3], bb[3], zav[3], zbv[3];
+                az = azl;
+                uint32_t mk = rmask;
+                while (mk) {
+                    const int qa = rq0 + __builtin_ctz(mk);
+                    mk &= mk - 1;
+                    if (mk) {
+                        const int qb = rq0 + __builtin_ctz(mk);
+                        mk &= mk - 1;
+                        const float4 *Ba = reinterpret_cast<const float4 *>(hc + (size_t)qa * 144 + a * 12);
+                        const float4 *Bb = reinterpret_cast<const float4 *>(hc + (size_t)qb * 144 + a * 12);
+                        const float4 *za = zc4 + bmap[qa] * 3, *zb = zc4 + bmap[qb] * 3;
+                        float4 ba[3], bb[3], zav[3], zbv[3];
 #pragma unroll
-                    for (int h = 0; h < 3; ++h) {
-                        ba[h] = Ba[h];
-                        bb[h] = Bb[h];
-                        zav[h] = za[h];
-                        zbv[h] = zb[h];
-                    }
+                        for (int h = 0; h < 3; ++h) {
+                            ba[h] = Ba[h];
+                            bb[h] = Bb[h];
+                            zav[h] = za[h];
+                            zbv[h] = zb[h];
+                        }
 #pragma unroll
-                    for (int h = 0; h < 3; ++h) {
-                        az = fma((double)ba[h].x, (double)zav[h].x, az);
-                        az1 = fma((double)bb[h].x, (double)zbv[h].x, az1);
-                        az = fma((double)ba[h].y, (double)zav[h].y, az);
-                        az1 = fma((double)bb[h].y, (double)zbv[h].y, az1);
-                        az = fma((double)ba[h].z, (double)zav[h].z, az);
-                        az1 = fma((double)bb[h].z, (double)zbv[h].z, az1);
-                        az = fma((double)ba[h].w, (double)zav[h].w, az);
-                        az1 = fma((double)bb[h].w, (double)zbv[h].w, az1);
-                    }
-                }
-                if (q < rq1) {
-                    const float4 *Ba = reinterpret_cast<const float4 *>(hc + (size_t)q * 144 + a * 12);
-                    const float4 *za = zc4 + bmap[q] * 3;
-#pragma unroll
-                    for (int h = 0; h < 3; ++h) {
-                        const float4 bv = Ba[h], zv = za[h];
-                        az = fma((double)bv.x, (double)zv.x, az);
-                        az = fma((double)bv.y, (double)zv.y, az);
-                        az = fma((double)bv.z, (double)zv.z, az);
-                        az = fma((double)bv.w, (double)zv.w, az);
+                        for (int h = 0; h < 3; ++h) {
+                            az = fma((double)ba[h].x, (double)zav[h].x, az);
+                            az1 = fma((double)bb[h].x, (double)zbv[h].x, az1);
+                            az = fma((double)ba[h].y, (double)zav[h].y, az);
+                            az1 = fma((double)bb[h].y, (double)zbv[h].y, az1);
+                            az = fma((double)ba[h].z, (double)zav[h].z, az);
+                            az1 = fma((double)bb[h].z, (double)zbv[h].z, az1);
+                            az = fma((double)ba[h].w, (double)zav[h].w, az);
+                            az1 = fma((double)bb[h].w, (double)zbv[h].w, az1);
+                        }
+                    } else {
+                        az = block_dot(qa, az);
                     }
                 }
                 az += az1;
@@ -711,6 +747,7 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
             for (int b = 0; b < 12; ++b) s = fmaf(M[b], vr[lr * 12 + b], s);
             z = s;
             st_dev(A.z + (size_t)j * 12 + a, z);
+            if (zslot >= 0) zc[zslot * 12 + a] = z;
         }
         if (upd) ++done;
         if (brk) stopped = true;
@@ -723,6 +760,7 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
                 st_dev(A.part + (size_t)((it + 1) * 4 + 3) * G + wg, v[2]);
             }
             publish(1, (unsigned)(it + 2), v[0]);
+            azl = local_part();
             rz = tag_sum(bar, gid0, G, 1, (unsigned)(it + 2), broken, red);
         }
         stage();
