@@ -14,6 +14,7 @@ import dataclasses
 import numpy as np
 
 from .assoc import associate
+from .corr import corr_energy, corr_residuals
 from .depthmap import normal_map
 from .energy import energies
 from .graph import build_graph
@@ -42,6 +43,9 @@ class Problem:
     lam: float = 1e-3
     gn_iters: int = 10
     pcg_iters: int = 10
+    kp_point: np.ndarray = None  # key points (Eq.(9)): carrying model point per key point
+    kp_target: np.ndarray = None  # (S, 3) matched positions, world frame
+    w_corr: float = 10.0          # Sec. III-B
 
     @staticmethod
     def from_scene(sc, **kw):
@@ -53,20 +57,29 @@ class Problem:
 
 
 def evaluate(pb, graph, x, Nmap, Nvalid, corr_override=None):
-    """Warp and associate at parameters x; returns (vc, nc, assoc, (e_data, e_rot, e_reg))."""
+    """Warp and associate at parameters x; returns (vc, nc, assoc, (e_data, e_rot, e_reg, e_corr)).
+
+    With key points, assoc["kp_r"] holds their Eq.(9) residuals."""
     vc = ed_warp(pb.points, pb.nodes, x, graph["idx"], graph["w"], pb.R, pb.T)
     nc = warp_normals(pb.normals, x, graph["idx"], graph["w"], pb.R)
     asc = associate(vc, nc, pb.depth, pb.camera, Nmap, Nvalid, pb.eps_d, pb.cos_eps_n)
     if corr_override is not None:
         asc = _adopt(asc, corr_override, vc, pb, Nmap)
-    return vc, nc, asc, energies(x, pb.nodes, graph["nbrs"], asc["r"])
+    e_corr = 0.0
+    if pb.kp_point is not None:
+        asc = dict(asc)
+        asc["kp_r"] = corr_residuals(pb.points, pb.nodes, x, graph["idx"], graph["w"], pb.R, pb.T,
+                                     pb.kp_point, pb.kp_target)
+        e_corr = corr_energy(asc["kp_r"])
+    return vc, nc, asc, energies(x, pb.nodes, graph["nbrs"], asc["r"]) + (e_corr,)
 
 
 def linearize(pb, graph, x, Nmap, Nvalid, corr_override=None, jac_round=None):
     """Warp, associate and assemble at parameters x; returns everything the step needs."""
     vc, nc, asc, e = evaluate(pb, graph, x, Nmap, Nvalid, corr_override)
+    corr = None if pb.kp_point is None else {"point": pb.kp_point, "r": asc["kp_r"], "w_corr": pb.w_corr}
     blocks, g = block_system(pb.points, pb.nodes, x, graph["idx"], graph["w"], pb.R, asc, graph["nbrs"],
-                             graph["row_ptr"], graph["col_idx"], (pb.w_rot, pb.w_reg, pb.w_data), jac_round)
+                             graph["row_ptr"], graph["col_idx"], (pb.w_rot, pb.w_reg, pb.w_data), jac_round, corr)
     return vc, nc, asc, blocks, g, e
 
 
@@ -125,7 +138,8 @@ def gn_register(pb, graph=None, x0=None, corr_sequence=None, record=False, jac_r
                 rho = -np.asarray(g).reshape(-1) - bsr_matvec(graph["row_ptr"], graph["col_idx"], h32, dx, pb.lam)
                 d2, _ = pcg(graph["row_ptr"], graph["col_idx"], blocks, -rho, pb.lam, pb.pcg_iters, Minv)
                 dx = dx + d2
-        entry = {"e_data": e[0], "e_rot": e[1], "e_reg": e[2], "n_valid": int(asc["valid"].sum()),
+        entry = {"e_data": e[0], "e_rot": e[1], "e_reg": e[2], "e_corr": e[3],
+                 "n_valid": int(asc["valid"].sum()),
                  "resid": info["resid"], "breakdown": info["breakdown"], "nonspd": int((~spd).sum())}
         if record:
             entry.update(corr=asc["corr"].copy(), margin=asc["margin"], blocks=blocks, g=g, dx=dx,
@@ -133,6 +147,7 @@ def gn_register(pb, graph=None, x0=None, corr_sequence=None, record=False, jac_r
         rep["iters"].append(entry)
         x = x + dx.reshape(m, 12)
     vc, nc, asc, e = evaluate(pb, graph, x, Nmap, Nvalid)
-    rep["final"] = {"e_data": e[0], "e_rot": e[1], "e_reg": e[2], "n_valid": int(asc["valid"].sum()),
+    rep["final"] = {"e_data": e[0], "e_rot": e[1], "e_reg": e[2], "e_corr": e[3],
+                    "n_valid": int(asc["valid"].sum()),
                     "vc": vc, "corr": asc["corr"]}
     return x, rep

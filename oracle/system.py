@@ -64,10 +64,11 @@ def reg_jacobian(nodes, nbrs):
     return js, ls, Jj, Jl
 
 
-def dense_system(points, nodes, params, idx, w, R, assoc, nbrs, weights):
+def dense_system(points, nodes, params, idx, w, R, assoc, nbrs, weights, corr=None):
     """Explicit dense Jacobian and normal equations (small problems only).
 
-    Rows: one per valid data point, 6 per node (rot), 3 per directed edge (reg);
+    Rows: one per valid data point, 6 per node (rot), 3 per directed edge (reg),
+    3 per key point when corr = {"point", "r" (S, 3), "w_corr"} is given (Eq.(9));
     columns 12 m.  Returns (J, wdiag, r, H, g) with H = J^T diag(w) J and
     g = J^T diag(w) r.
     """
@@ -104,6 +105,18 @@ def dense_system(points, nodes, params, idx, w, R, assoc, nbrs, weights):
             rows.append(row)
             wts.append(w_reg)
             res.append(rg[e, a])
+    if corr is not None and len(corr["point"]):
+        from .corr import corr_jacobian_rows
+        Jc = corr_jacobian_rows(points, nodes, idx, w, R, corr["point"])
+        for s, p in enumerate(np.asarray(corr["point"])):
+            for a in range(3):
+                row = np.zeros(12 * m)
+                for q in range(idx.shape[1]):
+                    j = idx[p, q]
+                    row[12 * j:12 * j + 12] += Jc[s, a, q]
+                rows.append(row)
+                wts.append(corr["w_corr"])
+                res.append(corr["r"][s, a])
     J = np.array(rows) if rows else np.zeros((0, 12 * m))
     wd = np.array(wts)
     r = np.array(res)
@@ -112,14 +125,16 @@ def dense_system(points, nodes, params, idx, w, R, assoc, nbrs, weights):
     return J, wd, r, H, g
 
 
-def block_system(points, nodes, params, idx, w, R, assoc, nbrs, row_ptr, col_idx, weights, jac_round=None):
+def block_system(points, nodes, params, idx, w, R, assoc, nbrs, row_ptr, col_idx, weights, jac_round=None,
+                 corr=None):
     """The same normal equations accumulated block by block into the BSR pattern.
 
     Every term's contribution J_a^T J_b is added to block (a, b); the sums use
     np.bincount over block ids, one entry of the 12x12 block at a time.
     jac_round, if given, maps the data-term Jacobian rows before they enter
     the blocks (not the gradient): the rounding a low-precision matrix-core
-    product applies to its inputs.
+    product applies to its inputs.  corr = {"point", "r" (S, 3), "w_corr"}
+    adds the key-point term of Eq.(9).
     Returns (blocks (nnzb, 12, 12), g (m, 12)).
     """
     w_rot, w_reg, w_data = weights
@@ -177,6 +192,20 @@ def block_system(points, nodes, params, idx, w, R, assoc, nbrs, row_ptr, col_idx
         np.add.at(blocks, key[ia, ib], contrib)
     np.add.at(gvec, js, w_reg * np.einsum("nqe,nq->ne", Jj, rg))
     np.add.at(gvec, ls, w_reg * np.einsum("nqe,nq->ne", Jl, rg))
+
+    # key-point term
+    if corr is not None and len(corr["point"]):
+        from .corr import corr_jacobian_rows
+        kp = np.asarray(corr["point"], dtype=np.int64)
+        Jc = corr_jacobian_rows(points, G, idx, w, R, kp)        # (S, 3, k, 12)
+        rc = np.asarray(corr["r"], dtype=np.float64)             # (S, 3)
+        wc = corr["w_corr"]
+        for a in range(k):
+            ja = idx[kp, a]
+            np.add.at(gvec, ja, wc * np.einsum("sre,sr->se", Jc[:, :, a, :], rc))
+            for b in range(k):
+                jb = idx[kp, b]
+                np.add.at(blocks, key[ja, jb], wc * np.einsum("sre,srf->sef", Jc[:, :, a, :], Jc[:, :, b, :]))
     return blocks, gvec
 
 
