@@ -78,6 +78,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--seq-frames", type=int, default=8, help="frames of the sweeping sequence (0: skip)")
     ap.add_argument("--no-lowp", action="store_true")
+    ap.add_argument("--no-keypoints", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -146,23 +147,23 @@ def main():
     w0, stamp0 = w.clone(), stamp.clone()
     fp = M.fuse_params(frame=1)
 
-    def frame(p=params):
+    def frame(p=params, keys=None):
         pts.copy_(pts0)
         nodes.copy_(nodes0)
         w.copy_(w0)
         stamp.copy_(stamp0)
         x.copy_(x0)
         g = M.build_graph(pts, nodes, p, ws)
-        rep, _ = M.gn_register(pts, nodes, x, g, depth, cam, pose, p, ws)
+        rep, _ = M.gn_register(pts, nodes, x, g, depth, cam, pose, p, ws, keys=keys)
         state["graph"], state["rep"], state["x"] = g, rep, x.clone()
         nmap = M.normal_map(depth, cam)
         M.fuse(pts, w, stamp, nodes, x, g, nmap, cam, pose, fp, ws)
 
-    def timed(p, steps):
+    def timed(p, steps, keys=None):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            frame(p)
+            frame(p, keys)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
@@ -214,6 +215,7 @@ def main():
     # the low-precision form on the same frame: without refinement (the float64
     # oracle's algorithm on a rounded data term) and with two refinement passes
     lowp = None if args.no_lowp else lowp_bench(M, _lib, sc, frame, timed, state, G, args)
+    kpb = None if args.no_keypoints else keypoint_bench(M, sc, frame, timed, state, params, G, args, torch)
 
     out = {
         "metric": "GN iters/s + ms/frame at 640x480, 1600 ED nodes, rel err vs FP64 oracle",
@@ -243,6 +245,8 @@ def main():
     }
     if lowp is not None:
         out["low_precision"] = lowp
+    if kpb is not None:
+        out["keypoints"] = kpb
     if not args.no_batch:
         out["batch"] = batch_bench(M, _lib, args)
     if args.seq_frames > 0:
@@ -328,6 +332,26 @@ def lowp_bench(M, _lib, sc, frame, timed, state, G, args):
             entry["accuracy_vs_same_form_oracle"] = accuracy(state, lp_rep, emu)
         lowp[f"bf16_r{steps}"] = entry
     return lowp
+
+
+def keypoint_bench(M, sc, frame, timed, state, params, G, args, torch):
+    """The Eq.(9) key-point term added to the same frame: 500 generated matches (gen.keypoints, seed 7,
+    0.05 mm noise, w_corr = 10), against the stored float64 oracle run of the same problem."""
+    import gen
+    kp, tgt = gen.keypoints(sc, 500, seed=7, noise=0.05)
+    keys = M.keypoints(torch.tensor(kp, device="cuda"), torch.tensor(tgt, device="cuda").contiguous(), 10.0)
+    for _ in range(max(1, args.warmup)):
+        frame(params, keys)
+    el = timed(params, args.steps, keys)
+    rep = M.read_report(state["rep"])
+    gold = os.path.join(ROOT, "tests", "golden", f"{args.config}_kp500_oracle.npz")
+    acc = accuracy(state, rep, gold)
+    if os.path.exists(gold):
+        z = np.load(gold)
+        acc["rel_err_e_corr_final"] = float(abs(rep[-1]["e_corr"] - z["e_corr_final"]) / z["e_corr_final"])
+    return {"workload": "the same frame with 500 key-point matches (Eq.(9), w_corr = 10)",
+            "ms_per_frame": round(1000.0 * el / args.steps, 4), "gn_iters_per_s": round(G * args.steps / el, 2),
+            "e_corr": [float(rep[0]["e_corr"]), float(rep[-1]["e_corr"])], "accuracy_vs_fp64_oracle": acc}
 
 
 def sequence_bench(M, frames):

@@ -2,7 +2,8 @@
 
 Manufactures inputs only: a key point is carried by one model point (drawn
 without replacement), and its matched observation is that point's position
-under the scene's known deformation (world frame, ``gt_points``) plus optional
+under the scene's known deformation (``gt_points``), mapped by the frame's
+pose into the camera coordinates the depth map lives in, plus optional
 isotropic Gaussian noise.  This stands in for the ORB/SURF feature matches of
 the paper's front end (Sec. II-B), which are not reproduced.
 """
@@ -14,7 +15,9 @@ def keypoints(sc, count, seed=0, noise=0.0):
     rng = np.random.Generator(np.random.PCG64(seed))
     n = len(sc["points"])
     idx = np.sort(rng.choice(n, size=min(count, n), replace=False)).astype(np.int32)
-    tgt = np.asarray(sc["gt_points"], dtype=np.float64)[idx]
+    R = np.asarray(sc["R"], dtype=np.float64)
+    T = np.asarray(sc["T"], dtype=np.float64)
+    tgt = np.asarray(sc["gt_points"], dtype=np.float64)[idx] @ R.T + T
     if noise > 0:
         tgt = tgt + rng.normal(0.0, noise, tgt.shape)
     return idx, tgt.astype(np.float32)

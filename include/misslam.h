@@ -147,7 +147,19 @@ typedef struct {
     int32_t flags;                           /* MISSLAM_FLAG_* */
     int32_t pcg_iters_done;
     int32_t reserved;
+    double e_corr;                           /* unweighted Eq.(9) key-point energy (0 without key points) */
 } misslam_report;
+
+/* (host) key-point matches of the Eq.(9) correspondence term, Sec. II-E: each key point is carried by one
+ * model point (its k nodes and skinning weights) and matched to a 3-D position in the frame's camera
+ * coordinates (those of the depth map).  The term enters the least-squares objective as
+ * w_corr * sum_s |V~_s - V_s|^2, V~_s the Eq.(1) warp of the carrying point with the pose applied. */
+typedef struct {
+    int32_t count;             /* key points, 0 <= count <= n */
+    float w_corr;              /* weight, Sec. III-B: 10 */
+    const int32_t *point;      /* (device) count carrying point indices; indices outside [0, n) are skipped */
+    const float *target;       /* (device) count x 3 matched positions (x, y, z), camera coordinates */
+} misslam_keypoints;
 
 /* (host) fusion settings (Alg. 1-2, Eqs.(12)-(15), Sec. III-B) */
 typedef struct {
@@ -252,6 +264,23 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
                                    const misslam_camera *camera, const misslam_pose *pose,
                                    const misslam_params *params, misslam_report *rep,
                                    int32_t *corr_hist, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * misslam_gn_register with the key-point correspondence term of Eq.(3) added
+ * (Eq.(9), Sec. II-E): each Gauss-Newton step adds, for every key point,
+ * w_corr * w_j w_l (d_j d_l^T) (x) I3 to the blocks (j, l) of its carrying
+ * point's k nodes and w_corr * w_j d_j (x) R^T r to g_j, with d_j = (v - g_j, 1)
+ * and r the warped point minus its match, before the block-Jacobi inverses are
+ * formed.  rep[i].e_corr holds the unweighted key-point energy.  keys must not
+ * be NULL (count 0 runs exactly as misslam_gn_register); float32 form only
+ * (MISSLAM_EUNSUPPORTED otherwise).
+ */
+misslam_status misslam_gn_register_keypoints(const misslam_points *points, misslam_nodes *nodes,
+                                             const misslam_graph *graph, const float *depth,
+                                             const misslam_camera *camera, const misslam_pose *pose,
+                                             const misslam_params *params, const misslam_keypoints *keys,
+                                             misslam_report *rep, int32_t *corr_hist, void *ws,
+                                             size_t ws_bytes, void *stream);
 
 /*
  * Model update after registration (Sec. II-G, Alg. 1-2, Eqs.(12), (14), (15)).

@@ -4,7 +4,8 @@ E_corr compares the new (warped) position of each matched key point with its
 observed position.  Reading: like every term of the Eq.(3) objective it enters
 the least-squares problem as a sum of squares, E_corr = sum_s |V~_s - V_s|^2,
 with V~_s the Eq.(1) warp (pose included) of the key point's canonical model
-point and V_s its matched 3-D position in the world frame.  A key point is
+point and V_s its matched 3-D position, both in the camera coordinates of
+the frame (the pose R, T maps the warped model there, as for the data term).  A key point is
 carried by one model point (index p_s), so it uses that point's k nodes and
 skinning weights.  Weight w_corr = 10 (Sec. III-B lists w_corr twice, 10 and
 1; the first is taken, the second read as a duplicate).
@@ -21,7 +22,7 @@ from .warp import ed_warp
 
 
 def corr_residuals(points, nodes, params, idx, w, R, T, kp_point, kp_target):
-    """(S, 3) residuals V~_s - V_s of the key points (float64)."""
+    """(S, 3) residuals V~_s - V_s of the key points (float64, camera coordinates)."""
     kp = np.asarray(kp_point, dtype=np.int64)
     if kp.size == 0:
         return np.zeros((0, 3))

@@ -44,7 +44,7 @@ class Problem:
     gn_iters: int = 10
     pcg_iters: int = 10
     kp_point: np.ndarray = None  # key points (Eq.(9)): carrying model point per key point
-    kp_target: np.ndarray = None  # (S, 3) matched positions, world frame
+    kp_target: np.ndarray = None  # (S, 3) matched positions, camera coordinates of the frame
     w_corr: float = 10.0          # Sec. III-B
 
     @staticmethod

@@ -62,7 +62,13 @@ class Params(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("e_data", ctypes.c_double), ("e_rot", ctypes.c_double), ("e_reg", ctypes.c_double),
                 ("pcg_resid", ctypes.c_double * (MAX_PCG + 1)), ("n_valid", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("pcg_iters_done", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("pcg_iters_done", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("e_corr", ctypes.c_double)]
+
+
+class Keypoints(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("w_corr", ctypes.c_float), ("point", ctypes.c_void_p),
+                ("target", ctypes.c_void_p)]
 
 
 class FuseParams(ctypes.Structure):
@@ -99,6 +105,8 @@ SIGNATURES = {
     "misslam_pcg_solve": (st, [P(Graph), ctypes.c_int32, vp, vp, P(Params), vp, vp, vp, ctypes.c_size_t, vp]),
     "misslam_gn_register": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params), vp, vp, vp,
                                  ctypes.c_size_t, vp]),
+    "misslam_gn_register_keypoints": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params),
+                                           P(Keypoints), vp, vp, vp, ctypes.c_size_t, vp]),
     "misslam_fuse": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(FuseParams), vp, vp, vp,
                           ctypes.c_size_t, vp]),
     "misslam_energy_vjp": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params), vp, vp, vp, vp,

@@ -14,10 +14,11 @@ namespace {
 
 enum Phase {
     PH_NORMAL_MAP, PH_GRAPH, PH_POINT_PASS, PH_ASSEMBLE, PH_ENERGY, PH_BJACOBI, PH_PCG, PH_FUSE, PH_REFINE, PH_GROW,
-    PH_LIST_PACK, PH_COUNT
+    PH_LIST_PACK, PH_CORR, PH_COUNT
 };
-const char *const kPhaseNames[PH_COUNT] = {"normal_map", "build_graph", "point_pass", "assemble", "energy",   "bjacobi",
-                                           "pcg",        "fuse",        "refine",     "grow",     "list_pack"};
+const char *const kPhaseNames[PH_COUNT] = {"normal_map", "build_graph", "point_pass", "assemble",  "energy",
+                                           "bjacobi",    "pcg",         "fuse",       "refine",    "grow",
+                                           "list_pack",  "corr"};
 
 struct Profiler {
     std::mutex mu;
@@ -108,6 +109,7 @@ struct Carver {
 
 struct Layout {
     msl::StepScratch step;
+    msl::CorrScratch corr;
     msl::PcgScratch pcg;
     msl::GraphScratch graph;
     float4 *nmap;
@@ -169,6 +171,9 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
     // last, so that every buffer above keeps its place whatever k is
     L.step.lpa = c.take<float4>((size_t)k * n);
     L.step.lpw = c.take<float4>((size_t)k * n * ((k + 3) / 4));
+    L.corr.kp_nodes = c.take<int32_t>((size_t)k * n);
+    L.corr.kp_data = c.take<float>((size_t)(3 + 4 * k) * n);
+    L.corr.kp_energy = c.take<double>((size_t)n);
     L.bytes = align_up(c.off);
     return L;
 }
@@ -297,7 +302,8 @@ misslam_status misslam_warp(const misslam_points *points, const misslam_nodes *n
 
 static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, int64_t n, int m,
                             misslam_report *rep, float reject, hipStream_t st, unsigned *zero_words = nullptr,
-                            int zero_count = 0) {
+                            int zero_count = 0, const msl::KeyArgs *kp = nullptr,
+                            const msl::CorrScratch *corr = nullptr) {
     hipError_t e;
     {
         Timed t(PH_POINT_PASS, st);
@@ -306,6 +312,10 @@ static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, i
     if (e == hipSuccess) {
         Timed t(PH_ASSEMBLE, st);
         e = msl::launch_assemble(a, s, st);
+    }
+    if (e == hipSuccess && kp && corr) {
+        Timed t(PH_CORR, st);
+        e = msl::launch_corr_rows(a, *kp, *corr, true, rep, st);
     }
     if (e == hipSuccess) {
         Timed t(PH_ENERGY, st);
@@ -413,15 +423,28 @@ misslam_status misslam_pcg_solve(const misslam_graph *graph, int32_t m, const fl
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
 }
 
-misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
-                                   const float *depth, const misslam_camera *camera, const misslam_pose *pose,
-                                   const misslam_params *params, misslam_report *rep, int32_t *corr_hist, void *ws,
-                                   size_t ws_bytes, void *stream) {
+static misslam_status gn_register(const misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
+                                  const float *depth, const misslam_camera *camera, const misslam_pose *pose,
+                                  const misslam_params *params, const misslam_keypoints *keys, misslam_report *rep,
+                                  int32_t *corr_hist, void *ws, size_t ws_bytes, void *stream) {
     if (!valid_points(points) || !valid_nodes(nodes) || !valid_graph(graph, points->n) || !depth ||
         !valid_camera(camera) || !pose || !valid_params(params) || !rep || !ws)
         return MISSLAM_EINVAL;
+    if (keys && (keys->count < 0 || keys->count > points->n || (keys->count > 0 && (!keys->point || !keys->target)) ||
+                 !std::isfinite(keys->w_corr) || keys->w_corr < 0.f))
+        return MISSLAM_EINVAL;
     if (graph->k != params->k) return MISSLAM_ESHAPE;
     if (params->precision != MISSLAM_PREC_FP32 && params->k > 4) return MISSLAM_EUNSUPPORTED;
+    if (params->precision != MISSLAM_PREC_FP32 && keys && keys->count > 0) return MISSLAM_EUNSUPPORTED;
+    msl::KeyArgs ka{};
+    const msl::KeyArgs *kp = nullptr;
+    if (keys && keys->count > 0) {
+        ka.count = keys->count;
+        ka.w_corr = keys->w_corr;
+        ka.point = keys->point;
+        ka.target = keys->target;
+        kp = &ka;
+    }
     const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, params->pcg_iters, params->k);
     if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
     if ((int64_t)graph->bsr_cap > (int64_t)nodes->m * MISSLAM_MAX_ROW) return MISSLAM_ECAPACITY;
@@ -437,6 +460,10 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
         Timed t(PH_NORMAL_MAP, st);
         e = msl::launch_normal_map(depth, view(camera), L.nmap, st);
     }
+    if (e == hipSuccess && kp)
+        e = msl::launch_kp_nodes(step_args(points, nodes, graph, L.nmap, camera, pose, params, L.blocks, L.gvec,
+                                           nullptr),
+                                 *kp, L.corr.kp_nodes, st);
     if (e == hipSuccess && !lowp && G > 0) {
         Timed t(PH_LIST_PACK, st);
         e = msl::launch_list_pack(step_args(points, nodes, graph, L.nmap, camera, pose, params, L.blocks, L.gvec,
@@ -456,11 +483,13 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
                 e = msl::launch_point_pass(a, L.step, st);
             }
             if (e == hipSuccess) e = msl::launch_node_energy(a, L.step, st);
+            if (e == hipSuccess && kp) e = msl::launch_corr_rows(a, *kp, L.corr, false, rep + it, st);
             if (e == hipSuccess) e = msl::launch_energy_report(L.step, n, m, rep + it, params->reject_threshold, st);
             break;
         }
         if (!lowp) {
-            e = linearize(a, L.step, n, m, rep + it, params->reject_threshold, st, L.pcg.bar, msl::msl_sync_words(m));
+            e = linearize(a, L.step, n, m, rep + it, params->reject_threshold, st, L.pcg.bar, msl::msl_sync_words(m),
+                          kp, &L.corr);
             if (e == hipSuccess) {
                 Timed t(PH_PCG, st);
                 e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
@@ -498,6 +527,25 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
         if (e == hipSuccess) e = msl::launch_axpy(nodes->params, L.delta, 12 * m, st);
     }
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
+}
+
+misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
+                                   const float *depth, const misslam_camera *camera, const misslam_pose *pose,
+                                   const misslam_params *params, misslam_report *rep, int32_t *corr_hist, void *ws,
+                                   size_t ws_bytes, void *stream) {
+    return gn_register(points, nodes, graph, depth, camera, pose, params, nullptr, rep, corr_hist, ws, ws_bytes,
+                       stream);
+}
+
+misslam_status misslam_gn_register_keypoints(const misslam_points *points, misslam_nodes *nodes,
+                                             const misslam_graph *graph, const float *depth,
+                                             const misslam_camera *camera, const misslam_pose *pose,
+                                             const misslam_params *params, const misslam_keypoints *keys,
+                                             misslam_report *rep, int32_t *corr_hist, void *ws, size_t ws_bytes,
+                                             void *stream) {
+    if (!keys) return MISSLAM_EINVAL;
+    return gn_register(points, nodes, graph, depth, camera, pose, params, keys, rep, corr_hist, ws, ws_bytes,
+                       stream);
 }
 
 misslam_status misslam_fuse(misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,

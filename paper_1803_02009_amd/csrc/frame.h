@@ -54,6 +54,13 @@ struct StepScratch {
     float4 *lpw;          // k n x ceil(k/4): w_pj w_pq over the entry's nodes q in index order, zero-padded
 };
 
+// Key-point term scratch (at most n key points).
+struct CorrScratch {
+    int32_t *kp_nodes;    // k per key point: the carrying point's nodes (-1: skipped key point)
+    float *kp_data;       // 3 + 4k per key point: R^T r, then per node w and v - g
+    double *kp_energy;    // 1 per key point: |r|^2
+};
+
 struct PcgScratch {
     float *r, *z, *p, *q;  // 12m each
     double *part;          // (pcg_iters + 1) x 4 x nblk partial sums
@@ -84,6 +91,14 @@ struct StepArgs {
     const int32_t *corr_in;  // optional frozen correspondences (no association, no gates)
     float *minv;       // optional m x 144 block-Jacobi inverses computed with the assembly
     int32_t *flags;    // report flags (NONSPD_BLOCK) when minv is set
+};
+
+// Key-point matches of the Eq.(9) correspondence term (device arrays).
+struct KeyArgs {
+    int count;
+    float w_corr;
+    const int32_t *point;    // carrying model point per key point (indices outside [0, n) are skipped)
+    const float *target;     // 3 per key point, camera coordinates of the frame
 };
 
 struct PcgArgs {
@@ -173,6 +188,14 @@ hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_
 // positions are fixed across its Gauss-Newton steps) before the first launch_assemble.
 hipError_t launch_list_pack(const StepArgs &a, const StepScratch &s, hipStream_t st);
 hipError_t launch_assemble(const StepArgs &a, const StepScratch &s, hipStream_t st);
+// Eq.(9): evaluates every key point at the current parameters and writes rep->e_corr; with assemble, adds
+// the term to the blocks and gradient of every row it touches (after launch_assemble) and re-inverts their
+// damped diagonal blocks.
+hipError_t launch_corr_rows(const StepArgs &a, const KeyArgs &kp, const CorrScratch &c, bool assemble,
+                            misslam_report *rep, hipStream_t st);
+// kp_nodes[s k + q] = node q of key point s's carrying point (-1 if its index is outside [0, n)); once per
+// registration, before launch_corr_rows.
+hipError_t launch_kp_nodes(const StepArgs &a, const KeyArgs &kp, int32_t *kp_nodes, hipStream_t st);
 hipError_t launch_assemble_lp(const StepArgs &a, const StepScratch &s, int precision, float *rr_out,
                               hipStream_t st);
 hipError_t launch_refine_rhs(const StepArgs &a, const StepScratch &s, const float *dx, const float *rr, const float *g,

@@ -270,6 +270,7 @@ __global__ void report_init_batched_kernel(const BatchItem *__restrict__ items, 
         rep[t].flags = 0;
         rep[t].pcg_iters_done = 0;
         rep[t].reserved = 0;
+        rep[t].e_corr = 0.0;
     }
 }
 
@@ -290,6 +291,7 @@ __global__ void report_init_kernel(misslam_report *rep, int count) {
         rep[t].flags = 0;
         rep[t].pcg_iters_done = 0;
         rep[t].reserved = 0;
+        rep[t].e_corr = 0.0;
     }
 }
 

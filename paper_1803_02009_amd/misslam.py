@@ -139,7 +139,7 @@ class Graph:
 
 REPORT_DTYPE = np.dtype([("e_data", "<f8"), ("e_rot", "<f8"), ("e_reg", "<f8"),
                          ("pcg_resid", "<f8", (_lib.MAX_PCG + 1,)), ("n_valid", "<i4"), ("flags", "<i4"),
-                         ("pcg_iters_done", "<i4"), ("reserved", "<i4")])
+                         ("pcg_iters_done", "<i4"), ("reserved", "<i4"), ("e_corr", "<f8")])
 assert REPORT_DTYPE.itemsize == ctypes.sizeof(_lib.Report)
 
 
@@ -209,16 +209,41 @@ def pcg_solve(graph, m, blocks, g, params, ws):
     return delta, rep
 
 
-def gn_register(points, nodes, x, graph, depth, cam, pose_, params, ws, corr_hist=False):
-    """Runs params.gn_iters Gauss-Newton steps, updating x in place; returns (report, corr_hist or None)."""
+class Keypoints:
+    """Key-point matches of Eq.(9): point (S,) int32 carrying model points, target (S, 3) float32 positions in the
+    frame's camera coordinates.  Holds the device tensors, so they live as long as this object."""
+
+    def __init__(self, point, target, w_corr=10.0):
+        _need(point, torch.int32, "point")
+        _need(target, torch.float32, "target")
+        if target.dim() != 2 or target.shape[1] != 3 or target.shape[0] != point.shape[0]:
+            raise ValueError("target must be (S, 3) matching point (S,)")
+        self.point, self.target, self.w_corr = point, target, float(w_corr)
+
+    def c(self):
+        return _lib.Keypoints(int(self.point.shape[0]), self.w_corr, _ptr(self.point), _ptr(self.target))
+
+
+def keypoints(point, target, w_corr=10.0):
+    return Keypoints(point, target, w_corr)
+
+
+def gn_register(points, nodes, x, graph, depth, cam, pose_, params, ws, corr_hist=False, keys=None):
+    """Runs params.gn_iters Gauss-Newton steps, updating x in place; returns (report, corr_hist or None).
+
+    keys (from keypoints()) adds the Eq.(9) key-point term."""
     n, m = points.shape[1], nodes.shape[1]
     rep = new_report(params.gn_iters + 1)
     ch = torch.empty((params.gn_iters, n), dtype=torch.int32, device=points.device) if corr_hist else None
     buf = ws.get(workspace_bytes(n, m, cam.width, cam.height, params))
-    check("misslam_gn_register", load().misslam_gn_register(
-        ctypes.byref(points_struct(points)), ctypes.byref(nodes_struct(nodes, x)), ctypes.byref(graph.c()),
-        _ptr(depth), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(params.c()), _ptr(rep), _ptr(ch),
-        _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
+    common = (ctypes.byref(points_struct(points)), ctypes.byref(nodes_struct(nodes, x)), ctypes.byref(graph.c()),
+              _ptr(depth), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(params.c()))
+    tail = (_ptr(rep), _ptr(ch), _ptr(buf), ctypes.c_size_t(buf.numel()), _stream())
+    if keys is None:
+        check("misslam_gn_register", load().misslam_gn_register(*common, *tail))
+    else:
+        kc = keys.c()
+        check("misslam_gn_register_keypoints", load().misslam_gn_register_keypoints(*common, ctypes.byref(kc), *tail))
     return rep, ch
 
 

@@ -1,13 +1,15 @@
 """Writes the float64 oracle's registration result for a generated frame.
 
-Calls only the scene generator and oracle/: nothing here comes from the GPU
-path.  Usage: python tests/golden/make_oracle_golden.py c3 [c3:bf16:2 ...]
+Calls only the input generators and oracle/: nothing here comes from the GPU
+path.  Usage: python tests/golden/make_oracle_golden.py c3 [c3:bf16:2 c3:kp:500 ...]
 A plain name runs the float64 oracle; name:prec:R runs its emulation of the
 low-precision form (data-term Jacobian rows rounded to bf16 / fp16 before
-J^T J, R refinement passes of each step against the unrounded system).
-Output: tests/golden/<name>[_<prec>_r<R>]_oracle.npz with x (m, 12) after the
-frame's Gauss-Newton iterations (independent decisions), the final energies
-and the per-iteration data energies.
+J^T J, R refinement passes of each step against the unrounded system);
+name:kp:S adds S generated key points (gen.keypoints, seed 7, 0.05 mm noise)
+with the Eq.(9) term at w_corr = 10.
+Output: tests/golden/<name>[_<prec>_r<R> | _kp<S>]_oracle.npz with x (m, 12)
+after the frame's Gauss-Newton iterations (independent decisions), the final
+energies and the per-iteration data energies.
 """
 import os
 import sys
@@ -31,6 +33,12 @@ def main(spec):
     if len(parts) == 1:
         x, rep = oracle.gn_register(pb)
         out = f"{name}_oracle.npz"
+    elif parts[1] == "kp":
+        S = int(parts[2])
+        kp, tgt = gen.keypoints(sc, S, seed=7, noise=0.05)
+        pb = oracle.Problem.from_scene(sc, kp_point=kp, kp_target=tgt, w_corr=10.0)
+        x, rep = oracle.gn_register(pb)
+        out = f"{name}_kp{S}_oracle.npz"
     else:
         prec, steps = parts[1], int(parts[2])
         rnd = ROUND[prec]
@@ -39,7 +47,7 @@ def main(spec):
     it = rep["iters"]
     np.savez_compressed(os.path.join(HERE, out), x=x, e_data_final=rep["final"]["e_data"],
                         e_rot_final=rep["final"]["e_rot"], e_reg_final=rep["final"]["e_reg"],
-                        n_valid_final=rep["final"]["n_valid"],
+                        n_valid_final=rep["final"]["n_valid"], e_corr_final=rep["final"]["e_corr"],
                         e_data=np.array([e["e_data"] for e in it]), n_valid=np.array([e["n_valid"] for e in it]))
     print(out, "final e_data", rep["final"]["e_data"], "n_valid", rep["final"]["n_valid"])
 

@@ -42,9 +42,9 @@ def test_struct_layout_matches_header():
 #include <stddef.h>
 #include "misslam.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(misslam_camera), sizeof(misslam_pose),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(misslam_camera), sizeof(misslam_pose),
          sizeof(misslam_points), sizeof(misslam_nodes), sizeof(misslam_graph), sizeof(misslam_params),
-         sizeof(misslam_report), sizeof(misslam_fuse_params), sizeof(misslam_problem));
+         sizeof(misslam_report), sizeof(misslam_fuse_params), sizeof(misslam_problem), sizeof(misslam_keypoints));
   printf("%zu %zu %zu %zu %zu\n", offsetof(misslam_params, eps_d), offsetof(misslam_params, lambda),
          offsetof(misslam_report, n_valid), offsetof(misslam_graph, info), offsetof(misslam_params, solve_launch));
   return 0;
@@ -58,7 +58,7 @@ int main(void) {
         out = subprocess.check_output([exe]).decode().split("\n")
     sizes = [int(v) for v in out[0].split()]
     want = [ctypes.sizeof(t) for t in (_lib.Camera, _lib.Pose, _lib.Points, _lib.Nodes, _lib.Graph, _lib.Params,
-                                       _lib.Report, _lib.FuseParams, _lib.Problem)]
+                                       _lib.Report, _lib.FuseParams, _lib.Problem, _lib.Keypoints)]
     assert sizes == want
     offs = [int(v) for v in out[1].split()]
     assert offs == [_lib.Params.eps_d.offset, _lib.Params.lambda_.offset, _lib.Report.n_valid.offset,
@@ -142,6 +142,21 @@ def test_validation_errors(lib):
     assert lib.misslam_build_graph(B(pts), B(nds), B(p), B(gr), FAKE, 16, None) == _lib.EWORKSPACE
     assert lib.misslam_gn_register(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(p), FAKE, None, FAKE, 16,
                                    None) == _lib.EWORKSPACE
+    # key points: required, count >= 0, arrays when count > 0, finite non-negative weight; float32 form only
+    kpr = lib.misslam_gn_register_keypoints
+    assert kpr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(p), None, FAKE, None, FAKE, 1 << 40,
+               None) == _lib.EINVAL
+    for bad in (_lib.Keypoints(-1, 10.0, FAKE, FAKE), _lib.Keypoints(3, 10.0, None, FAKE),
+                _lib.Keypoints(3, 10.0, FAKE, None), _lib.Keypoints(3, float("nan"), FAKE, FAKE),
+                _lib.Keypoints(3, -1.0, FAKE, FAKE)):
+        assert kpr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(p), B(bad), FAKE, None, FAKE, 1 << 40,
+                   None) == _lib.EINVAL
+    plp = _lib.Params()
+    lib.misslam_default_params(B(plp))
+    plp.precision = _lib.PREC_BF16
+    ok_keys = _lib.Keypoints(3, 10.0, FAKE, FAKE)
+    assert kpr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(plp), B(ok_keys), FAKE, None, FAKE, 1 << 40,
+               None) == _lib.EUNSUPPORTED
     # n above capacity, bad camera, bad k
     over = _lib.Points(200, 100, *([FAKE] * 6), 0, 0)
     assert lib.misslam_warp(B(over), B(nds), B(gr), None, FAKE, None, None) == _lib.EINVAL

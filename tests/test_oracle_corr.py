@@ -121,7 +121,7 @@ def test_gauss_newton_recovers_translation_from_key_points():
     d = np.array([0.6, -0.4, 1.2])
     kp = np.arange(0, len(sc["points"]), 11).astype(np.int32)
     R, T = sc["R"].astype(np.float64), sc["T"].astype(np.float64)
-    # targets in the world frame: the translated canonical point under the pose
+    # targets in camera coordinates: the translated canonical point under the pose
     tgt = ((sc["points"][kp].astype(np.float64) + d) @ R.T + T).astype(np.float32)
     pb = oracle.Problem.from_scene(sc, w_data=0.0, kp_point=kp, kp_target=tgt, gn_iters=6, pcg_iters=60)
     x, rep = oracle.gn_register(pb)
