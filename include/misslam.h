@@ -71,6 +71,7 @@ typedef enum {
 #define MISSLAM_MAX_PCG  64
 #define MISSLAM_MAX_ROW  32       /* max blocks per row of the normal matrix (node degree + 1) */
 #define MISSLAM_MAX_LIST 2048     /* max points influenced by one node */
+#define MISSLAM_MAX_KEYPOINTS 16777216   /* max key points per registration (2^24) */
 #define MISSLAM_SOLVE_ROWS 16     /* node rows per workgroup of the one-launch PCG of a single problem
                                      with at most 16 rows per CU (larger ones pack up to 21) */
 
@@ -155,7 +156,7 @@ typedef struct {
  * coordinates (those of the depth map).  The term enters the least-squares objective as
  * w_corr * sum_s |V~_s - V_s|^2, V~_s the Eq.(1) warp of the carrying point with the pose applied. */
 typedef struct {
-    int32_t count;             /* key points, 0 <= count <= n */
+    int32_t count;             /* key points, 0 <= count <= min(n, MISSLAM_MAX_KEYPOINTS) */
     float w_corr;              /* weight, Sec. III-B: 10 */
     const int32_t *point;      /* (device) count carrying point indices; indices outside [0, n) are skipped */
     const float *target;       /* (device) count x 3 matched positions (x, y, z), camera coordinates */

@@ -15,6 +15,7 @@ WEIGHT_GAUSS, WEIGHT_LINEAR = 0, 1
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 LAUNCH_PLAIN, LAUNCH_COOPERATIVE = 0, 1
 MAX_K, MAX_PCG, MAX_ROW, MAX_LIST, SOLVE_ROWS = 8, 64, 32, 2048, 16
+MAX_KEYPOINTS = 1 << 24
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
 c_int32_p = ctypes.POINTER(ctypes.c_int32)

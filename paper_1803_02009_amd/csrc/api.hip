@@ -305,21 +305,23 @@ static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, i
                             int zero_count = 0, const msl::KeyArgs *kp = nullptr,
                             const msl::CorrScratch *corr = nullptr) {
     hipError_t e;
+    const bool keys = kp && corr && kp->count > 0;
     {
         Timed t(PH_POINT_PASS, st);
-        e = msl::launch_point_pass(a, s, st);
+        e = msl::launch_point_pass(a, s, st, keys ? kp : nullptr, keys ? corr : nullptr);
     }
     if (e == hipSuccess) {
         Timed t(PH_ASSEMBLE, st);
         e = msl::launch_assemble(a, s, st);
     }
-    if (e == hipSuccess && kp && corr) {
+    if (e == hipSuccess && keys) {
         Timed t(PH_CORR, st);
-        e = msl::launch_corr_rows(a, *kp, *corr, true, rep, st);
+        e = msl::launch_corr_rows(a, *kp, *corr, st);
     }
     if (e == hipSuccess) {
         Timed t(PH_ENERGY, st);
-        e = msl::launch_energy_report(s, n, m, rep, reject, st, zero_words, zero_count);
+        e = msl::launch_energy_report(s, n, m, rep, reject, st, zero_words, zero_count,
+                                      keys ? corr->kp_energy : nullptr, keys ? kp->count : 0);
     }
     return e;
 }
@@ -430,7 +432,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
     if (!valid_points(points) || !valid_nodes(nodes) || !valid_graph(graph, points->n) || !depth ||
         !valid_camera(camera) || !pose || !valid_params(params) || !rep || !ws)
         return MISSLAM_EINVAL;
-    if (keys && (keys->count < 0 || keys->count > points->n || (keys->count > 0 && (!keys->point || !keys->target)) ||
+    if (keys && (keys->count < 0 || keys->count > points->n || keys->count > MISSLAM_MAX_KEYPOINTS || (keys->count > 0 && (!keys->point || !keys->target)) ||
                  !std::isfinite(keys->w_corr) || keys->w_corr < 0.f))
         return MISSLAM_EINVAL;
     if (graph->k != params->k) return MISSLAM_ESHAPE;
@@ -478,13 +480,15 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
             a.flags = &rep[it].flags;
         }
         if (it == G) {   // final entry: energies at the returned parameters, no system needed
+            const bool keys = kp && kp->count > 0;
             {
                 Timed t(PH_POINT_PASS, st);
-                e = msl::launch_point_pass(a, L.step, st);
+                e = msl::launch_point_pass(a, L.step, st, keys ? kp : nullptr, keys ? &L.corr : nullptr);
             }
             if (e == hipSuccess) e = msl::launch_node_energy(a, L.step, st);
-            if (e == hipSuccess && kp) e = msl::launch_corr_rows(a, *kp, L.corr, false, rep + it, st);
-            if (e == hipSuccess) e = msl::launch_energy_report(L.step, n, m, rep + it, params->reject_threshold, st);
+            if (e == hipSuccess)
+                e = msl::launch_energy_report(L.step, n, m, rep + it, params->reject_threshold, st, nullptr, 0,
+                                              keys ? L.corr.kp_energy : nullptr, keys ? kp->count : 0);
             break;
         }
         if (!lowp) {

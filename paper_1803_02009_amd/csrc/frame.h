@@ -101,6 +101,44 @@ struct KeyArgs {
     const float *target;     // 3 per key point, camera coordinates of the frame
 };
 
+template <int K>
+constexpr int kp_stride() { return 3 + 4 * K; }   // per key point: R^T r, then per node q: w_q, d_q (3)
+
+// Eq.(9) at the current parameters for key point s: residual r = V~ - V (float32), R^T r, the k weights
+// and d_q = v - g_q into kp_data, the energy |r|^2 (float64; 0 for a skipped key point) into kp_energy.
+template <int K>
+__device__ __forceinline__ void kp_eval_body(const StepArgs &a, const KeyArgs &kp, float *kp_data,
+                                             double *kp_energy, int s) {
+    if (s >= kp.count) return;
+    float *o = kp_data + (size_t)s * kp_stride<K>();
+    const int64_t n = a.pts.n;
+    const int p = kp.point[s];
+    if (p < 0 || p >= n) {
+        for (int t = 0; t < kp_stride<K>(); ++t) o[t] = 0.f;
+        kp_energy[s] = 0.0;
+        return;
+    }
+    const float vx = a.pts.px[p], vy = a.pts.py[p], vz = a.pts.pz[p];
+    float ox, oy, oz;
+    ed_blend<K>(vx, vy, vz, a.g.knn_idx, a.g.knn_w, n, p, a.nd, ox, oy, oz);
+    apply_pose(a.pose, ox, oy, oz);
+    const float rx = ox - kp.target[3 * (size_t)s], ry = oy - kp.target[3 * (size_t)s + 1],
+                rz = oz - kp.target[3 * (size_t)s + 2];
+    const float *R = a.pose.R;
+    o[0] = fmaf(R[6], rz, fmaf(R[3], ry, R[0] * rx));
+    o[1] = fmaf(R[7], rz, fmaf(R[4], ry, R[1] * rx));
+    o[2] = fmaf(R[8], rz, fmaf(R[5], ry, R[2] * rx));
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const int l = a.g.knn_idx[(int64_t)q * n + p];
+        o[3 + 4 * q] = a.g.knn_w[(int64_t)q * n + p];
+        o[4 + 4 * q] = vx - a.nd.gx[l];
+        o[5 + 4 * q] = vy - a.nd.gy[l];
+        o[6 + 4 * q] = vz - a.nd.gz[l];
+    }
+    kp_energy[s] = ((double)rx * rx + (double)ry * ry) + (double)rz * rz;
+}
+
 struct PcgArgs {
     const int32_t *row_ptr, *col_idx;
     const float *blocks, *minv, *g;
@@ -183,16 +221,16 @@ struct FuseArgs {
 hipError_t launch_fuse(const FuseArgs &f, float *gx, float *gy, float *gz, float *params, int m, int32_t *reg_map,
                        hipStream_t st);
 
-hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_t st);
+// With key points (kp, c), the same launch also evaluates them (kp_eval_body) in blocks of its own.
+hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_t st, const KeyArgs *kp = nullptr,
+                             const CorrScratch *c = nullptr);
 // The list-entry packing the assembly reads; run once per registration (the graph, canonical points and node
 // positions are fixed across its Gauss-Newton steps) before the first launch_assemble.
 hipError_t launch_list_pack(const StepArgs &a, const StepScratch &s, hipStream_t st);
 hipError_t launch_assemble(const StepArgs &a, const StepScratch &s, hipStream_t st);
-// Eq.(9): evaluates every key point at the current parameters and writes rep->e_corr; with assemble, adds
-// the term to the blocks and gradient of every row it touches (after launch_assemble) and re-inverts their
-// damped diagonal blocks.
-hipError_t launch_corr_rows(const StepArgs &a, const KeyArgs &kp, const CorrScratch &c, bool assemble,
-                            misslam_report *rep, hipStream_t st);
+// Eq.(9): adds the term to the blocks and gradient of every row it touches (after launch_assemble and
+// launch_kp_eval) and re-inverts their damped diagonal blocks.
+hipError_t launch_corr_rows(const StepArgs &a, const KeyArgs &kp, const CorrScratch &c, hipStream_t st);
 // kp_nodes[s k + q] = node q of key point s's carrying point (-1 if its index is outside [0, n)); once per
 // registration, before launch_corr_rows.
 hipError_t launch_kp_nodes(const StepArgs &a, const KeyArgs &kp, int32_t *kp_nodes, hipStream_t st);
@@ -208,9 +246,11 @@ hipError_t launch_grad_params(const float *g, int m, const float *grad_e, float 
 hipError_t launch_energy_total(const misslam_report *rep, float w_data, float w_rot, float w_reg, double *out,
                                hipStream_t st);
 // zero_words (optional): zero_count words (a multiple of 4, 16-byte aligned) cleared on the way
-// (the next persistent solve's sync area)
+// (the next persistent solve's sync area); kp_energy (optional): kp_count key-point energies summed into
+// rep->e_corr
 hipError_t launch_energy_report(const StepScratch &s, int64_t n, int m, misslam_report *rep, float reject_thr,
-                                hipStream_t st, unsigned *zero_words = nullptr, int zero_count = 0);
+                                hipStream_t st, unsigned *zero_words = nullptr, int zero_count = 0,
+                                const double *kp_energy = nullptr, int kp_count = 0);
 hipError_t launch_bjacobi(const GraphView &g, int m, const float *blocks, float lambda, float *minv,
                           int32_t *flags, hipStream_t st);
 // PCG solve into delta; when params != nullptr also applies params += delta (the GN update).

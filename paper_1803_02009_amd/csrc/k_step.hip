@@ -103,8 +103,12 @@ __device__ __forceinline__ void point_pass_body(const StepArgs &a, const StepScr
 }
 
 template <int K>
-__global__ void __launch_bounds__(kPtBlock) point_pass_kernel(StepArgs a, StepScratch s) {
-    point_pass_body<K>(a, s, blockIdx.x);
+__global__ void __launch_bounds__(kPtBlock) point_pass_kernel(StepArgs a, StepScratch s, KeyArgs kp, float *kp_data,
+                                                             double *kp_energy, unsigned ptb) {
+    if (blockIdx.x < ptb)
+        point_pass_body<K>(a, s, blockIdx.x);
+    else   // the key points, Eq.(9), one per thread
+        kp_eval_body<K>(a, kp, kp_data, kp_energy, (int)(blockIdx.x - ptb) * kPtBlock + (int)threadIdx.x);
 }
 
 // ---------------------------------------------------------------- row assembly
@@ -1175,12 +1179,13 @@ hipError_t launch_energy_total(const misslam_report *rep, float w_data, float w_
 __device__ __forceinline__ void energy_report_body(const double *__restrict__ pt_part, int npb,
                                                    const double *__restrict__ node_part, int m, misslam_report *rep,
                                                    float reject_thr, unsigned *__restrict__ zero_words,
-                                                   int zero_count) {
-    __shared__ double red[5][256 / kWave];
+                                                   int zero_count, const double *__restrict__ kp_energy = nullptr,
+                                                   int kp_count = 0) {
+    __shared__ double red[6][256 / kWave];
     if (zero_words)   // the next solve's sync area
         for (int t = threadIdx.x; t < zero_count / 4; t += 256)
             reinterpret_cast<uint4 *>(zero_words)[t] = make_uint4(0u, 0u, 0u, 0u);
-    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int t = threadIdx.x; t < npb; t += 256) {
         v[0] += pt_part[3 * t];
         v[1] += pt_part[3 * t + 1];
@@ -1190,10 +1195,11 @@ __device__ __forceinline__ void energy_report_body(const double *__restrict__ pt
         v[3] += node_part[2 * t];
         v[4] += node_part[2 * t + 1];
     }
+    for (int t = threadIdx.x; t < kp_count; t += 256) v[5] += kp_energy[t];
     // wave butterflies, then the four waves in order: a fixed summation order
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
+    for (int q = 0; q < 6; ++q) {
         double t = v[q];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
@@ -1201,15 +1207,16 @@ __device__ __forceinline__ void energy_report_body(const double *__restrict__ pt
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double tot[5];
-        for (int q = 0; q < 5; ++q) tot[q] = ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
+        double tot[6];
+        for (int q = 0; q < 6; ++q) tot[q] = ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
         const double ed = tot[0], nv = tot[1], sa = tot[2], er = tot[3], eg = tot[4];
         rep->e_data = ed;
         rep->e_rot = er;
         rep->e_reg = eg;
         rep->n_valid = (int32_t)nv;
+        rep->e_corr = tot[5];
         int flags = 0;
-        if (!isfinite(ed) || !isfinite(er) || !isfinite(eg)) flags |= MISSLAM_FLAG_NONFINITE;
+        if (!isfinite(ed) || !isfinite(er) || !isfinite(eg) || !isfinite(tot[5])) flags |= MISSLAM_FLAG_NONFINITE;
         if (reject_thr > 0.f && nv > 0 && sa / nv > (double)reject_thr) flags |= MISSLAM_FLAG_FRAME_REJECT;
         rep->flags |= flags;
     }
@@ -1218,16 +1225,29 @@ __device__ __forceinline__ void energy_report_body(const double *__restrict__ pt
 __global__ void __launch_bounds__(256) energy_report_kernel(const double *__restrict__ pt_part, int npb,
                                                             const double *__restrict__ node_part, int m,
                                                             misslam_report *rep, float reject_thr,
-                                                            unsigned *__restrict__ zero_words, int zero_count) {
-    energy_report_body(pt_part, npb, node_part, m, rep, reject_thr, zero_words, zero_count);
+                                                            unsigned *__restrict__ zero_words, int zero_count,
+                                                            const double *__restrict__ kp_energy, int kp_count) {
+    energy_report_body(pt_part, npb, node_part, m, rep, reject_thr, zero_words, zero_count, kp_energy, kp_count);
 }
 
-hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_t st) {
+hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_t st, const KeyArgs *kp,
+                             const CorrScratch *c) {
     const int64_t n = a.pts.n;
     const unsigned ptb = nblk(n > 0 ? n : 1, kPtBlock);
+    KeyArgs kk{};
+    float *kd = nullptr;
+    double *ke = nullptr;
+    if (kp && c && kp->count > 0) {
+        kk = *kp;
+        kd = c->kp_data;
+        ke = c->kp_energy;
+    }
+    const unsigned kpb = (unsigned)((kk.count + kPtBlock - 1) / kPtBlock);
     switch (a.g.k) {
 #define MSL_PP_CASE(KK)                                                                                     \
-    case KK: hipLaunchKernelGGL((point_pass_kernel<KK>), dim3(ptb), dim3(kPtBlock), 0, st, a, s); break;
+    case KK:                                                                                                \
+        hipLaunchKernelGGL((point_pass_kernel<KK>), dim3(ptb + kpb), dim3(kPtBlock), 0, st, a, s, kk, kd, ke, ptb); \
+        break;
         MSL_PP_CASE(1) MSL_PP_CASE(2) MSL_PP_CASE(3) MSL_PP_CASE(4)
         MSL_PP_CASE(5) MSL_PP_CASE(6) MSL_PP_CASE(7) MSL_PP_CASE(8)
 #undef MSL_PP_CASE
@@ -1265,11 +1285,12 @@ hipError_t launch_assemble(const StepArgs &a, const StepScratch &s, hipStream_t 
 }
 
 hipError_t launch_energy_report(const StepScratch &s, int64_t n, int m, misslam_report *rep, float reject_thr,
-                                hipStream_t st, unsigned *zero_words, int zero_count) {
+                                hipStream_t st, unsigned *zero_words, int zero_count, const double *kp_energy,
+                                int kp_count) {
     const int npb = (int)nblk(n > 0 ? n : 1, kPtBlock);
     if (zero_count < 0 || zero_count > MSL_BAR_WORDS || zero_count % 4) return hipErrorInvalidValue;
     hipLaunchKernelGGL(energy_report_kernel, dim3(1), dim3(256), 0, st, s.pt_part, npb, s.node_part, m, rep,
-                       reject_thr, zero_words, zero_count);
+                       reject_thr, zero_words, zero_count, kp_energy, kp_energy ? kp_count : 0);
     return hipGetLastError();
 }
 

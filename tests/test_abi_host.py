@@ -71,7 +71,8 @@ def test_header_constants_match_binding():
     want = {"FLAG_SYNC_TIMEOUT": _lib.FLAG_SYNC_TIMEOUT, "PREC_FP32": _lib.PREC_FP32, "PREC_BF16": _lib.PREC_BF16,
             "PREC_FP16": _lib.PREC_FP16, "LAUNCH_PLAIN": _lib.LAUNCH_PLAIN,
             "LAUNCH_COOPERATIVE": _lib.LAUNCH_COOPERATIVE, "MAX_K": _lib.MAX_K, "MAX_PCG": _lib.MAX_PCG,
-            "MAX_ROW": _lib.MAX_ROW, "MAX_LIST": _lib.MAX_LIST, "SOLVE_ROWS": _lib.SOLVE_ROWS}
+            "MAX_ROW": _lib.MAX_ROW, "MAX_LIST": _lib.MAX_LIST, "SOLVE_ROWS": _lib.SOLVE_ROWS,
+            "MAX_KEYPOINTS": _lib.MAX_KEYPOINTS}
     for k, v in want.items():
         assert defs[k] == v, k
 
