@@ -10,7 +10,7 @@ section and equation number as numbered in the LaTeX source order:
   Eq.(3) total energy (Sec. II-E)     Eqs.(4)-(5) rotation term
   Eq.(6) regularisation term          Eq.(7) visibility gates
   Eq.(8) point-to-plane data term     Eq.(9) key-point correspondence term
-  Sec. II-F optimisation (LM; here damped GN + PCG)
+  Sec. II-F optimisation (LM: damped GN + PCG, fixed or adaptive damping)
   Alg. 1/2 registration and fusion    Eqs.(12)-(15) fusion update (Sec. II-G)
   Alg. 2 steps 3-5, Alg. 3            growth, removal, down-sampling, node regeneration
 Where the paper is silent or garbled the reading taken is stated in the
@@ -34,3 +34,4 @@ from .fuse import fuse, fuse_warped, zbuffer  # noqa: F401
 from .mixed import round_bf16, round_fp16  # noqa: F401
 from .grow import grow, voxel_keys  # noqa: F401
 from .corr import corr_residuals, corr_jacobian_rows, corr_energy  # noqa: F401
+from .lm import LMSchedule, lm_iterate, lm_register, objective  # noqa: F401
