@@ -79,6 +79,7 @@ def parse():
     ap.add_argument("--seq-frames", type=int, default=8, help="frames of the sweeping sequence (0: skip)")
     ap.add_argument("--no-lowp", action="store_true")
     ap.add_argument("--no-keypoints", action="store_true")
+    ap.add_argument("--no-lm", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -147,23 +148,26 @@ def main():
     w0, stamp0 = w.clone(), stamp.clone()
     fp = M.fuse_params(frame=1)
 
-    def frame(p=params, keys=None):
+    def frame(p=params, keys=None, lm=None):
         pts.copy_(pts0)
         nodes.copy_(nodes0)
         w.copy_(w0)
         stamp.copy_(stamp0)
         x.copy_(x0)
         g = M.build_graph(pts, nodes, p, ws)
-        rep, _ = M.gn_register(pts, nodes, x, g, depth, cam, pose, p, ws, keys=keys)
+        if lm is None:
+            rep, _ = M.gn_register(pts, nodes, x, g, depth, cam, pose, p, ws, keys=keys)
+        else:
+            rep, _ = M.lm_register(pts, nodes, x, g, depth, cam, pose, p, ws, lm=lm, keys=keys)
         state["graph"], state["rep"], state["x"] = g, rep, x.clone()
         nmap = M.normal_map(depth, cam)
         M.fuse(pts, w, stamp, nodes, x, g, nmap, cam, pose, fp, ws)
 
-    def timed(p, steps, keys=None):
+    def timed(p, steps, keys=None, lm=None):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            frame(p, keys)
+            frame(p, keys, lm)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
@@ -216,6 +220,7 @@ def main():
     # oracle's algorithm on a rounded data term) and with two refinement passes
     lowp = None if args.no_lowp else lowp_bench(M, _lib, sc, frame, timed, state, G, args)
     kpb = None if args.no_keypoints else keypoint_bench(M, sc, frame, timed, state, params, G, args, torch)
+    lmb = None if args.no_lm else lm_bench(M, frame, timed, state, params, G, args)
 
     out = {
         "metric": "GN iters/s + ms/frame at 640x480, 1600 ED nodes, rel err vs FP64 oracle",
@@ -247,6 +252,8 @@ def main():
         out["low_precision"] = lowp
     if kpb is not None:
         out["keypoints"] = kpb
+    if lmb is not None:
+        out["adaptive_lm"] = lmb
     if not args.no_batch:
         out["batch"] = batch_bench(M, _lib, args)
     if args.seq_frames > 0:
@@ -405,6 +412,28 @@ def sequence_bench(M, frames):
     return {"workload": f"sweep over a breathing 250x200 mm sheet, 640x480, frames 1..{frames} after the lifted "
                         f"frame 0; graph + 10x10 registration + fusion + growth per frame",
             "ms_per_frame": round(1000 * dt, 3), "points_nodes_per_frame": sizes, "report_flags": flags}
+
+
+def lm_bench(M, frame, timed, state, params, G, args):
+    """The same frame with adaptive Levenberg-Marquardt damping (default schedule): each step also evaluates
+    the objective at its trial point.  Against the stored float64 oracle run of the same schedule."""
+    lm = M.LMParams()
+    for _ in range(max(1, args.warmup)):
+        frame(params, None, lm)
+    el = timed(params, args.steps, None, lm)
+    rep = M.read_report(state["rep"])
+    gold = os.path.join(ROOT, "tests", "golden", f"{args.config}_lm_oracle.npz")
+    acc = accuracy(state, rep, gold)
+    dec = "".join("A" if a else "r" for a in rep["lm_accepted"][:G])
+    out = {"workload": "the same frame, adaptive damping (lambda0 1e-3, x0.1 on a taken step, x10 on a rejected "
+                       "one, within [1e-6, 1e6])",
+           "ms_per_frame": round(1000.0 * el / args.steps, 4), "gn_iters_per_s": round(G * args.steps / el, 2),
+           "decisions": dec, "lambda": [float(v) for v in rep["lm_lambda"][:G]],
+           "accuracy_vs_fp64_oracle": acc}
+    if os.path.exists(gold):
+        z = np.load(gold)
+        out["oracle_decisions"] = "".join("A" if a else "r" for a in z["accepted"])
+    return out
 
 
 def accuracy(state, rep, gold):

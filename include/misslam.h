@@ -149,7 +149,25 @@ typedef struct {
     int32_t pcg_iters_done;
     int32_t reserved;
     double e_corr;                           /* unweighted Eq.(9) key-point energy (0 without key points) */
+    /* adaptive damping (misslam_lm_register; all 0 otherwise): the weighted objective at the step's
+     * linearisation point and at the trial point x + dx, the damping the step was solved with, and
+     * whether the trial point was taken */
+    double lm_e, lm_e_trial;
+    float lm_lambda;
+    int32_t lm_accepted;
 } misslam_report;
+
+/* (host) adaptive damping schedule of misslam_lm_register (Sec. II-F names Levenberg-Marquardt and no
+ * schedule; this is the classical one): a step solved with damping lambda is taken when it lowers the
+ * weighted Eq.(3) objective, and lambda then becomes max(lambda * down, lambda_min); otherwise the
+ * parameters stay and lambda becomes min(lambda * up, lambda_max). */
+typedef struct {
+    float lambda0;             /* damping of the first step: 1e-3 */
+    float up;                  /* 10 */
+    float down;                /* 0.1 */
+    float lambda_min;          /* 1e-6 */
+    float lambda_max;          /* 1e6 */
+} misslam_lm_params;
 
 /* (host) key-point matches of the Eq.(9) correspondence term, Sec. II-E: each key point is carried by one
  * model point (its k nodes and skinning weights) and matched to a 3-D position in the frame's camera
@@ -282,6 +300,30 @@ misslam_status misslam_gn_register_keypoints(const misslam_points *points, missl
                                              const misslam_params *params, const misslam_keypoints *keys,
                                              misslam_report *rep, int32_t *corr_hist, void *ws,
                                              size_t ws_bytes, void *stream);
+
+/* (host) fills *lm with the defaults above */
+void misslam_default_lm_params(misslam_lm_params *lm);
+
+/*
+ * Registration with adaptive Levenberg-Marquardt damping (Sec. II-F): step i
+ * linearises at x as misslam_gn_register does, solves (H + lambda_i I) dx = -g
+ * with the same block-Jacobi PCG, evaluates the weighted objective
+ * w_data E_data + w_rot E_rot + w_reg E_reg + w_corr E_corr at x + dx (the
+ * correspondences re-decided there), and keeps x + dx only when that is lower
+ * than at x; lambda follows *lm (params->lambda is not used).  keys may be
+ * NULL (no key-point term) or as for misslam_gn_register_keypoints.  rep
+ * (device) holds gn_iters + 1 entries as for misslam_gn_register, with the
+ * lm_* fields of the first gn_iters set.  Errors as misslam_gn_register;
+ * MISSLAM_EINVAL for lm NULL or a schedule outside 0 <= lambda_min <=
+ * lambda0 <= lambda_max (finite), 1 <= up (finite), 0 < down <= 1; float32
+ * form only (MISSLAM_EUNSUPPORTED otherwise).
+ */
+misslam_status misslam_lm_register(const misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
+                                   const float *depth, const misslam_camera *camera, const misslam_pose *pose,
+                                   const misslam_params *params, const misslam_keypoints *keys,
+                                   const misslam_lm_params *lm, misslam_report *rep, int32_t *corr_hist, void *ws,
+                                   size_t ws_bytes, void *stream);
+
 
 /*
  * Model update after registration (Sec. II-G, Alg. 1-2, Eqs.(12), (14), (15)).

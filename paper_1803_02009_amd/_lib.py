@@ -64,7 +64,13 @@ class Report(ctypes.Structure):
     _fields_ = [("e_data", ctypes.c_double), ("e_rot", ctypes.c_double), ("e_reg", ctypes.c_double),
                 ("pcg_resid", ctypes.c_double * (MAX_PCG + 1)), ("n_valid", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("pcg_iters_done", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("e_corr", ctypes.c_double)]
+                ("e_corr", ctypes.c_double), ("lm_e", ctypes.c_double), ("lm_e_trial", ctypes.c_double),
+                ("lm_lambda", ctypes.c_float), ("lm_accepted", ctypes.c_int32)]
+
+
+class LMParams(ctypes.Structure):
+    _fields_ = [("lambda0", ctypes.c_float), ("up", ctypes.c_float), ("down", ctypes.c_float),
+                ("lambda_min", ctypes.c_float), ("lambda_max", ctypes.c_float)]
 
 
 class Keypoints(ctypes.Structure):
@@ -108,6 +114,9 @@ SIGNATURES = {
                                  ctypes.c_size_t, vp]),
     "misslam_gn_register_keypoints": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params),
                                            P(Keypoints), vp, vp, vp, ctypes.c_size_t, vp]),
+    "misslam_default_lm_params": (None, [P(LMParams)]),
+    "misslam_lm_register": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params), P(Keypoints),
+                                 P(LMParams), vp, vp, vp, ctypes.c_size_t, vp]),
     "misslam_fuse": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(FuseParams), vp, vp, vp,
                           ctypes.c_size_t, vp]),
     "misslam_energy_vjp": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params), vp, vp, vp, vp,

@@ -14,11 +14,11 @@ namespace {
 
 enum Phase {
     PH_NORMAL_MAP, PH_GRAPH, PH_POINT_PASS, PH_ASSEMBLE, PH_ENERGY, PH_BJACOBI, PH_PCG, PH_FUSE, PH_REFINE, PH_GROW,
-    PH_LIST_PACK, PH_CORR, PH_COUNT
+    PH_LIST_PACK, PH_CORR, PH_LM, PH_COUNT
 };
 const char *const kPhaseNames[PH_COUNT] = {"normal_map", "build_graph", "point_pass", "assemble",  "energy",
                                            "bjacobi",    "pcg",         "fuse",       "refine",    "grow",
-                                           "list_pack",  "corr"};
+                                           "list_pack",  "corr",        "lm_trial"};
 
 struct Profiler {
     std::mutex mu;
@@ -110,6 +110,7 @@ struct Carver {
 struct Layout {
     msl::StepScratch step;
     msl::CorrScratch corr;
+    float *lm_lambda;   // the adaptive damping of the next step (one float)
     msl::PcgScratch pcg;
     msl::GraphScratch graph;
     float4 *nmap;
@@ -174,6 +175,7 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
     L.corr.kp_nodes = c.take<int32_t>((size_t)k * n);
     L.corr.kp_data = c.take<float>((size_t)(3 + 4 * k) * n);
     L.corr.kp_energy = c.take<double>((size_t)n);
+    L.lm_lambda = c.take<float>(4);
     L.bytes = align_up(c.off);
     return L;
 }
@@ -332,12 +334,12 @@ static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, i
 static hipError_t solve_persistent(const msl::GraphView &g, int m, const float *blocks, const float *gvec,
                                    const float *minv, float lambda, int iters, float *delta, const msl::PcgScratch &s,
                                    misslam_report *rep, float *params, hipStream_t st, bool coop,
-                                   int zeroed_words = 0) {
+                                   int zeroed_words = 0, const float *lambda_dev = nullptr) {
     bool used = false;
     hipError_t e = msl::launch_pcg_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st,
-                                              &used, coop, zeroed_words);
+                                              &used, coop, zeroed_words, lambda_dev);
     if (e == hipSuccess && !used)
-        e = msl::launch_pcg_update(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st);
+        e = msl::launch_pcg_update(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st, lambda_dev);
     return e;
 }
 
@@ -427,8 +429,9 @@ misslam_status misslam_pcg_solve(const misslam_graph *graph, int32_t m, const fl
 
 static misslam_status gn_register(const misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
                                   const float *depth, const misslam_camera *camera, const misslam_pose *pose,
-                                  const misslam_params *params, const misslam_keypoints *keys, misslam_report *rep,
-                                  int32_t *corr_hist, void *ws, size_t ws_bytes, void *stream) {
+                                  const misslam_params *params, const misslam_keypoints *keys,
+                                  const misslam_lm_params *lm, misslam_report *rep, int32_t *corr_hist, void *ws,
+                                  size_t ws_bytes, void *stream) {
     if (!valid_points(points) || !valid_nodes(nodes) || !valid_graph(graph, points->n) || !depth ||
         !valid_camera(camera) || !pose || !valid_params(params) || !rep || !ws)
         return MISSLAM_EINVAL;
@@ -438,6 +441,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
     if (graph->k != params->k) return MISSLAM_ESHAPE;
     if (params->precision != MISSLAM_PREC_FP32 && params->k > 4) return MISSLAM_EUNSUPPORTED;
     if (params->precision != MISSLAM_PREC_FP32 && keys && keys->count > 0) return MISSLAM_EUNSUPPORTED;
+    if (params->precision != MISSLAM_PREC_FP32 && lm) return MISSLAM_EUNSUPPORTED;
     msl::KeyArgs ka{};
     const msl::KeyArgs *kp = nullptr;
     if (keys && keys->count > 0) {
@@ -458,6 +462,8 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
     const int m = nodes->m;
     hipError_t e = msl::launch_report_init(rep, G + 1, st);
     if (e == hipSuccess && lowp) e = msl::launch_report_init(L.rep, 1, st);
+    if (e == hipSuccess && lm) e = msl::launch_lm_init(L.lm_lambda, lm->lambda0, st);
+    if (e == hipSuccess && lm) e = msl::launch_report_init(L.rep, 1, st);
     if (e == hipSuccess) {
         Timed t(PH_NORMAL_MAP, st);
         e = msl::launch_normal_map(depth, view(camera), L.nmap, st);
@@ -492,12 +498,33 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
             break;
         }
         if (!lowp) {
+            if (lm) a.lambda_dev = L.lm_lambda;
             e = linearize(a, L.step, n, m, rep + it, params->reject_threshold, st, L.pcg.bar, msl::msl_sync_words(m),
                           kp, &L.corr);
             if (e == hipSuccess) {
                 Timed t(PH_PCG, st);
                 e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
-                                     L.delta, L.pcg, rep + it, nodes->params, st, coop, msl::msl_sync_words(m));
+                                     L.delta, L.pcg, rep + it, lm ? nullptr : nodes->params, st, coop,
+                                     msl::msl_sync_words(m), lm ? L.lm_lambda : nullptr);
+            }
+            if (e == hipSuccess && lm) {
+                // the trial point x + dx: its objective decides whether the step is taken
+                Timed t(PH_LM, st);
+                float *xt = L.delta2;
+                const bool keys = kp && kp->count > 0;
+                e = msl::launch_lm_trial(nodes->params, L.delta, xt, 12 * m, st);
+                msl::StepArgs at = step_args(points, nodes, graph, L.nmap, camera, pose, params, L.blocks, L.gvec,
+                                             nullptr);
+                at.nd.x = xt;
+                if (e == hipSuccess)
+                    e = msl::launch_point_pass(at, L.step, st, keys ? kp : nullptr, keys ? &L.corr : nullptr);
+                if (e == hipSuccess) e = msl::launch_node_energy(at, L.step, st);
+                if (e == hipSuccess)
+                    e = msl::launch_energy_report(L.step, n, m, L.rep, 0.f, st, nullptr, 0,
+                                                  keys ? L.corr.kp_energy : nullptr, keys ? kp->count : 0);
+                if (e == hipSuccess)
+                    e = msl::launch_lm_decide(rep + it, L.rep, *lm, params->w_data, params->w_rot, params->w_reg,
+                                              keys ? kp->w_corr : 0.f, nodes->params, xt, 12 * m, L.lm_lambda, st);
             }
             continue;
         }
@@ -537,8 +564,8 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
                                    const float *depth, const misslam_camera *camera, const misslam_pose *pose,
                                    const misslam_params *params, misslam_report *rep, int32_t *corr_hist, void *ws,
                                    size_t ws_bytes, void *stream) {
-    return gn_register(points, nodes, graph, depth, camera, pose, params, nullptr, rep, corr_hist, ws, ws_bytes,
-                       stream);
+    return gn_register(points, nodes, graph, depth, camera, pose, params, nullptr, nullptr, rep, corr_hist, ws,
+                       ws_bytes, stream);
 }
 
 misslam_status misslam_gn_register_keypoints(const misslam_points *points, misslam_nodes *nodes,
@@ -548,7 +575,30 @@ misslam_status misslam_gn_register_keypoints(const misslam_points *points, missl
                                              misslam_report *rep, int32_t *corr_hist, void *ws, size_t ws_bytes,
                                              void *stream) {
     if (!keys) return MISSLAM_EINVAL;
-    return gn_register(points, nodes, graph, depth, camera, pose, params, keys, rep, corr_hist, ws, ws_bytes,
+    return gn_register(points, nodes, graph, depth, camera, pose, params, keys, nullptr, rep, corr_hist, ws,
+                       ws_bytes, stream);
+}
+
+void misslam_default_lm_params(misslam_lm_params *lm) {
+    if (!lm) return;
+    lm->lambda0 = 1e-3f;
+    lm->up = 10.f;
+    lm->down = 0.1f;
+    lm->lambda_min = 1e-6f;
+    lm->lambda_max = 1e6f;
+}
+
+misslam_status misslam_lm_register(const misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
+                                   const float *depth, const misslam_camera *camera, const misslam_pose *pose,
+                                   const misslam_params *params, const misslam_keypoints *keys,
+                                   const misslam_lm_params *lm, misslam_report *rep, int32_t *corr_hist, void *ws,
+                                   size_t ws_bytes, void *stream) {
+    if (!lm || !std::isfinite(lm->lambda0) || !std::isfinite(lm->up) || !std::isfinite(lm->down) ||
+        !std::isfinite(lm->lambda_min) || !std::isfinite(lm->lambda_max) || !(lm->lambda_min >= 0.f) ||
+        !(lm->lambda0 >= lm->lambda_min) || !(lm->lambda_max >= lm->lambda0) || !(lm->up >= 1.f) ||
+        !(lm->down > 0.f) || !(lm->down <= 1.f))
+        return MISSLAM_EINVAL;
+    return gn_register(points, nodes, graph, depth, camera, pose, params, keys, lm, rep, corr_hist, ws, ws_bytes,
                        stream);
 }
 

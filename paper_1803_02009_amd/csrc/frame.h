@@ -91,7 +91,10 @@ struct StepArgs {
     const int32_t *corr_in;  // optional frozen correspondences (no association, no gates)
     float *minv;       // optional m x 144 block-Jacobi inverses computed with the assembly
     int32_t *flags;    // report flags (NONSPD_BLOCK) when minv is set
+    const float *lambda_dev = nullptr;   // optional device damping, read in place of lambda
 };
+
+__device__ __forceinline__ float step_lambda(const StepArgs &a) { return a.lambda_dev ? *a.lambda_dev : a.lambda; }
 
 // Key-point matches of the Eq.(9) correspondence term (device arrays).
 struct KeyArgs {
@@ -143,6 +146,7 @@ struct PcgArgs {
     const int32_t *row_ptr, *col_idx;
     const float *blocks, *minv, *g;
     float lambda;
+    const float *lambda_dev = nullptr;   // optional device damping, read in place of lambda
     int m, nblk, iters, cap;
     float *x, *r, *z, *p, *q;
     double *part;     // [(it * 4 + kind) * nblk + block], kind 0 = r.z, 1 = r.r, 2 = p.q, 3 = #non-finite x
@@ -253,10 +257,19 @@ hipError_t launch_energy_report(const StepScratch &s, int64_t n, int m, misslam_
                                 const double *kp_energy = nullptr, int kp_count = 0);
 hipError_t launch_bjacobi(const GraphView &g, int m, const float *blocks, float lambda, float *minv,
                           int32_t *flags, hipStream_t st);
-// PCG solve into delta; when params != nullptr also applies params += delta (the GN update).
+// PCG solve into delta; when params != nullptr also applies params += delta (the GN update).  lambda_dev
+// (optional): device damping read in place of lambda.
 hipError_t launch_pcg_update(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                              float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
-                             float *params, hipStream_t st);
+                             float *params, hipStream_t st, const float *lambda_dev = nullptr);
+// Adaptive damping (Sec. II-F): lambda slot := lambda0; x_trial = x + dx; then the decision on the
+// trial point (objectives from rep_x and rep_t, weights w[4] = data, rot, reg, corr): x := x_trial when
+// lower, the lambda slot updated, rep_x's lm_* fields written.
+hipError_t launch_lm_init(float *lambda_slot, float lambda0, hipStream_t st);
+hipError_t launch_lm_trial(const float *x, const float *dx, float *x_trial, int n, hipStream_t st);
+hipError_t launch_lm_decide(misslam_report *rep_x, const misslam_report *rep_t, const misslam_lm_params &lm,
+                            float w_data, float w_rot, float w_reg, float w_corr, float *x, const float *x_trial,
+                            int n, float *lambda_slot, hipStream_t st);
 hipError_t launch_report_init(misslam_report *rep, int count, hipStream_t st);
 // Same solve as launch_pcg_update in one launch whose workgroups must all be
 // resident (cooperative: guaranteed by the runtime; plain: no other work may
@@ -265,7 +278,7 @@ hipError_t launch_report_init(misslam_report *rep, int count, hipStream_t st);
 hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                                  float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
                                  float *params, hipStream_t st, bool *used, bool cooperative,
-                                 int zeroed_words = 0);
+                                 int zeroed_words = 0, const float *lambda_dev = nullptr);
 int pcg_blocks(int m);
 // Batched launches: one grid covers every problem of items[0..count).
 hipError_t launch_normal_map_batched(const BatchItem *items, int count, int total_blocks, hipStream_t st);

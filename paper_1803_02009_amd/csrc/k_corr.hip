@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(kCorrThreads) corr_rows_kernel(StepArgs a, Key
             }
             if (inv && off[e] / 144 == dslot) {
                 const int en = off[e] % 144;
-                Hd[en / 12][en % 12] = (double)h[e] + (en / 12 == en % 12 ? (double)a.lambda : 0.0);
+                Hd[en / 12][en % 12] = (double)h[e] + (en / 12 == en % 12 ? (double)step_lambda(a) : 0.0);
             }
         }
     }

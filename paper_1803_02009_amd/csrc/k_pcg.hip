@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(kPcgThreads) pcg_dir_kernel(PcgArgs A, int it)
         }
         const size_t o = (size_t)j * 12 + a;
         const float zj = A.z[o];
-        az = fma((double)A.lambda, (double)zj, az);
+        az = fma((double)(A.lambda_dev ? *A.lambda_dev : A.lambda), (double)zj, az);
         float p, q;
         if (it > 0) {
             p = fmaf(beta, A.p[o], zj);
@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(kPcgThreads) pcg_finish_kernel(PcgArgs A, miss
 
 hipError_t launch_pcg_update(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                              float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
-                             float *params, hipStream_t st) {
+                             float *params, hipStream_t st, const float *lambda_dev) {
     PcgArgs A;
     A.row_ptr = g.row_ptr;
     A.col_idx = g.col_idx;
@@ -236,6 +236,7 @@ hipError_t launch_pcg_update(const GraphView &g, int m, const float *blocks, con
     A.minv = minv;
     A.g = gvec;
     A.lambda = lambda;
+    A.lambda_dev = lambda_dev;
     A.m = m;
     A.nblk = s.nblk;
     A.iters = iters;
@@ -271,6 +272,10 @@ __global__ void report_init_batched_kernel(const BatchItem *__restrict__ items, 
         rep[t].pcg_iters_done = 0;
         rep[t].reserved = 0;
         rep[t].e_corr = 0.0;
+        rep[t].lm_e = 0.0;
+        rep[t].lm_e_trial = 0.0;
+        rep[t].lm_lambda = 0.f;
+        rep[t].lm_accepted = 0;
     }
 }
 
@@ -292,6 +297,10 @@ __global__ void report_init_kernel(misslam_report *rep, int count) {
         rep[t].pcg_iters_done = 0;
         rep[t].reserved = 0;
         rep[t].e_corr = 0.0;
+        rep[t].lm_e = 0.0;
+        rep[t].lm_e_trial = 0.0;
+        rep[t].lm_lambda = 0.f;
+        rep[t].lm_accepted = 0;
     }
 }
 
@@ -442,6 +451,7 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
     __shared__ int cnt_u, cmin_s, cmax_s;
     __shared__ int lslot[kRowsPerBlk];                 // staged slot of each of this workgroup's own columns
     float *zc = reinterpret_cast<float *>(zc4);
+    const double lam = (double)(A.lambda_dev ? *A.lambda_dev : A.lambda);
     const int r0 = min(A.m, wg * rows_per_wg);
     const int r1 = min(A.m, r0 + rows_per_wg);
     const int b0 = min(A.row_ptr[r0], A.cap), b1 = min(A.row_ptr[r1], A.cap);
@@ -717,7 +727,7 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
                     for (int b = 0; b < 12; ++b) az = fma((double)B[b], (double)ld_dev(zl + b), az);
                 }
             }
-            az = fma((double)A.lambda, (double)z, az);
+            az = fma(lam, (double)z, az);
             const float pv = it > 0 ? fmaf(beta, vp[li], z) : z;
             const float qv = it > 0 ? (float)fma((double)beta, (double)vq[li], az) : (float)az;
             vp[li] = pv;
@@ -840,7 +850,8 @@ static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes) {
 
 hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                                  float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
-                                 float *params, hipStream_t st, bool *used, bool cooperative, int zeroed_words) {
+                                 float *params, hipStream_t st, bool *used, bool cooperative, int zeroed_words,
+                                 const float *lambda_dev) {
     *used = false;
     int rows = 0, lds = 0;
     const int G = persistent_grid(m, rows, lds);
@@ -852,6 +863,7 @@ hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks,
     A.minv = minv;
     A.g = gvec;
     A.lambda = lambda;
+    A.lambda_dev = lambda_dev;
     A.m = m;
     A.nblk = G;
     A.iters = iters;

@@ -247,7 +247,8 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
         }
         rn.EE[tid] = sacc;
     }
-    for (int t = tid; t < 144; t += NT) rn.Hd[t / 12][t % 12] = t / 12 == t % 12 ? (double)a.lambda : 0.0;
+    const double lam = (double)step_lambda(a);
+    for (int t = tid; t < 144; t += NT) rn.Hd[t / 12][t % 12] = t / 12 == t % 12 ? lam : 0.0;
     __syncthreads();
     if (tid == 0) {
         double erot = 0.0;
@@ -298,7 +299,7 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
             }
             const float rr = fmaf(wrot, rot, wreg * reg);
             const float h = fmaf(wrot, rot, fmaf(wreg, reg, wd * hd));
-            rn.Hd[R][C] = (double)h + (R == C ? (double)a.lambda : 0.0);
+            rn.Hd[R][C] = (double)h + (R == C ? lam : 0.0);
             outb[(size_t)dsl * 144 + en] = h;
             if (rr_out) rr_out[(size_t)(rb + dsl) * 144 + en] = rr;
         }

@@ -139,7 +139,8 @@ class Graph:
 
 REPORT_DTYPE = np.dtype([("e_data", "<f8"), ("e_rot", "<f8"), ("e_reg", "<f8"),
                          ("pcg_resid", "<f8", (_lib.MAX_PCG + 1,)), ("n_valid", "<i4"), ("flags", "<i4"),
-                         ("pcg_iters_done", "<i4"), ("reserved", "<i4"), ("e_corr", "<f8")])
+                         ("pcg_iters_done", "<i4"), ("reserved", "<i4"), ("e_corr", "<f8"), ("lm_e", "<f8"),
+                         ("lm_e_trial", "<f8"), ("lm_lambda", "<f4"), ("lm_accepted", "<i4")])
 assert REPORT_DTYPE.itemsize == ctypes.sizeof(_lib.Report)
 
 
@@ -244,6 +245,37 @@ def gn_register(points, nodes, x, graph, depth, cam, pose_, params, ws, corr_his
     else:
         kc = keys.c()
         check("misslam_gn_register_keypoints", load().misslam_gn_register_keypoints(*common, ctypes.byref(kc), *tail))
+    return rep, ch
+
+
+@dataclasses.dataclass
+class LMParams:
+    """Adaptive damping schedule (Sec. II-F): classical Levenberg-Marquardt factors."""
+    lambda0: float = 1e-3
+    up: float = 10.0
+    down: float = 0.1
+    lambda_min: float = 1e-6
+    lambda_max: float = 1e6
+
+    def c(self):
+        return _lib.LMParams(self.lambda0, self.up, self.down, self.lambda_min, self.lambda_max)
+
+
+def lm_register(points, nodes, x, graph, depth, cam, pose_, params, ws, lm=None, keys=None, corr_hist=False):
+    """Registration with adaptive Levenberg-Marquardt damping, updating x in place; returns (report, corr_hist
+    or None).  The report's lm_* fields hold each step's objective at x and at x + dx, its damping and whether
+    the step was taken."""
+    n, m = points.shape[1], nodes.shape[1]
+    rep = new_report(params.gn_iters + 1)
+    ch = torch.empty((params.gn_iters, n), dtype=torch.int32, device=points.device) if corr_hist else None
+    buf = ws.get(workspace_bytes(n, m, cam.width, cam.height, params))
+    kc = keys.c() if keys is not None else None
+    lc = (lm or LMParams()).c()
+    check("misslam_lm_register", load().misslam_lm_register(
+        ctypes.byref(points_struct(points)), ctypes.byref(nodes_struct(nodes, x)), ctypes.byref(graph.c()),
+        _ptr(depth), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(params.c()),
+        ctypes.byref(kc) if kc is not None else None, ctypes.byref(lc), _ptr(rep), _ptr(ch), _ptr(buf),
+        ctypes.c_size_t(buf.numel()), _stream()))
     return rep, ch
 
 

@@ -6,10 +6,12 @@ A plain name runs the float64 oracle; name:prec:R runs its emulation of the
 low-precision form (data-term Jacobian rows rounded to bf16 / fp16 before
 J^T J, R refinement passes of each step against the unrounded system);
 name:kp:S adds S generated key points (gen.keypoints, seed 7, 0.05 mm noise)
-with the Eq.(9) term at w_corr = 10.
-Output: tests/golden/<name>[_<prec>_r<R> | _kp<S>]_oracle.npz with x (m, 12)
-after the frame's Gauss-Newton iterations (independent decisions), the final
-energies and the per-iteration data energies.
+with the Eq.(9) term at w_corr = 10; name:lm runs the adaptive
+Levenberg-Marquardt schedule (default factors) instead of the fixed damping.
+Output: tests/golden/<name>[_<prec>_r<R> | _kp<S> | _lm]_oracle.npz with x
+(m, 12) after the frame's iterations (independent decisions), the final
+energies and the per-iteration data energies (and, for lm, the per-step
+decisions and dampings).
 """
 import os
 import sys
@@ -33,6 +35,9 @@ def main(spec):
     if len(parts) == 1:
         x, rep = oracle.gn_register(pb)
         out = f"{name}_oracle.npz"
+    elif parts[1] == "lm":
+        x, rep = oracle.lm_register(pb, oracle.LMSchedule())
+        out = f"{name}_lm_oracle.npz"
     elif parts[1] == "kp":
         S = int(parts[2])
         kp, tgt = gen.keypoints(sc, S, seed=7, noise=0.05)
@@ -45,10 +50,15 @@ def main(spec):
         x, rep = oracle.gn_register(pb, jac_round=lambda J: rnd(J.astype(np.float32)), refine_steps=steps)
         out = f"{name}_{prec}_r{steps}_oracle.npz"
     it = rep["iters"]
+    extra = {}
+    if "accepted" in it[0]:
+        extra = dict(accepted=np.array([e["accepted"] for e in it]), lam=np.array([e["lambda"] for e in it]),
+                     E=np.array([e["E"] for e in it]), E_trial=np.array([e["E_trial"] for e in it]))
     np.savez_compressed(os.path.join(HERE, out), x=x, e_data_final=rep["final"]["e_data"],
                         e_rot_final=rep["final"]["e_rot"], e_reg_final=rep["final"]["e_reg"],
                         n_valid_final=rep["final"]["n_valid"], e_corr_final=rep["final"]["e_corr"],
-                        e_data=np.array([e["e_data"] for e in it]), n_valid=np.array([e["n_valid"] for e in it]))
+                        e_data=np.array([e["e_data"] for e in it]), n_valid=np.array([e["n_valid"] for e in it]),
+                        **extra)
     print(out, "final e_data", rep["final"]["e_data"], "n_valid", rep["final"]["n_valid"])
 
 

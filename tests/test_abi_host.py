@@ -42,11 +42,13 @@ def test_struct_layout_matches_header():
 #include <stddef.h>
 #include "misslam.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(misslam_camera), sizeof(misslam_pose),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(misslam_camera), sizeof(misslam_pose),
          sizeof(misslam_points), sizeof(misslam_nodes), sizeof(misslam_graph), sizeof(misslam_params),
-         sizeof(misslam_report), sizeof(misslam_fuse_params), sizeof(misslam_problem), sizeof(misslam_keypoints));
-  printf("%zu %zu %zu %zu %zu\n", offsetof(misslam_params, eps_d), offsetof(misslam_params, lambda),
-         offsetof(misslam_report, n_valid), offsetof(misslam_graph, info), offsetof(misslam_params, solve_launch));
+         sizeof(misslam_report), sizeof(misslam_fuse_params), sizeof(misslam_problem), sizeof(misslam_keypoints),
+         sizeof(misslam_lm_params));
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(misslam_params, eps_d), offsetof(misslam_params, lambda),
+         offsetof(misslam_report, n_valid), offsetof(misslam_graph, info), offsetof(misslam_params, solve_launch),
+         offsetof(misslam_report, lm_e), offsetof(misslam_report, lm_accepted));
   return 0;
 }
 """
@@ -58,11 +60,12 @@ int main(void) {
         out = subprocess.check_output([exe]).decode().split("\n")
     sizes = [int(v) for v in out[0].split()]
     want = [ctypes.sizeof(t) for t in (_lib.Camera, _lib.Pose, _lib.Points, _lib.Nodes, _lib.Graph, _lib.Params,
-                                       _lib.Report, _lib.FuseParams, _lib.Problem, _lib.Keypoints)]
+                                       _lib.Report, _lib.FuseParams, _lib.Problem, _lib.Keypoints, _lib.LMParams)]
     assert sizes == want
     offs = [int(v) for v in out[1].split()]
     assert offs == [_lib.Params.eps_d.offset, _lib.Params.lambda_.offset, _lib.Report.n_valid.offset,
-                    _lib.Graph.info.offset, _lib.Params.solve_launch.offset]
+                    _lib.Graph.info.offset, _lib.Params.solve_launch.offset, _lib.Report.lm_e.offset,
+                    _lib.Report.lm_accepted.offset]
 
 
 def test_header_constants_match_binding():
@@ -157,6 +160,23 @@ def test_validation_errors(lib):
     plp.precision = _lib.PREC_BF16
     ok_keys = _lib.Keypoints(3, 10.0, FAKE, FAKE)
     assert kpr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(plp), B(ok_keys), FAKE, None, FAKE, 1 << 40,
+               None) == _lib.EUNSUPPORTED
+    # adaptive damping: a schedule is required and must be ordered, finite, up >= 1, 0 < down <= 1;
+    # float32 form only
+    lmr = lib.misslam_lm_register
+    good = _lib.LMParams()
+    lib.misslam_default_lm_params(B(good))
+    assert (good.lambda0, good.up, good.down, good.lambda_min, good.lambda_max) == pytest.approx(
+        (1e-3, 10.0, 0.1, 1e-6, 1e6), rel=1e-6)
+    assert lmr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(p), None, None, FAKE, None, FAKE, 1 << 40,
+               None) == _lib.EINVAL
+    for bad in (_lib.LMParams(1e-3, 0.5, 0.1, 1e-6, 1e6), _lib.LMParams(1e-3, 10.0, 0.0, 1e-6, 1e6),
+                _lib.LMParams(1e-3, 10.0, 1.5, 1e-6, 1e6), _lib.LMParams(1e-7, 10.0, 0.1, 1e-6, 1e6),
+                _lib.LMParams(10.0, 10.0, 0.1, 1e-6, 1.0), _lib.LMParams(1e-3, 10.0, 0.1, -1.0, 1e6),
+                _lib.LMParams(float("nan"), 10.0, 0.1, 1e-6, 1e6), _lib.LMParams(1e-3, float("inf"), 0.1, 1e-6, 1e6)):
+        assert lmr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(p), None, B(bad), FAKE, None, FAKE, 1 << 40,
+                   None) == _lib.EINVAL
+    assert lmr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(plp), None, B(good), FAKE, None, FAKE, 1 << 40,
                None) == _lib.EUNSUPPORTED
     # n above capacity, bad camera, bad k
     over = _lib.Points(200, 100, *([FAKE] * 6), 0, 0)
