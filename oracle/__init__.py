@@ -9,7 +9,7 @@ section and equation number as numbered in the LaTeX source order:
   Eq.(1) ED warp (Sec. II-D)          Eq.(2) skinning weight (Sec. II-D)
   Eq.(3) total energy (Sec. II-E)     Eqs.(4)-(5) rotation term
   Eq.(6) regularisation term          Eq.(7) visibility gates
-  Eq.(8) point-to-plane data term     Eq.(9) key-point correspondence term
+  Eq.(8) point-to-plane data term     Eq.(9) key-point correspondence term  Eq.(10) global pose terms (joint pose + ED)
   Sec. II-F optimisation (LM: damped GN + PCG, fixed or adaptive damping)
   Alg. 1/2 registration and fusion    Eqs.(12)-(15) fusion update (Sec. II-G)
   Alg. 2 steps 3-5, Alg. 3            growth, removal, down-sampling, node regeneration
@@ -35,3 +35,4 @@ from .mixed import round_bf16, round_fp16  # noqa: F401
 from .grow import grow, voxel_keys  # noqa: F401
 from .corr import corr_residuals, corr_jacobian_rows, corr_energy  # noqa: F401
 from .lm import LMSchedule, lm_iterate, lm_register, objective  # noqa: F401
+from .pose import joint_register, joint_linearize, joint_pcg, so3_exp, so3_log  # noqa: F401
