@@ -155,7 +155,16 @@ typedef struct {
     double lm_e, lm_e_trial;
     float lm_lambda;
     int32_t lm_accepted;
+    /* joint pose (misslam_joint_register; 0 otherwise): unweighted Eq.(10) energies E_r = |log(R R0^T)|^2
+     * and E_p = |C - C0|^2 at the step's pose, C = -R^T T the camera centre */
+    double e_pose_r, e_pose_p;
 } misslam_report;
+
+/* (host) weights of the Eq.(10) global-pose terms, Sec. III-B: w_r = 1e6, w_p = 1e3 */
+typedef struct {
+    float w_r;
+    float w_p;
+} misslam_pose_weights;
 
 /* (host) adaptive damping schedule of misslam_lm_register (Sec. II-F names Levenberg-Marquardt and no
  * schedule; this is the classical one): a step solved with damping lambda is taken when it lowers the
@@ -303,6 +312,31 @@ misslam_status misslam_gn_register_keypoints(const misslam_points *points, missl
 
 /* (host) fills *lm with the defaults above */
 void misslam_default_lm_params(misslam_lm_params *lm);
+
+/*
+ * Joint registration of the rigid pose and the ED graph (Eq.(3) with the
+ * Eq.(10) pose terms; Sec. II-F: six more unknowns).  The pose *pose (the
+ * front end's estimate) is the start and the prior: E_r = |log(R R0^T)|^2,
+ * E_p = |C - C0|^2 with C = -R^T T the camera centre, weighted by *pw.  Each
+ * Gauss-Newton step perturbs the pose by a rigid motion in camera coordinates
+ * (R <- exp([dw]x) R, T <- exp([dw]x) T + dt), so the data rows gain pose
+ * columns (v~ x N, N); the bordered system [[H, B], [B^T, H_pp]] is solved by
+ * block-Jacobi PCG over the joint vector (params->pcg_iters iterations, the
+ * damping params->lambda on the whole diagonal, the damped 6x6 pose block in
+ * the preconditioner), then x += dx and the pose takes its step.
+ * pose_out (device, 12 floats: R row-major, then T) receives the refined
+ * pose; it is also the working pose during the call.  rep as for
+ * misslam_gn_register, with e_pose_r / e_pose_p set.  Errors as
+ * misslam_gn_register; MISSLAM_EINVAL for pw or pose_out NULL or a weight
+ * that is negative or not finite; float32 form only (MISSLAM_EUNSUPPORTED
+ * otherwise).
+ */
+misslam_status misslam_joint_register(const misslam_points *points, misslam_nodes *nodes,
+                                      const misslam_graph *graph, const float *depth,
+                                      const misslam_camera *camera, const misslam_pose *pose,
+                                      const misslam_pose_weights *pw, const misslam_params *params,
+                                      float *pose_out, misslam_report *rep, int32_t *corr_hist, void *ws,
+                                      size_t ws_bytes, void *stream);
 
 /*
  * Registration with adaptive Levenberg-Marquardt damping (Sec. II-F): step i

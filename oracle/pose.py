@@ -112,14 +112,14 @@ def pose_border(pb, graph, x, R, asc, vc, kp_vc=None):
     nprime = np.asarray(asc["Np"], dtype=np.float64) @ R      # rows (R^T N)^T
     r = np.asarray(asc["r"], dtype=np.float64)
     wd = pb.w_data
-    for i in np.nonzero(ok)[0]:
-        Hpp += wd * np.outer(Jp[i], Jp[i])
-        gp += wd * Jp[i] * r[i]
-        for s in range(k):
-            j = idx[i, s]
-            dh = np.append(P[i] - G[j], 1.0)
-            Je = w[i, s] * np.kron(dh, nprime[i])               # index 3c + a
-            B[j] += wd * np.outer(Je, Jp[i])
+    iv = np.nonzero(ok)[0]
+    Hpp += wd * Jp[iv].T @ Jp[iv]
+    gp += wd * Jp[iv].T @ r[iv]
+    for s in range(k):
+        j = idx[iv, s]
+        dh = np.concatenate([P[iv] - G[j], np.ones((len(iv), 1))], axis=1)
+        Je = w[iv, s][:, None] * (dh[:, :, None] * nprime[iv][:, None, :]).reshape(len(iv), 12)   # index 3c + a
+        np.add.at(B, j, wd * Je[:, :, None] * Jp[iv][:, None, :])
     if pb.kp_point is not None and len(pb.kp_point):
         r3 = asc["kp_r"]
         J3 = corr_pose_rows(kp_vc)

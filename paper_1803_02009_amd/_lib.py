@@ -65,7 +65,12 @@ class Report(ctypes.Structure):
                 ("pcg_resid", ctypes.c_double * (MAX_PCG + 1)), ("n_valid", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("pcg_iters_done", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("e_corr", ctypes.c_double), ("lm_e", ctypes.c_double), ("lm_e_trial", ctypes.c_double),
-                ("lm_lambda", ctypes.c_float), ("lm_accepted", ctypes.c_int32)]
+                ("lm_lambda", ctypes.c_float), ("lm_accepted", ctypes.c_int32), ("e_pose_r", ctypes.c_double),
+                ("e_pose_p", ctypes.c_double)]
+
+
+class PoseWeights(ctypes.Structure):
+    _fields_ = [("w_r", ctypes.c_float), ("w_p", ctypes.c_float)]
 
 
 class LMParams(ctypes.Structure):
@@ -115,6 +120,8 @@ SIGNATURES = {
     "misslam_gn_register_keypoints": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params),
                                            P(Keypoints), vp, vp, vp, ctypes.c_size_t, vp]),
     "misslam_default_lm_params": (None, [P(LMParams)]),
+    "misslam_joint_register": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(PoseWeights), P(Params),
+                                    vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "misslam_lm_register": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params), P(Keypoints),
                                  P(LMParams), vp, vp, vp, ctypes.c_size_t, vp]),
     "misslam_fuse": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(FuseParams), vp, vp, vp,

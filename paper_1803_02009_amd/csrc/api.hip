@@ -14,11 +14,11 @@ namespace {
 
 enum Phase {
     PH_NORMAL_MAP, PH_GRAPH, PH_POINT_PASS, PH_ASSEMBLE, PH_ENERGY, PH_BJACOBI, PH_PCG, PH_FUSE, PH_REFINE, PH_GROW,
-    PH_LIST_PACK, PH_CORR, PH_LM, PH_COUNT
+    PH_LIST_PACK, PH_CORR, PH_LM, PH_POSE, PH_COUNT
 };
 const char *const kPhaseNames[PH_COUNT] = {"normal_map", "build_graph", "point_pass", "assemble",  "energy",
                                            "bjacobi",    "pcg",         "fuse",       "refine",    "grow",
-                                           "list_pack",  "corr",        "lm_trial"};
+                                           "list_pack",  "corr",        "lm_trial",  "pose_border"};
 
 struct Profiler {
     std::mutex mu;
@@ -111,6 +111,7 @@ struct Layout {
     msl::StepScratch step;
     msl::CorrScratch corr;
     float *lm_lambda;   // the adaptive damping of the next step (one float)
+    msl::JointScratch joint;
     msl::PcgScratch pcg;
     msl::GraphScratch graph;
     float4 *nmap;
@@ -176,6 +177,13 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
     L.corr.kp_data = c.take<float>((size_t)(3 + 4 * k) * n);
     L.corr.kp_energy = c.take<double>((size_t)n);
     L.lm_lambda = c.take<float>(4);
+    // joint pose form
+    L.step.jp = c.take<float4>((size_t)2 * n);
+    L.step.pose_part = c.take<double>((size_t)msl::kPosePart * msl::point_blocks(n));
+    L.joint.B = c.take<float>((size_t)72 * m);
+    L.joint.sys = c.take<double>(80);
+    L.joint.jpart = c.take<double>((size_t)(pcg_iters + 2) * 10 * ((m + 20) / 21));
+    L.joint.pst = c.take<double>((size_t)(pcg_iters + 2) * 32);
     L.bytes = align_up(c.off);
     return L;
 }
@@ -431,7 +439,8 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
                                   const float *depth, const misslam_camera *camera, const misslam_pose *pose,
                                   const misslam_params *params, const misslam_keypoints *keys,
                                   const misslam_lm_params *lm, misslam_report *rep, int32_t *corr_hist, void *ws,
-                                  size_t ws_bytes, void *stream) {
+                                  size_t ws_bytes, void *stream, const misslam_pose_weights *pw = nullptr,
+                                  float *pose_out = nullptr) {
     if (!valid_points(points) || !valid_nodes(nodes) || !valid_graph(graph, points->n) || !depth ||
         !valid_camera(camera) || !pose || !valid_params(params) || !rep || !ws)
         return MISSLAM_EINVAL;
@@ -442,6 +451,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
     if (params->precision != MISSLAM_PREC_FP32 && params->k > 4) return MISSLAM_EUNSUPPORTED;
     if (params->precision != MISSLAM_PREC_FP32 && keys && keys->count > 0) return MISSLAM_EUNSUPPORTED;
     if (params->precision != MISSLAM_PREC_FP32 && lm) return MISSLAM_EUNSUPPORTED;
+    if (pw && (params->precision != MISSLAM_PREC_FP32 || lm || (keys && keys->count > 0))) return MISSLAM_EUNSUPPORTED;
     msl::KeyArgs ka{};
     const msl::KeyArgs *kp = nullptr;
     if (keys && keys->count > 0) {
@@ -464,6 +474,15 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
     if (e == hipSuccess && lowp) e = msl::launch_report_init(L.rep, 1, st);
     if (e == hipSuccess && lm) e = msl::launch_lm_init(L.lm_lambda, lm->lambda0, st);
     if (e == hipSuccess && lm) e = msl::launch_report_init(L.rep, 1, st);
+    msl::PosePrior prior{};
+    if (pw) {
+        for (int t = 0; t < 9; ++t) prior.R0[t] = pose->R[t];
+        for (int t = 0; t < 3; ++t) prior.T0[t] = pose->T[t];
+        prior.w_r = pw->w_r;
+        prior.w_p = pw->w_p;
+        prior.w_data = params->w_data;
+        if (e == hipSuccess) e = msl::launch_pose_init(view(pose), pose_out, st);
+    }
     if (e == hipSuccess) {
         Timed t(PH_NORMAL_MAP, st);
         e = msl::launch_normal_map(depth, view(camera), L.nmap, st);
@@ -484,6 +503,40 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
         if (it < G) {
             a.minv = L.step.minv;     // block-Jacobi inverses come out of the assembly
             a.flags = &rep[it].flags;
+        }
+        if (pw) {   // joint pose + ED: the pose lives on the device
+            a.pose_dev = pose_out;
+            {
+                Timed t(PH_POINT_PASS, st);
+                e = msl::launch_point_pass_joint(a, L.step, st);
+            }
+            if (it == G) {
+                if (e == hipSuccess) e = msl::launch_node_energy(a, L.step, st);
+                if (e == hipSuccess) e = msl::launch_energy_report(L.step, n, m, rep + it, params->reject_threshold, st);
+                if (e == hipSuccess)
+                    e = msl::launch_pose_setup(pose_out, prior, L.step.pose_part, msl::point_blocks(n), params->lambda,
+                                               nullptr, rep + it, st);
+                break;
+            }
+            if (e == hipSuccess) {
+                Timed t(PH_ASSEMBLE, st);
+                e = msl::launch_assemble(a, L.step, st);
+            }
+            if (e == hipSuccess) {
+                Timed t(PH_POSE, st);
+                e = msl::launch_border_rows(a, L.step, L.joint.B, st);
+            }
+            if (e == hipSuccess) e = msl::launch_energy_report(L.step, n, m, rep + it, params->reject_threshold, st);
+            if (e == hipSuccess)
+                e = msl::launch_pose_setup(pose_out, prior, L.step.pose_part, msl::point_blocks(n), params->lambda,
+                                           L.joint.sys, rep + it, st);
+            if (e == hipSuccess) {
+                Timed t(PH_PCG, st);
+                e = msl::launch_joint_pcg(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda,
+                                          params->pcg_iters, L.delta, L.pcg, L.joint, rep + it, nodes->params,
+                                          pose_out, st);
+            }
+            continue;
         }
         if (it == G) {   // final entry: energies at the returned parameters, no system needed
             const bool keys = kp && kp->count > 0;
@@ -586,6 +639,19 @@ void misslam_default_lm_params(misslam_lm_params *lm) {
     lm->down = 0.1f;
     lm->lambda_min = 1e-6f;
     lm->lambda_max = 1e6f;
+}
+
+misslam_status misslam_joint_register(const misslam_points *points, misslam_nodes *nodes,
+                                      const misslam_graph *graph, const float *depth,
+                                      const misslam_camera *camera, const misslam_pose *pose,
+                                      const misslam_pose_weights *pw, const misslam_params *params,
+                                      float *pose_out, misslam_report *rep, int32_t *corr_hist, void *ws,
+                                      size_t ws_bytes, void *stream) {
+    if (!pw || !pose_out || !pose || !std::isfinite(pw->w_r) || !std::isfinite(pw->w_p) || !(pw->w_r >= 0.f) ||
+        !(pw->w_p >= 0.f))
+        return MISSLAM_EINVAL;
+    return gn_register(points, nodes, graph, depth, camera, pose, params, nullptr, nullptr, rep, corr_hist, ws,
+                       ws_bytes, stream, pw, pose_out);
 }
 
 misslam_status misslam_lm_register(const misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,

@@ -52,7 +52,12 @@ struct StepScratch {
     // per list entry of node j (point p), packed once per registration for the assembly:
     float4 *lpa;          // k n: (v_p - g_j, w_pj)
     float4 *lpw;          // k n x ceil(k/4): w_pj w_pq over the entry's nodes q in index order, zero-padded
+    // joint pose form only:
+    float4 *jp;           // 2 n: pose columns of the point's data row (v~ x N, N), 0 when unmatched
+    double *pose_part;    // 27 per point block: upper triangle of sum Jp Jp^T (21), sum Jp r (6)
 };
+
+constexpr int kPosePart = 27;
 
 // Key-point term scratch (at most n key points).
 struct CorrScratch {
@@ -92,7 +97,18 @@ struct StepArgs {
     float *minv;       // optional m x 144 block-Jacobi inverses computed with the assembly
     int32_t *flags;    // report flags (NONSPD_BLOCK) when minv is set
     const float *lambda_dev = nullptr;   // optional device damping, read in place of lambda
+    const float *pose_dev = nullptr;     // optional device pose (R row-major, T), read in place of pose
 };
+
+__device__ __forceinline__ Pose step_pose(const StepArgs &a) {
+    if (!a.pose_dev) return a.pose;
+    Pose P;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) P.R[t] = a.pose_dev[t];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) P.T[t] = a.pose_dev[9 + t];
+    return P;
+}
 
 __device__ __forceinline__ float step_lambda(const StepArgs &a) { return a.lambda_dev ? *a.lambda_dev : a.lambda; }
 
@@ -228,6 +244,30 @@ hipError_t launch_fuse(const FuseArgs &f, float *gx, float *gy, float *gz, float
 // With key points (kp, c), the same launch also evaluates them (kp_eval_body) in blocks of its own.
 hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_t st, const KeyArgs *kp = nullptr,
                              const CorrScratch *c = nullptr);
+// Joint pose form: the point pass with the pose read from a.pose_dev, also writing s.jp and s.pose_part.
+hipError_t launch_point_pass_joint(const StepArgs &a, const StepScratch &s, hipStream_t st);
+int point_blocks(int64_t n);
+
+// Joint pose + ED (Eq.(10)).
+struct JointScratch {
+    float *B;             // 72 m: the border, row 3c + a of node j, column k at B[j * 72 + (3c + a) * 6 + k]
+    double *sys;          // 36 H_pp, 6 g_p, 36 (H_pp + lambda I)^-1
+    double *jpart;        // (pcg_iters + 2) x 10 x nblk partial sums
+    double *pst;          // (pcg_iters + 2) x 32: pose r, z, p, q, x per iteration
+};
+struct PosePrior {
+    float R0[9], T0[3];
+    float w_r, w_p, w_data;
+};
+hipError_t launch_pose_init(const Pose &pose, float *pose_dev, hipStream_t st);
+hipError_t launch_border_rows(const StepArgs &a, const StepScratch &s, float *B, hipStream_t st);
+// Reduces the point pass's pose partials, adds the priors (energies into rep) and factors the damped block.
+hipError_t launch_pose_setup(const float *pose_dev, const PosePrior &pr, const double *pose_part, int nblk_pts,
+                             float lambda, double *sys, misslam_report *rep, hipStream_t st);
+// Joint PCG into delta (12 m) and the pose step; applies params += delta and the pose step unless non-finite.
+hipError_t launch_joint_pcg(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
+                            float lambda, int iters, float *delta, const PcgScratch &s, const JointScratch &js,
+                            misslam_report *rep, float *params, float *pose_dev, hipStream_t st);
 // The list-entry packing the assembly reads; run once per registration (the graph, canonical points and node
 // positions are fixed across its Gauss-Newton steps) before the first launch_assemble.
 hipError_t launch_list_pack(const StepArgs &a, const StepScratch &s, hipStream_t st);

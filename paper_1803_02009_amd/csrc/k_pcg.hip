@@ -276,6 +276,8 @@ __global__ void report_init_batched_kernel(const BatchItem *__restrict__ items, 
         rep[t].lm_e_trial = 0.0;
         rep[t].lm_lambda = 0.f;
         rep[t].lm_accepted = 0;
+        rep[t].e_pose_r = 0.0;
+        rep[t].e_pose_p = 0.0;
     }
 }
 
@@ -301,6 +303,8 @@ __global__ void report_init_kernel(misslam_report *rep, int count) {
         rep[t].lm_e_trial = 0.0;
         rep[t].lm_lambda = 0.f;
         rep[t].lm_accepted = 0;
+        rep[t].e_pose_r = 0.0;
+        rep[t].e_pose_p = 0.0;
     }
 }
 

@@ -1,0 +1,530 @@
+// Joint rigid pose + ED registration (Eq.(3) with the Eq.(10) pose terms;
+// Sec. II-F: six more unknowns).  The pose perturbation xi = (dw, dt) acts as
+// R <- exp([dw]x) R, T <- exp([dw]x) T + dt, so a data row gains the pose
+// columns Jp = (v~ x N, N).  Per Gauss-Newton step:
+//   - the joint point pass writes Jp per point and per-block partials of
+//     sum Jp Jp^T and sum Jp r;
+//   - border_rows_kernel forms B_j = w_data sum_i w_ij kron(d_ij, n'_i) Jp_i^T
+//     (12 x 6 per node) from the node's list, one workgroup per node;
+//   - pose_setup_kernel reduces the partials, adds the priors w_r |log(R R0^T)|^2
+//     and w_p |C - C0|^2 (C = -R^T T; Jacobians I and -R^T, the first exact for
+//     the gradient) and factors the damped 6x6 block;
+//   - the joint PCG runs the textbook recurrence of the ED solve over the joint
+//     vector (the pose part in float64, computed redundantly by every block from
+//     the same partials, so every block holds the same values), then applies
+//     x += dx and the pose step.
+#include "frame.h"
+
+namespace msl {
+
+constexpr int kJThreads = 256;
+constexpr int kJRows = 21;          // node rows per block, 12 threads per row
+constexpr int kJKinds = 10;         // partial kinds per iteration: r.z, r.r, p.q, #non-finite, B^T z (6)
+constexpr int kPst = 32;            // pose state per iteration: r, z, p, q, x (6 each)
+
+__global__ void pose_init_kernel(Pose P, float *pose_dev) {
+    const int t = threadIdx.x;
+    if (t < 9) pose_dev[t] = P.R[t];
+    else if (t < 12) pose_dev[t] = P.T[t - 9];
+}
+
+// ---------------------------------------------------------------- border B_j
+
+__global__ void __launch_bounds__(64) border_rows_kernel(StepArgs a, StepScratch s, float *B) {
+    __shared__ float ent[64][14];   // w d (4), n' (3), Jp (6), pad
+    const int j = blockIdx.x, tid = threadIdx.x;
+    const int l0 = a.g.list_ptr[j], l1 = a.g.list_ptr[j + 1];
+    // this thread's entries (3c + a) * 6 + k of B_j: tid and tid + 64 (< 72)
+    const int e0 = tid, e1 = tid + 64;
+    const int c0 = (e0 / 6) / 3, a0 = (e0 / 6) % 3, k0 = e0 % 6;
+    const int c1 = (e1 / 6) / 3, a1 = (e1 / 6) % 3, k1 = e1 % 6;
+    float acc0 = 0.f, acc1 = 0.f;
+    for (int base = l0; base < l1; base += 64) {
+        const int le = base + tid;
+        if (le < l1) {
+            const int p = a.g.list_pts[le];
+            const float4 dw = s.lpa[le];
+            const float4 nr = s.nr[p];
+            const float4 j0 = s.jp[2 * (size_t)p], j1 = s.jp[2 * (size_t)p + 1];
+            ent[tid][0] = dw.w * dw.x;
+            ent[tid][1] = dw.w * dw.y;
+            ent[tid][2] = dw.w * dw.z;
+            ent[tid][3] = dw.w;
+            ent[tid][4] = nr.x;
+            ent[tid][5] = nr.y;
+            ent[tid][6] = nr.z;
+            ent[tid][7] = j0.x;
+            ent[tid][8] = j0.y;
+            ent[tid][9] = j0.z;
+            ent[tid][10] = j0.w;
+            ent[tid][11] = j1.x;
+            ent[tid][12] = j1.y;
+        }
+        __syncthreads();
+        const int cnt = min(64, l1 - base);
+        for (int t = 0; t < cnt; ++t) {
+            acc0 = fmaf(ent[t][c0] * ent[t][4 + a0], ent[t][7 + k0], acc0);
+            if (e1 < 72) acc1 = fmaf(ent[t][c1] * ent[t][4 + a1], ent[t][7 + k1], acc1);
+        }
+        __syncthreads();
+    }
+    B[(size_t)j * 72 + e0] = a.w_data * acc0;
+    if (e1 < 72) B[(size_t)j * 72 + e1] = a.w_data * acc1;
+}
+
+hipError_t launch_border_rows(const StepArgs &a, const StepScratch &s, float *B, hipStream_t st) {
+    if (a.nd.m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(border_rows_kernel, dim3(a.nd.m), dim3(64), 0, st, a, s, B);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- pose block
+
+__device__ inline void so3_log_d(const double R[9], double w[3]) {
+    const double c = fmin(1.0, fmax(-1.0, (R[0] + R[4] + R[8] - 1.0) * 0.5));
+    const double th = acos(c);
+    const double v[3] = {R[7] - R[5], R[2] - R[6], R[3] - R[1]};
+    const double f = th < 1e-8 ? 0.5 : th / (2.0 * sin(th));
+    for (int t = 0; t < 3; ++t) w[t] = f * v[t];
+}
+
+__device__ inline void so3_exp_d(const double w[3], double E[9]) {
+    const double th = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    const double K[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
+    double KK[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) KK[3 * r + c] = K[3 * r] * K[c] + K[3 * r + 1] * K[3 + c] + K[3 * r + 2] * K[6 + c];
+    const double f1 = th < 1e-12 ? 1.0 : sin(th) / th;
+    const double f2 = th < 1e-12 ? 0.5 : (1.0 - cos(th)) / (th * th);
+    for (int t = 0; t < 9; ++t) E[t] = (t % 4 == 0 ? 1.0 : 0.0) + f1 * K[t] + f2 * KK[t];
+}
+
+// Gauss-Jordan with partial pivoting on a 6x6 float64 system (one thread).
+__device__ inline bool inverse6(const double A_in[36], double out[36]) {
+    double A[6][12];
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 12; ++c) A[r][c] = c < 6 ? A_in[6 * r + c] : (c - 6 == r ? 1.0 : 0.0);
+    for (int k = 0; k < 6; ++k) {
+        int piv = k;
+        for (int r = k + 1; r < 6; ++r)
+            if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
+        if (!(fabs(A[piv][k]) > 0.0)) return false;
+        if (piv != k)
+            for (int c = 0; c < 12; ++c) {
+                const double t = A[k][c];
+                A[k][c] = A[piv][c];
+                A[piv][c] = t;
+            }
+        const double ip = 1.0 / A[k][k];
+        for (int c = 0; c < 12; ++c) A[k][c] *= ip;
+        for (int r = 0; r < 6; ++r) {
+            if (r == k) continue;
+            const double f = A[r][k];
+            for (int c = 0; c < 12; ++c) A[r][c] -= f * A[k][c];
+        }
+    }
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) out[6 * r + c] = A[r][6 + c];
+    return true;
+}
+
+__global__ void __launch_bounds__(256) pose_setup_kernel(const float *pose_dev, PosePrior pr,
+                                                         const double *__restrict__ part, int nblk_pts, float lambda,
+                                                         double *sys, misslam_report *rep) {
+    __shared__ double wred[256 / kWave][kPosePart];
+    double v[kPosePart];
+#pragma unroll
+    for (int q = 0; q < kPosePart; ++q) v[q] = 0.0;
+    for (int b = threadIdx.x; b < nblk_pts; b += 256)
+#pragma unroll
+        for (int q = 0; q < kPosePart; ++q) v[q] += part[(size_t)kPosePart * b + q];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int q = 0; q < kPosePart; ++q) {
+        double t = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (lane == 0) wred[wave][q] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double S[kPosePart];
+    for (int q = 0; q < kPosePart; ++q) S[q] = ((wred[0][q] + wred[1][q]) + wred[2][q]) + wred[3][q];
+    double H[36], g[6];
+    int e = 0;
+    for (int u = 0; u < 6; ++u)
+        for (int w = u; w < 6; ++w) {
+            H[6 * u + w] = (double)pr.w_data * S[e];
+            H[6 * w + u] = (double)pr.w_data * S[e];
+            ++e;
+        }
+    for (int u = 0; u < 6; ++u) g[u] = (double)pr.w_data * S[21 + u];
+    // priors: rho_r = log(R R0^T), rho_p = C - C0
+    double R[9], T[3], R0[9], T0[3], M[9];
+    for (int t = 0; t < 9; ++t) {
+        R[t] = pose_dev[t];
+        R0[t] = pr.R0[t];
+    }
+    for (int t = 0; t < 3; ++t) {
+        T[t] = pose_dev[9 + t];
+        T0[t] = pr.T0[t];
+    }
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            M[3 * r + c] = (R[3 * r] * R0[3 * c] + R[3 * r + 1] * R0[3 * c + 1]) + R[3 * r + 2] * R0[3 * c + 2];
+    double rr[3], rp[3];
+    so3_log_d(M, rr);
+    for (int a = 0; a < 3; ++a) {
+        const double C = -((R[a] * T[0] + R[3 + a] * T[1]) + R[6 + a] * T[2]);
+        const double C0 = -((R0[a] * T0[0] + R0[3 + a] * T0[1]) + R0[6 + a] * T0[2]);
+        rp[a] = C - C0;
+    }
+    for (int a = 0; a < 3; ++a) {
+        H[6 * a + a] += (double)pr.w_r;
+        g[a] += (double)pr.w_r * rr[a];
+        g[3 + a] -= (double)pr.w_p * ((R[3 * a] * rp[0] + R[3 * a + 1] * rp[1]) + R[3 * a + 2] * rp[2]);
+        for (int b = 0; b < 3; ++b)
+            H[6 * (3 + a) + 3 + b] +=
+                (double)pr.w_p * ((R[3 * a] * R[3 * b] + R[3 * a + 1] * R[3 * b + 1]) + R[3 * a + 2] * R[3 * b + 2]);
+    }
+    if (rep) {
+        rep->e_pose_r = (rr[0] * rr[0] + rr[1] * rr[1]) + rr[2] * rr[2];
+        rep->e_pose_p = (rp[0] * rp[0] + rp[1] * rp[1]) + rp[2] * rp[2];
+    }
+    if (!sys) return;
+    double Hd[36], Mi[36];
+    for (int t = 0; t < 36; ++t) Hd[t] = H[t] + (t % 7 == 0 ? (double)lambda : 0.0);
+    const bool ok = inverse6(Hd, Mi);
+    for (int t = 0; t < 36; ++t) {
+        sys[t] = H[t];
+        sys[42 + t] = ok ? Mi[t] : (t % 7 == 0 ? 1.0 : 0.0);
+    }
+    for (int t = 0; t < 6; ++t) sys[36 + t] = g[t];
+    if (!ok && rep) rep->flags |= MISSLAM_FLAG_NONSPD_BLOCK;
+}
+
+hipError_t launch_pose_init(const Pose &pose, float *pose_dev, hipStream_t st) {
+    hipLaunchKernelGGL(pose_init_kernel, dim3(1), dim3(64), 0, st, pose, pose_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_setup(const float *pose_dev, const PosePrior &pr, const double *pose_part, int nblk_pts,
+                             float lambda, double *sys, misslam_report *rep, hipStream_t st) {
+    hipLaunchKernelGGL(pose_setup_kernel, dim3(1), dim3(256), 0, st, pose_dev, pr, pose_part, nblk_pts, lambda, sys,
+                       rep);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- joint PCG
+
+struct JArgs {
+    PcgArgs A;
+    const float *B;
+    const double *sys;    // H_pp (36), g_p (6), (H_pp + lambda I)^-1 (36)
+    double *jpart;
+    double *pst;
+};
+
+__device__ __forceinline__ double jgather(const JArgs &J, int it, int kind, double *lds) {
+    const double *p = J.jpart + (size_t)(it * kJKinds + kind) * J.A.nblk;
+    double s = 0.0;
+    for (int t = threadIdx.x; t < J.A.nblk; t += kJThreads) s += p[t];
+    return block_sum<kJThreads>(s, lds);
+}
+
+__device__ __forceinline__ float jprecond(const float *minv, int j, int a, const float *rl) {
+    const float *M = minv + (size_t)j * 144 + a * 12;
+    float s = 0.f;
+#pragma unroll
+    for (int b = 0; b < 12; ++b) s = fmaf(M[b], rl[b], s);
+    return s;
+}
+
+__global__ void __launch_bounds__(kJThreads) jpcg_init_kernel(JArgs J) {
+    const PcgArgs &A = J.A;
+    __shared__ double red[kJThreads];
+    __shared__ float rl[kJRows][12];
+    const int row = threadIdx.x / 12, a = threadIdx.x % 12;
+    const int j = blockIdx.x * kJRows + row;
+    const bool act = row < kJRows && j < A.m;
+    float r = 0.f, z = 0.f;
+    if (act) {
+        r = -A.g[(size_t)j * 12 + a];
+        rl[row][a] = r;
+    }
+    __syncthreads();
+    if (act) {
+        z = jprecond(A.minv, j, a, rl[row]);
+        A.r[(size_t)j * 12 + a] = r;
+        A.z[(size_t)j * 12 + a] = z;
+        A.x[(size_t)j * 12 + a] = 0.f;
+    }
+    double rz = block_sum<kJThreads>((double)r * (double)z, red);
+    double rr = block_sum<kJThreads>((double)r * (double)r, red);
+    if (threadIdx.x == 0) {
+        if (blockIdx.x == 0) {   // the pose part: r_p = -g_p, z_p = M_p r_p
+            double rp[6], zp[6];
+            for (int u = 0; u < 6; ++u) rp[u] = -J.sys[36 + u];
+            for (int u = 0; u < 6; ++u) {
+                double t = 0.0;
+                for (int w = 0; w < 6; ++w) t += J.sys[42 + 6 * u + w] * rp[w];
+                zp[u] = t;
+            }
+            for (int u = 0; u < 6; ++u) {
+                rz += rp[u] * zp[u];
+                rr += rp[u] * rp[u];
+                J.pst[u] = rp[u];
+                J.pst[6 + u] = zp[u];
+                J.pst[12 + u] = 0.0;
+                J.pst[18 + u] = 0.0;
+                J.pst[24 + u] = 0.0;
+            }
+        }
+        J.jpart[(size_t)0 * A.nblk + blockIdx.x] = rz;
+        J.jpart[(size_t)1 * A.nblk + blockIdx.x] = rr;
+        J.jpart[(size_t)3 * A.nblk + blockIdx.x] = 0.0;
+    }
+    if (blockIdx.x == 0)
+        for (int t = threadIdx.x; t <= A.iters; t += kJThreads) {
+            A.status[t] = 0;
+            A.done[t] = 0;
+        }
+}
+
+// q_e = H z_e + lambda z_e + B z_p + beta q_e, p_e = z_e + beta p_e; partials p_e.q_e and B^T z_e.
+__global__ void __launch_bounds__(kJThreads) jpcg_dir_kernel(JArgs J, int it) {
+    const PcgArgs &A = J.A;
+    __shared__ double red[kJThreads];
+    __shared__ double zp[6];
+    const double rz = jgather(J, it, 0, red);
+    const double rz_prev = it > 0 ? jgather(J, it - 1, 0, red) : 1.0;
+    if (threadIdx.x < 6) zp[threadIdx.x] = J.pst[(size_t)it * kPst + 6 + threadIdx.x];
+    __syncthreads();
+    const bool skip = A.status[it] != 0 || rz == 0.0;
+    const int row = threadIdx.x / 12, a = threadIdx.x % 12;
+    const int j = blockIdx.x * kJRows + row;
+    const bool act = row < kJRows && j < A.m && !skip;
+    double pq = 0.0, btz[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (act) {
+        const float beta = it > 0 ? (float)(rz / rz_prev) : 0.f;
+        double az = 0.0;
+        const int p0 = A.row_ptr[j], p1 = min(A.row_ptr[j + 1], A.cap);
+        for (int pb = p0; pb < p1; ++pb) {
+            const int l = A.col_idx[pb];
+            const float *Bk = A.blocks + (size_t)pb * 144 + a * 12;
+            const float *zl = A.z + (size_t)l * 12;
+#pragma unroll
+            for (int b = 0; b < 12; ++b) az = fma((double)Bk[b], (double)zl[b], az);
+        }
+        const size_t o = (size_t)j * 12 + a;
+        const float zj = A.z[o];
+        az = fma((double)A.lambda, (double)zj, az);
+        const float *Bj = J.B + (size_t)j * 72 + a * 6;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            az = fma((double)Bj[k], zp[k], az);
+            btz[k] = (double)Bj[k] * (double)zj;
+        }
+        float p, q;
+        if (it > 0) {
+            p = fmaf(beta, A.p[o], zj);
+            q = (float)fma((double)beta, (double)A.q[o], az);
+        } else {
+            p = zj;
+            q = (float)az;
+        }
+        A.p[o] = p;
+        A.q[o] = q;
+        pq = (double)p * (double)q;
+    }
+    const double t = block_sum<kJThreads>(pq, red);
+    double bt[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) bt[k] = block_sum<kJThreads>(btz[k], red);
+    if (threadIdx.x == 0) {
+        J.jpart[(size_t)(it * kJKinds + 2) * A.nblk + blockIdx.x] = t;
+        for (int k = 0; k < 6; ++k) J.jpart[(size_t)(it * kJKinds + 4 + k) * A.nblk + blockIdx.x] = bt[k];
+    }
+}
+
+// The pose part of the product and the step, then the ED step: alpha = r.z / p.q over the joint vector.
+__global__ void __launch_bounds__(kJThreads) jpcg_step_kernel(JArgs J, int it) {
+    const PcgArgs &A = J.A;
+    __shared__ double red[kJThreads];
+    __shared__ float rl[kJRows][12];
+    __shared__ double ps[kPst];   // this iteration's pose r, z, p, q, x after the step
+    __shared__ double pq_pose;
+    const double rz = jgather(J, it, 0, red);
+    const double rz_prev = it > 0 ? jgather(J, it - 1, 0, red) : 1.0;
+    const double pq_e = jgather(J, it, 2, red);
+    double btz[6];
+    for (int k = 0; k < 6; ++k) btz[k] = jgather(J, it, 4 + k, red);
+    const int st = A.status[it];
+    const bool skip = st != 0 || rz == 0.0;
+    const float beta = it > 0 ? (float)(rz / rz_prev) : 0.f;
+    if (threadIdx.x == 0) {
+        const double *cur = J.pst + (size_t)it * kPst;
+        double zp[6], pp[6], qp[6];
+        for (int u = 0; u < 6; ++u) {
+            double az = btz[u];
+            for (int w = 0; w < 6; ++w) az += J.sys[6 * u + w] * cur[6 + w];
+            az += (double)A.lambda * cur[6 + u];
+            zp[u] = cur[6 + u];
+            qp[u] = it > 0 ? (double)beta * cur[18 + u] + az : az;
+            pp[u] = it > 0 ? (double)beta * cur[12 + u] + zp[u] : zp[u];
+        }
+        double t = 0.0;
+        for (int u = 0; u < 6; ++u) t += pp[u] * qp[u];
+        pq_pose = t;
+        for (int u = 0; u < 6; ++u) {
+            ps[u] = cur[u];
+            ps[6 + u] = cur[6 + u];
+            ps[12 + u] = skip ? cur[12 + u] : pp[u];
+            ps[18 + u] = skip ? cur[18 + u] : qp[u];
+            ps[24 + u] = cur[24 + u];
+        }
+    }
+    __syncthreads();
+    const double pq = pq_e + pq_pose;
+    const bool brk = !skip && !(pq > 0.0);
+    const bool upd = !skip && !brk;
+    const float alpha = upd ? (float)(rz / pq) : 0.f;
+    const int row = threadIdx.x / 12, a = threadIdx.x % 12;
+    const int j = blockIdx.x * kJRows + row;
+    const bool in = row < kJRows && j < A.m;
+    const size_t o = (size_t)j * 12 + a;
+    float r = 0.f;
+    double bad = 0.0;
+    if (in) {
+        r = A.r[o];
+        float xv = A.x[o];
+        if (upd) {
+            xv = fmaf(alpha, A.p[o], xv);
+            A.x[o] = xv;
+            r = fmaf(-alpha, A.q[o], r);
+            A.r[o] = r;
+        }
+        bad = isfinite(xv) ? 0.0 : 1.0;
+        rl[row][a] = r;
+    }
+    __syncthreads();
+    float z = 0.f;
+    if (in) {
+        if (upd) {
+            z = jprecond(A.minv, j, a, rl[row]);
+            A.z[o] = z;
+        } else {
+            z = A.z[o];
+        }
+    }
+    double rzn = block_sum<kJThreads>((double)r * (double)z, red);
+    double rrn = block_sum<kJThreads>((double)r * (double)r, red);
+    double nb = block_sum<kJThreads>(bad, red);
+    if (threadIdx.x == 0) {
+        if (blockIdx.x == 0) {   // the pose step, stored for the next iteration
+            double *nxt = J.pst + (size_t)(it + 1) * kPst;
+            double rp[6], zp[6];
+            for (int u = 0; u < 6; ++u) {
+                rp[u] = upd ? ps[u] - (double)alpha * ps[18 + u] : ps[u];
+                nxt[24 + u] = upd ? ps[24 + u] + (double)alpha * ps[12 + u] : ps[24 + u];
+                if (!isfinite(nxt[24 + u])) nb += 1.0;
+            }
+            for (int u = 0; u < 6; ++u) {
+                double t = 0.0;
+                for (int w = 0; w < 6; ++w) t += J.sys[42 + 6 * u + w] * rp[w];
+                zp[u] = upd ? t : ps[6 + u];
+            }
+            for (int u = 0; u < 6; ++u) {
+                rzn += rp[u] * zp[u];
+                rrn += rp[u] * rp[u];
+                nxt[u] = rp[u];
+                nxt[6 + u] = zp[u];
+                nxt[12 + u] = ps[12 + u];
+                nxt[18 + u] = ps[18 + u];
+            }
+            A.status[it + 1] = st != 0 ? st : (brk ? 2 : 0);
+            A.done[it] = upd ? 1 : 0;
+        }
+        J.jpart[(size_t)((it + 1) * kJKinds + 0) * A.nblk + blockIdx.x] = rzn;
+        J.jpart[(size_t)((it + 1) * kJKinds + 1) * A.nblk + blockIdx.x] = rrn;
+        J.jpart[(size_t)((it + 1) * kJKinds + 3) * A.nblk + blockIdx.x] = nb;
+    }
+}
+
+// Report (block 0), params += x_e and the pose step unless anything is non-finite.
+__global__ void __launch_bounds__(kJThreads) jpcg_finish_kernel(JArgs J, misslam_report *rep,
+                                                                float *__restrict__ params, float *pose_dev) {
+    const PcgArgs &A = J.A;
+    __shared__ double red[kJThreads];
+    const double nbad = jgather(J, A.iters, 3, red);
+    const int total = A.m * 12;
+    const int t = blockIdx.x * kJThreads + threadIdx.x;
+    if (params && nbad == 0.0 && t < total) params[t] += A.x[t];
+    if (blockIdx.x != 0) return;
+    int done = 0;
+    for (int q = 0; q < A.iters; ++q) done += A.done[q];
+    for (int q = 0; q <= done; ++q) {
+        const double rr = jgather(J, q, 1, red);
+        if (threadIdx.x == 0 && q <= MISSLAM_MAX_PCG) rep->pcg_resid[q] = sqrt(rr);
+    }
+    if (threadIdx.x == 0) {
+        rep->pcg_iters_done = done;
+        int f = rep->flags;
+        if (A.status[A.iters] & 2) f |= MISSLAM_FLAG_PCG_BREAKDOWN;
+        if (nbad != 0.0) f |= MISSLAM_FLAG_NONFINITE;
+        rep->flags = f;
+        if (nbad == 0.0) {
+            const double *xp = J.pst + (size_t)A.iters * kPst + 24;
+            double E[9], R[9], T[3];
+            so3_exp_d(xp, E);
+            for (int u = 0; u < 9; ++u) R[u] = pose_dev[u];
+            for (int u = 0; u < 3; ++u) T[u] = pose_dev[9 + u];
+            for (int r = 0; r < 3; ++r) {
+                for (int c = 0; c < 3; ++c)
+                    pose_dev[3 * r + c] =
+                        (float)((E[3 * r] * R[c] + E[3 * r + 1] * R[3 + c]) + E[3 * r + 2] * R[6 + c]);
+                pose_dev[9 + r] = (float)(((E[3 * r] * T[0] + E[3 * r + 1] * T[1]) + E[3 * r + 2] * T[2]) + xp[3 + r]);
+            }
+        }
+    }
+}
+
+hipError_t launch_joint_pcg(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
+                            float lambda, int iters, float *delta, const PcgScratch &s, const JointScratch &js,
+                            misslam_report *rep, float *params, float *pose_dev, hipStream_t st) {
+    JArgs J;
+    PcgArgs &A = J.A;
+    A.row_ptr = g.row_ptr;
+    A.col_idx = g.col_idx;
+    A.blocks = blocks;
+    A.minv = minv;
+    A.g = gvec;
+    A.lambda = lambda;
+    A.m = m;
+    A.nblk = (m + kJRows - 1) / kJRows;
+    A.iters = iters;
+    A.cap = g.bsr_cap;
+    A.x = delta;
+    A.r = s.r;
+    A.z = s.z;
+    A.p = s.p;
+    A.q = s.q;
+    A.part = nullptr;
+    A.status = s.status;
+    A.done = s.status + (iters + 2);
+    J.B = js.B;
+    J.sys = js.sys;
+    J.jpart = js.jpart;
+    J.pst = js.pst;
+    const dim3 grid(A.nblk), blk(kJThreads);
+    hipLaunchKernelGGL(jpcg_init_kernel, grid, blk, 0, st, J);
+    for (int it = 0; it < iters; ++it) {
+        hipLaunchKernelGGL(jpcg_dir_kernel, grid, blk, 0, st, J, it);
+        hipLaunchKernelGGL(jpcg_step_kernel, grid, blk, 0, st, J, it);
+    }
+    hipLaunchKernelGGL(jpcg_finish_kernel, dim3((12 * m + kJThreads - 1) / kJThreads), blk, 0, st, J, rep, params,
+                       pose_dev);
+    return hipGetLastError();
+}
+
+}  // namespace msl

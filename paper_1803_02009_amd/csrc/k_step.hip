@@ -61,24 +61,42 @@ constexpr int kPtBlock = 256;
 // One thread per model point: warps point and normal into the camera, finds
 // the matched pixel, stores (n', r) with n' = R^T N for the assembly, and leaves
 // per-block float64 sums (r^2, count, |r|) for the energy report.
-template <int K>
+// Joint pose form (JOINT): the pose comes from the device, and each point also
+// writes the pose columns Jp = (v~ x N, N) of its data row and adds Jp Jp^T and
+// Jp r to per-block float64 partials (27 values, fixed reduction order).
+template <int K, bool JOINT = false>
 __device__ __forceinline__ void point_pass_body(const StepArgs &a, const StepScratch &s, int64_t blk) {
     __shared__ double red[kPtBlock];
     const int64_t n = a.pts.n;
     const int64_t i = blk * kPtBlock + threadIdx.x;
+    const Pose P = JOINT ? step_pose(a) : a.pose;
     double r2 = 0.0, cnt = 0.0, ra = 0.0;
+    float jp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, rres = 0.f;
     if (i < n) {
         float x, y, z, nx, ny, nz;
         ed_blend<K>(a.pts.px[i], a.pts.py[i], a.pts.pz[i], a.g.knn_idx, a.g.knn_w, n, i, a.nd, x, y, z);
-        apply_pose(a.pose, x, y, z);
+        apply_pose(P, x, y, z);
         ed_blend_normal<K>(a.pts.nx[i], a.pts.ny[i], a.pts.nz[i], a.g.knn_idx, a.g.knn_w, n, i, a.nd, nx, ny, nz);
-        rotate(a.pose, nx, ny, nz);
+        rotate(P, nx, ny, nz);
         normalize3(nx, ny, nz);
         const Match mt = a.corr_in ? match_fixed(x, y, z, a.corr_in[i], a.nmap, a.cam)
                                    : associate(x, y, z, nx, ny, nz, a.nmap, a.cam, a.eps_d, a.cos_eps_n);
         float p0 = 0.f, p1 = 0.f, p2 = 0.f, rr = 0.f;
+        if (JOINT && mt.pix >= 0) {
+            jp[0] = fmaf(y, mt.Nz, -z * mt.Ny);
+            jp[1] = fmaf(z, mt.Nx, -x * mt.Nz);
+            jp[2] = fmaf(x, mt.Ny, -y * mt.Nx);
+            jp[3] = mt.Nx;
+            jp[4] = mt.Ny;
+            jp[5] = mt.Nz;
+            rres = mt.r;
+        }
+        if (JOINT) {
+            s.jp[2 * i] = make_float4(jp[0], jp[1], jp[2], jp[3]);
+            s.jp[2 * i + 1] = make_float4(jp[4], jp[5], 0.f, 0.f);
+        }
         if (mt.pix >= 0) {
-            const float *R = a.pose.R;
+            const float *R = P.R;
             // n' = R^T N
             p0 = fmaf(R[6], mt.Nz, fmaf(R[3], mt.Ny, R[0] * mt.Nx));
             p1 = fmaf(R[7], mt.Nz, fmaf(R[4], mt.Ny, R[1] * mt.Nx));
@@ -99,6 +117,33 @@ __device__ __forceinline__ void point_pass_body(const StepArgs &a, const StepScr
         s.pt_part[3 * blk + 0] = t0;
         s.pt_part[3 * blk + 1] = t1;
         s.pt_part[3 * blk + 2] = t2;
+    }
+    if (JOINT) {
+        // 27 sums at once: wave butterflies, then the waves in order
+        __shared__ double wred[kPtBlock / kWave][kPosePart];
+        double v[kPosePart];
+        int e = 0;
+#pragma unroll
+        for (int u = 0; u < 6; ++u)
+#pragma unroll
+            for (int w = u; w < 6; ++w) v[e++] = (double)jp[u] * (double)jp[w];
+#pragma unroll
+        for (int u = 0; u < 6; ++u) v[e++] = (double)jp[u] * (double)rres;
+        const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+        for (int q = 0; q < kPosePart; ++q) {
+            double t = v[q];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+            if (lane == 0) wred[wave][q] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x < kPosePart) {
+            double t = wred[0][threadIdx.x];
+#pragma unroll
+            for (int w = 1; w < kPtBlock / kWave; ++w) t += wred[w][threadIdx.x];
+            s.pose_part[(size_t)kPosePart * blk + threadIdx.x] = t;
+        }
     }
 }
 
@@ -1229,6 +1274,26 @@ __global__ void __launch_bounds__(256) energy_report_kernel(const double *__rest
                                                             unsigned *__restrict__ zero_words, int zero_count,
                                                             const double *__restrict__ kp_energy, int kp_count) {
     energy_report_body(pt_part, npb, node_part, m, rep, reject_thr, zero_words, zero_count, kp_energy, kp_count);
+}
+
+template <int K>
+__global__ void __launch_bounds__(kPtBlock) point_pass_joint_kernel(StepArgs a, StepScratch s) {
+    point_pass_body<K, true>(a, s, blockIdx.x);
+}
+
+int point_blocks(int64_t n) { return (int)nblk(n > 0 ? n : 1, kPtBlock); }
+
+hipError_t launch_point_pass_joint(const StepArgs &a, const StepScratch &s, hipStream_t st) {
+    const unsigned ptb = nblk(a.pts.n > 0 ? a.pts.n : 1, kPtBlock);
+    switch (a.g.k) {
+#define MSL_PJ_CASE(KK)                                                                                     \
+    case KK: hipLaunchKernelGGL((point_pass_joint_kernel<KK>), dim3(ptb), dim3(kPtBlock), 0, st, a, s); break;
+        MSL_PJ_CASE(1) MSL_PJ_CASE(2) MSL_PJ_CASE(3) MSL_PJ_CASE(4)
+        MSL_PJ_CASE(5) MSL_PJ_CASE(6) MSL_PJ_CASE(7) MSL_PJ_CASE(8)
+#undef MSL_PJ_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_t st, const KeyArgs *kp,

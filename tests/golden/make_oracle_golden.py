@@ -7,8 +7,10 @@ low-precision form (data-term Jacobian rows rounded to bf16 / fp16 before
 J^T J, R refinement passes of each step against the unrounded system);
 name:kp:S adds S generated key points (gen.keypoints, seed 7, 0.05 mm noise)
 with the Eq.(9) term at w_corr = 10; name:lm runs the adaptive
-Levenberg-Marquardt schedule (default factors) instead of the fixed damping.
-Output: tests/golden/<name>[_<prec>_r<R> | _kp<S> | _lm]_oracle.npz with x
+Levenberg-Marquardt schedule (default factors) instead of the fixed damping;
+name:joint registers the rigid pose with the ED graph (Eq.(10) terms,
+w_r = 1e6, w_p = 1e3), storing the refined pose too.
+Output: tests/golden/<name>[_<prec>_r<R> | _kp<S> | _lm | _joint]_oracle.npz with x
 (m, 12) after the frame's iterations (independent decisions), the final
 energies and the per-iteration data energies (and, for lm, the per-step
 decisions and dampings).
@@ -35,6 +37,10 @@ def main(spec):
     if len(parts) == 1:
         x, rep = oracle.gn_register(pb)
         out = f"{name}_oracle.npz"
+    elif parts[1] == "joint":
+        x, R, T, rep = oracle.joint_register(pb)
+        out = f"{name}_joint_oracle.npz"
+        extra_pose = dict(R=R, T=T, e_r_final=rep["final"]["e_r"], e_p_final=rep["final"]["e_p"])
     elif parts[1] == "lm":
         x, rep = oracle.lm_register(pb, oracle.LMSchedule())
         out = f"{name}_lm_oracle.npz"
@@ -50,9 +56,9 @@ def main(spec):
         x, rep = oracle.gn_register(pb, jac_round=lambda J: rnd(J.astype(np.float32)), refine_steps=steps)
         out = f"{name}_{prec}_r{steps}_oracle.npz"
     it = rep["iters"]
-    extra = {}
+    extra = dict(extra_pose) if len(parts) > 1 and parts[1] == "joint" else {}
     if "accepted" in it[0]:
-        extra = dict(accepted=np.array([e["accepted"] for e in it]), lam=np.array([e["lambda"] for e in it]),
+        extra.update(accepted=np.array([e["accepted"] for e in it]), lam=np.array([e["lambda"] for e in it]),
                      E=np.array([e["E"] for e in it]), E_trial=np.array([e["E_trial"] for e in it]))
     np.savez_compressed(os.path.join(HERE, out), x=x, e_data_final=rep["final"]["e_data"],
                         e_rot_final=rep["final"]["e_rot"], e_reg_final=rep["final"]["e_reg"],

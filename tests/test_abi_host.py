@@ -42,10 +42,10 @@ def test_struct_layout_matches_header():
 #include <stddef.h>
 #include "misslam.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(misslam_camera), sizeof(misslam_pose),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(misslam_camera), sizeof(misslam_pose),
          sizeof(misslam_points), sizeof(misslam_nodes), sizeof(misslam_graph), sizeof(misslam_params),
          sizeof(misslam_report), sizeof(misslam_fuse_params), sizeof(misslam_problem), sizeof(misslam_keypoints),
-         sizeof(misslam_lm_params));
+         sizeof(misslam_lm_params), sizeof(misslam_pose_weights));
   printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(misslam_params, eps_d), offsetof(misslam_params, lambda),
          offsetof(misslam_report, n_valid), offsetof(misslam_graph, info), offsetof(misslam_params, solve_launch),
          offsetof(misslam_report, lm_e), offsetof(misslam_report, lm_accepted));
@@ -60,7 +60,8 @@ int main(void) {
         out = subprocess.check_output([exe]).decode().split("\n")
     sizes = [int(v) for v in out[0].split()]
     want = [ctypes.sizeof(t) for t in (_lib.Camera, _lib.Pose, _lib.Points, _lib.Nodes, _lib.Graph, _lib.Params,
-                                       _lib.Report, _lib.FuseParams, _lib.Problem, _lib.Keypoints, _lib.LMParams)]
+                                       _lib.Report, _lib.FuseParams, _lib.Problem, _lib.Keypoints, _lib.LMParams,
+                                       _lib.PoseWeights)]
     assert sizes == want
     offs = [int(v) for v in out[1].split()]
     assert offs == [_lib.Params.eps_d.offset, _lib.Params.lambda_.offset, _lib.Report.n_valid.offset,
@@ -178,6 +179,18 @@ def test_validation_errors(lib):
                    None) == _lib.EINVAL
     assert lmr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(plp), None, B(good), FAKE, None, FAKE, 1 << 40,
                None) == _lib.EUNSUPPORTED
+    # joint pose: weights and an output pose are required, weights finite and >= 0; float32 form only
+    jr = lib.misslam_joint_register
+    pw = _lib.PoseWeights(1e6, 1e3)
+    assert jr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), None, B(p), FAKE, FAKE, None, FAKE, 1 << 40,
+              None) == _lib.EINVAL
+    assert jr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(pw), B(p), None, FAKE, None, FAKE, 1 << 40,
+              None) == _lib.EINVAL
+    for bad in (_lib.PoseWeights(-1.0, 1e3), _lib.PoseWeights(1e6, float("nan")), _lib.PoseWeights(float("inf"), 1.0)):
+        assert jr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(bad), B(p), FAKE, FAKE, None, FAKE, 1 << 40,
+                  None) == _lib.EINVAL
+    assert jr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(pw), B(plp), FAKE, FAKE, None, FAKE, 1 << 40,
+              None) == _lib.EUNSUPPORTED
     # n above capacity, bad camera, bad k
     over = _lib.Points(200, 100, *([FAKE] * 6), 0, 0)
     assert lib.misslam_warp(B(over), B(nds), B(gr), None, FAKE, None, None) == _lib.EINVAL
