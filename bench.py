@@ -80,6 +80,7 @@ def parse():
     ap.add_argument("--no-lowp", action="store_true")
     ap.add_argument("--no-keypoints", action="store_true")
     ap.add_argument("--no-lm", action="store_true")
+    ap.add_argument("--no-joint", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run 5 device-to-device copies of this many MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -148,14 +149,17 @@ def main():
     w0, stamp0 = w.clone(), stamp.clone()
     fp = M.fuse_params(frame=1)
 
-    def frame(p=params, keys=None, lm=None):
+    def frame(p=params, keys=None, lm=None, joint=False):
         pts.copy_(pts0)
         nodes.copy_(nodes0)
         w.copy_(w0)
         stamp.copy_(stamp0)
         x.copy_(x0)
         g = M.build_graph(pts, nodes, p, ws)
-        if lm is None:
+        if joint:
+            rep, pz, _ = M.joint_register(pts, nodes, x, g, depth, cam, pose, p, ws)
+            state["pose"] = pz
+        elif lm is None:
             rep, _ = M.gn_register(pts, nodes, x, g, depth, cam, pose, p, ws, keys=keys)
         else:
             rep, _ = M.lm_register(pts, nodes, x, g, depth, cam, pose, p, ws, lm=lm, keys=keys)
@@ -163,11 +167,11 @@ def main():
         nmap = M.normal_map(depth, cam)
         M.fuse(pts, w, stamp, nodes, x, g, nmap, cam, pose, fp, ws)
 
-    def timed(p, steps, keys=None, lm=None):
+    def timed(p, steps, keys=None, lm=None, joint=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            frame(p, keys, lm)
+            frame(p, keys, lm, joint)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
@@ -221,6 +225,7 @@ def main():
     lowp = None if args.no_lowp else lowp_bench(M, _lib, sc, frame, timed, state, G, args)
     kpb = None if args.no_keypoints else keypoint_bench(M, sc, frame, timed, state, params, G, args, torch)
     lmb = None if args.no_lm else lm_bench(M, frame, timed, state, params, G, args)
+    jb = None if args.no_joint else joint_bench(M, sc, frame, timed, state, params, G, args)
 
     out = {
         "metric": "GN iters/s + ms/frame at 640x480, 1600 ED nodes, rel err vs FP64 oracle",
@@ -254,6 +259,8 @@ def main():
         out["keypoints"] = kpb
     if lmb is not None:
         out["adaptive_lm"] = lmb
+    if jb is not None:
+        out["joint_pose"] = jb
     if not args.no_batch:
         out["batch"] = batch_bench(M, _lib, args)
     if args.seq_frames > 0:
@@ -433,6 +440,30 @@ def lm_bench(M, frame, timed, state, params, G, args):
     if os.path.exists(gold):
         z = np.load(gold)
         out["oracle_decisions"] = "".join("A" if a else "r" for a in z["accepted"])
+    return out
+
+
+def joint_bench(M, sc, frame, timed, state, params, G, args):
+    """The same frame registering the rigid pose with the ED graph (Eq.(10) terms, w_r = 1e6, w_p = 1e3), the
+    generated pose as start and prior; against the stored float64 oracle run of the same problem."""
+    for _ in range(max(1, args.warmup)):
+        frame(params, None, None, True)
+    el = timed(params, args.steps, None, None, True)
+    rep = M.read_report(state["rep"])
+    gold = os.path.join(ROOT, "tests", "golden", f"{args.config}_joint_oracle.npz")
+    acc = accuracy(state, rep, gold)
+    P = state["pose"].cpu().numpy().astype(np.float64)
+    R0 = np.asarray(sc["R"], np.float32).astype(np.float64)
+    T0 = np.asarray(sc["T"], np.float32).astype(np.float64)
+    out = {"workload": "the same frame, pose + ED unknowns (Eq.(10) priors at the generated pose)",
+           "ms_per_frame": round(1000.0 * el / args.steps, 4), "gn_iters_per_s": round(G * args.steps / el, 2),
+           "pose_moved": {"max_abs_dR": float(np.abs(P[:9].reshape(3, 3) - R0).max()),
+                          "max_abs_dT_mm": float(np.abs(P[9:] - T0).max())},
+           "e_data": [float(rep[0]["e_data"]), float(rep[-1]["e_data"])], "accuracy_vs_fp64_oracle": acc}
+    if os.path.exists(gold):
+        z = np.load(gold)
+        acc["max_abs_err_R"] = float(np.abs(P[:9].reshape(3, 3) - z["R"]).max())
+        acc["max_abs_err_T_mm"] = float(np.abs(P[9:] - z["T"]).max())
     return out
 
 

@@ -30,51 +30,63 @@ __global__ void pose_init_kernel(Pose P, float *pose_dev) {
 
 // ---------------------------------------------------------------- border B_j
 
-__global__ void __launch_bounds__(64) border_rows_kernel(StepArgs a, StepScratch s, float *B) {
-    __shared__ float ent[64][14];   // w d (4), n' (3), Jp (6), pad
-    const int j = blockIdx.x, tid = threadIdx.x;
+constexpr int kBorderWaves = 4;
+
+__global__ void __launch_bounds__(kBorderWaves * 64) border_rows_kernel(StepArgs a, StepScratch s, float *B) {
+    __shared__ float ent[kBorderWaves][64][14];   // per wave: w d (4), n' (3), Jp (6), pad
+    __shared__ float part[kBorderWaves][72];
+    const int j = blockIdx.x;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int l0 = a.g.list_ptr[j], l1 = a.g.list_ptr[j + 1];
-    // this thread's entries (3c + a) * 6 + k of B_j: tid and tid + 64 (< 72)
-    const int e0 = tid, e1 = tid + 64;
+    // this lane's entries (3c + a) * 6 + k of B_j: lane and lane + 64 (< 72)
+    const int e0 = lane, e1 = lane + 64;
     const int c0 = (e0 / 6) / 3, a0 = (e0 / 6) % 3, k0 = e0 % 6;
     const int c1 = (e1 / 6) / 3, a1 = (e1 / 6) % 3, k1 = e1 % 6;
     float acc0 = 0.f, acc1 = 0.f;
-    for (int base = l0; base < l1; base += 64) {
-        const int le = base + tid;
+    // wave w takes the list entries base0 + 64 w .. + 63 of each pass: a fixed order per wave
+    for (int base0 = l0; base0 < l1; base0 += 64 * kBorderWaves) {
+        const int base = base0 + 64 * wave;
+        const int le = base + lane;
+        float (*E)[14] = ent[wave];
         if (le < l1) {
             const int p = a.g.list_pts[le];
             const float4 dw = s.lpa[le];
             const float4 nr = s.nr[p];
             const float4 j0 = s.jp[2 * (size_t)p], j1 = s.jp[2 * (size_t)p + 1];
-            ent[tid][0] = dw.w * dw.x;
-            ent[tid][1] = dw.w * dw.y;
-            ent[tid][2] = dw.w * dw.z;
-            ent[tid][3] = dw.w;
-            ent[tid][4] = nr.x;
-            ent[tid][5] = nr.y;
-            ent[tid][6] = nr.z;
-            ent[tid][7] = j0.x;
-            ent[tid][8] = j0.y;
-            ent[tid][9] = j0.z;
-            ent[tid][10] = j0.w;
-            ent[tid][11] = j1.x;
-            ent[tid][12] = j1.y;
+            E[lane][0] = dw.w * dw.x;
+            E[lane][1] = dw.w * dw.y;
+            E[lane][2] = dw.w * dw.z;
+            E[lane][3] = dw.w;
+            E[lane][4] = nr.x;
+            E[lane][5] = nr.y;
+            E[lane][6] = nr.z;
+            E[lane][7] = j0.x;
+            E[lane][8] = j0.y;
+            E[lane][9] = j0.z;
+            E[lane][10] = j0.w;
+            E[lane][11] = j1.x;
+            E[lane][12] = j1.y;
         }
         __syncthreads();
-        const int cnt = min(64, l1 - base);
+        const int cnt = max(0, min(64, l1 - base));
         for (int t = 0; t < cnt; ++t) {
-            acc0 = fmaf(ent[t][c0] * ent[t][4 + a0], ent[t][7 + k0], acc0);
-            if (e1 < 72) acc1 = fmaf(ent[t][c1] * ent[t][4 + a1], ent[t][7 + k1], acc1);
+            acc0 = fmaf(E[t][c0] * E[t][4 + a0], E[t][7 + k0], acc0);
+            if (e1 < 72) acc1 = fmaf(E[t][c1] * E[t][4 + a1], E[t][7 + k1], acc1);
         }
         __syncthreads();
     }
-    B[(size_t)j * 72 + e0] = a.w_data * acc0;
-    if (e1 < 72) B[(size_t)j * 72 + e1] = a.w_data * acc1;
+    part[wave][e0] = acc0;
+    if (e1 < 72) part[wave][e1] = acc1;
+    __syncthreads();
+    if (threadIdx.x < 72) {
+        const int e = threadIdx.x;
+        B[(size_t)j * 72 + e] = a.w_data * (((part[0][e] + part[1][e]) + part[2][e]) + part[3][e]);
+    }
 }
 
 hipError_t launch_border_rows(const StepArgs &a, const StepScratch &s, float *B, hipStream_t st) {
     if (a.nd.m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(border_rows_kernel, dim3(a.nd.m), dim3(64), 0, st, a, s, B);
+    hipLaunchKernelGGL(border_rows_kernel, dim3(a.nd.m), dim3(kBorderWaves * 64), 0, st, a, s, B);
     return hipGetLastError();
 }
 
@@ -85,6 +97,7 @@ __device__ inline void so3_log_d(const double R[9], double w[3]) {
     const double th = acos(c);
     const double v[3] = {R[7] - R[5], R[2] - R[6], R[3] - R[1]};
     const double f = th < 1e-8 ? 0.5 : th / (2.0 * sin(th));
+#pragma unroll
     for (int t = 0; t < 3; ++t) w[t] = f * v[t];
 }
 
@@ -92,40 +105,45 @@ __device__ inline void so3_exp_d(const double w[3], double E[9]) {
     const double th = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
     const double K[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
     double KK[9];
+#pragma unroll
     for (int r = 0; r < 3; ++r)
+#pragma unroll
         for (int c = 0; c < 3; ++c) KK[3 * r + c] = K[3 * r] * K[c] + K[3 * r + 1] * K[3 + c] + K[3 * r + 2] * K[6 + c];
     const double f1 = th < 1e-12 ? 1.0 : sin(th) / th;
     const double f2 = th < 1e-12 ? 0.5 : (1.0 - cos(th)) / (th * th);
+#pragma unroll
     for (int t = 0; t < 9; ++t) E[t] = (t % 4 == 0 ? 1.0 : 0.0) + f1 * K[t] + f2 * KK[t];
 }
 
-// Gauss-Jordan with partial pivoting on a 6x6 float64 system (one thread).
+// Gauss-Jordan on the diagonal pivots of a 6x6 SPD float64 matrix (one thread,
+// fully unrolled so that the matrix stays in registers).  A non-positive pivot
+// (not SPD) returns false.
 __device__ inline bool inverse6(const double A_in[36], double out[36]) {
     double A[6][12];
+#pragma unroll
     for (int r = 0; r < 6; ++r)
+#pragma unroll
         for (int c = 0; c < 12; ++c) A[r][c] = c < 6 ? A_in[6 * r + c] : (c - 6 == r ? 1.0 : 0.0);
+    bool ok = true;
+#pragma unroll
     for (int k = 0; k < 6; ++k) {
-        int piv = k;
-        for (int r = k + 1; r < 6; ++r)
-            if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
-        if (!(fabs(A[piv][k]) > 0.0)) return false;
-        if (piv != k)
-            for (int c = 0; c < 12; ++c) {
-                const double t = A[k][c];
-                A[k][c] = A[piv][c];
-                A[piv][c] = t;
-            }
-        const double ip = 1.0 / A[k][k];
+        ok = ok && A[k][k] > 0.0;
+        const double ip = A[k][k] > 0.0 ? 1.0 / A[k][k] : 1.0;
+#pragma unroll
         for (int c = 0; c < 12; ++c) A[k][c] *= ip;
+#pragma unroll
         for (int r = 0; r < 6; ++r) {
             if (r == k) continue;
             const double f = A[r][k];
+#pragma unroll
             for (int c = 0; c < 12; ++c) A[r][c] -= f * A[k][c];
         }
     }
+#pragma unroll
     for (int r = 0; r < 6; ++r)
+#pragma unroll
         for (int c = 0; c < 6; ++c) out[6 * r + c] = A[r][6 + c];
-    return true;
+    return ok;
 }
 
 __global__ void __launch_bounds__(256) pose_setup_kernel(const float *pose_dev, PosePrior pr,
@@ -149,40 +167,51 @@ __global__ void __launch_bounds__(256) pose_setup_kernel(const float *pose_dev, 
     __syncthreads();
     if (threadIdx.x != 0) return;
     double S[kPosePart];
+#pragma unroll
     for (int q = 0; q < kPosePart; ++q) S[q] = ((wred[0][q] + wred[1][q]) + wred[2][q]) + wred[3][q];
     double H[36], g[6];
     int e = 0;
+#pragma unroll
     for (int u = 0; u < 6; ++u)
+#pragma unroll
         for (int w = u; w < 6; ++w) {
             H[6 * u + w] = (double)pr.w_data * S[e];
             H[6 * w + u] = (double)pr.w_data * S[e];
             ++e;
         }
+#pragma unroll
     for (int u = 0; u < 6; ++u) g[u] = (double)pr.w_data * S[21 + u];
     // priors: rho_r = log(R R0^T), rho_p = C - C0
     double R[9], T[3], R0[9], T0[3], M[9];
+#pragma unroll
     for (int t = 0; t < 9; ++t) {
         R[t] = pose_dev[t];
         R0[t] = pr.R0[t];
     }
+#pragma unroll
     for (int t = 0; t < 3; ++t) {
         T[t] = pose_dev[9 + t];
         T0[t] = pr.T0[t];
     }
+#pragma unroll
     for (int r = 0; r < 3; ++r)
+#pragma unroll
         for (int c = 0; c < 3; ++c)
             M[3 * r + c] = (R[3 * r] * R0[3 * c] + R[3 * r + 1] * R0[3 * c + 1]) + R[3 * r + 2] * R0[3 * c + 2];
     double rr[3], rp[3];
     so3_log_d(M, rr);
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double C = -((R[a] * T[0] + R[3 + a] * T[1]) + R[6 + a] * T[2]);
         const double C0 = -((R0[a] * T0[0] + R0[3 + a] * T0[1]) + R0[6 + a] * T0[2]);
         rp[a] = C - C0;
     }
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
         H[6 * a + a] += (double)pr.w_r;
         g[a] += (double)pr.w_r * rr[a];
         g[3 + a] -= (double)pr.w_p * ((R[3 * a] * rp[0] + R[3 * a + 1] * rp[1]) + R[3 * a + 2] * rp[2]);
+#pragma unroll
         for (int b = 0; b < 3; ++b)
             H[6 * (3 + a) + 3 + b] +=
                 (double)pr.w_p * ((R[3 * a] * R[3 * b] + R[3 * a + 1] * R[3 * b + 1]) + R[3 * a + 2] * R[3 * b + 2]);
@@ -193,12 +222,15 @@ __global__ void __launch_bounds__(256) pose_setup_kernel(const float *pose_dev, 
     }
     if (!sys) return;
     double Hd[36], Mi[36];
+#pragma unroll
     for (int t = 0; t < 36; ++t) Hd[t] = H[t] + (t % 7 == 0 ? (double)lambda : 0.0);
     const bool ok = inverse6(Hd, Mi);
+#pragma unroll
     for (int t = 0; t < 36; ++t) {
         sys[t] = H[t];
         sys[42 + t] = ok ? Mi[t] : (t % 7 == 0 ? 1.0 : 0.0);
     }
+#pragma unroll
     for (int t = 0; t < 6; ++t) sys[36 + t] = g[t];
     if (!ok && rep) rep->flags |= MISSLAM_FLAG_NONSPD_BLOCK;
 }
@@ -225,11 +257,34 @@ struct JArgs {
     double *pst;
 };
 
-__device__ __forceinline__ double jgather(const JArgs &J, int it, int kind, double *lds) {
-    const double *p = J.jpart + (size_t)(it * kJKinds + kind) * J.A.nblk;
-    double s = 0.0;
-    for (int t = threadIdx.x; t < J.A.nblk; t += kJThreads) s += p[t];
-    return block_sum<kJThreads>(s, lds);
+// Sums N values over the block (wave butterflies, then the waves in order); every thread gets the totals.
+template <int N>
+__device__ __forceinline__ void block_sums(double (&v)[N], double (*lds)[kJThreads / kWave]) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        double t = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (lane == 0) lds[q][wave] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = ((lds[q][0] + lds[q][1]) + lds[q][2]) + lds[q][3];
+    __syncthreads();
+}
+
+// The block totals of N partial kinds: (iteration, kind) pairs its[q], kinds[q].
+template <int N>
+__device__ __forceinline__ void jgather(const JArgs &J, const int (&its)[N], const int (&kinds)[N], double (&out)[N],
+                                        double (*lds)[kJThreads / kWave]) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        out[q] = 0.0;
+        const double *p = J.jpart + (size_t)(its[q] * kJKinds + kinds[q]) * J.A.nblk;
+        for (int t = threadIdx.x; t < J.A.nblk; t += kJThreads) out[q] += p[t];
+    }
+    block_sums<N>(out, lds);
 }
 
 __device__ __forceinline__ float jprecond(const float *minv, int j, int a, const float *rl) {
@@ -242,7 +297,7 @@ __device__ __forceinline__ float jprecond(const float *minv, int j, int a, const
 
 __global__ void __launch_bounds__(kJThreads) jpcg_init_kernel(JArgs J) {
     const PcgArgs &A = J.A;
-    __shared__ double red[kJThreads];
+    __shared__ double red[16][kJThreads / kWave];
     __shared__ float rl[kJRows][12];
     const int row = threadIdx.x / 12, a = threadIdx.x % 12;
     const int j = blockIdx.x * kJRows + row;
@@ -259,8 +314,9 @@ __global__ void __launch_bounds__(kJThreads) jpcg_init_kernel(JArgs J) {
         A.z[(size_t)j * 12 + a] = z;
         A.x[(size_t)j * 12 + a] = 0.f;
     }
-    double rz = block_sum<kJThreads>((double)r * (double)z, red);
-    double rr = block_sum<kJThreads>((double)r * (double)r, red);
+    double sums[2] = {(double)r * (double)z, (double)r * (double)r};
+    block_sums<2>(sums, red);
+    double rz = sums[0], rr = sums[1];
     if (threadIdx.x == 0) {
         if (blockIdx.x == 0) {   // the pose part: r_p = -g_p, z_p = M_p r_p
             double rp[6], zp[6];
@@ -294,10 +350,12 @@ __global__ void __launch_bounds__(kJThreads) jpcg_init_kernel(JArgs J) {
 // q_e = H z_e + lambda z_e + B z_p + beta q_e, p_e = z_e + beta p_e; partials p_e.q_e and B^T z_e.
 __global__ void __launch_bounds__(kJThreads) jpcg_dir_kernel(JArgs J, int it) {
     const PcgArgs &A = J.A;
-    __shared__ double red[kJThreads];
+    __shared__ double red[16][kJThreads / kWave];
     __shared__ double zp[6];
-    const double rz = jgather(J, it, 0, red);
-    const double rz_prev = it > 0 ? jgather(J, it - 1, 0, red) : 1.0;
+    double gz[2];
+    jgather<2>(J, {it, it > 0 ? it - 1 : 0}, {0, 0}, gz, red);
+    const double rz = gz[0];
+    const double rz_prev = it > 0 ? gz[1] : 1.0;
     if (threadIdx.x < 6) zp[threadIdx.x] = J.pst[(size_t)it * kPst + 6 + threadIdx.x];
     __syncthreads();
     const bool skip = A.status[it] != 0 || rz == 0.0;
@@ -337,28 +395,28 @@ __global__ void __launch_bounds__(kJThreads) jpcg_dir_kernel(JArgs J, int it) {
         A.q[o] = q;
         pq = (double)p * (double)q;
     }
-    const double t = block_sum<kJThreads>(pq, red);
-    double bt[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) bt[k] = block_sum<kJThreads>(btz[k], red);
+    double sums[7] = {pq, btz[0], btz[1], btz[2], btz[3], btz[4], btz[5]};
+    block_sums<7>(sums, red);
     if (threadIdx.x == 0) {
-        J.jpart[(size_t)(it * kJKinds + 2) * A.nblk + blockIdx.x] = t;
-        for (int k = 0; k < 6; ++k) J.jpart[(size_t)(it * kJKinds + 4 + k) * A.nblk + blockIdx.x] = bt[k];
+        J.jpart[(size_t)(it * kJKinds + 2) * A.nblk + blockIdx.x] = sums[0];
+        for (int k = 0; k < 6; ++k) J.jpart[(size_t)(it * kJKinds + 4 + k) * A.nblk + blockIdx.x] = sums[1 + k];
     }
 }
 
 // The pose part of the product and the step, then the ED step: alpha = r.z / p.q over the joint vector.
 __global__ void __launch_bounds__(kJThreads) jpcg_step_kernel(JArgs J, int it) {
     const PcgArgs &A = J.A;
-    __shared__ double red[kJThreads];
+    __shared__ double red[16][kJThreads / kWave];
     __shared__ float rl[kJRows][12];
     __shared__ double ps[kPst];   // this iteration's pose r, z, p, q, x after the step
     __shared__ double pq_pose;
-    const double rz = jgather(J, it, 0, red);
-    const double rz_prev = it > 0 ? jgather(J, it - 1, 0, red) : 1.0;
-    const double pq_e = jgather(J, it, 2, red);
-    double btz[6];
-    for (int k = 0; k < 6; ++k) btz[k] = jgather(J, it, 4 + k, red);
+    const int ip = it > 0 ? it - 1 : 0;
+    double gs[9];
+    jgather<9>(J, {it, ip, it, it, it, it, it, it, it}, {0, 0, 2, 4, 5, 6, 7, 8, 9}, gs, red);
+    const double rz = gs[0];
+    const double rz_prev = it > 0 ? gs[1] : 1.0;
+    const double pq_e = gs[2];
+    const double btz[6] = {gs[3], gs[4], gs[5], gs[6], gs[7], gs[8]};
     const int st = A.status[it];
     const bool skip = st != 0 || rz == 0.0;
     const float beta = it > 0 ? (float)(rz / rz_prev) : 0.f;
@@ -417,9 +475,9 @@ __global__ void __launch_bounds__(kJThreads) jpcg_step_kernel(JArgs J, int it) {
             z = A.z[o];
         }
     }
-    double rzn = block_sum<kJThreads>((double)r * (double)z, red);
-    double rrn = block_sum<kJThreads>((double)r * (double)r, red);
-    double nb = block_sum<kJThreads>(bad, red);
+    double sums[3] = {(double)r * (double)z, (double)r * (double)r, bad};
+    block_sums<3>(sums, red);
+    double rzn = sums[0], rrn = sums[1], nb = sums[2];
     if (threadIdx.x == 0) {
         if (blockIdx.x == 0) {   // the pose step, stored for the next iteration
             double *nxt = J.pst + (size_t)(it + 1) * kPst;
@@ -455,8 +513,10 @@ __global__ void __launch_bounds__(kJThreads) jpcg_step_kernel(JArgs J, int it) {
 __global__ void __launch_bounds__(kJThreads) jpcg_finish_kernel(JArgs J, misslam_report *rep,
                                                                 float *__restrict__ params, float *pose_dev) {
     const PcgArgs &A = J.A;
-    __shared__ double red[kJThreads];
-    const double nbad = jgather(J, A.iters, 3, red);
+    __shared__ double red[16][kJThreads / kWave];
+    double nb1[1];
+    jgather<1>(J, {A.iters}, {3}, nb1, red);
+    const double nbad = nb1[0];
     const int total = A.m * 12;
     const int t = blockIdx.x * kJThreads + threadIdx.x;
     if (params && nbad == 0.0 && t < total) params[t] += A.x[t];
@@ -464,8 +524,9 @@ __global__ void __launch_bounds__(kJThreads) jpcg_finish_kernel(JArgs J, misslam
     int done = 0;
     for (int q = 0; q < A.iters; ++q) done += A.done[q];
     for (int q = 0; q <= done; ++q) {
-        const double rr = jgather(J, q, 1, red);
-        if (threadIdx.x == 0 && q <= MISSLAM_MAX_PCG) rep->pcg_resid[q] = sqrt(rr);
+        double rr[1];
+        jgather<1>(J, {q}, {1}, rr, red);
+        if (threadIdx.x == 0 && q <= MISSLAM_MAX_PCG) rep->pcg_resid[q] = sqrt(rr[0]);
     }
     if (threadIdx.x == 0) {
         rep->pcg_iters_done = done;
