@@ -16,6 +16,10 @@ inconsistent:
     with w_max = 20 (Sec. III-B; the 10 in Sec. II-G conflicts).
   * Registered points are stamped with the frame index.  Every point moves to
     its warped position; every node moves by its own translation, g_j + t_j.
+  * Eq.(13) (colour): a registered point's colour becomes the same weighted
+    mean of its colour and the frame's colour at the matched pixel,
+    c <- (w c + I(p)) / (w + 1), per channel, with the weight before the
+    Eq.(15) update; colours are view-independent (no rotation).
 Test infrastructure only (see the package header).
 """
 import numpy as np
@@ -46,12 +50,13 @@ def zbuffer(vc, inside, ui, vi, W, H):
 
 
 def fuse_warped(vw, nw, vc, nc, weight, stamp, depth, camera, R, T, Nmap, Nvalid, frame,
-                tau=10.0, cos_delta=float(np.cos(np.deg2rad(10.0))), w_max=20.0):
-    """Alg. 1-2 steps 2-3 and Eqs.(12), (14), (15) for an already warped model.
+                tau=10.0, cos_delta=float(np.cos(np.deg2rad(10.0))), w_max=20.0, color=None, image=None):
+    """Alg. 1-2 steps 2-3 and Eqs.(12)-(15) for an already warped model.
 
     vw, nw: warped points and unit normals in world coordinates; vc, nc: the same
-    in the camera frame.  Returns dict(points, normals, weight, stamp,
-    registered (N,) bool, reg (H*W,) winner per pixel).
+    in the camera frame.  color (N, 3) and image (H, W, 3), if given, take part
+    in Eq.(13).  Returns dict(points, normals, weight, stamp, registered (N,)
+    bool, reg (H*W,) winner per pixel[, color]).
     """
     W, H = camera[0], camera[1]
     Rm = np.asarray(R, dtype=np.float64)
@@ -79,11 +84,16 @@ def fuse_warped(vw, nw, vc, nc, weight, stamp, depth, camera, R, T, Nmap, Nvalid
     nn = nn / np.linalg.norm(nn, axis=1, keepdims=True)
     om_new = np.where(reg, np.minimum(om + 1.0, w_max), om)
     st_new = np.where(reg, frame, np.asarray(stamp))
-    return {"points": p_new, "normals": nn, "weight": om_new, "stamp": st_new, "registered": reg, "reg": win}
+    out = {"points": p_new, "normals": nn, "weight": om_new, "stamp": st_new, "registered": reg, "reg": win}
+    if color is not None:
+        c = np.asarray(color, dtype=np.float64)
+        Ip = np.asarray(image, dtype=np.float64)[vi, ui]
+        out["color"] = np.where(reg[:, None], (om[:, None] * c + Ip) / (om[:, None] + 1.0), c)
+    return out
 
 
 def fuse(points, normals, weight, stamp, nodes, params, idx, w, depth, camera, R, T, Nmap, Nvalid,
-         frame, tau=10.0, cos_delta=float(np.cos(np.deg2rad(10.0))), w_max=20.0):
+         frame, tau=10.0, cos_delta=float(np.cos(np.deg2rad(10.0))), w_max=20.0, color=None, image=None):
     """Deform the model with the frame's final parameters, then fuse (see fuse_warped).
 
     Also returns the moved nodes g_j + t_j.
@@ -93,7 +103,7 @@ def fuse(points, normals, weight, stamp, nodes, params, idx, w, depth, camera, R
     vw = ed_warp(points, nodes, params, idx, w)             # world
     nw = warp_normals(normals, params, idx, w)
     out = fuse_warped(vw, nw, vw @ Rm.T + Tv, nw @ Rm.T, weight, stamp, depth, camera, R, T, Nmap, Nvalid, frame,
-                      tau, cos_delta, w_max)
+                      tau, cos_delta, w_max, color, image)
     _, t = split(params)
     out["nodes"] = np.asarray(nodes, dtype=np.float64) + t
     return out

@@ -407,6 +407,39 @@ def test_fusion_weighted_average_on_ray():
     assert not out3["registered"][0] and out3["weight"][0] == 3.0 and out3["points"][0, 2] == 60.0
 
 
+def test_color_fusion_telescopes_to_the_observation():
+    """Eq.(13) on one point seen n times with the same colour I from weight w0 (below the cap): the recursion
+    c <- (w c + I)/(w + 1), w <- w + 1 telescopes to c_n = I + (c_0 - I) w0 / (w0 + n); an unregistered point
+    keeps its colour, and a constant colour is a fixed point."""
+    cam = (16, 12, 20.0, 20.0, 8.0, 6.0)
+    D = np.full((12, 16), 61.0)
+    Nm, ok = oracle.normal_map(D, cam)
+    u, v = 9, 7
+    p = np.array([[(u - 8) / 20 * 60.0, (v - 6) / 20 * 60.0, 60.0]])
+    nrm = np.array([[0.0, 0.0, -1.0]])
+    x = oracle.identity_params(1)
+    idx = np.zeros((1, 1), dtype=np.int64)
+    wk = np.ones((1, 1))
+    I = np.zeros((12, 16, 3))
+    I[v, u] = [0.9, 0.2, 0.5]
+    c0 = np.array([[0.1, 0.7, 0.5]])
+    w0 = 2.0
+    c, w, pts = c0.copy(), np.array([w0]), p.copy()
+    for it in range(5):
+        out = oracle.fuse(pts, nrm, w, np.array([0]), pts.copy(), x, idx, wk, D, cam, np.eye(3), np.zeros(3), Nm,
+                          ok, frame=it, color=c, image=I)
+        assert out["registered"][0]
+        c, w, pts = out["color"], out["weight"], out["points"]
+    want = I[v, u] + (c0[0] - I[v, u]) * w0 / (w0 + 5)
+    np.testing.assert_allclose(c[0], want, rtol=0, atol=1e-14)
+    assert c[0, 2] == 0.5
+    D3 = np.full((12, 16), 71.5)
+    Nm3, ok3 = oracle.normal_map(D3, cam)
+    out3 = oracle.fuse(p, nrm, np.array([3.0]), np.array([0]), p.copy(), x, idx, wk, D3, cam, np.eye(3), np.zeros(3),
+                       Nm3, ok3, frame=9, color=c0, image=I)
+    assert not out3["registered"][0] and np.array_equal(out3["color"], c0)
+
+
 def test_zbuffer_nearest_then_lowest_index():
     vc = np.array([[0, 0, 5.0], [0, 0, 4.0], [0, 0, 4.0], [0, 0, 9.0]])
     ui = np.array([1, 1, 1, 2])
