@@ -374,6 +374,20 @@ misslam_status misslam_lm_register(const misslam_points *points, misslam_nodes *
  * reg_map (height x width int32, winner point or -1) and registered (n int32,
  * 1/0) are optional outputs.
  */
+/*
+ * misslam_fuse with the colour of Eq.(13) fused too: a registered point's
+ * colour becomes (w c + I(p)) / (w + 1) per channel, with its weight before
+ * the Eq.(15) update and I(p) the frame's colour at its pixel; other points
+ * keep theirs.  image (device): height x width x 3 float32, interleaved;
+ * color (device, in/out): 3 x n float32, the r, g and b planes.  Everything
+ * else as misslam_fuse (bitwise the same outputs); MISSLAM_EINVAL for a NULL
+ * image or color when n > 0.
+ */
+misslam_status misslam_fuse_color(misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
+                                  const float *nmap, const misslam_camera *camera, const misslam_pose *pose,
+                                  const misslam_fuse_params *fp, const float *image, float *color, int32_t *reg_map,
+                                  int32_t *registered, void *ws, size_t ws_bytes, void *stream);
+
 misslam_status misslam_fuse(misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
                             const float *nmap, const misslam_camera *camera, const misslam_pose *pose,
                             const misslam_fuse_params *fp, int32_t *reg_map, int32_t *registered, void *ws,

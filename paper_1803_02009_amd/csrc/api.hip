@@ -668,10 +668,10 @@ misslam_status misslam_lm_register(const misslam_points *points, misslam_nodes *
                        stream);
 }
 
-misslam_status misslam_fuse(misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
-                            const float *nmap, const misslam_camera *camera, const misslam_pose *pose,
-                            const misslam_fuse_params *fp, int32_t *reg_map, int32_t *registered, void *ws,
-                            size_t ws_bytes, void *stream) {
+static misslam_status fuse_impl(misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
+                                const float *nmap, const misslam_camera *camera, const misslam_pose *pose,
+                                const misslam_fuse_params *fp, const float *image, float *color, int32_t *reg_map,
+                                int32_t *registered, void *ws, size_t ws_bytes, void *stream) {
     if (!valid_points(points) || !valid_nodes(nodes) || !valid_graph(graph, points->n) || !nmap ||
         !valid_camera(camera) || !pose || !fp || !ws || (points->n > 0 && (!points->w || !points->stamp)) ||
         !std::isfinite(fp->tau) || !std::isfinite(fp->cos_delta) || !(fp->w_max > 0.f))
@@ -707,10 +707,29 @@ misslam_status misslam_fuse(misslam_points *points, misslam_nodes *nodes, const 
     f.tmp = L.fuse_tmp;
     f.pix = L.fuse_pix;
     f.zbuf = L.zbuf;
+    f.image = image;
+    f.color = color;
     Timed t(PH_FUSE, stream_of(stream));
     const hipError_t e = msl::launch_fuse(f, nodes->gx, nodes->gy, nodes->gz, nodes->params, nodes->m, reg_map,
                                           stream_of(stream));
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
+}
+
+misslam_status misslam_fuse(misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
+                            const float *nmap, const misslam_camera *camera, const misslam_pose *pose,
+                            const misslam_fuse_params *fp, int32_t *reg_map, int32_t *registered, void *ws,
+                            size_t ws_bytes, void *stream) {
+    return fuse_impl(points, nodes, graph, nmap, camera, pose, fp, nullptr, nullptr, reg_map, registered, ws,
+                     ws_bytes, stream);
+}
+
+misslam_status misslam_fuse_color(misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
+                                  const float *nmap, const misslam_camera *camera, const misslam_pose *pose,
+                                  const misslam_fuse_params *fp, const float *image, float *color, int32_t *reg_map,
+                                  int32_t *registered, void *ws, size_t ws_bytes, void *stream) {
+    if (points && points->n > 0 && (!image || !color)) return MISSLAM_EINVAL;
+    return fuse_impl(points, nodes, graph, nmap, camera, pose, fp, image, color, reg_map, registered, ws, ws_bytes,
+                     stream);
 }
 
 misslam_status misslam_energy_vjp(const misslam_points *points, const misslam_nodes *nodes,

@@ -236,6 +236,8 @@ struct FuseArgs {
     float *tmp;                    // 6 x n: world warp and unnormalised warped normal
     int32_t *pix;                  // n
     unsigned long long *zbuf;      // H x W
+    const float *image = nullptr;  // optional H x W x 3 colour of the frame (Eq.(13))
+    float *color = nullptr;        // optional 3 x n point colours (planes r, g, b), in/out
 };
 
 hipError_t launch_fuse(const FuseArgs &f, float *gx, float *gy, float *gz, float *params, int m, int32_t *reg_map,

@@ -81,6 +81,14 @@ __global__ void __launch_bounds__(256) fuse_update_kernel(FuseArgs f) {
     }
     float w = f.w_in[i];
     int st = f.stamp_in[i];
+    if (reg && f.color) {   // Eq.(13): the same weighted mean of the colour, with the weight before Eq.(15)
+        const double om = w, den = om + 1.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float *cc = f.color + (size_t)c * n + i;
+            *cc = (float)((om * (double)*cc + (double)f.image[(size_t)pix * 3 + c]) / den);
+        }
+    }
     if (reg) {
         const int u = pix % f.cam.W, v = pix / f.cam.W;
         const double d = q.w;

@@ -302,8 +302,9 @@ def fuse_params(frame, tau=10.0, cos_delta=math.cos(math.radians(10.0)), w_max=2
     return _lib.FuseParams(float(tau), float(cos_delta), float(w_max), int(frame))
 
 
-def fuse(points, w, stamp, nodes, x, graph, nmap, cam, pose_, fp, ws, outputs=False):
+def fuse(points, w, stamp, nodes, x, graph, nmap, cam, pose_, fp, ws, outputs=False, image=None, color=None):
     """Deforms and fuses in place: points (6, N), w (N), stamp (N int32), nodes (3, m) and x (reset to identity).
+    With image (H, W, 3) and color (3, N) float32, the point colours are fused too (Eq.(13)), in place.
 
     Returns (reg_map (H, W) int32, registered (N,) int32) when outputs=True.
     """
@@ -313,10 +314,20 @@ def fuse(points, w, stamp, nodes, x, graph, nmap, cam, pose_, fp, ws, outputs=Fa
     reg = torch.empty((cam.height, cam.width), dtype=torch.int32, device=points.device) if outputs else None
     regd = torch.empty(max(n, 1), dtype=torch.int32, device=points.device) if outputs else None
     buf = ws.get(workspace_bytes(n, m, cam.width, cam.height, Params()))
-    check("misslam_fuse", load().misslam_fuse(
-        ctypes.byref(points_struct(points, w, stamp)), ctypes.byref(nodes_struct(nodes, x)), ctypes.byref(graph.c()),
-        _ptr(nmap), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(fp), _ptr(reg), _ptr(regd), _ptr(buf),
-        ctypes.c_size_t(buf.numel()), _stream()))
+    if image is None and color is None:
+        check("misslam_fuse", load().misslam_fuse(
+            ctypes.byref(points_struct(points, w, stamp)), ctypes.byref(nodes_struct(nodes, x)),
+            ctypes.byref(graph.c()), _ptr(nmap), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(fp), _ptr(reg),
+            _ptr(regd), _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
+    else:
+        _need(image, torch.float32, "image")
+        _need(color, torch.float32, "color")
+        if tuple(image.shape) != (cam.height, cam.width, 3) or tuple(color.shape) != (3, n):
+            raise ValueError("image must be (H, W, 3) and color (3, N)")
+        check("misslam_fuse_color", load().misslam_fuse_color(
+            ctypes.byref(points_struct(points, w, stamp)), ctypes.byref(nodes_struct(nodes, x)),
+            ctypes.byref(graph.c()), _ptr(nmap), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(fp),
+            _ptr(image), _ptr(color), _ptr(reg), _ptr(regd), _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
     return (reg, regd[:n]) if outputs else None
 
 

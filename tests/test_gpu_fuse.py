@@ -71,3 +71,43 @@ def test_fuse_after_registration_end_to_end(lib):
     # fusion moves registered points a quarter of the way (w = 3) toward the noisy observation
     assert np.all(w.cpu().numpy()[regg] == 4.0) and np.all(st.cpu().numpy()[regg] == 1)
     assert np.isfinite(after).all() and after.mean() < before.mean() + 0.05
+
+
+def test_fuse_color_matches_oracle(lib):
+    """Eq.(13): registered points' colours are the weighted mean of theirs and the frame's colour at the pixel;
+    positions, normals, weights and stamps are those of the colourless fusion, bit for bit."""
+    import gen
+    s = Scene("c2")
+    rng = np.random.default_rng(9)
+    xg = random_params(s.m, 43, 0.003, 0.3)
+    x = torch.tensor(xg, device="cuda")
+    vw, nw = s.M.warp(s.pts, s.nodes, x, s.graph, None)
+    vc, nc = s.M.warp(s.pts, s.nodes, x, s.graph, s.pose)
+    w0 = rng.integers(1, 21, s.n).astype(np.float32)
+    st0 = rng.integers(0, 5, s.n).astype(np.int32)
+    img = gen.color_image(s.cam.height, s.cam.width, seed=3)
+    col0 = gen.point_colors(s.n, seed=4)
+    nmap = s.M.normal_map(s.depth, s.cam)
+    runs = []
+    for with_color in (False, True):
+        pts2, nodes2, x2 = s.pts.clone(), s.nodes.clone(), x.clone()
+        w = torch.tensor(w0, device="cuda")
+        st = torch.tensor(st0, device="cuda")
+        col = torch.tensor(np.ascontiguousarray(col0.T), device="cuda")
+        kw = dict(image=torch.tensor(img, device="cuda"), color=col) if with_color else {}
+        reg, regd = s.M.fuse(pts2, w, st, nodes2, x2, s.graph, nmap, s.cam, s.pose, s.M.fuse_params(7), s.ws,
+                             outputs=True, **kw)
+        torch.cuda.synchronize()
+        runs.append((pts2.cpu().numpy(), w.cpu().numpy(), st.cpu().numpy(), regd.cpu().numpy(), col.cpu().numpy()))
+    for a, b in zip(runs[0][:4], runs[1][:4]):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    Nm, ok = oracle.normal_map(s.sc["depth"], s.sc["camera"])
+    out = oracle.fuse_warped(vw.cpu().numpy().T, nw.cpu().numpy().T, vc.cpu().numpy().T, nc.cpu().numpy().T,
+                             w0, st0, s.sc["depth"], s.sc["camera"], s.sc["R"], s.sc["T"], Nm.astype(np.float32), ok,
+                             7, color=col0, image=img)
+    regg = runs[1][3].astype(bool)
+    assert np.array_equal(regg, out["registered"]) and regg.sum() > 0.2 * s.n
+    C = runs[1][4].T
+    assert np.abs(C[regg] - out["color"][regg]).max() <= 1e-6
+    assert np.array_equal(C[~regg], col0[~regg])
+    assert np.abs(C[regg] - col0[regg]).max() > 0.01
