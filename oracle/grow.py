@@ -23,6 +23,9 @@ Readings where the paper is silent or loose:
     the old ones in ascending (kz, ky, kx) order of their voxel.  kNN sets,
     N(j) and the pattern are rebuilt by the next frame's graph setup, and the
     parameters restart at identity.
+  * Colour (Eq.(13)), when the model carries it: survivors keep theirs, a
+    lifted point takes the frame's colour at its pixel, a merged voxel the
+    mean of its members' colours (float64, ascending index).
 Test infrastructure only (see the package header).
 """
 import numpy as np
@@ -52,10 +55,10 @@ def _groups(keys):
 
 
 def grow(points, normals, weight, stamp, registered, reg, depth, camera, R, T, Nmap, Nvalid, frame, nodes,
-         node_spacing, voxel=0.22, tau_time=10, tau_weight=2.0):
+         node_spacing, voxel=0.22, tau_time=10, tau_weight=2.0, color=None, image=None):
     """Alg. 2 steps 3-5 and Alg. 3 on a fused model.  Returns dict(points, normals,
     weight, stamp (float32/int arrays of the new model), nodes (old + new),
-    lifted, culled, merged (counts))."""
+    lifted, culled, merged (counts)[, color])."""
     P = np.asarray(points, dtype=np.float64)
     Nn = np.asarray(normals, dtype=np.float64)
     w = np.asarray(weight, dtype=np.float64)
@@ -87,6 +90,10 @@ def grow(points, normals, weight, stamp, registered, reg, depth, camera, R, T, N
     nrm = np.concatenate([Nn[keep].astype(np.float32), ln])
     wt = np.concatenate([w[keep], np.ones(len(lp))]).astype(np.float32)
     stp = np.concatenate([st[keep], np.full(len(lp), frame, dtype=np.int64)])
+    col = None
+    if color is not None:
+        col = np.concatenate([np.asarray(color, dtype=np.float32)[keep],
+                              np.asarray(image, dtype=np.float32).reshape(-1, 3)[lift]])
 
     # down-sampling of touched voxels (Alg. 3)
     alive = np.ones(len(pts), dtype=bool)
@@ -109,9 +116,17 @@ def grow(points, normals, weight, stamp, registered, reg, depth, camera, R, T, N
                 np.float32)
             wt[lead] = wt[members].max()
             stp[lead] = stp[members].max()
+            if col is not None:
+                cm = col[members].astype(np.float64)
+                cs = np.zeros(3)
+                for q in range(len(members)):
+                    cs = cs + cm[q]
+                col[lead] = (cs / len(members)).astype(np.float32)
             alive[members[1:]] = False
             merged += len(members) - 1
     pts, nrm, wt, stp = pts[alive], nrm[alive], wt[alive], stp[alive]
+    if col is not None:
+        col = col[alive]
 
     # node regeneration (Alg. 2 step 5)
     G = np.asarray(nodes, dtype=np.float32)
@@ -132,6 +147,8 @@ def grow(points, normals, weight, stamp, registered, reg, depth, camera, R, T, N
                     continue
             new_nodes.append(c.astype(np.float32))
     nodes_out = np.concatenate([G, np.array(new_nodes, dtype=np.float32).reshape(-1, 3)])
-    return {"points": pts, "normals": nrm, "weight": wt, "stamp": stp, "nodes": nodes_out,
-            "lifted": int(lift.sum()), "culled": int((~keep).sum()), "merged": merged,
-            "new_nodes": len(new_nodes)}
+    out = {"points": pts, "normals": nrm, "weight": wt, "stamp": stp, "nodes": nodes_out,
+           "lifted": int(lift.sum()), "culled": int((~keep).sum()), "merged": merged, "new_nodes": len(new_nodes)}
+    if col is not None:
+        out["color"] = col
+    return out

@@ -90,6 +90,33 @@ def test_voxel_merge_only_in_touched_voxels():
     np.testing.assert_array_equal(out["points"][1:], p[[2, 3, 4]])
 
 
+def test_colour_follows_lift_merge_and_removal():
+    """Survivors keep their colour, lifted points take the pixel's colour, a merged voxel the mean of its
+    members', removed points' colours leave with them (Eq.(13) carried through Alg. 2-3)."""
+    D, N, ok = _frame()
+    ok[:] = False
+    ok[1, 2] = True                                 # only pixel (u=2, v=1) can be lifted
+    p, nrm = _model(5)
+    p[:] = [[0.05, 0.05, 50.01], [0.15, 0.10, 50.02],   # one touched voxel (point 1 stamped this frame)
+            [3.0, 3.0, 50.0],                           # alone, kept
+            [9.0, 9.0, 50.0],                           # old and light: removed
+            [0.20, 0.01, 50.03]]                        # joins the first voxel
+    w = np.array([3, 4, 5, 1, 2], np.float32)
+    st = np.array([5, 9, 8, -5, 7])
+    col = np.array([[0.1, 0.2, 0.3], [0.5, 0.6, 0.7], [0.9, 0.8, 0.7], [0.0, 0.0, 1.0], [0.3, 0.1, 0.2]],
+                   np.float32)
+    img = np.zeros((3, 4, 3), np.float32)
+    img[1, 2] = [0.25, 0.5, 0.75]
+    out = oracle.grow(p, nrm, w, st, np.zeros(5, bool), np.full(12, -1), D, CAM, I3, Z3, N, ok, 9,
+                      np.zeros((0, 3), np.float32), 1000.0, voxel=0.22, color=col, image=img)
+    assert out["culled"] == 1 and out["lifted"] == 1 and out["merged"] == 2
+    c = out["color"]
+    assert len(c) == len(out["points"]) == 3
+    np.testing.assert_allclose(c[0], col[[0, 1, 4]].astype(np.float64).mean(axis=0), atol=1e-7)
+    np.testing.assert_array_equal(c[1], col[2])
+    np.testing.assert_array_equal(c[2], img[1, 2])
+
+
 def test_node_regeneration():
     D, N, ok = _frame(0.0)
     p, nrm = _model(4)
