@@ -379,14 +379,16 @@ misslam_status misslam_lm_register(const misslam_points *points, misslam_nodes *
  * colour becomes (w c + I(p)) / (w + 1) per channel, with its weight before
  * the Eq.(15) update and I(p) the frame's colour at its pixel; other points
  * keep theirs.  image (device): height x width x 3 float32, interleaved;
- * color (device, in/out): 3 x n float32, the r, g and b planes.  Everything
- * else as misslam_fuse (bitwise the same outputs); MISSLAM_EINVAL for a NULL
- * image or color when n > 0.
+ * color (device, in/out): the r, g and b planes of the point colours at color,
+ * color + color_stride and color + 2 color_stride (color_stride >= n).
+ * Everything else as misslam_fuse (bitwise the same outputs); MISSLAM_EINVAL
+ * for a NULL image or color, or a short stride, when n > 0.
  */
 misslam_status misslam_fuse_color(misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
                                   const float *nmap, const misslam_camera *camera, const misslam_pose *pose,
-                                  const misslam_fuse_params *fp, const float *image, float *color, int32_t *reg_map,
-                                  int32_t *registered, void *ws, size_t ws_bytes, void *stream);
+                                  const misslam_fuse_params *fp, const float *image, float *color,
+                                  int64_t color_stride, int32_t *reg_map, int32_t *registered, void *ws,
+                                  size_t ws_bytes, void *stream);
 
 misslam_status misslam_fuse(misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
                             const float *nmap, const misslam_camera *camera, const misslam_pose *pose,
@@ -455,6 +457,22 @@ misslam_status misslam_grow(misslam_points *points, misslam_nodes *nodes, const 
                             const int32_t *registered, const float *nmap, const misslam_camera *camera,
                             const misslam_pose *pose, const misslam_grow_params *gp, int64_t *counts_out, void *ws,
                             size_t ws_bytes, void *stream);
+
+/*
+ * misslam_grow carrying the point colours of Eq.(13) along: survivors keep
+ * theirs, a lifted point takes the frame's colour at its pixel, a merged
+ * voxel the mean of its members' colours (float64, ascending index).  image
+ * (device): height x width x 3 float32, interleaved; color (device, in/out):
+ * the r, g, b planes at color, color + color_stride, color + 2 color_stride,
+ * each of points->capacity entries (color_stride >= capacity).  Everything
+ * else as misslam_grow (bitwise the same outputs); MISSLAM_EINVAL for a NULL
+ * image or color or a short stride.
+ */
+misslam_status misslam_grow_color(misslam_points *points, misslam_nodes *nodes, const int32_t *reg_map,
+                                  const int32_t *registered, const float *nmap, const misslam_camera *camera,
+                                  const misslam_pose *pose, const misslam_grow_params *gp, const float *image,
+                                  float *color, int64_t color_stride, int64_t *counts_out, void *ws, size_t ws_bytes,
+                                  void *stream);
 
 /* ------------------------------------------------------------------ uneven batches */
 

@@ -124,8 +124,10 @@ SIGNATURES = {
                                     vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "misslam_lm_register": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params), P(Keypoints),
                                  P(LMParams), vp, vp, vp, ctypes.c_size_t, vp]),
-    "misslam_fuse_color": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(FuseParams), vp, vp, vp,
-                                vp, vp, ctypes.c_size_t, vp]),
+    "misslam_fuse_color": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(FuseParams), vp, vp,
+                                ctypes.c_int64, vp, vp, vp, ctypes.c_size_t, vp]),
+    "misslam_grow_color": (st, [P(Points), P(Nodes), vp, vp, vp, P(Camera), P(Pose), P(GrowParams), vp, vp,
+                                ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]),
     "misslam_fuse": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(FuseParams), vp, vp, vp,
                           ctypes.c_size_t, vp]),
     "misslam_energy_vjp": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params), vp, vp, vp, vp,

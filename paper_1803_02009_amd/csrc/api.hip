@@ -670,8 +670,9 @@ misslam_status misslam_lm_register(const misslam_points *points, misslam_nodes *
 
 static misslam_status fuse_impl(misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
                                 const float *nmap, const misslam_camera *camera, const misslam_pose *pose,
-                                const misslam_fuse_params *fp, const float *image, float *color, int32_t *reg_map,
-                                int32_t *registered, void *ws, size_t ws_bytes, void *stream) {
+                                const misslam_fuse_params *fp, const float *image, float *color,
+                                int64_t color_stride, int32_t *reg_map, int32_t *registered, void *ws,
+                                size_t ws_bytes, void *stream) {
     if (!valid_points(points) || !valid_nodes(nodes) || !valid_graph(graph, points->n) || !nmap ||
         !valid_camera(camera) || !pose || !fp || !ws || (points->n > 0 && (!points->w || !points->stamp)) ||
         !std::isfinite(fp->tau) || !std::isfinite(fp->cos_delta) || !(fp->w_max > 0.f))
@@ -709,6 +710,7 @@ static misslam_status fuse_impl(misslam_points *points, misslam_nodes *nodes, co
     f.zbuf = L.zbuf;
     f.image = image;
     f.color = color;
+    f.color_stride = color_stride;
     Timed t(PH_FUSE, stream_of(stream));
     const hipError_t e = msl::launch_fuse(f, nodes->gx, nodes->gy, nodes->gz, nodes->params, nodes->m, reg_map,
                                           stream_of(stream));
@@ -719,17 +721,18 @@ misslam_status misslam_fuse(misslam_points *points, misslam_nodes *nodes, const 
                             const float *nmap, const misslam_camera *camera, const misslam_pose *pose,
                             const misslam_fuse_params *fp, int32_t *reg_map, int32_t *registered, void *ws,
                             size_t ws_bytes, void *stream) {
-    return fuse_impl(points, nodes, graph, nmap, camera, pose, fp, nullptr, nullptr, reg_map, registered, ws,
+    return fuse_impl(points, nodes, graph, nmap, camera, pose, fp, nullptr, nullptr, 0, reg_map, registered, ws,
                      ws_bytes, stream);
 }
 
 misslam_status misslam_fuse_color(misslam_points *points, misslam_nodes *nodes, const misslam_graph *graph,
                                   const float *nmap, const misslam_camera *camera, const misslam_pose *pose,
-                                  const misslam_fuse_params *fp, const float *image, float *color, int32_t *reg_map,
-                                  int32_t *registered, void *ws, size_t ws_bytes, void *stream) {
-    if (points && points->n > 0 && (!image || !color)) return MISSLAM_EINVAL;
-    return fuse_impl(points, nodes, graph, nmap, camera, pose, fp, image, color, reg_map, registered, ws, ws_bytes,
-                     stream);
+                                  const misslam_fuse_params *fp, const float *image, float *color,
+                                  int64_t color_stride, int32_t *reg_map, int32_t *registered, void *ws,
+                                  size_t ws_bytes, void *stream) {
+    if (points && points->n > 0 && (!image || !color || color_stride < points->n)) return MISSLAM_EINVAL;
+    return fuse_impl(points, nodes, graph, nmap, camera, pose, fp, image, color, color_stride, reg_map, registered,
+                     ws, ws_bytes, stream);
 }
 
 misslam_status misslam_energy_vjp(const misslam_points *points, const misslam_nodes *nodes,
@@ -804,6 +807,7 @@ struct GrowLayout {
     msl::GrowScratch s;
     float *stage;
     int32_t *stage_stamp;
+    float *stage_color;
     size_t bytes;
 };
 
@@ -829,6 +833,7 @@ GrowLayout carve_grow(void *ws, int64_t n, int32_t W, int32_t H) {
     L.s.v0 = c.take<uint32_t>((size_t)Cb);
     L.s.v1 = c.take<uint32_t>((size_t)Cb);
     L.s.cent = c.take<float>((size_t)3 * Cb);
+    L.stage_color = c.take<float>((size_t)3 * Cb);
     L.bytes = align_up(c.off);
     return L;
 }
@@ -842,10 +847,11 @@ size_t misslam_grow_workspace_bytes(int64_t n, int32_t width, int32_t height) {
     return carve_grow(nullptr, n, width, height).bytes;
 }
 
-misslam_status misslam_grow(misslam_points *points, misslam_nodes *nodes, const int32_t *reg_map,
-                            const int32_t *registered, const float *nmap, const misslam_camera *camera,
-                            const misslam_pose *pose, const misslam_grow_params *gp, int64_t *counts_out, void *ws,
-                            size_t ws_bytes, void *stream) {
+static misslam_status grow_impl(misslam_points *points, misslam_nodes *nodes, const int32_t *reg_map,
+                                const int32_t *registered, const float *nmap, const misslam_camera *camera,
+                                const misslam_pose *pose, const misslam_grow_params *gp, const float *image,
+                                float *color, int64_t color_stride, int64_t *counts_out, void *ws, size_t ws_bytes,
+                                void *stream) {
     if (!points || points->n < 0 || points->n > points->capacity || !points->px || !points->py || !points->pz ||
         !points->nx || !points->ny || !points->nz || !points->w || !points->stamp || !nodes || nodes->m < 0 ||
         nodes->m > nodes->capacity || !nodes->gx || !nodes->gy || !nodes->gz || !nodes->params || !reg_map ||
@@ -889,10 +895,32 @@ misslam_status misslam_grow(misslam_points *points, misslam_nodes *nodes, const 
     g.stage_stamp = L.stage_stamp;
     g.stage_cap = C;
     g.count = L.s.count;
+    g.image = image;
+    g.color = color;
+    g.color_stride = color_stride;
+    g.stage_color = L.stage_color;
     const hipStream_t st = stream_of(stream);
     Timed t(PH_GROW, st);
     const hipError_t e = msl::launch_grow(g, L.s, counts_out, st);
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
+}
+
+misslam_status misslam_grow(misslam_points *points, misslam_nodes *nodes, const int32_t *reg_map,
+                            const int32_t *registered, const float *nmap, const misslam_camera *camera,
+                            const misslam_pose *pose, const misslam_grow_params *gp, int64_t *counts_out, void *ws,
+                            size_t ws_bytes, void *stream) {
+    return grow_impl(points, nodes, reg_map, registered, nmap, camera, pose, gp, nullptr, nullptr, 0, counts_out, ws,
+                     ws_bytes, stream);
+}
+
+misslam_status misslam_grow_color(misslam_points *points, misslam_nodes *nodes, const int32_t *reg_map,
+                                  const int32_t *registered, const float *nmap, const misslam_camera *camera,
+                                  const misslam_pose *pose, const misslam_grow_params *gp, const float *image,
+                                  float *color, int64_t color_stride, int64_t *counts_out, void *ws, size_t ws_bytes,
+                                  void *stream) {
+    if (!points || !image || !color || color_stride < points->capacity) return MISSLAM_EINVAL;
+    return grow_impl(points, nodes, reg_map, registered, nmap, camera, pose, gp, image, color, color_stride,
+                     counts_out, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

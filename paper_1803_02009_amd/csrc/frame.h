@@ -208,6 +208,12 @@ struct GrowArgs {
     int32_t *stage_stamp;
     int64_t stage_cap;        // n + W H
     const int32_t *count;     // device: [0] staged points, [1] kept, [2] final, [3] new nodes
+    // optional colour (Eq.(13)): the frame's H x W x 3 image, the point colours (planes r, g, b, color_stride
+    // apart, capacity each) and 3 staging planes of stage_cap
+    const float *image = nullptr;
+    float *color = nullptr;
+    int64_t color_stride = 0;
+    float *stage_color = nullptr;
 };
 
 struct GrowScratch {
@@ -237,7 +243,8 @@ struct FuseArgs {
     int32_t *pix;                  // n
     unsigned long long *zbuf;      // H x W
     const float *image = nullptr;  // optional H x W x 3 colour of the frame (Eq.(13))
-    float *color = nullptr;        // optional 3 x n point colours (planes r, g, b), in/out
+    float *color = nullptr;        // optional point colours (planes r, g, b, color_stride apart), in/out
+    int64_t color_stride = 0;
 };
 
 hipError_t launch_fuse(const FuseArgs &f, float *gx, float *gy, float *gz, float *params, int m, int32_t *reg_map,

@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(256) fuse_update_kernel(FuseArgs f) {
         const double om = w, den = om + 1.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            float *cc = f.color + (size_t)c * n + i;
+            float *cc = f.color + (size_t)c * f.color_stride + i;
             *cc = (float)((om * (double)*cc + (double)f.image[(size_t)pix * 3 + c]) / den);
         }
     }

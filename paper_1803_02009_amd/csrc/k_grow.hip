@@ -206,6 +206,9 @@ __global__ void __launch_bounds__(kGrowBlock) grow_scatter_kernel(GrowArgs g, co
         S[5 * C + pos] = g.nz[e];
         S[6 * C + pos] = g.w[e];
         g.stage_stamp[pos] = g.stamp[e];
+        if (g.color)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) g.stage_color[c * C + pos] = g.color[c * g.color_stride + e];
     } else {
         const int64_t t = e - n;
         const int u = (int)(t % g.cam.W), v = (int)(t / g.cam.W);
@@ -223,6 +226,9 @@ __global__ void __launch_bounds__(kGrowBlock) grow_scatter_kernel(GrowArgs g, co
         }
         S[6 * C + pos] = 1.f;
         g.stage_stamp[pos] = g.frame;
+        if (g.color)   // a lifted point takes the frame's colour at its pixel
+#pragma unroll
+            for (int c = 0; c < 3; ++c) g.stage_color[c * C + pos] = g.image[t * 3 + c];
     }
 }
 
@@ -256,7 +262,7 @@ __global__ void __launch_bounds__(kGrowBlock) merge_kernel(GrowArgs g, const uns
     bool touched = false;
     for (int64_t j = i; j < j1; ++j) touched = touched || g.stage_stamp[idx[j]] == g.frame;
     if (!touched || j1 - i < 2) return;
-    double ps[3] = {0.0, 0.0, 0.0}, ns[3] = {0.0, 0.0, 0.0};
+    double ps[3] = {0.0, 0.0, 0.0}, ns[3] = {0.0, 0.0, 0.0}, cs[3] = {0.0, 0.0, 0.0};
     float wmax = -__builtin_huge_valf();
     int smax = -2147483647 - 1;
     for (int64_t j = i; j < j1; ++j) {   // ascending index
@@ -265,6 +271,7 @@ __global__ void __launch_bounds__(kGrowBlock) merge_kernel(GrowArgs g, const uns
         for (int a = 0; a < 3; ++a) {
             ps[a] += (double)S[a * C + q];
             ns[a] += (double)S[(3 + a) * C + q];
+            if (g.color) cs[a] += (double)g.stage_color[a * C + q];
         }
         wmax = fmaxf(wmax, S[6 * C + q]);
         smax = max(smax, g.stage_stamp[q]);
@@ -283,6 +290,9 @@ __global__ void __launch_bounds__(kGrowBlock) merge_kernel(GrowArgs g, const uns
     for (int a = 0; a < 3; ++a) S[(3 + a) * C + lead] = (float)(nm[a] / nn);
     S[6 * C + lead] = wmax;
     g.stage_stamp[lead] = smax;
+    if (g.color)   // mean colour of the voxel
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g.stage_color[a * C + lead] = (float)(cs[a] / cnt);
 }
 
 __global__ void __launch_bounds__(kGrowBlock) alive_init_kernel(int32_t *__restrict__ alive, const int32_t *count,
@@ -312,6 +322,9 @@ __global__ void __launch_bounds__(kGrowBlock) final_scatter_kernel(GrowArgs g, c
     g.nz[pos] = S[5 * C + i];
     g.w[pos] = S[6 * C + i];
     g.stamp[pos] = g.stage_stamp[i];
+    if (g.color)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g.color[c * g.color_stride + pos] = g.stage_color[c * C + i];
 }
 
 // One thread per node-voxel group start: centroid (float64, ascending index)

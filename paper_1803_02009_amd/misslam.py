@@ -304,7 +304,8 @@ def fuse_params(frame, tau=10.0, cos_delta=math.cos(math.radians(10.0)), w_max=2
 
 def fuse(points, w, stamp, nodes, x, graph, nmap, cam, pose_, fp, ws, outputs=False, image=None, color=None):
     """Deforms and fuses in place: points (6, N), w (N), stamp (N int32), nodes (3, m) and x (reset to identity).
-    With image (H, W, 3) and color (3, N) float32, the point colours are fused too (Eq.(13)), in place.
+    With image (H, W, 3) and color (3, >= N) float32 (contiguous rows), the point colours are fused too
+    (Eq.(13)), in place.
 
     Returns (reg_map (H, W) int32, registered (N,) int32) when outputs=True.
     """
@@ -320,14 +321,12 @@ def fuse(points, w, stamp, nodes, x, graph, nmap, cam, pose_, fp, ws, outputs=Fa
             ctypes.byref(graph.c()), _ptr(nmap), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(fp), _ptr(reg),
             _ptr(regd), _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
     else:
-        _need(image, torch.float32, "image")
-        _need(color, torch.float32, "color")
-        if tuple(image.shape) != (cam.height, cam.width, 3) or tuple(color.shape) != (3, n):
-            raise ValueError("image must be (H, W, 3) and color (3, N)")
+        stride = _color_stride(image, color, cam, n)
         check("misslam_fuse_color", load().misslam_fuse_color(
             ctypes.byref(points_struct(points, w, stamp)), ctypes.byref(nodes_struct(nodes, x)),
             ctypes.byref(graph.c()), _ptr(nmap), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(fp),
-            _ptr(image), _ptr(color), _ptr(reg), _ptr(regd), _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
+            _ptr(image), _ptr(color), ctypes.c_int64(stride), _ptr(reg), _ptr(regd), _ptr(buf),
+            ctypes.c_size_t(buf.numel()), _stream()))
     return (reg, regd[:n]) if outputs else None
 
 
@@ -336,12 +335,23 @@ def grow_params(frame, node_spacing, voxel=0.22, tau_weight=2.0, tau_time=10):
     return _lib.GrowParams(float(voxel), float(node_spacing), float(tau_weight), int(tau_time), int(frame))
 
 
-def grow(points, w, stamp, n, nodes, x, m, reg_map, registered, nmap, cam, pose_, gp, ws):
+def _color_stride(image, color, cam, n):
+    _need(image, torch.float32, "image")
+    if tuple(image.shape) != (cam.height, cam.width, 3):
+        raise ValueError("image must be (H, W, 3)")
+    _need_rows(color, torch.float32, "color")
+    if color.shape[0] != 3 or color.shape[1] < n:
+        raise ValueError("color must be (3, >= N)")
+    return color.stride(0)
+
+
+def grow(points, w, stamp, n, nodes, x, m, reg_map, registered, nmap, cam, pose_, gp, ws, image=None, color=None):
     """Growth and maintenance after fuse (misslam_grow).
 
     points (6, capacity), w, stamp (capacity), nodes (3, node_capacity), x (node_capacity, 12): the model with
-    n points and m nodes in use; rewritten in place.  Returns the device counts tensor (7,) int64:
-    new n, new m, lifted, removed, merged away, new nodes, overflow.
+    n points and m nodes in use; rewritten in place.  With image (H, W, 3) and color (3, capacity) the point
+    colours follow (misslam_grow_color).  Returns the device counts tensor (7,) int64: new n, new m, lifted,
+    removed, merged away, new nodes, overflow.
     """
     counts = torch.zeros(7, dtype=torch.int64, device=points.device)
     cap = points.shape[1]
@@ -351,9 +361,17 @@ def grow(points, w, stamp, n, nodes, x, m, reg_map, registered, nmap, cam, pose_
     nstruct.m = int(m)
     nstruct.capacity = nodes.shape[1]
     buf = ws.get(load().misslam_grow_workspace_bytes(int(n), cam.width, cam.height))
-    check("misslam_grow", load().misslam_grow(
-        ctypes.byref(pstruct), ctypes.byref(nstruct), _ptr(reg_map), _ptr(registered), _ptr(nmap), ctypes.byref(cam),
-        ctypes.byref(pose_), ctypes.byref(gp), _ptr(counts), _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
+    if image is None and color is None:
+        check("misslam_grow", load().misslam_grow(
+            ctypes.byref(pstruct), ctypes.byref(nstruct), _ptr(reg_map), _ptr(registered), _ptr(nmap),
+            ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(gp), _ptr(counts), _ptr(buf),
+            ctypes.c_size_t(buf.numel()), _stream()))
+    else:
+        stride = _color_stride(image, color, cam, cap)
+        check("misslam_grow_color", load().misslam_grow_color(
+            ctypes.byref(pstruct), ctypes.byref(nstruct), _ptr(reg_map), _ptr(registered), _ptr(nmap),
+            ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(gp), _ptr(image), _ptr(color), ctypes.c_int64(stride),
+            _ptr(counts), _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
     return counts
 
 

@@ -193,10 +193,17 @@ def test_validation_errors(lib):
               None) == _lib.EUNSUPPORTED
     # colour fusion needs the image and the colours
     fp = _lib.FuseParams(10.0, 0.98, 20.0, 1)
-    assert lib.misslam_fuse_color(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(fp), None, FAKE, None, None, FAKE,
-                                  1 << 40, None) == _lib.EINVAL
-    assert lib.misslam_fuse_color(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(fp), FAKE, None, None, None, FAKE,
-                                  1 << 40, None) == _lib.EINVAL
+    fc = lib.misslam_fuse_color
+    assert fc(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(fp), None, FAKE, 1 << 20, None, None, FAKE, 1 << 40,
+              None) == _lib.EINVAL
+    assert fc(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(fp), FAKE, None, 1 << 20, None, None, FAKE, 1 << 40,
+              None) == _lib.EINVAL
+    assert fc(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(fp), FAKE, FAKE, 1, None, None, FAKE, 1 << 40,
+              None) == _lib.EINVAL
+    gpar = _lib.GrowParams()
+    gc = lib.misslam_grow_color
+    assert gc(B(pts), B(nds), FAKE, FAKE, FAKE, B(cam), B(pose), B(gpar), FAKE, FAKE, 1, FAKE, FAKE, 1 << 40,
+              None) == _lib.EINVAL
     # n above capacity, bad camera, bad k
     over = _lib.Points(200, 100, *([FAKE] * 6), 0, 0)
     assert lib.misslam_warp(B(over), B(nds), B(gr), None, FAKE, None, None) == _lib.EINVAL

@@ -148,3 +148,51 @@ def test_sequence_two_frames(lib):
     c1 = M.grow(P, W, S, n, G, X, m, reg, regd, nm1, cam, pose1, M.grow_params(1, 2.5), wsg).cpu().numpy()
     print("frame 1 growth counts", c1.tolist())
     assert c1[6] == 0 and c1[0] > 0.9 * n and c1[1] >= m
+
+
+def test_grow_color_matches_oracle(lib):
+    """Colours through fusion and growth: fused on the GPU (Eq.(13)), then grown; the oracle grows the GPU's
+    fused model and colours.  Survivors and lifted points carry their colours bit for bit, merged voxels the
+    float64 mean; every other output is that of the colourless growth, bit for bit."""
+    import gen
+    frame = 5
+    s, pts, w, st, nodes, x, reg, regd, nmap = _fused(lib, frame)
+    n, m = pts.shape[1], nodes.shape[1]
+    npx = s.cam.width * s.cam.height
+    C, Cm = n + npx, m + 4000
+    img = gen.color_image(s.cam.height, s.cam.width, seed=5)
+    col0 = gen.point_colors(n, seed=6)
+    image = torch.tensor(img, device="cuda")
+    results = []
+    for with_color in (False, True):
+        P = torch.zeros((6, C), device="cuda")
+        P[:, :n] = pts
+        W = torch.zeros(C, device="cuda")
+        W[:n] = w
+        S = torch.zeros(C, dtype=torch.int32, device="cuda")
+        S[:n] = st
+        G = torch.zeros((3, Cm), device="cuda")
+        G[:, :m] = nodes
+        X = torch.zeros((Cm, 12), device="cuda")
+        X[:m] = x
+        col = torch.zeros((3, C), device="cuda")
+        col[:, :n] = torch.tensor(np.ascontiguousarray(col0.T), device="cuda")
+        kw = dict(image=image, color=col) if with_color else {}
+        counts = s.M.grow(P, W, S, n, G, X, m, reg, regd, nmap, s.cam, s.pose, s.M.grow_params(frame, 5.0), s.ws,
+                          **kw)
+        torch.cuda.synchronize()
+        results.append((counts.cpu().numpy(), P.cpu().numpy(), W.cpu().numpy(), S.cpu().numpy(), G.cpu().numpy(),
+                        col.cpu().numpy()))
+    for a, b in zip(results[0][:5], results[1][:5]):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    counts, Pc, Wc, Sc, Gc, colc = results[1]
+    n_out = int(counts[0])
+    ok = ~np.all(nmap.cpu().numpy()[..., :3] == 0, axis=-1)
+    ref = oracle.grow(pts.cpu().numpy()[:3].T, pts.cpu().numpy()[3:].T, w.cpu().numpy(), st.cpu().numpy(),
+                      regd.cpu().numpy().astype(bool), reg.cpu().numpy().reshape(-1), s.sc["depth"], s.sc["camera"],
+                      s.sc["R"], s.sc["T"], nmap.cpu().numpy()[..., :3], ok, frame, nodes.cpu().numpy().T, 5.0,
+                      voxel=0.22, color=col0, image=img)
+    assert n_out == len(ref["points"]) and ref["merged"] > 0 and ref["lifted"] > 1000
+    got = colc[:, :n_out].T
+    print("colour max |d|", np.abs(got - ref["color"]).max())
+    assert np.abs(got - ref["color"]).max() <= 1e-6
