@@ -184,6 +184,7 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
     L.joint.sys = c.take<double>(80);
     L.joint.jpart = c.take<double>((size_t)(pcg_iters + 2) * 10 * ((m + 20) / 21));
     L.joint.pst = c.take<double>((size_t)(pcg_iters + 2) * 32);
+    L.joint.jbar = c.take<unsigned long long>((size_t)32 * 1024);
     L.bytes = align_up(c.off);
     return L;
 }
@@ -529,7 +530,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
             if (e == hipSuccess) e = msl::launch_energy_report(L.step, n, m, rep + it, params->reject_threshold, st);
             if (e == hipSuccess)
                 e = msl::launch_pose_setup(pose_out, prior, L.step.pose_part, msl::point_blocks(n), params->lambda,
-                                           L.joint.sys, rep + it, st);
+                                           L.joint.sys, rep + it, st, L.joint.jbar, m);
             if (e == hipSuccess) {
                 Timed t(PH_PCG, st);
                 e = msl::launch_joint_pcg(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda,

@@ -263,6 +263,7 @@ struct JointScratch {
     double *sys;          // 36 H_pp, 6 g_p, 36 (H_pp + lambda I)^-1
     double *jpart;        // (pcg_iters + 2) x 10 x nblk partial sums
     double *pst;          // (pcg_iters + 2) x 32: pose r, z, p, q, x per iteration
+    unsigned long long *jbar;   // sync area of the one-launch joint solve (zeroed by launch_pose_setup)
 };
 struct PosePrior {
     float R0[9], T0[3];
@@ -271,8 +272,10 @@ struct PosePrior {
 hipError_t launch_pose_init(const Pose &pose, float *pose_dev, hipStream_t st);
 hipError_t launch_border_rows(const StepArgs &a, const StepScratch &s, float *B, hipStream_t st);
 // Reduces the point pass's pose partials, adds the priors (energies into rep) and factors the damped block.
+// jbar (optional): the joint solve's sync area for m node rows, zeroed on the way.
 hipError_t launch_pose_setup(const float *pose_dev, const PosePrior &pr, const double *pose_part, int nblk_pts,
-                             float lambda, double *sys, misslam_report *rep, hipStream_t st);
+                             float lambda, double *sys, misslam_report *rep, hipStream_t st,
+                             unsigned long long *jbar = nullptr, int m = 0);
 // Joint PCG into delta (12 m) and the pose step; applies params += delta and the pose step unless non-finite.
 hipError_t launch_joint_pcg(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                             float lambda, int iters, float *delta, const PcgScratch &s, const JointScratch &js,

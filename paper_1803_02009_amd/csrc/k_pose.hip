@@ -21,6 +21,8 @@ constexpr int kJThreads = 256;
 constexpr int kJRows = 21;          // node rows per block, 12 threads per row
 constexpr int kJKinds = 10;         // partial kinds per iteration: r.z, r.r, p.q, #non-finite, B^T z (6)
 constexpr int kPst = 32;            // pose state per iteration: r, z, p, q, x (6 each)
+constexpr int kJMaxWgs = 1024;      // workgroups of the one-launch joint solve (sync area size)
+constexpr int kJSlotWords = 32;     // sync words per workgroup: 2 parities x 8 values x 2 words
 
 __global__ void pose_init_kernel(Pose P, float *pose_dev) {
     const int t = threadIdx.x;
@@ -148,8 +150,10 @@ __device__ inline bool inverse6(const double A_in[36], double out[36]) {
 
 __global__ void __launch_bounds__(256) pose_setup_kernel(const float *pose_dev, PosePrior pr,
                                                          const double *__restrict__ part, int nblk_pts, float lambda,
-                                                         double *sys, misslam_report *rep) {
+                                                         double *sys, misslam_report *rep,
+                                                         unsigned long long *jbar, int jbar_words) {
     __shared__ double wred[256 / kWave][kPosePart];
+    for (int t = threadIdx.x; t < jbar_words; t += 256) jbar[t] = 0ull;   // the next joint solve's sync area
     double v[kPosePart];
 #pragma unroll
     for (int q = 0; q < kPosePart; ++q) v[q] = 0.0;
@@ -241,9 +245,11 @@ hipError_t launch_pose_init(const Pose &pose, float *pose_dev, hipStream_t st) {
 }
 
 hipError_t launch_pose_setup(const float *pose_dev, const PosePrior &pr, const double *pose_part, int nblk_pts,
-                             float lambda, double *sys, misslam_report *rep, hipStream_t st) {
+                             float lambda, double *sys, misslam_report *rep, hipStream_t st,
+                             unsigned long long *jbar, int m) {
+    const int words = jbar ? kJSlotWords * ((m + kJRows - 1) / kJRows) : 0;
     hipLaunchKernelGGL(pose_setup_kernel, dim3(1), dim3(256), 0, st, pose_dev, pr, pose_part, nblk_pts, lambda, sys,
-                       rep);
+                       rep, jbar, words < kJSlotWords * kJMaxWgs ? words : kJSlotWords * kJMaxWgs);
     return hipGetLastError();
 }
 
@@ -550,6 +556,268 @@ __global__ void __launch_bounds__(kJThreads) jpcg_finish_kernel(JArgs J, misslam
     }
 }
 
+// ---------------------------------------------------------------- joint PCG in one launch
+
+// The same recurrence with the kernel boundaries replaced by tagged exchanges
+// (as in the ED-only persistent solve): workgroup w publishes its partial sums
+// of exchange x as (high half | tag) and (low half | tag) 8-byte words at
+// agent scope, tag = x + 1, in the slot of parity x & 1 (a slot is rewritten
+// two exchanges later, when every workgroup has read it); every workgroup
+// waits for all of them (bounded) and adds them in workgroup order, so all
+// hold the same sums and the same float64 pose state.  Each thread keeps its
+// entry's r, z, p, q, x in registers; z travels through agent-scope stores
+// published only after they are acknowledged.
+__device__ __forceinline__ void jtag_publish(unsigned long long *bar, int wg, int x, const double *v, int N) {
+    unsigned long long *w = bar + (size_t)wg * kJSlotWords + (x & 1) * 16;
+    const unsigned long long tag = (unsigned)(x + 1);
+    for (int q = 0; q < N; ++q) {
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(v[q]);
+        __hip_atomic_store(w + 2 * q, (bits & 0xFFFFFFFF00000000ull) | tag, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(w + 2 * q + 1, (bits << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+constexpr unsigned kJSpinLimit = 1u << 18;
+
+template <int N>
+__device__ __forceinline__ void jtag_sum(unsigned long long *bar, int G, int x, double (&out)[N], bool &broken,
+                                         double (*lds)[kJThreads / kWave]) {
+    const unsigned tag = (unsigned)(x + 1);
+#pragma unroll
+    for (int q = 0; q < N; ++q) out[q] = 0.0;
+    bool ok = true;
+    for (int t = threadIdx.x; t < G; t += kJThreads) {
+        unsigned long long *w = bar + (size_t)t * kJSlotWords + (x & 1) * 16;
+        unsigned long long hv[N], lv[N];
+        unsigned spins = 0;
+        for (;;) {
+            bool all = true;
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                hv[q] = __hip_atomic_load(w + 2 * q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                lv[q] = __hip_atomic_load(w + 2 * q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                all = all && (unsigned)hv[q] == tag && (unsigned)lv[q] == tag;
+            }
+            if (all) break;
+            if (broken || ++spins > kJSpinLimit) {
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (ok)
+#pragma unroll
+            for (int q = 0; q < N; ++q)
+                out[q] += __longlong_as_double((long long)((hv[q] & 0xFFFFFFFF00000000ull) | (lv[q] >> 32)));
+    }
+    broken = __syncthreads_or(broken || !ok) != 0;
+    block_sums<N>(out, lds);
+}
+
+__global__ void __launch_bounds__(kJThreads) jpcg_persistent_kernel(JArgs J, unsigned long long *bar, int G,
+                                                                    misslam_report *rep, float *params,
+                                                                    float *pose_dev) {
+    const PcgArgs &A = J.A;
+    __shared__ double red[16][kJThreads / kWave];
+    __shared__ float rl[kJRows][12];
+    __shared__ double ps[kPst];          // pose r, z, p, q, x (the same in every workgroup)
+    __shared__ double pshare[2];         // this iteration's pose p.q; pose r.z / r.r partial
+    __shared__ double resid[MISSLAM_MAX_PCG + 1];
+    const int wg = blockIdx.x;
+    const int row = threadIdx.x / 12, a = threadIdx.x % 12;
+    const int j = wg * kJRows + row;
+    const bool act = row < kJRows && j < A.m;
+    const size_t o = (size_t)j * 12 + a;
+    const double lam = (double)A.lambda;
+    bool broken = false;
+    auto publish = [&](int x, const double *v, int N) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) jtag_publish(bar, wg, x, v, N);
+    };
+    // init: r = -g, z = M r, x = 0; the pose part r_p = -g_p, z_p = M_p r_p
+    float r = 0.f, z = 0.f, xv = 0.f, pv = 0.f, qv = 0.f;
+    if (act) {
+        r = -A.g[o];
+        rl[row][a] = r;
+    }
+    if (threadIdx.x == 0) {
+        double rz_p = 0.0, rr_p = 0.0;
+        for (int u = 0; u < 6; ++u) ps[u] = -J.sys[36 + u];
+        for (int u = 0; u < 6; ++u) {
+            double t = 0.0;
+            for (int w = 0; w < 6; ++w) t += J.sys[42 + 6 * u + w] * ps[w];
+            ps[6 + u] = t;
+            ps[12 + u] = 0.0;
+            ps[18 + u] = 0.0;
+            ps[24 + u] = 0.0;
+        }
+        for (int u = 0; u < 6; ++u) {
+            rz_p += ps[u] * ps[6 + u];
+            rr_p += ps[u] * ps[u];
+        }
+        pshare[0] = rz_p;
+        pshare[1] = rr_p;
+    }
+    __syncthreads();
+    if (act) {
+        z = jprecond(A.minv, j, a, rl[row]);
+        __hip_atomic_store(A.z + o, z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    double s2[2] = {(double)r * (double)z, (double)r * (double)r};
+    block_sums<2>(s2, red);
+    if (wg == 0) {
+        s2[0] += pshare[0];
+        s2[1] += pshare[1];
+    }
+    publish(0, s2, 2);
+    double t2[2];
+    jtag_sum<2>(bar, G, 0, t2, broken, red);
+    double rz = t2[0], rz_prev = 1.0, nbad = 0.0;
+    if (wg == 0 && threadIdx.x == 0) resid[0] = sqrt(t2[1]);
+    int done = 0, status = 0;
+    for (int it = 0; it < A.iters; ++it) {
+        if (status != 0 || rz == 0.0 || broken) break;   // workgroup-uniform, the same in every workgroup
+        const float beta = it > 0 ? (float)(rz / rz_prev) : 0.f;
+        // direction and product: q = H z + lambda z + B z_p + beta q, p = z + beta p
+        double pq = 0.0, btz[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (act) {
+            double az = 0.0;
+            const int p0 = A.row_ptr[j], p1 = min(A.row_ptr[j + 1], A.cap);
+            for (int pb = p0; pb < p1; ++pb) {
+                const float *Bk = A.blocks + (size_t)pb * 144 + a * 12;
+                const float *zl = A.z + (size_t)A.col_idx[pb] * 12;
+#pragma unroll
+                for (int b = 0; b < 12; ++b)
+                    az = fma((double)Bk[b],
+                             (double)__hip_atomic_load(const_cast<float *>(zl + b), __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT),
+                             az);
+            }
+            az = fma(lam, (double)z, az);
+            const float *Bj = J.B + (size_t)j * 72 + a * 6;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                az = fma((double)Bj[k], ps[6 + k], az);
+                btz[k] = (double)Bj[k] * (double)z;
+            }
+            if (it > 0) {
+                pv = fmaf(beta, pv, z);
+                qv = (float)fma((double)beta, (double)qv, az);
+            } else {
+                pv = z;
+                qv = (float)az;
+            }
+            pq = (double)pv * (double)qv;
+        }
+        double s7[7] = {pq, btz[0], btz[1], btz[2], btz[3], btz[4], btz[5]};
+        block_sums<7>(s7, red);
+        publish(1 + 2 * it, s7, 7);
+        double t7[7];
+        jtag_sum<7>(bar, G, 1 + 2 * it, t7, broken, red);
+        if (threadIdx.x == 0) {   // the pose part of the product and its direction
+            double qp[6], pp[6], t = 0.0;
+            for (int u = 0; u < 6; ++u) {
+                double az = t7[1 + u];
+                for (int w = 0; w < 6; ++w) az += J.sys[6 * u + w] * ps[6 + w];
+                az += lam * ps[6 + u];
+                qp[u] = it > 0 ? (double)beta * ps[18 + u] + az : az;
+                pp[u] = it > 0 ? (double)beta * ps[12 + u] + ps[6 + u] : ps[6 + u];
+                t += pp[u] * qp[u];
+            }
+            for (int u = 0; u < 6; ++u) {
+                ps[12 + u] = pp[u];
+                ps[18 + u] = qp[u];
+            }
+            pshare[0] = t;
+        }
+        __syncthreads();
+        const double pqt = t7[0] + pshare[0];
+        __syncthreads();
+        if (!(pqt > 0.0) || broken) {   // breakdown: no update (uniform)
+            status = broken ? status : 2;
+            break;
+        }
+        const float alpha = (float)(rz / pqt);
+        double bad = 0.0;
+        if (act) {
+            xv = fmaf(alpha, pv, xv);
+            r = fmaf(-alpha, qv, r);
+            bad = isfinite(xv) ? 0.0 : 1.0;
+            rl[row][a] = r;
+        }
+        if (threadIdx.x == 0) {   // the pose step and its preconditioned residual
+            double rz_p = 0.0, rr_p = 0.0, nb_p = 0.0;
+            for (int u = 0; u < 6; ++u) {
+                ps[24 + u] += (double)alpha * ps[12 + u];
+                ps[u] -= (double)alpha * ps[18 + u];
+                if (!isfinite(ps[24 + u])) nb_p += 1.0;
+            }
+            for (int u = 0; u < 6; ++u) {
+                double t = 0.0;
+                for (int w = 0; w < 6; ++w) t += J.sys[42 + 6 * u + w] * ps[w];
+                ps[6 + u] = t;
+            }
+            for (int u = 0; u < 6; ++u) {
+                rz_p += ps[u] * ps[6 + u];
+                rr_p += ps[u] * ps[u];
+            }
+            red[15][0] = rz_p;
+            red[15][1] = rr_p;
+            red[15][2] = nb_p;
+        }
+        __syncthreads();
+        if (act) {
+            z = jprecond(A.minv, j, a, rl[row]);
+            __hip_atomic_store(A.z + o, z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const double pose_rz = red[15][0], pose_rr = red[15][1], pose_nb = red[15][2];
+        double s3[3] = {(double)r * (double)z, (double)r * (double)r, bad};
+        block_sums<3>(s3, red);
+        if (wg == 0) {
+            s3[0] += pose_rz;
+            s3[1] += pose_rr;
+            s3[2] += pose_nb;
+        }
+        publish(2 + 2 * it, s3, 3);
+        double t3[3];
+        jtag_sum<3>(bar, G, 2 + 2 * it, t3, broken, red);
+        rz_prev = rz;
+        rz = t3[0];
+        nbad = t3[2];
+        done = it + 1;
+        if (wg == 0 && threadIdx.x == 0) resid[done] = sqrt(t3[1]);
+    }
+    // finish: delta, params += delta and the pose step unless non-finite; the report
+    if (act) {
+        A.x[o] = xv;
+        if (params && nbad == 0.0 && !broken) params[o] += xv;
+    }
+    if (wg == 0 && threadIdx.x == 0) {
+        for (int q = 0; q <= done && q <= MISSLAM_MAX_PCG; ++q) rep->pcg_resid[q] = resid[q];
+        rep->pcg_iters_done = done;
+        int f = rep->flags;
+        if (status == 2) f |= MISSLAM_FLAG_PCG_BREAKDOWN;
+        if (nbad != 0.0) f |= MISSLAM_FLAG_NONFINITE;
+        if (broken) f |= MISSLAM_FLAG_SYNC_TIMEOUT;
+        rep->flags = f;
+        if (nbad == 0.0 && !broken) {
+            double E[9], R[9], T[3];
+            so3_exp_d(ps + 24, E);
+            for (int u = 0; u < 9; ++u) R[u] = pose_dev[u];
+            for (int u = 0; u < 3; ++u) T[u] = pose_dev[9 + u];
+            for (int rr = 0; rr < 3; ++rr) {
+                for (int c = 0; c < 3; ++c)
+                    pose_dev[3 * rr + c] =
+                        (float)((E[3 * rr] * R[c] + E[3 * rr + 1] * R[3 + c]) + E[3 * rr + 2] * R[6 + c]);
+                pose_dev[9 + rr] =
+                    (float)(((E[3 * rr] * T[0] + E[3 * rr + 1] * T[1]) + E[3 * rr + 2] * T[2]) + ps[27 + rr]);
+            }
+        }
+    }
+}
+
 hipError_t launch_joint_pcg(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                             float lambda, int iters, float *delta, const PcgScratch &s, const JointScratch &js,
                             misslam_report *rep, float *params, float *pose_dev, hipStream_t st) {
@@ -577,6 +845,18 @@ hipError_t launch_joint_pcg(const GraphView &g, int m, const float *blocks, cons
     J.sys = js.sys;
     J.jpart = js.jpart;
     J.pst = js.pst;
+    static int cus = -1;
+    if (cus < 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 0;
+    }
+    if (js.jbar && A.nblk <= cus && A.nblk <= kJMaxWgs) {   // every workgroup resident: one launch
+        hipLaunchKernelGGL(jpcg_persistent_kernel, dim3(A.nblk), dim3(kJThreads), 0, st, J, js.jbar, A.nblk, rep,
+                           params, pose_dev);
+        return hipGetLastError();
+    }
     const dim3 grid(A.nblk), blk(kJThreads);
     hipLaunchKernelGGL(jpcg_init_kernel, grid, blk, 0, st, J);
     for (int it = 0; it < iters; ++it) {
