@@ -110,3 +110,37 @@ def test_lm_with_keypoints_matches_oracle(lib):
     xg, r, cs = _run_lm(s, s.params, lm, keys=keys)
     _check(s, s.params, lm, r, xg, cs, pb_kw=dict(kp_point=kp, kp_target=tgt, w_corr=10.0))
     assert r[-1]["e_corr"] < 0.5 * r[0]["e_corr"]
+
+
+def test_every_step_rejected_leaves_x_and_raises_lambda(lib):
+    """A start whose undamped steps overshoot by orders of magnitude (columns of A at 0.1, rotation weight
+    1e5, 60 PCG iterations): every step is rejected, x stays bitwise the start, the objective is the same at
+    every step and lambda grows tenfold per step."""
+    s = Scene("c1")
+    params = s.M.Params(sigma=s.params.sigma, gn_iters=6, pcg_iters=60, w_rot=1e5, w_reg=1.0)
+    x = s.M.identity_params(s.m)
+    x[:, :9] *= 0.1
+    x0 = x.clone()
+    rep, _ = s.M.lm_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, params, s.ws, lm=s.M.LMParams())
+    torch.cuda.synchronize()
+    r = s.M.read_report(rep)
+    G = params.gn_iters
+    assert np.all(r["lm_accepted"][:G] == 0)
+    assert torch.equal(x, x0)
+    assert np.all(r["lm_e"][:G] == r["lm_e"][0]) and np.all(r["lm_e_trial"][:G] > 100 * r["lm_e"][:G])
+    lam = np.float32(1e-3)
+    for k in range(G):
+        assert r[k]["lm_lambda"] == lam
+        lam = np.float32(min(lam * np.float32(10.0), np.float32(1e6)))
+    assert r[-1]["e_data"] == r[0]["e_data"] and r[-1]["e_rot"] == pytest.approx(r[0]["e_rot"], rel=1e-6)
+
+
+def test_zero_steps(lib):
+    """gn_iters = 0: only the final entry, x untouched."""
+    s = Scene("c1")
+    params = s.M.Params(sigma=s.params.sigma, gn_iters=0, pcg_iters=10)
+    x = s.M.identity_params(s.m)
+    rep, _ = s.M.lm_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, params, s.ws, lm=s.M.LMParams())
+    torch.cuda.synchronize()
+    r = s.M.read_report(rep)
+    assert len(r) == 1 and torch.equal(x, s.M.identity_params(s.m)) and r[0]["e_data"] > 0

@@ -67,3 +67,15 @@ def test_stiff_priors_are_the_fixed_pose_registration(lib):
     T0 = np.asarray(s.sc["T"], np.float32).astype(np.float64)
     assert np.abs(Rg - R0).max() <= 1e-6 and np.abs(Tg - T0).max() <= 1e-5
     assert rel_err(xg, x.cpu().numpy()) < 1e-5
+
+
+def test_zero_steps_keep_the_pose(lib):
+    """gn_iters = 0: the pose comes back as given, bit for bit, with zero pose energies."""
+    s = Scene("c1")
+    params = s.M.Params(sigma=s.params.sigma, gn_iters=0, pcg_iters=10)
+    xg, Rg, Tg, r, _ = _run(s, params)
+    R0 = np.asarray(s.sc["R"], np.float32).astype(np.float64)
+    T0 = np.asarray(s.sc["T"], np.float32).astype(np.float64)
+    assert np.array_equal(Rg, R0) and np.array_equal(Tg, T0)
+    assert len(r) == 1 and r[0]["e_pose_r"] == 0.0 and r[0]["e_pose_p"] == 0.0
+    assert np.array_equal(xg, s.M.identity_params(s.m).cpu().numpy())
