@@ -325,8 +325,10 @@ void misslam_default_lm_params(misslam_lm_params *lm);
  * damping params->lambda on the whole diagonal, the damped 6x6 pose block in
  * the preconditioner), then x += dx and the pose takes its step.
  * pose_out (device, 12 floats: R row-major, then T) receives the refined
- * pose; it is also the working pose during the call.  rep as for
- * misslam_gn_register, with e_pose_r / e_pose_p set.  Errors as
+ * pose; it is also the working pose during the call.  keys (may be NULL) adds
+ * the Eq.(9) term as in misslam_gn_register_keypoints, its rows gaining the
+ * pose columns [-[v~]x, I]: all six terms of Eq.(3) together.  rep as for
+ * misslam_gn_register, with e_pose_r / e_pose_p (and e_corr) set.  Errors as
  * misslam_gn_register; MISSLAM_EINVAL for pw or pose_out NULL or a weight
  * that is negative or not finite; float32 form only (MISSLAM_EUNSUPPORTED
  * otherwise).
@@ -334,9 +336,9 @@ void misslam_default_lm_params(misslam_lm_params *lm);
 misslam_status misslam_joint_register(const misslam_points *points, misslam_nodes *nodes,
                                       const misslam_graph *graph, const float *depth,
                                       const misslam_camera *camera, const misslam_pose *pose,
-                                      const misslam_pose_weights *pw, const misslam_params *params,
-                                      float *pose_out, misslam_report *rep, int32_t *corr_hist, void *ws,
-                                      size_t ws_bytes, void *stream);
+                                      const misslam_pose_weights *pw, const misslam_keypoints *keys,
+                                      const misslam_params *params, float *pose_out, misslam_report *rep,
+                                      int32_t *corr_hist, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Registration with adaptive Levenberg-Marquardt damping (Sec. II-F): step i

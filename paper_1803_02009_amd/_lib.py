@@ -120,8 +120,8 @@ SIGNATURES = {
     "misslam_gn_register_keypoints": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params),
                                            P(Keypoints), vp, vp, vp, ctypes.c_size_t, vp]),
     "misslam_default_lm_params": (None, [P(LMParams)]),
-    "misslam_joint_register": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(PoseWeights), P(Params),
-                                    vp, vp, vp, vp, ctypes.c_size_t, vp]),
+    "misslam_joint_register": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(PoseWeights),
+                                    P(Keypoints), P(Params), vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "misslam_lm_register": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params), P(Keypoints),
                                  P(LMParams), vp, vp, vp, ctypes.c_size_t, vp]),
     "misslam_fuse_color": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(FuseParams), vp, vp,

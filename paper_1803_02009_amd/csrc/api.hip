@@ -174,7 +174,7 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
     L.step.lpa = c.take<float4>((size_t)k * n);
     L.step.lpw = c.take<float4>((size_t)k * n * ((k + 3) / 4));
     L.corr.kp_nodes = c.take<int32_t>((size_t)k * n);
-    L.corr.kp_data = c.take<float>((size_t)(3 + 4 * k) * n);
+    L.corr.kp_data = c.take<float>((size_t)(9 + 4 * k) * n);
     L.corr.kp_energy = c.take<double>((size_t)n);
     L.lm_lambda = c.take<float>(4);
     // joint pose form
@@ -452,7 +452,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
     if (params->precision != MISSLAM_PREC_FP32 && params->k > 4) return MISSLAM_EUNSUPPORTED;
     if (params->precision != MISSLAM_PREC_FP32 && keys && keys->count > 0) return MISSLAM_EUNSUPPORTED;
     if (params->precision != MISSLAM_PREC_FP32 && lm) return MISSLAM_EUNSUPPORTED;
-    if (pw && (params->precision != MISSLAM_PREC_FP32 || lm || (keys && keys->count > 0))) return MISSLAM_EUNSUPPORTED;
+    if (pw && (params->precision != MISSLAM_PREC_FP32 || lm)) return MISSLAM_EUNSUPPORTED;
     msl::KeyArgs ka{};
     const msl::KeyArgs *kp = nullptr;
     if (keys && keys->count > 0) {
@@ -507,13 +507,16 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
         }
         if (pw) {   // joint pose + ED: the pose lives on the device
             a.pose_dev = pose_out;
+            const bool keys = kp && kp->count > 0;
             {
                 Timed t(PH_POINT_PASS, st);
-                e = msl::launch_point_pass_joint(a, L.step, st);
+                e = msl::launch_point_pass_joint(a, L.step, st, keys ? kp : nullptr, keys ? &L.corr : nullptr);
             }
             if (it == G) {
                 if (e == hipSuccess) e = msl::launch_node_energy(a, L.step, st);
-                if (e == hipSuccess) e = msl::launch_energy_report(L.step, n, m, rep + it, params->reject_threshold, st);
+                if (e == hipSuccess)
+                    e = msl::launch_energy_report(L.step, n, m, rep + it, params->reject_threshold, st, nullptr, 0,
+                                                  keys ? L.corr.kp_energy : nullptr, keys ? kp->count : 0);
                 if (e == hipSuccess)
                     e = msl::launch_pose_setup(pose_out, prior, L.step.pose_part, msl::point_blocks(n), params->lambda,
                                                nullptr, rep + it, st);
@@ -527,10 +530,17 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
                 Timed t(PH_POSE, st);
                 e = msl::launch_border_rows(a, L.step, L.joint.B, st);
             }
-            if (e == hipSuccess) e = msl::launch_energy_report(L.step, n, m, rep + it, params->reject_threshold, st);
+            if (e == hipSuccess && keys) {   // Eq.(9): ED rows and blocks, and its part of the border
+                Timed t(PH_CORR, st);
+                e = msl::launch_corr_rows(a, *kp, L.corr, st, L.joint.B);
+            }
+            if (e == hipSuccess)
+                e = msl::launch_energy_report(L.step, n, m, rep + it, params->reject_threshold, st, nullptr, 0,
+                                              keys ? L.corr.kp_energy : nullptr, keys ? kp->count : 0);
             if (e == hipSuccess)
                 e = msl::launch_pose_setup(pose_out, prior, L.step.pose_part, msl::point_blocks(n), params->lambda,
-                                           L.joint.sys, rep + it, st, L.joint.jbar, m);
+                                           L.joint.sys, rep + it, st, L.joint.jbar, m, keys ? kp : nullptr,
+                                           keys ? &L.corr : nullptr, n, params->k);
             if (e == hipSuccess) {
                 Timed t(PH_PCG, st);
                 e = msl::launch_joint_pcg(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda,
@@ -645,13 +655,13 @@ void misslam_default_lm_params(misslam_lm_params *lm) {
 misslam_status misslam_joint_register(const misslam_points *points, misslam_nodes *nodes,
                                       const misslam_graph *graph, const float *depth,
                                       const misslam_camera *camera, const misslam_pose *pose,
-                                      const misslam_pose_weights *pw, const misslam_params *params,
-                                      float *pose_out, misslam_report *rep, int32_t *corr_hist, void *ws,
-                                      size_t ws_bytes, void *stream) {
+                                      const misslam_pose_weights *pw, const misslam_keypoints *keys,
+                                      const misslam_params *params, float *pose_out, misslam_report *rep,
+                                      int32_t *corr_hist, void *ws, size_t ws_bytes, void *stream) {
     if (!pw || !pose_out || !pose || !std::isfinite(pw->w_r) || !std::isfinite(pw->w_p) || !(pw->w_r >= 0.f) ||
         !(pw->w_p >= 0.f))
         return MISSLAM_EINVAL;
-    return gn_register(points, nodes, graph, depth, camera, pose, params, nullptr, nullptr, rep, corr_hist, ws,
+    return gn_register(points, nodes, graph, depth, camera, pose, params, keys, nullptr, rep, corr_hist, ws,
                        ws_bytes, stream, pw, pose_out);
 }
 

@@ -121,10 +121,11 @@ struct KeyArgs {
 };
 
 template <int K>
-constexpr int kp_stride() { return 3 + 4 * K; }   // per key point: R^T r, then per node q: w_q, d_q (3)
+constexpr int kp_stride() { return 9 + 4 * K; }   // per key point: R^T r, per node q: w_q, d_q (3); v~, r
 
 // Eq.(9) at the current parameters for key point s: residual r = V~ - V (float32), R^T r, the k weights
-// and d_q = v - g_q into kp_data, the energy |r|^2 (float64; 0 for a skipped key point) into kp_energy.
+// and d_q = v - g_q, the warped point V~ and r (camera coordinates) into kp_data, the energy |r|^2 (float64; 0
+// for a skipped key point) into kp_energy.  The pose is the device pose when a.pose_dev is set.
 template <int K>
 __device__ __forceinline__ void kp_eval_body(const StepArgs &a, const KeyArgs &kp, float *kp_data,
                                              double *kp_energy, int s) {
@@ -138,12 +139,13 @@ __device__ __forceinline__ void kp_eval_body(const StepArgs &a, const KeyArgs &k
         return;
     }
     const float vx = a.pts.px[p], vy = a.pts.py[p], vz = a.pts.pz[p];
+    const Pose P = step_pose(a);
     float ox, oy, oz;
     ed_blend<K>(vx, vy, vz, a.g.knn_idx, a.g.knn_w, n, p, a.nd, ox, oy, oz);
-    apply_pose(a.pose, ox, oy, oz);
+    apply_pose(P, ox, oy, oz);
     const float rx = ox - kp.target[3 * (size_t)s], ry = oy - kp.target[3 * (size_t)s + 1],
                 rz = oz - kp.target[3 * (size_t)s + 2];
-    const float *R = a.pose.R;
+    const float *R = P.R;
     o[0] = fmaf(R[6], rz, fmaf(R[3], ry, R[0] * rx));
     o[1] = fmaf(R[7], rz, fmaf(R[4], ry, R[1] * rx));
     o[2] = fmaf(R[8], rz, fmaf(R[5], ry, R[2] * rx));
@@ -155,6 +157,12 @@ __device__ __forceinline__ void kp_eval_body(const StepArgs &a, const KeyArgs &k
         o[5 + 4 * q] = vy - a.nd.gy[l];
         o[6 + 4 * q] = vz - a.nd.gz[l];
     }
+    o[3 + 4 * K] = ox;
+    o[4 + 4 * K] = oy;
+    o[5 + 4 * K] = oz;
+    o[6 + 4 * K] = rx;
+    o[7 + 4 * K] = ry;
+    o[8 + 4 * K] = rz;
     kp_energy[s] = ((double)rx * rx + (double)ry * ry) + (double)rz * rz;
 }
 
@@ -253,8 +261,10 @@ hipError_t launch_fuse(const FuseArgs &f, float *gx, float *gy, float *gz, float
 // With key points (kp, c), the same launch also evaluates them (kp_eval_body) in blocks of its own.
 hipError_t launch_point_pass(const StepArgs &a, const StepScratch &s, hipStream_t st, const KeyArgs *kp = nullptr,
                              const CorrScratch *c = nullptr);
-// Joint pose form: the point pass with the pose read from a.pose_dev, also writing s.jp and s.pose_part.
-hipError_t launch_point_pass_joint(const StepArgs &a, const StepScratch &s, hipStream_t st);
+// Joint pose form: the point pass with the pose read from a.pose_dev, also writing s.jp and s.pose_part (and
+// evaluating the key points (kp, c) at the device pose in blocks of its own).
+hipError_t launch_point_pass_joint(const StepArgs &a, const StepScratch &s, hipStream_t st,
+                                   const KeyArgs *kp = nullptr, const CorrScratch *c = nullptr);
 int point_blocks(int64_t n);
 
 // Joint pose + ED (Eq.(10)).
@@ -272,10 +282,12 @@ struct PosePrior {
 hipError_t launch_pose_init(const Pose &pose, float *pose_dev, hipStream_t st);
 hipError_t launch_border_rows(const StepArgs &a, const StepScratch &s, float *B, hipStream_t st);
 // Reduces the point pass's pose partials, adds the priors (energies into rep) and factors the damped block.
-// jbar (optional): the joint solve's sync area for m node rows, zeroed on the way.
+// jbar (optional): the joint solve's sync area for m node rows, zeroed on the way.  kp (optional): the key
+// points' part of H_pp and g_p, from c.kp_data (carrying points outside [0, n) skipped).
 hipError_t launch_pose_setup(const float *pose_dev, const PosePrior &pr, const double *pose_part, int nblk_pts,
                              float lambda, double *sys, misslam_report *rep, hipStream_t st,
-                             unsigned long long *jbar = nullptr, int m = 0);
+                             unsigned long long *jbar = nullptr, int m = 0, const KeyArgs *kp = nullptr,
+                             const CorrScratch *c = nullptr, int64_t n = 0, int k = 4);
 // Joint PCG into delta (12 m) and the pose step; applies params += delta and the pose step unless non-finite.
 hipError_t launch_joint_pcg(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                             float lambda, int iters, float *delta, const PcgScratch &s, const JointScratch &js,
@@ -286,7 +298,9 @@ hipError_t launch_list_pack(const StepArgs &a, const StepScratch &s, hipStream_t
 hipError_t launch_assemble(const StepArgs &a, const StepScratch &s, hipStream_t st);
 // Eq.(9): adds the term to the blocks and gradient of every row it touches (after launch_assemble and
 // launch_kp_eval) and re-inverts their damped diagonal blocks.
-hipError_t launch_corr_rows(const StepArgs &a, const KeyArgs &kp, const CorrScratch &c, hipStream_t st);
+// With B (joint pose form), also adds the key points' part of the pose border B_j.
+hipError_t launch_corr_rows(const StepArgs &a, const KeyArgs &kp, const CorrScratch &c, hipStream_t st,
+                            float *B = nullptr);
 // kp_nodes[s k + q] = node q of key point s's carrying point (-1 if its index is outside [0, n)); once per
 // registration, before launch_corr_rows.
 hipError_t launch_kp_nodes(const StepArgs &a, const KeyArgs &kp, int32_t *kp_nodes, hipStream_t st);

@@ -45,7 +45,7 @@ constexpr int kWbPerThread = 8;
 template <int K>
 __global__ void __launch_bounds__(kCorrThreads) corr_rows_kernel(StepArgs a, KeyArgs kp,
                                                                  const int32_t *__restrict__ kp_nodes,
-                                                                 const float *__restrict__ kp_data) {
+                                                                 const float *__restrict__ kp_data, float *Bout) {
     constexpr int S = kp_stride<K>();
     constexpr int kPass = kScanChunks * kCorrThreads;   // key points scanned per pass
     static_assert(MISSLAM_MAX_ROW <= kCorrThreads, "one thread per slot");
@@ -70,6 +70,10 @@ __global__ void __launch_bounds__(kCorrThreads) corr_rows_kernel(StepArgs a, Key
     for (int t = tid; t < MISSLAM_MAX_ROW * 16; t += kCorrThreads) macc[t] = 0.f;
     double gacc = 0.0;     // gradient entry tid (< 12) of row j
     bool any = false;      // workgroup-uniform
+    // joint pose form: entries tid and tid + 64 (< 72) of this row's border B_j, (3c + a) * 6 + k:
+    //   w_corr w_j d_c R[:, a]^T [-[v~]x, I][:, k] = w_corr w_j d_c ((v~ x R[:, a])_k, or R[k - 3][a])
+    float bacc0 = 0.f, bacc1 = 0.f;
+    const Pose P = step_pose(a);
     const uint64_t below = (1ull << tid) - 1ull;
     for (int s0 = 0; s0 < kp.count; s0 += kPass) {
         int nd[kScanChunks][K];
@@ -145,6 +149,30 @@ __global__ void __launch_bounds__(kCorrThreads) corr_rows_kernel(StepArgs a, Key
                     }
                 }
             }
+            if (Bout) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int e = tid + 64 * h;
+                    if (e >= 72) continue;
+                    const int c = (e / 6) / 3, ax = (e / 6) % 3, k = e % 6;
+                    const float ux = P.R[ax], uy = P.R[3 + ax], uz = P.R[6 + ax];   // R[:, a]
+                    float acc = h ? bacc1 : bacc0;
+                    for (int L = 0; L < cnt; ++L) {
+                        const int qjL = kqj[L];
+                        const float wj = kd[L][3 + 4 * qjL];
+                        const float dc = c < 3 ? kd[L][4 + 4 * qjL + c] : 1.f;
+                        const float vx = kd[L][3 + 4 * K], vy = kd[L][4 + 4 * K], vz = kd[L][5 + 4 * K];
+                        float col;
+                        if (k == 0) col = fmaf(vy, uz, -vz * uy);
+                        else if (k == 1) col = fmaf(vz, ux, -vx * uz);
+                        else if (k == 2) col = fmaf(vx, uy, -vy * ux);
+                        else col = k == 3 ? ux : (k == 4 ? uy : uz);
+                        acc = fmaf(kp.w_corr * wj * dc, col, acc);
+                    }
+                    if (h) bacc1 = acc;
+                    else bacc0 = acc;
+                }
+            }
             __syncthreads();   // hits, kd, kslot and kqj are refilled next
         }
     }
@@ -194,6 +222,10 @@ __global__ void __launch_bounds__(kCorrThreads) corr_rows_kernel(StepArgs a, Key
         }
     }
     if (tid < 12) a.gvec[(size_t)j * 12 + tid] = (float)((double)a.gvec[(size_t)j * 12 + tid] + gacc);
+    if (Bout) {
+        Bout[(size_t)j * 72 + tid] += bacc0;
+        if (tid + 64 < 72) Bout[(size_t)j * 72 + tid + 64] += bacc1;
+    }
     if (inv) {
         __syncthreads();
         const bool ok = gj_inverse_block<kCorrThreads>(Hd, a.minv + (size_t)j * 144);
@@ -215,14 +247,14 @@ hipError_t launch_kp_nodes(const StepArgs &a, const KeyArgs &kp, int32_t *kp_nod
     return hipGetLastError();
 }
 
-hipError_t launch_corr_rows(const StepArgs &a, const KeyArgs &kp, const CorrScratch &c, hipStream_t st) {
+hipError_t launch_corr_rows(const StepArgs &a, const KeyArgs &kp, const CorrScratch &c, hipStream_t st, float *B) {
     const int m = a.nd.m;
     if (kp.count <= 0 || m <= 0) return hipSuccess;
     switch (a.g.k) {
 #define MSL_KP_CASE(KK)                                                                                      \
     case KK:                                                                                                 \
         hipLaunchKernelGGL((corr_rows_kernel<KK>), dim3(m), dim3(kCorrThreads), 0, st, a, kp, c.kp_nodes,   \
-                           c.kp_data);                                                                       \
+                           c.kp_data, B);                                                                       \
         break;
         MSL_KP_CASE(1) MSL_KP_CASE(2) MSL_KP_CASE(3) MSL_KP_CASE(4)
         MSL_KP_CASE(5) MSL_KP_CASE(6) MSL_KP_CASE(7) MSL_KP_CASE(8)

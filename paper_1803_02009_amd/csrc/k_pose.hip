@@ -148,43 +148,82 @@ __device__ inline bool inverse6(const double A_in[36], double out[36]) {
     return ok;
 }
 
+struct PoseKeys {
+    int count;
+    float w_corr;
+    const int32_t *point;
+    const float *data;     // kp_data
+    int stride;            // 9 + 4k
+    int off_v;             // offset of v~ (then r) in a record: 3 + 4k
+    int64_t n;
+};
+
 __global__ void __launch_bounds__(256) pose_setup_kernel(const float *pose_dev, PosePrior pr,
                                                          const double *__restrict__ part, int nblk_pts, float lambda,
                                                          double *sys, misslam_report *rep,
-                                                         unsigned long long *jbar, int jbar_words) {
-    __shared__ double wred[256 / kWave][kPosePart];
+                                                         unsigned long long *jbar, int jbar_words, PoseKeys pk) {
+    __shared__ double wred[2][256 / kWave][kPosePart];
     for (int t = threadIdx.x; t < jbar_words; t += 256) jbar[t] = 0ull;   // the next joint solve's sync area
-    double v[kPosePart];
+    double v[kPosePart], vk[kPosePart];
 #pragma unroll
-    for (int q = 0; q < kPosePart; ++q) v[q] = 0.0;
+    for (int q = 0; q < kPosePart; ++q) {
+        v[q] = 0.0;
+        vk[q] = 0.0;
+    }
     for (int b = threadIdx.x; b < nblk_pts; b += 256)
 #pragma unroll
         for (int q = 0; q < kPosePart; ++q) v[q] += part[(size_t)kPosePart * b + q];
+    // key points: rows [-[v~]x, I] with residual r, weight w_corr
+    for (int s = threadIdx.x; s < pk.count; s += 256) {
+        const int p = pk.point[s];
+        if (p < 0 || p >= pk.n) continue;
+        const float *o = pk.data + (size_t)s * pk.stride + pk.off_v;
+        const double vx = o[0], vy = o[1], vz = o[2], r3[3] = {o[3], o[4], o[5]};
+        const double J[3][6] = {{0.0, vz, -vy, 1.0, 0.0, 0.0}, {-vz, 0.0, vx, 0.0, 1.0, 0.0},
+                                {vy, -vx, 0.0, 0.0, 0.0, 1.0}};
+        const double wc = (double)pk.w_corr;
+        int e = 0;
+#pragma unroll
+        for (int u = 0; u < 6; ++u)
+#pragma unroll
+            for (int w = u; w < 6; ++w) vk[e++] += wc * ((J[0][u] * J[0][w] + J[1][u] * J[1][w]) + J[2][u] * J[2][w]);
+#pragma unroll
+        for (int u = 0; u < 6; ++u) vk[21 + u] += wc * ((J[0][u] * r3[0] + J[1][u] * r3[1]) + J[2][u] * r3[2]);
+    }
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
 #pragma unroll
     for (int q = 0; q < kPosePart; ++q) {
-        double t = v[q];
+        double t = v[q], tk = vk[q];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-        if (lane == 0) wred[wave][q] = t;
+        for (int off = 32; off > 0; off >>= 1) {
+            t += __shfl_xor(t, off, 64);
+            tk += __shfl_xor(tk, off, 64);
+        }
+        if (lane == 0) {
+            wred[0][wave][q] = t;
+            wred[1][wave][q] = tk;
+        }
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    double S[kPosePart];
+    double S[kPosePart], SK[kPosePart];
 #pragma unroll
-    for (int q = 0; q < kPosePart; ++q) S[q] = ((wred[0][q] + wred[1][q]) + wred[2][q]) + wred[3][q];
+    for (int q = 0; q < kPosePart; ++q) {
+        S[q] = ((wred[0][0][q] + wred[0][1][q]) + wred[0][2][q]) + wred[0][3][q];
+        SK[q] = ((wred[1][0][q] + wred[1][1][q]) + wred[1][2][q]) + wred[1][3][q];
+    }
     double H[36], g[6];
     int e = 0;
 #pragma unroll
     for (int u = 0; u < 6; ++u)
 #pragma unroll
         for (int w = u; w < 6; ++w) {
-            H[6 * u + w] = (double)pr.w_data * S[e];
-            H[6 * w + u] = (double)pr.w_data * S[e];
+            H[6 * u + w] = (double)pr.w_data * S[e] + SK[e];
+            H[6 * w + u] = (double)pr.w_data * S[e] + SK[e];
             ++e;
         }
 #pragma unroll
-    for (int u = 0; u < 6; ++u) g[u] = (double)pr.w_data * S[21 + u];
+    for (int u = 0; u < 6; ++u) g[u] = (double)pr.w_data * S[21 + u] + SK[21 + u];
     // priors: rho_r = log(R R0^T), rho_p = C - C0
     double R[9], T[3], R0[9], T0[3], M[9];
 #pragma unroll
@@ -246,10 +285,21 @@ hipError_t launch_pose_init(const Pose &pose, float *pose_dev, hipStream_t st) {
 
 hipError_t launch_pose_setup(const float *pose_dev, const PosePrior &pr, const double *pose_part, int nblk_pts,
                              float lambda, double *sys, misslam_report *rep, hipStream_t st,
-                             unsigned long long *jbar, int m) {
+                             unsigned long long *jbar, int m, const KeyArgs *kp, const CorrScratch *c, int64_t n,
+                             int k) {
     const int words = jbar ? kJSlotWords * ((m + kJRows - 1) / kJRows) : 0;
+    PoseKeys pk{};
+    if (kp && c && kp->count > 0) {
+        pk.count = kp->count;
+        pk.w_corr = kp->w_corr;
+        pk.point = kp->point;
+        pk.data = c->kp_data;
+        pk.stride = 9 + 4 * k;
+        pk.off_v = 3 + 4 * k;
+        pk.n = n;
+    }
     hipLaunchKernelGGL(pose_setup_kernel, dim3(1), dim3(256), 0, st, pose_dev, pr, pose_part, nblk_pts, lambda, sys,
-                       rep, jbar, words < kJSlotWords * kJMaxWgs ? words : kJSlotWords * kJMaxWgs);
+                       rep, jbar, words < kJSlotWords * kJMaxWgs ? words : kJSlotWords * kJMaxWgs, pk);
     return hipGetLastError();
 }
 

@@ -1277,17 +1277,34 @@ __global__ void __launch_bounds__(256) energy_report_kernel(const double *__rest
 }
 
 template <int K>
-__global__ void __launch_bounds__(kPtBlock) point_pass_joint_kernel(StepArgs a, StepScratch s) {
-    point_pass_body<K, true>(a, s, blockIdx.x);
+__global__ void __launch_bounds__(kPtBlock) point_pass_joint_kernel(StepArgs a, StepScratch s, KeyArgs kp,
+                                                                   float *kp_data, double *kp_energy, unsigned ptb) {
+    if (blockIdx.x < ptb)
+        point_pass_body<K, true>(a, s, blockIdx.x);
+    else   // the key points, Eq.(9), one per thread, at the device pose
+        kp_eval_body<K>(a, kp, kp_data, kp_energy, (int)(blockIdx.x - ptb) * kPtBlock + (int)threadIdx.x);
 }
 
 int point_blocks(int64_t n) { return (int)nblk(n > 0 ? n : 1, kPtBlock); }
 
-hipError_t launch_point_pass_joint(const StepArgs &a, const StepScratch &s, hipStream_t st) {
+hipError_t launch_point_pass_joint(const StepArgs &a, const StepScratch &s, hipStream_t st, const KeyArgs *kp,
+                                  const CorrScratch *c) {
     const unsigned ptb = nblk(a.pts.n > 0 ? a.pts.n : 1, kPtBlock);
+    KeyArgs kk{};
+    float *kd = nullptr;
+    double *ke = nullptr;
+    if (kp && c && kp->count > 0) {
+        kk = *kp;
+        kd = c->kp_data;
+        ke = c->kp_energy;
+    }
+    const unsigned kpb = (unsigned)((kk.count + kPtBlock - 1) / kPtBlock);
     switch (a.g.k) {
 #define MSL_PJ_CASE(KK)                                                                                     \
-    case KK: hipLaunchKernelGGL((point_pass_joint_kernel<KK>), dim3(ptb), dim3(kPtBlock), 0, st, a, s); break;
+    case KK:                                                                                                \
+        hipLaunchKernelGGL((point_pass_joint_kernel<KK>), dim3(ptb + kpb), dim3(kPtBlock), 0, st, a, s, kk, kd, ke, \
+                           ptb);                                                                            \
+        break;
         MSL_PJ_CASE(1) MSL_PJ_CASE(2) MSL_PJ_CASE(3) MSL_PJ_CASE(4)
         MSL_PJ_CASE(5) MSL_PJ_CASE(6) MSL_PJ_CASE(7) MSL_PJ_CASE(8)
 #undef MSL_PJ_CASE

@@ -280,19 +280,22 @@ def lm_register(points, nodes, x, graph, depth, cam, pose_, params, ws, lm=None,
     return rep, ch
 
 
-def joint_register(points, nodes, x, graph, depth, cam, pose_, params, ws, w_r=1e6, w_p=1e3, corr_hist=False):
-    """Joint registration of the rigid pose and the ED graph (Eq.(10) pose terms, weights of Sec. III-B);
-    updates x in place.  Returns (report, pose (12,) float32 device tensor: R row-major then T, corr_hist or
-    None)."""
+def joint_register(points, nodes, x, graph, depth, cam, pose_, params, ws, w_r=1e6, w_p=1e3, corr_hist=False,
+                   keys=None):
+    """Joint registration of the rigid pose and the ED graph (Eq.(10) pose terms, weights of Sec. III-B),
+    with the Eq.(9) key points when keys is given; updates x in place.  Returns (report, pose (12,) float32
+    device tensor: R row-major then T, corr_hist or None)."""
     n, m = points.shape[1], nodes.shape[1]
     rep = new_report(params.gn_iters + 1)
     ch = torch.empty((params.gn_iters, n), dtype=torch.int32, device=points.device) if corr_hist else None
     pose_out = torch.empty(12, dtype=torch.float32, device=points.device)
     buf = ws.get(workspace_bytes(n, m, cam.width, cam.height, params))
     pw = _lib.PoseWeights(float(w_r), float(w_p))
+    kc = keys.c() if keys is not None else None
     check("misslam_joint_register", load().misslam_joint_register(
         ctypes.byref(points_struct(points)), ctypes.byref(nodes_struct(nodes, x)), ctypes.byref(graph.c()),
-        _ptr(depth), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(pw), ctypes.byref(params.c()),
+        _ptr(depth), ctypes.byref(cam), ctypes.byref(pose_), ctypes.byref(pw),
+        ctypes.byref(kc) if kc is not None else None, ctypes.byref(params.c()),
         _ptr(pose_out), _ptr(rep), _ptr(ch), _ptr(buf), ctypes.c_size_t(buf.numel()), _stream()))
     return rep, pose_out, ch
 

@@ -182,15 +182,17 @@ def test_validation_errors(lib):
     # joint pose: weights and an output pose are required, weights finite and >= 0; float32 form only
     jr = lib.misslam_joint_register
     pw = _lib.PoseWeights(1e6, 1e3)
-    assert jr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), None, B(p), FAKE, FAKE, None, FAKE, 1 << 40,
+    assert jr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), None, None, B(p), FAKE, FAKE, None, FAKE, 1 << 40,
               None) == _lib.EINVAL
-    assert jr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(pw), B(p), None, FAKE, None, FAKE, 1 << 40,
+    assert jr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(pw), None, B(p), None, FAKE, None, FAKE, 1 << 40,
               None) == _lib.EINVAL
     for bad in (_lib.PoseWeights(-1.0, 1e3), _lib.PoseWeights(1e6, float("nan")), _lib.PoseWeights(float("inf"), 1.0)):
-        assert jr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(bad), B(p), FAKE, FAKE, None, FAKE, 1 << 40,
+        assert jr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(bad), None, B(p), FAKE, FAKE, None, FAKE, 1 << 40,
                   None) == _lib.EINVAL
-    assert jr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(pw), B(plp), FAKE, FAKE, None, FAKE, 1 << 40,
+    assert jr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(pw), None, B(plp), FAKE, FAKE, None, FAKE, 1 << 40,
               None) == _lib.EUNSUPPORTED
+    assert jr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(pw), B(_lib.Keypoints(-1, 10.0, FAKE, FAKE)), B(p),
+              FAKE, FAKE, None, FAKE, 1 << 40, None) == _lib.EINVAL
     # colour fusion needs the image and the colours
     fp = _lib.FuseParams(10.0, 0.98, 20.0, 1)
     fc = lib.misslam_fuse_color

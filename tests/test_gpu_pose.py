@@ -79,3 +79,34 @@ def test_zero_steps_keep_the_pose(lib):
     assert np.array_equal(Rg, R0) and np.array_equal(Tg, T0)
     assert len(r) == 1 and r[0]["e_pose_r"] == 0.0 and r[0]["e_pose_p"] == 0.0
     assert np.array_equal(xg, s.M.identity_params(s.m).cpu().numpy())
+
+
+def test_joint_with_keypoints_matches_oracle(lib):
+    """All six terms of Eq.(3) together: the joint pose with 200 key points (their rows gain the pose columns
+    [-[v~]x, I]; their part of the border and of the pose block)."""
+    import gen
+    s = Scene("c2")
+    kp, tgt = gen.keypoints(s.sc, 200, seed=7, noise=0.05)
+    keys = s.M.keypoints(torch.tensor(kp, device="cuda"), torch.tensor(tgt, device="cuda").contiguous(), 10.0)
+    x = s.M.identity_params(s.m)
+    rep, pose, ch = s.M.joint_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, s.params, s.ws,
+                                       corr_hist=True, keys=keys)
+    torch.cuda.synchronize()
+    P = pose.cpu().numpy().astype(np.float64)
+    Rg, Tg, xg, r = P[:9].reshape(3, 3), P[9:], x.cpu().numpy(), s.M.read_report(rep)
+    cs = list(ch.cpu().numpy())
+    pb = s.problem(kp_point=kp, kp_target=tgt, w_corr=10.0)
+    xo, Ro, To, orep = joint_register(pb, graph=s.oracle_graph_from_gpu(), corr_sequence=cs)
+    x0 = oracle.identity_params(s.m)
+    T0 = pb.T.astype(np.float64)
+    print("joint+kp x rel", rel_err(xg, xo), "delta rel", rel_err(xg - x0, xo - x0), "|dT|", np.abs(Tg - To).max(),
+          "moved", np.abs(To - T0).max(), "e_corr", r["e_corr"][[0, -1]].tolist(), orep["final"]["e_corr"])
+    assert rel_err(xg, xo) < 1e-4
+    assert rel_err(xg - x0, xo - x0) < 1e-3
+    assert np.abs(Rg - Ro).max() <= 1e-3 * np.abs(Ro - pb.R).max() + 2e-7
+    assert np.abs(Tg - To).max() <= 1e-3 * np.abs(To - T0).max() + 2e-5
+    for k in range(pb.gn_iters):
+        assert r[k]["e_corr"] == pytest.approx(orep["iters"][k]["e_corr"], rel=1e-4)
+        assert r[k]["e_data"] == pytest.approx(orep["iters"][k]["e_data"], rel=1e-4)
+        assert r[k]["e_pose_p"] == pytest.approx(orep["iters"][k]["e_p"], rel=2e-3, abs=1e-9)
+    assert np.all(r["flags"] == 0)
