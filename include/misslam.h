@@ -62,6 +62,10 @@ typedef enum {
                                         long sets MISSLAM_FLAG_SYNC_TIMEOUT */
 #define MISSLAM_LAUNCH_COOPERATIVE 1 /* a cooperative launch: residency guaranteed by the runtime, at about
                                         15 us more per solve */
+#define MISSLAM_LAUNCH_KERNELS 2     /* no one-launch solve: one launch per PCG phase, nothing depends on
+                                        residency (the path taken anyway when the grid does not fit); the
+                                        same results to rounding (bitwise for the joint pose form); not for
+                                        batches (MISSLAM_EUNSUPPORTED) */
 
 #define MISSLAM_PREC_FP32 0       /* plain float32 normal equations */
 #define MISSLAM_PREC_BF16 1       /* data-term products in bfloat16 on the matrix cores, float32 accumulation */

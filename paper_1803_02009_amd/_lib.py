@@ -13,7 +13,7 @@ FLAG_NONSPD_BLOCK, FLAG_PCG_BREAKDOWN, FLAG_NONFINITE, FLAG_FRAME_REJECT, FLAG_G
 FLAG_SYNC_TIMEOUT = 32
 WEIGHT_GAUSS, WEIGHT_LINEAR = 0, 1
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
-LAUNCH_PLAIN, LAUNCH_COOPERATIVE = 0, 1
+LAUNCH_PLAIN, LAUNCH_COOPERATIVE, LAUNCH_KERNELS = 0, 1, 2
 MAX_K, MAX_PCG, MAX_ROW, MAX_LIST, SOLVE_ROWS = 8, 64, 32, 2048, 16
 MAX_KEYPOINTS = 1 << 24
 

@@ -196,7 +196,8 @@ bool valid_params(const misslam_params *p) {
            p->pcg_iters <= MISSLAM_MAX_PCG && std::isfinite(p->lambda) && p->lambda >= 0.f &&
            std::isfinite(p->w_rot) && std::isfinite(p->w_reg) && std::isfinite(p->w_data) &&
            p->precision >= MISSLAM_PREC_FP32 && p->precision <= MISSLAM_PREC_FP16 && p->refine_steps >= 0 &&
-           (p->solve_launch == MISSLAM_LAUNCH_PLAIN || p->solve_launch == MISSLAM_LAUNCH_COOPERATIVE);
+           (p->solve_launch == MISSLAM_LAUNCH_PLAIN || p->solve_launch == MISSLAM_LAUNCH_COOPERATIVE ||
+            p->solve_launch == MISSLAM_LAUNCH_KERNELS);
 }
 
 bool valid_points(const misslam_points *p) {
@@ -343,10 +344,11 @@ static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, i
 static hipError_t solve_persistent(const msl::GraphView &g, int m, const float *blocks, const float *gvec,
                                    const float *minv, float lambda, int iters, float *delta, const msl::PcgScratch &s,
                                    misslam_report *rep, float *params, hipStream_t st, bool coop,
-                                   int zeroed_words = 0, const float *lambda_dev = nullptr) {
+                                   int zeroed_words = 0, const float *lambda_dev = nullptr, bool kernels = false) {
     bool used = false;
-    hipError_t e = msl::launch_pcg_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st,
-                                              &used, coop, zeroed_words, lambda_dev);
+    hipError_t e = kernels ? hipSuccess
+                           : msl::launch_pcg_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep,
+                                                        params, st, &used, coop, zeroed_words, lambda_dev);
     if (e == hipSuccess && !used)
         e = msl::launch_pcg_update(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st, lambda_dev);
     return e;
@@ -354,7 +356,7 @@ static hipError_t solve_persistent(const msl::GraphView &g, int m, const float *
 
 static hipError_t solve(const msl::GraphView &g, int m, const float *blocks, const float *gvec, float *minv,
                         float lambda, int iters, float *delta, const msl::PcgScratch &s, misslam_report *rep,
-                        float *params, hipStream_t st, bool coop) {
+                        float *params, hipStream_t st, bool coop, bool kernels = false) {
     hipError_t e;
     {
         Timed t(PH_BJACOBI, st);
@@ -362,7 +364,8 @@ static hipError_t solve(const msl::GraphView &g, int m, const float *blocks, con
     }
     if (e == hipSuccess) {
         Timed t(PH_PCG, st);
-        e = solve_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st, coop);
+        e = solve_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st, coop, 0, nullptr,
+                             kernels);
     }
     return e;
 }
@@ -432,7 +435,8 @@ misslam_status misslam_pcg_solve(const misslam_graph *graph, int32_t m, const fl
     hipError_t e = msl::launch_report_init(rep, 1, st);
     if (e == hipSuccess)
         e = solve(gv, m, blocks, g, L.step.minv, params->lambda, params->pcg_iters, delta, L.pcg, rep, nullptr, st,
-                  params->solve_launch == MISSLAM_LAUNCH_COOPERATIVE);
+                  params->solve_launch == MISSLAM_LAUNCH_COOPERATIVE,
+                  params->solve_launch == MISSLAM_LAUNCH_KERNELS);
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
 }
 
@@ -467,6 +471,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
     if ((int64_t)graph->bsr_cap > (int64_t)nodes->m * MISSLAM_MAX_ROW) return MISSLAM_ECAPACITY;
     const bool lowp = params->precision != MISSLAM_PREC_FP32;
     const bool coop = params->solve_launch == MISSLAM_LAUNCH_COOPERATIVE;
+    const bool kernels = params->solve_launch == MISSLAM_LAUNCH_KERNELS;
     const hipStream_t st = stream_of(stream);
     const int G = params->gn_iters;
     const int64_t n = points->n;
@@ -545,7 +550,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
                 Timed t(PH_PCG, st);
                 e = msl::launch_joint_pcg(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda,
                                           params->pcg_iters, L.delta, L.pcg, L.joint, rep + it, nodes->params,
-                                          pose_out, st);
+                                          pose_out, st, kernels);
             }
             continue;
         }
@@ -569,7 +574,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
                 Timed t(PH_PCG, st);
                 e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
                                      L.delta, L.pcg, rep + it, lm ? nullptr : nodes->params, st, coop,
-                                     msl::msl_sync_words(m), lm ? L.lm_lambda : nullptr);
+                                     msl::msl_sync_words(m), lm ? L.lm_lambda : nullptr, kernels);
             }
             if (e == hipSuccess && lm) {
                 // the trial point x + dx: its objective decides whether the step is taken
@@ -605,7 +610,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
         if (e == hipSuccess) {
             Timed t(PH_PCG, st);
             e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
-                                 L.delta, L.pcg, rep + it, nullptr, st, coop);
+                                 L.delta, L.pcg, rep + it, nullptr, st, coop, 0, nullptr, kernels);
         }
         for (int r = 0; r < params->refine_steps && e == hipSuccess; ++r) {
             {
@@ -615,7 +620,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
             if (e == hipSuccess) {
                 Timed t(PH_PCG, st);
                 e = solve_persistent(view(graph), m, L.blocks, L.rhs, L.step.minv, params->lambda, params->pcg_iters,
-                                     L.delta2, L.pcg, L.rep, nullptr, st, coop);
+                                     L.delta2, L.pcg, L.rep, nullptr, st, coop, 0, nullptr, kernels);
             }
             if (e == hipSuccess) e = msl::launch_axpy(L.delta, L.delta2, 12 * m, st);
         }
@@ -1113,7 +1118,8 @@ misslam_status misslam_batch_create(const misslam_problem *problems, int32_t cou
     if (!problems || count < 1 || count > 1024 || !valid_params(params) || !out || rows_per_wg < 0 ||
         rows_per_wg > 21)
         return MISSLAM_EINVAL;
-    if (params->precision != MISSLAM_PREC_FP32) return MISSLAM_EUNSUPPORTED;
+    if (params->precision != MISSLAM_PREC_FP32 || params->solve_launch == MISSLAM_LAUNCH_KERNELS)
+        return MISSLAM_EUNSUPPORTED;
     for (int i = 0; i < count; ++i) {
         const misslam_problem &p = problems[i];
         if (!valid_points(&p.points) || !valid_nodes(&p.nodes) || !valid_graph(&p.graph, p.points.n) || !p.depth ||

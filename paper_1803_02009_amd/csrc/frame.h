@@ -289,9 +289,12 @@ hipError_t launch_pose_setup(const float *pose_dev, const PosePrior &pr, const d
                              unsigned long long *jbar = nullptr, int m = 0, const KeyArgs *kp = nullptr,
                              const CorrScratch *c = nullptr, int64_t n = 0, int k = 4);
 // Joint PCG into delta (12 m) and the pose step; applies params += delta and the pose step unless non-finite.
+// One launch when every workgroup fits at once, else (or with kernels) one launch per phase: the same
+// partition and reduction order, so the same bits.
 hipError_t launch_joint_pcg(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                             float lambda, int iters, float *delta, const PcgScratch &s, const JointScratch &js,
-                            misslam_report *rep, float *params, float *pose_dev, hipStream_t st);
+                            misslam_report *rep, float *params, float *pose_dev, hipStream_t st,
+                            bool kernels = false);
 // The list-entry packing the assembly reads; run once per registration (the graph, canonical points and node
 // positions are fixed across its Gauss-Newton steps) before the first launch_assemble.
 hipError_t launch_list_pack(const StepArgs &a, const StepScratch &s, hipStream_t st);

@@ -382,15 +382,18 @@ __global__ void __launch_bounds__(kJThreads) jpcg_init_kernel(JArgs J) {
                 for (int w = 0; w < 6; ++w) t += J.sys[42 + 6 * u + w] * rp[w];
                 zp[u] = t;
             }
+            double rz_p = 0.0, rr_p = 0.0;   // summed apart, then added: the one-launch solve's order
             for (int u = 0; u < 6; ++u) {
-                rz += rp[u] * zp[u];
-                rr += rp[u] * rp[u];
+                rz_p += rp[u] * zp[u];
+                rr_p += rp[u] * rp[u];
                 J.pst[u] = rp[u];
                 J.pst[6 + u] = zp[u];
                 J.pst[12 + u] = 0.0;
                 J.pst[18 + u] = 0.0;
                 J.pst[24 + u] = 0.0;
             }
+            rz += rz_p;
+            rr += rr_p;
         }
         J.jpart[(size_t)0 * A.nblk + blockIdx.x] = rz;
         J.jpart[(size_t)1 * A.nblk + blockIdx.x] = rr;
@@ -537,25 +540,28 @@ __global__ void __launch_bounds__(kJThreads) jpcg_step_kernel(JArgs J, int it) {
     if (threadIdx.x == 0) {
         if (blockIdx.x == 0) {   // the pose step, stored for the next iteration
             double *nxt = J.pst + (size_t)(it + 1) * kPst;
-            double rp[6], zp[6];
+            double rp[6], zp[6], rz_p = 0.0, rr_p = 0.0, nb_p = 0.0;
             for (int u = 0; u < 6; ++u) {
                 rp[u] = upd ? ps[u] - (double)alpha * ps[18 + u] : ps[u];
                 nxt[24 + u] = upd ? ps[24 + u] + (double)alpha * ps[12 + u] : ps[24 + u];
-                if (!isfinite(nxt[24 + u])) nb += 1.0;
+                if (!isfinite(nxt[24 + u])) nb_p += 1.0;
             }
             for (int u = 0; u < 6; ++u) {
                 double t = 0.0;
                 for (int w = 0; w < 6; ++w) t += J.sys[42 + 6 * u + w] * rp[w];
                 zp[u] = upd ? t : ps[6 + u];
             }
-            for (int u = 0; u < 6; ++u) {
-                rzn += rp[u] * zp[u];
-                rrn += rp[u] * rp[u];
+            for (int u = 0; u < 6; ++u) {   // summed apart, then added: the one-launch solve's order
+                rz_p += rp[u] * zp[u];
+                rr_p += rp[u] * rp[u];
                 nxt[u] = rp[u];
                 nxt[6 + u] = zp[u];
                 nxt[12 + u] = ps[12 + u];
                 nxt[18 + u] = ps[18 + u];
             }
+            rzn += rz_p;
+            rrn += rr_p;
+            nb += nb_p;
             A.status[it + 1] = st != 0 ? st : (brk ? 2 : 0);
             A.done[it] = upd ? 1 : 0;
         }
@@ -870,7 +876,7 @@ __global__ void __launch_bounds__(kJThreads) jpcg_persistent_kernel(JArgs J, uns
 
 hipError_t launch_joint_pcg(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                             float lambda, int iters, float *delta, const PcgScratch &s, const JointScratch &js,
-                            misslam_report *rep, float *params, float *pose_dev, hipStream_t st) {
+                            misslam_report *rep, float *params, float *pose_dev, hipStream_t st, bool kernels) {
     JArgs J;
     PcgArgs &A = J.A;
     A.row_ptr = g.row_ptr;
@@ -902,7 +908,7 @@ hipError_t launch_joint_pcg(const GraphView &g, int m, const float *blocks, cons
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             cus = 0;
     }
-    if (js.jbar && A.nblk <= cus && A.nblk <= kJMaxWgs) {   // every workgroup resident: one launch
+    if (!kernels && js.jbar && A.nblk <= cus && A.nblk <= kJMaxWgs) {   // every workgroup resident: one launch
         hipLaunchKernelGGL(jpcg_persistent_kernel, dim3(A.nblk), dim3(kJThreads), 0, st, J, js.jbar, A.nblk, rep,
                            params, pose_dev);
         return hipGetLastError();

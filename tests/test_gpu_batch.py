@@ -96,3 +96,12 @@ def test_batch_autotuned_tile(problems):
         assert rel_err(x1[i], xs[i]) < 1e-5
         assert r1[i][-1]["e_data"] == pytest.approx(reps[i][-1]["e_data"], rel=1e-4)
         assert np.array_equal(r1[i]["n_valid"][:1], reps[i]["n_valid"][:1])
+
+
+def test_batch_rejects_per_phase_launches(problems):
+    """The batch always runs its solve in one launch: the per-phase launch form is refused at creation."""
+    import dataclasses
+    from paper_1803_02009_amd import _lib
+    p = dataclasses.replace(problems[0].params, solve_launch=_lib.LAUNCH_KERNELS)
+    with pytest.raises(_lib.MisslamError, match="unsupported"):
+        _batch(problems, SOLVE_ROWS, calls=1, params=p)

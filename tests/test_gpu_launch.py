@@ -1,29 +1,63 @@
-"""The one-launch PCG started as a plain launch (the default) and as a cooperative launch.
+"""The PCG solves in their three launch forms.
 
-Both run the same kernel over the same partition, so parameters and reports
-must be bitwise equal, with no workgroup giving up its waits.
+The one-launch PCG started as a plain launch (the default) and as a
+cooperative launch runs the same kernel over the same partition: parameters
+and reports must be bitwise equal, with no workgroup giving up its waits.
+The per-phase launches (no residency needed) take the same steps in another
+reduction order for the fixed-pose solve (equal to rounding) and in the same
+order for the joint pose form (bitwise equal).
 """
 import dataclasses
 
 import numpy as np
 import pytest
+import torch
 
 from paper_1803_02009_amd import _lib
-from gpu_util import Scene
+from gpu_util import Scene, rel_err
 
 pytestmark = pytest.mark.gpu
+
+
+def _fixed(s, mode):
+    p = dataclasses.replace(s.params, solve_launch=mode)
+    x = s.M.identity_params(s.m)
+    rep, _ = s.M.gn_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, p, s.ws)
+    return x.cpu().numpy(), s.M.read_report(rep)
 
 
 @pytest.mark.parametrize("case", ["c2", "c3"])
 def test_plain_and_cooperative_launch_agree_bitwise(lib, case):
     s = Scene(case)
-    out = {}
-    for mode in (_lib.LAUNCH_PLAIN, _lib.LAUNCH_COOPERATIVE):
+    (x0, r0), (x1, r1) = _fixed(s, _lib.LAUNCH_PLAIN), _fixed(s, _lib.LAUNCH_COOPERATIVE)
+    assert np.array_equal(x0.view(np.uint32), x1.view(np.uint32))
+    assert r0.tobytes() == r1.tobytes()
+    assert np.all(r0["flags"] == 0)
+
+
+def test_per_phase_launches_agree_to_rounding(lib):
+    s = Scene("c2")
+    (x0, r0), (x1, r1) = _fixed(s, _lib.LAUNCH_PLAIN), _fixed(s, _lib.LAUNCH_KERNELS)
+    x_id = s.M.identity_params(s.m).cpu().numpy()
+    print("per-phase vs one launch: x rel", rel_err(x1, x0), "delta rel", rel_err(x1 - x_id, x0 - x_id))
+    assert rel_err(x1 - x_id, x0 - x_id) < 1e-4
+    for k in range(len(r0)):
+        assert r1[k]["e_data"] == pytest.approx(r0[k]["e_data"], rel=1e-4)
+        assert r1[k]["pcg_resid"] == pytest.approx(r0[k]["pcg_resid"], rel=1e-2, abs=1e-6)
+    assert np.all(r0["flags"] == 0) and np.all(r1["flags"] == 0)
+
+
+def test_joint_per_phase_launches_agree_bitwise(lib):
+    s = Scene("c2")
+    out = []
+    for mode in (_lib.LAUNCH_PLAIN, _lib.LAUNCH_KERNELS):
         p = dataclasses.replace(s.params, solve_launch=mode)
         x = s.M.identity_params(s.m)
-        rep, _ = s.M.gn_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, p, s.ws)
-        out[mode] = (x.cpu().numpy(), s.M.read_report(rep))
-    (x0, r0), (x1, r1) = out[_lib.LAUNCH_PLAIN], out[_lib.LAUNCH_COOPERATIVE]
+        rep, pose, _ = s.M.joint_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, p, s.ws)
+        torch.cuda.synchronize()
+        out.append((x.cpu().numpy(), pose.cpu().numpy(), s.M.read_report(rep)))
+    (x0, P0, r0), (x1, P1, r1) = out
     assert np.array_equal(x0.view(np.uint32), x1.view(np.uint32))
+    assert np.array_equal(P0.view(np.uint32), P1.view(np.uint32))
     assert r0.tobytes() == r1.tobytes()
     assert np.all(r0["flags"] == 0)
