@@ -680,6 +680,7 @@ __global__ void __launch_bounds__(kJThreads) jpcg_persistent_kernel(JArgs J, uns
     __shared__ double ps[kPst];          // pose r, z, p, q, x (the same in every workgroup)
     __shared__ double pshare[2];         // this iteration's pose p.q; pose r.z / r.r partial
     __shared__ double resid[MISSLAM_MAX_PCG + 1];
+    __shared__ double sysl[78];          // H_pp, g_p, (H_pp + lambda I)^-1: read by the serial pose steps
     const int wg = blockIdx.x;
     const int row = threadIdx.x / 12, a = threadIdx.x % 12;
     const int j = wg * kJRows + row;
@@ -698,12 +699,14 @@ __global__ void __launch_bounds__(kJThreads) jpcg_persistent_kernel(JArgs J, uns
         r = -A.g[o];
         rl[row][a] = r;
     }
+    if (threadIdx.x < 78) sysl[threadIdx.x] = J.sys[threadIdx.x];
+    __syncthreads();
     if (threadIdx.x == 0) {
         double rz_p = 0.0, rr_p = 0.0;
-        for (int u = 0; u < 6; ++u) ps[u] = -J.sys[36 + u];
+        for (int u = 0; u < 6; ++u) ps[u] = -sysl[36 + u];
         for (int u = 0; u < 6; ++u) {
             double t = 0.0;
-            for (int w = 0; w < 6; ++w) t += J.sys[42 + 6 * u + w] * ps[w];
+            for (int w = 0; w < 6; ++w) t += sysl[42 + 6 * u + w] * ps[w];
             ps[6 + u] = t;
             ps[12 + u] = 0.0;
             ps[18 + u] = 0.0;
@@ -776,7 +779,7 @@ __global__ void __launch_bounds__(kJThreads) jpcg_persistent_kernel(JArgs J, uns
             double qp[6], pp[6], t = 0.0;
             for (int u = 0; u < 6; ++u) {
                 double az = t7[1 + u];
-                for (int w = 0; w < 6; ++w) az += J.sys[6 * u + w] * ps[6 + w];
+                for (int w = 0; w < 6; ++w) az += sysl[6 * u + w] * ps[6 + w];
                 az += lam * ps[6 + u];
                 qp[u] = it > 0 ? (double)beta * ps[18 + u] + az : az;
                 pp[u] = it > 0 ? (double)beta * ps[12 + u] + ps[6 + u] : ps[6 + u];
@@ -812,7 +815,7 @@ __global__ void __launch_bounds__(kJThreads) jpcg_persistent_kernel(JArgs J, uns
             }
             for (int u = 0; u < 6; ++u) {
                 double t = 0.0;
-                for (int w = 0; w < 6; ++w) t += J.sys[42 + 6 * u + w] * ps[w];
+                for (int w = 0; w < 6; ++w) t += sysl[42 + 6 * u + w] * ps[w];
                 ps[6 + u] = t;
             }
             for (int u = 0; u < 6; ++u) {
