@@ -130,3 +130,59 @@ def test_c3_end_to_end_against_stored_oracle(c3):
     assert rel_err(xg - xi, xo - xi) < 1e-4
     assert r[-1]["e_data"] == pytest.approx(float(gold["e_data_final"]), rel=1e-4)
     assert np.all((r["flags"] & ~8) == 0)
+
+
+def _against_stored(s, x, rep, name, e_rel):
+    """Parameters and final data energy of a full-frame run against a stored oracle run of the same problem."""
+    gold = np.load(os.path.join(HERE, "golden", f"c3_{name}_oracle.npz"))
+    r = s.M.read_report(rep)
+    xg = x.cpu().numpy().astype(np.float64)
+    xo = gold["x"]
+    xi = oracle.identity_params(s.m)
+    print(name, "x rel", rel_err(xg, xo), "delta rel", rel_err(xg - xi, xo - xi), "e_data rel",
+          abs(r[-1]["e_data"] - float(gold["e_data_final"])) / float(gold["e_data_final"]))
+    assert rel_err(xg, xo) < 1e-5
+    assert rel_err(xg - xi, xo - xi) < 1e-4
+    assert r[-1]["e_data"] == pytest.approx(float(gold["e_data_final"]), rel=e_rel)
+    assert np.all((r["flags"] & ~8) == 0)
+    return gold, r
+
+
+def test_c3_keypoints_against_stored_oracle(c3):
+    """The frame with 500 key-point matches (Eq.(9), w_corr = 10), as the benchmark runs it."""
+    import gen
+    s = c3
+    kp, tgt = gen.keypoints(s.sc, 500, seed=7, noise=0.05)
+    keys = s.M.keypoints(torch.tensor(kp, device="cuda"), torch.tensor(tgt, device="cuda").contiguous(), 10.0)
+    x = s.M.identity_params(s.m)
+    rep, _ = s.M.gn_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, s.params, s.ws, keys=keys)
+    gold, r = _against_stored(s, x, rep, "kp500", 1e-4)
+    assert r[-1]["e_corr"] == pytest.approx(float(gold["e_corr_final"]), rel=1e-4)
+
+
+def test_c3_adaptive_lm_against_stored_oracle(c3):
+    """The frame with the default adaptive schedule: the same accept / reject decisions and damping values as
+    the stored oracle run (no decisions adopted from the GPU here)."""
+    s = c3
+    x = s.M.identity_params(s.m)
+    rep, _ = s.M.lm_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, s.params, s.ws,
+                             lm=s.M.LMParams())
+    gold, r = _against_stored(s, x, rep, "lm", 1e-4)
+    G = s.params.gn_iters
+    assert [bool(v) for v in r["lm_accepted"][:G]] == [bool(v) for v in gold["accepted"]]
+    np.testing.assert_allclose(r["lm_lambda"][:G], gold["lam"], rtol=1e-5)
+
+
+def test_c3_joint_pose_against_stored_oracle(c3):
+    """The frame with the pose as unknowns (Eq.(10), w_r = 1e6, w_p = 1e3).  The returned pose is float32, and
+    its rounding moves the data term more than the ED parameters do, hence the wider energy bar."""
+    s = c3
+    x = s.M.identity_params(s.m)
+    rep, pose, _ = s.M.joint_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, s.params, s.ws)
+    gold, r = _against_stored(s, x, rep, "joint", 2e-4)
+    P = pose.cpu().numpy().astype(np.float64)
+    T0 = np.asarray(s.sc["T"], np.float32).astype(np.float64)
+    moved = np.abs(gold["T"] - T0).max()
+    assert moved > 0.1   # the pose moves (mm)
+    assert np.abs(P[:9].reshape(3, 3) - gold["R"]).max() < 1e-5
+    assert np.abs(P[9:] - gold["T"]).max() < 1e-3 * max(moved, 1.0)
