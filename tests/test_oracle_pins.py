@@ -74,6 +74,22 @@ def test_gauss_weights_normalised_and_monotone(c1_graph):
     assert np.all(np.diff(w, axis=1) <= 1e-15)       # nearer nodes weigh more
 
 
+@pytest.mark.parametrize("sigma", [1.0, 2.5, 6.0])
+def test_gauss_weights_hand_values(sigma):
+    """Squared distances 0, sigma^2, 4 sigma^2 and 9 sigma^2 give raw weights 1, e^-1/2, e^-2, e^-9/2 (the
+    Gaussian of standard deviation sigma).  The decimals are the tabulated values of those exponentials, so a
+    weight of exp(-d^2 / sigma^2) (0.3679 at d = sigma) or one without the square fails."""
+    e_half, e_2, e_9half = 0.6065306597126334, 0.1353352832366127, 0.011108996538242306
+    raw = np.array([1.0, e_half, e_2, e_9half])
+    d2 = np.array([[0.0, 1.0, 4.0, 9.0, 16.0]]) * sigma * sigma
+    w = oracle.skin_weights(d2, 4, "gauss", sigma)
+    assert np.allclose(w[0], raw / 1.7529749395, rtol=0, atol=1e-10)
+    assert w[0, 1] / w[0, 0] == pytest.approx(e_half, rel=1e-14)
+    # the fifth node's distance plays no part in the Gaussian kind
+    w5 = oracle.skin_weights(np.array([[0.0, 1.0, 4.0, 9.0, 1e6]]) * sigma * sigma, 4, "gauss", sigma)
+    assert np.array_equal(w, w5)
+
+
 # ---------------------------------------------------------------- node graph
 def test_node_graph_is_symmetric_coinfluence(c1_graph):
     nb = c1_graph["nbrs"]
@@ -110,6 +126,44 @@ def test_rigid_field_reproduced_exactly(c1, c1_graph):
     rr, _, _ = reg_residuals(x, G, c1_graph["nbrs"])
     assert np.abs(rr).max() < 1e-12
     assert np.abs(oracle.rot_residuals(x)).max() < 1e-14
+
+
+@pytest.mark.parametrize("kind", ["stretch", "shear"])
+def test_warped_normal_is_normal_to_the_warped_surface(c1, c1_graph, kind):
+    """With one non-orthogonal affine map shared by every node the warp of Eq.(1) is that affine map, so the
+    warped surface is known by geometry: a tangent step v + h t (t orthogonal to n) lands on the warped
+    surface, and the warped normal must be orthogonal to every warped tangent step (and point to the same
+    side as the mapped normal).  The warped tangents come from ed_warp itself, not from a retyped formula;
+    mapping normals by A (instead of its inverse transpose) tilts them by several degrees here and fails."""
+    if kind == "stretch":
+        A = np.diag([2.0, 1.0, 0.7])
+    else:
+        A = np.array([[1.0, 0.6, 0.0], [0.0, 1.0, 0.3], [0.2, 0.0, 1.0]])
+    G = c1["nodes"].astype(np.float64)
+    c = np.array([0.4, -1.1, 0.8])
+    x = params_from(np.repeat(A[None], len(G), axis=0), G @ A.T + c - G)
+    P = c1["points"].astype(np.float64)[::7]
+    Nn = c1["normals"].astype(np.float64)[::7]
+    idx, w = c1_graph["idx"][::7], c1_graph["w"][::7]
+    nrm = oracle.warp_normals(Nn, x, idx, w)
+    base = oracle.ed_warp(P, G, x, idx, w)
+    # two tangent directions per point, orthogonal to its normal
+    ref = np.where(np.abs(Nn[:, :1]) < 0.9, np.array([[1.0, 0, 0]]), np.array([[0, 1.0, 0]]))
+    t1 = np.cross(Nn, ref)
+    t1 /= np.linalg.norm(t1, axis=1, keepdims=True)
+    t2 = np.cross(Nn, t1)
+    h = 0.01
+    for t in (t1, t2):
+        step = oracle.ed_warp(P + h * t, G, x, idx, w) - base
+        cosang = np.sum(nrm * step, axis=1) / np.linalg.norm(step, axis=1)
+        assert np.abs(cosang).max() < 1e-11
+    assert np.all(np.sum(nrm * (Nn @ A.T), axis=1) > 0)
+    assert np.allclose(np.linalg.norm(nrm, axis=1), 1.0, atol=1e-14)
+    # the mapping by A itself is measurably off the surface normal (the pin discriminates)
+    bad = Nn @ A.T
+    bad /= np.linalg.norm(bad, axis=1, keepdims=True)
+    step = oracle.ed_warp(P + h * t1, G, x, idx, w) - base
+    assert np.abs(np.sum(bad * step, axis=1) / np.linalg.norm(step, axis=1)).max() > 0.05
 
 
 # ---------------------------------------------------------------- P2 identity
