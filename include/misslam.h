@@ -74,7 +74,7 @@ typedef enum {
 #define MISSLAM_MAX_K    8
 #define MISSLAM_MAX_PCG  64
 #define MISSLAM_MAX_ROW  32       /* max blocks per row of the normal matrix (node degree + 1) */
-#define MISSLAM_MAX_LIST 2048     /* max points influenced by one node */
+#define MISSLAM_MAX_LIST 2048     /* node lists up to this length are sorted in one LDS pass; longer ones are merged */
 #define MISSLAM_MAX_KEYPOINTS 16777216   /* max key points per registration (2^24) */
 #define MISSLAM_SOLVE_ROWS 16     /* node rows per workgroup of the one-launch PCG of a single problem
                                      with at most 16 rows per CU (larger ones pack up to 21) */
@@ -142,6 +142,8 @@ typedef struct {
     int32_t refine_steps;      /* iterative-refinement steps for BF16/FP16 */
     float reject_threshold;    /* mean |r| above which FRAME_REJECT is set; <= 0 disables */
     int32_t solve_launch;      /* MISSLAM_LAUNCH_*: how the one-launch PCG is started */
+    int32_t sync_spin_limit;   /* polls of one wait in the one-launch solves before they give up
+                                  (MISSLAM_FLAG_SYNC_TIMEOUT, the step discarded); 0: 262144 */
 } misslam_params;
 
 /* one entry per Gauss-Newton iteration, plus a final entry at the returned parameters (device) */
@@ -232,8 +234,10 @@ misslam_status misslam_normal_map(const float *depth, const misslam_camera *came
 /*
  * kNN sets, skinning weights (Eq.(2)), node graph N(j) (Eq.(6)), block pattern
  * and node -> point lists from the canonical points and nodes.  Capacities:
- * bsr_cap blocks; rows longer than MISSLAM_MAX_ROW or lists longer than
- * MISSLAM_MAX_LIST set graph->info[3] (the caller checks it after a sync).
+ * bsr_cap blocks; rows longer than MISSLAM_MAX_ROW (or a pattern beyond
+ * bsr_cap) set graph->info[3] = MISSLAM_FLAG_GRAPH_OVERFLOW; every report of a
+ * registration on that graph then carries the flag.  Node lists have no length
+ * limit (info[2] holds the longest).
  */
 misslam_status misslam_build_graph(const misslam_points *points, const misslam_nodes *nodes,
                                    const misslam_params *params, misslam_graph *graph, void *ws,

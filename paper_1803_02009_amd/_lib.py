@@ -57,7 +57,7 @@ class Params(ctypes.Structure):
                 ("eps_d", ctypes.c_double), ("cos_eps_n", ctypes.c_double), ("lambda_", ctypes.c_float),
                 ("gn_iters", ctypes.c_int32), ("pcg_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("refine_steps", ctypes.c_int32), ("reject_threshold", ctypes.c_float),
-                ("solve_launch", ctypes.c_int32)]
+                ("solve_launch", ctypes.c_int32), ("sync_spin_limit", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):

@@ -129,9 +129,25 @@ struct Layout {
     size_t bytes;
 };
 
-Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters, int k) {
+// Optional parts of the registration workspace.  Every entry point that takes a
+// caller workspace carves all of them (WS_ALL), so its layout does not depend on
+// the form it runs; the allocation-free registration carves the core only.
+enum : unsigned {
+    WS_CORE = 0,        // normal map, point pass, packed lists, system, solve
+    WS_GRAPH = 1u << 0, // kNN grid and pattern scratch (graph setup)
+    WS_FUSE = 1u << 1,  // fusion staging and z-buffer
+    WS_LOWP = 1u << 2,  // bf16/fp16 form: fp32 regulariser blocks, matrix-free refinement vectors
+    WS_KEYS = 1u << 3,  // key-point term
+    WS_JOINT = 1u << 4, // joint pose form
+    WS_LM = 1u << 5,    // adaptive damping: trial point and its report
+    WS_ALL = 63u
+};
+
+Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters, int k, unsigned parts = WS_ALL) {
     Carver c{static_cast<char *>(ws)};
     Layout L{};
+    const bool graph = parts & WS_GRAPH, fuse = parts & WS_FUSE, lowp = parts & WS_LOWP, keys = parts & WS_KEYS,
+               joint = parts & WS_JOINT, lm = parts & WS_LM;
     const int64_t npb = (n + 255) / 256 + 1;
     const int nblk = msl::pcg_blocks(m > 0 ? m : 1);
     const int nblk_max = nblk > 4096 ? nblk : 4096;
@@ -154,37 +170,42 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
     L.pcg.bar = c.take<unsigned>(msl::MSL_BAR_WORDS);
     L.pcg.nblk = nblk;
     L.pcg.nblk_max = nblk_max;
-    L.graph.tmp = c.take<int32_t>((size_t)m * MISSLAM_MAX_ROW);
-    L.fuse_tmp = c.take<float>((size_t)6 * n);
-    L.fuse_pix = c.take<int32_t>((size_t)n);
-    L.zbuf = c.take<unsigned long long>((size_t)W * H);
-    L.rep = c.take<misslam_report>(1);
-    const bool lp = pcg_iters >= 0;   // sized for every precision
-    L.rr = lp ? c.take<float>((size_t)m * MISSLAM_MAX_ROW * 144) : nullptr;
-    L.jv = c.take<float>((size_t)n);
-    L.rhs = c.take<float>((size_t)12 * m);
-    L.delta2 = c.take<float>((size_t)12 * m);
-    L.graph.cnt = c.take<int32_t>((size_t)2 * m + 8);
-    L.graph.grid.hdr = c.take<double>(4);
-    L.graph.grid.dims = c.take<int32_t>(4);
-    L.graph.grid.start = c.take<int32_t>((size_t)msl::MSL_GRID_CELLS + 1);
-    L.graph.grid.cursor = c.take<int32_t>((size_t)msl::MSL_GRID_CELLS);
-    L.graph.grid.nodes = c.take<float4>((size_t)m);
+    L.graph.tmp = graph ? c.take<int32_t>((size_t)m * MISSLAM_MAX_ROW) : nullptr;
+    L.fuse_tmp = fuse ? c.take<float>((size_t)6 * n) : nullptr;
+    L.fuse_pix = fuse ? c.take<int32_t>((size_t)n) : nullptr;
+    L.zbuf = fuse ? c.take<unsigned long long>((size_t)W * H) : nullptr;
+    L.rep = (lowp || lm) ? c.take<misslam_report>(1) : nullptr;
+    L.rr = lowp ? c.take<float>((size_t)m * MISSLAM_MAX_ROW * 144) : nullptr;
+    L.jv = lowp ? c.take<float>((size_t)n) : nullptr;
+    L.rhs = lowp ? c.take<float>((size_t)12 * m) : nullptr;
+    L.delta2 = (lowp || lm) ? c.take<float>((size_t)12 * m) : nullptr;
+    if (graph) {
+        L.graph.cnt = c.take<int32_t>((size_t)2 * m + 8);
+        L.graph.grid.hdr = c.take<double>(4);
+        L.graph.grid.dims = c.take<int32_t>(4);
+        L.graph.grid.start = c.take<int32_t>((size_t)msl::MSL_GRID_CELLS + 1);
+        L.graph.grid.cursor = c.take<int32_t>((size_t)msl::MSL_GRID_CELLS);
+        L.graph.grid.nodes = c.take<float4>((size_t)m);
+        L.graph.ltmp = c.take<int32_t>((size_t)k * n);
+    }
     // last, so that every buffer above keeps its place whatever k is
     L.step.lpa = c.take<float4>((size_t)k * n);
     L.step.lpw = c.take<float4>((size_t)k * n * ((k + 3) / 4));
-    L.corr.kp_nodes = c.take<int32_t>((size_t)k * n);
-    L.corr.kp_data = c.take<float>((size_t)(9 + 4 * k) * n);
-    L.corr.kp_energy = c.take<double>((size_t)n);
-    L.lm_lambda = c.take<float>(4);
-    // joint pose form
-    L.step.jp = c.take<float4>((size_t)2 * n);
-    L.step.pose_part = c.take<double>((size_t)msl::kPosePart * msl::point_blocks(n));
-    L.joint.B = c.take<float>((size_t)72 * m);
-    L.joint.sys = c.take<double>(80);
-    L.joint.jpart = c.take<double>((size_t)(pcg_iters + 2) * 10 * ((m + 20) / 21));
-    L.joint.pst = c.take<double>((size_t)(pcg_iters + 2) * 32);
-    L.joint.jbar = c.take<unsigned long long>((size_t)32 * 1024);
+    if (keys) {
+        L.corr.kp_nodes = c.take<int32_t>((size_t)k * n);
+        L.corr.kp_data = c.take<float>((size_t)(9 + 4 * k) * n);
+        L.corr.kp_energy = c.take<double>((size_t)n);
+    }
+    L.lm_lambda = lm ? c.take<float>(4) : nullptr;
+    if (joint) {
+        L.step.jp = c.take<float4>((size_t)2 * n);
+        L.step.pose_part = c.take<double>((size_t)msl::kPosePart * msl::point_blocks(n));
+        L.joint.B = c.take<float>((size_t)72 * m);
+        L.joint.sys = c.take<double>(80);
+        L.joint.jpart = c.take<double>((size_t)(pcg_iters + 2) * 10 * ((m + 20) / 21));
+        L.joint.pst = c.take<double>((size_t)(pcg_iters + 2) * 32);
+        L.joint.jbar = c.take<unsigned long long>((size_t)32 * 1024);
+    }
     L.bytes = align_up(c.off);
     return L;
 }
@@ -197,7 +218,8 @@ bool valid_params(const misslam_params *p) {
            std::isfinite(p->w_rot) && std::isfinite(p->w_reg) && std::isfinite(p->w_data) &&
            p->precision >= MISSLAM_PREC_FP32 && p->precision <= MISSLAM_PREC_FP16 && p->refine_steps >= 0 &&
            (p->solve_launch == MISSLAM_LAUNCH_PLAIN || p->solve_launch == MISSLAM_LAUNCH_COOPERATIVE ||
-            p->solve_launch == MISSLAM_LAUNCH_KERNELS);
+            p->solve_launch == MISSLAM_LAUNCH_KERNELS) &&
+           p->sync_spin_limit >= 0;
 }
 
 bool valid_points(const misslam_points *p) {
@@ -258,6 +280,7 @@ void misslam_default_params(misslam_params *p) {
     p->refine_steps = 0;
     p->reject_threshold = 0.0f;
     p->solve_launch = MISSLAM_LAUNCH_PLAIN;
+    p->sync_spin_limit = 0;
 }
 
 const char *misslam_status_string(int32_t s) {
@@ -344,11 +367,12 @@ static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, i
 static hipError_t solve_persistent(const msl::GraphView &g, int m, const float *blocks, const float *gvec,
                                    const float *minv, float lambda, int iters, float *delta, const msl::PcgScratch &s,
                                    misslam_report *rep, float *params, hipStream_t st, bool coop,
-                                   int zeroed_words = 0, const float *lambda_dev = nullptr, bool kernels = false) {
+                                   int zeroed_words = 0, const float *lambda_dev = nullptr, bool kernels = false,
+                                   unsigned spin = 0) {
     bool used = false;
     hipError_t e = kernels ? hipSuccess
                            : msl::launch_pcg_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep,
-                                                        params, st, &used, coop, zeroed_words, lambda_dev);
+                                                        params, st, &used, coop, zeroed_words, lambda_dev, spin);
     if (e == hipSuccess && !used)
         e = msl::launch_pcg_update(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st, lambda_dev);
     return e;
@@ -356,7 +380,7 @@ static hipError_t solve_persistent(const msl::GraphView &g, int m, const float *
 
 static hipError_t solve(const msl::GraphView &g, int m, const float *blocks, const float *gvec, float *minv,
                         float lambda, int iters, float *delta, const msl::PcgScratch &s, misslam_report *rep,
-                        float *params, hipStream_t st, bool coop, bool kernels = false) {
+                        float *params, hipStream_t st, bool coop, bool kernels = false, unsigned spin = 0) {
     hipError_t e;
     {
         Timed t(PH_BJACOBI, st);
@@ -365,7 +389,7 @@ static hipError_t solve(const msl::GraphView &g, int m, const float *blocks, con
     if (e == hipSuccess) {
         Timed t(PH_PCG, st);
         e = solve_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st, coop, 0, nullptr,
-                             kernels);
+                             kernels, spin);
     }
     return e;
 }
@@ -436,7 +460,7 @@ misslam_status misslam_pcg_solve(const misslam_graph *graph, int32_t m, const fl
     if (e == hipSuccess)
         e = solve(gv, m, blocks, g, L.step.minv, params->lambda, params->pcg_iters, delta, L.pcg, rep, nullptr, st,
                   params->solve_launch == MISSLAM_LAUNCH_COOPERATIVE,
-                  params->solve_launch == MISSLAM_LAUNCH_KERNELS);
+                  params->solve_launch == MISSLAM_LAUNCH_KERNELS, (unsigned)params->sync_spin_limit);
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
 }
 
@@ -445,7 +469,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
                                   const misslam_params *params, const misslam_keypoints *keys,
                                   const misslam_lm_params *lm, misslam_report *rep, int32_t *corr_hist, void *ws,
                                   size_t ws_bytes, void *stream, const misslam_pose_weights *pw = nullptr,
-                                  float *pose_out = nullptr) {
+                                  float *pose_out = nullptr, bool core_only = false) {
     if (!valid_points(points) || !valid_nodes(nodes) || !valid_graph(graph, points->n) || !depth ||
         !valid_camera(camera) || !pose || !valid_params(params) || !rep || !ws)
         return MISSLAM_EINVAL;
@@ -466,8 +490,10 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
         ka.target = keys->target;
         kp = &ka;
     }
-    const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, params->pcg_iters, params->k);
-    if (ws_bytes < L.bytes) return MISSLAM_EWORKSPACE;
+    if (core_only && (params->precision != MISSLAM_PREC_FP32 || kp || lm || pw)) return MISSLAM_EUNSUPPORTED;
+    const Layout L = carve(ws, points->n, nodes->m, camera->width, camera->height, params->pcg_iters, params->k,
+                           core_only ? WS_CORE : WS_ALL);
+    if (ws_bytes < L.bytes) return core_only ? MISSLAM_ECAPACITY : MISSLAM_EWORKSPACE;
     if ((int64_t)graph->bsr_cap > (int64_t)nodes->m * MISSLAM_MAX_ROW) return MISSLAM_ECAPACITY;
     const bool lowp = params->precision != MISSLAM_PREC_FP32;
     const bool coop = params->solve_launch == MISSLAM_LAUNCH_COOPERATIVE;
@@ -476,7 +502,8 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
     const int G = params->gn_iters;
     const int64_t n = points->n;
     const int m = nodes->m;
-    hipError_t e = msl::launch_report_init(rep, G + 1, st);
+    const unsigned spin = (unsigned)params->sync_spin_limit;
+    hipError_t e = msl::launch_report_init(rep, G + 1, st, graph->info);
     if (e == hipSuccess && lowp) e = msl::launch_report_init(L.rep, 1, st);
     if (e == hipSuccess && lm) e = msl::launch_lm_init(L.lm_lambda, lm->lambda0, st);
     if (e == hipSuccess && lm) e = msl::launch_report_init(L.rep, 1, st);
@@ -550,7 +577,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
                 Timed t(PH_PCG, st);
                 e = msl::launch_joint_pcg(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda,
                                           params->pcg_iters, L.delta, L.pcg, L.joint, rep + it, nodes->params,
-                                          pose_out, st, kernels);
+                                          pose_out, st, kernels, spin);
             }
             continue;
         }
@@ -574,7 +601,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
                 Timed t(PH_PCG, st);
                 e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
                                      L.delta, L.pcg, rep + it, lm ? nullptr : nodes->params, st, coop,
-                                     msl::msl_sync_words(m), lm ? L.lm_lambda : nullptr, kernels);
+                                     msl::msl_sync_words(m), lm ? L.lm_lambda : nullptr, kernels, spin);
             }
             if (e == hipSuccess && lm) {
                 // the trial point x + dx: its objective decides whether the step is taken
@@ -610,21 +637,24 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
         if (e == hipSuccess) {
             Timed t(PH_PCG, st);
             e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
-                                 L.delta, L.pcg, rep + it, nullptr, st, coop, 0, nullptr, kernels);
+                                 L.delta, L.pcg, rep + it, nullptr, st, coop, 0, nullptr, kernels, spin);
         }
         for (int r = 0; r < params->refine_steps && e == hipSuccess; ++r) {
             {
                 Timed t(PH_REFINE, st);
                 e = msl::launch_refine_rhs(a, L.step, L.delta, L.rr, L.gvec, L.jv, L.rhs, st);
             }
+            if (e == hipSuccess) e = msl::launch_report_init(L.rep, 1, st);
             if (e == hipSuccess) {
                 Timed t(PH_PCG, st);
                 e = solve_persistent(view(graph), m, L.blocks, L.rhs, L.step.minv, params->lambda, params->pcg_iters,
-                                     L.delta2, L.pcg, L.rep, nullptr, st, coop, 0, nullptr, kernels);
+                                     L.delta2, L.pcg, L.rep, nullptr, st, coop, 0, nullptr, kernels, spin);
             }
-            if (e == hipSuccess) e = msl::launch_axpy(L.delta, L.delta2, 12 * m, st);
+            // dx += the correction unless its solve failed; its flags join the step's report
+            if (e == hipSuccess) e = msl::launch_step_commit(L.delta, L.delta2, 12 * m, L.rep, st, rep + it);
         }
-        if (e == hipSuccess) e = msl::launch_axpy(nodes->params, L.delta, 12 * m, st);
+        // x += dx unless the step's report (its own solve's flags and every refinement's) rules it out
+        if (e == hipSuccess) e = msl::launch_step_commit(nodes->params, L.delta, 12 * m, rep + it, st);
     }
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
 }
@@ -1014,6 +1044,7 @@ void batch_items(misslam_batch *b, void *ws, int rows) {
         A.part = L.pcg.part;
         A.status = L.pcg.status;
         A.done = L.pcg.status + (b->params.pcg_iters + 2);
+        if (b->params.sync_spin_limit > 0) A.spin = (unsigned)b->params.sync_spin_limit;
         it.rep = p.report;
         it.params = p.nodes.params;
         it.depth = p.depth;
@@ -1055,7 +1086,7 @@ hipError_t batch_enqueue(misslam_batch *b, hipStream_t st, bool cooperative) {
                                                                    std::min(8 * b->total_wgs, msl::MSL_BAR_WORDS), st);
         bool used = false;
         if (e == hipSuccess)
-            e = msl::launch_pcg_batched(d, count, b->rows, b->total_wgs, it, b->bar,
+            e = msl::launch_pcg_batched(d, count, b->rows, b->total_wgs, b->total_rows, it, b->bar,
                                         cooperative && b->params.solve_launch == MISSLAM_LAUNCH_COOPERATIVE, st, &used);
         if (e == hipSuccess && !used) return hipErrorInvalidConfiguration;
     }
@@ -1089,6 +1120,8 @@ float batch_try(misslam_batch *b, void *ws, int rows, hipStream_t st) {
     int wgs = 0;
     for (const auto &p : b->probs) wgs += (p.nodes.m + rows - 1) / rows;
     if (!msl::pcg_batched_fits(wgs)) return -1.f;
+    // the descriptors are rewritten by a blocking copy: nothing queued on st may still read them
+    if (hipStreamSynchronize(st) != hipSuccess) return -1.f;
     if (batch_upload(b, ws, rows) != hipSuccess) return -1.f;
     b->rows = rows;
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -37,6 +37,7 @@ struct GridView {
 
 struct GraphScratch {
     int32_t *tmp;     // m x MISSLAM_MAX_ROW row columns
+    int32_t *ltmp;    // k n: merge buffer of the node lists longer than MISSLAM_MAX_LIST
     int32_t *cnt;     // 2m + 8
     GridView grid;
 };
@@ -176,6 +177,7 @@ struct PcgArgs {
     double *part;     // [(it * 4 + kind) * nblk + block], kind 0 = r.z, 1 = r.r, 2 = p.q, 3 = #non-finite x
     int32_t *status;  // [it]: 0 running, 2 stopped by breakdown (propagates)
     int32_t *done;    // [it]: 1 if iteration it updated x
+    unsigned spin = 1u << 18;   // polls of one wait of the one-launch solves before they give up
 };
 
 // One registration problem of a batch solved side by side: its step and
@@ -288,13 +290,14 @@ hipError_t launch_pose_setup(const float *pose_dev, const PosePrior &pr, const d
                              float lambda, double *sys, misslam_report *rep, hipStream_t st,
                              unsigned long long *jbar = nullptr, int m = 0, const KeyArgs *kp = nullptr,
                              const CorrScratch *c = nullptr, int64_t n = 0, int k = 4);
-// Joint PCG into delta (12 m) and the pose step; applies params += delta and the pose step unless non-finite.
-// One launch when every workgroup fits at once, else (or with kernels) one launch per phase: the same
-// partition and reduction order, so the same bits.
+// Joint PCG into delta (12 m) and the pose step; applies params += delta and the pose step unless non-finite
+// or (one launch) a workgroup timed out.  One launch when every workgroup fits at once, else (or with kernels)
+// one launch per phase: the same partition and reduction order, so the same bits.  spin: polls of one wait of
+// the one-launch form (0: the default bound).
 hipError_t launch_joint_pcg(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                             float lambda, int iters, float *delta, const PcgScratch &s, const JointScratch &js,
                             misslam_report *rep, float *params, float *pose_dev, hipStream_t st,
-                            bool kernels = false);
+                            bool kernels = false, unsigned spin = 0);
 // The list-entry packing the assembly reads; run once per registration (the graph, canonical points and node
 // positions are fixed across its Gauss-Newton steps) before the first launch_assemble.
 hipError_t launch_list_pack(const StepArgs &a, const StepScratch &s, hipStream_t st);
@@ -339,15 +342,22 @@ hipError_t launch_lm_trial(const float *x, const float *dx, float *x_trial, int 
 hipError_t launch_lm_decide(misslam_report *rep_x, const misslam_report *rep_t, const misslam_lm_params &lm,
                             float w_data, float w_rot, float w_reg, float w_corr, float *x, const float *x_trial,
                             int n, float *lambda_slot, hipStream_t st);
-hipError_t launch_report_init(misslam_report *rep, int count, hipStream_t st);
+// graph_info (optional): the graph's info words; a graph overflow (info[3]) starts every entry's flags.
+hipError_t launch_report_init(misslam_report *rep, int count, hipStream_t st, const int32_t *graph_info = nullptr);
 // Same solve as launch_pcg_update in one launch whose workgroups must all be
 // resident (cooperative: guaranteed by the runtime; plain: no other work may
 // hold the CUs); *used = false when the device cannot hold the grid at once
-// (nothing launched, caller falls back).
+// (nothing launched, caller falls back).  params += delta is a separate launch
+// after the solve (launch_step_commit), so a timeout discards the whole step.
+// spin: polls of one wait before it gives up (0: the default bound).
 hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                                  float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
                                  float *params, hipStream_t st, bool *used, bool cooperative,
-                                 int zeroed_words = 0, const float *lambda_dev = nullptr);
+                                 int zeroed_words = 0, const float *lambda_dev = nullptr, unsigned spin = 0);
+// x += dx (n entries) unless rep's flags, ORed with extra's when given (and written back into rep), carry
+// MISSLAM_FLAG_NONFINITE or MISSLAM_FLAG_SYNC_TIMEOUT: the whole step or nothing.
+hipError_t launch_step_commit(float *x, const float *dx, int n, misslam_report *rep, hipStream_t st,
+                              const misslam_report *extra = nullptr);
 int pcg_blocks(int m);
 // Batched launches: one grid covers every problem of items[0..count).
 hipError_t launch_normal_map_batched(const BatchItem *items, int count, int total_blocks, hipStream_t st);
@@ -362,8 +372,10 @@ hipError_t launch_report_init_batched(const BatchItem *items, int count, int per
 // Side-by-side persistent solves: cooperative (co-residency checked by the
 // runtime) unless capture is set, where the grid is checked against the
 // occupancy instead.  *used = false: the shape does not fit; nothing launched.
-hipError_t launch_pcg_batched(const BatchItem *items, int count, int rows_per_wg, int total_wgs, int it,
-                              unsigned *bar, bool cooperative, hipStream_t st, bool *used);
+// Each problem's params += dx follows in a second launch (skipped per problem on a non-finite value or a
+// timeout in its report).
+hipError_t launch_pcg_batched(const BatchItem *items, int count, int rows_per_wg, int total_wgs, int total_rows,
+                              int it, unsigned *bar, bool cooperative, hipStream_t st, bool *used);
 int pcg_batched_fits(int total_wgs);
 
 hipError_t launch_grow(GrowArgs g, const GrowScratch &s, int64_t *counts_out, hipStream_t st);

@@ -415,26 +415,69 @@ __device__ __forceinline__ bool key_less(uint64_t ah, uint64_t al, uint32_t ap, 
     return ap < bp;
 }
 
-// One block per node: bitonic sort of its list by (sorted node set, point index) in LDS.  512 threads: half the
-// passes per thread of 256 (229 -> 218 us of graph setup at 640x480), the same order.
+// One block per node: its list sorted by (sorted node set, point index).  A list of up to MISSLAM_MAX_LIST
+// entries is bitonic-sorted in LDS in one piece; a longer one is sorted in pieces of MISSLAM_MAX_LIST, which
+// are then merged pairwise in global memory through tmp (the same positions as the list), each merge split
+// over the block's threads along the merge path.  512 threads: half the passes per thread of 256 (229 -> 218
+// us of graph setup at 640x480), the same order.  The order is a total one (point indices are distinct), so
+// the result does not depend on the way it was reached.
 constexpr int kSortThreads = 512;
+
+template <int K>
+__device__ __forceinline__ bool entry_less(const int32_t *__restrict__ idx, int64_t n, uint32_t a, uint32_t b) {
+    uint64_t ah, al, bh, bl;
+    set_key<K>(idx, n, a, ah, al);
+    set_key<K>(idx, n, b, bh, bl);
+    return key_less(ah, K > 4 ? al : 0, a, bh, K > 4 ? bl : 0, b);
+}
+
+// Merges the sorted runs src[0, la) and src[la, la + lb) into dst[0, la + lb), split over the block's threads.
+template <int K>
+__device__ void merge_runs(const int32_t *__restrict__ idx, int64_t n, const int32_t *src, int la, int lb,
+                           int32_t *dst) {
+    const int T = la + lb;
+    const int per = (T + kSortThreads - 1) / kSortThreads;
+    const int d0 = min(T, (int)threadIdx.x * per), d1 = min(T, d0 + per);
+    if (d0 >= d1) return;
+    // merge path: the number of entries of run A among the first d0 of the output
+    int lo = max(0, d0 - lb), hi = min(d0, la);
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        // take A[mid] before B[d0 - mid - 1]?
+        if (entry_less<K>(idx, n, (uint32_t)src[mid], (uint32_t)src[la + d0 - mid - 1]))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    int ia = lo, ib = d0 - lo;
+    for (int d = d0; d < d1; ++d) {
+        bool take_a;
+        if (ia >= la) take_a = false;
+        else if (ib >= lb) take_a = true;
+        else take_a = entry_less<K>(idx, n, (uint32_t)src[ia], (uint32_t)src[la + ib]);
+        dst[d] = take_a ? src[ia++] : src[la + ib++];
+    }
+}
+
 template <int K>
 __global__ void __launch_bounds__(kSortThreads) list_sort_kernel(const int32_t *__restrict__ idx, int64_t n,
                                                         const int32_t *__restrict__ ptr,
-                                                        int32_t *__restrict__ list) {
+                                                        int32_t *__restrict__ list, int32_t *__restrict__ tmp) {
     __shared__ uint64_t kh[MISSLAM_MAX_LIST];
     __shared__ uint64_t kl[K > 4 ? MISSLAM_MAX_LIST : 1];
     __shared__ uint32_t kp[MISSLAM_MAX_LIST];
     const int j = blockIdx.x;
     const int b = ptr[j];
-    const int c = min(ptr[j + 1] - b, MISSLAM_MAX_LIST);
+    const int call = ptr[j + 1] - b;
+    for (int c0 = 0; c0 < call; c0 += MISSLAM_MAX_LIST) {   // one piece unless the list is long
+    const int c = min(call - c0, MISSLAM_MAX_LIST);
     int P = 1;
     while (P < c) P <<= 1;
     for (int t = threadIdx.x; t < P; t += kSortThreads) {
         uint64_t h = ~0ull, l = ~0ull;
         uint32_t p = 0xFFFFFFFFu;
         if (t < c) {
-            p = (uint32_t)list[b + t];
+            p = (uint32_t)list[b + c0 + t];
             set_key<K>(idx, n, p, h, l);
         }
         kh[t] = h;
@@ -466,7 +509,27 @@ __global__ void __launch_bounds__(kSortThreads) list_sort_kernel(const int32_t *
             __syncthreads();
         }
     }
-    for (int t = threadIdx.x; t < c; t += kSortThreads) list[b + t] = (int32_t)kp[t];
+    for (int t = threadIdx.x; t < c; t += kSortThreads) list[b + c0 + t] = (int32_t)kp[t];
+    __syncthreads();
+    }
+    if (call <= MISSLAM_MAX_LIST) return;
+    // pairwise merges of the sorted pieces, list -> tmp -> list ...
+    int32_t *src = list + b, *dst = tmp + b;
+    for (int run = MISSLAM_MAX_LIST; run < call; run *= 2) {
+        for (int s0 = 0; s0 < call; s0 += 2 * run) {
+            const int la = min(run, call - s0);
+            const int lb = min(run, call - s0 - la);
+            merge_runs<K>(idx, n, src + s0, la, lb, dst + s0);
+        }
+        __threadfence_block();
+        __syncthreads();
+        int32_t *t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != list + b) {
+        for (int t = threadIdx.x; t < call; t += kSortThreads) list[b + t] = src[t];
+    }
 }
 
 // ---------------------------------------------------------------- node graph and block pattern
@@ -488,7 +551,7 @@ __global__ void __launch_bounds__(256) row_collect_kernel(const int32_t *__restr
     __syncthreads();
     if (threadIdx.x == 0) atomicOr(&bm[j >> 5], 1u << (j & 31));
     const int b = lptr[j];
-    const int c = min(lptr[j + 1] - b, MISSLAM_MAX_LIST);
+    const int c = lptr[j + 1] - b;
     for (int t = threadIdx.x; t < c; t += 256) {
         const int p = list[b + t];
 #pragma unroll
@@ -648,11 +711,12 @@ static hipError_t graph_k(const PointsView &pts, const NodesView &nd, int wkind,
         hipLaunchKernelGGL((list_count_kernel<K>), dim3(nblk(n, 256)), dim3(256), 0, st, g.knn_idx, n, lcnt);
     }
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, lcnt, m, g.list_ptr, g.info, -1, 2,
-                       MISSLAM_MAX_LIST, (int64_t)K * n);
+                       0x7FFFFFFF, (int64_t)K * n);
     if (n > 0) {
         hipLaunchKernelGGL((list_fill_kernel<K>), dim3(nblk(n, 256)), dim3(256), 0, st, g.knn_idx, n, g.list_ptr,
                            s.cnt, g.list_pts);
-        hipLaunchKernelGGL((list_sort_kernel<K>), dim3(m), dim3(kSortThreads), 0, st, g.knn_idx, n, g.list_ptr, g.list_pts);
+        hipLaunchKernelGGL((list_sort_kernel<K>), dim3(m), dim3(kSortThreads), 0, st, g.knn_idx, n, g.list_ptr,
+                           g.list_pts, s.ltmp);
     }
     hipLaunchKernelGGL((row_collect_kernel<K>), dim3(m), dim3(256), 0, st, g.knn_idx, n, m, g.list_ptr, g.list_pts,
                        s.tmp, s.cnt, g.info);

@@ -34,7 +34,8 @@ __global__ void __launch_bounds__(256) lm_decide_kernel(misslam_report *rep_x, c
                                                         const float *__restrict__ xt, int n, float *lambda_slot) {
     const double E = lm_objective(*rep_x, w_data, w_rot, w_reg, w_corr);
     const double Et = lm_objective(*rep_t, w_data, w_rot, w_reg, w_corr);
-    const bool take = Et < E;   // false for a non-finite trial objective
+    // never a step whose solve timed out or met a non-finite value; false too for a non-finite objective
+    const bool take = Et < E && !(rep_x->flags & (MISSLAM_FLAG_NONFINITE | MISSLAM_FLAG_SYNC_TIMEOUT));
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (take && i < n) x[i] = xt[i];
     if (blockIdx.x == 0 && threadIdx.x == 0) {

@@ -262,13 +262,15 @@ hipError_t launch_pcg_update(const GraphView &g, int m, const float *blocks, con
 
 __global__ void report_init_batched_kernel(const BatchItem *__restrict__ items, int per_problem) {
     misslam_report *rep = items[blockIdx.x].rep;
+    const int32_t *info = items[blockIdx.x].a.g.info;
+    const int gf = info[3] != 0 ? MISSLAM_FLAG_GRAPH_OVERFLOW : 0;
     for (int t = threadIdx.x; t < per_problem; t += blockDim.x) {
         rep[t].e_data = 0.0;
         rep[t].e_rot = 0.0;
         rep[t].e_reg = 0.0;
         for (int q = 0; q <= MISSLAM_MAX_PCG; ++q) rep[t].pcg_resid[q] = 0.0;
         rep[t].n_valid = 0;
-        rep[t].flags = 0;
+        rep[t].flags = gf;
         rep[t].pcg_iters_done = 0;
         rep[t].reserved = 0;
         rep[t].e_corr = 0.0;
@@ -287,15 +289,16 @@ hipError_t launch_report_init_batched(const BatchItem *items, int count, int per
     return hipGetLastError();
 }
 
-__global__ void report_init_kernel(misslam_report *rep, int count) {
+__global__ void report_init_kernel(misslam_report *rep, int count, const int32_t *graph_info) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < count) {
+        const int gf = graph_info && graph_info[3] != 0 ? MISSLAM_FLAG_GRAPH_OVERFLOW : 0;
         rep[t].e_data = 0.0;
         rep[t].e_rot = 0.0;
         rep[t].e_reg = 0.0;
         for (int q = 0; q <= MISSLAM_MAX_PCG; ++q) rep[t].pcg_resid[q] = 0.0;
         rep[t].n_valid = 0;
-        rep[t].flags = 0;
+        rep[t].flags = gf;
         rep[t].pcg_iters_done = 0;
         rep[t].reserved = 0;
         rep[t].e_corr = 0.0;
@@ -308,9 +311,9 @@ __global__ void report_init_kernel(misslam_report *rep, int count) {
     }
 }
 
-hipError_t launch_report_init(misslam_report *rep, int count, hipStream_t st) {
+hipError_t launch_report_init(misslam_report *rep, int count, hipStream_t st, const int32_t *graph_info) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(report_init_kernel, dim3((count + 63) / 64), dim3(64), 0, st, rep, count);
+    hipLaunchKernelGGL(report_init_kernel, dim3((count + 63) / 64), dim3(64), 0, st, rep, count, graph_info);
     return hipGetLastError();
 }
 
@@ -344,10 +347,10 @@ __device__ __forceinline__ double ld_dev(const double *p) {
     return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bound on the polls of one wait.  A workgroup that gives up (which a launch
-// whose workgroups are all resident never causes) stops waiting from then on
-// and the solve reports it.
-constexpr unsigned kSpinLimit = 1u << 18;
+// The polls of one wait are bounded (PcgArgs::spin).  A workgroup that gives
+// up (which a launch whose workgroups are all resident never causes) stops
+// waiting from then on and the solve reports it; the step is then discarded
+// as a whole by step_commit_kernel, which runs after the solve.
 
 // Sum of up to three doubles over the workgroup: wave butterflies, then the
 // waves in order (fixed order: bitwise reproducible).
@@ -402,7 +405,7 @@ __device__ __forceinline__ void tag_publish(unsigned *bar, int gid, int which, u
 // Fixed-order sum of the values that workgroups g0 .. g0+G-1 published with
 // `tag`, waiting for each (bounded: a timeout marks the workgroup broken).
 __device__ __forceinline__ double tag_sum(unsigned *bar, int g0, int G, int which, unsigned tag, bool &broken,
-                                          double (*lds)[kPcgThreads / kWave]) {
+                                          double (*lds)[kPcgThreads / kWave], unsigned spin_limit) {
     const unsigned long long *base = tag_slots(bar) + 2 * which;
     double v[1] = {0.0};
     bool ok = true;
@@ -414,7 +417,7 @@ __device__ __forceinline__ double tag_sum(unsigned *bar, int g0, int G, int whic
             hi = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             lo = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((unsigned)hi == tag && (unsigned)lo == tag) break;
-            if (broken || ++spins > kSpinLimit) {
+            if (broken || ++spins > spin_limit) {
                 ok = false;
                 break;
             }
@@ -436,65 +439,67 @@ __device__ __forceinline__ unsigned long long ld_dev64(const float *p) {
                              __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One workgroup's share of the solve: workgroup wg of the G that own this
-// system's rows, which are workgroups gid0 .. gid0+G-1 of the launch (a batch
-// solves several systems side by side, each over its own sync slots).  The
-// columns of the workgroup's blocks are reduced to their distinct nodes once;
-// each iteration stages z of those nodes in LDS (8-byte device-scope loads,
-// all in flight together).
-__device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_per_wg, int cache_blocks, unsigned *bar,
-                                                    int gid0, int wg, int G, misslam_report *rep, float *params) {
-    extern __shared__ float4 dyn4[];
-    __shared__ double red[3][kPcgThreads / kWave];
-    __shared__ float vx[kRowsPerBlk * 12], vr[kRowsPerBlk * 12], vp[kRowsPerBlk * 12], vq[kRowsPerBlk * 12];
-    __shared__ int bmap[kMaxBlocksWg];                 // block -> distinct-column slot (-1: beyond the cap)
-    __shared__ int colL[kMaxBlocksWg];
-    __shared__ int scan_w[kPcgThreads / kWave];
-    __shared__ int ucol[kMaxUnique];
-    __shared__ float4 zc4[kMaxUnique * 3];             // z of the distinct columns (setup: first-block map)
-    __shared__ int cnt_u, cmin_s, cmax_s;
-    __shared__ int lslot[kRowsPerBlk];                 // staged slot of each of this workgroup's own columns
-    float *zc = reinterpret_cast<float *>(zc4);
-    const double lam = (double)(A.lambda_dev ? *A.lambda_dev : A.lambda);
-    const int r0 = min(A.m, wg * rows_per_wg);
-    const int r1 = min(A.m, r0 + rows_per_wg);
-    const int b0 = min(A.row_ptr[r0], A.cap), b1 = min(A.row_ptr[r1], A.cap);
-    const int nb = min(b1 - b0, kMaxBlocksWg);         // blocks of this workgroup's rows
-    const int cached = min(nb, cache_blocks);
-    float *hc = reinterpret_cast<float *>(dyn4);       // cached blocks
-    float *mc = hc + (size_t)cache_blocks * 144;       // preconditioner blocks of the rows
+// LDS of one workgroup's share of a one-launch solve besides the cached blocks: the columns of its blocks
+// reduced to their distinct nodes (each staged once per iteration).
+struct TileLds {
+    int bmap[kMaxBlocksWg];                 // block -> distinct-column slot (-1: beyond the cap)
+    int colL[kMaxBlocksWg];                 // column of each block
+    int scan_w[kPcgThreads / kWave];
+    int ucol[kMaxUnique];                   // node of each distinct-column slot
+    int cnt_u, cmin_s, cmax_s;
+    int lslot[kRowsPerBlk];                 // staged slot of each of this workgroup's own columns (-1: none)
+};
+
+struct TileRange {
+    int r0, r1;      // rows [r0, r1)
+    int b0, nb;      // their blocks [b0, b0 + nb) of the system
+    int cached;      // blocks held in LDS (the first `cached`)
+    int U;           // distinct columns with a slot
+};
+
+// Setup of workgroup wg's share: its rows' blocks (as many as fit) into hc, their preconditioner blocks into
+// mc, and the distinct-column map.  firstmap: kMaxUnique * 12 ints of scratch LDS (free again on return).
+__device__ __forceinline__ TileRange tile_setup(const PcgArgs &A, int rows_per_wg, int cache_blocks, int wg,
+                                                float4 *hc4, float *mc, TileLds &t, int *firstmap) {
+    TileRange R;
+    R.r0 = min(A.m, wg * rows_per_wg);
+    R.r1 = min(A.m, R.r0 + rows_per_wg);
+    R.b0 = min(A.row_ptr[R.r0], A.cap);
+    const int b1 = min(A.row_ptr[R.r1], A.cap);
+    R.nb = min(b1 - R.b0, kMaxBlocksWg);
+    R.cached = min(R.nb, cache_blocks);
     {   // 16-byte copies, several in flight per thread
-        const float4 *src = reinterpret_cast<const float4 *>(A.blocks + (size_t)b0 * 144);
-        const int n4 = cached * 36;
+        const float4 *src = reinterpret_cast<const float4 *>(A.blocks + (size_t)R.b0 * 144);
+        const int n4 = R.cached * 36;
 #pragma unroll 4
-        for (int t = threadIdx.x; t < n4; t += kPcgThreads) dyn4[t] = src[t];
-        const float4 *srcm = reinterpret_cast<const float4 *>(A.minv + (size_t)r0 * 144);
+        for (int q = threadIdx.x; q < n4; q += kPcgThreads) hc4[q] = src[q];
+        const float4 *srcm = reinterpret_cast<const float4 *>(A.minv + (size_t)R.r0 * 144);
         float4 *dstm = reinterpret_cast<float4 *>(mc);
-        for (int t = threadIdx.x; t < (r1 - r0) * 36; t += kPcgThreads) dstm[t] = srcm[t];
+        for (int q = threadIdx.x; q < (R.r1 - R.r0) * 36; q += kPcgThreads) dstm[q] = srcm[q];
     }
     // distinct columns: a block whose column appears at no earlier block of the workgroup gets the next
     // slot (in block order, by a workgroup scan); later blocks of that column share it
     if (threadIdx.x == 0) {
-        cmin_s = 0x7FFFFFFF;
-        cmax_s = -1;
+        t.cmin_s = 0x7FFFFFFF;
+        t.cmax_s = -1;
     }
-    if (threadIdx.x < kRowsPerBlk) lslot[threadIdx.x] = -1;
+    if (threadIdx.x < kRowsPerBlk) t.lslot[threadIdx.x] = -1;
     __syncthreads();
-    for (int t = threadIdx.x; t < nb; t += kPcgThreads) {
-        const int c = A.col_idx[b0 + t];
-        colL[t] = c;
-        atomicMin(&cmin_s, c);
-        atomicMax(&cmax_s, c);
+    const int nb = R.nb, b0 = R.b0, r0 = R.r0, r1 = R.r1;
+    for (int q = threadIdx.x; q < nb; q += kPcgThreads) {
+        const int c = A.col_idx[b0 + q];
+        t.colL[q] = c;
+        atomicMin(&t.cmin_s, c);
+        atomicMax(&t.cmax_s, c);
     }
     __syncthreads();
-    const int cmin = cmin_s, crange = cmax_s - cmin_s + 1;
-    constexpr int kMapRange = kMaxUnique * 12;         // ints of the first-block map (in zc's space)
-    int *firstmap = reinterpret_cast<int *>(zc4);
+    const int cmin = t.cmin_s, crange = t.cmax_s - t.cmin_s + 1;
+    constexpr int kMapRange = kMaxUnique * 12;         // ints of the first-block map
     const bool mapped = nb > 0 && crange <= kMapRange;
     if (mapped) {
-        for (int t = threadIdx.x; t < crange; t += kPcgThreads) firstmap[t] = 0x7FFFFFFF;
+        for (int q = threadIdx.x; q < crange; q += kPcgThreads) firstmap[q] = 0x7FFFFFFF;
         __syncthreads();
-        for (int t = threadIdx.x; t < nb; t += kPcgThreads) atomicMin(&firstmap[colL[t] - cmin], t);
+        for (int q = threadIdx.x; q < nb; q += kPcgThreads) atomicMin(&firstmap[t.colL[q] - cmin], q);
         __syncthreads();
     }
     constexpr int kPerT = (kMaxBlocksWg + kPcgThreads - 1) / kPcgThreads;   // entries per thread in the scan
@@ -502,25 +507,25 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
     int nfirst = 0;
 #pragma unroll
     for (int e = 0; e < kPerT; ++e) {
-        const int t = threadIdx.x * kPerT + e;
+        const int q = threadIdx.x * kPerT + e;
         firstpos[e] = -1;
-        if (t < nb) {
-            const int c = colL[t];
-            int f = t;
+        if (q < nb) {
+            const int c = t.colL[q];
+            int f = q;
             if (mapped) {
                 f = firstmap[c - cmin];
             } else {
-                for (int u = 0; u < t; ++u)
-                    if (colL[u] == c) {
+                for (int u = 0; u < q; ++u)
+                    if (t.colL[u] == c) {
                         f = u;
                         break;
                     }
             }
             firstpos[e] = f;
-            nfirst += f == t;
+            nfirst += f == q;
         }
     }
-    __syncthreads();   // the map's space becomes zc again
+    __syncthreads();   // the map's space is free again
     // exclusive scan of nfirst over the workgroup: wave scans, then the waves in order
     {
         const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -530,36 +535,59 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
             const int v = __shfl_up(incl, off, kWave);
             if (lane >= off) incl += v;
         }
-        if (lane == kWave - 1) scan_w[wave] = incl;
+        if (lane == kWave - 1) t.scan_w[wave] = incl;
         __syncthreads();
         int base = 0;
-        for (int w = 0; w < wave; ++w) base += scan_w[w];
+        for (int w = 0; w < wave; ++w) base += t.scan_w[w];
         int slot = base + incl - nfirst;
 #pragma unroll
         for (int e = 0; e < kPerT; ++e) {
-            const int t = threadIdx.x * kPerT + e;
-            if (t < nb && firstpos[e] == t) {
+            const int q = threadIdx.x * kPerT + e;
+            if (q < nb && firstpos[e] == q) {
                 const int sl = slot < kMaxUnique ? slot : -1;
-                if (sl >= 0) ucol[sl] = colL[t];
-                if (sl >= 0 && colL[t] >= r0 && colL[t] < r1) lslot[colL[t] - r0] = sl;
-                bmap[t] = sl;
+                if (sl >= 0) t.ucol[sl] = t.colL[q];
+                if (sl >= 0 && t.colL[q] >= r0 && t.colL[q] < r1) t.lslot[t.colL[q] - r0] = sl;
+                t.bmap[q] = sl;
                 ++slot;
             }
         }
         if (threadIdx.x == kPcgThreads - 1) {
             int tot = 0;
-            for (int w = 0; w < kPcgThreads / kWave; ++w) tot += scan_w[w];
-            cnt_u = tot < kMaxUnique ? tot : kMaxUnique;
+            for (int w = 0; w < kPcgThreads / kWave; ++w) tot += t.scan_w[w];
+            t.cnt_u = tot < kMaxUnique ? tot : kMaxUnique;
         }
     }
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < kPerT; ++e) {
-        const int t = threadIdx.x * kPerT + e;
-        if (t < nb && firstpos[e] != t) bmap[t] = bmap[firstpos[e]];   // a first occurrence: already set
+        const int q = threadIdx.x * kPerT + e;
+        if (q < nb && firstpos[e] != q) t.bmap[q] = t.bmap[firstpos[e]];   // a first occurrence: already set
     }
     __syncthreads();
-    const int U = cnt_u;
+    R.U = t.cnt_u;
+    return R;
+}
+
+// One workgroup's share of the solve: workgroup wg of the G that own this
+// system's rows, which are workgroups gid0 .. gid0+G-1 of the launch (a batch
+// solves several systems side by side, each over its own sync slots).  The
+// columns of the workgroup's blocks are reduced to their distinct nodes once;
+// each iteration stages z of those nodes in LDS (8-byte device-scope loads,
+// all in flight together).
+__device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_per_wg, int cache_blocks, unsigned *bar,
+                                                    int gid0, int wg, int G, misslam_report *rep) {
+    extern __shared__ float4 dyn4[];
+    __shared__ double red[3][kPcgThreads / kWave];
+    __shared__ float vx[kRowsPerBlk * 12], vr[kRowsPerBlk * 12], vp[kRowsPerBlk * 12], vq[kRowsPerBlk * 12];
+    __shared__ TileLds tl;
+    __shared__ float4 zc4[kMaxUnique * 3];             // z of the distinct columns (setup: first-block map)
+    float *zc = reinterpret_cast<float *>(zc4);
+    const double lam = (double)(A.lambda_dev ? *A.lambda_dev : A.lambda);
+    float *hc = reinterpret_cast<float *>(dyn4);       // cached blocks
+    float *mc = hc + (size_t)cache_blocks * 144;       // preconditioner blocks of the rows
+    const TileRange R = tile_setup(A, rows_per_wg, cache_blocks, wg, dyn4, mc, tl, reinterpret_cast<int *>(zc4));
+    const int r0 = R.r0, r1 = R.r1, b0 = R.b0, nb = R.nb, cached = R.cached, U = R.U;
+    const int *bmap = tl.bmap, *colL = tl.colL, *ucol = tl.ucol, *lslot = tl.lslot;
     const int lr = threadIdx.x / 12, a = threadIdx.x % 12;
     const int j = r0 + lr;
     const bool act = lr < kRowsPerBlk && j < r1;
@@ -654,7 +682,7 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
         if (threadIdx.x == 0) st_dev(A.part + (size_t)(0 * 4 + 1) * G + wg, v[1]);
         publish(1, 1u, v[0]);
         azl = local_part();
-        rz = tag_sum(bar, gid0, G, 1, 1u, broken, red);
+        rz = tag_sum(bar, gid0, G, 1, 1u, broken, red, A.spin);
         stage();
     }
     bool stopped = false;
@@ -743,7 +771,7 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
             double v[1] = {pq};
             wg_sum<1>(v, red);
             publish(0, (unsigned)(it + 1), v[0]);
-            pqs = tag_sum(bar, gid0, G, 0, (unsigned)(it + 1), broken, red);
+            pqs = tag_sum(bar, gid0, G, 0, (unsigned)(it + 1), broken, red, A.spin);
         }
         // ---- step: alpha = r.z / p.q, x += alpha p, r -= alpha q, z = M r
         const bool brk = !skip && !(pqs > 0.0);
@@ -777,16 +805,13 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
             }
             publish(1, (unsigned)(it + 2), v[0]);
             azl = local_part();
-            rz = tag_sum(bar, gid0, G, 1, (unsigned)(it + 2), broken, red);
+            rz = tag_sum(bar, gid0, G, 1, (unsigned)(it + 2), broken, red, A.spin);
         }
         stage();
     }
-    // ---- finish: report (first workgroup), x out, params += x unless non-finite
+    // ---- finish: report (first workgroup), x out; the update itself is step_commit_kernel's
     const double nbad = A.iters > 0 ? gather_dev(A.part + (size_t)(A.iters * 4 + 3) * G, G, red) : 0.0;
-    if (act) {
-        A.x[(size_t)j * 12 + a] = vx[li];
-        if (params && nbad == 0.0 && !broken) params[(size_t)j * 12 + a] += vx[li];
-    }
+    if (act) A.x[(size_t)j * 12 + a] = vx[li];
     if (wg == 0) {
         for (int q = 0; q <= done; ++q) {
             const double rr = gather_dev(A.part + (size_t)(q * 4 + 1) * G, G, red);
@@ -794,19 +819,39 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
         }
         if (threadIdx.x == 0) {
             rep->pcg_iters_done = done;
-            int f = rep->flags;
+            int f = 0;
             if (stopped) f |= MISSLAM_FLAG_PCG_BREAKDOWN;
             if (nbad != 0.0) f |= MISSLAM_FLAG_NONFINITE;
-            rep->flags = f;
+            if (f) atomicOr(&rep->flags, f);   // atomic: other workgroups may be adding the timeout bit
         }
     }
     if (broken && threadIdx.x == 0) atomicOr(&rep->flags, MISSLAM_FLAG_SYNC_TIMEOUT);
 }
 
 __global__ void __launch_bounds__(kPcgThreads) pcg_persistent_kernel(PcgArgs A, int rows_per_wg, int cache_blocks,
-                                                                    unsigned *bar, misslam_report *rep,
-                                                                    float *params) {
-    pcg_persistent_body(A, rows_per_wg, cache_blocks, bar, 0, blockIdx.x, gridDim.x, rep, params);
+                                                                    unsigned *bar, misslam_report *rep) {
+    pcg_persistent_body(A, rows_per_wg, cache_blocks, bar, 0, blockIdx.x, gridDim.x, rep);
+}
+
+// x += dx over n entries as one step, after the solve that produced dx has
+// completed: skipped entirely when the step's report carries a non-finite
+// value or a solve timeout, so no entry changes unless every workgroup of the
+// solve finished.  extra_flags (optional) is ORed into that report first
+// (block 0), for steps assembled from several solves.
+__global__ void __launch_bounds__(256) step_commit_kernel(float *__restrict__ x, const float *__restrict__ dx,
+                                                          int n, misslam_report *rep, const misslam_report *extra) {
+    const int xf = extra ? extra->flags : 0;
+    const int f = rep->flags | xf;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (!(f & (MISSLAM_FLAG_NONFINITE | MISSLAM_FLAG_SYNC_TIMEOUT)) && i < n) x[i] += dx[i];
+    if (extra && blockIdx.x == 0 && threadIdx.x == 0) rep->flags = f;
+}
+
+hipError_t launch_step_commit(float *x, const float *dx, int n, misslam_report *rep, hipStream_t st,
+                              const misslam_report *extra) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(step_commit_kernel, dim3((n + 255) / 256), dim3(256), 0, st, x, dx, n, rep, extra);
+    return hipGetLastError();
 }
 
 // Grid shape of the persistent solve for m rows on this device, or 0 when a
@@ -855,7 +900,7 @@ static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes) {
 hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                                  float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
                                  float *params, hipStream_t st, bool *used, bool cooperative, int zeroed_words,
-                                 const float *lambda_dev) {
+                                 const float *lambda_dev, unsigned spin) {
     *used = false;
     int rows = 0, lds = 0;
     const int G = persistent_grid(m, rows, lds);
@@ -880,6 +925,7 @@ hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks,
     A.part = s.part;
     A.status = s.status;
     A.done = s.status + (iters + 2);
+    if (spin > 0) A.spin = spin;
     // dynamic LDS: cached blocks (144 floats each) and the rows' preconditioner
     const int cache_blocks = (lds / 4 - rows * 144) / 144;
     if (cache_blocks < 1) return hipSuccess;
@@ -887,15 +933,16 @@ hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks,
     if (zeroed_words < 8 * G) hipLaunchKernelGGL(fill_u32_kernel_pcg, dim3((8 * G + 255) / 256), dim3(256), 0, st, bar, 8 * G);
     hipError_t e;
     if (cooperative) {
-        void *args[] = {&A, (void *)&rows, (void *)&cache_blocks, &bar, &rep, &params};
+        void *args[] = {&A, (void *)&rows, (void *)&cache_blocks, &bar, &rep};
         e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(pcg_persistent_kernel), dim3(G),
                                        dim3(kPcgThreads), args, (unsigned)lds, st);
     } else {
         hipLaunchKernelGGL(pcg_persistent_kernel, dim3(G), dim3(kPcgThreads), (unsigned)lds, st, A, rows,
-                           cache_blocks, bar, rep, params);
+                           cache_blocks, bar, rep);
         e = hipGetLastError();
     }
     if (e == hipSuccess) *used = true;
+    if (e == hipSuccess && params) e = launch_step_commit(params, delta, 12 * m, rep, st, nullptr);
     return e;
 }
 
@@ -915,8 +962,22 @@ __global__ void __launch_bounds__(kPcgThreads) pcg_batched_kernel(const BatchIte
     int b = count - 1;
     while (b > 0 && items[b].wg0 > (int)blockIdx.x) --b;
     const BatchItem &it = items[b];
-    pcg_persistent_body(it.p, rows_per_wg, cache_blocks, bar, it.wg0, (int)blockIdx.x - it.wg0, it.wgs, it.rep + gi,
-                        it.params);
+    pcg_persistent_body(it.p, rows_per_wg, cache_blocks, bar, it.wg0, (int)blockIdx.x - it.wg0, it.wgs, it.rep + gi);
+}
+
+// step_commit_kernel over every problem of a batch: params += dx of problem b unless its step's report
+// carries a non-finite value or a solve timeout.  One thread per parameter entry (rows row0 .. of problem b).
+__global__ void __launch_bounds__(256) step_commit_batched_kernel(const BatchItem *__restrict__ items, int count,
+                                                                  int total_rows, int gi) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= 12 * total_rows) return;
+    const int row = t / 12;
+    int b = count - 1;
+    while (b > 0 && items[b].row0 > row) --b;
+    const BatchItem &it = items[b];
+    const int f = it.rep[gi].flags;
+    const int o = t - 12 * it.row0;
+    if (!(f & (MISSLAM_FLAG_NONFINITE | MISSLAM_FLAG_SYNC_TIMEOUT))) it.params[o] += it.p.x[o];
 }
 
 static int batched_static_lds() {
@@ -955,8 +1016,8 @@ static int batched_lds(int total_wgs) {
 
 int pcg_batched_fits(int total_wgs) { return total_wgs > 0 && batched_lds(total_wgs) > 0 ? 1 : 0; }
 
-hipError_t launch_pcg_batched(const BatchItem *items, int count, int rows_per_wg, int total_wgs, int it,
-                              unsigned *bar, bool cooperative, hipStream_t st, bool *used) {
+hipError_t launch_pcg_batched(const BatchItem *items, int count, int rows_per_wg, int total_wgs, int total_rows,
+                              int it, unsigned *bar, bool cooperative, hipStream_t st, bool *used) {
     *used = false;
     const int lds = batched_lds(total_wgs);
     if (lds <= 0 || rows_per_wg < 1 || rows_per_wg > kRowsPerBlk) return hipSuccess;
@@ -974,6 +1035,11 @@ hipError_t launch_pcg_batched(const BatchItem *items, int count, int rows_per_wg
         e = hipGetLastError();
     }
     if (e == hipSuccess) *used = true;
+    if (e == hipSuccess && total_rows > 0) {
+        hipLaunchKernelGGL(step_commit_batched_kernel, dim3((12 * total_rows + 255) / 256), dim3(256), 0, st, items,
+                           count, total_rows, it);
+        e = hipGetLastError();
+    }
     return e;
 }
 

@@ -634,11 +634,11 @@ __device__ __forceinline__ void jtag_publish(unsigned long long *bar, int wg, in
     }
 }
 
-constexpr unsigned kJSpinLimit = 1u << 18;
-
+// Each wait polls at most J.A.spin times (a timeout marks the workgroup broken; the step is then discarded
+// whole by joint_commit_kernel, which runs after the solve).
 template <int N>
 __device__ __forceinline__ void jtag_sum(unsigned long long *bar, int G, int x, double (&out)[N], bool &broken,
-                                         double (*lds)[kJThreads / kWave]) {
+                                         double (*lds)[kJThreads / kWave], unsigned spin_limit) {
     const unsigned tag = (unsigned)(x + 1);
 #pragma unroll
     for (int q = 0; q < N; ++q) out[q] = 0.0;
@@ -656,7 +656,7 @@ __device__ __forceinline__ void jtag_sum(unsigned long long *bar, int G, int x, 
                 all = all && (unsigned)hv[q] == tag && (unsigned)lv[q] == tag;
             }
             if (all) break;
-            if (broken || ++spins > kJSpinLimit) {
+            if (broken || ++spins > spin_limit) {
                 ok = false;
                 break;
             }
@@ -672,8 +672,7 @@ __device__ __forceinline__ void jtag_sum(unsigned long long *bar, int G, int x, 
 }
 
 __global__ void __launch_bounds__(kJThreads) jpcg_persistent_kernel(JArgs J, unsigned long long *bar, int G,
-                                                                    misslam_report *rep, float *params,
-                                                                    float *pose_dev) {
+                                                                    misslam_report *rep) {
     const PcgArgs &A = J.A;
     __shared__ double red[16][kJThreads / kWave];
     __shared__ float rl[kJRows][12];
@@ -732,7 +731,7 @@ __global__ void __launch_bounds__(kJThreads) jpcg_persistent_kernel(JArgs J, uns
     }
     publish(0, s2, 2);
     double t2[2];
-    jtag_sum<2>(bar, G, 0, t2, broken, red);
+    jtag_sum<2>(bar, G, 0, t2, broken, red, A.spin);
     double rz = t2[0], rz_prev = 1.0, nbad = 0.0;
     if (wg == 0 && threadIdx.x == 0) resid[0] = sqrt(t2[1]);
     int done = 0, status = 0;
@@ -774,7 +773,7 @@ __global__ void __launch_bounds__(kJThreads) jpcg_persistent_kernel(JArgs J, uns
         block_sums<7>(s7, red);
         publish(1 + 2 * it, s7, 7);
         double t7[7];
-        jtag_sum<7>(bar, G, 1 + 2 * it, t7, broken, red);
+        jtag_sum<7>(bar, G, 1 + 2 * it, t7, broken, red, A.spin);
         if (threadIdx.x == 0) {   // the pose part of the product and its direction
             double qp[6], pp[6], t = 0.0;
             for (int u = 0; u < 6; ++u) {
@@ -841,45 +840,53 @@ __global__ void __launch_bounds__(kJThreads) jpcg_persistent_kernel(JArgs J, uns
         }
         publish(2 + 2 * it, s3, 3);
         double t3[3];
-        jtag_sum<3>(bar, G, 2 + 2 * it, t3, broken, red);
+        jtag_sum<3>(bar, G, 2 + 2 * it, t3, broken, red, A.spin);
         rz_prev = rz;
         rz = t3[0];
         nbad = t3[2];
         done = it + 1;
         if (wg == 0 && threadIdx.x == 0) resid[done] = sqrt(t3[1]);
     }
-    // finish: delta, params += delta and the pose step unless non-finite; the report
-    if (act) {
-        A.x[o] = xv;
-        if (params && nbad == 0.0 && !broken) params[o] += xv;
-    }
+    // finish: delta and the pose step out (joint_commit_kernel applies them); the report.  Flags are ORed
+    // atomically: every workgroup that gave up a wait adds the timeout bit.
+    if (act) A.x[o] = xv;
     if (wg == 0 && threadIdx.x == 0) {
         for (int q = 0; q <= done && q <= MISSLAM_MAX_PCG; ++q) rep->pcg_resid[q] = resid[q];
         rep->pcg_iters_done = done;
-        int f = rep->flags;
+        for (int u = 0; u < 6; ++u) J.pst[(size_t)A.iters * kPst + 24 + u] = ps[24 + u];
+        int f = 0;
         if (status == 2) f |= MISSLAM_FLAG_PCG_BREAKDOWN;
         if (nbad != 0.0) f |= MISSLAM_FLAG_NONFINITE;
-        if (broken) f |= MISSLAM_FLAG_SYNC_TIMEOUT;
-        rep->flags = f;
-        if (nbad == 0.0 && !broken) {
-            double E[9], R[9], T[3];
-            so3_exp_d(ps + 24, E);
-            for (int u = 0; u < 9; ++u) R[u] = pose_dev[u];
-            for (int u = 0; u < 3; ++u) T[u] = pose_dev[9 + u];
-            for (int rr = 0; rr < 3; ++rr) {
-                for (int c = 0; c < 3; ++c)
-                    pose_dev[3 * rr + c] =
-                        (float)((E[3 * rr] * R[c] + E[3 * rr + 1] * R[3 + c]) + E[3 * rr + 2] * R[6 + c]);
-                pose_dev[9 + rr] =
-                    (float)(((E[3 * rr] * T[0] + E[3 * rr + 1] * T[1]) + E[3 * rr + 2] * T[2]) + ps[27 + rr]);
-            }
+        if (f) atomicOr(&rep->flags, f);
+    }
+    if (broken && threadIdx.x == 0) atomicOr(&rep->flags, MISSLAM_FLAG_SYNC_TIMEOUT);
+}
+
+// After the one-launch joint solve: params += delta and the pose step (stored by its first workgroup at
+// pst), unless the step's report carries a non-finite value or a timeout of any workgroup.
+__global__ void __launch_bounds__(256) joint_commit_kernel(float *__restrict__ params, const float *__restrict__ dx,
+                                                           int n, const misslam_report *rep, float *pose_dev,
+                                                           const double *xp) {
+    if (rep->flags & (MISSLAM_FLAG_NONFINITE | MISSLAM_FLAG_SYNC_TIMEOUT)) return;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (params && i < n) params[i] += dx[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double E[9], R[9], T[3];
+        so3_exp_d(xp, E);
+        for (int u = 0; u < 9; ++u) R[u] = pose_dev[u];
+        for (int u = 0; u < 3; ++u) T[u] = pose_dev[9 + u];
+        for (int rr = 0; rr < 3; ++rr) {
+            for (int c = 0; c < 3; ++c)
+                pose_dev[3 * rr + c] = (float)((E[3 * rr] * R[c] + E[3 * rr + 1] * R[3 + c]) + E[3 * rr + 2] * R[6 + c]);
+            pose_dev[9 + rr] = (float)(((E[3 * rr] * T[0] + E[3 * rr + 1] * T[1]) + E[3 * rr + 2] * T[2]) + xp[3 + rr]);
         }
     }
 }
 
 hipError_t launch_joint_pcg(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                             float lambda, int iters, float *delta, const PcgScratch &s, const JointScratch &js,
-                            misslam_report *rep, float *params, float *pose_dev, hipStream_t st, bool kernels) {
+                            misslam_report *rep, float *params, float *pose_dev, hipStream_t st, bool kernels,
+                            unsigned spin) {
     JArgs J;
     PcgArgs &A = J.A;
     A.row_ptr = g.row_ptr;
@@ -912,8 +919,12 @@ hipError_t launch_joint_pcg(const GraphView &g, int m, const float *blocks, cons
             cus = 0;
     }
     if (!kernels && js.jbar && A.nblk <= cus && A.nblk <= kJMaxWgs) {   // every workgroup resident: one launch
-        hipLaunchKernelGGL(jpcg_persistent_kernel, dim3(A.nblk), dim3(kJThreads), 0, st, J, js.jbar, A.nblk, rep,
-                           params, pose_dev);
+        if (spin > 0) A.spin = spin;
+        hipLaunchKernelGGL(jpcg_persistent_kernel, dim3(A.nblk), dim3(kJThreads), 0, st, J, js.jbar, A.nblk, rep);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(joint_commit_kernel, dim3((12 * m + 255) / 256), dim3(256), 0, st, params, delta, 12 * m,
+                           rep, pose_dev, J.pst + (size_t)iters * kPst + 24);
         return hipGetLastError();
     }
     const dim3 grid(A.nblk), blk(kJThreads);

@@ -414,7 +414,7 @@ __device__ __forceinline__ void list_pack_body(const StepArgs &a, const StepScra
     if (j >= a.nd.m) return;
     const int64_t n = a.pts.n;
     const int lb = a.g.list_ptr[j];
-    const int cnt = min(a.g.list_ptr[j + 1] - lb, MISSLAM_MAX_LIST);
+    const int cnt = a.g.list_ptr[j + 1] - lb;
     const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
     for (int t = threadIdx.x; t < cnt; t += 256) {
         const int le = lb + t;
@@ -500,7 +500,7 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
 
     const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
     const int lb = a.g.list_ptr[j];
-    const int cnt = min(a.g.list_ptr[j + 1] - lb, MISSLAM_MAX_LIST);
+    const int cnt = a.g.list_ptr[j + 1] - lb;
     const int quota = (cnt + kAsmWaves - 1) / kAsmWaves;
     const int my0 = min(cnt, wave * quota), my1 = min(cnt, my0 + quota);
     const int nbatch = (my1 - my0 + kBatch - 1) / kBatch;
@@ -801,7 +801,7 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
     const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
     const double e_reg = row_prepare<kLpThreads>(a, sh.rn, j, nslots, gjx, gjy, gjz);
     const int lb = a.g.list_ptr[j];
-    const int cnt = min(a.g.list_ptr[j + 1] - lb, MISSLAM_MAX_LIST);
+    const int cnt = a.g.list_ptr[j + 1] - lb;
     const int quota = (cnt + kLpWaves - 1) / kLpWaves;
     const int my0 = min(cnt, wave * quota), my1 = min(cnt, my0 + quota);
     const int nbatch = (my1 - my0 + kBatch - 1) / kBatch;
@@ -1010,7 +1010,7 @@ __global__ void __launch_bounds__(64) jtv_row_kernel(StepArgs a, StepScratch s, 
     const int64_t n = a.pts.n;
     const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
     const int lb = a.g.list_ptr[j];
-    const int cnt = min(a.g.list_ptr[j + 1] - lb, MISSLAM_MAX_LIST);
+    const int cnt = a.g.list_ptr[j + 1] - lb;
     float acc[12];
 #pragma unroll
     for (int q = 0; q < 12; ++q) acc[q] = 0.f;

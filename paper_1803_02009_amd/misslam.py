@@ -49,11 +49,13 @@ class Params:
     refine_steps: int = 0
     reject_threshold: float = 0.0
     solve_launch: int = _lib.LAUNCH_PLAIN
+    sync_spin_limit: int = 0
 
     def c(self):
         return _lib.Params(self.k, self.weight_kind, self.sigma, self.w_rot, self.w_reg, self.w_data, self.eps_d,
                            self.cos_eps_n, self.lam, self.gn_iters, self.pcg_iters, self.precision,
-                           self.refine_steps, self.reject_threshold, self.solve_launch)
+                           self.refine_steps, self.reject_threshold, self.solve_launch,
+                           self.sync_spin_limit)
 
 
 def camera(width, height, fx, fy, cx, cy):

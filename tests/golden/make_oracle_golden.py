@@ -9,7 +9,8 @@ name:kp:S adds S generated key points (gen.keypoints, seed 7, 0.05 mm noise)
 with the Eq.(9) term at w_corr = 10; name:lm runs the adaptive
 Levenberg-Marquardt schedule (default factors) instead of the fixed damping;
 name:joint registers the rigid pose with the ED graph (Eq.(10) terms,
-w_r = 1e6, w_p = 1e3), storing the refined pose too.
+w_r = 1e6, w_p = 1e3), storing the refined pose too.  batch<b> is problem b
+of the uneven batch (gen.batch_spec(b)).
 Output: tests/golden/<name>[_<prec>_r<R> | _kp<S> | _lm | _joint]_oracle.npz with x
 (m, 12) after the frame's iterations (independent decisions), the final
 energies and the per-iteration data energies (and, for lm, the per-step
@@ -32,7 +33,7 @@ ROUND = {"bf16": oracle.round_bf16, "fp16": oracle.round_fp16}
 def main(spec):
     parts = spec.split(":")
     name = parts[0]
-    sc = gen.make_scene(name)
+    sc = gen.make_scene(gen.batch_spec(int(name[5:])) if name.startswith("batch") else name)
     pb = oracle.Problem.from_scene(sc)
     if len(parts) == 1:
         x, rep = oracle.gn_register(pb)

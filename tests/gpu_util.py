@@ -67,3 +67,57 @@ def rel_err(a, b):
 
 
 COS10 = math.cos(math.radians(10.0))
+
+
+def check_energy(s, x_gpu, e_gpu, x_ref=None, e_ref=None, tol=1e-5, pose_gpu=None, pose_ref=None, label=""):
+    """The data energy a registration reports for its state, against float64.
+
+    (1) e_gpu, reported for parameters x_gpu, equals the float64 energy of that state: the oracle's residuals at
+        x_gpu over the GPU's own correspondences (those of one point pass at x_gpu, which is what the report
+        evaluates), within tol.
+    (2) The GPU's float32 decisions at x_gpu differ from the oracle's float64 decisions at the same x_gpu only
+        for points within rounding of a pixel boundary or a gate threshold: at most 1e-3 of the valid points.
+    When the oracle's own run is given (x_ref, its energy e_ref), the gap between the two runs' energies is
+    printed with its two parts: the flipped decisions' share and the share of the parameter difference (points
+    whose decisions agree).  That gap follows from the parameters, which the callers gate on their own.
+    pose_gpu / pose_ref: (R, T) of each side when the pose was refined too (default: the scene's pose).
+    Returns the number of flipped decisions at x_gpu."""
+    import dataclasses
+
+    import oracle
+    from oracle.gn import _adopt, evaluate
+    og = s.oracle_graph_from_gpu()
+    pb = s.problem()
+    Nm, ok = oracle.normal_map(s.sc["depth"], s.sc["camera"])
+    Nm32 = Nm.astype(np.float32)
+
+    def posed(pose):
+        return pb if pose is None else dataclasses.replace(pb, R=np.asarray(pose[0], np.float64),
+                                                           T=np.asarray(pose[1], np.float64))
+    pbg = posed(pose_gpu)
+    xg64 = np.asarray(x_gpu, np.float64)
+    x = torch.tensor(np.asarray(x_gpu, np.float32), device="cuda")
+    nmap = s.M.normal_map(s.depth, s.cam)
+    pg = s.pose if pose_gpu is None else s.M.pose(np.asarray(pose_gpu[0], np.float32),
+                                                  np.asarray(pose_gpu[1], np.float32))
+    _, _, corr, _ = s.M.build_normal_eq(s.pts, s.nodes, x, s.graph, nmap, s.cam, pg, s.params, s.ws)
+    cg = corr.cpu().numpy()
+    vc = oracle.ed_warp(pb.points, pb.nodes, xg64, og["idx"], og["w"], pbg.R, pbg.T)
+    asc_g = _adopt({}, cg, vc, pb, Nm32)
+    e64 = float(np.sum(asc_g["r"] ** 2)) * pb.w_data
+    _, _, asc_64, _ = evaluate(pbg, og, xg64, Nm32, ok)
+    flips = int(np.sum(cg != asc_64["corr"]))
+    nvalid = int(asc_64["valid"].sum())
+    msg = (f"{label} E_data {e_gpu:.6f} vs float64 of the same state {e64:.6f} ({abs(e_gpu - e64) / e64:.2e} rel);"
+           f" {flips} of {nvalid} decisions flip against float64 at the same x")
+    if x_ref is not None:
+        _, _, asc_r, _ = evaluate(posed(pose_ref), og, np.asarray(x_ref, np.float64), Nm32, ok)
+        same = cg == asc_r["corr"]
+        d = asc_g["r"] ** 2 - asc_r["r"] ** 2
+        msg += (f"; gap to the oracle run {(e_gpu - e_ref) / e_ref:+.2e} rel = flips {np.sum(d[~same]) / e_ref:+.2e}"
+                f" ({int((~same).sum())} points) + parameters {np.sum(d[same]) / e_ref:+.2e}"
+                f" + arithmetic {(e_gpu - e64) / e_ref:+.2e}")
+    print(msg)
+    assert abs(e_gpu - e64) <= tol * e64, msg
+    assert flips <= 1e-3 * max(nvalid, 1), msg
+    return flips

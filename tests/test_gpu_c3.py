@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import Scene, rel_err
+from gpu_util import Scene, check_energy, rel_err
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -113,7 +113,7 @@ def test_c3_pcg_full(c3):
     nnzb = len(og["col_idx"])
     dx, info = oracle.pcg(og["row_ptr"], og["col_idx"], blocks.cpu().numpy()[:nnzb].astype(np.float64),
                           gv.cpu().numpy().astype(np.float64), float(np.float32(s.params.lam)), s.params.pcg_iters)
-    assert rel_err(delta.cpu().numpy().reshape(-1), dx) < 1e-4
+    assert rel_err(delta.cpu().numpy().reshape(-1), dx) < 1e-5
     assert s.M.read_report(rep)[0]["pcg_iters_done"] == info["iters"]
 
 
@@ -126,13 +126,15 @@ def test_c3_end_to_end_against_stored_oracle(c3):
     xg = x.cpu().numpy().astype(np.float64)
     xo = gold["x"]
     xi = oracle.identity_params(s.m)
+    print("c3 x rel", rel_err(xg, xo), "delta rel", rel_err(xg - xi, xo - xi))
     assert rel_err(xg, xo) < 1e-5
     assert rel_err(xg - xi, xo - xi) < 1e-4
-    assert r[-1]["e_data"] == pytest.approx(float(gold["e_data_final"]), rel=1e-4)
+    check_energy(s, xi, r[0]["e_data"], xi, float(gold["e_data"][0]), label="c3 first step")
+    check_energy(s, xg, r[-1]["e_data"], xo, float(gold["e_data_final"]), label="c3 final")
     assert np.all((r["flags"] & ~8) == 0)
 
 
-def _against_stored(s, x, rep, name, e_rel):
+def _against_stored(s, x, rep, name, pose_gpu=None):
     """Parameters and final data energy of a full-frame run against a stored oracle run of the same problem."""
     gold = np.load(os.path.join(HERE, "golden", f"c3_{name}_oracle.npz"))
     r = s.M.read_report(rep)
@@ -143,7 +145,9 @@ def _against_stored(s, x, rep, name, e_rel):
           abs(r[-1]["e_data"] - float(gold["e_data_final"])) / float(gold["e_data_final"]))
     assert rel_err(xg, xo) < 1e-5
     assert rel_err(xg - xi, xo - xi) < 1e-4
-    assert r[-1]["e_data"] == pytest.approx(float(gold["e_data_final"]), rel=e_rel)
+    pose_ref = (gold["R"], gold["T"]) if pose_gpu is not None else None
+    check_energy(s, xg, r[-1]["e_data"], xo, float(gold["e_data_final"]), pose_gpu=pose_gpu, pose_ref=pose_ref,
+                 label=f"c3 {name} final")
     assert np.all((r["flags"] & ~8) == 0)
     return gold, r
 
@@ -156,7 +160,7 @@ def test_c3_keypoints_against_stored_oracle(c3):
     keys = s.M.keypoints(torch.tensor(kp, device="cuda"), torch.tensor(tgt, device="cuda").contiguous(), 10.0)
     x = s.M.identity_params(s.m)
     rep, _ = s.M.gn_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, s.params, s.ws, keys=keys)
-    gold, r = _against_stored(s, x, rep, "kp500", 1e-4)
+    gold, r = _against_stored(s, x, rep, "kp500")
     assert r[-1]["e_corr"] == pytest.approx(float(gold["e_corr_final"]), rel=1e-4)
 
 
@@ -167,20 +171,20 @@ def test_c3_adaptive_lm_against_stored_oracle(c3):
     x = s.M.identity_params(s.m)
     rep, _ = s.M.lm_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, s.params, s.ws,
                              lm=s.M.LMParams())
-    gold, r = _against_stored(s, x, rep, "lm", 1e-4)
+    gold, r = _against_stored(s, x, rep, "lm")
     G = s.params.gn_iters
     assert [bool(v) for v in r["lm_accepted"][:G]] == [bool(v) for v in gold["accepted"]]
     np.testing.assert_allclose(r["lm_lambda"][:G], gold["lam"], rtol=1e-5)
 
 
 def test_c3_joint_pose_against_stored_oracle(c3):
-    """The frame with the pose as unknowns (Eq.(10), w_r = 1e6, w_p = 1e3).  The returned pose is float32, and
-    its rounding moves the data term more than the ED parameters do, hence the wider energy bar."""
+    """The frame with the pose as unknowns (Eq.(10), w_r = 1e6, w_p = 1e3); each side's final decisions are
+    taken at its own refined pose."""
     s = c3
     x = s.M.identity_params(s.m)
     rep, pose, _ = s.M.joint_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, s.params, s.ws)
-    gold, r = _against_stored(s, x, rep, "joint", 2e-4)
     P = pose.cpu().numpy().astype(np.float64)
+    gold, r = _against_stored(s, x, rep, "joint", pose_gpu=(P[:9].reshape(3, 3), P[9:]))
     T0 = np.asarray(s.sc["T"], np.float32).astype(np.float64)
     moved = np.abs(gold["T"] - T0).max()
     assert moved > 0.1   # the pose moves (mm)

@@ -136,3 +136,36 @@ def test_capacity_overflow_is_flagged_not_fatal(lib):
     rep, _ = s.M.gn_register(s.pts, s.nodes, x, g, s.depth, s.cam, s.pose, s.params, s.ws)
     torch.cuda.synchronize()
     assert s.M.read_report(rep).shape[0] == s.params.gn_iters + 1
+
+
+@pytest.mark.parametrize("k,step", [(4, 3), (8, 3), (4, 5)])
+def test_long_node_lists(lib, k, step):
+    """Coarse nodes over a dense model: every node list is longer than one LDS sort holds (MISSLAM_MAX_LIST),
+    up to several pieces and an odd number of them; the lists must still be complete and in (sorted node set,
+    point index) order, and the registration must follow the oracle."""
+    sc = gen.make_scene("c2")
+    nodes = sc["nodes"].reshape(16, 25, 3)[::step, ::step].reshape(-1, 3).copy()
+    sc = dict(sc, nodes=nodes, sigma=5.0 * step, node_spacing=5.0 * step)
+    s = Scene(sc)
+    s.params.k = k
+    g = s.graph
+    info = g.info.cpu().numpy()
+    assert info[3] == 0
+    assert info[2] > 2 * 2048 if step == 5 else info[2] > 2048      # longest list
+    ref = oracle.build_graph(sc["points"], sc["nodes"], k, "gauss", sc["sigma"])
+    assert np.array_equal(g.knn_idx.cpu().numpy().T, ref["idx"])
+    lp = g.list_ptr.cpu().numpy()
+    lst = g.list_pts.cpu().numpy()
+    keys = [tuple(sorted(r)) for r in ref["idx"]]
+    for j in range(s.m):
+        want = sorted(np.nonzero(np.any(ref["idx"] == j, axis=1))[0].tolist(), key=lambda p: (keys[p], p))
+        assert lst[lp[j]:lp[j + 1]].tolist() == want, j
+    x = s.M.identity_params(s.m)
+    s.params.gn_iters = 3
+    rep, ch = s.M.gn_register(s.pts, s.nodes, x, g, s.depth, s.cam, s.pose, s.params, s.ws, corr_hist=True)
+    torch.cuda.synchronize()
+    r = s.M.read_report(rep)
+    assert np.all(r["flags"] == 0)
+    xo, _ = oracle.gn_register(s.problem(), graph=s.oracle_graph_from_gpu(), corr_sequence=list(ch.cpu().numpy()))
+    print("long lists k", k, "longest", info[2], "x rel", rel_err(x.cpu().numpy(), xo))
+    assert rel_err(x.cpu().numpy(), xo) < 1e-5

@@ -46,11 +46,15 @@ def test_keypoint_registration_matches_oracle(lib, name, count):
     x0 = oracle.identity_params(s.m)
     print(name, "x rel", rel_err(xg, xo), "delta rel", rel_err(xg - x0, xo - x0),
           "e_corr", r["e_corr"][[0, -1]].tolist(), [orep["iters"][0]["e_corr"], orep["final"]["e_corr"]])
-    assert rel_err(xg, xo) < 1e-4
-    assert rel_err(xg - x0, xo - x0) < 1e-3
+    assert rel_err(xg, xo) < 1e-5
+    assert rel_err(xg - x0, xo - x0) < 1e-4
+    # each key-point residual is a difference of ~60 mm float32 positions: a few ulps of 60 mm through the
+    # warp, about 1e-5 mm per coordinate, so |dE_corr| <= 2 sqrt(3 S E_corr) 1e-5 + 3 S 1e-10 (S key points)
     for it in range(pb.gn_iters):
-        assert r[it]["e_corr"] == pytest.approx(orep["iters"][it]["e_corr"], rel=1e-4)
-        assert r[it]["e_data"] == pytest.approx(orep["iters"][it]["e_data"], rel=1e-4)
+        e_it = orep["iters"][it]["e_corr"]
+        bound = 2.0 * np.sqrt(3 * count * e_it) * 1e-5 + 3 * count * 1e-10
+        assert abs(r[it]["e_corr"] - e_it) <= bound
+        assert r[it]["e_data"] == pytest.approx(orep["iters"][it]["e_data"], rel=1e-5)
     assert r[-1]["e_corr"] == pytest.approx(orep["final"]["e_corr"], rel=1e-3)
     assert np.all(r["flags"] == 0)
     # the term pulls the key points toward their matches

@@ -44,10 +44,10 @@ def _check(s, params, lm, r, xg, cs, pb_kw=None, keys=None):
     print("decisions", "".join("A" if a else "r" for a in acc), "x rel", rel_err(xg, xo), "delta rel",
           rel_err(xg - x0, xo - x0), "E", [float(v) for v in r["lm_e"][:G]], "lambda",
           [float(v) for v in r["lm_lambda"][:G]])
-    assert rel_err(xg, xo) < 1e-4
-    assert rel_err(xg - x0, xo - x0) < 1e-3
+    assert rel_err(xg, xo) < 1e-5
+    assert rel_err(xg - x0, xo - x0) < 1e-4
     for k in range(G):
-        assert r[k]["lm_e"] == pytest.approx(it[k]["E"], rel=1e-4)
+        assert r[k]["lm_e"] == pytest.approx(it[k]["E"], rel=1e-5)
         assert r[k]["lm_lambda"] == pytest.approx(it[k]["lambda"], rel=1e-5)
         # the GPU's own bookkeeping: the decision follows its objectives; the next step starts at the trial
         # point when the step was taken and at the same x (the same objective, bit for bit) when not

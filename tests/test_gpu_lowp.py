@@ -75,7 +75,8 @@ def test_low_precision_registration_c3(lib, prec, steps):
     s = Scene("c3")
     plain = np.load(os.path.join(HERE, "golden", "c3_oracle.npz"))
     emu_file = os.path.join(HERE, "golden", f"c3_{prec}_r{steps}_oracle.npz")
-    gold = np.load(emu_file) if os.path.exists(emu_file) else plain
+    assert os.path.exists(emu_file), f"missing same-form oracle run {emu_file} (tests/golden/make_oracle_golden.py)"
+    gold = np.load(emu_file)
     xi = oracle.identity_params(s.m)
     s.params.precision = PREC[prec][0]
     s.params.refine_steps = steps
