@@ -75,6 +75,7 @@ typedef enum {
 #define MISSLAM_MAX_PCG  64
 #define MISSLAM_MAX_ROW  32       /* max blocks per row of the normal matrix (node degree + 1) */
 #define MISSLAM_MAX_LIST 2048     /* node lists up to this length are sorted in one LDS pass; longer ones are merged */
+#define MISSLAM_NOALLOC_SCRATCH_BYTES 100663296   /* 96 MiB: scratch of misslam_gn_register_noalloc, per device */
 #define MISSLAM_MAX_KEYPOINTS 16777216   /* max key points per registration (2^24) */
 #define MISSLAM_SOLVE_ROWS 16     /* node rows per workgroup of the one-launch PCG of a single problem
                                      with at most 16 rows per CU (larger ones pack up to 21) */
@@ -300,6 +301,31 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
                                    const misslam_camera *camera, const misslam_pose *pose,
                                    const misslam_params *params, misslam_report *rep,
                                    int32_t *corr_hist, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * For callers that cannot allocate device memory or pass a workspace: code
+ * recorded under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The float32 form of misslam_gn_register (same kernels, same
+ * arguments and results bit for bit) with its scratch in a file-scope device
+ * array of MISSLAM_NOALLOC_SCRATCH_BYTES (96 MiB) that every device the library
+ * runs on holds until the process ends.  It calls no hipMalloc or hipFree and
+ * records no profiling events; on its first call on a device it looks up that
+ * device's address of the array (hipGetSymbolAddress).
+ * Errors: MISSLAM_EINVAL as misslam_gn_register; MISSLAM_EUNSUPPORTED unless
+ * params->precision is FP32; MISSLAM_ECAPACITY when the frame's scratch (normal
+ * map, point pass, packed node lists, normal matrix, solve vectors: about
+ * 75 MB at 640x480, 250,000 points, 1,600 nodes, k = 4) exceeds the array.
+ * Every size check runs before any HIP call.
+ * All calls on one device share the one array and each leaves its contents
+ * behind (the calls clear what must start at zero themselves): calls that
+ * overlap on one device, on different streams or threads, race and must not
+ * be issued.
+ */
+misslam_status misslam_gn_register_noalloc(const misslam_points *points, misslam_nodes *nodes,
+                                           const misslam_graph *graph, const float *depth,
+                                           const misslam_camera *camera, const misslam_pose *pose,
+                                           const misslam_params *params, misslam_report *rep,
+                                           int32_t *corr_hist, void *stream);
 
 /*
  * misslam_gn_register with the key-point correspondence term of Eq.(3) added

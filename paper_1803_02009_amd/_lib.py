@@ -16,6 +16,7 @@ PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 LAUNCH_PLAIN, LAUNCH_COOPERATIVE, LAUNCH_KERNELS = 0, 1, 2
 MAX_K, MAX_PCG, MAX_ROW, MAX_LIST, SOLVE_ROWS = 8, 64, 32, 2048, 16
 MAX_KEYPOINTS = 1 << 24
+NOALLOC_SCRATCH_BYTES = 96 << 20
 
 c_float_p = ctypes.POINTER(ctypes.c_float)
 c_int32_p = ctypes.POINTER(ctypes.c_int32)
@@ -119,6 +120,8 @@ SIGNATURES = {
                                  ctypes.c_size_t, vp]),
     "misslam_gn_register_keypoints": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params),
                                            P(Keypoints), vp, vp, vp, ctypes.c_size_t, vp]),
+    "misslam_gn_register_noalloc": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(Params), vp, vp,
+                                         vp]),
     "misslam_default_lm_params": (None, [P(LMParams)]),
     "misslam_joint_register": (st, [P(Points), P(Nodes), P(Graph), vp, P(Camera), P(Pose), P(PoseWeights),
                                     P(Keypoints), P(Params), vp, vp, vp, vp, ctypes.c_size_t, vp]),

@@ -61,12 +61,17 @@ Profiler &prof() {
     return p;
 }
 
+// Set while the allocation-free registration enqueues: it records no events
+// (creating one can allocate).
+thread_local bool tl_no_events = false;
+
 // Brackets the launches of one phase with events on its stream when profiling is on.
 struct Timed {
     hipStream_t st;
     int phase;
     hipEvent_t a = nullptr, b = nullptr;
     Timed(int ph, hipStream_t s) : st(s), phase(ph) {
+        if (tl_no_events) return;
         Profiler &p = prof();
         std::lock_guard<std::mutex> lk(p.mu);
         if (!p.on) return;
@@ -665,6 +670,76 @@ misslam_status misslam_gn_register(const misslam_points *points, misslam_nodes *
                                    size_t ws_bytes, void *stream) {
     return gn_register(points, nodes, graph, depth, camera, pose, params, nullptr, nullptr, rep, corr_hist, ws,
                        ws_bytes, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free registration
+
+namespace {
+
+// Scratch of misslam_gn_register_noalloc.  Each device holds its own copy from
+// the library's load until the process ends.  Host code never uses the name as
+// an address: the device address comes from hipGetSymbolAddress, per device.
+static __device__ __align__(256) unsigned char scratch[MISSLAM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+struct ScratchTable {
+    std::mutex mu;
+    void *ptr[kMaxDevices] = {};
+};
+
+ScratchTable &scratch_table() {
+    static ScratchTable t;
+    return t;
+}
+
+// The current device's address of the scratch array, looked up on the first call on that device.
+hipError_t scratch_address(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    ScratchTable &t = scratch_table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (!t.ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        t.ptr[dev] = p;
+    }
+    *out = t.ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+misslam_status misslam_gn_register_noalloc(const misslam_points *points, misslam_nodes *nodes,
+                                           const misslam_graph *graph, const float *depth,
+                                           const misslam_camera *camera, const misslam_pose *pose,
+                                           const misslam_params *params, misslam_report *rep, int32_t *corr_hist,
+                                           void *stream) {
+    // every size check first, before any HIP call
+    if (!valid_points(points) || !valid_nodes(nodes) || !valid_graph(graph, points->n) || !depth ||
+        !valid_camera(camera) || !pose || !valid_params(params) || !rep)
+        return MISSLAM_EINVAL;
+    if (params->precision != MISSLAM_PREC_FP32) return MISSLAM_EUNSUPPORTED;
+    if (carve(nullptr, points->n, nodes->m, camera->width, camera->height, params->pcg_iters, params->k, WS_CORE)
+            .bytes > (size_t)MISSLAM_NOALLOC_SCRATCH_BYTES)
+        return MISSLAM_ECAPACITY;
+    void *ws = nullptr;
+    const hipError_t e = scratch_address(&ws);
+    if (e != hipSuccess) return hip_fail(e);
+    tl_no_events = true;
+    const misslam_status st = gn_register(points, nodes, graph, depth, camera, pose, params, nullptr, nullptr, rep,
+                                          corr_hist, ws, (size_t)MISSLAM_NOALLOC_SCRATCH_BYTES, stream, nullptr,
+                                          nullptr, true);
+    tl_no_events = false;
+    return st;
 }
 
 misslam_status misslam_gn_register_keypoints(const misslam_points *points, misslam_nodes *nodes,

@@ -251,6 +251,21 @@ def gn_register(points, nodes, x, graph, depth, cam, pose_, params, ws, corr_his
     return rep, ch
 
 
+def gn_register_noalloc(points, nodes, x, graph, depth, cam, pose_, params, corr_hist=False):
+    """misslam_gn_register_noalloc: the float32 registration with the library's own per-device scratch array
+    instead of a workspace (nothing is allocated by the call).  Returns (report, corr_hist or None); the report
+    and the history are the caller's outputs, allocated here by torch."""
+    n = points.shape[1]
+    rep = new_report(params.gn_iters + 1)
+    ch = torch.empty((params.gn_iters, n), dtype=torch.int32, device=points.device) if corr_hist else None
+    check("misslam_gn_register_noalloc",
+          load().misslam_gn_register_noalloc(ctypes.byref(points_struct(points)), ctypes.byref(nodes_struct(nodes, x)),
+                                             ctypes.byref(graph.c()), _ptr(depth), ctypes.byref(cam),
+                                             ctypes.byref(pose_), ctypes.byref(params.c()), _ptr(rep), _ptr(ch),
+                                             _stream()))
+    return rep, ch
+
+
 @dataclasses.dataclass
 class LMParams:
     """Adaptive damping schedule (Sec. II-F): classical Levenberg-Marquardt factors."""

@@ -76,7 +76,7 @@ def test_header_constants_match_binding():
             "PREC_FP16": _lib.PREC_FP16, "LAUNCH_PLAIN": _lib.LAUNCH_PLAIN,
             "LAUNCH_COOPERATIVE": _lib.LAUNCH_COOPERATIVE, "LAUNCH_KERNELS": _lib.LAUNCH_KERNELS, "MAX_K": _lib.MAX_K, "MAX_PCG": _lib.MAX_PCG,
             "MAX_ROW": _lib.MAX_ROW, "MAX_LIST": _lib.MAX_LIST, "SOLVE_ROWS": _lib.SOLVE_ROWS,
-            "MAX_KEYPOINTS": _lib.MAX_KEYPOINTS}
+            "MAX_KEYPOINTS": _lib.MAX_KEYPOINTS, "NOALLOC_SCRATCH_BYTES": _lib.NOALLOC_SCRATCH_BYTES}
     for k, v in want.items():
         assert defs[k] == v, k
 
@@ -220,6 +220,31 @@ def test_validation_errors(lib):
     p2.k = 4
     p2.lambda_ = -1.0
     assert lib.misslam_pcg_solve(B(gr), 10, FAKE, FAKE, B(p2), FAKE, FAKE, FAKE, 1 << 30, None) == _lib.EINVAL
+
+
+def test_noalloc_registration_checks_on_host(lib):
+    """The allocation-free registration checks every size before any HIP call: a frame whose scratch exceeds
+    the fixed array is refused (ECAPACITY), as are the low-precision forms and missing arguments."""
+    B = ctypes.byref
+    nr = lib.misslam_gn_register_noalloc
+    pts, nds, gr, p, cam, pose = _structs()
+    assert nr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(p), None, None, None) == _lib.EINVAL
+    assert nr(B(pts), B(nds), B(gr), None, B(cam), B(pose), B(p), FAKE, None, None) == _lib.EINVAL
+    plp = _lib.Params()
+    lib.misslam_default_params(B(plp))
+    plp.precision = _lib.PREC_FP16
+    assert nr(B(pts), B(nds), B(gr), FAKE, B(cam), B(pose), B(plp), FAKE, None, None) == _lib.EUNSUPPORTED
+    # the benchmark frame's scratch is below the array, twice its points is not; the workspace query of the
+    # same frame (every form's buffers) is larger than the array
+    big_cam = _lib.Camera(640, 480, 256.0, 256.0, 320.0, 240.0)
+    p.sigma = 2.5
+    full = lib.misslam_workspace_bytes(250000, 1600, 640, 480, B(p))
+    assert full > _lib.NOALLOC_SCRATCH_BYTES
+    over_pts, over_nds, over_gr, _, _, _ = _structs(n=600000, m=1600)
+    assert nr(B(over_pts), B(over_nds), B(over_gr), FAKE, B(big_cam), B(pose), B(p), FAKE, None,
+              None) == _lib.ECAPACITY
+    huge_cam = _lib.Camera(4096, 4096, 1600.0, 1600.0, 2048.0, 2048.0)
+    assert nr(B(pts), B(nds), B(gr), FAKE, B(huge_cam), B(pose), B(p), FAKE, None, None) == _lib.ECAPACITY
 
 
 def test_profiler_api_on_host(lib):
