@@ -26,6 +26,15 @@ Readings where the paper is silent or loose:
   * Colour (Eq.(13)), when the model carries it: survivors keep theirs, a
     lifted point takes the frame's colour at its pixel, a merged voxel the
     mean of its members' colours (float64, ascending index).
+  * Stability S_i (Sec. II-G: unstable points, seen in few frames and not
+    recently, are dropped; Alg. 3): a point becomes stable once it has been
+    registered in enough frames, its weight (one per registration, Eq.(15))
+    having reached tau_weight, and stays stable from then on, as in the
+    point fusion of Keller et al. 2013 that the section follows.  Removal
+    deletes an unstable point whose age exceeds tau_time; a lifted point
+    starts stable only if its weight 1 reaches tau_weight; a merged voxel is
+    stable when one of its members is.  With S_i = (weight >= tau_weight) on
+    entry the removal is the weight rule above.
 Test infrastructure only (see the package header).
 """
 import numpy as np
@@ -55,10 +64,11 @@ def _groups(keys):
 
 
 def grow(points, normals, weight, stamp, registered, reg, depth, camera, R, T, Nmap, Nvalid, frame, nodes,
-         node_spacing, voxel=0.22, tau_time=10, tau_weight=2.0, color=None, image=None):
+         node_spacing, voxel=0.22, tau_time=10, tau_weight=2.0, color=None, image=None, stable=None):
     """Alg. 2 steps 3-5 and Alg. 3 on a fused model.  Returns dict(points, normals,
     weight, stamp (float32/int arrays of the new model), nodes (old + new),
-    lifted, culled, merged (counts)[, color])."""
+    lifted, culled, merged (counts)[, color][, stable]).  stable: the points'
+    S_i flags (bool) when the model carries them."""
     P = np.asarray(points, dtype=np.float64)
     Nn = np.asarray(normals, dtype=np.float64)
     w = np.asarray(weight, dtype=np.float64)
@@ -68,8 +78,11 @@ def grow(points, normals, weight, stamp, registered, reg, depth, camera, R, T, N
     Rm = np.asarray(R, dtype=np.float64)
     Tv = np.asarray(T, dtype=np.float64)
 
-    # removal (Alg. 3)
-    keep = ~((frame - st > tau_time) & (w < tau_weight))
+    # stability, then removal (Alg. 3)
+    S = w >= tau_weight
+    if stable is not None:
+        S = S | np.asarray(stable, dtype=bool)
+    keep = ~((frame - st > tau_time) & ~S)
     # Group 2: unregistered pixels with depth and a normal
     win = np.asarray(reg, dtype=np.int64).reshape(-1)
     reg_pix = np.zeros(W * H, dtype=bool)
@@ -90,6 +103,7 @@ def grow(points, normals, weight, stamp, registered, reg, depth, camera, R, T, N
     nrm = np.concatenate([Nn[keep].astype(np.float32), ln])
     wt = np.concatenate([w[keep], np.ones(len(lp))]).astype(np.float32)
     stp = np.concatenate([st[keep], np.full(len(lp), frame, dtype=np.int64)])
+    stab = np.concatenate([S[keep], np.full(len(lp), 1.0 >= tau_weight)])
     col = None
     if color is not None:
         col = np.concatenate([np.asarray(color, dtype=np.float32)[keep],
@@ -116,6 +130,7 @@ def grow(points, normals, weight, stamp, registered, reg, depth, camera, R, T, N
                 np.float32)
             wt[lead] = wt[members].max()
             stp[lead] = stp[members].max()
+            stab[lead] = stab[members].any()
             if col is not None:
                 cm = col[members].astype(np.float64)
                 cs = np.zeros(3)
@@ -124,7 +139,7 @@ def grow(points, normals, weight, stamp, registered, reg, depth, camera, R, T, N
                 col[lead] = (cs / len(members)).astype(np.float32)
             alive[members[1:]] = False
             merged += len(members) - 1
-    pts, nrm, wt, stp = pts[alive], nrm[alive], wt[alive], stp[alive]
+    pts, nrm, wt, stp, stab = pts[alive], nrm[alive], wt[alive], stp[alive], stab[alive]
     if col is not None:
         col = col[alive]
 
@@ -151,4 +166,6 @@ def grow(points, normals, weight, stamp, registered, reg, depth, camera, R, T, N
            "lifted": int(lift.sum()), "culled": int((~keep).sum()), "merged": merged, "new_nodes": len(new_nodes)}
     if col is not None:
         out["color"] = col
+    if stable is not None:
+        out["stable"] = stab
     return out

@@ -117,6 +117,38 @@ def test_colour_follows_lift_merge_and_removal():
     np.testing.assert_array_equal(c[2], img[1, 2])
 
 
+def test_stability_flag():
+    """S_i (Sec. II-G, Alg. 3): stable once registered in enough frames (weight >= tau_weight) and from then
+    on; removal takes only unstable points older than tau_time; a merged voxel is stable when a member is;
+    lifted points start unstable at tau_weight 2 (their weight is 1) and stable at tau_weight 1."""
+    D, N, ok = _frame(0.0)                          # empty frame: nothing lifted
+    p, nrm = _model(6)
+    p[:] = [[0, 0, 50], [10, 0, 50], [20, 0, 50], [30, 0, 50], [40.05, 0.05, 50.01], [40.10, 0.10, 50.02]]
+    w = np.array([1.0, 1.0, 3.0, 1.0, 1.0, 5.0], np.float32)
+    st = np.array([5, 5, 5, 20, 20, 3])            # frame 20: ages 15, 15, 15, 0, 0, 17
+    S0 = np.array([0, 1, 0, 0, 0, 0], bool)
+    args = (np.zeros(6, bool), np.full(12, -1), D, CAM, I3, Z3, N, ok, 20, np.zeros((0, 3), np.float32), 1000.0)
+    out = oracle.grow(p, nrm, w, st, *args, voxel=0.22, stable=S0)
+    # 0: unstable and old: removed.  1: flagged stable: kept, light and old as it is.  2: weight 3 >= 2: stable,
+    # kept.  3: unstable but seen this frame: kept, unstable.  4 and 5 share a voxel that 4 touches this frame:
+    # merged into 4, stable because 5 (weight 5) is.
+    assert out["culled"] == 1 and out["merged"] == 1
+    np.testing.assert_array_equal(out["points"][:3], p[[1, 2, 3]])
+    np.testing.assert_array_equal(out["stable"], [True, True, False, True])
+    # without the flag plane the weight alone decides, which removes point 1 as well
+    out_w = oracle.grow(p, nrm, w, st, *args, voxel=0.22)
+    assert out_w["culled"] == 2 and "stable" not in out_w
+    # with S_i = (weight >= tau_weight) on entry the two agree
+    out_s = oracle.grow(p, nrm, w, st, *args, voxel=0.22, stable=w >= 2.0)
+    np.testing.assert_array_equal(out_s["points"], out_w["points"])
+    D2, N2, ok2 = _frame()
+    for tw, want in ((2.0, False), (1.0, True)):
+        o2 = oracle.grow(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32), np.zeros(0, np.float32),
+                         np.zeros(0, int), np.zeros(0, bool), np.full(12, -1), D2, CAM, I3, Z3, N2, ok2, 1,
+                         np.zeros((0, 3), np.float32), 1000.0, voxel=1e-3, tau_weight=tw, stable=np.zeros(0, bool))
+        assert o2["lifted"] == 12 and np.all(o2["stable"] == want)
+
+
 def test_node_regeneration():
     D, N, ok = _frame(0.0)
     p, nrm = _model(4)
