@@ -67,6 +67,13 @@ typedef enum {
                                         same results to rounding (bitwise for the joint pose form); not for
                                         batches (MISSLAM_EUNSUPPORTED) */
 
+/* The recurrence of the one-launch solve (fixed pose; the joint pose form and
+ * MISSLAM_LAUNCH_KERNELS always use the textbook one). */
+#define MISSLAM_SOLVE_TEXTBOOK 0     /* the textbook recurrence: two exchanges per iteration, float32 vectors
+                                        with float64 sums (default) */
+#define MISSLAM_SOLVE_PIPELINED 1    /* pipelined preconditioned CG (Ghysels and Vanroose 2014): one exchange
+                                        between workgroups per iteration, float64 vectors */
+
 #define MISSLAM_PREC_FP32 0       /* plain float32 normal equations */
 #define MISSLAM_PREC_BF16 1       /* data-term products in bfloat16 on the matrix cores, float32 accumulation */
 #define MISSLAM_PREC_FP16 2       /* same with float16 inputs */
@@ -86,13 +93,14 @@ typedef struct { int32_t width, height; float fx, fy, cx, cy; } misslam_camera;
 /* (host) rigid scope pose of the frame, camera = R * world + T, R row-major (Eq.(1)'s R, T) */
 typedef struct { float R[9]; float T[3]; } misslam_pose;
 
-/* model point cloud (Sec. II-A): coordinate, normal, fusion weight, time stamp */
+/* model point cloud (Sec. II-A): coordinate, normal, fusion weight, time stamp, stability */
 typedef struct {
     int64_t n, capacity;
     float *px, *py, *pz;      /* canonical coordinates, n (<= capacity) each */
     float *nx, *ny, *nz;      /* unit normals */
     float *w;                 /* fusion weight (Eq.(15)); may be NULL outside misslam_fuse */
     int32_t *stamp;           /* last registered frame; may be NULL outside misslam_fuse */
+    uint8_t *stable;          /* stability S_i (Sec. II-G), 0 or 1; may be NULL; kept by misslam_grow */
 } misslam_points;
 
 /* ED nodes (Sec. II-D): positions g_j and parameters x_j */
@@ -145,6 +153,7 @@ typedef struct {
     int32_t solve_launch;      /* MISSLAM_LAUNCH_*: how the one-launch PCG is started */
     int32_t sync_spin_limit;   /* polls of one wait in the one-launch solves before they give up
                                   (MISSLAM_FLAG_SYNC_TIMEOUT, the step discarded); 0: 262144 */
+    int32_t solve_form;        /* MISSLAM_SOLVE_*: recurrence of the one-launch solve */
 } misslam_params;
 
 /* one entry per Gauss-Newton iteration, plus a final entry at the returned parameters (device) */

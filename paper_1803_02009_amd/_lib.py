@@ -14,6 +14,7 @@ FLAG_SYNC_TIMEOUT = 32
 WEIGHT_GAUSS, WEIGHT_LINEAR = 0, 1
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 LAUNCH_PLAIN, LAUNCH_COOPERATIVE, LAUNCH_KERNELS = 0, 1, 2
+SOLVE_TEXTBOOK, SOLVE_PIPELINED = 0, 1
 MAX_K, MAX_PCG, MAX_ROW, MAX_LIST, SOLVE_ROWS = 8, 64, 32, 2048, 16
 MAX_KEYPOINTS = 1 << 24
 NOALLOC_SCRATCH_BYTES = 96 << 20
@@ -35,7 +36,7 @@ class Points(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("capacity", ctypes.c_int64),
                 ("px", ctypes.c_void_p), ("py", ctypes.c_void_p), ("pz", ctypes.c_void_p),
                 ("nx", ctypes.c_void_p), ("ny", ctypes.c_void_p), ("nz", ctypes.c_void_p),
-                ("w", ctypes.c_void_p), ("stamp", ctypes.c_void_p)]
+                ("w", ctypes.c_void_p), ("stamp", ctypes.c_void_p), ("stable", ctypes.c_void_p)]
 
 
 class Nodes(ctypes.Structure):
@@ -58,7 +59,8 @@ class Params(ctypes.Structure):
                 ("eps_d", ctypes.c_double), ("cos_eps_n", ctypes.c_double), ("lambda_", ctypes.c_float),
                 ("gn_iters", ctypes.c_int32), ("pcg_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("refine_steps", ctypes.c_int32), ("reject_threshold", ctypes.c_float),
-                ("solve_launch", ctypes.c_int32), ("sync_spin_limit", ctypes.c_int32)]
+                ("solve_launch", ctypes.c_int32), ("sync_spin_limit", ctypes.c_int32),
+                ("solve_form", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):

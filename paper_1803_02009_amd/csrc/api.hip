@@ -173,6 +173,7 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
     L.pcg.part = c.take<double>((size_t)(pcg_iters + 2) * 4 * nblk_max);
     L.pcg.status = c.take<int32_t>((size_t)2 * (pcg_iters + 2));
     L.pcg.bar = c.take<unsigned>(msl::MSL_BAR_WORDS);
+    L.pcg.halo = c.take<double>((size_t)24 * m);
     L.pcg.nblk = nblk;
     L.pcg.nblk_max = nblk_max;
     L.graph.tmp = graph ? c.take<int32_t>((size_t)m * MISSLAM_MAX_ROW) : nullptr;
@@ -224,7 +225,7 @@ bool valid_params(const misslam_params *p) {
            p->precision >= MISSLAM_PREC_FP32 && p->precision <= MISSLAM_PREC_FP16 && p->refine_steps >= 0 &&
            (p->solve_launch == MISSLAM_LAUNCH_PLAIN || p->solve_launch == MISSLAM_LAUNCH_COOPERATIVE ||
             p->solve_launch == MISSLAM_LAUNCH_KERNELS) &&
-           p->sync_spin_limit >= 0;
+           p->sync_spin_limit >= 0 && (p->solve_form == MISSLAM_SOLVE_PIPELINED || p->solve_form == MISSLAM_SOLVE_TEXTBOOK);
 }
 
 bool valid_points(const misslam_points *p) {
@@ -286,6 +287,7 @@ void misslam_default_params(misslam_params *p) {
     p->reject_threshold = 0.0f;
     p->solve_launch = MISSLAM_LAUNCH_PLAIN;
     p->sync_spin_limit = 0;
+    p->solve_form = MISSLAM_SOLVE_TEXTBOOK;
 }
 
 const char *misslam_status_string(int32_t s) {
@@ -373,11 +375,12 @@ static hipError_t solve_persistent(const msl::GraphView &g, int m, const float *
                                    const float *minv, float lambda, int iters, float *delta, const msl::PcgScratch &s,
                                    misslam_report *rep, float *params, hipStream_t st, bool coop,
                                    int zeroed_words = 0, const float *lambda_dev = nullptr, bool kernels = false,
-                                   unsigned spin = 0) {
+                                   unsigned spin = 0, bool textbook = false) {
     bool used = false;
     hipError_t e = kernels ? hipSuccess
                            : msl::launch_pcg_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep,
-                                                        params, st, &used, coop, zeroed_words, lambda_dev, spin);
+                                                        params, st, &used, coop, zeroed_words, lambda_dev, spin,
+                                                        textbook);
     if (e == hipSuccess && !used)
         e = msl::launch_pcg_update(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st, lambda_dev);
     return e;
@@ -385,7 +388,8 @@ static hipError_t solve_persistent(const msl::GraphView &g, int m, const float *
 
 static hipError_t solve(const msl::GraphView &g, int m, const float *blocks, const float *gvec, float *minv,
                         float lambda, int iters, float *delta, const msl::PcgScratch &s, misslam_report *rep,
-                        float *params, hipStream_t st, bool coop, bool kernels = false, unsigned spin = 0) {
+                        float *params, hipStream_t st, bool coop, bool kernels = false, unsigned spin = 0,
+                        bool textbook = false) {
     hipError_t e;
     {
         Timed t(PH_BJACOBI, st);
@@ -394,7 +398,7 @@ static hipError_t solve(const msl::GraphView &g, int m, const float *blocks, con
     if (e == hipSuccess) {
         Timed t(PH_PCG, st);
         e = solve_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st, coop, 0, nullptr,
-                             kernels, spin);
+                             kernels, spin, textbook);
     }
     return e;
 }
@@ -465,7 +469,8 @@ misslam_status misslam_pcg_solve(const misslam_graph *graph, int32_t m, const fl
     if (e == hipSuccess)
         e = solve(gv, m, blocks, g, L.step.minv, params->lambda, params->pcg_iters, delta, L.pcg, rep, nullptr, st,
                   params->solve_launch == MISSLAM_LAUNCH_COOPERATIVE,
-                  params->solve_launch == MISSLAM_LAUNCH_KERNELS, (unsigned)params->sync_spin_limit);
+                  params->solve_launch == MISSLAM_LAUNCH_KERNELS, (unsigned)params->sync_spin_limit,
+                  params->solve_form == MISSLAM_SOLVE_TEXTBOOK);
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
 }
 
@@ -508,6 +513,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
     const int64_t n = points->n;
     const int m = nodes->m;
     const unsigned spin = (unsigned)params->sync_spin_limit;
+    const bool textbook = params->solve_form == MISSLAM_SOLVE_TEXTBOOK;
     hipError_t e = msl::launch_report_init(rep, G + 1, st, graph->info);
     if (e == hipSuccess && lowp) e = msl::launch_report_init(L.rep, 1, st);
     if (e == hipSuccess && lm) e = msl::launch_lm_init(L.lm_lambda, lm->lambda0, st);
@@ -606,7 +612,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
                 Timed t(PH_PCG, st);
                 e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
                                      L.delta, L.pcg, rep + it, lm ? nullptr : nodes->params, st, coop,
-                                     msl::msl_sync_words(m), lm ? L.lm_lambda : nullptr, kernels, spin);
+                                     msl::msl_sync_words(m), lm ? L.lm_lambda : nullptr, kernels, spin, textbook);
             }
             if (e == hipSuccess && lm) {
                 // the trial point x + dx: its objective decides whether the step is taken
@@ -642,7 +648,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
         if (e == hipSuccess) {
             Timed t(PH_PCG, st);
             e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
-                                 L.delta, L.pcg, rep + it, nullptr, st, coop, 0, nullptr, kernels, spin);
+                                 L.delta, L.pcg, rep + it, nullptr, st, coop, 0, nullptr, kernels, spin, textbook);
         }
         for (int r = 0; r < params->refine_steps && e == hipSuccess; ++r) {
             {
@@ -653,7 +659,7 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
             if (e == hipSuccess) {
                 Timed t(PH_PCG, st);
                 e = solve_persistent(view(graph), m, L.blocks, L.rhs, L.step.minv, params->lambda, params->pcg_iters,
-                                     L.delta2, L.pcg, L.rep, nullptr, st, coop, 0, nullptr, kernels, spin);
+                                     L.delta2, L.pcg, L.rep, nullptr, st, coop, 0, nullptr, kernels, spin, textbook);
             }
             // dx += the correction unless its solve failed; its flags join the step's report
             if (e == hipSuccess) e = msl::launch_step_commit(L.delta, L.delta2, 12 * m, L.rep, st, rep + it);
@@ -929,6 +935,7 @@ struct GrowLayout {
     float *stage;
     int32_t *stage_stamp;
     float *stage_color;
+    uint8_t *stage_stable;
     size_t bytes;
 };
 
@@ -955,6 +962,7 @@ GrowLayout carve_grow(void *ws, int64_t n, int32_t W, int32_t H) {
     L.s.v1 = c.take<uint32_t>((size_t)Cb);
     L.s.cent = c.take<float>((size_t)3 * Cb);
     L.stage_color = c.take<float>((size_t)3 * Cb);
+    L.stage_stable = c.take<uint8_t>((size_t)Cb);
     L.bytes = align_up(c.off);
     return L;
 }
@@ -1020,6 +1028,8 @@ static misslam_status grow_impl(misslam_points *points, misslam_nodes *nodes, co
     g.color = color;
     g.color_stride = color_stride;
     g.stage_color = L.stage_color;
+    g.stable = points->stable;
+    g.stage_stable = L.stage_stable;
     const hipStream_t st = stream_of(stream);
     Timed t(PH_GROW, st);
     const hipError_t e = msl::launch_grow(g, L.s, counts_out, st);
@@ -1120,6 +1130,9 @@ void batch_items(misslam_batch *b, void *ws, int rows) {
         A.status = L.pcg.status;
         A.done = L.pcg.status + (b->params.pcg_iters + 2);
         if (b->params.sync_spin_limit > 0) A.spin = (unsigned)b->params.sync_spin_limit;
+        A.halo[0] = L.pcg.halo;                       // the pipelined recurrence's exchanged vectors
+        A.halo[1] = L.pcg.halo + (size_t)12 * m;
+        A.textbook = b->params.solve_form == MISSLAM_SOLVE_TEXTBOOK;
         it.rep = p.report;
         it.params = p.nodes.params;
         it.depth = p.depth;
@@ -1158,11 +1171,12 @@ hipError_t batch_enqueue(misslam_batch *b, hipStream_t st, bool cooperative) {
         e = msl::launch_point_pass_batched(d, count, k, b->total_pp, it, st);
         if (e == hipSuccess) e = msl::launch_assemble_batched(d, count, k, b->total_rows, it, st);
         if (e == hipSuccess) e = msl::launch_energy_report_batched(d, count, it, b->bar,
-                                                                   std::min(8 * b->total_wgs, msl::MSL_BAR_WORDS), st);
+                                                                   std::min(msl::MSL_WG_WORDS * b->total_wgs, msl::MSL_BAR_WORDS), st);
         bool used = false;
         if (e == hipSuccess)
             e = msl::launch_pcg_batched(d, count, b->rows, b->total_wgs, b->total_rows, it, b->bar,
-                                        cooperative && b->params.solve_launch == MISSLAM_LAUNCH_COOPERATIVE, st, &used);
+                                        cooperative && b->params.solve_launch == MISSLAM_LAUNCH_COOPERATIVE, st, &used,
+                                        b->params.solve_form == MISSLAM_SOLVE_TEXTBOOK);
         if (e == hipSuccess && !used) return hipErrorInvalidConfiguration;
     }
     if (e == hipSuccess) e = msl::launch_point_pass_batched(d, count, k, b->total_pp, G, st);
@@ -1194,7 +1208,7 @@ hipError_t batch_save_params(misslam_batch *b, hipStream_t st, bool restore) {
 float batch_try(misslam_batch *b, void *ws, int rows, hipStream_t st) {
     int wgs = 0;
     for (const auto &p : b->probs) wgs += (p.nodes.m + rows - 1) / rows;
-    if (!msl::pcg_batched_fits(wgs)) return -1.f;
+    if (!msl::pcg_batched_fits(wgs, b->params.solve_form == MISSLAM_SOLVE_TEXTBOOK)) return -1.f;
     // the descriptors are rewritten by a blocking copy: nothing queued on st may still read them
     if (hipStreamSynchronize(st) != hipSuccess) return -1.f;
     if (batch_upload(b, ws, rows) != hipSuccess) return -1.f;
@@ -1270,7 +1284,8 @@ misslam_status misslam_batch_register(misslam_batch *b, void *ws, size_t ws_byte
         if (b->req_rows > 0) {
             int wgs = 0;
             for (const auto &p : b->probs) wgs += (p.nodes.m + b->req_rows - 1) / b->req_rows;
-            if (!msl::pcg_batched_fits(wgs)) return MISSLAM_EUNSUPPORTED;
+            if (!msl::pcg_batched_fits(wgs, b->params.solve_form == MISSLAM_SOLVE_TEXTBOOK))
+                return MISSLAM_EUNSUPPORTED;
             b->rows = b->req_rows;
         } else {
             // the tile: rows per solve workgroup, timed on this batch

@@ -14,15 +14,16 @@ struct GraphView {
     int32_t *info;
 };
 
-// Sync area of a persistent solve: 8 words (4 tagged 8-byte words) for each
+// Sync area of a persistent solve: 16 words (8 tagged 8-byte words) for each
 // of at most MSL_TAG_WGS workgroups of one launch.  The words of the
 // launch's workgroups must be zero when a solve starts.
 constexpr int MSL_TAG_WGS = 1024;
-constexpr int MSL_BAR_WORDS = 8 * MSL_TAG_WGS;
+constexpr int MSL_WG_WORDS = 16;
+constexpr int MSL_BAR_WORDS = MSL_WG_WORDS * MSL_TAG_WGS;
 // Sync words a persistent solve of m rows uses.
 inline int msl_sync_words(int m) {
     const int g = (m + MISSLAM_SOLVE_ROWS - 1) / MISSLAM_SOLVE_ROWS;
-    return g < 1 ? 8 : (g > MSL_TAG_WGS ? MSL_BAR_WORDS : 8 * g);
+    return g < 1 ? MSL_WG_WORDS : (g > MSL_TAG_WGS ? MSL_BAR_WORDS : MSL_WG_WORDS * g);
 }
 
 // Uniform grid of the nodes for the kNN search.
@@ -74,6 +75,7 @@ struct PcgScratch {
     int nblk;              // workgroups of the multi-kernel path
     int nblk_max;          // partial slots per reduction (>= every path's workgroup count)
     unsigned *bar;         // MSL_BAR_WORDS words: sync area of the persistent solve
+    double *halo;          // 2 x 12m: exchanged vectors of the pipelined one-launch solve
 };
 
 hipError_t launch_normal_map(const float *depth, const Cam &cam, float4 *out, hipStream_t st);
@@ -178,6 +180,8 @@ struct PcgArgs {
     int32_t *status;  // [it]: 0 running, 2 stopped by breakdown (propagates)
     int32_t *done;    // [it]: 1 if iteration it updated x
     unsigned spin = 1u << 18;   // polls of one wait of the one-launch solves before they give up
+    double *halo[2] = {nullptr, nullptr};   // 12 m each: the exchanged vector of the pipelined recurrence
+    bool textbook = false;      // one-launch solve: the textbook recurrence instead of the pipelined one
 };
 
 // One registration problem of a batch solved side by side: its step and
@@ -224,6 +228,9 @@ struct GrowArgs {
     float *color = nullptr;
     int64_t color_stride = 0;
     float *stage_color = nullptr;
+    // optional stability S_i (capacity flags) and its staging plane (stage_cap)
+    uint8_t *stable = nullptr;
+    uint8_t *stage_stable = nullptr;
 };
 
 struct GrowScratch {
@@ -353,7 +360,8 @@ hipError_t launch_report_init(misslam_report *rep, int count, hipStream_t st, co
 hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                                  float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
                                  float *params, hipStream_t st, bool *used, bool cooperative,
-                                 int zeroed_words = 0, const float *lambda_dev = nullptr, unsigned spin = 0);
+                                 int zeroed_words = 0, const float *lambda_dev = nullptr, unsigned spin = 0,
+                                 bool textbook = false);
 // x += dx (n entries) unless rep's flags, ORed with extra's when given (and written back into rep), carry
 // MISSLAM_FLAG_NONFINITE or MISSLAM_FLAG_SYNC_TIMEOUT: the whole step or nothing.
 hipError_t launch_step_commit(float *x, const float *dx, int n, misslam_report *rep, hipStream_t st,
@@ -375,8 +383,8 @@ hipError_t launch_report_init_batched(const BatchItem *items, int count, int per
 // Each problem's params += dx follows in a second launch (skipped per problem on a non-finite value or a
 // timeout in its report).
 hipError_t launch_pcg_batched(const BatchItem *items, int count, int rows_per_wg, int total_wgs, int total_rows,
-                              int it, unsigned *bar, bool cooperative, hipStream_t st, bool *used);
-int pcg_batched_fits(int total_wgs);
+                              int it, unsigned *bar, bool cooperative, hipStream_t st, bool *used, bool textbook);
+int pcg_batched_fits(int total_wgs, bool textbook);
 
 hipError_t launch_grow(GrowArgs g, const GrowScratch &s, int64_t *counts_out, hipStream_t st);
 int64_t grow_hist_entries(int64_t cap);

@@ -167,12 +167,19 @@ static hipError_t radix_sort(unsigned long long *k0, uint32_t *v0, unsigned long
 
 // ---------------------------------------------------------------- growth steps
 
-// flags over [existing points | pixels]: keep (Alg. 3 removal rule) and lift (Group 2)
+// Stability S_i (Sec. II-G, Alg. 3): stable once the weight (one per registration) has reached tau_weight,
+// and from then on; without the flag plane the weight alone decides.
+__device__ __forceinline__ bool point_stable(const GrowArgs &g, int64_t e) {
+    return g.w[e] >= g.tau_weight || (g.stable && g.stable[e] != 0);
+}
+
+// flags over [existing points | pixels]: keep (Alg. 3 removal rule: an unstable point older than tau_time
+// goes) and lift (Group 2)
 __global__ void __launch_bounds__(kGrowBlock) grow_flags_kernel(GrowArgs g, int32_t *__restrict__ flags) {
     const int64_t e = (int64_t)blockIdx.x * kGrowBlock + threadIdx.x;
     const int64_t n = g.n, npx = (int64_t)g.cam.W * g.cam.H;
     if (e < n) {
-        const bool del = (int64_t)g.frame - (int64_t)g.stamp[e] > (int64_t)g.tau_time && g.w[e] < g.tau_weight;
+        const bool del = (int64_t)g.frame - (int64_t)g.stamp[e] > (int64_t)g.tau_time && !point_stable(g, e);
         flags[e] = del ? 0 : 1;
     } else if (e < n + npx) {
         const int64_t t = e - n;
@@ -206,6 +213,7 @@ __global__ void __launch_bounds__(kGrowBlock) grow_scatter_kernel(GrowArgs g, co
         S[5 * C + pos] = g.nz[e];
         S[6 * C + pos] = g.w[e];
         g.stage_stamp[pos] = g.stamp[e];
+        if (g.stable) g.stage_stable[pos] = point_stable(g, e) ? 1 : 0;
         if (g.color)
 #pragma unroll
             for (int c = 0; c < 3; ++c) g.stage_color[c * C + pos] = g.color[c * g.color_stride + e];
@@ -226,6 +234,7 @@ __global__ void __launch_bounds__(kGrowBlock) grow_scatter_kernel(GrowArgs g, co
         }
         S[6 * C + pos] = 1.f;
         g.stage_stamp[pos] = g.frame;
+        if (g.stable) g.stage_stable[pos] = 1.f >= g.tau_weight ? 1 : 0;   // a lifted point has weight 1
         if (g.color)   // a lifted point takes the frame's colour at its pixel
 #pragma unroll
             for (int c = 0; c < 3; ++c) g.stage_color[c * C + pos] = g.image[t * 3 + c];
@@ -265,6 +274,7 @@ __global__ void __launch_bounds__(kGrowBlock) merge_kernel(GrowArgs g, const uns
     double ps[3] = {0.0, 0.0, 0.0}, ns[3] = {0.0, 0.0, 0.0}, cs[3] = {0.0, 0.0, 0.0};
     float wmax = -__builtin_huge_valf();
     int smax = -2147483647 - 1;
+    uint8_t sor = 0;
     for (int64_t j = i; j < j1; ++j) {   // ascending index
         const uint32_t q = idx[j];
 #pragma unroll
@@ -275,6 +285,7 @@ __global__ void __launch_bounds__(kGrowBlock) merge_kernel(GrowArgs g, const uns
         }
         wmax = fmaxf(wmax, S[6 * C + q]);
         smax = max(smax, g.stage_stamp[q]);
+        if (g.stable) sor |= g.stage_stable[q];
         if (j > i) alive[q] = 0;
     }
     const double cnt = (double)(j1 - i);
@@ -290,6 +301,7 @@ __global__ void __launch_bounds__(kGrowBlock) merge_kernel(GrowArgs g, const uns
     for (int a = 0; a < 3; ++a) S[(3 + a) * C + lead] = (float)(nm[a] / nn);
     S[6 * C + lead] = wmax;
     g.stage_stamp[lead] = smax;
+    if (g.stable) g.stage_stable[lead] = sor;   // stable when a member is
     if (g.color)   // mean colour of the voxel
 #pragma unroll
         for (int a = 0; a < 3; ++a) g.stage_color[a * C + lead] = (float)(cs[a] / cnt);
@@ -322,6 +334,7 @@ __global__ void __launch_bounds__(kGrowBlock) final_scatter_kernel(GrowArgs g, c
     g.nz[pos] = S[5 * C + i];
     g.w[pos] = S[6 * C + i];
     g.stamp[pos] = g.stage_stamp[i];
+    if (g.stable) g.stable[pos] = g.stage_stable[i];
     if (g.color)
 #pragma unroll
         for (int c = 0; c < 3; ++c) g.color[c * g.color_stride + pos] = g.stage_color[c * C + i];

@@ -458,9 +458,11 @@ struct TileRange {
 };
 
 // Setup of workgroup wg's share: its rows' blocks (as many as fit) into hc, their preconditioner blocks into
-// mc, and the distinct-column map.  firstmap: kMaxUnique * 12 ints of scratch LDS (free again on return).
+// mc, and the distinct-column map with at most max_unique (<= kMaxUnique) slots.  firstmap: map_ints ints of
+// scratch LDS (free again on return).
 __device__ __forceinline__ TileRange tile_setup(const PcgArgs &A, int rows_per_wg, int cache_blocks, int wg,
-                                                float4 *hc4, float *mc, TileLds &t, int *firstmap) {
+                                                float4 *hc4, float *mc, TileLds &t, int *firstmap, int map_ints,
+                                                int max_unique) {
     TileRange R;
     R.r0 = min(A.m, wg * rows_per_wg);
     R.r1 = min(A.m, R.r0 + rows_per_wg);
@@ -494,8 +496,7 @@ __device__ __forceinline__ TileRange tile_setup(const PcgArgs &A, int rows_per_w
     }
     __syncthreads();
     const int cmin = t.cmin_s, crange = t.cmax_s - t.cmin_s + 1;
-    constexpr int kMapRange = kMaxUnique * 12;         // ints of the first-block map
-    const bool mapped = nb > 0 && crange <= kMapRange;
+    const bool mapped = nb > 0 && crange <= map_ints;
     if (mapped) {
         for (int q = threadIdx.x; q < crange; q += kPcgThreads) firstmap[q] = 0x7FFFFFFF;
         __syncthreads();
@@ -544,7 +545,7 @@ __device__ __forceinline__ TileRange tile_setup(const PcgArgs &A, int rows_per_w
         for (int e = 0; e < kPerT; ++e) {
             const int q = threadIdx.x * kPerT + e;
             if (q < nb && firstpos[e] == q) {
-                const int sl = slot < kMaxUnique ? slot : -1;
+                const int sl = slot < max_unique ? slot : -1;
                 if (sl >= 0) t.ucol[sl] = t.colL[q];
                 if (sl >= 0 && t.colL[q] >= r0 && t.colL[q] < r1) t.lslot[t.colL[q] - r0] = sl;
                 t.bmap[q] = sl;
@@ -554,7 +555,7 @@ __device__ __forceinline__ TileRange tile_setup(const PcgArgs &A, int rows_per_w
         if (threadIdx.x == kPcgThreads - 1) {
             int tot = 0;
             for (int w = 0; w < kPcgThreads / kWave; ++w) tot += t.scan_w[w];
-            t.cnt_u = tot < kMaxUnique ? tot : kMaxUnique;
+            t.cnt_u = tot < max_unique ? tot : max_unique;
         }
     }
     __syncthreads();
@@ -585,7 +586,8 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
     const double lam = (double)(A.lambda_dev ? *A.lambda_dev : A.lambda);
     float *hc = reinterpret_cast<float *>(dyn4);       // cached blocks
     float *mc = hc + (size_t)cache_blocks * 144;       // preconditioner blocks of the rows
-    const TileRange R = tile_setup(A, rows_per_wg, cache_blocks, wg, dyn4, mc, tl, reinterpret_cast<int *>(zc4));
+    const TileRange R = tile_setup(A, rows_per_wg, cache_blocks, wg, dyn4, mc, tl, reinterpret_cast<int *>(zc4),
+                                   kMaxUnique * 12, kMaxUnique);
     const int r0 = R.r0, r1 = R.r1, b0 = R.b0, nb = R.nb, cached = R.cached, U = R.U;
     const int *bmap = tl.bmap, *colL = tl.colL, *ucol = tl.ucol, *lslot = tl.lslot;
     const int lr = threadIdx.x / 12, a = threadIdx.x % 12;
@@ -854,6 +856,321 @@ hipError_t launch_step_commit(float *x, const float *dx, int n, misslam_report *
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- pipelined PCG in one launch
+
+// The default recurrence of the one-launch solve: the preconditioned pipelined
+// conjugate gradients of Ghysels and Vanroose (2014), the same iterates as the
+// textbook recurrence in exact arithmetic.  Besides x, r and the direction p it
+// carries u = M r, w = A u, s = A p, q = M s and z = A q, so that the two inner
+// products of an iteration, gamma = r.u and delta = w.u, are formed before the
+// iteration's only product n = A m (m = M w) and travel in the same exchange as
+// m itself: one exchange per iteration instead of two.  Every vector is kept in
+// float64 (in registers: each thread owns one entry of each), which keeps the
+// longer recurrence as accurate as the textbook one: the only float32 values
+// are the matrix blocks and the preconditioner blocks.  The decisions are the
+// textbook ones: gamma = r.z = 0 stops the solve, p.Ap <= 0 (here
+// delta - beta gamma / alpha_prev) stops it and flags a breakdown.
+//
+// Exchange e (tag e = 1 before the first iteration, e = i + 2 in iteration i;
+// the sync words are zero at launch) publishes the workgroup's partials of
+// gamma and delta as tagged words in the sync slots of parity e & 1 (4
+// eight-byte words per workgroup), and the vector it multiplies next (u_0,
+// then m_i) through halo buffer e & 1; a workgroup rewrites a buffer or a slot
+// only two exchanges later, when every workgroup has read it.
+// |r|^2 of every iterate goes to A.part for the report, which ppcg_finish
+// completes after the launch (no exchange is spent on it).
+
+__device__ __forceinline__ void tag_publish2(unsigned *bar, int gid, unsigned tag, double v0, double v1) {
+    unsigned long long *w = tag_slots(bar) + 8 * gid + 4 * (tag & 1);
+    const unsigned long long b0 = (unsigned long long)__double_as_longlong(v0);
+    const unsigned long long b1 = (unsigned long long)__double_as_longlong(v1);
+    __hip_atomic_store(w, (b0 & 0xFFFFFFFF00000000ull) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(w + 1, (b0 << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(w + 2, (b1 & 0xFFFFFFFF00000000ull) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(w + 3, (b1 << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Fixed-order sums of the two values workgroups g0 .. g0+G-1 published with `tag` (bounded waits).
+__device__ __forceinline__ void tag_sum2(unsigned *bar, int g0, int G, unsigned tag, bool &broken,
+                                         double (*lds)[kPcgThreads / kWave], unsigned spin_limit, double &s0,
+                                         double &s1) {
+    double v[2] = {0.0, 0.0};
+    bool ok = true;
+    for (int t = threadIdx.x; t < G; t += kPcgThreads) {
+        unsigned long long *w = tag_slots(bar) + 8 * (g0 + t) + 4 * (tag & 1);
+        unsigned long long h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+        unsigned spins = 0;
+        for (;;) {
+            h0 = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            l0 = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            h1 = __hip_atomic_load(w + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            l1 = __hip_atomic_load(w + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((unsigned)h0 == tag && (unsigned)l0 == tag && (unsigned)h1 == tag && (unsigned)l1 == tag) break;
+            if (broken || ++spins > spin_limit) {
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (ok) {
+            v[0] += __longlong_as_double((long long)((h0 & 0xFFFFFFFF00000000ull) | (l0 >> 32)));
+            v[1] += __longlong_as_double((long long)((h1 & 0xFFFFFFFF00000000ull) | (l1 >> 32)));
+        }
+    }
+    broken = __syncthreads_or(broken || !ok) != 0;
+    wg_sum<2>(v, lds);
+    s0 = v[0];
+    s1 = v[1];
+}
+
+constexpr int kMaxUniqueP = 96;   // distinct columns staged per iteration (float64): 16 rows have about 50
+constexpr int kMPer = (kMaxUniqueP * 12 + kPcgThreads - 1) / kPcgThreads;   // staged doubles per thread
+
+__device__ __forceinline__ void ppcg_persistent_body(const PcgArgs &A, int rows_per_wg, int cache_blocks,
+                                                     unsigned *bar, int gid0, int wg, int G, misslam_report *rep) {
+    extern __shared__ float4 dyn4[];
+    __shared__ double red[2][kPcgThreads / kWave];
+    __shared__ TileLds tl;
+    __shared__ double mz[kMaxUniqueP * 12];           // the multiplied vector at the distinct columns
+    __shared__ double vv[kRowsPerBlk * 12];           // the rows' vector going through the preconditioner
+    const double lam = (double)(A.lambda_dev ? *A.lambda_dev : A.lambda);
+    float *hc = reinterpret_cast<float *>(dyn4);       // cached blocks
+    float *mc = hc + (size_t)cache_blocks * 144;       // preconditioner blocks of the rows
+    const TileRange R = tile_setup(A, rows_per_wg, cache_blocks, wg, dyn4, mc, tl, reinterpret_cast<int *>(mz),
+                                   kMaxUniqueP * 24, kMaxUniqueP);
+    const int r0 = R.r0, r1 = R.r1, b0 = R.b0, nb = R.nb, cached = R.cached, U = R.U;
+    const int *bmap = tl.bmap, *colL = tl.colL, *ucol = tl.ucol;
+    const int lr = threadIdx.x / 12, a = threadIdx.x % 12;
+    const int j = r0 + lr;
+    const bool act = lr < kRowsPerBlk && j < r1;
+    const int li = lr * 12 + a;
+    const size_t o = (size_t)j * 12 + a;
+    bool broken = false;
+    // this thread's row: its blocks q in [rq0, rq1) of the workgroup (at most MISSLAM_MAX_ROW), split into the
+    // blocks whose column is one of this workgroup's rows (multiplied while the exchange is in flight) and the
+    // others.  The summation order is the same whether a block is cached in LDS or read from memory, and
+    // whether its column is staged or not: own columns in block order into one chain, then the other blocks
+    // alternately into two chains, added at the end.
+    const int rq0 = act ? min(A.row_ptr[j], A.cap) - b0 : 0;
+    const int rq1 = act ? min(min(A.row_ptr[j + 1], A.cap) - b0, rq0 + MISSLAM_MAX_ROW) : 0;
+    uint32_t lmask = 0, rmask = 0;
+    for (int q = rq0; q < rq1; ++q) {
+        const int c = q < nb ? colL[q] : A.col_idx[b0 + q];
+        if (c >= r0 && c < r1)
+            lmask |= 1u << (q - rq0);
+        else
+            rmask |= 1u << (q - rq0);
+    }
+    const int mslot = act ? tl.lslot[lr] : -1;   // staged slot of this row's own column (-1: none)
+
+    // one block (workgroup block q) times the multiplied vector, float32 entries times float64 values summed
+    // in float64 in entry order; the block from LDS when cached, the vector from its staged slot when it has
+    // one, else from memory (halo buffer hb)
+    auto block_dot = [&](int q, double t, const double *hb) {
+        const int slot = q < nb ? bmap[q] : -1;
+        if (q < cached && slot >= 0) {
+            const float4 *Bq = reinterpret_cast<const float4 *>(hc + (size_t)q * 144 + a * 12);
+            const double *mq = mz + slot * 12;
+#pragma unroll
+            for (int h = 0; h < 3; ++h) {
+                const float4 b4 = Bq[h];
+                t = fma((double)b4.x, mq[4 * h], t);
+                t = fma((double)b4.y, mq[4 * h + 1], t);
+                t = fma((double)b4.z, mq[4 * h + 2], t);
+                t = fma((double)b4.w, mq[4 * h + 3], t);
+            }
+            return t;
+        }
+        const float *B = q < cached ? hc + (size_t)q * 144 + a * 12 : A.blocks + (size_t)(b0 + q) * 144 + a * 12;
+        if (slot >= 0) {
+            const double *ml = mz + slot * 12;
+#pragma unroll
+            for (int b = 0; b < 12; ++b) t = fma((double)B[b], ml[b], t);
+        } else {
+            const double *ml = hb + (size_t)A.col_idx[b0 + q] * 12;
+#pragma unroll
+            for (int b = 0; b < 12; ++b) t = fma((double)B[b], ld_dev(ml + b), t);
+        }
+        return t;
+    };
+    auto local_part = [&](const double *hb) {
+        double t = 0.0;
+        for (uint32_t mk = lmask; mk; mk &= mk - 1) t = block_dot(rq0 + __builtin_ctz(mk), t, hb);
+        return t;
+    };
+    // the other blocks of the row's product, the vector staged from halo buffer hb; t holds the local part
+    auto remote_part = [&](double t, const double *hb) {
+        double t1 = 0.0;
+        uint32_t mk = rmask;
+        while (mk) {
+            const int qa = rq0 + __builtin_ctz(mk);
+            mk &= mk - 1;
+            if (mk) {
+                const int qb = rq0 + __builtin_ctz(mk);
+                mk &= mk - 1;
+                t = block_dot(qa, t, hb);
+                t1 = block_dot(qb, t1, hb);
+            } else {
+                t = block_dot(qa, t, hb);
+            }
+        }
+        return t + t1;
+    };
+    // stage the vector at the distinct columns owned by other workgroups (own columns are written by their
+    // rows' threads), all loads in flight together
+    auto stage = [&](const double *hb) {
+        double mv[kMPer];
+#pragma unroll
+        for (int e = 0; e < kMPer; ++e) {
+            const int t = threadIdx.x + e * kPcgThreads;
+            if (t < U * 12 && (ucol[t / 12] < r0 || ucol[t / 12] >= r1))
+                mv[e] = ld_dev(hb + (size_t)ucol[t / 12] * 12 + t % 12);
+        }
+#pragma unroll
+        for (int e = 0; e < kMPer; ++e) {
+            const int t = threadIdx.x + e * kPcgThreads;
+            if (t < U * 12 && (ucol[t / 12] < r0 || ucol[t / 12] >= r1)) mz[t] = mv[e];
+        }
+        __syncthreads();
+    };
+    // M_j v for this thread's entry, v of the row in vv
+    auto precond = [&]() {
+        const float *M = mc + (size_t)lr * 144 + a * 12;
+        double t = 0.0;
+#pragma unroll
+        for (int b = 0; b < 12; ++b) t = fma((double)M[b], vv[lr * 12 + b], t);
+        return t;
+    };
+    // this entry of the vector to multiply next: into halo buffer hb and this row's staged slot
+    auto put = [&](double *hb, double v) {
+        st_dev(hb + o, v);
+        if (mslot >= 0) mz[mslot * 12 + a] = v;
+    };
+    auto publish = [&](unsigned tag, double v0, double v1) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) tag_publish2(bar, gid0 + wg, tag, v0, v1);
+    };
+    auto rr_out = [&](int it, double rr) {   // |r_it|^2 partial, read by ppcg_finish after the launch
+        double v[1] = {rr};
+        wg_sum<1>(v, red);
+        if (threadIdx.x == 0) A.part[(size_t)it * G + wg] = v[0];
+    };
+
+    // init: x = 0, r = -g, u = M r, w = A u (exchange 0 carries u)
+    double x = 0.0, r = 0.0, u = 0.0, w = 0.0, p = 0.0, s = 0.0, q = 0.0, z = 0.0;
+    if (act) {
+        r = -(double)A.g[o];
+        vv[li] = r;
+    }
+    __syncthreads();
+    if (act) {
+        u = precond();
+        put(A.halo[1], u);
+    }
+    publish(1u, 0.0, 0.0);
+    {
+        double l = act ? local_part(A.halo[1]) : 0.0;
+        double d0, d1;
+        tag_sum2(bar, gid0, G, 1u, broken, red, A.spin, d0, d1);
+        stage(A.halo[1]);
+        if (act) w = fma(lam, u, remote_part(l, A.halo[1]));
+    }
+    bool stopped = false, brk = false;
+    int done = 0;
+    double gamma_prev = 1.0, alpha_prev = 1.0;
+    for (int it = 0; it < A.iters; ++it) {
+        rr_out(it, act ? r * r : 0.0);
+        double v[2] = {act ? r * u : 0.0, act ? w * u : 0.0};
+        wg_sum<2>(v, red);
+        // m = M w: multiplied while gamma and delta are in flight
+        double m = 0.0;
+        if (act) vv[li] = w;
+        __syncthreads();
+        double *hb = A.halo[it & 1];
+        if (act) {
+            m = precond();
+            put(hb, m);
+        }
+        publish((unsigned)(it + 2), v[0], v[1]);
+        double n = act ? local_part(hb) : 0.0;
+        double gamma, delta;
+        tag_sum2(bar, gid0, G, (unsigned)(it + 2), broken, red, A.spin, gamma, delta);
+        stage(hb);
+        if (act) n = fma(lam, m, remote_part(n, hb));
+        // the textbook decisions, from scalars every workgroup holds alike
+        if (stopped || gamma == 0.0) {
+            stopped = true;
+            continue;
+        }
+        const double beta = it > 0 ? gamma / gamma_prev : 0.0;
+        const double pap = it > 0 ? delta - beta * gamma / alpha_prev : delta;   // p.A p
+        if (!(pap > 0.0)) {
+            stopped = brk = true;
+            continue;
+        }
+        const double alpha = gamma / pap;
+        if (act) {
+            z = fma(beta, z, n);
+            q = fma(beta, q, m);
+            s = fma(beta, s, w);
+            p = fma(beta, p, u);
+            x = fma(alpha, p, x);
+            r = fma(-alpha, s, r);
+            u = fma(-alpha, q, u);
+            w = fma(-alpha, z, w);
+        }
+        gamma_prev = gamma;
+        alpha_prev = alpha;
+        ++done;
+    }
+    rr_out(A.iters, act ? r * r : 0.0);
+    // x out (float32), this workgroup's non-finite check, the report's scalars (first workgroup); the
+    // residual norms and the update itself are ppcg_finish's
+    const float xf = (float)x;
+    if (act) A.x[o] = xf;
+    const bool bad = __syncthreads_or(act && !isfinite(xf)) != 0;
+    if (threadIdx.x == 0) {
+        int f = 0;
+        if (bad) f |= MISSLAM_FLAG_NONFINITE;
+        if (broken) f |= MISSLAM_FLAG_SYNC_TIMEOUT;
+        if (wg == 0) {
+            rep->pcg_iters_done = done;
+            if (brk) f |= MISSLAM_FLAG_PCG_BREAKDOWN;
+        }
+        if (f) atomicOr(&rep->flags, f);
+    }
+}
+
+__global__ void __launch_bounds__(kPcgThreads) ppcg_persistent_kernel(PcgArgs A, int rows_per_wg, int cache_blocks,
+                                                                     unsigned *bar, misslam_report *rep) {
+    ppcg_persistent_body(A, rows_per_wg, cache_blocks, bar, 0, blockIdx.x, gridDim.x, rep);
+}
+
+// After a pipelined one-launch solve of G workgroups: the report's residual norms |r_q|, q = 0 .. iterations
+// done (the partials every workgroup left, added in workgroup order; first block), and x += dx unless the
+// report carries a non-finite value or a timeout (params may be null: the solve alone).
+__device__ __forceinline__ void ppcg_finish_body(const double *part, int G, misslam_report *rep, float *params,
+                                                 const float *dx, int n, int blk, double *lds) {
+    const int f = rep->flags;
+    const int i = blk * kPcgThreads + threadIdx.x;
+    if (params && !(f & (MISSLAM_FLAG_NONFINITE | MISSLAM_FLAG_SYNC_TIMEOUT)) && i < n) params[i] += dx[i];
+    if (blk != 0) return;
+    const int done = rep->pcg_iters_done;
+    for (int q = 0; q <= done && q <= MISSLAM_MAX_PCG; ++q) {
+        double v = 0.0;
+        for (int t = threadIdx.x; t < G; t += kPcgThreads) v += part[(size_t)q * G + t];
+        v = block_sum<kPcgThreads>(v, lds);
+        if (threadIdx.x == 0) rep->pcg_resid[q] = sqrt(v);
+    }
+}
+
+__global__ void __launch_bounds__(kPcgThreads) ppcg_finish_kernel(const double *part, int G, misslam_report *rep,
+                                                                 float *params, const float *dx, int n) {
+    __shared__ double lds[kPcgThreads];
+    ppcg_finish_body(part, G, rep, params, dx, n, blockIdx.x, lds);
+}
+
 // Grid shape of the persistent solve for m rows on this device, or 0 when a
 // cooperative launch cannot hold it (the multi-kernel path is used then).
 // Rows are packed MISSLAM_SOLVE_ROWS to a workgroup: fewer workgroups make
@@ -861,31 +1178,41 @@ hipError_t launch_step_commit(float *x, const float *dx, int n, misslam_report *
 // on a surface graph) still fit the LDS left beside the static arrays.  One
 // workgroup per CU must hold them all, so a larger system packs up to
 // kRowsPerBlk rows (blocks beyond the LDS cache are read from global memory).
-static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes) {
-    static int max_blocks = -1, max_lds = 0;
-    if (max_blocks < 0) {
-        int dev = 0, cus = 0, coop = 0, shmem = 0;
-        hipFuncAttributes fa{};
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
-            hipDeviceGetAttribute(&shmem, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
-            hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(pcg_persistent_kernel)) != hipSuccess || !coop) {
-            max_blocks = 0;
-        } else {
-            max_lds = (shmem < kPersistMaxLds ? shmem : kPersistMaxLds) - (int)fa.sharedSizeBytes - 1024;
-            int per_cu = 0;
-            if (max_lds <= 0 ||
-                hipFuncSetAttribute(reinterpret_cast<const void *>(pcg_persistent_kernel),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, max_lds) != hipSuccess ||
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pcg_persistent_kernel, kPcgThreads,
-                                                             max_lds) != hipSuccess ||
-                per_cu < 1)
-                max_blocks = 0;
-            else
-                max_blocks = cus;
-        }
+using PersistentKernel = void (*)(PcgArgs, int, int, unsigned *, misslam_report *);
+
+struct PersistentShape {
+    int max_blocks = -1, max_lds = 0;
+};
+
+// The device limits of one persistent kernel: queried once per process (first device used).
+static void persistent_limits(PersistentKernel kern, PersistentShape &sh) {
+    int dev = 0, cus = 0, coop = 0, shmem = 0;
+    hipFuncAttributes fa{};
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&shmem, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kern)) != hipSuccess || !coop) {
+        sh.max_blocks = 0;
+        return;
     }
+    sh.max_lds = (shmem < kPersistMaxLds ? shmem : kPersistMaxLds) - (int)fa.sharedSizeBytes - 1024;
+    int per_cu = 0;
+    if (sh.max_lds <= 0 ||
+        hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            sh.max_lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kPcgThreads, sh.max_lds) != hipSuccess ||
+        per_cu < 1)
+        sh.max_blocks = 0;
+    else
+        sh.max_blocks = cus;
+}
+
+static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes, bool textbook) {
+    static PersistentShape tb, pp;
+    PersistentShape &sh = textbook ? tb : pp;
+    if (sh.max_blocks < 0) persistent_limits(textbook ? pcg_persistent_kernel : ppcg_persistent_kernel, sh);
+    const int max_blocks = sh.max_blocks, max_lds = sh.max_lds;
     if (max_blocks <= 0 || m <= 0) return 0;
     // more rows per workgroup once one workgroup per CU no longer holds the system
     rows_per_wg = MISSLAM_SOLVE_ROWS;
@@ -900,10 +1227,10 @@ static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes) {
 hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                                  float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
                                  float *params, hipStream_t st, bool *used, bool cooperative, int zeroed_words,
-                                 const float *lambda_dev, unsigned spin) {
+                                 const float *lambda_dev, unsigned spin, bool textbook) {
     *used = false;
     int rows = 0, lds = 0;
-    const int G = persistent_grid(m, rows, lds);
+    const int G = persistent_grid(m, rows, lds, textbook);
     if (G <= 0 || G > s.nblk_max) return hipSuccess;
     PcgArgs A;
     A.row_ptr = g.row_ptr;
@@ -926,23 +1253,34 @@ hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks,
     A.status = s.status;
     A.done = s.status + (iters + 2);
     if (spin > 0) A.spin = spin;
+    A.halo[0] = s.halo;
+    A.halo[1] = s.halo + (size_t)12 * m;
+    A.textbook = textbook;
     // dynamic LDS: cached blocks (144 floats each) and the rows' preconditioner
     const int cache_blocks = (lds / 4 - rows * 144) / 144;
     if (cache_blocks < 1) return hipSuccess;
     unsigned *bar = s.bar;
-    if (zeroed_words < 8 * G) hipLaunchKernelGGL(fill_u32_kernel_pcg, dim3((8 * G + 255) / 256), dim3(256), 0, st, bar, 8 * G);
+    const int words = MSL_WG_WORDS * G;
+    if (zeroed_words < words)
+        hipLaunchKernelGGL(fill_u32_kernel_pcg, dim3((words + 255) / 256), dim3(256), 0, st, bar, words);
+    const PersistentKernel kern = textbook ? pcg_persistent_kernel : ppcg_persistent_kernel;
     hipError_t e;
     if (cooperative) {
         void *args[] = {&A, (void *)&rows, (void *)&cache_blocks, &bar, &rep};
-        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(pcg_persistent_kernel), dim3(G),
-                                       dim3(kPcgThreads), args, (unsigned)lds, st);
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G), dim3(kPcgThreads), args,
+                                       (unsigned)lds, st);
     } else {
-        hipLaunchKernelGGL(pcg_persistent_kernel, dim3(G), dim3(kPcgThreads), (unsigned)lds, st, A, rows,
-                           cache_blocks, bar, rep);
+        hipLaunchKernelGGL(kern, dim3(G), dim3(kPcgThreads), (unsigned)lds, st, A, rows, cache_blocks, bar, rep);
         e = hipGetLastError();
     }
     if (e == hipSuccess) *used = true;
-    if (e == hipSuccess && params) e = launch_step_commit(params, delta, 12 * m, rep, st, nullptr);
+    if (e == hipSuccess && textbook && params) e = launch_step_commit(params, delta, 12 * m, rep, st, nullptr);
+    if (e == hipSuccess && !textbook) {   // the residual norms, and the step unless it failed
+        const int blocks = params ? (12 * m + kPcgThreads - 1) / kPcgThreads : 1;
+        hipLaunchKernelGGL(ppcg_finish_kernel, dim3(blocks), dim3(kPcgThreads), 0, st, A.part, G, rep, params,
+                           delta, 12 * m);
+        e = hipGetLastError();
+    }
     return e;
 }
 
@@ -965,6 +1303,38 @@ __global__ void __launch_bounds__(kPcgThreads) pcg_batched_kernel(const BatchIte
     pcg_persistent_body(it.p, rows_per_wg, cache_blocks, bar, it.wg0, (int)blockIdx.x - it.wg0, it.wgs, it.rep + gi);
 }
 
+// The same with the pipelined recurrence.
+__global__ void __launch_bounds__(kPcgThreads) ppcg_batched_kernel(const BatchItem *__restrict__ items, int count,
+                                                                  int rows_per_wg, int cache_blocks, unsigned *bar,
+                                                                  int gi) {
+    int b = count - 1;
+    while (b > 0 && items[b].wg0 > (int)blockIdx.x) --b;
+    const BatchItem &it = items[b];
+    ppcg_persistent_body(it.p, rows_per_wg, cache_blocks, bar, it.wg0, (int)blockIdx.x - it.wg0, it.wgs,
+                         it.rep + gi);
+}
+
+// ppcg_finish over every problem of a batch: block b < count completes problem b's report; the blocks after
+// them apply each problem's step (one thread per parameter entry), unless its report rules it out.
+__global__ void __launch_bounds__(kPcgThreads) ppcg_finish_batched_kernel(const BatchItem *__restrict__ items,
+                                                                         int count, int total_rows, int gi) {
+    __shared__ double lds[kPcgThreads];
+    if ((int)blockIdx.x < count) {
+        const BatchItem &it = items[blockIdx.x];
+        ppcg_finish_body(it.p.part, it.wgs, it.rep + gi, nullptr, nullptr, 0, 0, lds);
+        return;
+    }
+    const int t = ((int)blockIdx.x - count) * kPcgThreads + threadIdx.x;
+    if (t >= 12 * total_rows) return;
+    const int row = t / 12;
+    int b = count - 1;
+    while (b > 0 && items[b].row0 > row) --b;
+    const BatchItem &it = items[b];
+    const int f = it.rep[gi].flags;
+    const int o = t - 12 * it.row0;
+    if (!(f & (MISSLAM_FLAG_NONFINITE | MISSLAM_FLAG_SYNC_TIMEOUT))) it.params[o] += it.p.x[o];
+}
+
 // step_commit_kernel over every problem of a batch: params += dx of problem b unless its step's report
 // carries a non-finite value or a solve timeout.  One thread per parameter entry (rows row0 .. of problem b).
 __global__ void __launch_bounds__(256) step_commit_batched_kernel(const BatchItem *__restrict__ items, int count,
@@ -980,19 +1350,20 @@ __global__ void __launch_bounds__(256) step_commit_batched_kernel(const BatchIte
     if (!(f & (MISSLAM_FLAG_NONFINITE | MISSLAM_FLAG_SYNC_TIMEOUT))) it.params[o] += it.p.x[o];
 }
 
-static int batched_static_lds() {
-    static int v = -1;
-    if (v < 0) {
-        hipFuncAttributes fa{};
-        v = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(pcg_batched_kernel)) == hipSuccess
-                ? (int)fa.sharedSizeBytes
-                : 1 << 30;
-    }
-    return v;
+using BatchedKernel = void (*)(const BatchItem *, int, int, int, unsigned *, int);
+
+static int batched_static_lds(BatchedKernel kern) {
+    hipFuncAttributes fa{};
+    return hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kern)) == hipSuccess ? (int)fa.sharedSizeBytes
+                                                                                         : 1 << 30;
 }
 
 // Dynamic LDS per workgroup for total_wgs co-resident workgroups, or 0 if they cannot all be resident.
-static int batched_lds(int total_wgs) {
+static int batched_lds(int total_wgs, bool textbook) {
+    static int static_lds[2] = {-1, -1};
+    const BatchedKernel kern = textbook ? pcg_batched_kernel : ppcg_batched_kernel;
+    if (static_lds[textbook] < 0) static_lds[textbook] = batched_static_lds(kern);
+    const int sl = static_lds[textbook];
     int dev = 0, cus = 0, shmem = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -1001,43 +1372,52 @@ static int batched_lds(int total_wgs) {
     const int per_cu = (total_wgs + cus - 1) / cus;
     if (per_cu > 4 || total_wgs > MSL_TAG_WGS) return 0;
     const int cu_lds = kPersistMaxLds;
-    int lds = cu_lds / per_cu - batched_static_lds() - 1024;
-    if (lds > shmem - batched_static_lds() - 1024) lds = shmem - batched_static_lds() - 1024;
+    int lds = cu_lds / per_cu - sl - 1024;
+    if (lds > shmem - sl - 1024) lds = shmem - sl - 1024;
     const int min_lds = (kRowsPerBlk * 144 + 144) * 4;   // the rows' preconditioner and one cached block
     if (lds < min_lds) return 0;
     int occ = 0;
-    if (hipFuncSetAttribute(reinterpret_cast<const void *>(pcg_batched_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pcg_batched_kernel, kPcgThreads, lds) != hipSuccess ||
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, lds) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kPcgThreads, lds) != hipSuccess ||
         occ * cus < total_wgs)
         return 0;
     return lds;
 }
 
-int pcg_batched_fits(int total_wgs) { return total_wgs > 0 && batched_lds(total_wgs) > 0 ? 1 : 0; }
+int pcg_batched_fits(int total_wgs, bool textbook) {
+    return total_wgs > 0 && batched_lds(total_wgs, textbook) > 0 ? 1 : 0;
+}
 
 hipError_t launch_pcg_batched(const BatchItem *items, int count, int rows_per_wg, int total_wgs, int total_rows,
-                              int it, unsigned *bar, bool cooperative, hipStream_t st, bool *used) {
+                              int it, unsigned *bar, bool cooperative, hipStream_t st, bool *used, bool textbook) {
     *used = false;
-    const int lds = batched_lds(total_wgs);
+    const int lds = batched_lds(total_wgs, textbook);
     if (lds <= 0 || rows_per_wg < 1 || rows_per_wg > kRowsPerBlk) return hipSuccess;
     const int cache_blocks = (lds / 4 - rows_per_wg * 144) / 144;
     if (cache_blocks < 1) return hipSuccess;
+    const BatchedKernel kern = textbook ? pcg_batched_kernel : ppcg_batched_kernel;
     hipError_t e;
     if (cooperative) {
         void *args[] = {(void *)&items, (void *)&count, (void *)&rows_per_wg, (void *)&cache_blocks, (void *)&bar,
                         (void *)&it};
-        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(pcg_batched_kernel), dim3(total_wgs),
-                                       dim3(kPcgThreads), args, (unsigned)lds, st);
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(total_wgs), dim3(kPcgThreads), args,
+                                       (unsigned)lds, st);
     } else {
-        hipLaunchKernelGGL(pcg_batched_kernel, dim3(total_wgs), dim3(kPcgThreads), (unsigned)lds, st, items, count,
-                           rows_per_wg, cache_blocks, bar, it);
+        hipLaunchKernelGGL(kern, dim3(total_wgs), dim3(kPcgThreads), (unsigned)lds, st, items, count, rows_per_wg,
+                           cache_blocks, bar, it);
         e = hipGetLastError();
     }
     if (e == hipSuccess) *used = true;
-    if (e == hipSuccess && total_rows > 0) {
+    if (e == hipSuccess && textbook && total_rows > 0) {
         hipLaunchKernelGGL(step_commit_batched_kernel, dim3((12 * total_rows + 255) / 256), dim3(256), 0, st, items,
                            count, total_rows, it);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && !textbook) {
+        const int blocks = count + (12 * total_rows + kPcgThreads - 1) / kPcgThreads;
+        hipLaunchKernelGGL(ppcg_finish_batched_kernel, dim3(blocks), dim3(kPcgThreads), 0, st, items, count,
+                           total_rows, it);
         e = hipGetLastError();
     }
     return e;

@@ -282,7 +282,14 @@ template <int NT, class DataFn>
 __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratch &s, RowNode<NT> &rn, int j, int rb,
                                              int nslots, double e_reg, DataFn data, float *rr_out) {
     const int tid = threadIdx.x;
-    const double ereg_tot = block_sum<NT>(e_reg, rn.red);   // also a barrier
+    // the row's regulariser energy: its edges' terms added in slot order, as node_energy_kernel adds them, so
+    // that the energy of a point in parameter space does not depend on which kernel evaluated it
+    if (tid < nslots) rn.red[tid] = e_reg;
+    __syncthreads();
+    double ereg_tot = 0.0;
+    if (tid == 0)
+        for (int t = 0; t < nslots; ++t)
+            if (rn.cols[t] != j) ereg_tot += rn.red[t];
     if (tid < 10) {
         float sacc = 0.f;
         for (int t = 0; t < nslots; ++t) {

@@ -50,12 +50,13 @@ class Params:
     reject_threshold: float = 0.0
     solve_launch: int = _lib.LAUNCH_PLAIN
     sync_spin_limit: int = 0
+    solve_form: int = _lib.SOLVE_TEXTBOOK
 
     def c(self):
         return _lib.Params(self.k, self.weight_kind, self.sigma, self.w_rot, self.w_reg, self.w_data, self.eps_d,
                            self.cos_eps_n, self.lam, self.gn_iters, self.pcg_iters, self.precision,
                            self.refine_steps, self.reject_threshold, self.solve_launch,
-                           self.sync_spin_limit)
+                           self.sync_spin_limit, self.solve_form)
 
 
 def camera(width, height, fx, fy, cx, cy):
@@ -74,14 +75,17 @@ def _need_rows(t, dtype, name):
         raise ValueError(f"{name} must be a (rows, n) {dtype} CUDA tensor with contiguous rows")
 
 
-def points_struct(points, w=None, stamp=None, capacity=None):
+def points_struct(points, w=None, stamp=None, capacity=None, stable=None):
     _need_rows(points, torch.float32, "points")
     n = points.shape[1]
     base = points.data_ptr()
     cap = n if capacity is None else capacity
     row = points.stride(0) * 4
+    if stable is not None:
+        _need(stable, torch.uint8, "stable")
     return _lib.Points(n, cap, base, base + row, base + 2 * row, base + 3 * row, base + 4 * row, base + 5 * row,
-                       w.data_ptr() if w is not None else 0, stamp.data_ptr() if stamp is not None else 0)
+                       w.data_ptr() if w is not None else 0, stamp.data_ptr() if stamp is not None else 0,
+                       stable.data_ptr() if stable is not None else 0)
 
 
 def nodes_struct(nodes, x):
@@ -365,17 +369,18 @@ def _color_stride(image, color, cam, n):
     return color.stride(0)
 
 
-def grow(points, w, stamp, n, nodes, x, m, reg_map, registered, nmap, cam, pose_, gp, ws, image=None, color=None):
+def grow(points, w, stamp, n, nodes, x, m, reg_map, registered, nmap, cam, pose_, gp, ws, image=None, color=None,
+         stable=None):
     """Growth and maintenance after fuse (misslam_grow).
 
     points (6, capacity), w, stamp (capacity), nodes (3, node_capacity), x (node_capacity, 12): the model with
     n points and m nodes in use; rewritten in place.  With image (H, W, 3) and color (3, capacity) the point
-    colours follow (misslam_grow_color).  Returns the device counts tensor (7,) int64: new n, new m, lifted,
-    removed, merged away, new nodes, overflow.
+    colours follow (misslam_grow_color); with stable (capacity,) uint8 the stability flags S_i.  Returns the
+    device counts tensor (7,) int64: new n, new m, lifted, removed, merged away, new nodes, overflow.
     """
     counts = torch.zeros(7, dtype=torch.int64, device=points.device)
     cap = points.shape[1]
-    pstruct = points_struct(points, w, stamp, capacity=cap)
+    pstruct = points_struct(points, w, stamp, capacity=cap, stable=stable)
     pstruct.n = int(n)
     nstruct = nodes_struct(nodes, x)
     nstruct.m = int(m)

@@ -74,7 +74,8 @@ def test_header_constants_match_binding():
     defs = {k: int(v, 0) for k, v in re.findall(r"#define\s+MISSLAM_([A-Z_0-9]+)\s+(-?(?:0x[0-9a-fA-F]+|\d+))", text)}
     want = {"FLAG_SYNC_TIMEOUT": _lib.FLAG_SYNC_TIMEOUT, "PREC_FP32": _lib.PREC_FP32, "PREC_BF16": _lib.PREC_BF16,
             "PREC_FP16": _lib.PREC_FP16, "LAUNCH_PLAIN": _lib.LAUNCH_PLAIN,
-            "LAUNCH_COOPERATIVE": _lib.LAUNCH_COOPERATIVE, "LAUNCH_KERNELS": _lib.LAUNCH_KERNELS, "MAX_K": _lib.MAX_K, "MAX_PCG": _lib.MAX_PCG,
+            "LAUNCH_COOPERATIVE": _lib.LAUNCH_COOPERATIVE, "LAUNCH_KERNELS": _lib.LAUNCH_KERNELS,
+            "SOLVE_PIPELINED": _lib.SOLVE_PIPELINED, "SOLVE_TEXTBOOK": _lib.SOLVE_TEXTBOOK, "MAX_K": _lib.MAX_K, "MAX_PCG": _lib.MAX_PCG,
             "MAX_ROW": _lib.MAX_ROW, "MAX_LIST": _lib.MAX_LIST, "SOLVE_ROWS": _lib.SOLVE_ROWS,
             "MAX_KEYPOINTS": _lib.MAX_KEYPOINTS, "NOALLOC_SCRATCH_BYTES": _lib.NOALLOC_SCRATCH_BYTES}
     for k, v in want.items():

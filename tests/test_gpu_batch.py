@@ -36,11 +36,11 @@ def problems(lib):
     return out
 
 
-def _single(problems):
+def _single(problems, params=None):
     xs, reps = [], []
     for s in problems:
         x = s.M.identity_params(s.m)
-        rep, _ = s.M.gn_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, s.params, s.ws)
+        rep, _ = s.M.gn_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, params or s.params, s.ws)
         xs.append(x)
         reps.append(rep)
     torch.cuda.synchronize()
@@ -77,6 +77,21 @@ def test_batch_equals_single_calls_bitwise(problems):
             assert rb[i].tobytes() == reps[i].tobytes(), (call, i)
     for r in reps:
         assert np.all(r["flags"] == 0)
+
+
+def test_batch_pipelined_equals_single_calls_bitwise(problems):
+    """The pipelined recurrence side by side: each problem's rows take the same product order in the batch
+    (whose smaller LDS share leaves more blocks uncached) as in a single call."""
+    import dataclasses
+    from paper_1803_02009_amd import _lib
+    p = dataclasses.replace(problems[0].params, solve_form=_lib.SOLVE_PIPELINED)
+    xs, reps = _single(problems, p)
+    outs, _ = _batch(problems, SOLVE_ROWS, calls=1, params=p)
+    xb, rb = outs[0]
+    for i in range(len(problems)):
+        assert np.array_equal(xb[i].view(np.uint32), xs[i].view(np.uint32)), i
+        assert rb[i].tobytes() == reps[i].tobytes(), i
+        assert np.all(rb[i]["flags"] == 0), i
 
 
 def test_batch_cooperative_launch_equals_single_calls_bitwise(problems):

@@ -40,15 +40,17 @@ def c2(lib):
     return s
 
 
-def test_timeout_discards_the_whole_step(c2):
+@pytest.mark.parametrize("form", [0, 1])   # textbook, pipelined
+def test_timeout_discards_the_whole_step(c2, form):
     s = c2
-    one = dataclasses.replace(s.params, gn_iters=1)
+    one = dataclasses.replace(s.params, gn_iters=1, solve_form=form)
     x_ok = s.M.identity_params(s.m)
     s.M.gn_register(s.pts, s.nodes, x_ok, s.graph, s.depth, s.cam, s.pose, one, s.ws)
     timed_out = 0
     for _ in range(3):
         x = s.M.identity_params(s.m)
-        rep, _ = s.M.gn_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, _spin(s, gn_iters=1), s.ws)
+        rep, _ = s.M.gn_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose,
+                                 _spin(s, gn_iters=1, solve_form=form), s.ws)
         torch.cuda.synchronize()
         f = int(s.M.read_report(rep)[0]["flags"])
         want = s.M.identity_params(s.m) if f & TIMEOUT else x_ok

@@ -196,3 +196,47 @@ def test_grow_color_matches_oracle(lib):
     got = colc[:, :n_out].T
     print("colour max |d|", np.abs(got - ref["color"]).max())
     assert np.abs(got - ref["color"]).max() <= 1e-6
+
+
+def test_grow_stability_matches_oracle(lib):
+    """The stability flags S_i through growth (Sec. II-G, Alg. 3): a seeded third of the fused 320x240 model is
+    flagged stable on entry, so old points are kept or removed by their flag as well as their weight; counts,
+    order and every point's flag must equal the oracle's."""
+    frame = 12
+    s, pts, w, st, nodes, x, reg, regd, nmap = _fused(lib, frame, 0)
+    n, m = pts.shape[1], nodes.shape[1]
+    C = n + s.cam.width * s.cam.height
+    Cm = m + 4000
+    rng = np.random.default_rng(3)
+    S0 = rng.random(n) < 0.33
+    P = torch.zeros((6, C), device="cuda")
+    P[:, :n] = pts
+    W = torch.zeros(C, device="cuda")
+    W[:n] = w
+    T = torch.zeros(C, dtype=torch.int32, device="cuda")
+    T[:n] = st
+    B = torch.zeros(C, dtype=torch.uint8, device="cuda")
+    B[:n] = torch.tensor(S0.astype(np.uint8), device="cuda")
+    G = torch.zeros((3, Cm), device="cuda")
+    G[:, :m] = nodes
+    X = torch.zeros((Cm, 12), device="cuda")
+    X[:m] = x
+    pf, wf, sf, rg, rd, nm, nd = (pts.cpu().numpy(), w.cpu().numpy(), st.cpu().numpy(), reg.cpu().numpy(),
+                                  regd.cpu().numpy(), nmap.cpu().numpy(), nodes.cpu().numpy())
+    counts = s.M.grow(P, W, T, n, G, X, m, reg, regd, nmap, s.cam, s.pose, s.M.grow_params(frame, 5.0), s.ws,
+                      stable=B).cpu().numpy()
+    torch.cuda.synchronize()
+    ok = ~np.all(nm[..., :3] == 0, axis=-1)
+    ref = oracle.grow(pf[:3].T, pf[3:].T, wf, sf, rd.astype(bool), rg.reshape(-1), s.sc["depth"], s.sc["camera"],
+                      s.sc["R"], s.sc["T"], nm[..., :3], ok, frame, nd.T, 5.0, voxel=0.22, stable=S0)
+    plain = oracle.grow(pf[:3].T, pf[3:].T, wf, sf, rd.astype(bool), rg.reshape(-1), s.sc["depth"],
+                        s.sc["camera"], s.sc["R"], s.sc["T"], nm[..., :3], ok, frame, nd.T, 5.0, voxel=0.22)
+    n_out = int(counts[0])
+    print("stability: culled", ref["culled"], "without flags", plain["culled"], "stable out", int(ref["stable"].sum()),
+          "of", len(ref["stable"]))
+    assert ref["culled"] < plain["culled"]                   # the flags keep old light points
+    assert counts[3] == ref["culled"] and counts[4] == ref["merged"] and n_out == len(ref["points"])
+    np.testing.assert_array_equal(B.cpu().numpy()[:n_out].astype(bool), ref["stable"])
+    np.testing.assert_array_equal(T.cpu().numpy()[:n_out], ref["stamp"])
+    np.testing.assert_array_equal(W.cpu().numpy()[:n_out], ref["weight"])
+    assert np.abs(P.cpu().numpy()[:3, :n_out].T - ref["points"]).max() < 1e-4

@@ -1,8 +1,10 @@
-"""The PCG solves in their three launch forms.
+"""The PCG solves in their three launch forms and two recurrences.
 
 The one-launch PCG started as a plain launch (the default) and as a
 cooperative launch runs the same kernel over the same partition: parameters
-and reports must be bitwise equal, with no workgroup giving up its waits.
+and reports must be bitwise equal, with no workgroup giving up its waits,
+for the pipelined recurrence (the default) and the textbook one.  The two
+recurrences are the same iterates in exact arithmetic and agree to rounding.
 The per-phase launches (no residency needed) take the same steps in another
 reduction order for the fixed-pose solve (equal to rounding) and in the same
 order for the joint pose form (bitwise equal).
@@ -19,17 +21,18 @@ from gpu_util import Scene, rel_err
 pytestmark = pytest.mark.gpu
 
 
-def _fixed(s, mode):
-    p = dataclasses.replace(s.params, solve_launch=mode)
+def _fixed(s, mode, form=_lib.SOLVE_TEXTBOOK):
+    p = dataclasses.replace(s.params, solve_launch=mode, solve_form=form)
     x = s.M.identity_params(s.m)
     rep, _ = s.M.gn_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, p, s.ws)
     return x.cpu().numpy(), s.M.read_report(rep)
 
 
-@pytest.mark.parametrize("case", ["c2", "c3"])
-def test_plain_and_cooperative_launch_agree_bitwise(lib, case):
+@pytest.mark.parametrize("case,form", [("c2", _lib.SOLVE_PIPELINED), ("c3", _lib.SOLVE_PIPELINED),
+                                       ("c2", _lib.SOLVE_TEXTBOOK), ("c3", _lib.SOLVE_TEXTBOOK)])
+def test_plain_and_cooperative_launch_agree_bitwise(lib, case, form):
     s = Scene(case)
-    (x0, r0), (x1, r1) = _fixed(s, _lib.LAUNCH_PLAIN), _fixed(s, _lib.LAUNCH_COOPERATIVE)
+    (x0, r0), (x1, r1) = _fixed(s, _lib.LAUNCH_PLAIN, form), _fixed(s, _lib.LAUNCH_COOPERATIVE, form)
     assert np.array_equal(x0.view(np.uint32), x1.view(np.uint32))
     assert r0.tobytes() == r1.tobytes()
     assert np.all(r0["flags"] == 0)
@@ -61,3 +64,19 @@ def test_joint_per_phase_launches_agree_bitwise(lib):
     assert np.array_equal(P0.view(np.uint32), P1.view(np.uint32))
     assert r0.tobytes() == r1.tobytes()
     assert np.all(r0["flags"] == 0)
+
+
+@pytest.mark.parametrize("case", ["c2", "c3"])
+def test_pipelined_and_textbook_recurrences_agree(lib, case):
+    """The same 10 x 10 registration with either recurrence: equal in exact arithmetic; the textbook form keeps
+    float32 vectors, so the two differ by its rounding."""
+    s = Scene(case)
+    (x0, r0), (x1, r1) = _fixed(s, _lib.LAUNCH_PLAIN, _lib.SOLVE_PIPELINED), _fixed(s, _lib.LAUNCH_PLAIN)
+    x_id = s.M.identity_params(s.m).cpu().numpy()
+    print(case, "pipelined vs textbook: x rel", rel_err(x0, x1), "delta rel", rel_err(x0 - x_id, x1 - x_id))
+    assert rel_err(x0, x1) < 1e-5
+    assert rel_err(x0 - x_id, x1 - x_id) < 1e-4
+    for k in range(len(r0)):
+        assert r0[k]["pcg_iters_done"] == r1[k]["pcg_iters_done"]
+        assert r1[k]["pcg_resid"] == pytest.approx(r0[k]["pcg_resid"], rel=1e-3, abs=1e-9)
+    assert np.all(r0["flags"] == 0) and np.all(r1["flags"] == 0)
