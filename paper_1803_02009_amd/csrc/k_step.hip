@@ -183,13 +183,19 @@ __device__ __forceinline__ int na_index(int a, int b) {  // a, b in 0..2
     return 3 * lo - (lo * (lo - 1)) / 2 + (hi - lo);
 }
 
-constexpr int kAsmThreads = 64;
+constexpr int kAsmThreads = 128;
 constexpr int kAsmWaves = kAsmThreads / kWave;
 constexpr int kBatch = 64;
+// Statistic slots of each wave of a row.  A row with more column slots accumulates on its first wave alone,
+// over the slots of all waves.
+constexpr int kSlotsPerWave = 18;
+static_assert(kAsmWaves * kSlotsPerWave >= MISSLAM_MAX_ROW, "a row's slots must fit the statistic area");
+// Staged entries per statistic row: the batch plus the four-entry read-ahead; 69 floats keep the rows of the
+// staged products (read by lanes with different statistic entries) in distinct banks.
+constexpr int kStage = kBatch + 5;
 
 // LDS of the node-level part of a row: columns, regulariser residuals,
-// rotation Jacobian, the damped diagonal block and its Cholesky scratch.
-template <int NT>
+// rotation Jacobian and the data gradient.
 struct RowNode {
     int cols[MISSLAM_MAX_ROW];
     float rg[MISSLAM_MAX_ROW][9];    // per neighbour slot: e = g_l - g_j, r_jl, r_lj
@@ -198,20 +204,35 @@ struct RowNode {
     float rr[6];
     float xj[12];
     double gd[12];                   // data-term gradient of the row (unweighted)
-    double Hd[12][12];               // damped diagonal block for the preconditioner
+};
+
+// LDS used only once the row's data term is complete (it may share memory with the staging buffers): the
+// damped diagonal block, inverted in place for the preconditioner, and a reduction area.
+template <int NT>
+struct RowFin {
+    double Hd[12][12];
     double red[NT];
+};
+
+// One wave's staged batch: per entry its products, weights and kNN key.
+template <int K>
+struct AsmStage {
+    float Pc[10][kStage];
+    float Na[6][kStage];
+    float4 W[kBatch + 4][(K + 3) / 4];
+    uint32_t key[kBatch][2];
 };
 
 template <int K>
 struct AsmShared {
-    float accS[kAsmWaves][MISSLAM_MAX_ROW][64];
-    // kBatch + 9 per row: conflict-free by entry and by statistic entry, and room for the read-ahead
-    float Pc[kAsmWaves][10][kBatch + 9];
-    float Na[kAsmWaves][6][kBatch + 9];
-    float4 W[kAsmWaves][kBatch + 8][(K + 3) / 4];
-    uint32_t key[kAsmWaves][kBatch][2];
-    double gw[kAsmWaves][12];
-    RowNode<kAsmThreads> rn;
+    float accS[kAsmWaves * kSlotsPerWave][60];   // statistic per slot; wave w's slots start at w kSlotsPerWave
+    union {
+        AsmStage<K> st[kAsmWaves];
+        // wave w's data gradient (gw[w][0..11]), over its own staging once its batches are done
+        double gw[kAsmWaves][sizeof(AsmStage<K>) / sizeof(double)];
+        RowFin<kAsmThreads> fin;
+    };
+    RowNode rn;
 };
 
 // Node-level residuals of row j, computed before the data phase so that their
@@ -219,8 +240,7 @@ struct AsmShared {
 // vector and both Eq.(6) residuals, and (thread 0) the Eq.(5) residuals and
 // Jacobian of node j; threads < 12 stage x_j.  Returns this thread's share of
 // E_reg (summed in row_finalize).  The columns must already be in rn.cols.
-template <int NT>
-__device__ __forceinline__ double row_prepare(const StepArgs &a, RowNode<NT> &rn, int j, int nslots, float gjx,
+__device__ __forceinline__ double row_prepare(const StepArgs &a, RowNode &rn, int j, int nslots, float gjx,
                                               float gjy, float gjz) {
     const int tid = threadIdx.x;
     const float *xj = a.nd.x + (size_t)j * 12;
@@ -277,19 +297,20 @@ __device__ __forceinline__ double row_prepare(const StepArgs &a, RowNode<NT> &rn
 // already weighted by the point weights) and, when requested, the
 // block-Jacobi inverse of the damped diagonal block.  rr_out, if set,
 // receives the regulariser + rotation part of each block alone.  The
-// node-level residuals come from row_prepare (e_reg: this thread's share).
+// node-level residuals come from row_prepare (e_reg: this thread's share); lamf is the damping.
 template <int NT, class DataFn>
-__device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratch &s, RowNode<NT> &rn, int j, int rb,
-                                             int nslots, double e_reg, DataFn data, float *rr_out) {
+__device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratch &s, RowNode &rn, RowFin<NT> &fin,
+                                             int j, int rb, int nslots, double e_reg, float lamf, DataFn data,
+                                             float *rr_out) {
     const int tid = threadIdx.x;
     // the row's regulariser energy: its edges' terms added in slot order, as node_energy_kernel adds them, so
     // that the energy of a point in parameter space does not depend on which kernel evaluated it
-    if (tid < nslots) rn.red[tid] = e_reg;
+    if (tid < nslots) fin.red[tid] = e_reg;
     __syncthreads();
     double ereg_tot = 0.0;
     if (tid == 0)
         for (int t = 0; t < nslots; ++t)
-            if (rn.cols[t] != j) ereg_tot += rn.red[t];
+            if (rn.cols[t] != j) ereg_tot += fin.red[t];
     if (tid < 10) {
         float sacc = 0.f;
         for (int t = 0; t < nslots; ++t) {
@@ -299,8 +320,8 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
         }
         rn.EE[tid] = sacc;
     }
-    const double lam = (double)step_lambda(a);
-    for (int t = tid; t < 144; t += NT) rn.Hd[t / 12][t % 12] = t / 12 == t % 12 ? lam : 0.0;
+    const double lam = (double)lamf;
+    for (int t = tid; t < 144; t += NT) fin.Hd[t / 12][t % 12] = t / 12 == t % 12 ? lam : 0.0;
     __syncthreads();
     if (tid == 0) {
         double erot = 0.0;
@@ -317,31 +338,34 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
     dsl = __builtin_amdgcn_readfirstlane(dsl);
     const float wd = a.w_data, wreg = a.w_reg, wrot = a.w_rot;
     float *outb = a.blocks + (size_t)rb * 144;
-    // each thread owns entries en of every block of the row; the slots' loads are independent
-    for (int en = tid; en < 144; en += NT) {
+    // the blocks of the edges j -> l: (slot, entry) pairs spread over the threads, straight-line bodies
+    // (selects, no branches) so that the loads of consecutive pairs overlap; the diagonal slot is skipped here
+#pragma unroll 4
+    for (int t = tid; t < nslots * 144; t += NT) {
+        const int sl = t / 144, en = t - sl * 144;
         const int R = en / 12, C = en % 12;
         const int c = R / 3, aa = R % 3, c2 = C / 3, a2 = C % 3;
-        const bool same_a = aa == a2;
-        // straight-line body (selects, no branches) so that the slots' loads overlap; the diagonal slot
-        // gets this value too and is overwritten below (same thread, same address: in order)
-#pragma unroll 4
-        for (int sl = 0; sl < nslots; ++sl) {   // edges j -> l
-            const float hd = data(sl, R, C, true);
-            const float rgc = rn.rg[sl][c < 3 ? c : 0], rgc2 = rn.rg[sl][c2 < 3 ? c2 : 0];
-            const float eh_c = c < 3 ? rgc : 1.f;
-            const float fh_c2 = c2 < 3 ? -rgc2 : 1.f;
-            const float r1 = c2 == 3 ? 0.f - eh_c : 0.f;   // edge j -> l
-            const float r2 = c == 3 ? r1 - fh_c2 : r1;     // edge l -> j
-            const float reg = same_a ? r2 : 0.f;
-            const float rr = fmaf(wrot, 0.f, wreg * reg);
-            const float h = fmaf(wreg, reg, wd * hd);
+        const float hd = data(sl, R, C, true);
+        const float rgc = rn.rg[sl][c < 3 ? c : 0], rgc2 = rn.rg[sl][c2 < 3 ? c2 : 0];
+        const float eh_c = c < 3 ? rgc : 1.f;
+        const float fh_c2 = c2 < 3 ? -rgc2 : 1.f;
+        const float r1 = c2 == 3 ? 0.f - eh_c : 0.f;   // edge j -> l
+        const float r2 = c == 3 ? r1 - fh_c2 : r1;     // edge l -> j
+        const float reg = aa == a2 ? r2 : 0.f;
+        const float rr = fmaf(wrot, 0.f, wreg * reg);
+        const float h = fmaf(wreg, reg, wd * hd);
+        if (sl != dsl) {
             outb[(size_t)sl * 144 + en] = h;
             if (rr_out) rr_out[(size_t)(rb + sl) * 144 + en] = rr;
         }
-        if (dsl >= 0) {   // the diagonal block: regulariser and rotation terms of node j
+    }
+    if (dsl >= 0) {   // the diagonal block: regulariser and rotation terms of node j
+        for (int en = tid; en < 144; en += NT) {
+            const int R = en / 12, C = en % 12;
+            const int c = R / 3, aa = R % 3, c2 = C / 3, a2 = C % 3;
             const float hd = data(dsl, R, C, false);
             float reg = 0.f, rot = 0.f;
-            if (same_a) {
+            if (aa == a2) {
                 reg = rn.EE[pc_index(c, c2)];
                 if (c == 3 && c2 == 3) reg += (float)deg;
             }
@@ -351,7 +375,7 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
             }
             const float rr = fmaf(wrot, rot, wreg * reg);
             const float h = fmaf(wrot, rot, fmaf(wreg, reg, wd * hd));
-            rn.Hd[R][C] = (double)h + (R == C ? lam : 0.0);
+            fin.Hd[R][C] = (double)h + (R == C ? lam : 0.0);
             outb[(size_t)dsl * 144 + en] = h;
             if (rr_out) rr_out[(size_t)(rb + dsl) * 144 + en] = rr;
         }
@@ -376,7 +400,7 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
     // block-Jacobi preconditioner of this row: (H_jj + lambda I)^-1 in float64, whole workgroup
     if (a.minv) {
         __syncthreads();
-        const bool ok = gj_inverse_block<NT>(rn.Hd, a.minv + (size_t)j * 144);
+        const bool ok = gj_inverse_block<NT>(fin.Hd, a.minv + (size_t)j * 144);
         if (!ok && tid == 0) atomicOr(a.flags, MISSLAM_FLAG_NONSPD_BLOCK);
     }
 }
@@ -482,10 +506,12 @@ __device__ __forceinline__ void entry_load(const StepArgs &a, const StepScratch 
 }
 
 // One workgroup per node row j (rows spread so each XCD owns a contiguous band).
-// Four waves split the row's point list and run independently: each stages 64
+// Two waves split the row's point list and run independently: each stages 64
 // list entries at a time (lane = entry) while the next 64 are already being
 // fetched, then accumulates the 60 statistic entries (lane = entry of the
-// statistic) for the k node pairs of each run of equal kNN sets.  Then the
+// statistic) for the k node pairs of each run of equal kNN sets, into slots of
+// its own.  The LDS of a row stays under 23 KB, so seven rows fit a CU and a
+// 1600-node graph is resident at once.  Then the
 // node terms (Eqs.(5)-(6)) are added, the row's blocks and gradient are
 // written, and the damped diagonal block is inverted for the block-Jacobi
 // preconditioner.  Fixed summation order throughout: bitwise reproducible.
@@ -503,14 +529,26 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
     for (int t = tid; t < (re - rb - nslots) * 144; t += kAsmThreads)
         a.blocks[(size_t)(rb + nslots) * 144 + t] = 0.f;   // blocks of a row longer than MISSLAM_MAX_ROW
     for (int t = tid; t < nslots; t += kAsmThreads) sh.rn.cols[t] = a.g.col_idx[rb + t];
-    for (int t = lane; t < MISSLAM_MAX_ROW * 64; t += kWave) (&sh.accS[wave][0][0])[t] = 0.f;
+    // the waves split the point list, each with slots of its own; a row with more slots than a wave holds is
+    // accumulated by the first wave alone, over the slots of all waves.  Each wave clears the slots it uses
+    // (no other wave touches them until the workgroup barrier after the data phase).
+    const bool split = nslots <= kSlotsPerWave;
+    const int nw = split ? kAsmWaves : 1;
+    float(*accw)[60] = sh.accS + (split ? wave * kSlotsPerWave : 0);
+    {
+        const int nclr = (wave < nw ? (split ? kSlotsPerWave : kAsmWaves * kSlotsPerWave) : 0) * 60 / 4;
+        for (int t = lane; t < nclr; t += kWave)
+            reinterpret_cast<float4 *>(&accw[0][0])[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
 
     const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
     const int lb = a.g.list_ptr[j];
     const int cnt = a.g.list_ptr[j + 1] - lb;
-    const int quota = (cnt + kAsmWaves - 1) / kAsmWaves;
-    const int my0 = min(cnt, wave * quota), my1 = min(cnt, my0 + quota);
+    const int quota = (cnt + nw - 1) / nw;
+    const int my0 = wave < nw ? min(cnt, wave * quota) : cnt;
+    const int my1 = wave < nw ? min(cnt, my0 + quota) : cnt;
     const int nbatch = (my1 - my0 + kBatch - 1) / kBatch;
+    AsmStage<K> &st = sh.st[wave];
     // Entries are fetched in two stages: the point index two batches ahead (coalesced), the point's data one
     // batch ahead (gathers whose addresses are known by then), so no wait in the loop is a chain of two
     // dependent loads.  The first batch's entries are fetched before the node-level loads are waited for.
@@ -519,7 +557,8 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
     if (nbatch > 0 && lane < min(kBatch, my1 - my0))
         entry_pack<K>(a, s, lb + my0 + lane, a.g.list_pts[lb + my0 + lane], nxt);
     if (nbatch > 1 && lane < min(kBatch, my1 - my0 - kBatch)) pnext = a.g.list_pts[lb + my0 + kBatch + lane];
-    const double e_reg = row_prepare<kAsmThreads>(a, sh.rn, j, nslots, gjx, gjy, gjz);
+    const float lamf = step_lambda(a);
+    const double e_reg = row_prepare(a, sh.rn, j, nslots, gjx, gjy, gjz);
 
     const int e = lane;                      // statistic entry owned in phase 2 (e < 60)
     const int pci = e < 60 ? e / 6 : 0, nai = e < 60 ? e % 6 : 0;
@@ -536,11 +575,11 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
 #pragma unroll
             for (int q = 0; q < K; ++q) {
                 slot[q] = q < 4 ? (k0 >> (8 * q)) & 0xFF : (k1 >> (8 * (q - 4))) & 0xFF;
-                old[q] = slot[q] < (uint32_t)nslots ? sh.accS[wave][slot[q]][e] : 0.f;
+                old[q] = slot[q] < (uint32_t)nslots ? accw[slot[q]][e] : 0.f;
             }
 #pragma unroll
             for (int q = 0; q < K; ++q)
-                if (slot[q] < (uint32_t)nslots) sh.accS[wave][slot[q]][e] = old[q] + ac[q];
+                if (slot[q] < (uint32_t)nslots) accw[slot[q]][e] = old[q] + ac[q];
         }
 #pragma unroll
         for (int q = 0; q < K; ++q) ac[q] = 0.f;
@@ -571,13 +610,13 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
             const float uu[4] = {cu.uw.x, cu.uw.y, cu.uw.z, 1.f};
             const float nn[3] = {cu.nr.x, cu.nr.y, cu.nr.z};
 #pragma unroll
-            for (int t = 0; t < 10; ++t) sh.Pc[wave][t][pv] = uu[pair_c0(t)] * uu[pair_c1(t)];
+            for (int t = 0; t < 10; ++t) st.Pc[t][pv] = uu[pair_c0(t)] * uu[pair_c1(t)];
 #pragma unroll
-            for (int t = 0; t < 6; ++t) sh.Na[wave][t][pv] = nn[pair_a0(t)] * nn[pair_a1(t)];
+            for (int t = 0; t < 6; ++t) st.Na[t][pv] = nn[pair_a0(t)] * nn[pair_a1(t)];
 #pragma unroll
-            for (int t = 0; t < (K + 3) / 4; ++t) sh.W[wave][pv][t] = cu.w[t];
-            sh.key[wave][pv][0] = cu.k0;
-            sh.key[wave][pv][1] = cu.k1;
+            for (int t = 0; t < (K + 3) / 4; ++t) st.W[pv][t] = cu.w[t];
+            st.key[pv][0] = cu.k0;
+            st.key[pv][1] = cu.k1;
             const float wr = wj * cu.nr.w;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -591,9 +630,9 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
         // list is ordered by set, so equal sets stay contiguous after packing)
         bool start = false;
         if (lane < np) {
-            const uint32_t q0 = lane == 0 ? cur0 : sh.key[wave][lane - 1][0];
-            const uint32_t q1 = lane == 0 ? cur1 : sh.key[wave][lane - 1][1];
-            start = sh.key[wave][lane][0] != q0 || sh.key[wave][lane][1] != q1;
+            const uint32_t q0 = lane == 0 ? cur0 : st.key[lane - 1][0];
+            const uint32_t q1 = lane == 0 ? cur1 : st.key[lane - 1][1];
+            start = st.key[lane][0] != q0 || st.key[lane][1] != q1;
         }
         const uint64_t starts = __ballot(start);
         // ---- phase 2: lane = statistic entry, the entries in order; a run of equal kNN sets ends by adding
@@ -603,13 +642,13 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
             // v_mfma_f32_4x4x1 (16 blocks): lane e = 4 b + c gives A = W[u][e % 4] and B = the product of entry u
             // for statistic entry e, so register q of lane e accumulates W[u][q] * product (one fused
             // multiply-add per entry, the same arithmetic as the vector path)
-            const float *Wf = reinterpret_cast<const float *>(&sh.W[wave][0][0]);
+            const float *Wf = reinterpret_cast<const float *>(&st.W[0][0]);
             float cA[4], nA[4], wA[4], cB[4], nB[4], wB[4];
             auto fetch = [&](int u0, float(&cv)[4], float(&nv)[4], float(&wv)[4]) {
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {
-                    cv[h] = sh.Pc[wave][pci][u0 + h];
-                    nv[h] = sh.Na[wave][nai][u0 + h];
+                    cv[h] = st.Pc[pci][u0 + h];
+                    nv[h] = st.Na[nai][u0 + h];
                     wv[h] = Wf[(u0 + h) * 4 + (lane & 3)];
                 }
             };
@@ -630,8 +669,8 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
                         for (int q = 0; q < K; ++q) acc[q] = acc4[q];
                         flush(cur0, cur1, acc);
                         acc4 = f32x4_t{0.f, 0.f, 0.f, 0.f};
-                        cur0 = __builtin_amdgcn_readfirstlane(sh.key[wave][u][0]);
-                        cur1 = __builtin_amdgcn_readfirstlane(sh.key[wave][u][1]);
+                        cur0 = __builtin_amdgcn_readfirstlane(st.key[u][0]);
+                        cur1 = __builtin_amdgcn_readfirstlane(st.key[u][1]);
                     }
                     acc4 = __builtin_amdgcn_mfma_f32_4x4x1f32(wv[h], cv[h] * nv[h], acc4, 0, 0, 0);
                 }
@@ -651,10 +690,10 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
             auto fetch = [&](int u0, float(&cv)[4], float(&nv)[4], float4(&wv)[4][KW]) {
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {
-                    cv[h] = sh.Pc[wave][pci][u0 + h];
-                    nv[h] = sh.Na[wave][nai][u0 + h];
+                    cv[h] = st.Pc[pci][u0 + h];
+                    nv[h] = st.Na[nai][u0 + h];
 #pragma unroll
-                    for (int g4 = 0; g4 < KW; ++g4) wv[h][g4] = sh.W[wave][u0 + h][g4];
+                    for (int g4 = 0; g4 < KW; ++g4) wv[h][g4] = st.W[u0 + h][g4];
                 }
             };
             auto consume = [&](int u0, const float(&cv)[4], const float(&nv)[4], const float4(&wv)[4][KW]) {
@@ -664,8 +703,8 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
                     if (u >= np) break;
                     if ((starts >> u) & 1ull) {   // a run starts at entry u
                         flush(cur0, cur1, acc);
-                        cur0 = __builtin_amdgcn_readfirstlane(sh.key[wave][u][0]);
-                        cur1 = __builtin_amdgcn_readfirstlane(sh.key[wave][u][1]);
+                        cur0 = __builtin_amdgcn_readfirstlane(st.key[u][0]);
+                        cur1 = __builtin_amdgcn_readfirstlane(st.key[u][1]);
                     }
                     const float mv = cv[h] * nv[h];
 #pragma unroll
@@ -706,13 +745,13 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
         for (int q = 0; q < 12; ++q) sh.gw[wave][q] = gacc[q];
     }
     __syncthreads();
-    for (int t = tid; t < nslots * 64; t += kAsmThreads) {
-        const int sl = t / 64, en = t % 64;
-        if (en < 60) {
-            float v = sh.accS[0][sl][en];
+    if (split) {
+        for (int t = tid; t < nslots * 60; t += kAsmThreads) {
+            const int sl = t / 60, en = t - sl * 60;
+            float v = sh.accS[sl][en];
 #pragma unroll
-            for (int w = 1; w < kAsmWaves; ++w) v += sh.accS[w][sl][en];   // waves in order
-            sh.accS[0][sl][en] = v;
+            for (int w = 1; w < kAsmWaves; ++w) v += sh.accS[w * kSlotsPerWave + sl][en];   // waves in order
+            sh.accS[sl][en] = v;
         }
     }
     if (tid < 12) {
@@ -726,13 +765,13 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
     // off: slot sl is not the diagonal; every operand is read whether used or not (independent loads)
     auto data = [&](int sl, int R, int C, bool off) {
         const int c = R / 3, aa = R % 3, c2 = C / 3, a2 = C % 3;
-        const float *S = sh.accS[0][sl];
+        const float *S = sh.accS[sl];
         const int ni = na_index(aa, a2);
         const float s1 = S[pc_index(c, c2) * 6 + ni], s3 = S[pc_index(c, 3) * 6 + ni];
         const float e = sh.rn.rg[sl][c2 < 3 ? c2 : 0];
         return off && c2 < 3 ? fmaf(-e, s3, s1) : s1;   // delta = -e
     };
-    row_finalize<kAsmThreads>(a, s, sh.rn, j, rb, nslots, e_reg, data, nullptr);
+    row_finalize<kAsmThreads>(a, s, sh.rn, sh.fin, j, rb, nslots, e_reg, lamf, data, nullptr);
 }
 
 template <int K>
@@ -776,7 +815,8 @@ struct LpShared {
     T Jt[kLpWaves][12 * (K + 1)][kBatch];   // per entry: J of node j (rows 0-11), then of its k set nodes
     uint32_t key[kLpWaves][kBatch][2];
     double gw[kLpWaves][12];
-    RowNode<kLpThreads> rn;
+    RowNode rn;
+    RowFin<kLpThreads> fin;
 };
 
 // Same rows as assemble_rows_kernel, but the data term is formed from the
@@ -806,7 +846,8 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
     for (int t = lane; t < MISSLAM_MAX_ROW * 144; t += kWave) sh.acc[wave][t] = 0.f;
 
     const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
-    const double e_reg = row_prepare<kLpThreads>(a, sh.rn, j, nslots, gjx, gjy, gjz);
+    const float lamf = step_lambda(a);
+    const double e_reg = row_prepare(a, sh.rn, j, nslots, gjx, gjy, gjz);
     const int lb = a.g.list_ptr[j];
     const int cnt = a.g.list_ptr[j + 1] - lb;
     const int quota = (cnt + kLpWaves - 1) / kLpWaves;
@@ -957,7 +998,7 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
     }
     __syncthreads();
     auto data = [&](int sl, int R, int C, bool) { return sh.acc[0][sl * 144 + R * 12 + C]; };
-    row_finalize<kLpThreads>(a, s, sh.rn, j, rb, nslots, e_reg, data, rr_out);
+    row_finalize<kLpThreads>(a, s, sh.rn, sh.fin, j, rb, nslots, e_reg, lamf, data, rr_out);
 }
 
 hipError_t launch_assemble_lp(const StepArgs &a, const StepScratch &s, int precision, float *rr_out,

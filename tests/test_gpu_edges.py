@@ -80,11 +80,15 @@ def test_k1_block_diagonal_solved_in_one_iteration(lib):
 
 
 def test_k8_graph_and_normal_equations(lib):
+    """k = 8: rows of up to 29 blocks.  The assembly splits a row's points over two waves with 18 statistic
+    slots each and accumulates a longer row on one wave; this graph has rows of both kinds."""
     s = Scene("c1")
     s.params.k = 8
     s.params.sigma = 8.0
     g = s.graph
     ref = oracle.build_graph(s.sc["points"], s.sc["nodes"], 8, "gauss", 8.0)
+    rl = np.diff(ref["row_ptr"])
+    assert (rl > 18).any() and (rl <= 18).any()
     assert np.array_equal(g.knn_idx.cpu().numpy().T, ref["idx"])
     assert g.info.cpu().numpy()[3] == 0
     nnzb = int(g.info.cpu().numpy()[0])
