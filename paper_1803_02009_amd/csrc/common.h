@@ -322,4 +322,46 @@ __device__ __forceinline__ bool gj_inverse_block(double (*A)[12], float *out) {
     return !bad;
 }
 
+// The value of v on lane l (l uniform), for float64.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The same inverse as gj_inverse_block (the same operations in the same order, so the same bits), by one
+// wave without LDS traffic or barriers: lane c < 12 holds column c of A in registers, and each elimination
+// step reads the pivot column from lane k.  A (row-major float64 in LDS) is only read.  Returns false on
+// every lane when a pivot is not positive, and out is then I.
+__device__ __forceinline__ bool gj_inverse_lanes(const double (*A)[12], float *out) {
+    const int lane = threadIdx.x % 64;
+    const int c = lane < 12 ? lane : 0;
+    double col[12];
+#pragma unroll
+    for (int R = 0; R < 12; ++R) col[R] = A[R][c];
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        double ark[12];
+#pragma unroll
+        for (int R = 0; R < 12; ++R) ark[R] = readlane_f64(col[R], k);   // A[R][k]
+        const double p = ark[k];
+        bad = bad || !(p > 0.0);
+        const double ip = p > 0.0 ? 1.0 / p : 1.0;
+        const double akc = col[k];   // A[k][c]
+        const bool ck = c == k;
+#pragma unroll
+        for (int R = 0; R < 12; ++R) {
+            if (R == k) col[R] = ck ? ip : akc * ip;
+            else col[R] = ck ? -ark[R] * ip : col[R] - ark[R] * (akc * ip);
+        }
+    }
+    if (lane < 12) {
+#pragma unroll
+        for (int R = 0; R < 12; ++R) out[R * 12 + c] = bad ? (R == c ? 1.f : 0.f) : (float)col[R];
+    }
+    return !bad;
+}
+
 }  // namespace msl

@@ -302,67 +302,79 @@ template <int NT, class DataFn>
 __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratch &s, RowNode &rn, RowFin<NT> &fin,
                                              int j, int rb, int nslots, double e_reg, float lamf, DataFn data,
                                              float *rr_out) {
+    static_assert(NT >= 2 * kWave, "the last phase runs the preconditioner and the gradient on two waves");
+    static_assert(MISSLAM_MAX_ROW <= kWave, "one lane per slot");
     const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
+    // the diagonal slot and the degree, by a ballot over the slots
+    const uint64_t dmask = __ballot(lane < nslots && rn.cols[lane] == j);
+    const int dsl = dmask ? (int)__builtin_ctzll(dmask) : -1;
+    const int deg = nslots - __popcll(dmask);
     // the row's regulariser energy: its edges' terms added in slot order, as node_energy_kernel adds them, so
-    // that the energy of a point in parameter space does not depend on which kernel evaluated it
+    // that the energy of a point in parameter space does not depend on which kernel evaluated it.  Loops over
+    // the slots take kChunk slots at a time, their LDS reads issued together, and skip the diagonal slot.
+    constexpr int kChunk = 8;
     if (tid < nslots) fin.red[tid] = e_reg;
-    __syncthreads();
-    double ereg_tot = 0.0;
-    if (tid == 0)
-        for (int t = 0; t < nslots; ++t)
-            if (rn.cols[t] != j) ereg_tot += fin.red[t];
+    const double lam = (double)lamf;
+    for (int t = tid; t < 144; t += NT) fin.Hd[t / 12][t % 12] = t / 12 == t % 12 ? lam : 0.0;
     if (tid < 10) {
+        const int p0 = pair_c0(tid), p1 = pair_c1(tid);
         float sacc = 0.f;
-        for (int t = 0; t < nslots; ++t) {
-            if (rn.cols[t] == j) continue;
-            const float eh[4] = {rn.rg[t][0], rn.rg[t][1], rn.rg[t][2], 1.f};
-            sacc = fmaf(eh[pair_c0(tid)], eh[pair_c1(tid)], sacc);
+        for (int t0 = 0; t0 < nslots; t0 += kChunk) {
+            float eh0[kChunk], eh1[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                const int t = min(t0 + u, MISSLAM_MAX_ROW - 1);
+                eh0[u] = p0 < 3 ? rn.rg[t][p0 < 3 ? p0 : 0] : 1.f;
+                eh1[u] = p1 < 3 ? rn.rg[t][p1 < 3 ? p1 : 0] : 1.f;
+            }
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u)
+                if (t0 + u < nslots && !((dmask >> (t0 + u)) & 1)) sacc = fmaf(eh0[u], eh1[u], sacc);
         }
         rn.EE[tid] = sacc;
     }
-    const double lam = (double)lamf;
-    for (int t = tid; t < 144; t += NT) fin.Hd[t / 12][t % 12] = t / 12 == t % 12 ? lam : 0.0;
     __syncthreads();
     if (tid == 0) {
+        double ereg_tot = 0.0;
+        for (int t0 = 0; t0 < nslots; t0 += kChunk) {
+            double red[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) red[u] = fin.red[min(t0 + u, NT - 1)];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u)
+                if (t0 + u < nslots && !((dmask >> (t0 + u)) & 1)) ereg_tot += red[u];
+        }
         double erot = 0.0;
         for (int q = 0; q < 6; ++q) erot += (double)rn.rr[q] * rn.rr[q];
         s.node_part[2 * j + 0] = erot;
         s.node_part[2 * j + 1] = ereg_tot;
     }
-    int deg = 0, dsl = -1;
-    for (int q = 0; q < nslots; ++q) {
-        deg += rn.cols[q] != j;
-        if (rn.cols[q] == j) dsl = q;
-    }
-    deg = __builtin_amdgcn_readfirstlane(deg);
-    dsl = __builtin_amdgcn_readfirstlane(dsl);
     const float wd = a.w_data, wreg = a.w_reg, wrot = a.w_rot;
     float *outb = a.blocks + (size_t)rb * 144;
-    // the blocks of the edges j -> l: (slot, entry) pairs spread over the threads, straight-line bodies
-    // (selects, no branches) so that the loads of consecutive pairs overlap; the diagonal slot is skipped here
-#pragma unroll 4
-    for (int t = tid; t < nslots * 144; t += NT) {
-        const int sl = t / 144, en = t - sl * 144;
+    // each thread owns entries en of every block of the row: its index arithmetic is done once, and the slots'
+    // loads are independent (straight-line bodies, selects, no branches)
+    for (int en = tid; en < 144; en += NT) {
         const int R = en / 12, C = en % 12;
         const int c = R / 3, aa = R % 3, c2 = C / 3, a2 = C % 3;
-        const float hd = data(sl, R, C, true);
-        const float rgc = rn.rg[sl][c < 3 ? c : 0], rgc2 = rn.rg[sl][c2 < 3 ? c2 : 0];
-        const float eh_c = c < 3 ? rgc : 1.f;
-        const float fh_c2 = c2 < 3 ? -rgc2 : 1.f;
-        const float r1 = c2 == 3 ? 0.f - eh_c : 0.f;   // edge j -> l
-        const float r2 = c == 3 ? r1 - fh_c2 : r1;     // edge l -> j
-        const float reg = aa == a2 ? r2 : 0.f;
-        const float rr = fmaf(wrot, 0.f, wreg * reg);
-        const float h = fmaf(wreg, reg, wd * hd);
-        if (sl != dsl) {
-            outb[(size_t)sl * 144 + en] = h;
-            if (rr_out) rr_out[(size_t)(rb + sl) * 144 + en] = rr;
+        const int ic = c < 3 ? c : 0, ic2 = c2 < 3 ? c2 : 0;
+#pragma unroll 4
+        for (int sl = 0; sl < nslots; ++sl) {   // edges j -> l; the diagonal slot is written below
+            const float hd = data(sl, R, C, true);
+            const float rgc = rn.rg[sl][ic], rgc2 = rn.rg[sl][ic2];
+            const float eh_c = c < 3 ? rgc : 1.f;
+            const float fh_c2 = c2 < 3 ? -rgc2 : 1.f;
+            const float r1 = c2 == 3 ? 0.f - eh_c : 0.f;   // edge j -> l
+            const float r2 = c == 3 ? r1 - fh_c2 : r1;     // edge l -> j
+            const float reg = aa == a2 ? r2 : 0.f;
+            const float rr = fmaf(wrot, 0.f, wreg * reg);
+            const float h = fmaf(wreg, reg, wd * hd);
+            if (sl != dsl) {
+                outb[(size_t)sl * 144 + en] = h;
+                if (rr_out) rr_out[(size_t)(rb + sl) * 144 + en] = rr;
+            }
         }
-    }
-    if (dsl >= 0) {   // the diagonal block: regulariser and rotation terms of node j
-        for (int en = tid; en < 144; en += NT) {
-            const int R = en / 12, C = en % 12;
-            const int c = R / 3, aa = R % 3, c2 = C / 3, a2 = C % 3;
+        if (dsl >= 0) {   // the diagonal block: regulariser and rotation terms of node j
             const float hd = data(dsl, R, C, false);
             float reg = 0.f, rot = 0.f;
             if (aa == a2) {
@@ -380,28 +392,41 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
             if (rr_out) rr_out[(size_t)(rb + dsl) * 144 + en] = rr;
         }
     }
-    if (tid < 12) {
-        const int c = tid / 3, aa = tid % 3;
+    __syncthreads();
+    if (wave == 0) {
+        // block-Jacobi preconditioner of this row: (H_jj + lambda I)^-1 in float64 on lanes 0-11
+        if (a.minv) {
+            const bool ok = gj_inverse_lanes(fin.Hd, a.minv + (size_t)j * 144);
+            if (!ok && lane == 0) atomicOr(a.flags, MISSLAM_FLAG_NONSPD_BLOCK);
+        }
+    } else if (wave == 1 && lane < 12) {
+        const int c = lane / 3, aa = lane % 3;
         double reg = 0.0;
-        for (int t = 0; t < nslots; ++t) {
-            if (rn.cols[t] == j) continue;
-            const float eh_c = c < 3 ? rn.rg[t][c] : 1.f;
-            reg = fma((double)eh_c, (double)rn.rg[t][3 + aa], reg);
-            if (c == 3) reg -= rn.rg[t][6 + aa];
+        for (int t0 = 0; t0 < nslots; t0 += kChunk) {
+            float ehc[kChunk], rja[kChunk], rla[kChunk];
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                const int t = min(t0 + u, MISSLAM_MAX_ROW - 1);
+                ehc[u] = c < 3 ? rn.rg[t][c < 3 ? c : 0] : 1.f;
+                rja[u] = rn.rg[t][3 + aa];
+                rla[u] = rn.rg[t][6 + aa];
+            }
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+                if (t0 + u < nslots && !((dmask >> (t0 + u)) & 1)) {
+                    reg = fma((double)ehc[u], (double)rja[u], reg);
+                    if (c == 3) reg -= rla[u];
+                }
+            }
         }
         double rot = 0.0;
         if (c < 3) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) rot = fma((double)rn.Jr[q][tid], (double)rn.rr[q], rot);
+            for (int q = 0; q < 6; ++q) rot = fma((double)rn.Jr[q][lane], (double)rn.rr[q], rot);
         }
         // the three terms balance near convergence: combined in float64, rounded once
-        a.gvec[(size_t)j * 12 + tid] = (float)fma((double)wrot, rot, fma((double)wreg, reg, (double)wd * rn.gd[tid]));
-    }
-    // block-Jacobi preconditioner of this row: (H_jj + lambda I)^-1 in float64, whole workgroup
-    if (a.minv) {
-        __syncthreads();
-        const bool ok = gj_inverse_block<NT>(fin.Hd, a.minv + (size_t)j * 144);
-        if (!ok && tid == 0) atomicOr(a.flags, MISSLAM_FLAG_NONSPD_BLOCK);
+        a.gvec[(size_t)j * 12 + lane] =
+            (float)fma((double)wrot, rot, fma((double)wreg, reg, (double)wd * rn.gd[lane]));
     }
 }
 
@@ -775,7 +800,8 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
 }
 
 template <int K>
-__global__ void __launch_bounds__(kAsmThreads) assemble_rows_kernel(StepArgs a, StepScratch s) {
+__global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_eu(4)))
+assemble_rows_kernel(StepArgs a, StepScratch s) {
     const int m = a.nd.m;
     const int per = (int)((m + 7) / 8);
     const int j = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
@@ -1455,7 +1481,8 @@ __global__ void __launch_bounds__(256) list_pack_batched_kernel(const BatchItem 
 }
 
 template <int K>
-__global__ void __launch_bounds__(kAsmThreads) assemble_batched_kernel(const BatchItem *__restrict__ items, int count,
+__global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_eu(4)))
+assemble_batched_kernel(const BatchItem *__restrict__ items, int count,
                                                                        int gi) {
     const BatchItem &it = items[batch_of(items, count, blockIdx.x, 1)];
     StepArgs a = it.a;
