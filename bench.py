@@ -76,7 +76,9 @@ def parse():
     ap.add_argument("--config", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--seq-frames", type=int, default=8, help="frames of the sweeping sequence (0: skip)")
+    ap.add_argument("--seq-frames", type=int, default=8,
+                    help="frames of the sweeping sequence (0: skip; 300 is the whole sweep)")
+    ap.add_argument("--no-cold", action="store_true", help="skip the frame timed after a 512 MiB cache flush")
     ap.add_argument("--no-lowp", action="store_true")
     ap.add_argument("--no-keypoints", action="store_true")
     ap.add_argument("--no-lm", action="store_true")
@@ -126,6 +128,8 @@ def main():
     from paper_1803_02009_amd import _lib
     from paper_1803_02009_amd import misslam as M
 
+    # the sweep's frames are generated on the host first, in worker processes forked before any GPU use
+    seq_frames = generate_sequence(args.seq_frames + 1) if args.seq_frames > 0 else None
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     lib = _lib.load()
     sc = gen.make_scene(args.config)
@@ -219,6 +223,8 @@ def main():
 
     # accuracy against the stored float64 oracle result of the same frame
     acc = accuracy(state, rep, os.path.join(ROOT, "tests", "golden", f"{args.config}_oracle.npz"))
+    hbm = copy_bandwidth(torch)
+    cold = None if args.no_cold else cold_frames(torch, frame, args.steps)
 
     # the low-precision form on the same frame: without refinement (the float64
     # oracle's algorithm on a rounded data term) and with two refinement passes
@@ -252,7 +258,10 @@ def main():
                          "flags": int(rep[-1]["flags"])},
         "roofline": roofline,
         "roofline_other": [v for k, v in lines.items() if k != dominant],
+        "hbm_copy": hbm,
     }
+    if cold is not None:
+        out["cold_cache"] = cold
     if lowp is not None:
         out["low_precision"] = lowp
     if kpb is not None:
@@ -263,11 +272,72 @@ def main():
         out["joint_pose"] = jb
     if not args.no_batch:
         out["batch"] = batch_bench(M, _lib, args)
-    if args.seq_frames > 0:
-        out["sequence"] = sequence_bench(M, args.seq_frames)
+    if seq_frames is not None:
+        out["sequence"] = sequence_bench(M, seq_frames)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, params)
     print(json.dumps(out))
+
+
+def copy_bandwidth(torch, mib=256, reps=10):
+    """Achievable HBM bandwidth: a device-to-device copy of mib MiB (read + write bytes over the event time)."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * src.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return {"copy_mib": mib, "achieved_gbs": round(gbs, 1), "of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def cold_frames(torch, frame, steps, flush_mib=512):
+    """The frame with cold caches: before each frame a 512 MiB buffer is written, which evicts the 256 MB
+    last-level cache and the L2s; the frame alone is timed with events on the same stream."""
+    buf = torch.empty(flush_mib << 18, dtype=torch.float32, device="cuda")
+    times = []
+    for k in range(steps):
+        buf.fill_(float(k))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        frame()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del buf
+    return {"flush_mib": flush_mib, "ms_per_frame": round(float(np.mean(times)), 4),
+            "ms_per_frame_min": round(float(np.min(times)), 4)}
+
+
+_SEQ = None
+
+
+def _sequence_frame(f):
+    global _SEQ
+    if _SEQ is None:
+        from gen.sequence import Sequence
+        _SEQ = Sequence()
+    return _SEQ.frame(f)
+
+
+def generate_sequence(frames):
+    """Frames 0..frames-1 of the sweep, generated in parallel worker processes (fork, before any GPU use)."""
+    import multiprocessing as mp
+    workers = max(1, min(16, len(os.sched_getaffinity(0)), frames))
+    t0 = time.perf_counter()
+    if workers == 1:
+        data = [_sequence_frame(f) for f in range(frames)]
+    else:
+        with mp.get_context("fork").Pool(workers) as pool:
+            data = pool.map(_sequence_frame, range(frames), chunksize=1)
+    print(f"sequence: {frames} frames generated in {time.perf_counter() - t0:.1f} s on {workers} processes",
+          file=sys.stderr, flush=True)
+    return data
 
 
 def batch_bench(M, _lib, args, count=16):
@@ -325,26 +395,41 @@ def batch_bench(M, _lib, args, count=16):
 
 
 def lowp_bench(M, _lib, sc, frame, timed, state, G, args):
-    """The low-precision form on the same frame: without refinement (the float64 oracle's algorithm on a
-    rounded data term) and with two refinement passes."""
-    lowp = {"form": "bf16 data-term J^T J on the matrix cores (fp32 accumulation); refine_steps fp32 "
+    """The low-precision forms on the same frame: bf16 and fp16 data terms without refinement (the float64
+    oracle's algorithm on a rounded data term) and with two refinement passes, each against the plain and the
+    same-form oracle runs.  Beside them, the float32 form with the PCG work of two refinement passes (three
+    10-iteration solves per step: 30 PCG iterations), against the oracle run with 30 PCG iterations."""
+    lowp = {"form": "bf16 / fp16 data-term J^T J on the matrix cores (fp32 accumulation); refine_steps fp32 "
                     "matrix-free refinement passes per GN step"}
     plain = os.path.join(ROOT, "tests", "golden", f"{args.config}_oracle.npz")
-    for steps in (0, 2):
-        lp = M.Params(sigma=sc["sigma"], gn_iters=sc["gn_iters"], pcg_iters=sc["pcg_iters"],
-                      precision=_lib.PREC_BF16, refine_steps=steps)
-        for _ in range(max(1, args.warmup)):
-            frame(lp)
-        lp_elapsed = timed(lp, args.steps)
-        lp_rep = M.read_report(state["rep"])
-        entry = {"refine_steps": steps, "ms_per_frame": round(1000.0 * lp_elapsed / args.steps, 4),
-                 "gn_iters_per_s": round(G * args.steps / lp_elapsed, 2),
-                 "accuracy_vs_fp64_oracle": accuracy(state, lp_rep, plain),
-                 "e_data_final": float(lp_rep[-1]["e_data"])}
-        emu = os.path.join(ROOT, "tests", "golden", f"{args.config}_bf16_r{steps}_oracle.npz")
-        if steps > 0:
-            entry["accuracy_vs_same_form_oracle"] = accuracy(state, lp_rep, emu)
-        lowp[f"bf16_r{steps}"] = entry
+    for prec, code in (("bf16", _lib.PREC_BF16), ("fp16", _lib.PREC_FP16)):
+        for steps in (0, 2):
+            lp = M.Params(sigma=sc["sigma"], gn_iters=sc["gn_iters"], pcg_iters=sc["pcg_iters"],
+                          precision=code, refine_steps=steps)
+            for _ in range(max(1, args.warmup)):
+                frame(lp)
+            lp_elapsed = timed(lp, args.steps)
+            lp_rep = M.read_report(state["rep"])
+            entry = {"refine_steps": steps, "ms_per_frame": round(1000.0 * lp_elapsed / args.steps, 4),
+                     "gn_iters_per_s": round(G * args.steps / lp_elapsed, 2),
+                     "accuracy_vs_fp64_oracle": accuracy(state, lp_rep, plain),
+                     "accuracy_vs_same_form_oracle": accuracy(
+                         state, lp_rep, os.path.join(ROOT, "tests", "golden", f"{args.config}_{prec}_r{steps}_oracle.npz")),
+                     "e_data_final": float(lp_rep[-1]["e_data"])}
+            lowp[f"{prec}_r{steps}"] = entry
+    p30 = M.Params(sigma=sc["sigma"], gn_iters=sc["gn_iters"], pcg_iters=3 * sc["pcg_iters"])
+    for _ in range(max(1, args.warmup)):
+        frame(p30)
+    el = timed(p30, args.steps)
+    rep30 = M.read_report(state["rep"])
+    lowp["fp32_pcg30"] = {"pcg_iters": p30.pcg_iters, "ms_per_frame": round(1000.0 * el / args.steps, 4),
+                          "gn_iters_per_s": round(G * args.steps / el, 2),
+                          "accuracy_vs_same_work_oracle": accuracy(
+                              state, rep30, os.path.join(ROOT, "tests", "golden", f"{args.config}_pcg30_oracle.npz")),
+                          "e_data_final": float(rep30[-1]["e_data"])}
+    for prec in ("bf16", "fp16"):
+        lowp[f"{prec}_r2_vs_fp32_same_pcg_work"] = round(
+            lowp["fp32_pcg30"]["ms_per_frame"] / lowp[f"{prec}_r2"]["ms_per_frame"], 3)
     return lowp
 
 
@@ -368,17 +453,15 @@ def keypoint_bench(M, sc, frame, timed, state, params, G, args, torch):
             "e_corr": [float(rep[0]["e_corr"]), float(rep[-1]["e_corr"])], "accuracy_vs_fp64_oracle": acc}
 
 
-def sequence_bench(M, frames):
+def sequence_bench(M, data):
     """The sweeping, breathing 250 x 200 mm sheet at 640x480: frame 0 lifts the first model and its nodes;
     every later frame runs graph setup, registration (10 x 10), fusion and growth/maintenance.  Frames are
-    generated on the host before timing; only the GPU frame loop is timed (a host read of the new model
-    size closes every frame, as a caller sizing the next frame's buffers must)."""
+    generated on the host before timing; only the GPU frame loop is timed, frame by frame (a host read of the
+    new model size closes every frame, as a caller sizing the next frame's buffers must)."""
     import torch
 
-    from gen.sequence import Sequence
-    seq = Sequence()
-    data = [seq.frame(f) for f in range(frames + 1)]
-    cap_n, cap_m = 1_500_000, 10_000
+    frames = len(data) - 1
+    cap_n, cap_m = 2_000_000, 12_000
     P = torch.zeros((6, cap_n), device="cuda")
     W = torch.zeros(cap_n, device="cuda")
     S = torch.zeros(cap_n, dtype=torch.int32, device="cuda")
@@ -400,9 +483,11 @@ def sequence_bench(M, frames):
     n, m = int(c[0]), int(c[1])
     sizes = [(n, m)]
     torch.cuda.synchronize()
+    flags = overflow = 0
+    per_frame = []
     t0 = time.perf_counter()
-    flags = 0
     for f in range(1, frames + 1):
+        tf = time.perf_counter()
         fi = frames_in[f]
         g = M.build_graph(P[:, :n], G[:, :m], params, ws)
         rep, _ = M.gn_register(P[:, :n], G[:, :m], X[:m], g, fi["depth"], fi["cam"], fi["pose"], params, ws)
@@ -412,13 +497,24 @@ def sequence_bench(M, frames):
         c = M.grow(P, W, S, n, G, X, m, reg, regd, nmap, fi["cam"], fi["pose"], M.grow_params(f, 2.5),
                    ws_g).cpu().numpy()
         flags |= int(M.read_report(rep)["flags"].max())
+        overflow |= int(c[6])
         n, m = int(c[0]), int(c[1])
         sizes.append((n, m))
+        per_frame.append(1000.0 * (time.perf_counter() - tf))
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / frames
-    return {"workload": f"sweep over a breathing 250x200 mm sheet, 640x480, frames 1..{frames} after the lifted "
-                        f"frame 0; graph + 10x10 registration + fusion + growth per frame",
-            "ms_per_frame": round(1000 * dt, 3), "points_nodes_per_frame": sizes, "report_flags": flags}
+    out = {"workload": f"sweep over a breathing 250x200 mm sheet, 640x480, frames 1..{frames} after the lifted "
+                       f"frame 0; graph + 10x10 registration + fusion + growth per frame",
+           "frames": frames, "ms_per_frame": round(1000 * dt, 3), "report_flags": flags,
+           "capacity_overflow": overflow, "final_points_nodes": sizes[-1]}
+    if frames <= 20:
+        out["points_nodes_per_frame"] = sizes
+    else:   # ms per frame against model size, in bins of 25 frames
+        out["by_model_size"] = [{"frames": [f0_ + 1, min(f0_ + 25, frames)],
+                                 "points_nodes_at_end": sizes[min(f0_ + 25, frames)],
+                                 "ms_per_frame": round(float(np.mean(per_frame[f0_:f0_ + 25])), 3)}
+                                for f0_ in range(0, frames, 25)]
+    return out
 
 
 def lm_bench(M, frame, timed, state, params, G, args):
@@ -481,8 +577,21 @@ def accuracy(state, rep, gold):
             "rel_err_e_data_final": float(abs(rep[-1]["e_data"] - z["e_data_final"]) / z["e_data_final"])}
 
 
-def cpu_baseline(sc, params):
-    """Float64 oracle on the same frame, single-threaded: graph setup and one GN iteration."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(sc, params, reps=3):
+    """Float64 oracle on the same frame: its graph setup once, then one GN iteration (10 PCG) timed reps times
+    with BLAS limited to one thread and reps times with BLAS on every core the process may use; medians.
+    NumPy's elementwise work runs on one thread either way."""
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:  # pragma: no cover
@@ -491,26 +600,38 @@ def cpu_baseline(sc, params):
     from oracle.gn import linearize
     from oracle.pcg import block_jacobi, pcg
 
-    ctx = threadpool_limits(1) if threadpool_limits else None
-    try:
-        pb = oracle.Problem.from_scene(sc, gn_iters=1)
-        t0 = time.perf_counter()
-        graph = oracle.build_graph(pb.points, pb.nodes, pb.k, pb.weight_kind, pb.sigma)
-        t1 = time.perf_counter()
-        Nmap, Nvalid = oracle.normal_map(pb.depth, pb.camera)
-        x = oracle.identity_params(len(pb.nodes))
+    pb = oracle.Problem.from_scene(sc, gn_iters=1)
+    t0 = time.perf_counter()
+    graph = oracle.build_graph(pb.points, pb.nodes, pb.k, pb.weight_kind, pb.sigma)
+    t1 = time.perf_counter()
+    Nmap, Nvalid = oracle.normal_map(pb.depth, pb.camera)
+    x = oracle.identity_params(len(pb.nodes))
+
+    def gn_iteration():
+        ta = time.perf_counter()
         _, _, _, blocks, g, _ = linearize(pb, graph, x, Nmap, Nvalid)
         Minv, _ = block_jacobi(graph["row_ptr"], graph["col_idx"], blocks, pb.lam)
         pcg(graph["row_ptr"], graph["col_idx"], blocks, g, pb.lam, params.pcg_iters, Minv)
-        t2 = time.perf_counter()
-    finally:
-        if ctx is not None:
-            ctx.__exit__(None, None, None)
-    gn_s = t2 - t1
-    return {"value": round(1.0 / gn_s, 4), "unit": "GN iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"one GN iteration ({params.pcg_iters} PCG) of the same frame after the oracle's graph setup; "
-                      f"graph setup {t1 - t0:.1f} s, GN iteration {gn_s:.1f} s, float64 numpy, 1 thread",
-            "graph_setup_s": round(t1 - t0, 2), "gn_iter_s": round(gn_s, 2)}
+        return time.perf_counter() - ta
+
+    def timed(limit):
+        ctx = threadpool_limits(limit) if threadpool_limits else None
+        try:
+            return float(np.median([gn_iteration() for _ in range(reps)]))
+        finally:
+            if ctx is not None:
+                ctx.__exit__(None, None, None)
+
+    cores = len(os.sched_getaffinity(0))
+    one = timed(1)
+    allc = timed(cores)
+    return {"value": round(1.0 / allc, 4), "unit": "GN iters/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"one GN iteration ({params.pcg_iters} PCG) of the same frame after the oracle's graph setup "
+                      f"({t1 - t0:.1f} s), median of {reps}, float64 numpy/scipy, BLAS on the {cores} cores the "
+                      f"process may use; one_thread: the same with BLAS on 1 thread",
+            "gn_iter_s": round(allc, 3), "graph_setup_s": round(t1 - t0, 2),
+            "one_thread": {"value": round(1.0 / one, 4), "gn_iter_s": round(one, 3), "cores": 1}}
 
 
 if __name__ == "__main__":

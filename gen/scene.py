@@ -185,7 +185,9 @@ def render_depth(spec, surface, field, R, T, rng, noise_sigma):
 
     For each pixel centre, a 2-D Newton iteration in float64 finds the canonical
     (x, y) whose deformed, posed surface point projects onto it; depth is that
-    point's camera z.  Pixels that do not converge to 1e-9 px, or whose
+    point's camera z.  A pixel stops iterating once it has converged (each
+    pixel's iterates do not depend on the others, so only the unconverged ones
+    are carried on).  Pixels that do not converge to 1e-9 px, or whose
     canonical point leaves the tissue patch, stay empty.  Gaussian noise is then
     added to valid pixels.
     """
@@ -200,7 +202,7 @@ def render_depth(spec, surface, field, R, T, rng, noise_sigma):
         Y = field(X)
         return Y @ R.T + T
 
-    def residual(x, y):
+    def residual(x, y, u, v):
         P = cam_point(x, y)
         return P[:, 0] / P[:, 2] * fx + cx - u, P[:, 1] / P[:, 2] * fy + cy - v, P[:, 2]
 
@@ -212,28 +214,27 @@ def render_depth(spec, surface, field, R, T, rng, noise_sigma):
     x = o[0] + s * d[:, 0]
     y = o[1] + s * d[:, 1]
     h = 1e-6
-    ok = np.zeros(u.shape, dtype=bool)
+    act = np.arange(u.size)          # pixels still iterating
     for _ in range(40):
-        fu, fv, _ = residual(x, y)
-        ok = (np.abs(fu) < 1e-9) & (np.abs(fv) < 1e-9)
-        if ok.all():
+        xa, ya, ua, va = x[act], y[act], u[act], v[act]
+        fu, fv, _ = residual(xa, ya, ua, va)
+        go = ~((np.abs(fu) < 1e-9) & (np.abs(fv) < 1e-9))
+        act, xa, ya, ua, va, fu, fv = act[go], xa[go], ya[go], ua[go], va[go], fu[go], fv[go]
+        if act.size == 0:
             break
-        fu_x, fv_x, _ = residual(x + h, y)
-        fu_xm, fv_xm, _ = residual(x - h, y)
-        fu_y, fv_y, _ = residual(x, y + h)
-        fu_ym, fv_ym, _ = residual(x, y - h)
+        fu_x, fv_x, _ = residual(xa + h, ya, ua, va)
+        fu_xm, fv_xm, _ = residual(xa - h, ya, ua, va)
+        fu_y, fv_y, _ = residual(xa, ya + h, ua, va)
+        fu_ym, fv_ym, _ = residual(xa, ya - h, ua, va)
         a = (fu_x - fu_xm) / (2 * h)
         b = (fu_y - fu_ym) / (2 * h)
         c = (fv_x - fv_xm) / (2 * h)
         e = (fv_y - fv_ym) / (2 * h)
         det = a * e - b * c
         det = np.where(np.abs(det) < 1e-30, 1e-30, det)
-        dx = (e * fu - b * fv) / det
-        dy = (-c * fu + a * fv) / det
-        step = np.where(ok, 0.0, 1.0)
-        x = x - step * dx
-        y = y - step * dy
-    fu, fv, z = residual(x, y)
+        x[act] = xa - (e * fu - b * fv) / det
+        y[act] = ya - (-c * fu + a * fv) / det
+    fu, fv, z = residual(x, y, u, v)
     ok = (np.abs(fu) < 1e-9) & (np.abs(fv) < 1e-9) & np.isfinite(z) & (z > 0)
     x0, x1, y0, y1 = spec.patch
     ok &= (x >= x0) & (x <= x1) & (y >= y0) & (y <= y1)

@@ -9,9 +9,10 @@ name:kp:S adds S generated key points (gen.keypoints, seed 7, 0.05 mm noise)
 with the Eq.(9) term at w_corr = 10; name:lm runs the adaptive
 Levenberg-Marquardt schedule (default factors) instead of the fixed damping;
 name:joint registers the rigid pose with the ED graph (Eq.(10) terms,
-w_r = 1e6, w_p = 1e3), storing the refined pose too.  batch<b> is problem b
-of the uneven batch (gen.batch_spec(b)).
-Output: tests/golden/<name>[_<prec>_r<R> | _kp<S> | _lm | _joint]_oracle.npz with x
+w_r = 1e6, w_p = 1e3), storing the refined pose too; name:pcg:P runs the
+plain oracle with P PCG iterations per step.  batch<b> is problem b of the
+uneven batch (gen.batch_spec(b)).
+Output: tests/golden/<name>[_<prec>_r<R> | _kp<S> | _lm | _joint | _pcg<P>]_oracle.npz with x
 (m, 12) after the frame's iterations (independent decisions), the final
 energies and the per-iteration data energies (and, for lm, the per-step
 decisions and dampings).
@@ -45,6 +46,11 @@ def main(spec):
     elif parts[1] == "lm":
         x, rep = oracle.lm_register(pb, oracle.LMSchedule())
         out = f"{name}_lm_oracle.npz"
+    elif parts[1] == "pcg":
+        P = int(parts[2])
+        pb = oracle.Problem.from_scene(sc, pcg_iters=P)
+        x, rep = oracle.gn_register(pb)
+        out = f"{name}_pcg{P}_oracle.npz"
     elif parts[1] == "kp":
         S = int(parts[2])
         kp, tgt = gen.keypoints(sc, S, seed=7, noise=0.05)
