@@ -7,9 +7,12 @@ method runs in the library's gfx950 kernels.  Layouts:
   x       (m, 12) float32 cuda: node parameters (c1, c2, c3, t)
   depth   (H, W) float32 cuda
 """
+import atexit
 import ctypes
 import dataclasses
 import math
+import sys
+import weakref
 
 import numpy as np
 import torch
@@ -454,6 +457,17 @@ class WarpEnergy(torch.autograd.Function):
         return gp, gv, None
 
 
+# Batches still open when the interpreter exits are closed by an exit hook, while the HIP runtime is still
+# up; a batch collected during interpreter shutdown makes no library call.
+_open_batches = weakref.WeakSet()
+
+
+@atexit.register
+def _close_open_batches():
+    for b in list(_open_batches):
+        b.close()
+
+
 class Batch:
     """Uneven problems registered together (misslam_batch_*): one launch per
     phase over every problem, the frame captured once into a hipGraph.
@@ -467,6 +481,7 @@ class Batch:
     def __init__(self, problems, params, rows_per_wg=0):
         self.params = params
         self.keep = []
+        _open_batches.add(self)
         self.reports = []
         arr = (_lib.Problem * len(problems))()
         for i, pr in enumerate(problems):
@@ -499,7 +514,9 @@ class Batch:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():   # the exit hook has closed it, or the runtime may be gone
+            return
         try:
             self.close()
-        except Exception:  # pragma: no cover - interpreter shutdown
+        except Exception:  # pragma: no cover
             pass
