@@ -484,6 +484,8 @@ def sequence_bench(M, data):
     sizes = [(n, m)]
     torch.cuda.synchronize()
     flags = overflow = 0
+    first_flag = {}      # flag bit -> first frame whose report carries it
+    first_overflow = None
     per_frame = []
     t0 = time.perf_counter()
     for f in range(1, frames + 1):
@@ -496,7 +498,13 @@ def sequence_bench(M, data):
                            M.fuse_params(f), ws, outputs=True)
         c = M.grow(P, W, S, n, G, X, m, reg, regd, nmap, fi["cam"], fi["pose"], M.grow_params(f, 2.5),
                    ws_g).cpu().numpy()
-        flags |= int(M.read_report(rep)["flags"].max())
+        ff = int(np.bitwise_or.reduce(M.read_report(rep)["flags"]))
+        flags |= ff
+        for bit in range(8):
+            if ff & (1 << bit) and (1 << bit) not in first_flag:
+                first_flag[1 << bit] = f
+        if c[6] and first_overflow is None:
+            first_overflow = f
         overflow |= int(c[6])
         n, m = int(c[0]), int(c[1])
         sizes.append((n, m))
@@ -506,7 +514,9 @@ def sequence_bench(M, data):
     out = {"workload": f"sweep over a breathing 250x200 mm sheet, 640x480, frames 1..{frames} after the lifted "
                        f"frame 0; graph + 10x10 registration + fusion + growth per frame",
            "frames": frames, "ms_per_frame": round(1000 * dt, 3), "report_flags": flags,
-           "capacity_overflow": overflow, "final_points_nodes": sizes[-1]}
+           "first_frame_of_flag": {str(k): v for k, v in sorted(first_flag.items())},
+           "capacity_overflow": overflow, "first_capacity_overflow_frame": first_overflow,
+           "final_points_nodes": sizes[-1]}
     if frames <= 20:
         out["points_nodes_per_frame"] = sizes
     else:   # ms per frame against model size, in bins of 25 frames
