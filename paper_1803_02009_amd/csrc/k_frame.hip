@@ -416,12 +416,11 @@ __device__ __forceinline__ bool key_less(uint64_t ah, uint64_t al, uint32_t ap, 
 }
 
 // One block per node: its list sorted by (sorted node set, point index).  A list of up to MISSLAM_MAX_LIST
-// entries is bitonic-sorted in LDS in one piece; a longer one is sorted in pieces of MISSLAM_MAX_LIST, which
-// are then merged pairwise in global memory through tmp (the same positions as the list), each merge split
-// over the block's threads along the merge path.  512 threads: half the passes per thread of 256 (229 -> 218
-// us of graph setup at 640x480), the same order.  The order is a total one (point indices are distinct), so
-// the result does not depend on the way it was reached.
-constexpr int kSortThreads = 512;
+// entries is bitonic-sorted in one piece; a longer one is sorted in pieces of MISSLAM_MAX_LIST, which are then
+// merged pairwise in global memory through tmp (the same positions as the list), each merge split over the
+// block's threads along the merge path.  The order is a total one (point indices are distinct), so the result
+// does not depend on the way it was reached.
+constexpr int kSortThreads = 256;
 
 template <int K>
 __device__ __forceinline__ bool entry_less(const int32_t *__restrict__ idx, int64_t n, uint32_t a, uint32_t b) {
@@ -459,6 +458,97 @@ __device__ void merge_runs(const int32_t *__restrict__ idx, int64_t n, const int
     }
 }
 
+// A list entry's sort key: the sorted k-node set (l is 0 for k <= 4) and the point index.
+struct SortKey {
+    uint64_t h, l;
+    uint32_t p;
+};
+
+__device__ __forceinline__ bool sk_less(const SortKey &a, const SortKey &b) {
+    return key_less(a.h, a.l, a.p, b.h, b.l, b.p);
+}
+
+// The bitonic network over one piece of P = kSortThreads * E entries (padded with keys above every entry).
+// Thread t holds entries t E .. t E + E - 1 in registers: a stage whose partner is in the same thread swaps
+// registers, one whose partner is in the same wave exchanges with __shfl_xor, and only a stage whose partner
+// is in another wave goes through LDS (3 of the 36-66 stages), with a barrier.
+template <int K, int E, int S>
+__device__ __forceinline__ void bitonic_in_thread(SortKey (&x)[E], int i0, int size) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if ((e & S) != 0 || e + S >= E) continue;
+        const bool asc = ((i0 + e) & size) == 0;
+        const SortKey a = x[e], b = x[e + S];
+        const bool sw = sk_less(b, a) == asc;
+        x[e] = sw ? b : a;
+        x[e + S] = sw ? a : b;
+    }
+}
+
+template <int K, int E>
+__device__ __forceinline__ void sort_piece(const int32_t *__restrict__ idx, int64_t n, int32_t *__restrict__ lst,
+                                           int c, uint64_t *kh, uint64_t *kl, uint32_t *kp) {
+    constexpr int P = kSortThreads * E;
+    const int i0 = (int)threadIdx.x * E;
+    SortKey x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        x[e].h = ~0ull;
+        x[e].l = K > 4 ? ~0ull : 0ull;
+        x[e].p = 0xFFFFFFFFu;
+        if (i0 + e < c) {
+            x[e].p = (uint32_t)lst[i0 + e];
+            uint64_t h, l;
+            set_key<K>(idx, n, x[e].p, h, l);
+            x[e].h = h;
+            if (K > 4) x[e].l = l;
+        }
+    }
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride < E) {   // partner in this thread
+                if (stride == 4) bitonic_in_thread<K, E, 4>(x, i0, size);
+                else if (stride == 2) bitonic_in_thread<K, E, 2>(x, i0, size);
+                else bitonic_in_thread<K, E, 1>(x, i0, size);
+            } else if (stride < kWave * E) {   // partner in this wave
+                const int mask = stride / E;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    SortKey y;
+                    y.h = __shfl_xor(x[e].h, mask, kWave);
+                    y.l = K > 4 ? __shfl_xor(x[e].l, mask, kWave) : 0ull;
+                    y.p = __shfl_xor(x[e].p, mask, kWave);
+                    const int i = i0 + e;
+                    const bool take_min = ((i & stride) == 0) == ((i & size) == 0);
+                    if (sk_less(y, x[e]) == take_min) x[e] = y;
+                }
+            } else {   // partner in another wave: through LDS
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    kh[i0 + e] = x[e].h;
+                    if (K > 4) kl[i0 + e] = x[e].l;
+                    kp[i0 + e] = x[e].p;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = i0 + e, o = i ^ stride;
+                    SortKey y;
+                    y.h = kh[o];
+                    y.l = K > 4 ? kl[o] : 0ull;
+                    y.p = kp[o];
+                    const bool take_min = ((i & stride) == 0) == ((i & size) == 0);
+                    if (sk_less(y, x[e]) == take_min) x[e] = y;
+                }
+                __syncthreads();
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        if (i0 + e < c) lst[i0 + e] = (int32_t)x[e].p;
+}
+
 template <int K>
 __global__ void __launch_bounds__(kSortThreads) list_sort_kernel(const int32_t *__restrict__ idx, int64_t n,
                                                         const int32_t *__restrict__ ptr,
@@ -470,47 +560,13 @@ __global__ void __launch_bounds__(kSortThreads) list_sort_kernel(const int32_t *
     const int b = ptr[j];
     const int call = ptr[j + 1] - b;
     for (int c0 = 0; c0 < call; c0 += MISSLAM_MAX_LIST) {   // one piece unless the list is long
-    const int c = min(call - c0, MISSLAM_MAX_LIST);
-    int P = 1;
-    while (P < c) P <<= 1;
-    for (int t = threadIdx.x; t < P; t += kSortThreads) {
-        uint64_t h = ~0ull, l = ~0ull;
-        uint32_t p = 0xFFFFFFFFu;
-        if (t < c) {
-            p = (uint32_t)list[b + c0 + t];
-            set_key<K>(idx, n, p, h, l);
-        }
-        kh[t] = h;
-        if (K > 4) kl[t] = l;
-        kp[t] = p;
-    }
-    __syncthreads();
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = threadIdx.x; t < P; t += kSortThreads) {
-                const int o = t ^ stride;
-                if (o > t) {
-                    const bool up = (t & size) == 0;
-                    const uint64_t th = kh[t], oh = kh[o];
-                    const uint32_t tp = kp[t], op = kp[o];
-                    const uint64_t tl = K > 4 ? kl[t] : 0, ol = K > 4 ? kl[o] : 0;
-                    if (key_less(oh, ol, op, th, tl, tp) == up) {
-                        kh[t] = oh;
-                        kh[o] = th;
-                        kp[t] = op;
-                        kp[o] = tp;
-                        if (K > 4) {
-                            kl[t] = ol;
-                            kl[o] = tl;
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int t = threadIdx.x; t < c; t += kSortThreads) list[b + c0 + t] = (int32_t)kp[t];
-    __syncthreads();
+        const int c = min(call - c0, MISSLAM_MAX_LIST);
+        int32_t *lst = list + b + c0;
+        if (c <= kSortThreads) sort_piece<K, 1>(idx, n, lst, c, kh, kl, kp);
+        else if (c <= 2 * kSortThreads) sort_piece<K, 2>(idx, n, lst, c, kh, kl, kp);
+        else if (c <= 4 * kSortThreads) sort_piece<K, 4>(idx, n, lst, c, kh, kl, kp);
+        else sort_piece<K, 8>(idx, n, lst, c, kh, kl, kp);
+        __syncthreads();
     }
     if (call <= MISSLAM_MAX_LIST) return;
     // pairwise merges of the sorted pieces, list -> tmp -> list ...
