@@ -388,7 +388,7 @@ def batch_bench(M, _lib, args, count=16):
         res[name] = {"ms_per_batch_frame": round(1000 * dt, 4), "gn_iters_per_s": round(count * G / dt, 1)}
     out = {"workload": f"{count} uneven problems, {n_tot} points and {m_tot} nodes in all, {G} GN x "
                        f"{probs[0]['params'].pcg_iters} PCG each; a step registers every problem once",
-           "solve_tile_rows": bt.tile, **res,
+           "solve_tile_rows": bt.tile, "asm_waves_per_row": bt.asm_waves, "tile_source": bt.tile_source, **res,
            "speedup": round(res["single_calls"]["ms_per_batch_frame"] / res["batched_graph"]["ms_per_batch_frame"], 3)}
     bt.close()
     return out

@@ -154,6 +154,8 @@ typedef struct {
     int32_t sync_spin_limit;   /* polls of one wait in the one-launch solves before they give up
                                   (MISSLAM_FLAG_SYNC_TIMEOUT, the step discarded); 0: 262144 */
     int32_t solve_form;        /* MISSLAM_SOLVE_*: recurrence of the one-launch solve */
+    int32_t asm_waves;         /* assembly tile: waves per node row, 1 or 2; 0: 2 (a batch created with
+                                  rows_per_wg 0 times both) */
 } misslam_params;
 
 /* one entry per Gauss-Newton iteration, plus a final entry at the returned parameters (device) */
@@ -553,6 +555,9 @@ misslam_status misslam_grow_color(misslam_points *points, misslam_nodes *nodes, 
  *   as misslam_gn_register; MISSLAM_EUNSUPPORTED if the solves of the batch
  *   cannot all be resident at once with any tile.
  * misslam_batch_tile: the rows per workgroup in use (0 before the first call).
+ * misslam_batch_asm_waves: the assembly tile in use, waves per node row (0
+ *   before the first call).  With rows_per_wg 0 and params->asm_waves 0 the
+ *   first call times both tiles with every solve tile.
  */
 typedef struct {
     misslam_points points;
@@ -571,6 +576,7 @@ misslam_status misslam_batch_create(const misslam_problem *problems, int32_t cou
 size_t misslam_batch_workspace_bytes(const misslam_batch *batch);
 misslam_status misslam_batch_register(misslam_batch *batch, void *ws, size_t ws_bytes, void *stream);
 int32_t misslam_batch_tile(const misslam_batch *batch);
+int32_t misslam_batch_asm_waves(const misslam_batch *batch);
 void misslam_batch_destroy(misslam_batch *batch);
 
 /* ------------------------------------------------------------------ profiling */

@@ -60,7 +60,7 @@ class Params(ctypes.Structure):
                 ("gn_iters", ctypes.c_int32), ("pcg_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("refine_steps", ctypes.c_int32), ("reject_threshold", ctypes.c_float),
                 ("solve_launch", ctypes.c_int32), ("sync_spin_limit", ctypes.c_int32),
-                ("solve_form", ctypes.c_int32)]
+                ("solve_form", ctypes.c_int32), ("asm_waves", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -144,6 +144,7 @@ SIGNATURES = {
     "misslam_batch_workspace_bytes": (ctypes.c_size_t, [vp]),
     "misslam_batch_register": (st, [vp, vp, ctypes.c_size_t, vp]),
     "misslam_batch_tile": (ctypes.c_int32, [vp]),
+    "misslam_batch_asm_waves": (ctypes.c_int32, [vp]),
     "misslam_batch_destroy": (None, [vp]),
     "misslam_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "misslam_profile_get": (st, [ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int64)]),

@@ -225,7 +225,8 @@ bool valid_params(const misslam_params *p) {
            p->precision >= MISSLAM_PREC_FP32 && p->precision <= MISSLAM_PREC_FP16 && p->refine_steps >= 0 &&
            (p->solve_launch == MISSLAM_LAUNCH_PLAIN || p->solve_launch == MISSLAM_LAUNCH_COOPERATIVE ||
             p->solve_launch == MISSLAM_LAUNCH_KERNELS) &&
-           p->sync_spin_limit >= 0 && (p->solve_form == MISSLAM_SOLVE_PIPELINED || p->solve_form == MISSLAM_SOLVE_TEXTBOOK);
+           p->sync_spin_limit >= 0 && (p->solve_form == MISSLAM_SOLVE_PIPELINED || p->solve_form == MISSLAM_SOLVE_TEXTBOOK) &&
+           p->asm_waves >= 0 && p->asm_waves <= 2;
 }
 
 bool valid_points(const misslam_points *p) {
@@ -288,6 +289,7 @@ void misslam_default_params(misslam_params *p) {
     p->solve_launch = MISSLAM_LAUNCH_PLAIN;
     p->sync_spin_limit = 0;
     p->solve_form = MISSLAM_SOLVE_TEXTBOOK;
+    p->asm_waves = 0;
 }
 
 const char *misslam_status_string(int32_t s) {
@@ -426,6 +428,7 @@ static msl::StepArgs step_args(const misslam_points *points, const misslam_nodes
     a.corr_in = nullptr;
     a.minv = nullptr;
     a.flags = nullptr;
+    a.asm_waves = params->asm_waves == 1 ? 1 : 2;
     return a;
 }
 
@@ -1064,6 +1067,7 @@ struct misslam_batch {
     int count = 0;
     int req_rows = 0;          // 0: tune on the first call
     int rows = 0;              // tile in use
+    int waves = 0;             // assembly tile in use (waves per node row)
     msl::BatchItem *d_items = nullptr;
     float *d_backup = nullptr; // params of every problem (tuning restores them)
     std::vector<size_t> param_off;
@@ -1077,6 +1081,7 @@ struct misslam_batch {
     hipGraphExec_t exec = nullptr;
     void *exec_ws = nullptr;
     int exec_rows = 0;
+    int exec_waves = 0;
 };
 
 namespace {
@@ -1169,7 +1174,7 @@ hipError_t batch_enqueue(misslam_batch *b, hipStream_t st, bool cooperative) {
     if (e == hipSuccess && G > 0) e = msl::launch_list_pack_batched(d, count, k, b->total_rows, st);
     for (int it = 0; it < G && e == hipSuccess; ++it) {
         e = msl::launch_point_pass_batched(d, count, k, b->total_pp, it, st);
-        if (e == hipSuccess) e = msl::launch_assemble_batched(d, count, k, b->total_rows, it, st);
+        if (e == hipSuccess) e = msl::launch_assemble_batched(d, count, k, b->total_rows, it, b->waves, st);
         if (e == hipSuccess) e = msl::launch_energy_report_batched(d, count, it, b->bar,
                                                                    std::min(msl::MSL_WG_WORDS * b->total_wgs, msl::MSL_BAR_WORDS), st);
         bool used = false;
@@ -1275,34 +1280,45 @@ size_t misslam_batch_workspace_bytes(const misslam_batch *batch) { return batch 
 
 int32_t misslam_batch_tile(const misslam_batch *batch) { return batch ? batch->rows : 0; }
 
+int32_t misslam_batch_asm_waves(const misslam_batch *batch) { return batch && batch->rows ? batch->waves : 0; }
+
 misslam_status misslam_batch_register(misslam_batch *b, void *ws, size_t ws_bytes, void *stream) {
     if (!b || !ws) return MISSLAM_EINVAL;
     if (ws_bytes < batch_bytes(b)) return MISSLAM_EWORKSPACE;
     const hipStream_t st = stream_of(stream);
     hipError_t e = hipSuccess;
     if (b->rows == 0) {
+        const int req_waves = b->params.asm_waves;
         if (b->req_rows > 0) {
             int wgs = 0;
             for (const auto &p : b->probs) wgs += (p.nodes.m + b->req_rows - 1) / b->req_rows;
             if (!msl::pcg_batched_fits(wgs, b->params.solve_form == MISSLAM_SOLVE_TEXTBOOK))
                 return MISSLAM_EUNSUPPORTED;
             b->rows = b->req_rows;
+            b->waves = req_waves == 1 ? 1 : 2;
         } else {
-            // the tile: rows per solve workgroup, timed on this batch
+            // the tiles: rows per solve workgroup and waves per assembly row, timed on this batch
             e = batch_save_params(b, st, false);
             float best = -1.f;
-            int best_rows = 0;
+            int best_rows = 0, best_waves = 0;
             const int cand[4] = {21, 16, 12, 8};
-            for (int c = 0; c < 4 && e == hipSuccess; ++c) {
-                const float ms = batch_try(b, ws, cand[c], st);
-                if (ms > 0.f && (best < 0.f || ms < best)) {
-                    best = ms;
-                    best_rows = cand[c];
+            const int wcand[2] = {2, 1};
+            for (int w = 0; w < 2 && e == hipSuccess; ++w) {
+                if (req_waves != 0 && wcand[w] != req_waves) continue;
+                b->waves = wcand[w];
+                for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+                    const float ms = batch_try(b, ws, cand[c], st);
+                    if (ms > 0.f && (best < 0.f || ms < best)) {
+                        best = ms;
+                        best_rows = cand[c];
+                        best_waves = wcand[w];
+                    }
                 }
             }
             if (e != hipSuccess) return hip_fail(e);
             if (best_rows == 0) return MISSLAM_EUNSUPPORTED;
             b->rows = best_rows;
+            b->waves = best_waves;
         }
     }
     if (b->items_ws != ws || b->items_rows != b->rows) {
@@ -1310,7 +1326,7 @@ misslam_status misslam_batch_register(misslam_batch *b, void *ws, size_t ws_byte
         if (e == hipSuccess) e = batch_upload(b, ws, b->rows);
         if (e != hipSuccess) return hip_fail(e);
     }
-    if (!b->exec || b->exec_ws != ws || b->exec_rows != b->rows) {
+    if (!b->exec || b->exec_ws != ws || b->exec_rows != b->rows || b->exec_waves != b->waves) {
         if (b->exec) {
             (void)hipGraphExecDestroy(b->exec);
             b->exec = nullptr;
@@ -1331,6 +1347,7 @@ misslam_status misslam_batch_register(misslam_batch *b, void *ws, size_t ws_byte
         }
         b->exec_ws = ws;
         b->exec_rows = b->rows;
+        b->exec_waves = b->waves;
     }
     e = hipGraphLaunch(b->exec, st);
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);

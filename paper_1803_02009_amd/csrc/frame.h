@@ -101,6 +101,7 @@ struct StepArgs {
     int32_t *flags;    // report flags (NONSPD_BLOCK) when minv is set
     const float *lambda_dev = nullptr;   // optional device damping, read in place of lambda
     const float *pose_dev = nullptr;     // optional device pose (R row-major, T), read in place of pose
+    int asm_waves = 2;                   // assembly tile: waves per node row, 1 or 2
 };
 
 __device__ __forceinline__ Pose step_pose(const StepArgs &a) {
@@ -372,7 +373,8 @@ hipError_t launch_normal_map_batched(const BatchItem *items, int count, int tota
 hipError_t launch_point_pass_batched(const BatchItem *items, int count, int k, int64_t total_blocks, int it,
                                      hipStream_t st);
 hipError_t launch_list_pack_batched(const BatchItem *items, int count, int k, int total_rows, hipStream_t st);
-hipError_t launch_assemble_batched(const BatchItem *items, int count, int k, int total_rows, int it, hipStream_t st);
+hipError_t launch_assemble_batched(const BatchItem *items, int count, int k, int total_rows, int it, int waves,
+                                   hipStream_t st);
 hipError_t launch_energy_report_batched(const BatchItem *items, int count, int it, unsigned *zero_words,
                                         int zero_count, hipStream_t st);
 hipError_t launch_node_energy_batched(const BatchItem *items, int count, int total_blocks, hipStream_t st);

@@ -183,13 +183,12 @@ __device__ __forceinline__ int na_index(int a, int b) {  // a, b in 0..2
     return 3 * lo - (lo * (lo - 1)) / 2 + (hi - lo);
 }
 
-constexpr int kAsmThreads = 128;
-constexpr int kAsmWaves = kAsmThreads / kWave;
 constexpr int kBatch = 64;
-// Statistic slots of each wave of a row.  A row with more column slots accumulates on its first wave alone,
-// over the slots of all waves.
-constexpr int kSlotsPerWave = 18;
-static_assert(kAsmWaves * kSlotsPerWave >= MISSLAM_MAX_ROW, "a row's slots must fit the statistic area");
+// Statistic slots of a row, shared out among its W waves (one or two, the assembly tile): each wave has
+// kAsmSlots / W of its own.  A row with more column slots than a wave holds accumulates on its first wave
+// alone, over the slots of all waves.
+constexpr int kAsmSlots = 36;
+static_assert(kAsmSlots >= MISSLAM_MAX_ROW, "a row's slots must fit the statistic area");
 // Staged entries per statistic row: the batch plus the four-entry read-ahead; 69 floats keep the rows of the
 // staged products (read by lanes with different statistic entries) in distinct banks.
 constexpr int kStage = kBatch + 5;
@@ -223,14 +222,14 @@ struct AsmStage {
     uint32_t key[kBatch][2];
 };
 
-template <int K>
+template <int K, int W>
 struct AsmShared {
-    float accS[kAsmWaves * kSlotsPerWave][60];   // statistic per slot; wave w's slots start at w kSlotsPerWave
+    float accS[kAsmSlots][60];   // statistic per slot; wave w's slots start at w kAsmSlots / W
     union {
-        AsmStage<K> st[kAsmWaves];
+        AsmStage<K> st[W];
         // wave w's data gradient (gw[w][0..11]), over its own staging once its batches are done
-        double gw[kAsmWaves][sizeof(AsmStage<K>) / sizeof(double)];
-        RowFin<kAsmThreads> fin;
+        double gw[W][sizeof(AsmStage<K>) / sizeof(double)];
+        RowFin<kWave * W> fin;
     };
     RowNode rn;
 };
@@ -302,7 +301,7 @@ template <int NT, class DataFn>
 __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratch &s, RowNode &rn, RowFin<NT> &fin,
                                              int j, int rb, int nslots, double e_reg, float lamf, DataFn data,
                                              float *rr_out) {
-    static_assert(NT >= 2 * kWave, "the last phase runs the preconditioner and the gradient on two waves");
+    static_assert(NT % kWave == 0, "whole waves");
     static_assert(MISSLAM_MAX_ROW <= kWave, "one lane per slot");
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
@@ -393,13 +392,16 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
         }
     }
     __syncthreads();
+    // the block-Jacobi preconditioner of this row on wave 0 and the gradient on the last wave (with one wave,
+    // one after the other)
     if (wave == 0) {
-        // block-Jacobi preconditioner of this row: (H_jj + lambda I)^-1 in float64 on lanes 0-11
+        // (H_jj + lambda I)^-1 in float64 on lanes 0-11
         if (a.minv) {
             const bool ok = gj_inverse_lanes(fin.Hd, a.minv + (size_t)j * 144);
             if (!ok && lane == 0) atomicOr(a.flags, MISSLAM_FLAG_NONSPD_BLOCK);
         }
-    } else if (wave == 1 && lane < 12) {
+    }
+    if (wave == NT / kWave - 1 && lane < 12) {
         const int c = lane / 3, aa = lane % 3;
         double reg = 0.0;
         for (int t0 = 0; t0 < nslots; t0 += kChunk) {
@@ -530,19 +532,21 @@ __device__ __forceinline__ void entry_load(const StepArgs &a, const StepScratch 
     r.k1 = a.g.list_key[2 * (size_t)le + 1];
 }
 
-// One workgroup per node row j (rows spread so each XCD owns a contiguous band).
-// Two waves split the row's point list and run independently: each stages 64
-// list entries at a time (lane = entry) while the next 64 are already being
-// fetched, then accumulates the 60 statistic entries (lane = entry of the
-// statistic) for the k node pairs of each run of equal kNN sets, into slots of
-// its own.  The LDS of a row stays under 23 KB, so seven rows fit a CU and a
-// 1600-node graph is resident at once.  Then the
+// One workgroup of W waves (the assembly tile: one or two) per node row j (rows
+// spread so each XCD owns a contiguous band).  The waves split the row's point
+// list and run independently: each stages 64 list entries at a time (lane =
+// entry) while the next 64 are already being fetched, then accumulates the 60
+// statistic entries (lane = entry of the statistic) for the k node pairs of
+// each run of equal kNN sets, into slots of its own.  With two waves the LDS of
+// a row stays under 23 KB, so seven rows fit a CU and a 1600-node graph is
+// resident at once.  Then the
 // node terms (Eqs.(5)-(6)) are added, the row's blocks and gradient are
 // written, and the damped diagonal block is inverted for the block-Jacobi
 // preconditioner.  Fixed summation order throughout: bitwise reproducible.
-template <int K>
+template <int K, int W>
 __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const StepScratch &s, int j) {
-    __shared__ AsmShared<K> sh;
+    constexpr int kAsmThreads = kWave * W, kAsmWaves = W, kSlotsPerWave = kAsmSlots / W;
+    __shared__ AsmShared<K, W> sh;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid % kWave;
     const int64_t n = a.pts.n;
@@ -770,7 +774,7 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
         for (int q = 0; q < 12; ++q) sh.gw[wave][q] = gacc[q];
     }
     __syncthreads();
-    if (split) {
+    if (kAsmWaves > 1 && split) {
         for (int t = tid; t < nslots * 60; t += kAsmThreads) {
             const int sl = t / 60, en = t - sl * 60;
             float v = sh.accS[sl][en];
@@ -799,14 +803,14 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
     row_finalize<kAsmThreads>(a, s, sh.rn, sh.fin, j, rb, nslots, e_reg, lamf, data, nullptr);
 }
 
-template <int K>
-__global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_eu(4)))
+template <int K, int W>
+__global__ void __launch_bounds__(kWave * W) __attribute__((amdgpu_waves_per_eu(4)))
 assemble_rows_kernel(StepArgs a, StepScratch s) {
     const int m = a.nd.m;
     const int per = (int)((m + 7) / 8);
     const int j = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (j >= m) return;
-    assemble_rows_body<K>(a, s, j);
+    assemble_rows_body<K, W>(a, s, j);
 }
 
 
@@ -1430,9 +1434,13 @@ hipError_t launch_list_pack(const StepArgs &a, const StepScratch &s, hipStream_t
 hipError_t launch_assemble(const StepArgs &a, const StepScratch &s, hipStream_t st) {
     const int m = a.nd.m;
     const unsigned rows = 8 * (unsigned)((m + 7) / 8);
+    const bool one = a.asm_waves == 1;
     switch (a.g.k) {
-#define MSL_AS_CASE(KK)                                                                                     \
-    case KK: hipLaunchKernelGGL((assemble_rows_kernel<KK>), dim3(rows), dim3(kAsmThreads), 0, st, a, s); break;
+#define MSL_AS_CASE(KK)                                                                                       \
+    case KK:                                                                                                  \
+        if (one) hipLaunchKernelGGL((assemble_rows_kernel<KK, 1>), dim3(rows), dim3(kWave), 0, st, a, s);     \
+        else hipLaunchKernelGGL((assemble_rows_kernel<KK, 2>), dim3(rows), dim3(2 * kWave), 0, st, a, s);     \
+        break;
         MSL_AS_CASE(1) MSL_AS_CASE(2) MSL_AS_CASE(3) MSL_AS_CASE(4)
         MSL_AS_CASE(5) MSL_AS_CASE(6) MSL_AS_CASE(7) MSL_AS_CASE(8)
 #undef MSL_AS_CASE
@@ -1480,14 +1488,13 @@ __global__ void __launch_bounds__(256) list_pack_batched_kernel(const BatchItem 
     list_pack_body<K>(it.a, it.s, (int)blockIdx.x - it.row0);
 }
 
-template <int K>
-__global__ void __launch_bounds__(kAsmThreads) __attribute__((amdgpu_waves_per_eu(4)))
-assemble_batched_kernel(const BatchItem *__restrict__ items, int count,
-                                                                       int gi) {
+template <int K, int W>
+__global__ void __launch_bounds__(kWave * W) __attribute__((amdgpu_waves_per_eu(4)))
+assemble_batched_kernel(const BatchItem *__restrict__ items, int count, int gi) {
     const BatchItem &it = items[batch_of(items, count, blockIdx.x, 1)];
     StepArgs a = it.a;
     a.flags = &it.rep[gi].flags;
-    assemble_rows_body<K>(a, it.s, (int)blockIdx.x - it.row0);
+    assemble_rows_body<K, W>(a, it.s, (int)blockIdx.x - it.row0);
 }
 
 __global__ void __launch_bounds__(256) node_energy_batched_kernel(const BatchItem *__restrict__ items, int count) {
@@ -1537,13 +1544,19 @@ hipError_t launch_list_pack_batched(const BatchItem *items, int count, int k, in
     return hipGetLastError();
 }
 
-hipError_t launch_assemble_batched(const BatchItem *items, int count, int k, int total_rows, int it, hipStream_t st) {
+hipError_t launch_assemble_batched(const BatchItem *items, int count, int k, int total_rows, int it, int waves,
+                                   hipStream_t st) {
     if (total_rows <= 0) return hipSuccess;
+    const bool one = waves == 1;
     switch (k) {
-#define MSL_AB_CASE(KK)                                                                                        \
-    case KK:                                                                                                   \
-        hipLaunchKernelGGL((assemble_batched_kernel<KK>), dim3(total_rows), dim3(kAsmThreads), 0, st, items, \
-                           count, it);                                                                         \
+#define MSL_AB_CASE(KK)                                                                                          \
+    case KK:                                                                                                     \
+        if (one)                                                                                                 \
+            hipLaunchKernelGGL((assemble_batched_kernel<KK, 1>), dim3(total_rows), dim3(kWave), 0, st, items,    \
+                               count, it);                                                                       \
+        else                                                                                                     \
+            hipLaunchKernelGGL((assemble_batched_kernel<KK, 2>), dim3(total_rows), dim3(2 * kWave), 0, st, items,\
+                               count, it);                                                                       \
         break;
         MSL_AB_CASE(1) MSL_AB_CASE(2) MSL_AB_CASE(3) MSL_AB_CASE(4)
         MSL_AB_CASE(5) MSL_AB_CASE(6) MSL_AB_CASE(7) MSL_AB_CASE(8)

@@ -10,7 +10,9 @@ method runs in the library's gfx950 kernels.  Layouts:
 import atexit
 import ctypes
 import dataclasses
+import json
 import math
+import os
 import sys
 import weakref
 
@@ -54,12 +56,13 @@ class Params:
     solve_launch: int = _lib.LAUNCH_PLAIN
     sync_spin_limit: int = 0
     solve_form: int = _lib.SOLVE_TEXTBOOK
+    asm_waves: int = 0
 
     def c(self):
         return _lib.Params(self.k, self.weight_kind, self.sigma, self.w_rot, self.w_reg, self.w_data, self.eps_d,
                            self.cos_eps_n, self.lam, self.gn_iters, self.pcg_iters, self.precision,
                            self.refine_steps, self.reject_threshold, self.solve_launch,
-                           self.sync_spin_limit, self.solve_form)
+                           self.sync_spin_limit, self.solve_form, self.asm_waves)
 
 
 def camera(width, height, fx, fy, cx, cy):
@@ -468,6 +471,45 @@ def _close_open_batches():
         b.close()
 
 
+def tile_cache_path():
+    """The JSON file of tuned batch tiles: $MISSLAM_TILE_CACHE, else ~/.cache/misslam/tiles.json."""
+    return os.environ.get("MISSLAM_TILE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "misslam",
+                                                                 "tiles.json")
+
+
+def _bucket(v):
+    return 1 << max(0, math.ceil(math.log2(max(int(v), 1))))
+
+
+def tile_key(problems, params):
+    """Cache key of a batch: point and node totals rounded up to powers of two, the largest frame, the
+    precision, and the settings the tiles depend on (k, PCG iterations, recurrence, problem count)."""
+    n = sum(int(pr["points"].shape[1]) for pr in problems)
+    m = sum(int(pr["nodes"].shape[1]) for pr in problems)
+    w, h = max((pr["cam"].width * pr["cam"].height, pr["cam"].width, pr["cam"].height) for pr in problems)[1:]
+    return (f"N{_bucket(n)}-m{_bucket(m)}-{w}x{h}-prec{params.precision}-k{params.k}-pcg{params.pcg_iters}"
+            f"-form{params.solve_form}-count{len(problems)}")
+
+
+def _read_tile_cache(path):
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _write_tile_cache(path, key, entry):
+    d = _read_tile_cache(path)
+    d[key] = entry
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
 class Batch:
     """Uneven problems registered together (misslam_batch_*): one launch per
     phase over every problem, the frame captured once into a hipGraph.
@@ -475,13 +517,30 @@ class Batch:
     problems: list of dicts with keys points (6, N), nodes (3, m), x (m, 12),
     graph (Graph), depth (H, W), cam, pose.  Tensors must stay alive and keep
     their addresses while the batch is used.  rows_per_wg: solve tile (1..21)
-    or 0 to time the candidates on the first call.
+    or 0 to choose the tiles (solve rows per workgroup and, with
+    params.asm_waves 0, assembly waves per node row).  Chosen tiles come from
+    the tile cache (tile_cache_path()) when it holds this batch's key, else the
+    first register() times the candidates and stores its choice there;
+    tile_cache=False skips the cache.  tile_source says which: "given",
+    "cache" or "tuned".
     """
 
-    def __init__(self, problems, params, rows_per_wg=0):
-        self.params = params
+    def __init__(self, problems, params, rows_per_wg=0, tile_cache=True):
         self.keep = []
         _open_batches.add(self)
+        self.tile_source = "given" if rows_per_wg else "tuned"
+        self._store_key = None
+        if rows_per_wg == 0 and params.asm_waves == 0 and tile_cache:
+            key = tile_key(problems, params)
+            hit = _read_tile_cache(tile_cache_path()).get(key)
+            if (isinstance(hit, dict) and hit.get("rows_per_wg") in range(1, 22)
+                    and hit.get("asm_waves") in (1, 2)):
+                rows_per_wg = int(hit["rows_per_wg"])
+                params = dataclasses.replace(params, asm_waves=int(hit["asm_waves"]))
+                self.tile_source = "cache"
+            else:
+                self._store_key = key
+        self.params = params
         self.reports = []
         arr = (_lib.Problem * len(problems))()
         for i, pr in enumerate(problems):
@@ -502,11 +561,22 @@ class Batch:
     def register(self):
         check("misslam_batch_register", load().misslam_batch_register(self.h, _ptr(self.ws),
                                                                       ctypes.c_size_t(self.ws.numel()), _stream()))
+        if self._store_key is not None:   # the first call chose the tiles: keep them for the next process
+            try:
+                _write_tile_cache(tile_cache_path(), self._store_key,
+                                  {"rows_per_wg": self.tile, "asm_waves": self.asm_waves})
+            except OSError:
+                pass
+            self._store_key = None
         return self.reports
 
     @property
     def tile(self):
         return int(load().misslam_batch_tile(self.h))
+
+    @property
+    def asm_waves(self):
+        return int(load().misslam_batch_asm_waves(self.h))
 
     def close(self):
         if getattr(self, "h", None):

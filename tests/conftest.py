@@ -20,6 +20,18 @@ def gpu_available():
         return False
 
 
+@pytest.fixture(scope="session", autouse=True)
+def _private_tile_cache(tmp_path_factory):
+    """Batches created with tuned tiles read and write a cache of this session only."""
+    old = os.environ.get("MISSLAM_TILE_CACHE")
+    os.environ["MISSLAM_TILE_CACHE"] = str(tmp_path_factory.mktemp("tiles") / "tiles.json")
+    yield
+    if old is None:
+        os.environ.pop("MISSLAM_TILE_CACHE", None)
+    else:
+        os.environ["MISSLAM_TILE_CACHE"] = old
+
+
 @pytest.fixture(scope="session")
 def lib():
     """The C-ABI library through its Python binding; GPU tests only."""

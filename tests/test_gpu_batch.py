@@ -119,6 +119,58 @@ def test_batch_autotuned_tile(problems):
         assert np.array_equal(r1[i]["n_valid"][:1], reps[i]["n_valid"][:1])
 
 
+def test_assembly_tile_one_wave(problems):
+    """One wave per assembly row (params.asm_waves = 1): a batch equals single calls with the same tile bit for
+    bit, and both agree with the two-wave rows to the float32 floor of a 10 x 10 registration (1-4e-6 in
+    parameters, from a float32 emulation of the oracle), gated at the 1e-5 parity bar: the statistic's partial
+    sums are added in another order."""
+    import dataclasses
+    p1 = dataclasses.replace(problems[0].params, asm_waves=1)
+    xs1, reps1 = _single(problems, params=p1)
+    outs, _ = _batch(problems, SOLVE_ROWS, calls=1, params=p1)
+    xb, rb = outs[0]
+    xs2, _ = _single(problems)
+    for i in range(len(problems)):
+        assert np.array_equal(xb[i].view(np.uint32), xs1[i].view(np.uint32)), i
+        assert rb[i].tobytes() == reps1[i].tobytes(), i
+        assert np.all(rb[i]["flags"] == 0), i
+        print("problem", IDS[i], "one vs two waves per row: x rel", rel_err(xs1[i], xs2[i]))
+        assert rel_err(xs1[i], xs2[i]) < 1e-5, i
+
+
+def test_tile_cache_round_trip(problems, tmp_path, monkeypatch):
+    """Tuned tiles are stored under the batch's key; a new batch of the same problems takes them from the cache
+    without timing and gives the same bits."""
+    import json
+    M = problems[0].M
+    path = tmp_path / "tiles.json"
+    monkeypatch.setenv("MISSLAM_TILE_CACHE", str(path))
+    items = [dict(points=s.pts, nodes=s.nodes, x=s.M.identity_params(s.m), graph=s.graph, depth=s.depth, cam=s.cam,
+                  pose=s.pose) for s in problems]
+    params = problems[0].params
+    bt = M.Batch(items, params, rows_per_wg=0)
+    assert bt.tile_source == "tuned"
+    bt.register()
+    torch.cuda.synchronize()
+    tiles = (bt.tile, bt.asm_waves)
+    x1 = [it["x"].cpu().numpy() for it in items]
+    bt.close()
+    assert tiles[0] in (21, 16, 12, 8) and tiles[1] in (1, 2)
+    d = json.loads(path.read_text())
+    assert d[M.tile_key(items, params)] == {"rows_per_wg": tiles[0], "asm_waves": tiles[1]}
+    for it in items:
+        it["x"].copy_(M.identity_params(it["x"].shape[0]))
+    bt2 = M.Batch(items, params, rows_per_wg=0)
+    assert bt2.tile_source == "cache"
+    bt2.register()
+    torch.cuda.synchronize()
+    assert (bt2.tile, bt2.asm_waves) == tiles
+    for i, it in enumerate(items):
+        assert np.array_equal(it["x"].cpu().numpy().view(np.uint32), x1[i].view(np.uint32)), i
+    bt2.close()
+    print("tuned tiles", tiles, "key", M.tile_key(items, params))
+
+
 def test_batch_rejects_per_phase_launches(problems):
     """The batch always runs its solve in one launch: the per-phase launch form is refused at creation."""
     import dataclasses
