@@ -1309,17 +1309,48 @@ __device__ __forceinline__ void energy_report_body(const double *__restrict__ pt
     if (zero_words)   // the next solve's sync area
         for (int t = threadIdx.x; t < zero_count / 4; t += 256)
             reinterpret_cast<uint4 *>(zero_words)[t] = make_uint4(0u, 0u, 0u, 0u);
+    // thread t adds entries t, t + 256, ... in order; the loads of eight entries are issued before their adds
+    constexpr int U = 8;
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int t = threadIdx.x; t < npb; t += 256) {
-        v[0] += pt_part[3 * t];
-        v[1] += pt_part[3 * t + 1];
-        v[2] += pt_part[3 * t + 2];
+    for (int t0 = threadIdx.x; t0 < npb; t0 += U * 256) {
+        double a[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = min(t0 + 256 * u, npb - 1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a[u][c] = pt_part[3 * t + c];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t0 + 256 * u < npb) {
+                v[0] += a[u][0];
+                v[1] += a[u][1];
+                v[2] += a[u][2];
+            }
     }
-    for (int t = threadIdx.x; t < m; t += 256) {
-        v[3] += node_part[2 * t];
-        v[4] += node_part[2 * t + 1];
+    for (int t0 = threadIdx.x; t0 < m; t0 += U * 256) {
+        double a[U][2];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = min(t0 + 256 * u, m - 1);
+            a[u][0] = node_part[2 * t];
+            a[u][1] = node_part[2 * t + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t0 + 256 * u < m) {
+                v[3] += a[u][0];
+                v[4] += a[u][1];
+            }
     }
-    for (int t = threadIdx.x; t < kp_count; t += 256) v[5] += kp_energy[t];
+    for (int t0 = threadIdx.x; t0 < kp_count; t0 += U * 256) {
+        double a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = kp_energy[min(t0 + 256 * u, kp_count - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t0 + 256 * u < kp_count) v[5] += a[u];
+    }
     // wave butterflies, then the four waves in order: a fixed summation order
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
 #pragma unroll
