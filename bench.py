@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP32_VALU_PEAK = 157.3       # TFLOP/s vendor figure
+MFMA_BF16_PEAK = 2500.0      # TFLOP/s, dense bf16 matrix cores, vendor figure
 
 # source files each timed kernel is compiled from (its counter figures are void once any of them changes)
 KERNEL_SOURCES = {
@@ -224,6 +225,7 @@ def main():
     # accuracy against the stored float64 oracle result of the same frame
     acc = accuracy(state, rep, os.path.join(ROOT, "tests", "golden", f"{args.config}_oracle.npz"))
     hbm = copy_bandwidth(torch)
+    mfma = mfma_peak(torch, lib)
     cold = None if args.no_cold else cold_frames(torch, frame, args.steps)
 
     # the low-precision form on the same frame: without refinement (the float64
@@ -259,6 +261,7 @@ def main():
         "roofline": roofline,
         "roofline_other": [v for k, v in lines.items() if k != dominant],
         "hbm_copy": hbm,
+        "mfma_bf16_probe": mfma,
     }
     if cold is not None:
         out["cold_cache"] = cold
@@ -294,6 +297,28 @@ def copy_bandwidth(torch, mib=256, reps=10):
     gbs = 2 * src.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src, dst
     return {"copy_mib": mib, "achieved_gbs": round(gbs, 1), "of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def mfma_peak(torch, lib, iters=20000):
+    """Achievable dense bf16 matrix-core rate: four workgroups of four waves per CU, each wave running eight
+    independent chains of 16x16x32 multiply-adds (misslam_probe_mfma_bf16), timed with events."""
+    import ctypes
+    blocks = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    sink = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    flops = ctypes.c_int64()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for _ in range(2):
+        lib.misslam_probe_mfma_bf16(iters // 10, blocks, ctypes.c_void_p(sink.data_ptr()), ctypes.byref(flops), stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    st = lib.misslam_probe_mfma_bf16(iters, blocks, ctypes.c_void_p(sink.data_ptr()), ctypes.byref(flops), stream)
+    e1.record()
+    torch.cuda.synchronize()
+    if st != 0:
+        return None
+    tflops = flops.value / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    return {"achieved_tflops": round(tflops, 1), "of_peak": round(tflops / MFMA_BF16_PEAK, 4),
+            "peak_tflops": MFMA_BF16_PEAK, "workgroups": blocks}
 
 
 def cold_frames(torch, frame, steps, flush_mib=512):

@@ -595,6 +595,17 @@ int32_t misslam_profile_enable(int32_t on);
 misslam_status misslam_profile_get(const char *phase, double *total_ms, int64_t *launches);
 void misslam_profile_reset(void);
 
+/*
+ * Calibration for measurement, not part of the registration: launches
+ * `blocks` workgroups of four waves, each wave running eight independent
+ * chains of `iters` bf16 16x16x32 matrix-core multiply-adds, on stream, and
+ * returns the flops that launch performs in *flops (host).  Timing the launch
+ * gives the device's achievable dense bf16 matrix-core rate.  sink (device,
+ * blocks x 256 floats) receives the accumulators.  MISSLAM_EINVAL for iters or
+ * blocks < 1 or a NULL pointer.
+ */
+misslam_status misslam_probe_mfma_bf16(int32_t iters, int32_t blocks, float *sink, int64_t *flops, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -145,6 +145,8 @@ SIGNATURES = {
     "misslam_batch_register": (st, [vp, vp, ctypes.c_size_t, vp]),
     "misslam_batch_tile": (ctypes.c_int32, [vp]),
     "misslam_batch_asm_waves": (ctypes.c_int32, [vp]),
+    "misslam_probe_mfma_bf16": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_int64),
+                                                 vp]),
     "misslam_batch_destroy": (None, [vp]),
     "misslam_profile_enable": (ctypes.c_int32, [ctypes.c_int32]),
     "misslam_profile_get": (st, [ctypes.c_char_p, P(ctypes.c_double), P(ctypes.c_int64)]),

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmisslam.so")
-SOURCES = ["api.hip", "k_frame.hip", "k_step.hip", "k_pcg.hip", "k_fuse.hip", "k_grow.hip", "k_corr.hip", "k_lm.hip", "k_pose.hip"]
+SOURCES = ["api.hip", "k_frame.hip", "k_step.hip", "k_pcg.hip", "k_fuse.hip", "k_grow.hip", "k_corr.hip", "k_lm.hip", "k_pose.hip",
+           "k_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
