@@ -64,8 +64,7 @@ typedef enum {
                                         15 us more per solve */
 #define MISSLAM_LAUNCH_KERNELS 2     /* no one-launch solve: one launch per PCG phase, nothing depends on
                                         residency (the path taken anyway when the grid does not fit); the
-                                        same results to rounding (bitwise for the joint pose form); not for
-                                        batches (MISSLAM_EUNSUPPORTED) */
+                                        same results to rounding; not for batches (MISSLAM_EUNSUPPORTED) */
 
 /* The recurrence of the one-launch solve (fixed pose; the joint pose form and
  * MISSLAM_LAUNCH_KERNELS always use the textbook one). */

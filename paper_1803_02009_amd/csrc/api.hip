@@ -210,7 +210,7 @@ Layout carve(void *ws, int64_t n, int32_t m, int32_t W, int32_t H, int pcg_iters
         L.joint.sys = c.take<double>(80);
         L.joint.jpart = c.take<double>((size_t)(pcg_iters + 2) * 10 * ((m + 20) / 21));
         L.joint.pst = c.take<double>((size_t)(pcg_iters + 2) * 32);
-        L.joint.jbar = c.take<unsigned long long>((size_t)32 * 1024);
+        L.joint.jbar = c.take<unsigned long long>((size_t)msl::kJointTagWords * msl::kJointMaxWgs);
     }
     L.bytes = align_up(c.off);
     return L;

@@ -322,6 +322,27 @@ __device__ __forceinline__ bool gj_inverse_block(double (*A)[12], float *out) {
     return !bad;
 }
 
+// Butterfly sums of N values over the wave (xor partners 32, 16, ..., 1): every lane gets the totals, each
+// value by the same additions in the same order as alone.  The values go stage by stage in groups of up to
+// nine, so the cross-lane reads of a group are in flight together instead of one value's at a time.
+template <int N, typename T>
+__device__ __forceinline__ void wave_sums(T (&v)[N]) {
+    constexpr int C = 9;
+#pragma unroll
+    for (int q0 = 0; q0 < N; q0 += C) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            T u[C];
+#pragma unroll
+            for (int q = 0; q < C; ++q)
+                if (q0 + q < N) u[q] = __shfl_xor(v[q0 + q], off, 64);
+#pragma unroll
+            for (int q = 0; q < C; ++q)
+                if (q0 + q < N) v[q0 + q] += u[q];
+        }
+    }
+}
+
 // The value of v on lane l (l uniform), for float64.
 __device__ __forceinline__ double readlane_f64(double v, int l) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);

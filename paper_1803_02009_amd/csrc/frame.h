@@ -20,6 +20,13 @@ struct GraphView {
 constexpr int MSL_TAG_WGS = 1024;
 constexpr int MSL_WG_WORDS = 16;
 constexpr int MSL_BAR_WORDS = MSL_WG_WORDS * MSL_TAG_WGS;
+constexpr int kJointTagWords = 16;   // 8-byte sync words per workgroup of the one-launch joint solve
+constexpr int kJointMaxWgs = 2048;   // its workgroups at most (sync area: kJointTagWords * kJointMaxWgs words)
+// 8-byte sync words the one-launch joint solve of m rows uses (at least MISSLAM_SOLVE_ROWS rows per workgroup).
+inline int joint_sync_words(int m) {
+    const int g = (m + MISSLAM_SOLVE_ROWS - 1) / MISSLAM_SOLVE_ROWS;
+    return kJointTagWords * (g < 1 ? 1 : (g > kJointMaxWgs ? kJointMaxWgs : g));
+}
 // Sync words a persistent solve of m rows uses.
 inline int msl_sync_words(int m) {
     const int g = (m + MISSLAM_SOLVE_ROWS - 1) / MISSLAM_SOLVE_ROWS;
@@ -363,6 +370,17 @@ hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks,
                                  float *params, hipStream_t st, bool *used, bool cooperative,
                                  int zeroed_words = 0, const float *lambda_dev = nullptr, unsigned spin = 0,
                                  bool textbook = false);
+// The pose columns of the joint system (pose + ED unknowns) for its one-launch solve.
+struct JointExtra {
+    const float *B = nullptr;      // the border: row 12 j + a, column k at B[j * 72 + a * 6 + k]
+    const double *sys = nullptr;   // H_pp (36), g_p (6), (H_pp + lambda I)^-1 (36)
+    double *xp_out = nullptr;      // the pose step (6), written by the first workgroup
+};
+// The joint system's one-launch solve (the tiled textbook recurrence with the pose part; base.part, x, z and the
+// system as for launch_pcg_persistent).  bar: its sync area, of which zeroed_words 8-byte words are zero.  Sets
+// *used = false and launches nothing when the grid does not fit (the per-phase joint kernels are used then).
+hipError_t launch_joint_pcg_persistent(const PcgArgs &base, const JointExtra &jx, unsigned long long *bar,
+                                       int zeroed_words, misslam_report *rep, hipStream_t st, bool *used);
 // x += dx (n entries) unless rep's flags, ORed with extra's when given (and written back into rep), carry
 // MISSLAM_FLAG_NONFINITE or MISSLAM_FLAG_SYNC_TIMEOUT: the whole step or nothing.
 hipError_t launch_step_commit(float *x, const float *dx, int n, misslam_report *rep, hipStream_t st,

@@ -357,13 +357,13 @@ __device__ __forceinline__ double ld_dev(const double *p) {
 template <int NV>
 __device__ __forceinline__ void wg_sum(double (&v)[NV], double (*lds)[kPcgThreads / kWave]) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    double t[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        double t = v[q];
+    for (int q = 0; q < NV; ++q) t[q] = v[q];
+    wave_sums(t);
+    if (lane == 0)
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-        if (lane == 0) lds[q][wave] = t;
-    }
+        for (int q = 0; q < NV; ++q) lds[q][wave] = t[q];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -569,19 +569,144 @@ __device__ __forceinline__ TileRange tile_setup(const PcgArgs &A, int rows_per_w
     return R;
 }
 
+// Joint form (pose + ED unknowns, Eq.(10)): the six pose unknowns border the
+// ED system, [[H, B], [B^T, H_pp]].  Their part of every vector (r, z, p, q, x
+// of the pose) is recomputed identically by every workgroup from the same
+// exchanged sums, so it never travels.  B^T z uses the z of the previous step,
+// so its partial sums ride in the r.z exchange (7 values) and the p.q exchange
+// stays one value: the same two exchanges per iteration as the ED-only solve.
+// Sync area: kJointTagWords 8-byte words per workgroup, the p.q value in words
+// 0-1 and the r.z, B^T z values in words 2-15 (high half | tag, low half | tag).
+constexpr int kPoseThread = kPcgThreads - 1;   // never holds an ED entry (kRowsPerBlk * 12 < kPcgThreads)
+
+template <int N>
+__device__ __forceinline__ void tagn_publish(unsigned *bar, int gid, int word0, unsigned tag, const double (&v)[N]) {
+    unsigned long long *w = tag_slots(bar) + (size_t)kJointTagWords * gid + word0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(v[q]);
+        __hip_atomic_store(w + 2 * q, (bits & 0xFFFFFFFF00000000ull) | tag, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(w + 2 * q + 1, (bits << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// The workgroup's publication: once every wave's device-scope stores are acknowledged.
+template <int N>
+__device__ __forceinline__ void tagn_publish_wg(unsigned *bar, int gid, int word0, unsigned tag,
+                                                const double (&v)[N]) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) tagn_publish<N>(bar, gid, word0, tag, v);
+}
+
+// Fixed-order sums of the N values that workgroups g0 .. g0+G-1 published with `tag` (bounded waits).
+template <int N>
+__device__ __forceinline__ void tagn_sum(unsigned *bar, int g0, int G, int word0, unsigned tag, bool &broken,
+                                         double (*lds)[kPcgThreads / kWave], unsigned spin_limit, double (&out)[N]) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) out[q] = 0.0;
+    bool ok = true;
+    for (int t = threadIdx.x; t < G; t += kPcgThreads) {
+        unsigned long long *w = tag_slots(bar) + (size_t)kJointTagWords * (g0 + t) + word0;
+        unsigned long long hv[N], lv[N];
+        unsigned spins = 0;
+        for (;;) {
+            bool all = true;
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                hv[q] = __hip_atomic_load(w + 2 * q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                lv[q] = __hip_atomic_load(w + 2 * q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                all = all && (unsigned)hv[q] == tag && (unsigned)lv[q] == tag;
+            }
+            if (all) break;
+            if (broken || ++spins > spin_limit) {
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (ok)
+#pragma unroll
+            for (int q = 0; q < N; ++q)
+                out[q] += __longlong_as_double((long long)((hv[q] & 0xFFFFFFFF00000000ull) | (lv[q] >> 32)));
+    }
+    broken = __syncthreads_or(broken || !ok) != 0;
+    wg_sum<N>(out, lds);
+}
+
+// The pose part of one iteration's direction (one thread; ps = pose r, z, p, q, x in LDS, the same in every
+// workgroup): q_p = (H_pp + lambda I) z_p + sum_j B_j^T z_j + beta q_p, p_p = z_p + beta p_p; returns p_p.q_p.
+__device__ __forceinline__ double pose_direction(double *ps, const double *sysl, const double (&btz)[6], double lam,
+                                                 int it, float beta) {
+    double z[6], qp[6], pp[6], t = 0.0;
+#pragma unroll
+    for (int u = 0; u < 6; ++u) z[u] = ps[6 + u];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+        double az = btz[u];
+#pragma unroll
+        for (int w = 0; w < 6; ++w) az += sysl[6 * u + w] * z[w];
+        az += lam * z[u];
+        qp[u] = it > 0 ? (double)beta * ps[18 + u] + az : az;
+        pp[u] = it > 0 ? (double)beta * ps[12 + u] + z[u] : z[u];
+        t += pp[u] * qp[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+        ps[12 + u] = pp[u];
+        ps[18 + u] = qp[u];
+    }
+    return t;
+}
+
+// The pose part of one step: x_p += alpha p_p, r_p -= alpha q_p, z_p = (H_pp + lambda I)^-1 r_p; out = r_p.z_p,
+// r_p.r_p and the count of non-finite x_p.
+__device__ __forceinline__ void pose_step(double *ps, const double *sysl, float alpha, double (&out)[3]) {
+    double r[6], nb = 0.0;
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+        const double x = ps[24 + u] + (double)alpha * ps[12 + u];
+        r[u] = ps[u] - (double)alpha * ps[18 + u];
+        ps[24 + u] = x;
+        ps[u] = r[u];
+        if (!isfinite(x)) nb += 1.0;
+    }
+    double rz = 0.0, rr = 0.0;
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < 6; ++w) t += sysl[42 + 6 * u + w] * r[w];
+        ps[6 + u] = t;
+        rz += r[u] * t;
+        rr += r[u] * r[u];
+    }
+    out[0] = rz;
+    out[1] = rr;
+    out[2] = nb;
+}
+
 // One workgroup's share of the solve: workgroup wg of the G that own this
 // system's rows, which are workgroups gid0 .. gid0+G-1 of the launch (a batch
 // solves several systems side by side, each over its own sync slots).  The
 // columns of the workgroup's blocks are reduced to their distinct nodes once;
 // each iteration stages z of those nodes in LDS (8-byte device-scope loads,
-// all in flight together).
+// all in flight together).  kJoint: the joint form above (one system, first
+// workgroup of the launch at gid0 = 0; bar is its own sync area).
+template <bool kJoint>
 __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_per_wg, int cache_blocks, unsigned *bar,
-                                                    int gid0, int wg, int G, misslam_report *rep) {
+                                                    int gid0, int wg, int G, misslam_report *rep,
+                                                    const JointExtra &jx) {
     extern __shared__ float4 dyn4[];
-    __shared__ double red[3][kPcgThreads / kWave];
+    __shared__ double red[kJoint ? 9 : 3][kPcgThreads / kWave];
     __shared__ float vx[kRowsPerBlk * 12], vr[kRowsPerBlk * 12], vp[kRowsPerBlk * 12], vq[kRowsPerBlk * 12];
     __shared__ TileLds tl;
     __shared__ float4 zc4[kMaxUnique * 3];             // z of the distinct columns (setup: first-block map)
+    // joint form: the pose part (r, z, p, q, x of the pose), H_pp | g_p | (H_pp + lambda I)^-1, this iteration's
+    // p_p.q_p, the pose step's r_p.z_p, r_p.r_p, #non-finite x_p, and r_p.r_p after each step (for the report)
+    __shared__ double ps[kJoint ? 30 : 1], sysl[kJoint ? 78 : 1], pose_s[kJoint ? 4 : 1];
+    __shared__ double rrp[kJoint ? MISSLAM_MAX_PCG + 1 : 1];
     float *zc = reinterpret_cast<float *>(zc4);
     const double lam = (double)(A.lambda_dev ? *A.lambda_dev : A.lambda);
     float *hc = reinterpret_cast<float *>(dyn4);       // cached blocks
@@ -667,6 +792,40 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
         vr[li] = r;
         vx[li] = 0.f;
     }
+    float brow[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // joint: this entry's row of the border
+    double btz[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};    // joint: sum_j B_j^T z_j of the current z
+    if constexpr (kJoint) {
+        if (act)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) brow[k] = jx.B[(size_t)j * 72 + a * 6 + k];
+        if (threadIdx.x < 78) sysl[threadIdx.x] = jx.sys[threadIdx.x];
+        __syncthreads();
+        if (threadIdx.x == kPoseThread) {   // r_p = -g_p, z_p = M_p r_p, p_p = q_p = x_p = 0
+            double rp[6], rz_p = 0.0, rr_p = 0.0;
+#pragma unroll
+            for (int u = 0; u < 6; ++u) rp[u] = -sysl[36 + u];
+#pragma unroll
+            for (int u = 0; u < 6; ++u) {
+                double t = 0.0;
+#pragma unroll
+                for (int w = 0; w < 6; ++w) t += sysl[42 + 6 * u + w] * rp[w];
+                ps[u] = rp[u];
+                ps[6 + u] = t;
+                ps[12 + u] = 0.0;
+                ps[18 + u] = 0.0;
+                ps[24 + u] = 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 6; ++u) {
+                rz_p += rp[u] * ps[6 + u];
+                rr_p += rp[u] * rp[u];
+            }
+            pose_s[1] = rz_p;
+            pose_s[2] = rr_p;
+            pose_s[3] = 0.0;
+            rrp[0] = rr_p;
+        }
+    }
     __syncthreads();
     if (act) {
         const float *M = mc + (size_t)lr * 144 + a * 12;
@@ -678,7 +837,22 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
         if (zslot >= 0) zc[zslot * 12 + a] = z;
     }
     double rz, azl;
-    {
+    if constexpr (kJoint) {   // r.z and B^T z travel together; the pose's r.z is added by every workgroup
+        double v[8] = {(double)r * (double)z, (double)r * (double)r};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[2 + k] = (double)brow[k] * (double)z;
+        wg_sum<8>(v, red);
+        if (threadIdx.x == 0) st_dev(A.part + (size_t)(0 * 4 + 1) * G + wg, v[1]);
+        const double pv7[7] = {v[0], v[2], v[3], v[4], v[5], v[6], v[7]};
+        tagn_publish_wg<7>(bar, gid0 + wg, 2, 1u, pv7);
+        azl = local_part();
+        double t7[7];
+        tagn_sum<7>(bar, gid0, G, 2, 1u, broken, red, A.spin, t7);
+        rz = t7[0] + pose_s[1];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) btz[k] = t7[1 + k];
+        stage();
+    } else {
         double v[2] = {(double)r * (double)z, (double)r * (double)r};
         wg_sum<2>(v, red);
         if (threadIdx.x == 0) st_dev(A.part + (size_t)(0 * 4 + 1) * G + wg, v[1]);
@@ -694,8 +868,10 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
         const bool skip = stopped || rz == 0.0;
         // ---- direction and product: p = z + beta p, q = (H + lambda I) z + beta q
         double pq = 0.0;
+        const float beta = it > 0 ? (float)(rz / rz_prev) : 0.f;
+        if constexpr (kJoint)   // the pose part, beside the ED product (the pose thread holds no entry)
+            if (threadIdx.x == kPoseThread && !skip) pose_s[0] = pose_direction(ps, sysl, btz, lam, it, beta);
         if (act && !skip) {
-            const float beta = it > 0 ? (float)(rz / rz_prev) : 0.f;
             double az = 0.0;                           // exact float64 sums of float32 products
             const int p0 = A.row_ptr[j], p1 = min(A.row_ptr[j + 1], A.cap);
             if (fast) {   // the local part, then the other blocks in two chains (pairs read together)
@@ -762,6 +938,9 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
                 }
             }
             az = fma(lam, (double)z, az);
+            if constexpr (kJoint)   // + B_j z_p
+#pragma unroll
+                for (int k = 0; k < 6; ++k) az = fma((double)brow[k], ps[6 + k], az);
             const float pv = it > 0 ? fmaf(beta, vp[li], z) : z;
             const float qv = it > 0 ? (float)fma((double)beta, (double)vq[li], az) : (float)az;
             vp[li] = pv;
@@ -772,8 +951,16 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
         {
             double v[1] = {pq};
             wg_sum<1>(v, red);
-            publish(0, (unsigned)(it + 1), v[0]);
-            pqs = tag_sum(bar, gid0, G, 0, (unsigned)(it + 1), broken, red, A.spin);
+            if constexpr (kJoint) {
+                double t1[1];
+                const double pv1[1] = {v[0]};
+                tagn_publish_wg<1>(bar, gid0 + wg, 0, (unsigned)(it + 1), pv1);
+                tagn_sum<1>(bar, gid0, G, 0, (unsigned)(it + 1), broken, red, A.spin, t1);
+                pqs = t1[0] + pose_s[0];   // + p_p.q_p, the same in every workgroup
+            } else {
+                publish(0, (unsigned)(it + 1), v[0]);
+                pqs = tag_sum(bar, gid0, G, 0, (unsigned)(it + 1), broken, red, A.spin);
+            }
         }
         // ---- step: alpha = r.z / p.q, x += alpha p, r -= alpha q, z = M r
         const bool brk = !skip && !(pqs > 0.0);
@@ -798,7 +985,33 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
         if (upd) ++done;
         if (brk) stopped = true;
         if (!skip) rz_prev = rz;
-        {
+        if constexpr (kJoint) {
+            double v[9] = {(double)r * (double)z, (double)r * (double)r, bad};
+#pragma unroll
+            for (int k = 0; k < 6; ++k) v[3 + k] = (double)brow[k] * (double)z;
+            wg_sum<9>(v, red);
+            if (threadIdx.x == 0) {
+                st_dev(A.part + (size_t)((it + 1) * 4 + 1) * G + wg, v[1]);
+                st_dev(A.part + (size_t)((it + 1) * 4 + 3) * G + wg, v[2]);
+            }
+            const double pv7[7] = {v[0], v[3], v[4], v[5], v[6], v[7], v[8]};
+            tagn_publish_wg<7>(bar, gid0 + wg, 2, (unsigned)(it + 2), pv7);
+            // the pose step, while the exchange is in flight (nothing before this point reads its results)
+            if (threadIdx.x == kPoseThread && upd) {
+                double o3[3];
+                pose_step(ps, sysl, (float)(rz / pqs), o3);
+                pose_s[1] = o3[0];
+                pose_s[2] = o3[1];
+                pose_s[3] = o3[2];
+                rrp[min(it + 1, MISSLAM_MAX_PCG)] = o3[1];
+            }
+            azl = local_part();
+            double t7[7];
+            tagn_sum<7>(bar, gid0, G, 2, (unsigned)(it + 2), broken, red, A.spin, t7);
+            rz = t7[0] + pose_s[1];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) btz[k] = t7[1 + k];
+        } else {
             double v[3] = {(double)r * (double)z, (double)r * (double)r, bad};
             wg_sum<3>(v, red);
             if (threadIdx.x == 0) {
@@ -812,13 +1025,18 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
         stage();
     }
     // ---- finish: report (first workgroup), x out; the update itself is step_commit_kernel's
-    const double nbad = A.iters > 0 ? gather_dev(A.part + (size_t)(A.iters * 4 + 3) * G, G, red) : 0.0;
+    double nbad = A.iters > 0 ? gather_dev(A.part + (size_t)(A.iters * 4 + 3) * G, G, red) : 0.0;
+    if constexpr (kJoint) nbad += pose_s[3];
     if (act) A.x[(size_t)j * 12 + a] = vx[li];
     if (wg == 0) {
         for (int q = 0; q <= done; ++q) {
-            const double rr = gather_dev(A.part + (size_t)(q * 4 + 1) * G, G, red);
+            double rr = gather_dev(A.part + (size_t)(q * 4 + 1) * G, G, red);
+            if constexpr (kJoint) rr += rrp[min(q, MISSLAM_MAX_PCG)];
             if (threadIdx.x == 0 && q <= MISSLAM_MAX_PCG) rep->pcg_resid[q] = sqrt(rr);
         }
+        if constexpr (kJoint)
+            if (threadIdx.x == 0)
+                for (int u = 0; u < 6; ++u) jx.xp_out[u] = ps[24 + u];
         if (threadIdx.x == 0) {
             rep->pcg_iters_done = done;
             int f = 0;
@@ -832,7 +1050,12 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
 
 __global__ void __launch_bounds__(kPcgThreads) pcg_persistent_kernel(PcgArgs A, int rows_per_wg, int cache_blocks,
                                                                     unsigned *bar, misslam_report *rep) {
-    pcg_persistent_body(A, rows_per_wg, cache_blocks, bar, 0, blockIdx.x, gridDim.x, rep);
+    pcg_persistent_body<false>(A, rows_per_wg, cache_blocks, bar, 0, blockIdx.x, gridDim.x, rep, JointExtra{});
+}
+
+__global__ void __launch_bounds__(kPcgThreads) jpcg_tiled_kernel(PcgArgs A, int rows_per_wg, int cache_blocks,
+                                                                unsigned *bar, misslam_report *rep, JointExtra jx) {
+    pcg_persistent_body<true>(A, rows_per_wg, cache_blocks, bar, 0, blockIdx.x, gridDim.x, rep, jx);
 }
 
 // x += dx over n entries as one step, after the solve that produced dx has
@@ -1185,7 +1408,8 @@ struct PersistentShape {
 };
 
 // The device limits of one persistent kernel: queried once per process (first device used).
-static void persistent_limits(PersistentKernel kern, PersistentShape &sh) {
+template <typename Kern>
+static void persistent_limits(Kern kern, PersistentShape &sh) {
     int dev = 0, cus = 0, coop = 0, shmem = 0;
     hipFuncAttributes fa{};
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1208,10 +1432,7 @@ static void persistent_limits(PersistentKernel kern, PersistentShape &sh) {
         sh.max_blocks = cus;
 }
 
-static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes, bool textbook) {
-    static PersistentShape tb, pp;
-    PersistentShape &sh = textbook ? tb : pp;
-    if (sh.max_blocks < 0) persistent_limits(textbook ? pcg_persistent_kernel : ppcg_persistent_kernel, sh);
+static int persistent_grid(const PersistentShape &sh, int m, int &rows_per_wg, int &lds_bytes) {
     const int max_blocks = sh.max_blocks, max_lds = sh.max_lds;
     if (max_blocks <= 0 || m <= 0) return 0;
     // more rows per workgroup once one workgroup per CU no longer holds the system
@@ -1222,6 +1443,18 @@ static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes, bool textboo
     if (G > max_blocks || G > MSL_TAG_WGS) return 0;
     lds_bytes = max_lds;
     return G;
+}
+
+static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes, bool textbook) {
+    static PersistentShape tb, pp;
+    PersistentShape &sh = textbook ? tb : pp;
+    if (sh.max_blocks < 0) {
+        if (textbook)
+            persistent_limits(pcg_persistent_kernel, sh);
+        else
+            persistent_limits(ppcg_persistent_kernel, sh);
+    }
+    return persistent_grid(sh, m, rows_per_wg, lds_bytes);
 }
 
 hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
@@ -1284,6 +1517,29 @@ hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks,
     return e;
 }
 
+hipError_t launch_joint_pcg_persistent(const PcgArgs &base, const JointExtra &jx, unsigned long long *bar,
+                                       int zeroed_words, misslam_report *rep, hipStream_t st, bool *used) {
+    *used = false;
+    static PersistentShape sh;
+    if (sh.max_blocks < 0) persistent_limits(jpcg_tiled_kernel, sh);
+    int rows = 0, lds = 0;
+    const int G = persistent_grid(sh, base.m, rows, lds);
+    if (G <= 0 || G > kJointMaxWgs || !bar || !base.part) return hipSuccess;
+    const int cache_blocks = (lds / 4 - rows * 144) / 144;
+    if (cache_blocks < 1) return hipSuccess;
+    PcgArgs A = base;
+    A.nblk = G;
+    unsigned *b32 = reinterpret_cast<unsigned *>(bar);
+    const int words = kJointTagWords * G;   // 8-byte words
+    if (zeroed_words < words)
+        hipLaunchKernelGGL(fill_u32_kernel_pcg, dim3((2 * words + 255) / 256), dim3(256), 0, st, b32, 2 * words);
+    hipLaunchKernelGGL(jpcg_tiled_kernel, dim3(G), dim3(kPcgThreads), (unsigned)lds, st, A, rows, cache_blocks, b32,
+                       rep, jx);
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) *used = true;
+    return e;
+}
+
 
 }  // namespace msl
 
@@ -1300,7 +1556,8 @@ __global__ void __launch_bounds__(kPcgThreads) pcg_batched_kernel(const BatchIte
     int b = count - 1;
     while (b > 0 && items[b].wg0 > (int)blockIdx.x) --b;
     const BatchItem &it = items[b];
-    pcg_persistent_body(it.p, rows_per_wg, cache_blocks, bar, it.wg0, (int)blockIdx.x - it.wg0, it.wgs, it.rep + gi);
+    pcg_persistent_body<false>(it.p, rows_per_wg, cache_blocks, bar, it.wg0, (int)blockIdx.x - it.wg0, it.wgs,
+                               it.rep + gi, JointExtra{});
 }
 
 // The same with the pipelined recurrence.

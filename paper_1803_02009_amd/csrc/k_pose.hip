@@ -21,8 +21,6 @@ constexpr int kJThreads = 256;
 constexpr int kJRows = 21;          // node rows per block, 12 threads per row
 constexpr int kJKinds = 10;         // partial kinds per iteration: r.z, r.r, p.q, #non-finite, B^T z (6)
 constexpr int kPst = 32;            // pose state per iteration: r, z, p, q, x (6 each)
-constexpr int kJMaxWgs = 1024;      // workgroups of the one-launch joint solve (sync area size)
-constexpr int kJSlotWords = 32;     // sync words per workgroup: 2 parities x 8 values x 2 words
 
 __global__ void pose_init_kernel(Pose P, float *pose_dev) {
     const int t = threadIdx.x;
@@ -191,19 +189,14 @@ __global__ void __launch_bounds__(256) pose_setup_kernel(const float *pose_dev, 
         for (int u = 0; u < 6; ++u) vk[21 + u] += wc * ((J[0][u] * r3[0] + J[1][u] * r3[1]) + J[2][u] * r3[2]);
     }
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    wave_sums(v);
+    if (pk.count > 0) wave_sums(vk);   // else every vk is +0.0, and so is its sum
+    if (lane == 0)
 #pragma unroll
-    for (int q = 0; q < kPosePart; ++q) {
-        double t = v[q], tk = vk[q];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            t += __shfl_xor(t, off, 64);
-            tk += __shfl_xor(tk, off, 64);
+        for (int q = 0; q < kPosePart; ++q) {
+            wred[0][wave][q] = v[q];
+            wred[1][wave][q] = vk[q];
         }
-        if (lane == 0) {
-            wred[0][wave][q] = t;
-            wred[1][wave][q] = tk;
-        }
-    }
     __syncthreads();
     if (threadIdx.x != 0) return;
     double S[kPosePart], SK[kPosePart];
@@ -287,7 +280,7 @@ hipError_t launch_pose_setup(const float *pose_dev, const PosePrior &pr, const d
                              float lambda, double *sys, misslam_report *rep, hipStream_t st,
                              unsigned long long *jbar, int m, const KeyArgs *kp, const CorrScratch *c, int64_t n,
                              int k) {
-    const int words = jbar ? kJSlotWords * ((m + kJRows - 1) / kJRows) : 0;
+    const int words = jbar ? joint_sync_words(m) : 0;
     PoseKeys pk{};
     if (kp && c && kp->count > 0) {
         pk.count = kp->count;
@@ -299,7 +292,7 @@ hipError_t launch_pose_setup(const float *pose_dev, const PosePrior &pr, const d
         pk.n = n;
     }
     hipLaunchKernelGGL(pose_setup_kernel, dim3(1), dim3(256), 0, st, pose_dev, pr, pose_part, nblk_pts, lambda, sys,
-                       rep, jbar, words < kJSlotWords * kJMaxWgs ? words : kJSlotWords * kJMaxWgs, pk);
+                       rep, jbar, words, pk);
     return hipGetLastError();
 }
 
@@ -317,13 +310,10 @@ struct JArgs {
 template <int N>
 __device__ __forceinline__ void block_sums(double (&v)[N], double (*lds)[kJThreads / kWave]) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    wave_sums(v);
+    if (lane == 0)
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
-        double t = v[q];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-        if (lane == 0) lds[q][wave] = t;
-    }
+        for (int q = 0; q < N; ++q) lds[q][wave] = v[q];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < N; ++q) v[q] = ((lds[q][0] + lds[q][1]) + lds[q][2]) + lds[q][3];
@@ -612,256 +602,6 @@ __global__ void __launch_bounds__(kJThreads) jpcg_finish_kernel(JArgs J, misslam
     }
 }
 
-// ---------------------------------------------------------------- joint PCG in one launch
-
-// The same recurrence with the kernel boundaries replaced by tagged exchanges
-// (as in the ED-only persistent solve): workgroup w publishes its partial sums
-// of exchange x as (high half | tag) and (low half | tag) 8-byte words at
-// agent scope, tag = x + 1, in the slot of parity x & 1 (a slot is rewritten
-// two exchanges later, when every workgroup has read it); every workgroup
-// waits for all of them (bounded) and adds them in workgroup order, so all
-// hold the same sums and the same float64 pose state.  Each thread keeps its
-// entry's r, z, p, q, x in registers; z travels through agent-scope stores
-// published only after they are acknowledged.
-__device__ __forceinline__ void jtag_publish(unsigned long long *bar, int wg, int x, const double *v, int N) {
-    unsigned long long *w = bar + (size_t)wg * kJSlotWords + (x & 1) * 16;
-    const unsigned long long tag = (unsigned)(x + 1);
-    for (int q = 0; q < N; ++q) {
-        const unsigned long long bits = (unsigned long long)__double_as_longlong(v[q]);
-        __hip_atomic_store(w + 2 * q, (bits & 0xFFFFFFFF00000000ull) | tag, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(w + 2 * q + 1, (bits << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// Each wait polls at most J.A.spin times (a timeout marks the workgroup broken; the step is then discarded
-// whole by joint_commit_kernel, which runs after the solve).
-template <int N>
-__device__ __forceinline__ void jtag_sum(unsigned long long *bar, int G, int x, double (&out)[N], bool &broken,
-                                         double (*lds)[kJThreads / kWave], unsigned spin_limit) {
-    const unsigned tag = (unsigned)(x + 1);
-#pragma unroll
-    for (int q = 0; q < N; ++q) out[q] = 0.0;
-    bool ok = true;
-    for (int t = threadIdx.x; t < G; t += kJThreads) {
-        unsigned long long *w = bar + (size_t)t * kJSlotWords + (x & 1) * 16;
-        unsigned long long hv[N], lv[N];
-        unsigned spins = 0;
-        for (;;) {
-            bool all = true;
-#pragma unroll
-            for (int q = 0; q < N; ++q) {
-                hv[q] = __hip_atomic_load(w + 2 * q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                lv[q] = __hip_atomic_load(w + 2 * q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                all = all && (unsigned)hv[q] == tag && (unsigned)lv[q] == tag;
-            }
-            if (all) break;
-            if (broken || ++spins > spin_limit) {
-                ok = false;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        if (ok)
-#pragma unroll
-            for (int q = 0; q < N; ++q)
-                out[q] += __longlong_as_double((long long)((hv[q] & 0xFFFFFFFF00000000ull) | (lv[q] >> 32)));
-    }
-    broken = __syncthreads_or(broken || !ok) != 0;
-    block_sums<N>(out, lds);
-}
-
-__global__ void __launch_bounds__(kJThreads) jpcg_persistent_kernel(JArgs J, unsigned long long *bar, int G,
-                                                                    misslam_report *rep) {
-    const PcgArgs &A = J.A;
-    __shared__ double red[16][kJThreads / kWave];
-    __shared__ float rl[kJRows][12];
-    __shared__ double ps[kPst];          // pose r, z, p, q, x (the same in every workgroup)
-    __shared__ double pshare[2];         // this iteration's pose p.q; pose r.z / r.r partial
-    __shared__ double resid[MISSLAM_MAX_PCG + 1];
-    __shared__ double sysl[78];          // H_pp, g_p, (H_pp + lambda I)^-1: read by the serial pose steps
-    const int wg = blockIdx.x;
-    const int row = threadIdx.x / 12, a = threadIdx.x % 12;
-    const int j = wg * kJRows + row;
-    const bool act = row < kJRows && j < A.m;
-    const size_t o = (size_t)j * 12 + a;
-    const double lam = (double)A.lambda;
-    bool broken = false;
-    auto publish = [&](int x, const double *v, int N) {
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (threadIdx.x == 0) jtag_publish(bar, wg, x, v, N);
-    };
-    // init: r = -g, z = M r, x = 0; the pose part r_p = -g_p, z_p = M_p r_p
-    float r = 0.f, z = 0.f, xv = 0.f, pv = 0.f, qv = 0.f;
-    if (act) {
-        r = -A.g[o];
-        rl[row][a] = r;
-    }
-    if (threadIdx.x < 78) sysl[threadIdx.x] = J.sys[threadIdx.x];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double rz_p = 0.0, rr_p = 0.0;
-        for (int u = 0; u < 6; ++u) ps[u] = -sysl[36 + u];
-        for (int u = 0; u < 6; ++u) {
-            double t = 0.0;
-            for (int w = 0; w < 6; ++w) t += sysl[42 + 6 * u + w] * ps[w];
-            ps[6 + u] = t;
-            ps[12 + u] = 0.0;
-            ps[18 + u] = 0.0;
-            ps[24 + u] = 0.0;
-        }
-        for (int u = 0; u < 6; ++u) {
-            rz_p += ps[u] * ps[6 + u];
-            rr_p += ps[u] * ps[u];
-        }
-        pshare[0] = rz_p;
-        pshare[1] = rr_p;
-    }
-    __syncthreads();
-    if (act) {
-        z = jprecond(A.minv, j, a, rl[row]);
-        __hip_atomic_store(A.z + o, z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    double s2[2] = {(double)r * (double)z, (double)r * (double)r};
-    block_sums<2>(s2, red);
-    if (wg == 0) {
-        s2[0] += pshare[0];
-        s2[1] += pshare[1];
-    }
-    publish(0, s2, 2);
-    double t2[2];
-    jtag_sum<2>(bar, G, 0, t2, broken, red, A.spin);
-    double rz = t2[0], rz_prev = 1.0, nbad = 0.0;
-    if (wg == 0 && threadIdx.x == 0) resid[0] = sqrt(t2[1]);
-    int done = 0, status = 0;
-    for (int it = 0; it < A.iters; ++it) {
-        if (status != 0 || rz == 0.0 || broken) break;   // workgroup-uniform, the same in every workgroup
-        const float beta = it > 0 ? (float)(rz / rz_prev) : 0.f;
-        // direction and product: q = H z + lambda z + B z_p + beta q, p = z + beta p
-        double pq = 0.0, btz[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (act) {
-            double az = 0.0;
-            const int p0 = A.row_ptr[j], p1 = min(A.row_ptr[j + 1], A.cap);
-            for (int pb = p0; pb < p1; ++pb) {
-                const float *Bk = A.blocks + (size_t)pb * 144 + a * 12;
-                const float *zl = A.z + (size_t)A.col_idx[pb] * 12;
-#pragma unroll
-                for (int b = 0; b < 12; ++b)
-                    az = fma((double)Bk[b],
-                             (double)__hip_atomic_load(const_cast<float *>(zl + b), __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT),
-                             az);
-            }
-            az = fma(lam, (double)z, az);
-            const float *Bj = J.B + (size_t)j * 72 + a * 6;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                az = fma((double)Bj[k], ps[6 + k], az);
-                btz[k] = (double)Bj[k] * (double)z;
-            }
-            if (it > 0) {
-                pv = fmaf(beta, pv, z);
-                qv = (float)fma((double)beta, (double)qv, az);
-            } else {
-                pv = z;
-                qv = (float)az;
-            }
-            pq = (double)pv * (double)qv;
-        }
-        double s7[7] = {pq, btz[0], btz[1], btz[2], btz[3], btz[4], btz[5]};
-        block_sums<7>(s7, red);
-        publish(1 + 2 * it, s7, 7);
-        double t7[7];
-        jtag_sum<7>(bar, G, 1 + 2 * it, t7, broken, red, A.spin);
-        if (threadIdx.x == 0) {   // the pose part of the product and its direction
-            double qp[6], pp[6], t = 0.0;
-            for (int u = 0; u < 6; ++u) {
-                double az = t7[1 + u];
-                for (int w = 0; w < 6; ++w) az += sysl[6 * u + w] * ps[6 + w];
-                az += lam * ps[6 + u];
-                qp[u] = it > 0 ? (double)beta * ps[18 + u] + az : az;
-                pp[u] = it > 0 ? (double)beta * ps[12 + u] + ps[6 + u] : ps[6 + u];
-                t += pp[u] * qp[u];
-            }
-            for (int u = 0; u < 6; ++u) {
-                ps[12 + u] = pp[u];
-                ps[18 + u] = qp[u];
-            }
-            pshare[0] = t;
-        }
-        __syncthreads();
-        const double pqt = t7[0] + pshare[0];
-        __syncthreads();
-        if (!(pqt > 0.0) || broken) {   // breakdown: no update (uniform)
-            status = broken ? status : 2;
-            break;
-        }
-        const float alpha = (float)(rz / pqt);
-        double bad = 0.0;
-        if (act) {
-            xv = fmaf(alpha, pv, xv);
-            r = fmaf(-alpha, qv, r);
-            bad = isfinite(xv) ? 0.0 : 1.0;
-            rl[row][a] = r;
-        }
-        if (threadIdx.x == 0) {   // the pose step and its preconditioned residual
-            double rz_p = 0.0, rr_p = 0.0, nb_p = 0.0;
-            for (int u = 0; u < 6; ++u) {
-                ps[24 + u] += (double)alpha * ps[12 + u];
-                ps[u] -= (double)alpha * ps[18 + u];
-                if (!isfinite(ps[24 + u])) nb_p += 1.0;
-            }
-            for (int u = 0; u < 6; ++u) {
-                double t = 0.0;
-                for (int w = 0; w < 6; ++w) t += sysl[42 + 6 * u + w] * ps[w];
-                ps[6 + u] = t;
-            }
-            for (int u = 0; u < 6; ++u) {
-                rz_p += ps[u] * ps[6 + u];
-                rr_p += ps[u] * ps[u];
-            }
-            red[15][0] = rz_p;
-            red[15][1] = rr_p;
-            red[15][2] = nb_p;
-        }
-        __syncthreads();
-        if (act) {
-            z = jprecond(A.minv, j, a, rl[row]);
-            __hip_atomic_store(A.z + o, z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        const double pose_rz = red[15][0], pose_rr = red[15][1], pose_nb = red[15][2];
-        double s3[3] = {(double)r * (double)z, (double)r * (double)r, bad};
-        block_sums<3>(s3, red);
-        if (wg == 0) {
-            s3[0] += pose_rz;
-            s3[1] += pose_rr;
-            s3[2] += pose_nb;
-        }
-        publish(2 + 2 * it, s3, 3);
-        double t3[3];
-        jtag_sum<3>(bar, G, 2 + 2 * it, t3, broken, red, A.spin);
-        rz_prev = rz;
-        rz = t3[0];
-        nbad = t3[2];
-        done = it + 1;
-        if (wg == 0 && threadIdx.x == 0) resid[done] = sqrt(t3[1]);
-    }
-    // finish: delta and the pose step out (joint_commit_kernel applies them); the report.  Flags are ORed
-    // atomically: every workgroup that gave up a wait adds the timeout bit.
-    if (act) A.x[o] = xv;
-    if (wg == 0 && threadIdx.x == 0) {
-        for (int q = 0; q <= done && q <= MISSLAM_MAX_PCG; ++q) rep->pcg_resid[q] = resid[q];
-        rep->pcg_iters_done = done;
-        for (int u = 0; u < 6; ++u) J.pst[(size_t)A.iters * kPst + 24 + u] = ps[24 + u];
-        int f = 0;
-        if (status == 2) f |= MISSLAM_FLAG_PCG_BREAKDOWN;
-        if (nbad != 0.0) f |= MISSLAM_FLAG_NONFINITE;
-        if (f) atomicOr(&rep->flags, f);
-    }
-    if (broken && threadIdx.x == 0) atomicOr(&rep->flags, MISSLAM_FLAG_SYNC_TIMEOUT);
-}
-
 // After the one-launch joint solve: params += delta and the pose step (stored by its first workgroup at
 // pst), unless the step's report carries a non-finite value or a timeout of any workgroup.
 __global__ void __launch_bounds__(256) joint_commit_kernel(float *__restrict__ params, const float *__restrict__ dx,
@@ -911,21 +651,22 @@ hipError_t launch_joint_pcg(const GraphView &g, int m, const float *blocks, cons
     J.sys = js.sys;
     J.jpart = js.jpart;
     J.pst = js.pst;
-    static int cus = -1;
-    if (cus < 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            cus = 0;
-    }
-    if (!kernels && js.jbar && A.nblk <= cus && A.nblk <= kJMaxWgs) {   // every workgroup resident: one launch
-        if (spin > 0) A.spin = spin;
-        hipLaunchKernelGGL(jpcg_persistent_kernel, dim3(A.nblk), dim3(kJThreads), 0, st, J, js.jbar, A.nblk, rep);
-        const hipError_t e = hipGetLastError();
+    if (!kernels && js.jbar) {   // one launch when every workgroup fits on the device at once
+        PcgArgs P = A;
+        P.part = s.part;
+        if (spin > 0) P.spin = spin;
+        JointExtra jx;
+        jx.B = js.B;
+        jx.sys = js.sys;
+        jx.xp_out = J.pst + (size_t)iters * kPst + 24;
+        bool used = false;
+        hipError_t e = launch_joint_pcg_persistent(P, jx, js.jbar, joint_sync_words(m), rep, st, &used);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(joint_commit_kernel, dim3((12 * m + 255) / 256), dim3(256), 0, st, params, delta, 12 * m,
-                           rep, pose_dev, J.pst + (size_t)iters * kPst + 24);
-        return hipGetLastError();
+        if (used) {
+            hipLaunchKernelGGL(joint_commit_kernel, dim3((12 * m + 255) / 256), dim3(256), 0, st, params, delta,
+                               12 * m, rep, pose_dev, jx.xp_out);
+            return hipGetLastError();
+        }
     }
     const dim3 grid(A.nblk), blk(kJThreads);
     hipLaunchKernelGGL(jpcg_init_kernel, grid, blk, 0, st, J);

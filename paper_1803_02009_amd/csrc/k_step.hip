@@ -130,13 +130,10 @@ __device__ __forceinline__ void point_pass_body(const StepArgs &a, const StepScr
 #pragma unroll
         for (int u = 0; u < 6; ++u) v[e++] = (double)jp[u] * (double)rres;
         const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+        wave_sums(v);
+        if (lane == 0)
 #pragma unroll
-        for (int q = 0; q < kPosePart; ++q) {
-            double t = v[q];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-            if (lane == 0) wred[wave][q] = t;
-        }
+            for (int q = 0; q < kPosePart; ++q) wred[wave][q] = v[q];
         __syncthreads();
         if (threadIdx.x < kPosePart) {
             double t = wred[0][threadIdx.x];
@@ -763,12 +760,7 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
     }
     flush(cur0, cur1, acc);
     // wave reduction of the data gradient (fixed butterfly order)
-#pragma unroll
-    for (int q = 0; q < 12; ++q) {
-        double v = gacc[q];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        gacc[q] = v;
-    }
+    wave_sums(gacc);
     if (lane == 0) {
 #pragma unroll
         for (int q = 0; q < 12; ++q) sh.gw[wave][q] = gacc[q];
@@ -1003,12 +995,7 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
         wave_sync();
     }
     flush();
-#pragma unroll
-    for (int q = 0; q < 12; ++q) {
-        double v = gacc[q];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        gacc[q] = v;
-    }
+    wave_sums(gacc);
     if (lane == 0) {
 #pragma unroll
         for (int q = 0; q < 12; ++q) sh.gw[wave][q] = gacc[q];
@@ -1107,12 +1094,7 @@ __global__ void __launch_bounds__(64) jtv_row_kernel(StepArgs a, StepScratch s, 
 #pragma unroll
             for (int aa = 0; aa < 3; ++aa) acc[3 * c + aa] = fmaf(f * uu[c], nn[aa], acc[3 * c + aa]);
     }
-#pragma unroll
-    for (int q = 0; q < 12; ++q) {
-        float v = acc[q];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        acc[q] = v;
-    }
+    wave_sums(acc);
     if (lane < 12) {
         float y = 0.f;
 #pragma unroll
@@ -1353,13 +1335,10 @@ __device__ __forceinline__ void energy_report_body(const double *__restrict__ pt
     }
     // wave butterflies, then the four waves in order: a fixed summation order
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    wave_sums(v);
+    if (lane == 0)
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        double t = v[q];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-        if (lane == 0) red[q][wave] = t;
-    }
+        for (int q = 0; q < 6; ++q) red[q][wave] = v[q];
     __syncthreads();
     if (threadIdx.x == 0) {
         double tot[6];

@@ -3,11 +3,11 @@
 The one-launch PCG started as a plain launch (the default) and as a
 cooperative launch runs the same kernel over the same partition: parameters
 and reports must be bitwise equal, with no workgroup giving up its waits,
-for the pipelined recurrence (the default) and the textbook one.  The two
+for the textbook recurrence (the default) and the pipelined one.  The two
 recurrences are the same iterates in exact arithmetic and agree to rounding.
 The per-phase launches (no residency needed) take the same steps in another
-reduction order for the fixed-pose solve (equal to rounding) and in the same
-order for the joint pose form (bitwise equal).
+reduction order, for the fixed-pose and the joint pose form alike (equal to
+rounding).
 """
 import dataclasses
 
@@ -50,7 +50,9 @@ def test_per_phase_launches_agree_to_rounding(lib):
     assert np.all(r0["flags"] == 0) and np.all(r1["flags"] == 0)
 
 
-def test_joint_per_phase_launches_agree_bitwise(lib):
+def test_joint_per_phase_launches_agree_to_rounding(lib):
+    """The joint one-launch solve sums each row's blocks as the fixed-form one does (own columns, then two
+    chains), the per-phase joint kernels in block order: equal in exact arithmetic."""
     s = Scene("c2")
     out = []
     for mode in (_lib.LAUNCH_PLAIN, _lib.LAUNCH_KERNELS):
@@ -58,12 +60,21 @@ def test_joint_per_phase_launches_agree_bitwise(lib):
         x = s.M.identity_params(s.m)
         rep, pose, _ = s.M.joint_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, p, s.ws)
         torch.cuda.synchronize()
-        out.append((x.cpu().numpy(), pose.cpu().numpy(), s.M.read_report(rep)))
+        out.append((x.cpu().numpy(), pose.cpu().numpy().astype(np.float64), s.M.read_report(rep)))
     (x0, P0, r0), (x1, P1, r1) = out
-    assert np.array_equal(x0.view(np.uint32), x1.view(np.uint32))
-    assert np.array_equal(P0.view(np.uint32), P1.view(np.uint32))
-    assert r0.tobytes() == r1.tobytes()
-    assert np.all(r0["flags"] == 0)
+    x_id = s.M.identity_params(s.m).cpu().numpy()
+    T0 = np.asarray(s.sc["T"], np.float64)
+    print("joint per-phase vs one launch: x rel", rel_err(x1, x0), "delta rel", rel_err(x1 - x_id, x0 - x_id),
+          "|dR|", np.abs(P1[:9] - P0[:9]).max(), "|dT|", np.abs(P1[9:] - P0[9:]).max(),
+          "moved", np.abs(P0[9:] - T0).max())
+    assert rel_err(x1 - x_id, x0 - x_id) < 1e-4
+    assert np.abs(P1[:9] - P0[:9]).max() < 1e-5
+    assert np.abs(P1[9:] - P0[9:]).max() < 1e-3 * max(np.abs(P0[9:] - T0).max(), 1.0)
+    for k in range(len(r0)):
+        assert r1[k]["e_data"] == pytest.approx(r0[k]["e_data"], rel=1e-4)
+        assert r1[k]["pcg_iters_done"] == r0[k]["pcg_iters_done"]
+        assert r1[k]["pcg_resid"] == pytest.approx(r0[k]["pcg_resid"], rel=1e-2, abs=1e-6)
+    assert np.all(r0["flags"] == 0) and np.all(r1["flags"] == 0)
 
 
 @pytest.mark.parametrize("case", ["c2", "c3"])
