@@ -322,25 +322,75 @@ __device__ __forceinline__ bool gj_inverse_block(double (*A)[12], float *out) {
     return !bad;
 }
 
+// Cross-lane partners for the wave butterfly without LDS traffic, on 32-bit words.  stage_pair<k32> returns
+// the word and its partner lane's (xor 32, or xor 16) in an order that depends on the lane, by the gfx950 lane
+// swaps (v_permlane32_swap / v_permlane16_swap with the word as both operands): their sum is the stage's sum.
+// dpp_word<kCtrl> reads the word of another lane of the same 16-lane row: row_ror:8 / row_ror:4 give the xor-8 /
+// xor-4 partner's value once the values repeat every 16 / 8 lanes (true after the larger stages), quad_perm
+// [2,3,0,1] / [1,0,3,2] give the xor-2 / xor-1 partner exactly.
+template <bool k32>
+__device__ __forceinline__ void stage_pair(unsigned w, unsigned &a, unsigned &b) {
+    if constexpr (k32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+        a = r[0];
+        b = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(w, w, false, false);
+        a = r[0];
+        b = r[1];
+    }
+}
+template <int kCtrl>
+__device__ __forceinline__ unsigned dpp_word(unsigned w) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)w, kCtrl, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float stage_sum32(float v, bool k32) {
+    unsigned a, b;
+    if (k32) stage_pair<true>(__float_as_uint(v), a, b);
+    else stage_pair<false>(__float_as_uint(v), a, b);
+    return __uint_as_float(a) + __uint_as_float(b);
+}
+__device__ __forceinline__ double stage_sum32(double v, bool k32) {
+    const unsigned long long x = (unsigned long long)__double_as_longlong(v);
+    unsigned al, bl, ah, bh;
+    if (k32) {
+        stage_pair<true>((unsigned)x, al, bl);
+        stage_pair<true>((unsigned)(x >> 32), ah, bh);
+    } else {
+        stage_pair<false>((unsigned)x, al, bl);
+        stage_pair<false>((unsigned)(x >> 32), ah, bh);
+    }
+    return __longlong_as_double((long long)(((unsigned long long)ah << 32) | al)) +
+           __longlong_as_double((long long)(((unsigned long long)bh << 32) | bl));
+}
+template <int kCtrl>
+__device__ __forceinline__ float partner(float v) {
+    return __uint_as_float(dpp_word<kCtrl>(__float_as_uint(v)));
+}
+template <int kCtrl>
+__device__ __forceinline__ double partner(double v) {
+    const unsigned long long x = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = dpp_word<kCtrl>((unsigned)x), hi = dpp_word<kCtrl>((unsigned)(x >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Butterfly sums of N values over the wave (xor partners 32, 16, ..., 1): every lane gets the totals, each
-// value by the same additions in the same order as alone.  The values go stage by stage in groups of up to
-// nine, so the cross-lane reads of a group are in flight together instead of one value's at a time.
+// value by the same additions as the textbook butterfly t += shfl_xor(t, off) (each stage adds a lane's value
+// and its partner's; addition commutes).  Stage by stage over all N values, so their cross-lane moves overlap.
 template <int N, typename T>
 __device__ __forceinline__ void wave_sums(T (&v)[N]) {
-    constexpr int C = 9;
 #pragma unroll
-    for (int q0 = 0; q0 < N; q0 += C) {
+    for (int q = 0; q < N; ++q) v[q] = stage_sum32(v[q], true);
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            T u[C];
+    for (int q = 0; q < N; ++q) v[q] = stage_sum32(v[q], false);
 #pragma unroll
-            for (int q = 0; q < C; ++q)
-                if (q0 + q < N) u[q] = __shfl_xor(v[q0 + q], off, 64);
+    for (int q = 0; q < N; ++q) v[q] += partner<0x128>(v[q]);   // row_ror:8
 #pragma unroll
-            for (int q = 0; q < C; ++q)
-                if (q0 + q < N) v[q0 + q] += u[q];
-        }
-    }
+    for (int q = 0; q < N; ++q) v[q] += partner<0x124>(v[q]);   // row_ror:4
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += partner<0x4E>(v[q]);    // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += partner<0xB1>(v[q]);    // quad_perm [1,0,3,2]
 }
 
 // The value of v on lane l (l uniform), for float64.
