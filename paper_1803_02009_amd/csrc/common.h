@@ -223,6 +223,25 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
     return t;
 }
 
+// The same tree for N values at once (one barrier per level for all of them): each total keeps the bits of
+// block_sum.  lds: N * BS doubles.
+template <int BS, int N>
+__device__ __forceinline__ void block_sums_tree(double (&v)[N], double *lds) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) lds[q * BS + threadIdx.x] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int s = BS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int q = 0; q < N; ++q) lds[q * BS + threadIdx.x] += lds[q * BS + threadIdx.x + s];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = lds[q * BS];
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------- damped block inverse (block-Jacobi)
 
 // Orders the LDS traffic of one wave (its lanes' writes before other lanes'

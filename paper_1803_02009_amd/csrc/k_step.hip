@@ -66,7 +66,7 @@ constexpr int kPtBlock = 256;
 // Jp r to per-block float64 partials (27 values, fixed reduction order).
 template <int K, bool JOINT = false>
 __device__ __forceinline__ void point_pass_body(const StepArgs &a, const StepScratch &s, int64_t blk) {
-    __shared__ double red[kPtBlock];
+    __shared__ double red[3 * kPtBlock];
     const int64_t n = a.pts.n;
     const int64_t i = blk * kPtBlock + threadIdx.x;
     const Pose P = JOINT ? step_pose(a) : a.pose;
@@ -110,9 +110,9 @@ __device__ __forceinline__ void point_pass_body(const StepArgs &a, const StepScr
         s.corr[i] = mt.pix;
         if (a.corr_out) a.corr_out[i] = mt.pix;
     }
-    const double t0 = block_sum<kPtBlock>(r2, red);
-    const double t1 = block_sum<kPtBlock>(cnt, red);
-    const double t2 = block_sum<kPtBlock>(ra, red);
+    double tv[3] = {r2, cnt, ra};
+    block_sums_tree<kPtBlock>(tv, red);
+    const double t0 = tv[0], t1 = tv[1], t2 = tv[2];
     if (threadIdx.x == 0) {
         s.pt_part[3 * blk + 0] = t0;
         s.pt_part[3 * blk + 1] = t1;
