@@ -31,56 +31,63 @@ __global__ void pose_init_kernel(Pose P, float *pose_dev) {
 // ---------------------------------------------------------------- border B_j
 
 constexpr int kBorderWaves = 4;
+constexpr int kBorderSlices = 5;   // entry slices per wave: lane = 12 * slice + (3c + a); lanes 60-63 only load
 
+// One workgroup per node row.  Each wave stages 64 of the row's list entries at a time (w d, n', Jp, all
+// float4-aligned) and only reads its own: lane (slice, 3c + a) adds, over the staged entries t = slice,
+// slice + 5, ..., (w d_c n'_a) Jp_k into its six columns k.  The partial sums are added slice by slice and wave
+// by wave in a fixed order.
 __global__ void __launch_bounds__(kBorderWaves * 64) border_rows_kernel(StepArgs a, StepScratch s, float *B) {
-    __shared__ float ent[kBorderWaves][64][14];   // per wave: w d (4), n' (3), Jp (6), pad
-    __shared__ float part[kBorderWaves][72];
+    __shared__ float4 ent[kBorderWaves][64][4];   // per wave: (w d, w), (n', 0), Jp 0-3, (Jp 4-5, 0, 0)
+    __shared__ float part[kBorderWaves][kBorderSlices][72];
     const int j = blockIdx.x;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int l0 = a.g.list_ptr[j], l1 = a.g.list_ptr[j + 1];
-    // this lane's entries (3c + a) * 6 + k of B_j: lane and lane + 64 (< 72)
-    const int e0 = lane, e1 = lane + 64;
-    const int c0 = (e0 / 6) / 3, a0 = (e0 / 6) % 3, k0 = e0 % 6;
-    const int c1 = (e1 / 6) / 3, a1 = (e1 / 6) % 3, k1 = e1 % 6;
-    float acc0 = 0.f, acc1 = 0.f;
-    // wave w takes the list entries base0 + 64 w .. + 63 of each pass: a fixed order per wave
+    const int slice = lane / 12, ca = lane % 12, c = ca / 3, aa = ca % 3;
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float4 (*E)[4] = ent[wave];
     for (int base0 = l0; base0 < l1; base0 += 64 * kBorderWaves) {
         const int base = base0 + 64 * wave;
         const int le = base + lane;
-        float (*E)[14] = ent[wave];
         if (le < l1) {
             const int p = a.g.list_pts[le];
             const float4 dw = s.lpa[le];
             const float4 nr = s.nr[p];
             const float4 j0 = s.jp[2 * (size_t)p], j1 = s.jp[2 * (size_t)p + 1];
-            E[lane][0] = dw.w * dw.x;
-            E[lane][1] = dw.w * dw.y;
-            E[lane][2] = dw.w * dw.z;
-            E[lane][3] = dw.w;
-            E[lane][4] = nr.x;
-            E[lane][5] = nr.y;
-            E[lane][6] = nr.z;
-            E[lane][7] = j0.x;
-            E[lane][8] = j0.y;
-            E[lane][9] = j0.z;
-            E[lane][10] = j0.w;
-            E[lane][11] = j1.x;
-            E[lane][12] = j1.y;
+            E[lane][0] = make_float4(dw.w * dw.x, dw.w * dw.y, dw.w * dw.z, dw.w);
+            E[lane][1] = make_float4(nr.x, nr.y, nr.z, 0.f);
+            E[lane][2] = j0;
+            E[lane][3] = j1;
         }
-        __syncthreads();
+        wave_sync();
         const int cnt = max(0, min(64, l1 - base));
-        for (int t = 0; t < cnt; ++t) {
-            acc0 = fmaf(E[t][c0] * E[t][4 + a0], E[t][7 + k0], acc0);
-            if (e1 < 72) acc1 = fmaf(E[t][c1] * E[t][4 + a1], E[t][7 + k1], acc1);
-        }
-        __syncthreads();
+        if (slice < kBorderSlices)
+            for (int t = slice; t < cnt; t += kBorderSlices) {
+                const float *wd = reinterpret_cast<const float *>(&E[t][0]);
+                const float *nn = reinterpret_cast<const float *>(&E[t][1]);
+                const float f = wd[c] * nn[aa];
+                const float4 ja = E[t][2], jb = E[t][3];
+                acc[0] = fmaf(f, ja.x, acc[0]);
+                acc[1] = fmaf(f, ja.y, acc[1]);
+                acc[2] = fmaf(f, ja.z, acc[2]);
+                acc[3] = fmaf(f, ja.w, acc[3]);
+                acc[4] = fmaf(f, jb.x, acc[4]);
+                acc[5] = fmaf(f, jb.y, acc[5]);
+            }
+        wave_sync();   // the wave's reads of this pass before its next writes
     }
-    part[wave][e0] = acc0;
-    if (e1 < 72) part[wave][e1] = acc1;
+    if (slice < kBorderSlices)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) part[wave][slice][ca * 6 + k] = acc[k];
     __syncthreads();
     if (threadIdx.x < 72) {
         const int e = threadIdx.x;
-        B[(size_t)j * 72 + e] = a.w_data * (((part[0][e] + part[1][e]) + part[2][e]) + part[3][e]);
+        float t = part[0][0][e];
+        for (int sl = 1; sl < kBorderSlices; ++sl) t += part[0][sl][e];
+#pragma unroll
+        for (int w = 1; w < kBorderWaves; ++w)
+            for (int sl = 0; sl < kBorderSlices; ++sl) t += part[w][sl][e];
+        B[(size_t)j * 72 + e] = a.w_data * t;
     }
 }
 
