@@ -831,14 +831,19 @@ struct MfmaOp<_Float16> {
 constexpr int kLpThreads = 128;
 constexpr int kLpWaves = kLpThreads / kWave;
 
+constexpr int kLpSlotsPerWave = kAsmSlots / kLpWaves;
+
 template <int K, typename T>
 struct LpShared {
-    float acc[kLpWaves][MISSLAM_MAX_ROW * 144];
-    T Jt[kLpWaves][12 * (K + 1)][kBatch];   // per entry: J of node j (rows 0-11), then of its k set nodes
+    float acc[kAsmSlots][144];   // blocks per slot; wave w's slots start at w kLpSlotsPerWave
+    union {
+        // per entry: J of node j (rows 0-11), then of its k set nodes; 16-byte groups of 8 entries
+        alignas(16) T Jt[kLpWaves][12 * (K + 1)][kBatch];
+        RowFin<kLpThreads> fin;   // once the data term is complete
+    };
     uint32_t key[kLpWaves][kBatch][2];
     double gw[kLpWaves][12];
     RowNode rn;
-    RowFin<kLpThreads> fin;
 };
 
 // Same rows as assemble_rows_kernel, but the data term is formed from the
@@ -865,15 +870,26 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
     const int nslots = min(re - rb, MISSLAM_MAX_ROW);
     for (int t = tid; t < (re - rb - nslots) * 144; t += kLpThreads) a.blocks[(size_t)(rb + nslots) * 144 + t] = 0.f;
     for (int t = tid; t < nslots; t += kLpThreads) sh.rn.cols[t] = a.g.col_idx[rb + t];
-    for (int t = lane; t < MISSLAM_MAX_ROW * 144; t += kWave) sh.acc[wave][t] = 0.f;
+    // as in the float32 rows: the waves split the point list, each with slots of its own, unless the row has
+    // more slots than a wave holds (then the first wave takes the whole list over every slot); each wave
+    // clears the slots it uses
+    const bool split = nslots <= kLpSlotsPerWave;
+    const int nw = split ? kLpWaves : 1;
+    float(*accw)[144] = sh.acc + (split ? wave * kLpSlotsPerWave : 0);
+    {
+        const int nclr = (wave < nw ? (split ? kLpSlotsPerWave : kLpWaves * kLpSlotsPerWave) : 0) * 144 / 4;
+        for (int t = lane; t < nclr; t += kWave)
+            reinterpret_cast<float4 *>(&accw[0][0])[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
 
     const float gjx = a.nd.gx[j], gjy = a.nd.gy[j], gjz = a.nd.gz[j];
     const float lamf = step_lambda(a);
     const double e_reg = row_prepare(a, sh.rn, j, nslots, gjx, gjy, gjz);
     const int lb = a.g.list_ptr[j];
     const int cnt = a.g.list_ptr[j + 1] - lb;
-    const int quota = (cnt + kLpWaves - 1) / kLpWaves;
-    const int my0 = min(cnt, wave * quota), my1 = min(cnt, my0 + quota);
+    const int quota = (cnt + nw - 1) / nw;
+    const int my0 = wave < nw ? min(cnt, wave * quota) : cnt;
+    const int my1 = wave < nw ? min(cnt, my0 + quota) : cnt;
     const int nbatch = (my1 - my0 + kBatch - 1) / kBatch;
     const int r16 = lane % 16, kb = 8 * (lane / 16);
 
@@ -898,7 +914,7 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int row = 4 * (lane / 16) + i;
-                        if (row < 12) sh.acc[wave][slot * 144 + row * 12 + col % 12] += D[q][i];
+                        if (row < 12) accw[slot][row * 12 + col % 12] += D[q][i];
                     }
                 }
             }
@@ -971,23 +987,29 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
             }
             const uint64_t later = t + 1 < 64 ? (starts >> (t + 1)) : 0ull;
             const int t1 = later ? min(nb, t + 1 + __builtin_ctzll(later)) : nb;
-            for (int c0 = t; c0 < t1; c0 += 32) {
-                typename MfmaOp<T>::vec av;
+            // 32-entry chunks from the run's first group of 8: each lane reads its 8 entries of a row as one
+            // 16-byte group and zeroes those outside [t, t1) with a bit mask (which also keeps out whatever the
+            // staging holds there)
+            for (int c0 = t & ~7; c0 < t1; c0 += 32) {
+                typedef typename MfmaOp<T>::vec vec;
+                typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+                const int g = c0 + kb;          // a group that starts before t1 ends inside the 64 entries
+                u32x4 mk = {0u, 0u, 0u, 0u};
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int e = c0 + kb + i;
-                    av[i] = (e < t1 && r16 < 12) ? sh.Jt[wave][r16][e] : (T)0.f;
+                for (int d = 0; d < 4; ++d) {
+                    const int e = g + 2 * d;
+                    mk[d] = (e >= t && e < t1 ? 0x0000FFFFu : 0u) | (e + 1 >= t && e + 1 < t1 ? 0xFFFF0000u : 0u);
                 }
+                const bool in = g < t1;
+                u32x4 ar = {0u, 0u, 0u, 0u};
+                if (in && r16 < 12) ar = *reinterpret_cast<const u32x4 *>(&sh.Jt[wave][r16][g]);
+                const vec av = __builtin_bit_cast(vec, ar & mk);
 #pragma unroll
                 for (int q = 0; q < NT; ++q) {
                     const int col = 16 * q + r16;
-                    typename MfmaOp<T>::vec bv;
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        const int e = c0 + kb + i;
-                        bv[i] = (e < t1 && col < 12 * K) ? sh.Jt[wave][12 + col][e] : (T)0.f;
-                    }
-                    D[q] = MfmaOp<T>::run(av, bv, D[q]);
+                    u32x4 br = {0u, 0u, 0u, 0u};
+                    if (in && col < 12 * K) br = *reinterpret_cast<const u32x4 *>(&sh.Jt[wave][12 + col][g]);
+                    D[q] = MfmaOp<T>::run(av, __builtin_bit_cast(vec, br & mk), D[q]);
                 }
             }
             t = t1;
@@ -1001,12 +1023,14 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
         for (int q = 0; q < 12; ++q) sh.gw[wave][q] = gacc[q];
     }
     __syncthreads();
-    for (int t = tid; t < nslots * 144; t += kLpThreads) {
-        float v = sh.acc[0][t];
+    if (split)
+        for (int t = tid; t < nslots * 144; t += kLpThreads) {
+            const int sl = t / 144, en = t - sl * 144;
+            float v = sh.acc[sl][en];
 #pragma unroll
-        for (int w = 1; w < kLpWaves; ++w) v += sh.acc[w][t];
-        sh.acc[0][t] = v;
-    }
+            for (int w = 1; w < kLpWaves; ++w) v += sh.acc[w * kLpSlotsPerWave + sl][en];   // waves in order
+            sh.acc[sl][en] = v;
+        }
     if (tid < 12) {
         double v = sh.gw[0][tid];
 #pragma unroll
@@ -1014,7 +1038,7 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
         sh.rn.gd[tid] = v;
     }
     __syncthreads();
-    auto data = [&](int sl, int R, int C, bool) { return sh.acc[0][sl * 144 + R * 12 + C]; };
+    auto data = [&](int sl, int R, int C, bool) { return sh.acc[sl][R * 12 + C]; };
     row_finalize<kLpThreads>(a, s, sh.rn, sh.fin, j, rb, nslots, e_reg, lamf, data, rr_out);
 }
 
