@@ -457,6 +457,17 @@ struct TileRange {
     int U;           // distinct columns with a slot
 };
 
+// n float4 from src (global) straight into LDS at dst, 16 bytes per lane (global_load_lds_dwordx4: lane i of a
+// wave fills dst + i, dst the same for the whole wave), every load in flight at once and no registers held.
+// The caller waits (vmcnt) and synchronises before reading dst.
+__device__ __forceinline__ void lds_copy16(const float4 *src, float4 *dst, int n) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    for (int q0 = wave * kWave; q0 < n; q0 += kPcgThreads)
+        if (q0 + lane < n)
+            __builtin_amdgcn_global_load_lds(static_cast<const void *>(src + q0 + lane),
+                                             (__attribute__((address_space(3))) void *)(dst + q0), 16, 0, 0);
+}
+
 // Setup of workgroup wg's share: its rows' blocks (as many as fit) into hc, their preconditioner blocks into
 // mc, and the distinct-column map with at most max_unique (<= kMaxUnique) slots.  firstmap: map_ints ints of
 // scratch LDS (free again on return).
@@ -470,15 +481,6 @@ __device__ __forceinline__ TileRange tile_setup(const PcgArgs &A, int rows_per_w
     const int b1 = min(A.row_ptr[R.r1], A.cap);
     R.nb = min(b1 - R.b0, kMaxBlocksWg);
     R.cached = min(R.nb, cache_blocks);
-    {   // 16-byte copies, several in flight per thread
-        const float4 *src = reinterpret_cast<const float4 *>(A.blocks + (size_t)R.b0 * 144);
-        const int n4 = R.cached * 36;
-#pragma unroll 4
-        for (int q = threadIdx.x; q < n4; q += kPcgThreads) hc4[q] = src[q];
-        const float4 *srcm = reinterpret_cast<const float4 *>(A.minv + (size_t)R.r0 * 144);
-        float4 *dstm = reinterpret_cast<float4 *>(mc);
-        for (int q = threadIdx.x; q < (R.r1 - R.r0) * 36; q += kPcgThreads) dstm[q] = srcm[q];
-    }
     // distinct columns: a block whose column appears at no earlier block of the workgroup gets the next
     // slot (in block order, by a workgroup scan); later blocks of that column share it
     if (threadIdx.x == 0) {
@@ -494,6 +496,11 @@ __device__ __forceinline__ TileRange tile_setup(const PcgArgs &A, int rows_per_w
         atomicMin(&t.cmin_s, c);
         atomicMax(&t.cmax_s, c);
     }
+    // the cached blocks and the rows' preconditioner blocks, straight into LDS: they arrive while the rest of
+    // the map is built (LDS work only), and are waited for at its end
+    lds_copy16(reinterpret_cast<const float4 *>(A.blocks + (size_t)R.b0 * 144), hc4, R.cached * 36);
+    lds_copy16(reinterpret_cast<const float4 *>(A.minv + (size_t)R.r0 * 144), reinterpret_cast<float4 *>(mc),
+               (R.r1 - R.r0) * 36);
     __syncthreads();
     const int cmin = t.cmin_s, crange = t.cmax_s - t.cmin_s + 1;
     const bool mapped = nb > 0 && crange <= map_ints;
@@ -564,6 +571,7 @@ __device__ __forceinline__ TileRange tile_setup(const PcgArgs &A, int rows_per_w
         const int q = threadIdx.x * kPerT + e;
         if (q < nb && firstpos[e] != q) t.bmap[q] = t.bmap[firstpos[e]];   // a first occurrence: already set
     }
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's LDS loads have landed (vmcnt); the barrier covers every wave's
     __syncthreads();
     R.U = t.cnt_u;
     return R;
