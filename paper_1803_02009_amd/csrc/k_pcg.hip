@@ -719,18 +719,32 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
     const double lam = (double)(A.lambda_dev ? *A.lambda_dev : A.lambda);
     float *hc = reinterpret_cast<float *>(dyn4);       // cached blocks
     float *mc = hc + (size_t)cache_blocks * 144;       // preconditioner blocks of the rows
+    const int lr = threadIdx.x / 12, a = threadIdx.x % 12;
+    // what does not depend on the setup is requested before it, so its latency hides behind the block copy:
+    // this thread's gradient entry and its row's block range (and, joint form, its row of the border)
+    const int r0e = min(A.m, wg * rows_per_wg), r1e = min(A.m, r0e + rows_per_wg);
+    const bool act = lr < kRowsPerBlk && r0e + lr < r1e;
+    float g_own = 0.f;
+    int rp0 = 0, rp1 = 0;
+    float brow[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // joint: this entry's row of the border
+    if (act) {
+        g_own = A.g[(size_t)(r0e + lr) * 12 + a];
+        rp0 = A.row_ptr[r0e + lr];
+        rp1 = A.row_ptr[r0e + lr + 1];
+        if constexpr (kJoint)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) brow[k] = jx.B[(size_t)(r0e + lr) * 72 + a * 6 + k];
+    }
     const TileRange R = tile_setup(A, rows_per_wg, cache_blocks, wg, dyn4, mc, tl, reinterpret_cast<int *>(zc4),
                                    kMaxUnique * 12, kMaxUnique);
     const int r0 = R.r0, r1 = R.r1, b0 = R.b0, nb = R.nb, cached = R.cached, U = R.U;
     const int *bmap = tl.bmap, *colL = tl.colL, *ucol = tl.ucol, *lslot = tl.lslot;
-    const int lr = threadIdx.x / 12, a = threadIdx.x % 12;
     const int j = r0 + lr;
-    const bool act = lr < kRowsPerBlk && j < r1;
     const int li = lr * 12 + a;
     bool broken = false;
     // this thread's row: its blocks q in [rq0, rq1) of the workgroup; fast = all cached with a staged column
-    const int rq0 = act ? min(A.row_ptr[j], A.cap) - b0 : 0;
-    const int rq1 = act ? min(A.row_ptr[j + 1], A.cap) - b0 : 0;
+    const int rq0 = act ? min(rp0, A.cap) - b0 : 0;
+    const int rq1 = act ? min(rp1, A.cap) - b0 : 0;
     bool fast = rq1 <= cached;
     for (int q = rq0; q < rq1 && fast; ++q) fast = bmap[q] >= 0;
     // Blocks whose column is one of this workgroup's own rows (bit i: block rq0 + i, fast rows only): their
@@ -796,16 +810,12 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
     // init: r = -g, z = M r, x = 0
     float r = 0.f, z = 0.f;
     if (act) {
-        r = -A.g[(size_t)j * 12 + a];
+        r = -g_own;
         vr[li] = r;
         vx[li] = 0.f;
     }
-    float brow[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // joint: this entry's row of the border
     double btz[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};    // joint: sum_j B_j^T z_j of the current z
     if constexpr (kJoint) {
-        if (act)
-#pragma unroll
-            for (int k = 0; k < 6; ++k) brow[k] = jx.B[(size_t)j * 72 + a * 6 + k];
         if (threadIdx.x < 78) sysl[threadIdx.x] = jx.sys[threadIdx.x];
         __syncthreads();
         if (threadIdx.x == kPoseThread) {   // r_p = -g_p, z_p = M_p r_p, p_p = q_p = x_p = 0

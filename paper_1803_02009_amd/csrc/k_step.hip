@@ -349,13 +349,15 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
     const float wd = a.w_data, wreg = a.w_reg, wrot = a.w_rot;
     float *outb = a.blocks + (size_t)rb * 144;
     // each thread owns entries en of every block of the row: its index arithmetic is done once, and the slots'
-    // loads are independent (straight-line bodies, selects, no branches)
-    for (int en = tid; en < 144; en += NT) {
+    // loads are independent (straight-line bodies, selects, no branches).  The 144 % NT entries left after the
+    // full passes share their slots among NT / (144 % NT) threads each (slots part, part + share, ...), so no
+    // wave runs a second pass over every slot alone.
+    auto out_entry = [&](int en, int sl0, int sstep) {
         const int R = en / 12, C = en % 12;
         const int c = R / 3, aa = R % 3, c2 = C / 3, a2 = C % 3;
         const int ic = c < 3 ? c : 0, ic2 = c2 < 3 ? c2 : 0;
 #pragma unroll 4
-        for (int sl = 0; sl < nslots; ++sl) {   // edges j -> l; the diagonal slot is written below
+        for (int sl = sl0; sl < nslots; sl += sstep) {   // edges j -> l; the diagonal slot is written below
             const float hd = data(sl, R, C, true);
             const float rgc = rn.rg[sl][ic], rgc2 = rn.rg[sl][ic2];
             const float eh_c = c < 3 ? rgc : 1.f;
@@ -370,7 +372,7 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
                 if (rr_out) rr_out[(size_t)(rb + sl) * 144 + en] = rr;
             }
         }
-        if (dsl >= 0) {   // the diagonal block: regulariser and rotation terms of node j
+        if (dsl >= 0 && dsl % sstep == sl0) {   // the diagonal block: regulariser and rotation terms of node j
             const float hd = data(dsl, R, C, false);
             float reg = 0.f, rot = 0.f;
             if (aa == a2) {
@@ -387,6 +389,12 @@ __device__ __forceinline__ void row_finalize(const StepArgs &a, const StepScratc
             outb[(size_t)dsl * 144 + en] = h;
             if (rr_out) rr_out[(size_t)(rb + dsl) * 144 + en] = rr;
         }
+    };
+    constexpr int kRem = 144 % NT, kFull = 144 - kRem;
+    for (int en = tid; en < kFull; en += NT) out_entry(en, 0, 1);
+    if constexpr (kRem > 0) {
+        static_assert(NT % kRem == 0, "the remaining entries share whole groups of threads");
+        out_entry(kFull + tid % kRem, tid / kRem, NT / kRem);
     }
     __syncthreads();
     // the block-Jacobi preconditioner of this row on wave 0 and the gradient on the last wave (with one wave,
