@@ -344,12 +344,20 @@ misslam_status misslam_warp(const misslam_points *points, const misslam_nodes *n
     return e == hipSuccess ? MISSLAM_OK : hip_fail(e);
 }
 
-static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, int64_t n, int m,
+// The point pass, the assembly (and the key-point rows), then the step's energy report.  With defer set the
+// report is not launched: its arguments go to *defer for the solve that follows, which forms it in an extra
+// workgroup (or launches it when it cannot), and the assembly clears the solve's sync area (zero_words).
+static hipError_t linearize(const msl::StepArgs &a0, const msl::StepScratch &s, int64_t n, int m,
                             misslam_report *rep, float reject, hipStream_t st, unsigned *zero_words = nullptr,
                             int zero_count = 0, const msl::KeyArgs *kp = nullptr,
-                            const msl::CorrScratch *corr = nullptr) {
+                            const msl::CorrScratch *corr = nullptr, msl::ReportArgs *defer = nullptr) {
     hipError_t e;
     const bool keys = kp && corr && kp->count > 0;
+    msl::StepArgs a = a0;
+    if (defer) {
+        a.zero_words = zero_words;
+        a.zero_count = zero_count;
+    }
     {
         Timed t(PH_POINT_PASS, st);
         e = msl::launch_point_pass(a, s, st, keys ? kp : nullptr, keys ? corr : nullptr);
@@ -361,6 +369,10 @@ static hipError_t linearize(const msl::StepArgs &a, const msl::StepScratch &s, i
     if (e == hipSuccess && keys) {
         Timed t(PH_CORR, st);
         e = msl::launch_corr_rows(a, *kp, *corr, st);
+    }
+    if (e == hipSuccess && defer) {
+        msl::report_args(s, n, m, rep, reject, keys ? corr->kp_energy : nullptr, keys ? kp->count : 0, *defer);
+        return e;
     }
     if (e == hipSuccess) {
         Timed t(PH_ENERGY, st);
@@ -377,14 +389,19 @@ static hipError_t solve_persistent(const msl::GraphView &g, int m, const float *
                                    const float *minv, float lambda, int iters, float *delta, const msl::PcgScratch &s,
                                    misslam_report *rep, float *params, hipStream_t st, bool coop,
                                    int zeroed_words = 0, const float *lambda_dev = nullptr, bool kernels = false,
-                                   unsigned spin = 0, bool textbook = false) {
+                                   unsigned spin = 0, bool textbook = false,
+                                   const msl::ReportArgs *report = nullptr) {
     bool used = false;
     hipError_t e = kernels ? hipSuccess
                            : msl::launch_pcg_persistent(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep,
                                                         params, st, &used, coop, zeroed_words, lambda_dev, spin,
-                                                        textbook);
-    if (e == hipSuccess && !used)
-        e = msl::launch_pcg_update(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st, lambda_dev);
+                                                        textbook, report);
+    if (e == hipSuccess && !used) {
+        if (report && report->rep) e = msl::launch_energy_report(*report, st);   // not formed by a solve workgroup
+        if (e == hipSuccess)
+            e = msl::launch_pcg_update(g, m, blocks, gvec, minv, lambda, iters, delta, s, rep, params, st,
+                                       lambda_dev);
+    }
     return e;
 }
 
@@ -609,13 +626,15 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
         }
         if (!lowp) {
             if (lm) a.lambda_dev = L.lm_lambda;
+            msl::ReportArgs ra;   // the step's report, formed by the solve's extra workgroup
             e = linearize(a, L.step, n, m, rep + it, params->reject_threshold, st, L.pcg.bar, msl::msl_sync_words(m),
-                          kp, &L.corr);
+                          kp, &L.corr, &ra);
             if (e == hipSuccess) {
                 Timed t(PH_PCG, st);
                 e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
                                      L.delta, L.pcg, rep + it, lm ? nullptr : nodes->params, st, coop,
-                                     msl::msl_sync_words(m), lm ? L.lm_lambda : nullptr, kernels, spin, textbook);
+                                     msl::msl_sync_words(m), lm ? L.lm_lambda : nullptr, kernels, spin, textbook,
+                                     &ra);
             }
             if (e == hipSuccess && lm) {
                 // the trial point x + dx: its objective decides whether the step is taken

@@ -412,6 +412,83 @@ __device__ __forceinline__ void wave_sums(T (&v)[N]) {
     for (int q = 0; q < N; ++q) v[q] += partner<0xB1>(v[q]);    // quad_perm [1,0,3,2]
 }
 
+// A Gauss-Newton step's report, by one workgroup of 256 threads: the energies (the point pass's data partials,
+// the assembly's node partials, the key points' energies) summed in a fixed order, n_valid, and the
+// NONFINITE / FRAME_REJECT flags ORed into rep->flags; zero_words (zero_count words, if set) are cleared first.
+__device__ __forceinline__ void energy_report_body(const double *__restrict__ pt_part, int npb,
+                                                   const double *__restrict__ node_part, int m, misslam_report *rep,
+                                                   float reject_thr, unsigned *__restrict__ zero_words,
+                                                   int zero_count, const double *__restrict__ kp_energy = nullptr,
+                                                   int kp_count = 0) {
+    __shared__ double red[6][256 / kWave];
+    if (zero_words)   // the next solve's sync area
+        for (int t = threadIdx.x; t < zero_count / 4; t += 256)
+            reinterpret_cast<uint4 *>(zero_words)[t] = make_uint4(0u, 0u, 0u, 0u);
+    // thread t adds entries t, t + 256, ... in order; the loads of eight entries are issued before their adds
+    constexpr int U = 8;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int t0 = threadIdx.x; t0 < npb; t0 += U * 256) {
+        double a[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = min(t0 + 256 * u, npb - 1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a[u][c] = pt_part[3 * t + c];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t0 + 256 * u < npb) {
+                v[0] += a[u][0];
+                v[1] += a[u][1];
+                v[2] += a[u][2];
+            }
+    }
+    for (int t0 = threadIdx.x; t0 < m; t0 += U * 256) {
+        double a[U][2];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = min(t0 + 256 * u, m - 1);
+            a[u][0] = node_part[2 * t];
+            a[u][1] = node_part[2 * t + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t0 + 256 * u < m) {
+                v[3] += a[u][0];
+                v[4] += a[u][1];
+            }
+    }
+    for (int t0 = threadIdx.x; t0 < kp_count; t0 += U * 256) {
+        double a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = kp_energy[min(t0 + 256 * u, kp_count - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (t0 + 256 * u < kp_count) v[5] += a[u];
+    }
+    // wave butterflies, then the four waves in order: a fixed summation order
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    wave_sums(v);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) red[q][wave] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot[6];
+        for (int q = 0; q < 6; ++q) tot[q] = ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
+        const double ed = tot[0], nv = tot[1], sa = tot[2], er = tot[3], eg = tot[4];
+        rep->e_data = ed;
+        rep->e_rot = er;
+        rep->e_reg = eg;
+        rep->n_valid = (int32_t)nv;
+        rep->e_corr = tot[5];
+        int flags = 0;
+        if (!isfinite(ed) || !isfinite(er) || !isfinite(eg) || !isfinite(tot[5])) flags |= MISSLAM_FLAG_NONFINITE;
+        if (reject_thr > 0.f && nv > 0 && sa / nv > (double)reject_thr) flags |= MISSLAM_FLAG_FRAME_REJECT;
+        rep->flags |= flags;
+    }
+}
+
 // The value of v on lane l (l uniform), for float64.
 __device__ __forceinline__ double readlane_f64(double v, int l) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);

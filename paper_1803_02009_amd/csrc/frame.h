@@ -109,6 +109,8 @@ struct StepArgs {
     const float *lambda_dev = nullptr;   // optional device damping, read in place of lambda
     const float *pose_dev = nullptr;     // optional device pose (R row-major, T), read in place of pose
     int asm_waves = 2;                   // assembly tile: waves per node row, 1 or 2
+    unsigned *zero_words = nullptr;      // optional: words the assembly clears (the next solve's sync area)
+    int zero_count = 0;                  // a multiple of 4
 };
 
 __device__ __forceinline__ Pose step_pose(const StepArgs &a) {
@@ -342,6 +344,12 @@ hipError_t launch_energy_total(const misslam_report *rep, float w_data, float w_
 hipError_t launch_energy_report(const StepScratch &s, int64_t n, int m, misslam_report *rep, float reject_thr,
                                 hipStream_t st, unsigned *zero_words = nullptr, int zero_count = 0,
                                 const double *kp_energy = nullptr, int kp_count = 0);
+struct ReportArgs;
+// The same report's arguments, for a solve that forms it in an extra workgroup (launch_pcg_persistent), and
+// the report kernel on them (when the solve does not).
+void report_args(const StepScratch &s, int64_t n, int m, misslam_report *rep, float reject_thr,
+                 const double *kp_energy, int kp_count, ReportArgs &out);
+hipError_t launch_energy_report(const ReportArgs &ra, hipStream_t st);
 hipError_t launch_bjacobi(const GraphView &g, int m, const float *blocks, float lambda, float *minv,
                           int32_t *flags, hipStream_t st);
 // PCG solve into delta; when params != nullptr also applies params += delta (the GN update).  lambda_dev
@@ -369,7 +377,19 @@ hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks,
                                  float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
                                  float *params, hipStream_t st, bool *used, bool cooperative,
                                  int zeroed_words = 0, const float *lambda_dev = nullptr, unsigned spin = 0,
-                                 bool textbook = false);
+                                 bool textbook = false, const ReportArgs *report = nullptr);
+// A step's energy report (energy_report_body) run by one extra workgroup of the one-launch solve: its inputs
+// come from the kernels before the solve, and the step commit after it reads its flags.
+struct ReportArgs {
+    const double *pt_part = nullptr;
+    int npb = 0;
+    const double *node_part = nullptr;
+    int m = 0;
+    misslam_report *rep = nullptr;   // null: no report workgroup
+    float reject = 0.f;
+    const double *kp_energy = nullptr;
+    int kp_count = 0;
+};
 // The pose columns of the joint system (pose + ED unknowns) for its one-launch solve.
 struct JointExtra {
     const float *B = nullptr;      // the border: row 12 j + a, column k at B[j * 72 + a * 6 + k]

@@ -1066,9 +1066,18 @@ __device__ __forceinline__ void pcg_persistent_body(const PcgArgs &A, int rows_p
     if (broken && threadIdx.x == 0) atomicOr(&rep->flags, MISSLAM_FLAG_SYNC_TIMEOUT);
 }
 
+// The solve's G workgroups, and with ra.rep set one more (the last) that forms the step's energy report and
+// exits: it takes no part in the exchanges.
 __global__ void __launch_bounds__(kPcgThreads) pcg_persistent_kernel(PcgArgs A, int rows_per_wg, int cache_blocks,
-                                                                    unsigned *bar, misslam_report *rep) {
-    pcg_persistent_body<false>(A, rows_per_wg, cache_blocks, bar, 0, blockIdx.x, gridDim.x, rep, JointExtra{});
+                                                                    unsigned *bar, misslam_report *rep,
+                                                                    ReportArgs ra) {
+    const int G = (int)gridDim.x - (ra.rep ? 1 : 0);
+    if ((int)blockIdx.x == G) {
+        energy_report_body(ra.pt_part, ra.npb, ra.node_part, ra.m, ra.rep, ra.reject, nullptr, 0, ra.kp_energy,
+                           ra.kp_count);
+        return;
+    }
+    pcg_persistent_body<false>(A, rows_per_wg, cache_blocks, bar, 0, blockIdx.x, G, rep, JointExtra{});
 }
 
 __global__ void __launch_bounds__(kPcgThreads) jpcg_tiled_kernel(PcgArgs A, int rows_per_wg, int cache_blocks,
@@ -1419,7 +1428,6 @@ __global__ void __launch_bounds__(kPcgThreads) ppcg_finish_kernel(const double *
 // on a surface graph) still fit the LDS left beside the static arrays.  One
 // workgroup per CU must hold them all, so a larger system packs up to
 // kRowsPerBlk rows (blocks beyond the LDS cache are read from global memory).
-using PersistentKernel = void (*)(PcgArgs, int, int, unsigned *, misslam_report *);
 
 struct PersistentShape {
     int max_blocks = -1, max_lds = 0;
@@ -1463,7 +1471,7 @@ static int persistent_grid(const PersistentShape &sh, int m, int &rows_per_wg, i
     return G;
 }
 
-static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes, bool textbook) {
+static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes, bool textbook, int extra_wgs = 0) {
     static PersistentShape tb, pp;
     PersistentShape &sh = textbook ? tb : pp;
     if (sh.max_blocks < 0) {
@@ -1472,16 +1480,21 @@ static int persistent_grid(int m, int &rows_per_wg, int &lds_bytes, bool textboo
         else
             persistent_limits(ppcg_persistent_kernel, sh);
     }
-    return persistent_grid(sh, m, rows_per_wg, lds_bytes);
+    const int G = persistent_grid(sh, m, rows_per_wg, lds_bytes);
+    return G > 0 && G + extra_wgs <= sh.max_blocks ? G : 0;
 }
 
 hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks, const float *gvec, const float *minv,
                                  float lambda, int iters, float *delta, const PcgScratch &s, misslam_report *rep,
                                  float *params, hipStream_t st, bool *used, bool cooperative, int zeroed_words,
-                                 const float *lambda_dev, unsigned spin, bool textbook) {
+                                 const float *lambda_dev, unsigned spin, bool textbook,
+                                 const ReportArgs *report) {
     *used = false;
+    ReportArgs ra;
+    if (report && textbook) ra = *report;   // the report workgroup rides with the textbook solve only
+    const int extra = ra.rep ? 1 : 0;
     int rows = 0, lds = 0;
-    const int G = persistent_grid(m, rows, lds, textbook);
+    const int G = persistent_grid(m, rows, lds, textbook, extra);
     if (G <= 0 || G > s.nblk_max) return hipSuccess;
     PcgArgs A;
     A.row_ptr = g.row_ptr;
@@ -1514,14 +1527,26 @@ hipError_t launch_pcg_persistent(const GraphView &g, int m, const float *blocks,
     const int words = MSL_WG_WORDS * G;
     if (zeroed_words < words)
         hipLaunchKernelGGL(fill_u32_kernel_pcg, dim3((words + 255) / 256), dim3(256), 0, st, bar, words);
-    const PersistentKernel kern = textbook ? pcg_persistent_kernel : ppcg_persistent_kernel;
-    hipError_t e;
-    if (cooperative) {
+    hipError_t e = hipSuccess;
+    if (report && report->rep && !textbook) e = launch_energy_report(*report, st);   // not formed by the solve
+    if (e != hipSuccess) return e;
+    if (textbook) {
+        if (cooperative) {
+            void *args[] = {&A, (void *)&rows, (void *)&cache_blocks, &bar, &rep, &ra};
+            e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(pcg_persistent_kernel), dim3(G + extra),
+                                           dim3(kPcgThreads), args, (unsigned)lds, st);
+        } else {
+            hipLaunchKernelGGL(pcg_persistent_kernel, dim3(G + extra), dim3(kPcgThreads), (unsigned)lds, st, A, rows,
+                               cache_blocks, bar, rep, ra);
+            e = hipGetLastError();
+        }
+    } else if (cooperative) {
         void *args[] = {&A, (void *)&rows, (void *)&cache_blocks, &bar, &rep};
-        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(G), dim3(kPcgThreads), args,
-                                       (unsigned)lds, st);
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(ppcg_persistent_kernel), dim3(G),
+                                       dim3(kPcgThreads), args, (unsigned)lds, st);
     } else {
-        hipLaunchKernelGGL(kern, dim3(G), dim3(kPcgThreads), (unsigned)lds, st, A, rows, cache_blocks, bar, rep);
+        hipLaunchKernelGGL(ppcg_persistent_kernel, dim3(G), dim3(kPcgThreads), (unsigned)lds, st, A, rows,
+                           cache_blocks, bar, rep);
         e = hipGetLastError();
     }
     if (e == hipSuccess) *used = true;

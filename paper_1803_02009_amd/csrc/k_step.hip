@@ -806,6 +806,9 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
 template <int K, int W>
 __global__ void __launch_bounds__(kWave * W) __attribute__((amdgpu_waves_per_eu(4)))
 assemble_rows_kernel(StepArgs a, StepScratch s) {
+    if (blockIdx.x == 0 && a.zero_words)   // the next solve's sync area (nothing reads it before that solve)
+        for (int t = threadIdx.x; t < a.zero_count / 4; t += kWave * W)
+            reinterpret_cast<uint4 *>(a.zero_words)[t] = make_uint4(0u, 0u, 0u, 0u);
     const int m = a.nd.m;
     const int per = (int)((m + 7) / 8);
     const int j = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
@@ -1314,80 +1317,6 @@ hipError_t launch_energy_total(const misslam_report *rep, float w_data, float w_
 
 // ---------------------------------------------------------------- energy report
 
-__device__ __forceinline__ void energy_report_body(const double *__restrict__ pt_part, int npb,
-                                                   const double *__restrict__ node_part, int m, misslam_report *rep,
-                                                   float reject_thr, unsigned *__restrict__ zero_words,
-                                                   int zero_count, const double *__restrict__ kp_energy = nullptr,
-                                                   int kp_count = 0) {
-    __shared__ double red[6][256 / kWave];
-    if (zero_words)   // the next solve's sync area
-        for (int t = threadIdx.x; t < zero_count / 4; t += 256)
-            reinterpret_cast<uint4 *>(zero_words)[t] = make_uint4(0u, 0u, 0u, 0u);
-    // thread t adds entries t, t + 256, ... in order; the loads of eight entries are issued before their adds
-    constexpr int U = 8;
-    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int t0 = threadIdx.x; t0 < npb; t0 += U * 256) {
-        double a[U][3];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int t = min(t0 + 256 * u, npb - 1);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) a[u][c] = pt_part[3 * t + c];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (t0 + 256 * u < npb) {
-                v[0] += a[u][0];
-                v[1] += a[u][1];
-                v[2] += a[u][2];
-            }
-    }
-    for (int t0 = threadIdx.x; t0 < m; t0 += U * 256) {
-        double a[U][2];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int t = min(t0 + 256 * u, m - 1);
-            a[u][0] = node_part[2 * t];
-            a[u][1] = node_part[2 * t + 1];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (t0 + 256 * u < m) {
-                v[3] += a[u][0];
-                v[4] += a[u][1];
-            }
-    }
-    for (int t0 = threadIdx.x; t0 < kp_count; t0 += U * 256) {
-        double a[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) a[u] = kp_energy[min(t0 + 256 * u, kp_count - 1)];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (t0 + 256 * u < kp_count) v[5] += a[u];
-    }
-    // wave butterflies, then the four waves in order: a fixed summation order
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    wave_sums(v);
-    if (lane == 0)
-#pragma unroll
-        for (int q = 0; q < 6; ++q) red[q][wave] = v[q];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double tot[6];
-        for (int q = 0; q < 6; ++q) tot[q] = ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
-        const double ed = tot[0], nv = tot[1], sa = tot[2], er = tot[3], eg = tot[4];
-        rep->e_data = ed;
-        rep->e_rot = er;
-        rep->e_reg = eg;
-        rep->n_valid = (int32_t)nv;
-        rep->e_corr = tot[5];
-        int flags = 0;
-        if (!isfinite(ed) || !isfinite(er) || !isfinite(eg) || !isfinite(tot[5])) flags |= MISSLAM_FLAG_NONFINITE;
-        if (reject_thr > 0.f && nv > 0 && sa / nv > (double)reject_thr) flags |= MISSLAM_FLAG_FRAME_REJECT;
-        rep->flags |= flags;
-    }
-}
-
 __global__ void __launch_bounds__(256) energy_report_kernel(const double *__restrict__ pt_part, int npb,
                                                             const double *__restrict__ node_part, int m,
                                                             misslam_report *rep, float reject_thr,
@@ -1474,6 +1403,8 @@ hipError_t launch_list_pack(const StepArgs &a, const StepScratch &s, hipStream_t
 }
 
 hipError_t launch_assemble(const StepArgs &a, const StepScratch &s, hipStream_t st) {
+    if (a.zero_words && (a.zero_count < 0 || a.zero_count > MSL_BAR_WORDS || a.zero_count % 4))
+        return hipErrorInvalidValue;
     const int m = a.nd.m;
     const unsigned rows = 8 * (unsigned)((m + 7) / 8);
     const bool one = a.asm_waves == 1;
@@ -1488,6 +1419,24 @@ hipError_t launch_assemble(const StepArgs &a, const StepScratch &s, hipStream_t 
 #undef MSL_AS_CASE
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+void report_args(const StepScratch &s, int64_t n, int m, misslam_report *rep, float reject_thr,
+                 const double *kp_energy, int kp_count, ReportArgs &out) {
+    out.pt_part = s.pt_part;
+    out.npb = (int)nblk(n > 0 ? n : 1, kPtBlock);
+    out.node_part = s.node_part;
+    out.m = m;
+    out.rep = rep;
+    out.reject = reject_thr;
+    out.kp_energy = kp_energy;
+    out.kp_count = kp_energy ? kp_count : 0;
+}
+
+hipError_t launch_energy_report(const ReportArgs &ra, hipStream_t st) {
+    hipLaunchKernelGGL(energy_report_kernel, dim3(1), dim3(256), 0, st, ra.pt_part, ra.npb, ra.node_part, ra.m,
+                       ra.rep, ra.reject, nullptr, 0, ra.kp_energy, ra.kp_count);
     return hipGetLastError();
 }
 
