@@ -657,31 +657,39 @@ static misslam_status gn_register(const misslam_points *points, misslam_nodes *n
             }
             continue;
         }
-        // low precision: H_lo from the matrix cores, then float32 refinement of the step
+        // low precision: H_lo from the matrix cores, then float32 refinement of the step.  The assembly and each
+        // refinement's right-hand side clear the next solve's sync area, and the step's report is formed by the
+        // first solve's extra workgroup (as in the float32 path).
+        msl::StepArgs al = a;
+        al.zero_words = L.pcg.bar;
+        al.zero_count = msl::msl_sync_words(m);
         {
             Timed t(PH_POINT_PASS, st);
             e = msl::launch_point_pass(a, L.step, st);
         }
         if (e == hipSuccess) {
             Timed t(PH_ASSEMBLE, st);
-            e = msl::launch_assemble_lp(a, L.step, params->precision, L.rr, st);
+            e = msl::launch_assemble_lp(al, L.step, params->precision, L.rr, st);
         }
-        if (e == hipSuccess) e = msl::launch_energy_report(L.step, n, m, rep + it, params->reject_threshold, st);
+        msl::ReportArgs ra;
+        msl::report_args(L.step, n, m, rep + it, params->reject_threshold, nullptr, 0, ra);
         if (e == hipSuccess) {
             Timed t(PH_PCG, st);
             e = solve_persistent(view(graph), m, L.blocks, L.gvec, L.step.minv, params->lambda, params->pcg_iters,
-                                 L.delta, L.pcg, rep + it, nullptr, st, coop, 0, nullptr, kernels, spin, textbook);
+                                 L.delta, L.pcg, rep + it, nullptr, st, coop, al.zero_count, nullptr, kernels, spin,
+                                 textbook, &ra);
         }
         for (int r = 0; r < params->refine_steps && e == hipSuccess; ++r) {
             {
                 Timed t(PH_REFINE, st);
-                e = msl::launch_refine_rhs(a, L.step, L.delta, L.rr, L.gvec, L.jv, L.rhs, st);
+                e = msl::launch_refine_rhs(al, L.step, L.delta, L.rr, L.gvec, L.jv, L.rhs, st);
             }
             if (e == hipSuccess) e = msl::launch_report_init(L.rep, 1, st);
             if (e == hipSuccess) {
                 Timed t(PH_PCG, st);
                 e = solve_persistent(view(graph), m, L.blocks, L.rhs, L.step.minv, params->lambda, params->pcg_iters,
-                                     L.delta2, L.pcg, L.rep, nullptr, st, coop, 0, nullptr, kernels, spin, textbook);
+                                     L.delta2, L.pcg, L.rep, nullptr, st, coop, al.zero_count, nullptr, kernels,
+                                     spin, textbook);
             }
             // dx += the correction unless its solve failed; its flags join the step's report
             if (e == hipSuccess) e = msl::launch_step_commit(L.delta, L.delta2, 12 * m, L.rep, st, rep + it);

@@ -803,12 +803,18 @@ __device__ __forceinline__ void assemble_rows_body(const StepArgs &a, const Step
     row_finalize<kAsmThreads>(a, s, sh.rn, sh.fin, j, rb, nslots, e_reg, lamf, data, nullptr);
 }
 
+// The first workgroup of a kernel that runs right before a one-launch solve clears the solve's sync area
+// (a.zero_words, if set): nothing reads it between that kernel and the solve.
+__device__ __forceinline__ void clear_sync_words(const StepArgs &a) {
+    if (blockIdx.x == 0 && a.zero_words)
+        for (int t = threadIdx.x; t < a.zero_count / 4; t += blockDim.x)
+            reinterpret_cast<uint4 *>(a.zero_words)[t] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 template <int K, int W>
 __global__ void __launch_bounds__(kWave * W) __attribute__((amdgpu_waves_per_eu(4)))
 assemble_rows_kernel(StepArgs a, StepScratch s) {
-    if (blockIdx.x == 0 && a.zero_words)   // the next solve's sync area (nothing reads it before that solve)
-        for (int t = threadIdx.x; t < a.zero_count / 4; t += kWave * W)
-            reinterpret_cast<uint4 *>(a.zero_words)[t] = make_uint4(0u, 0u, 0u, 0u);
+    clear_sync_words(a);
     const int m = a.nd.m;
     const int per = (int)((m + 7) / 8);
     const int j = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
@@ -868,6 +874,7 @@ template <int K, typename T>
 __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, StepScratch s, float *rr_out) {
     __shared__ LpShared<K, T> sh;
     constexpr int NT = (12 * K + 15) / 16;           // column tiles of the set nodes' parameters
+    clear_sync_words(a);
     const int m = a.nd.m;
     const int per = (int)((m + 7) / 8);
     const int j = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
@@ -1055,6 +1062,8 @@ __global__ void __launch_bounds__(kLpThreads) assemble_lp_kernel(StepArgs a, Ste
 
 hipError_t launch_assemble_lp(const StepArgs &a, const StepScratch &s, int precision, float *rr_out,
                               hipStream_t st) {
+    if (a.zero_words && (a.zero_count < 0 || a.zero_count > MSL_BAR_WORDS || a.zero_count % 4))
+        return hipErrorInvalidValue;
     const unsigned rows = 8 * (unsigned)((a.nd.m + 7) / 8);
     const bool bf = precision == MISSLAM_PREC_BF16;
     switch (a.g.k) {
@@ -1105,6 +1114,7 @@ template <int K>
 __global__ void __launch_bounds__(64) jtv_row_kernel(StepArgs a, StepScratch s, const float *__restrict__ jv,
                                                      const float *__restrict__ rr, const float *__restrict__ dx,
                                                      const float *__restrict__ g, float *__restrict__ rhs) {
+    clear_sync_words(a);
     const int j = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t n = a.pts.n;
@@ -1155,6 +1165,8 @@ __global__ void axpy_kernel(float *__restrict__ y, const float *__restrict__ x, 
 
 hipError_t launch_refine_rhs(const StepArgs &a, const StepScratch &s, const float *dx, const float *rr, const float *g,
                              float *jv, float *rhs, hipStream_t st) {
+    if (a.zero_words && (a.zero_count < 0 || a.zero_count > MSL_BAR_WORDS || a.zero_count % 4))
+        return hipErrorInvalidValue;
     const int64_t n = a.pts.n;
     if (n > 0) {
         switch (a.g.k) {
