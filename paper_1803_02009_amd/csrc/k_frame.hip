@@ -74,10 +74,17 @@ constexpr int kGridThreads = 1024;
 // twice the node spacing of a surface-sampled graph), widened until the
 // cell count fits MSL_GRID_CELLS.  The width only affects speed: the search
 // below is exact for any h.  One workgroup.
-__global__ void __launch_bounds__(kGridThreads) node_grid_kernel(NodesView nd, GridView gv) {
+constexpr int kGridLdsCells = 4096;   // grids up to this many cells are sorted in LDS
+
+// zero_a / zero_b (na / nb words, may be null): counters the graph build clears before its later kernels.
+__global__ void __launch_bounds__(kGridThreads) node_grid_kernel(NodesView nd, GridView gv, uint32_t *zero_a,
+                                                                 size_t na, uint32_t *zero_b, size_t nb) {
     __shared__ float red[6][kGridThreads];
     __shared__ int part[kGridThreads];
+    __shared__ int cell_s[kGridLdsCells + 1];   // counts, then fill cursors, of a grid that fits
     const int m = nd.m, tid = threadIdx.x;
+    for (size_t t = tid; t < na; t += kGridThreads) zero_a[t] = 0u;
+    for (size_t t = tid; t < nb; t += kGridThreads) zero_b[t] = 0u;
     float lo[3] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf()};
     float hi[3] = {-__builtin_huge_valf(), -__builtin_huge_valf(), -__builtin_huge_valf()};
     for (int t = tid; t < m; t += kGridThreads) {
@@ -138,9 +145,6 @@ __global__ void __launch_bounds__(kGridThreads) node_grid_kernel(NodesView nd, G
         gv.dims[1] = m > 0 ? dim[1] : 0;
         gv.dims[2] = m > 0 ? dim[2] : 0;
     }
-    // counting sort of the nodes by cell
-    for (int c = tid; c <= ncell; c += kGridThreads) gv.start[c] = 0;
-    __syncthreads();
     const double ih = 1.0 / h;
     auto cell_of = [&](int t) {
         const double c[3] = {(double)nd.gx[t], (double)nd.gy[t], (double)nd.gz[t]};
@@ -152,6 +156,41 @@ __global__ void __launch_bounds__(kGridThreads) node_grid_kernel(NodesView nd, G
         }
         return (q[2] * dim[1] + q[1]) * dim[0] + q[0];
     };
+    if (ncell <= kGridLdsCells) {   // counting sort in LDS: counts, an exclusive scan, cursors
+        for (int c = tid; c <= ncell; c += kGridThreads) cell_s[c] = 0;
+        __syncthreads();
+        for (int t = tid; t < m; t += kGridThreads) atomicAdd(&cell_s[cell_of(t)], 1);
+        __syncthreads();
+        const int chunk = (ncell + kGridThreads - 1) / kGridThreads;
+        const int c0 = min(ncell, tid * chunk), c1 = min(ncell, c0 + chunk);
+        int sum = 0;
+        for (int c = c0; c < c1; ++c) sum += cell_s[c];
+        part[tid] = sum;
+        __syncthreads();
+        for (int off = 1; off < kGridThreads; off <<= 1) {
+            const int v = tid >= off ? part[tid - off] : 0;
+            __syncthreads();
+            part[tid] += v;
+            __syncthreads();
+        }
+        int run = tid == 0 ? 0 : part[tid - 1];
+        for (int c = c0; c < c1; ++c) {
+            const int v = cell_s[c];
+            gv.start[c] = run;
+            cell_s[c] = run;
+            run += v;
+        }
+        if (tid == 0) gv.start[ncell] = m;
+        __syncthreads();
+        for (int t = tid; t < m; t += kGridThreads) {
+            const int pos = atomicAdd(&cell_s[cell_of(t)], 1);
+            gv.nodes[pos] = make_float4(nd.gx[t], nd.gy[t], nd.gz[t], __int_as_float(t));
+        }
+        return;
+    }
+    // a larger grid: the same in global memory
+    for (int c = tid; c <= ncell; c += kGridThreads) gv.start[c] = 0;
+    __syncthreads();
     for (int t = tid; t < m; t += kGridThreads) atomicAdd(&gv.start[cell_of(t)], 1);
     __syncthreads();
     // exclusive scan of ncell counts: each thread a contiguous chunk
@@ -756,15 +795,17 @@ static hipError_t graph_k(const PointsView &pts, const NodesView &nd, int wkind,
                           const GraphScratch &s, hipStream_t st) {
     const int64_t n = pts.n;
     const int m = nd.m;
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(nblk(2 * (int64_t)m + 8, 256)), dim3(256), 0, st, (uint32_t *)s.cnt,
-                       (size_t)(2 * m + 8), 0u);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, (uint32_t *)g.info, (size_t)8, 0u);
     int32_t *lcnt = s.cnt + m;
-    if (n > 0) {
-        hipLaunchKernelGGL(node_grid_kernel, dim3(1), dim3(kGridThreads), 0, st, nd, s.grid);
+    if (n > 0) {   // the node grid's kernel also clears the counters and the graph's flags
+        hipLaunchKernelGGL(node_grid_kernel, dim3(1), dim3(kGridThreads), 0, st, nd, s.grid, (uint32_t *)s.cnt,
+                           (size_t)(2 * m + 8), (uint32_t *)g.info, (size_t)8);
         hipLaunchKernelGGL((knn_kernel<K>), dim3(nblk(n, kKnnBlock)), dim3(kKnnBlock), 0, st, pts, s.grid, wkind,
                            sigma, g.knn_idx, g.knn_w);
         hipLaunchKernelGGL((list_count_kernel<K>), dim3(nblk(n, 256)), dim3(256), 0, st, g.knn_idx, n, lcnt);
+    } else {
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(nblk(2 * (int64_t)m + 8, 256)), dim3(256), 0, st, (uint32_t *)s.cnt,
+                           (size_t)(2 * m + 8), 0u);
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, (uint32_t *)g.info, (size_t)8, 0u);
     }
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, lcnt, m, g.list_ptr, g.info, -1, 2,
                        0x7FFFFFFF, (int64_t)K * n);
