@@ -222,6 +222,43 @@ __global__ void __launch_bounds__(kGridThreads) node_grid_kernel(NodesView nd, G
     }
 }
 
+// LDS hash of the node ids met by one block of points: open addressing, twice
+// as many slots as the block can insert, so probing always ends.
+template <int K>
+struct NodeHash {
+    static constexpr int kSlots = 2 * 256 * K;
+    int key[kSlots];
+    int cnt[kSlots];
+    int base[kSlots];
+    int rank[kSlots];
+};
+
+// The node counts alone (the kNN kernel's share of the list lengths).
+template <int K>
+struct NodeCount {
+    static constexpr int kSlots = NodeHash<K>::kSlots;
+    int key[kSlots];
+    int cnt[kSlots];
+};
+
+template <int K, class H>
+__device__ __forceinline__ int hash_insert(H &h, int j) {
+    int s = (int)(((uint32_t)j * 2654435761u) % (uint32_t)NodeHash<K>::kSlots);
+    while (true) {
+        const int old = atomicCAS(&h.key[s], -1, j);
+        if (old == -1 || old == j) return s;
+        s = s + 1 == NodeHash<K>::kSlots ? 0 : s + 1;
+    }
+}
+
+template <int K>
+__device__ __forceinline__ int hash_find(const NodeHash<K> &h, int j) {
+    int s = (int)(((uint32_t)j * 2654435761u) % (uint32_t)NodeHash<K>::kSlots);
+    while (h.key[s] != j) s = s + 1 == NodeHash<K>::kSlots ? 0 : s + 1;
+    return s;
+}
+
+// Entries per node: counted per block in LDS, one global add per distinct node.
 // Keeps the KK smallest (d^2, index) pairs in lexicographic order (equal
 // distances: lower index first), so the result does not depend on the order
 // in which candidates arrive.
@@ -251,10 +288,9 @@ __device__ __forceinline__ void knn_insert(double (&bd)[KK], int (&bi)[KK], doub
 // cell index) or the cube covers the grid: the result equals the exhaustive
 // search.  The weights of Eq.(2) follow in float64.
 template <int K>
-__global__ void __launch_bounds__(kKnnBlock) knn_kernel(PointsView pts, GridView gv, int wkind, float sigma,
-                                                        int32_t *__restrict__ idx_out, float *__restrict__ w_out) {
-    const int64_t i = (int64_t)blockIdx.x * kKnnBlock + threadIdx.x;
-    if (i >= pts.n) return;
+__device__ __forceinline__ void knn_point(PointsView pts, GridView gv, int wkind, float sigma,
+                                          int32_t *__restrict__ idx_out, float *__restrict__ w_out, int64_t i,
+                                          NodeCount<K> &hc) {
     const double px = (double)pts.px[i], py = (double)pts.py[i], pz = (double)pts.pz[i];
     constexpr int KK = K + 1;
     double bd[KK];
@@ -327,7 +363,27 @@ __global__ void __launch_bounds__(kKnnBlock) knn_kernel(PointsView pts, GridView
     for (int s = 0; s < K; ++s) {
         idx_out[(int64_t)s * pts.n + i] = bi[s];
         w_out[(int64_t)s * pts.n + i] = (float)(sum > 0.0 ? wv[s] / sum : 1.0 / K);
+        atomicAdd(&hc.cnt[hash_insert<K>(hc, bi[s])], 1);
     }
+}
+
+template <int K>
+__global__ void __launch_bounds__(kKnnBlock) knn_kernel(PointsView pts, GridView gv, int wkind, float sigma,
+                                                        int32_t *__restrict__ idx_out, float *__restrict__ w_out,
+                                                        int32_t *__restrict__ list_cnt) {
+    // the block's kNN sets are also counted per node (an LDS hash, then one device atomic per distinct node):
+    // the lengths of the node -> point lists
+    __shared__ NodeCount<K> hc;
+    for (int t = threadIdx.x; t < NodeCount<K>::kSlots; t += kKnnBlock) {
+        hc.key[t] = -1;
+        hc.cnt[t] = 0;
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kKnnBlock + threadIdx.x;
+    if (i < pts.n) knn_point<K>(pts, gv, wkind, sigma, idx_out, w_out, i, hc);
+    __syncthreads();
+    for (int t = threadIdx.x; t < NodeCount<K>::kSlots; t += kKnnBlock)
+        if (hc.key[t] >= 0) atomicAdd(&list_cnt[hc.key[t]], hc.cnt[t]);
 }
 
 // ---------------------------------------------------------------- node -> point lists
@@ -335,54 +391,6 @@ __global__ void __launch_bounds__(kKnnBlock) knn_kernel(PointsView pts, GridView
 __global__ void fill_u32_kernel(uint32_t *p, size_t n, uint32_t v) {
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) p[t] = v;
-}
-
-// LDS hash of the node ids met by one block of points: open addressing, twice
-// as many slots as the block can insert, so probing always ends.
-template <int K>
-struct NodeHash {
-    static constexpr int kSlots = 2 * 256 * K;
-    int key[kSlots];
-    int cnt[kSlots];
-    int base[kSlots];
-    int rank[kSlots];
-};
-
-template <int K>
-__device__ __forceinline__ int hash_insert(NodeHash<K> &h, int j) {
-    int s = (int)(((uint32_t)j * 2654435761u) % (uint32_t)NodeHash<K>::kSlots);
-    while (true) {
-        const int old = atomicCAS(&h.key[s], -1, j);
-        if (old == -1 || old == j) return s;
-        s = s + 1 == NodeHash<K>::kSlots ? 0 : s + 1;
-    }
-}
-
-template <int K>
-__device__ __forceinline__ int hash_find(const NodeHash<K> &h, int j) {
-    int s = (int)(((uint32_t)j * 2654435761u) % (uint32_t)NodeHash<K>::kSlots);
-    while (h.key[s] != j) s = s + 1 == NodeHash<K>::kSlots ? 0 : s + 1;
-    return s;
-}
-
-// Entries per node: counted per block in LDS, one global add per distinct node.
-template <int K>
-__global__ void __launch_bounds__(256) list_count_kernel(const int32_t *__restrict__ idx, int64_t n,
-                                                         int32_t *__restrict__ cnt) {
-    __shared__ NodeHash<K> h;
-    for (int t = threadIdx.x; t < NodeHash<K>::kSlots; t += 256) {
-        h.key[t] = -1;
-        h.cnt[t] = 0;
-    }
-    __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) {
-#pragma unroll
-        for (int s = 0; s < K; ++s) atomicAdd(&h.cnt[hash_insert<K>(h, idx[(int64_t)s * n + i])], 1);
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < NodeHash<K>::kSlots; t += 256)
-        if (h.key[t] >= 0) atomicAdd(&cnt[h.key[t]], h.cnt[t]);
 }
 
 // Unordered placement (list_sort_kernel imposes the order): each block reserves
@@ -800,8 +808,7 @@ static hipError_t graph_k(const PointsView &pts, const NodesView &nd, int wkind,
         hipLaunchKernelGGL(node_grid_kernel, dim3(1), dim3(kGridThreads), 0, st, nd, s.grid, (uint32_t *)s.cnt,
                            (size_t)(2 * m + 8), (uint32_t *)g.info, (size_t)8);
         hipLaunchKernelGGL((knn_kernel<K>), dim3(nblk(n, kKnnBlock)), dim3(kKnnBlock), 0, st, pts, s.grid, wkind,
-                           sigma, g.knn_idx, g.knn_w);
-        hipLaunchKernelGGL((list_count_kernel<K>), dim3(nblk(n, 256)), dim3(256), 0, st, g.knn_idx, n, lcnt);
+                           sigma, g.knn_idx, g.knn_w, lcnt);
     } else {
         hipLaunchKernelGGL(fill_u32_kernel, dim3(nblk(2 * (int64_t)m + 8, 256)), dim3(256), 0, st, (uint32_t *)s.cnt,
                            (size_t)(2 * m + 8), 0u);
