@@ -71,6 +71,37 @@ def test_knn_and_pattern_bit_exact(lib, name):
         assert list(lst[lp[j]:lp[j + 1]]) == want
 
 
+def test_knn_on_a_large_grid(lib):
+    """20,000 nodes filling a cube: the node grid has about 57^3 cells, far more than the 4096 that the grid
+    kernel sorts in LDS, so its device-memory path builds it.  The kNN sets of sampled points are checked
+    against the brute-force oracle, bit for bit."""
+    from paper_1803_02009_amd import misslam as M
+    rng = np.random.default_rng(11)
+    m, n = 20000, 30000
+    nodes = rng.uniform(-100.0, 100.0, size=(m, 3)).astype(np.float32)
+    pts = rng.uniform(-100.0, 100.0, size=(n, 3)).astype(np.float32)
+    nrm = np.tile(np.array([0.0, 0.0, 1.0], np.float32), (n, 1))
+    dev = "cuda"
+    P = torch.tensor(np.concatenate([pts.T, nrm.T]), device=dev).contiguous()
+    G = torch.tensor(np.ascontiguousarray(nodes.T), device=dev).contiguous()
+    params = M.Params(sigma=5.0)
+    g = M.build_graph(P, G, params, M.Workspace())
+    torch.cuda.synchronize()
+    # the grid's cell count as the kernel sizes it: well above the LDS path's 4096
+    ext = nodes.astype(np.float64).max(0) - nodes.astype(np.float64).min(0)
+    e = np.sort(ext)[::-1]
+    h = 2.0 * np.sqrt(e[0] * e[1] / m)
+    cells = np.prod(np.floor(ext / h) + 1.0)
+    while cells > (1 << 18):
+        h *= 1.25
+        cells = np.prod(np.floor(ext / h) + 1.0)
+    assert cells > 4096 * 10
+    sample = np.arange(0, n, 60)
+    ref_idx, _ = oracle.knn(pts[sample], nodes, params.k)
+    idx = g.knn_idx.cpu().numpy().T[sample]
+    assert np.array_equal(idx, ref_idx[:, :params.k])
+
+
 def test_linear_weights(lib):
     s = Scene("c1")
     s.params.weight_kind = 1
