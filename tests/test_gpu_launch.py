@@ -50,6 +50,26 @@ def test_per_phase_launches_agree_to_rounding(lib):
     assert np.all(r0["flags"] == 0) and np.all(r1["flags"] == 0)
 
 
+@pytest.mark.parametrize("precision", [_lib.PREC_FP32, _lib.PREC_BF16])
+def test_report_of_the_solve_workgroup_matches_the_report_kernel(lib, precision):
+    """The one-launch solve forms its step's energy report in an extra workgroup; the per-phase launches use
+    the report kernel.  At the first step both see the same partials, so the energies and the count of
+    valid points agree bit for bit."""
+    s = Scene("c2")
+    reps = []
+    for mode in (_lib.LAUNCH_PLAIN, _lib.LAUNCH_KERNELS):
+        p = dataclasses.replace(s.params, solve_launch=mode, precision=precision)
+        x = s.M.identity_params(s.m)
+        rep, _ = s.M.gn_register(s.pts, s.nodes, x, s.graph, s.depth, s.cam, s.pose, p, s.ws)
+        torch.cuda.synchronize()
+        reps.append(s.M.read_report(rep))
+    r0, r1 = reps
+    for f in ("e_data", "e_rot", "e_reg", "n_valid", "e_corr"):
+        assert r0[0][f] == r1[0][f], f
+    assert r0[0]["e_data"] > 0 and r0[0]["n_valid"] > 0
+    assert np.all(r0["flags"] == 0) and np.all(r1["flags"] == 0)
+
+
 def test_joint_per_phase_launches_agree_to_rounding(lib):
     """The joint one-launch solve sums each row's blocks as the fixed-form one does (own columns, then two
     chains), the per-phase joint kernels in block order: equal in exact arithmetic."""
